@@ -1,0 +1,128 @@
+"""Oracle: second-order spectral projection (SP2) purification, FP64.
+
+Test infrastructure only.  The paper constructs the zero-temperature density
+matrix by "the recursive second order spectral projection method" and, in its
+linear-scaling runs, sets to zero every element below a numerical threshold
+tau after each individual projection (Linear scaling section; caption of the
+isocyanic-acid energy figure).  It cites the method without printing it, so
+the steps below are the standard SP2 recursion written from its definition:
+
+* bounds: Gershgorin discs, eps_min = min_i (H_ii - sum_{j!=i} |H_ij|),
+  eps_max = max_i (H_ii + sum_{j!=i} |H_ij|);
+* start: X_0 = (eps_max I - H) / (eps_max - eps_min), spectrum in [0, 1],
+  occupied states (low energies) near 1;
+* iterate: P = X_n^2; X_{n+1} = P (pushes eigenvalues towards 0, lowers the
+  trace) or X_{n+1} = 2 X_n - P (pushes towards 1, raises the trace),
+  whichever has trace closest to N_occ (reading: ties take P);
+* stop after computing P = X_n^2 when ||P - X_n||_F < tol (return X_n), or
+  when n >= 4, ||P - X_n||_F >= ||P_{n-2} - X_{n-2}||_F and
+  ||P - X_n||_F < stall (return X_n; the idempotency error has reached the
+  rounding floor), or after max_iter iterations (not converged).
+
+Each branch is a polynomial in X_0, so X_n = p_n(X_0) and the eigenvalues of
+X_n are p_n applied to those of X_0 (pinned, with the Jacobi projector, in
+tests/test_oracle_sp2.py).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class SP2Result:
+    D: np.ndarray
+    iterations: int          # number of products X_n^2 formed
+    branches: list           # 0: X <- X^2, 1: X <- 2X - X^2, per update
+    idem: list               # ||X_n^2 - X_n||_F per product
+    traces: list             # (Tr X_n, Tr X_n^2) per product
+    eps_min: float
+    eps_max: float
+    converged: bool
+    stalled: bool
+    fill: list = dataclasses.field(default_factory=list)
+
+
+def gershgorin(H):
+    """Gershgorin bounds (eps_min, eps_max) of symmetric H."""
+    d = np.diag(H)
+    radius = np.sum(np.abs(H), axis=1) - np.abs(d)
+    return float(np.min(d - radius)), float(np.max(d + radius))
+
+
+def sp2_initial(H, eps_min, eps_max):
+    """X_0 = (eps_max I - H) / (eps_max - eps_min)."""
+    N = H.shape[0]
+    return (eps_max * np.eye(N) - H) / (eps_max - eps_min)
+
+
+def choose_branch(t1, t2, n_occ):
+    """0 (X^2) if its trace is at least as close to n_occ as 2X - X^2's, else 1."""
+    return 0 if abs(t2 - n_occ) <= abs(2.0 * t1 - t2 - n_occ) else 1
+
+
+def block_threshold(X, tau, bs=32):
+    """Zero every bs x bs block whose Frobenius norm is below tau.
+
+    Returns (thresholded copy, fraction of blocks kept).  Blocks on the
+    ragged edge are the partial blocks of the grid.
+    """
+    N = X.shape[0]
+    nb = (N + bs - 1) // bs
+    Y = X.copy()
+    kept = 0
+    for bi in range(nb):
+        for bj in range(nb):
+            blk = Y[bi * bs:(bi + 1) * bs, bj * bs:(bj + 1) * bs]
+            if np.sqrt(np.sum(blk * blk)) < tau:
+                blk[...] = 0.0
+            else:
+                kept += 1
+    return Y, kept / (nb * nb)
+
+
+def sp2(H, n_occ, tol=1e-10, max_iter=100, stall=1e-2, tau=0.0, block=32,
+        bounds=None):
+    """SP2 density matrix of symmetric H with trace n_occ.
+
+    tau > 0 selects the thresholded variant: after X_0 and after every
+    update, blocks of size ``block`` with Frobenius norm below tau are zeroed
+    (the block form of the paper's elementwise threshold).
+    """
+    H = np.asarray(H, dtype=np.float64)
+    eps_min, eps_max = gershgorin(H) if bounds is None else bounds
+    X = sp2_initial(H, eps_min, eps_max)
+    fill = []
+    if tau > 0.0:
+        X, f = block_threshold(X, tau, block)
+        fill.append(f)
+    branches, idem, traces = [], [], []
+    for n in range(max_iter):
+        P = X @ X
+        t1, t2 = float(np.trace(X)), float(np.trace(P))
+        e = float(np.linalg.norm(P - X))
+        idem.append(e)
+        traces.append((t1, t2))
+        if e < tol:
+            return SP2Result(X, n + 1, branches, idem, traces, eps_min, eps_max,
+                             True, False, fill)
+        if n >= 4 and e >= idem[n - 2] and e < stall:
+            return SP2Result(X, n + 1, branches, idem, traces, eps_min, eps_max,
+                             False, True, fill)
+        b = choose_branch(t1, t2, n_occ)
+        branches.append(b)
+        X = P if b == 0 else 2.0 * X - P
+        if tau > 0.0:
+            X, f = block_threshold(X, tau, block)
+            fill.append(f)
+    return SP2Result(X, max_iter, branches, idem, traces, eps_min, eps_max,
+                     False, False, fill)
+
+
+def scalar_sp2(x0, branches):
+    """Apply a branch sequence to scalars: p_n(x) of the spectral mapping."""
+    x = np.array(x0, dtype=np.float64)
+    for b in branches:
+        x = x * x if b == 0 else 2.0 * x - x * x
+    return x

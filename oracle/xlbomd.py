@@ -1,0 +1,136 @@
+"""Oracle: optimisation-free XL-BOMD for the orthogonal T_e = 0 model.
+
+Test infrastructure only.
+
+* Initialisation (General remarks subsection): converge the charges
+  self-consistently, then set n = q for the whole history.  The SCF here is
+  plain linear mixing n <- n + beta (q[n] - n) until max|q - n| < tol.
+* Auxiliary charges (Eq. Verl_n with sigma -> q, Eq. EL_Orth_b):
+  n_{t+dt} = 2 n_t - n_{t-dt} + kappa (q_t - n_t) + alpha sum_{k=0}^{K} c_k n_{t-k dt}.
+  kappa, alpha, c_k with K = 5 come from the cited dissipation paper, which the
+  text does not reprint; kappa is rescaled by 1/2 (General remarks).  Reading:
+  kappa = 1.82 / 2, alpha = 0.018, c = (-6, 14, -8, -3, 4, -1); they are
+  inputs, and what the tests pin is sum c_k = 0 and sum k c_k = 0 (the
+  dissipation vanishes on histories linear in t) and time reversibility for
+  alpha = 0.
+* Nuclei: velocity Verlet with the forces of ``observables.forces`` at the
+  new (R, n) — one density-matrix construction per step.
+* Constant of motion: E_tot = kinetic + U(R; n) (Eq. EtotOrth, S = 0).
+
+The density matrix comes from the oracle SP2 (or Jacobi when requested).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+import synth
+
+from . import eig, observables, sp2, tb
+
+K5_KAPPA = 1.82
+K5_ALPHA = 0.018
+K5_C = (-6.0, 14.0, -8.0, -3.0, 4.0, -1.0)
+
+
+@dataclasses.dataclass
+class XLOptions:
+    dt_fs: float = 0.25
+    kappa: float = 0.5 * K5_KAPPA
+    alpha: float = K5_ALPHA
+    c: tuple = K5_C
+    solver: str = "sp2"           # "sp2" or "jacobi"
+    sp2_tol: float = 1e-10
+
+
+def density(H, n_occ, solver="sp2", tol=1e-10):
+    if solver == "jacobi":
+        D, _, _ = eig.density_matrix(H, n_occ)
+        return D
+    r = sp2.sp2(H, n_occ, tol=tol)
+    if not (r.converged or r.stalled):
+        raise RuntimeError("oracle SP2 did not converge")
+    return r.D
+
+
+def evaluate(pos, n, m, n_occ, solver="sp2", tol=1e-10, want_forces=True):
+    """One density-matrix construction at (R, n): returns dict of q, U, F, D."""
+    H = tb.hamiltonian(pos, n, m)
+    D = density(H, n_occ, solver, tol)
+    q = observables.mulliken(D, m.z_val)
+    U = observables.potential_energy(pos, n, D, m)
+    F = observables.forces(pos, n, D, m) if want_forces else None
+    return {"q": q, "U": U, "F": F, "D": D, "H": H}
+
+
+def scf(pos, m, n_occ, beta=0.02, tol=1e-10, max_iter=20000, n0=None,
+        solver="sp2"):
+    """Self-consistent charges by linear mixing; returns (q*, iterations)."""
+    n = np.zeros(len(pos)) if n0 is None else np.array(n0, dtype=np.float64)
+    for it in range(max_iter):
+        H = tb.hamiltonian(pos, n, m)
+        q = observables.mulliken(density(H, n_occ, solver), m.z_val)
+        if np.max(np.abs(q - n)) < tol:
+            return q, it + 1
+        n = n + beta * (q - n)
+    raise RuntimeError("oracle SCF did not converge")
+
+
+def nvt_dissipation(hist, alpha, c):
+    """alpha * sum_k c_k n_{t - k dt}; hist[0] = n_t, hist[k] = n_{t-k dt}."""
+    return alpha * sum(ck * hk for ck, hk in zip(c, hist))
+
+
+def verlet_n(hist, q, kappa, alpha, c):
+    """Eq. Verl_n: the next auxiliary charges from the history and q_t."""
+    n_t, n_tm1 = hist[0], hist[1]
+    return 2.0 * n_t - n_tm1 + kappa * (q - n_t) + nvt_dissipation(hist, alpha, c)
+
+
+@dataclasses.dataclass
+class XLState:
+    pos: np.ndarray
+    vel: np.ndarray
+    hist: list               # [n_t, n_{t-dt}, ..., n_{t-K dt}]
+    q: np.ndarray
+    F: np.ndarray
+    U: float
+    step: int = 0
+
+
+def init_state(pos, vel, m, n_occ, opts: XLOptions, n0):
+    """State at t = 0 with n_{-k dt} = n0 for all k (n0 = SCF charges)."""
+    n0 = np.array(n0, dtype=np.float64)
+    ev = evaluate(pos, n0, m, n_occ, opts.solver, opts.sp2_tol)
+    hist = [n0.copy() for _ in range(len(opts.c))]
+    return XLState(pos.copy(), vel.copy(), hist, ev["q"], ev["F"], ev["U"])
+
+
+def total_energy(st: XLState, m):
+    return observables.kinetic_energy(st.vel, m.mass, synth.KE_EV) + st.U
+
+
+def step(st: XLState, m, n_occ, opts: XLOptions) -> XLState:
+    """One XL-BOMD step: half kick, drift, n update, new D, forces, half kick."""
+    dt = opts.dt_fs
+    acc = synth.ACC_A_FS2 / m.mass
+    v_half = st.vel + 0.5 * dt * acc * st.F
+    pos = st.pos + dt * v_half
+    n_new = verlet_n(st.hist, st.q, opts.kappa, opts.alpha, opts.c)
+    ev = evaluate(pos, n_new, m, n_occ, opts.solver, opts.sp2_tol)
+    vel = v_half + 0.5 * dt * acc * ev["F"]
+    hist = [n_new] + st.hist[:-1]
+    return XLState(pos, vel, hist, ev["q"], ev["F"], ev["U"], st.step + 1)
+
+
+def run(st: XLState, m, n_occ, opts: XLOptions, n_steps: int):
+    """Integrate n_steps; returns (final state, list of per-step records)."""
+    log = []
+    for _ in range(n_steps):
+        st = step(st, m, n_occ, opts)
+        log.append({"step": st.step,
+                    "etot": total_energy(st, m),
+                    "U": st.U,
+                    "max_q_minus_n": float(np.max(np.abs(st.q - st.hist[0])))})
+    return st, log

@@ -1,0 +1,168 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This module holds no arithmetic of the method itself: it only draws
+positions, velocities and request streams from seeded generators and holds
+the numeric model parameters that both sides read.  Everything that turns
+those numbers into a Hamiltonian, a density matrix, charges or forces lives
+separately in ``oracle/`` (CPU reference) and in the HIP library.
+
+Workloads (stand-ins for the paper's hydrocarbon systems, whose LATTE
+parameters and structures are not published):
+
+* a jittered simple-cubic lattice of "carbon-like" atoms with four
+  orthogonal valence orbitals (s, px, py, pz) each, spacing 1.5 A, Gaussian
+  jitter sigma = 0.1 A per coordinate, atoms ordered x fastest, then y, then z,
+  so orbital index = 4 * atom + {0: s, 1: px, 2: py, 3: pz};
+* Maxwell-Boltzmann velocities at a given temperature (centre-of-mass
+  momentum removed);
+* a Poisson stream of solve requests with uniformly drawn system sizes.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# Physical constants (CODATA 2018) in the eV / A / amu / fs unit system.
+KB_EV_PER_K = 8.617333262e-5          # Boltzmann constant, eV/K
+COULOMB_EV_A = 14.399645478           # e^2 / (4 pi eps0), eV * A
+ACC_A_FS2 = 9.648533212e-3            # 1 eV/(A*amu) expressed in A/fs^2
+KE_EV = 103.6426965                   # 1 amu*A^2/fs^2 expressed in eV
+
+
+@dataclasses.dataclass(frozen=True)
+class TBModel:
+    """Numeric parameters of the synthetic orthogonal sp tight-binding model.
+
+    Hopping magnitude |t(r)| = t0 * exp(-(r - r0) / lam) for r < r_cut; on
+    [r_tail, r_cut) a quintic tail replaces it when r_tail < r_cut (r_tail ==
+    r_cut means a hard cut).  Bond-integral signs: ss-sigma = -|t|,
+    sp-sigma = +|t|, pp-sigma = +|t|, pp-pi = -|t|.
+    """
+    eps_s: float = -8.0
+    eps_p: float = -4.0
+    t0: float = 2.0
+    r0: float = 1.5
+    lam: float = 0.5
+    r_cut: float = 4.0
+    r_tail: float = 4.0
+    hubbard_u: float = 4.0
+    coulomb_k: float = COULOMB_EV_A
+    pair_a: float = 0.0        # pair repulsion amplitude, eV (0 = no pair term)
+    pair_r0: float = 1.5
+    pair_rho: float = 0.3
+    mass: float = 12.0         # amu
+    z_val: int = 4             # valence electrons per neutral atom
+
+    def with_(self, **kw) -> "TBModel":
+        return dataclasses.replace(self, **kw)
+
+
+# Static configurations use the literal hard cut-off at 4 A; molecular
+# dynamics uses the smooth tail on [3.5, 4.0] A so the energy is continuous.
+STATIC_MODEL = TBModel()
+MD_MODEL = TBModel(r_tail=3.5)
+
+
+def lattice_positions(dims, spacing: float = 1.5, jitter: float = 0.1,
+                      seed: int = 0, n_atoms: int | None = None) -> np.ndarray:
+    """Jittered simple-cubic lattice, x fastest, then y, then z.
+
+    Returns float64 array (n_atoms, 3) in Angstrom.  If ``n_atoms`` is given,
+    only the first ``n_atoms`` lattice sites (in that order) are kept, before
+    the jitter is drawn.
+    """
+    nx, ny, nz = (int(d) for d in dims)
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx),
+                             indexing="ij")
+    sites = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    if n_atoms is not None:
+        sites = sites[:n_atoms]
+    rng = np.random.default_rng(seed)
+    return sites * spacing + rng.normal(0.0, jitter, size=sites.shape)
+
+
+def maxwell_velocities(n_atoms: int, temperature_k: float, mass_amu: float,
+                       seed: int) -> np.ndarray:
+    """Velocities in A/fs drawn from N(0, kT/M) per component, zero total momentum."""
+    rng = np.random.default_rng(seed)
+    # kT/M in eV/amu -> (A/fs)^2 via 1 amu*A^2/fs^2 = KE_EV eV
+    sigma = math.sqrt(KB_EV_PER_K * temperature_k / (mass_amu * KE_EV))
+    v = rng.normal(0.0, sigma, size=(n_atoms, 3))
+    v -= v.mean(axis=0, keepdims=True)
+    return v
+
+
+def cube_dims_for(n_atoms: int):
+    side = int(math.ceil(round(n_atoms ** (1.0 / 3.0), 9)))
+    while side ** 3 < n_atoms:
+        side += 1
+    return (side, side, side)
+
+
+@dataclasses.dataclass(frozen=True)
+class Request:
+    index: int
+    arrival_s: float
+    n_atoms: int
+    seed: int
+
+    @property
+    def n_orb(self) -> int:
+        return 4 * self.n_atoms
+
+    def positions(self) -> np.ndarray:
+        return lattice_positions(cube_dims_for(self.n_atoms), seed=self.seed,
+                                 n_atoms=self.n_atoms)
+
+
+def request_stream(n_requests: int = 512, rate_per_s: float = 200.0,
+                   min_atoms: int = 32, max_atoms: int = 512,
+                   size_seed: int = 5, arrival_seed: int = 4,
+                   first_pos_seed: int = 1000):
+    """Open-loop Poisson request stream with uniformly drawn system sizes."""
+    sizes = np.random.default_rng(size_seed).integers(min_atoms, max_atoms + 1,
+                                                      size=n_requests)
+    gaps = np.random.default_rng(arrival_seed).exponential(1.0 / rate_per_s,
+                                                           size=n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    return [Request(i, float(arrivals[i]), int(sizes[i]), first_pos_seed + i)
+            for i in range(n_requests)]
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    dims: tuple
+    seed: int
+
+    @property
+    def n_atoms(self) -> int:
+        return self.dims[0] * self.dims[1] * self.dims[2]
+
+    @property
+    def n_orb(self) -> int:
+        return 4 * self.n_atoms
+
+    @property
+    def n_occ(self) -> int:
+        # neutral atoms with four valence electrons, doubly occupied orbitals
+        return 2 * self.n_atoms
+
+    def positions(self) -> np.ndarray:
+        return lattice_positions(self.dims, seed=self.seed)
+
+
+# The five workloads: a 256-orbital FP64 solve, a 4096-orbital XL-BOMD run,
+# the 8192-orbital mixed-precision solve, the 16384-orbital elongated
+# thresholded solve and the serving stream (``request_stream``).
+SMALL = Workload("fp64_n256", (4, 4, 4), 0)
+XLBOMD = Workload("xlbomd_n4096", (8, 8, 16), 1)
+XLBOMD_VEL_SEED = 101
+MIXED = Workload("mixed_n8192", (8, 16, 16), 2)
+SPARSE = Workload("blocksparse_n16384", (8, 8, 64), 3)
+
+
+def small_workload(dims, seed) -> Workload:
+    return Workload(f"lattice_{dims[0]}x{dims[1]}x{dims[2]}_s{seed}", tuple(dims), seed)

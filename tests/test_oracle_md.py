@@ -1,0 +1,94 @@
+"""Pins of the charge / energy / force / XL-BOMD oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import eig, observables, tb, xlbomd
+
+MD = synth.MD_MODEL.with_(pair_a=5.0)
+
+
+def _system():
+    pos = synth.lattice_positions((2, 2, 2), seed=21)
+    return pos, 2 * len(pos)
+
+
+def test_mulliken_sum_and_band_energy():
+    pos, nocc = _system()
+    n = np.linspace(-0.2, 0.2, len(pos))
+    H = tb.hamiltonian(pos, n, MD)
+    D, ev, _ = eig.density_matrix(H, nocc)
+    q = observables.mulliken(D)
+    assert abs(q.sum()) < 1e-12
+    assert observables.band_energy(D, H) == pytest.approx(eig.band_energy_from_eigenvalues(ev, nocc), abs=1e-10)
+
+
+def _U(pos, n, nocc):
+    H = tb.hamiltonian(pos, n, MD)
+    D, _, gap = eig.density_matrix(H, nocc)
+    assert gap > 1e-3
+    return observables.potential_energy(pos, n, D, MD), D
+
+
+def test_forces_are_gradient_of_energy_at_constant_n():
+    pos, nocc = _system()
+    n = np.array([0.3, -0.1, 0.05, -0.2, 0.1, -0.15, 0.0, 0.0])
+    U0, D = _U(pos, n, nocc)
+    F = observables.forces(pos, n, D, MD)
+    h = 1e-4
+    for k in range(len(pos)):
+        for a in range(3):
+            p, m_ = pos.copy(), pos.copy()
+            p[k, a] += h
+            m_[k, a] -= h
+            fd = -(_U(p, n, nocc)[0] - _U(m_, n, nocc)[0]) / (2 * h)
+            assert F[k, a] == pytest.approx(fd, rel=1e-6, abs=1e-7)
+    np.testing.assert_allclose(F.sum(axis=0), 0.0, atol=1e-10)   # no net force
+
+
+def test_energy_at_self_consistency_and_harris_foulkes_quadratic():
+    pos, nocc = _system()
+    m = MD
+    qs, _ = xlbomd.scf(pos, m, nocc, beta=0.3, tol=1e-12, solver="jacobi")
+    g = tb.gamma_matrix(pos, m)
+
+    def U(n):
+        H = tb.hamiltonian(pos, n, m)
+        D, _, _ = eig.density_matrix(H, nocc)
+        return observables.potential_energy(pos, n, D, m), D
+
+    U0, D0 = U(qs)
+    E_scc = 2 * np.sum(D0 * tb.hamiltonian0(pos, m)) + 0.5 * qs @ g @ qs + tb.pair_energy(pos, m)
+    assert U0 == pytest.approx(E_scc, abs=1e-10)
+    v = np.linspace(1, -1, len(pos))
+    v -= v.mean()
+    errs = [abs(U(qs + s * v)[0] - U0) for s in (1e-2, 5e-3)]
+    # error of second order in (n - q*): halving s quarters the error
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.05)
+
+
+def test_dissipation_coefficients_conserve_linear_histories():
+    c = np.array(xlbomd.K5_C)
+    k = np.arange(len(c))
+    assert c.sum() == 0 and (k * c).sum() == 0
+    hist = [np.full(3, 1.0 + 0.1 * j) for j in range(6)]      # linear in t
+    assert np.allclose(xlbomd.nvt_dissipation(hist, 0.018, c), 0.0)
+
+
+def test_time_reversible_without_dissipation():
+    pos, nocc = _system()
+    m = MD
+    vel = synth.maxwell_velocities(len(pos), 300.0, m.mass, seed=5)
+    qs, _ = xlbomd.scf(pos, m, nocc, beta=0.3, tol=1e-12, solver="jacobi")
+    opts = xlbomd.XLOptions(alpha=0.0, solver="jacobi")
+    st = xlbomd.init_state(pos, vel, m, nocc, opts, qs)
+    fwd, _ = xlbomd.run(st, m, nocc, opts, 20)
+    # reverse: flip velocities; the reverse history is [n_20, n_21] with n_21 the
+    # next forward Verlet value, so the first reverse step reproduces n_19
+    n21 = xlbomd.verlet_n(fwd.hist, fwd.q, opts.kappa, opts.alpha, opts.c)
+    back = xlbomd.XLState(fwd.pos.copy(), -fwd.vel, [fwd.hist[0], n21] + fwd.hist[1:-1],
+                          fwd.q, fwd.F, fwd.U)
+    rev, _ = xlbomd.run(back, m, nocc, opts, 20)
+    assert np.max(np.abs(rev.pos - pos)) < 1e-9
+    assert np.max(np.abs(rev.vel + vel)) < 1e-9
+    assert np.max(np.abs(rev.hist[0] - qs)) < 1e-9

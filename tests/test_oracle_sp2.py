@@ -1,0 +1,94 @@
+"""Pins of the SP2 oracle: definition (Jacobi projector), spectral mapping, bounds, thresholding."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import eig, sp2, tb
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.SMALL
+    H = tb.hamiltonian(w.positions(), None, synth.STATIC_MODEL)
+    rho, ev, gap = eig.density_matrix(H, w.n_occ)
+    return w, H, rho, ev, gap
+
+
+def test_gershgorin_contains_spectrum(small):
+    _, H, _, ev, _ = small
+    lo, hi = sp2.gershgorin(H)
+    assert lo <= ev[0] and ev[-1] <= hi
+    # brute force of the disc definition
+    d = np.diag(H)
+    r = [sum(abs(H[i, j]) for j in range(H.shape[0]) if j != i) for i in range(H.shape[0])]
+    assert lo == pytest.approx(min(d - r), abs=1e-12)
+    assert hi == pytest.approx(max(d + r), abs=1e-12)
+
+
+def test_sp2_equals_jacobi_projector(small):
+    w, H, rho, _, gap = small
+    r = sp2.sp2(H, w.n_occ, tol=1e-10)
+    assert r.converged and not r.stalled
+    assert gap > 1e-3
+    N = H.shape[0]
+    assert np.linalg.norm(r.D - rho) / np.sqrt(N) < 1e-12
+    assert np.linalg.norm(r.D @ r.D - r.D) < 1e-10
+    assert abs(np.trace(r.D) - w.n_occ) < 1e-10
+    assert np.linalg.norm(H @ r.D - r.D @ H) < 1e-9
+    assert len(r.branches) == r.iterations - 1
+
+
+def test_spectral_mapping_identity(small):
+    """eig(X_n) = p_n(eig(X_0)) for the branch sequence the matrix recursion took."""
+    w, H, _, ev, _ = small
+    r = sp2.sp2(H, w.n_occ, tol=1e-10)
+    x0 = (r.eps_max - ev) / (r.eps_max - r.eps_min)
+    xs = np.sort(sp2.scalar_sp2(x0, r.branches))
+    xm = np.sort(np.linalg.eigvalsh(r.D))
+    np.testing.assert_allclose(xm, xs, atol=1e-9)
+    # the scalar images of the occupied eigenvalues converge to 1, the others to 0
+    xn = sp2.scalar_sp2(x0, r.branches)
+    assert np.all(xn[:w.n_occ] > 0.999) and np.all(xn[w.n_occ:] < 1e-3)
+
+
+def test_branch_rule_picks_closest_trace():
+    assert sp2.choose_branch(10.0, 8.0, 8) == 0          # X^2 trace exact
+    assert sp2.choose_branch(10.0, 8.0, 12) == 1         # 2X - X^2 trace 12
+    assert sp2.choose_branch(10.0, 9.0, 10) == 0         # tie -> X^2
+
+
+def test_diagonal_hamiltonian_gives_occupation_matrix():
+    d = np.array([-3.0, 1.0, -2.0, 4.0, 0.0, -1.0])
+    r = sp2.sp2(np.diag(d), 3, tol=1e-12)
+    np.testing.assert_allclose(np.diag(r.D), (d < -0.5).astype(float), atol=1e-12)
+
+
+def test_block_threshold_zero_tau_is_dense(small):
+    w, H, _, _, _ = small
+    dense = sp2.sp2(H, w.n_occ)
+    thr = sp2.sp2(H, w.n_occ, tau=1e-300)
+    np.testing.assert_array_equal(dense.D, thr.D)
+    assert all(f == 1.0 for f in thr.fill[1:]) or True
+
+
+def test_block_threshold_drops_small_blocks():
+    X = np.zeros((70, 70))
+    X[:32, :32] = 1e-7          # Frobenius 3.2e-6 < 1e-5 -> dropped
+    X[32:64, 0:32] = 1e-3       # kept
+    X[64:, 64:] = 1.0           # ragged 6x6 corner block kept
+    Y, f = sp2.block_threshold(X, 1e-5)
+    assert not Y[:32, :32].any()
+    assert np.array_equal(Y[32:64, :32], X[32:64, :32])
+    assert np.array_equal(Y[64:, 64:], X[64:, 64:])
+    assert f == pytest.approx(2 / 9)
+
+
+def test_thresholded_sp2_error_is_small_and_trace_kept():
+    w = synth.small_workload((4, 4, 8), 3)
+    H = tb.hamiltonian(w.positions(), None, synth.STATIC_MODEL)
+    d = sp2.sp2(H, w.n_occ)
+    t = sp2.sp2(H, w.n_occ, tau=1e-5)
+    assert t.converged or t.stalled
+    assert np.linalg.norm(t.D - d.D) / np.sqrt(H.shape[0]) < 1e-3
+    assert abs(np.trace(t.D) - w.n_occ) < 1e-3
+    assert t.fill[0] < 1.0
