@@ -1,0 +1,173 @@
+"""Benchmark: SP2 density-matrix solves at N = 8192 on one MI355X.
+
+One step = one whole solve of the 2048-atom (8 x 16 x 16 lattice) synthetic
+tight-binding Hamiltonian, N = 8192 orbitals, n_occ = 4096: Gershgorin bounds,
+X_0, every SP2 product with its fused update, the control steps, the copy-out
+of D, then Mulliken charges and the band energy.  H is built on the GPU
+(tb_hamiltonian) and resident in HBM before the timed region.
+
+Reported (one JSON line): useful SP2 TFLOP/s (2 N^3 per product, the
+GEMM-equivalent count) and solves/s of the reduced-precision path, the plain
+FP64 GPU path beside it, the error of D against the FP64 path, a roofline
+record of the dominant kernel measured with HIP events inside the timed
+region, and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision int8x|fp64|bf16x2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "int8x": 5000.0, "bf16x2": 2500.0}   # TFLOP/s (TOP/s for int8), dense
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(H_np, n_occ, n_products=2):
+    """The oracle's SP2 loop (numpy/OpenBLAS) on a bounded sample: n_products products."""
+    from oracle import sp2 as osp2
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    N = H_np.shape[0]
+    t0 = time.perf_counter()
+    osp2.sp2(H_np, n_occ, max_iter=n_products)
+    dt = time.perf_counter() - t0
+    return {"value": round(2.0 * N ** 3 * n_products / dt / 1e12, 4), "unit": "TFLOP/s",
+            "cores": int(cores), "kind": "oracle",
+            "sample": f"{n_products} SP2 products (X^2 via numpy/OpenBLAS FP64) of the same N={N} "
+                      f"Hamiltonian, {dt:.1f} s; GEMM-equivalent 2N^3 flops per product"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="int8x", choices=["int8x", "fp64", "bf16x2"])
+    ap.add_argument("--slices", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1203_6836_amd as p
+    import synth
+
+    w = synth.MIXED
+    N, nocc = w.n_orb, w.n_occ
+    ctx = p.Context(0)
+    xyz = torch.from_numpy(w.positions()).cuda()
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, xyz)
+    D = torch.empty_like(H)
+    torch.cuda.synchronize()
+
+    def solve(prec, Dout):
+        opts = p.options(prec, slices=args.slices) if prec == "int8x" else p.options(prec)
+        Dout, st = ctx.sp2_density_matrix(H, nocc, opts, D_out=Dout)
+        q = ctx.sp2_mulliken(Dout, w.n_atoms)
+        e = ctx.sp2_band_energy(Dout, H)
+        return st, q, e
+
+    # ---- plain FP64 GPU path (reference speed and D_fp64) ----
+    log(f"fp64 path: N={N}")
+    D64 = torch.empty_like(H)
+    solve("fp64", D64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        st64, q64, e64 = solve("fp64", D64)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / args.fp64_steps
+    tflops64 = 2.0 * N ** 3 * st64["iterations"] / (ms64 * 1e-3) / 1e12
+    log(f"  fp64: {ms64:.1f} ms/solve, {st64['iterations']} products, {tflops64:.2f} TFLOP/s")
+
+    prec = args.precision
+    log(f"{prec} path: warmup {args.warmup}, steps {args.steps}")
+    for _ in range(args.warmup):
+        solve(prec, D)
+    ctx.sp2_ctx_set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        st, q, e = solve(prec, D)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.sp2_ctx_set_profiling(False)
+    ms = dt * 1e3 / args.steps
+    iters = stats[-1]["iterations"]
+    tflops = 2.0 * N ** 3 * iters / (ms * 1e-3) / 1e12
+
+    # error of D against the FP64 GPU path (itself pinned to the oracle in tests)
+    err = float(torch.linalg.norm(D - D64)) / N ** 0.5
+    dq = float((q - q64).abs().max())
+    idem = float(torch.linalg.norm(D @ D - D))
+
+    # roofline of the dominant kernel: the product kernel of this precision
+    k = 0 if prec == "fp64" else 1
+    cnt = sum(s["prod_count"][k] for s in stats)
+    kms = sum(s["prod_ms"][k] for s in stats) / max(cnt, 1)
+    sym_flops = float(N) * N * (N + 1)          # distinct entries of a symmetric product
+    if prec == "int8x":
+        pairs = args.slices * (args.slices + 1) // 2
+        achieved = pairs * sym_flops / (kms * 1e-3) / 1e12
+        unit = "TOP/s"
+    elif prec == "bf16x2":
+        achieved = 3 * sym_flops / (kms * 1e-3) / 1e12
+        unit = "TFLOP/s"
+    else:
+        achieved = sym_flops / (kms * 1e-3) / 1e12
+        unit = "TFLOP/s"
+    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK[prec], "unit": unit,
+            "frac": round(achieved / PEAK[prec], 4), "traffic": None,
+            "kernel": "k_gemm_f64" if prec == "fp64" else ("k_gemm_int8x" if prec == "int8x" else "k_gemm_bf16x2"),
+            "kernel_ms_avg": round(kms, 4), "launches": cnt}
+
+    out = {
+        "metric": "SP2 TFLOP/s & solves/s (mixed vs FP64) at N=8192; p50/p99 served latency",
+        "value": round(tflops, 3), "unit": "TFLOP/s (useful, 2N^3 per SP2 product)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"int8x": "i8 (int32 accumulation, f64 combine)", "fp64": "f64",
+                  "bf16x2": "bf16 (f32 accumulation)"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "mixed_n8192: 2048-atom 8x16x16 jittered sp tight-binding lattice, "
+                               "N=8192, n_occ=4096", "precision": prec,
+                   "slices": args.slices if prec == "int8x" else None},
+        "solves_per_s": round(1e3 / ms, 4),
+        "products": iters,
+        "fp64_path": {"ms_per_solve": round(ms64, 2), "tflops": round(tflops64, 3),
+                      "products": st64["iterations"]},
+        "speedup_vs_fp64": round(ms64 / ms, 3),
+        "err_vs_fp64_per_sqrtN": err, "max_dq_vs_fp64": dq, "idempotency": idem,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(H.cpu().numpy(), nocc)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/* sp2qmd — zero-temperature density matrices by SP2 purification on MI355X,
+ * with the charge, energy, force and extended-Lagrangian (XL-BOMD) steps of
+ * Niklasson & Cawkwell, "Fast method for quantum mechanical molecular
+ * dynamics" (orthogonal self-consistent-charge tight binding, T_e = 0).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are dense, N x N, row-major, FP64, leading dimension N.
+ * - Every array argument is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *   tensor) on the context's device, unless the name ends in _host.  The
+ *   caller owns all arrays; the library never frees or retains them.  Inputs
+ *   are only read; outputs are written only when SP2_OK is returned (stats
+ *   structs are always filled).
+ * - All work is enqueued on the context's stream.  Functions that return
+ *   host values (stats, energies, *_host outputs) synchronise that stream
+ *   before returning.
+ * - Orbitals are atom-major: orbital index = 4 * atom + {s, px, py, pz}.
+ * - No exception crosses this ABI.  On error a status < 0 is returned and a
+ *   message is kept in the context (sp2_last_error).
+ * - A context is used by one host thread at a time.
+ */
+#ifndef SP2QMD_H
+#define SP2QMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SP2_OK = 0,
+    SP2_EINVAL = -1,    /* bad argument (size, pointer, option)              */
+    SP2_ENOMEM = -2,    /* device allocation failed                          */
+    SP2_EDEVICE = -3,   /* HIP runtime error                                 */
+    SP2_ENOCONV = -4,   /* SP2 reached max_iter without converging/stalling  */
+    SP2_EBUDGET = -6,   /* serving: request larger than the memory budget    */
+    SP2_ETIMEOUT = -8   /* serving: wait timed out                           */
+} sp2_status;
+
+/* Arithmetic of the SP2 products X_n^2 (the update, traces, branch and stop
+ * decisions are FP64 in every mode). */
+typedef enum {
+    SP2_PREC_FP64 = 0,   /* FP64 MFMA products                                   */
+    SP2_PREC_INT8X = 1,  /* FP64 master X split into `slices` row-scaled int8
+                            digit planes; all digit products with level t+u <
+                            slices on int8 MFMA with exact int32 accumulation,
+                            levels combined in FP64                             */
+    SP2_PREC_BF16X2 = 2  /* BF16 hi+lo split with FP32 MFMA accumulation, FP32
+                            master, then `fp32_tail` FP32 iterations            */
+} sp2_precision;
+
+typedef struct {
+    int precision;       /* sp2_precision                                        */
+    int max_iter;        /* products before SP2_ENOCONV (default 100)            */
+    double idem_tol;     /* stop when ||X_n^2 - X_n||_F < idem_tol (1e-10)       */
+    double stall_tol;    /* also stop when n >= 4, e_n >= e_{n-2}, e_n < stall_tol
+                            (idempotency error at its rounding floor; 1e-2)      */
+    int fp64_head;       /* INT8X: first products done in FP64 (default 0)      */
+    int slices;          /* INT8X: digit planes, 2..6 (default 5)                */
+    int fp32_tail;       /* BF16X2: FP32 iterations after the BF16 stage stalls
+                            (default 3)                                          */
+    double tau;          /* block threshold: after every update zero each
+                            32x32 block with Frobenius norm < tau (0 = dense)    */
+} sp2_options;
+
+typedef struct {
+    int iterations;          /* products X_n^2 formed                            */
+    int status;              /* 0 converged, 1 stalled, 2 max_iter               */
+    int fp64_products;       /* of which in FP64                                 */
+    int head_switch;         /* product index where the precision switched (-1)  */
+    double eps_min, eps_max; /* Gershgorin bounds used for X_0                   */
+    double idem_err;         /* ||X^2 - X||_F of the last product formed         */
+    double trace;            /* Tr D                                             */
+    uint64_t branch_bits[2]; /* bit n set: update n was X <- 2X - X^2            */
+    double ms;               /* wall time of the solve on the stream (ms)        */
+    double fill_min, fill_max; /* block-thresholded: kept-block fraction range   */
+    float idem_hist[128];    /* ||X_n^2 - X_n||_F of product n                   */
+    float fill_hist[128];    /* kept-block fraction after update n (tau > 0)     */
+    /* Filled only when profiling is on (sp2_ctx_set_profiling): summed HIP-event
+     * durations of the product kernels that formed products, [0] FP64 product
+     * kernel, [1] reduced-precision product kernel, and their launch counts;
+     * encode_ms: operand encoding; post_ms: block-threshold passes. */
+    double prod_ms[2];
+    int prod_count[2];
+    double encode_ms, post_ms;
+} sp2_stats;
+
+typedef struct sp2_ctx sp2_ctx;
+
+/* Fill *opt with the defaults listed above (precision FP64). */
+void sp2_options_default(sp2_options *opt);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (NULL: the null stream).  Library scratch (padded X buffers,
+ * partial sums, control state) is owned by the context and grows on demand. */
+sp2_status sp2_ctx_create(sp2_ctx **out, int device, void *hip_stream);
+void sp2_ctx_destroy(sp2_ctx *ctx);
+sp2_status sp2_ctx_set_stream(sp2_ctx *ctx, void *hip_stream);
+/* on != 0: bracket every product kernel with HIP events on the context's
+ * stream and report their durations in sp2_stats (small launch overhead). */
+sp2_status sp2_ctx_set_profiling(sp2_ctx *ctx, int on);
+const char *sp2_strerror(int status);
+const char *sp2_last_error(const sp2_ctx *ctx);
+
+/* Density matrix D = theta(mu0 I - H) with Tr D = n_occ by SP2 purification
+ * (Linear scaling section; orthogonal T_e = 0 subsection: the step function
+ * of the Hamiltonian).  H: N x N symmetric (device); D_out: N x N (device).
+ * 0 < n_occ < N.  opt NULL = defaults.  stats may be NULL.
+ * Returns SP2_ENOCONV if neither stop rule fired within max_iter products
+ * (D_out is then not written). */
+sp2_status sp2_density_matrix(sp2_ctx *ctx, int N, const double *H, int n_occ,
+                              const sp2_options *opt, double *D_out,
+                              sp2_stats *stats);
+
+/* Net Mulliken charges of an orthogonal basis (net-charge equation of the
+ * SCC-TB subsection, S = I): q_i = 2 sum_{alpha in atom i} D_{i alpha,i alpha}
+ * - z_val (electron excess).  D: (4 n_atoms)^2 device; q_out: n_atoms device. */
+sp2_status sp2_mulliken(sp2_ctx *ctx, int n_atoms, const double *D, double z_val,
+                        double *q_out);
+
+/* Band energy 2 Tr[D H] (doubly occupied orbitals, Eq. DFT_POT) returned on
+ * the host.  D, H: N x N device. */
+sp2_status sp2_band_energy(sp2_ctx *ctx, int N, const double *D, const double *H,
+                           double *e_host);
+
+/* ---------------------------------------------------------------------
+ * Tight-binding model, forces and XL-BOMD
+ * ------------------------------------------------------------------- */
+
+/* Parameters of the orthogonal sp tight-binding model (SCC-TB subsection):
+ * hopping |t(r)| = t0 exp(-(r - r0)/lam) for r < r_tail, a quintic tail on
+ * [r_tail, r_cut) matching value, slope and curvature at r_tail and vanishing
+ * with them at r_cut (r_tail == r_cut: hard cut); bond-integral signs
+ * ss-sigma < 0, sp-sigma > 0, pp-sigma > 0, pp-pi < 0; gamma_ii = hubbard_u,
+ * gamma_ij = coulomb_k / r_ij; pair repulsion pair_a exp(-(r - pair_r0) /
+ * pair_rho) with the same tail (pair_a = 0: none). */
+typedef struct {
+    double eps_s, eps_p;
+    double t0, r0, lam;
+    double r_cut, r_tail;
+    double hubbard_u, coulomb_k;
+    double pair_a, pair_r0, pair_rho;
+    double mass;      /* amu, all atoms */
+    double z_val;     /* valence electrons per neutral atom */
+} tb_params;
+
+/* H[n] = h(R) + diag over the four orbitals of atom i of V_i, V = gamma n
+ * (Eq. DFTB_2 with S = I).  xyz: 3 n_atoms device (A); n_aux: n_atoms device
+ * or NULL (then H = h); H_out: (4 n_atoms)^2 device. */
+sp2_status tb_hamiltonian(sp2_ctx *ctx, const tb_params *p, int n_atoms,
+                          const double *xyz, const double *n_aux, double *H_out);
+
+/* Forces at constant auxiliary charges n (Eq. EL_Orth_a with Eq. EL_Orth_c,
+ * on-site term read with rho - rho0):
+ *   F_k = -2 Tr[D dh/dR_k] - sum_ij (q_i n_j - n_i n_j / 2) dgamma_ij/dR_k
+ *         - dE_pair/dR_k,
+ * and the potential energy U = 2 Tr[D h] + q.V - n.V/2 + E_pair, V = gamma n
+ * (Eq. HF_POT_2 in charge form).  D: (4 n_atoms)^2 device; q, n: n_atoms
+ * device; F_out: 3 n_atoms device (may be NULL); U_host may be NULL. */
+sp2_status tb_forces(sp2_ctx *ctx, const tb_params *p, int n_atoms,
+                     const double *xyz, const double *D, const double *q,
+                     const double *n_aux, double *F_out, double *U_host);
+
+typedef struct {
+    double dt_fs;     /* time step (fs)                                        */
+    double kappa;     /* delta t^2 omega^2 of Eq. Verl_n                        */
+    double alpha;     /* dissipation strength                                  */
+    int K;            /* dissipation order, history length K + 1 (<= 8)        */
+    double c[9];      /* c_0 .. c_K                                            */
+    sp2_options sp2;  /* density-matrix options for the one solve per step     */
+} xlbomd_options;
+
+typedef struct {
+    double etot, epot, ekin;   /* eV                                           */
+    double max_q_minus_n;      /* max_i |q_i - n_i| at the step                 */
+    int sp2_iterations;
+} xlbomd_record;
+
+typedef struct xlbomd xlbomd;
+
+/* Create an XL-BOMD integrator (General remarks subsection: velocity Verlet
+ * for the nuclei, Eq. Verl_n for the auxiliary charges, one density matrix
+ * per step, no SCF).  xyz, vel (A, A/fs) and n0 are HOST arrays copied in;
+ * n0 is used for the whole initial history (n = q from a converged start). */
+sp2_status xlbomd_create(sp2_ctx *ctx, const tb_params *p, const xlbomd_options *o,
+                         int n_atoms, const double *xyz_host, const double *vel_host,
+                         const double *n0_host, xlbomd **out);
+/* Advance n_steps; log (host, n_steps entries) may be NULL. */
+sp2_status xlbomd_run(xlbomd *md, int n_steps, xlbomd_record *log);
+/* Copy current positions, velocities, charges q and n_t to host arrays (any may be NULL). */
+sp2_status xlbomd_get(xlbomd *md, double *xyz_host, double *vel_host,
+                      double *q_host, double *n_host);
+void xlbomd_destroy(xlbomd *md);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SP2QMD_H */

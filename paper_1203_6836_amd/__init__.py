@@ -1,0 +1,297 @@
+"""Python binding of libsp2qmd (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch CUDA
+tensors to device pointers, fills the C structs of ``include/sp2qmd.h`` and
+raises on error statuses.  If the library is not built, importing the module
+still works but every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsp2qmd.so")
+
+SP2_OK, SP2_EINVAL, SP2_ENOMEM, SP2_EDEVICE, SP2_ENOCONV = 0, -1, -2, -3, -4
+SP2_EBUDGET, SP2_ETIMEOUT = -6, -8
+PREC_FP64, PREC_INT8X, PREC_BF16X2 = 0, 1, 2
+PRECISIONS = {"fp64": PREC_FP64, "int8x": PREC_INT8X, "bf16x2": PREC_BF16X2}
+
+
+class Sp2Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("idem_tol", ctypes.c_double), ("stall_tol", ctypes.c_double),
+                ("fp64_head", ctypes.c_int), ("slices", ctypes.c_int),
+                ("fp32_tail", ctypes.c_int), ("tau", ctypes.c_double)]
+
+
+class Sp2Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("status", ctypes.c_int),
+                ("fp64_products", ctypes.c_int), ("head_switch", ctypes.c_int),
+                ("eps_min", ctypes.c_double), ("eps_max", ctypes.c_double),
+                ("idem_err", ctypes.c_double), ("trace", ctypes.c_double),
+                ("branch_bits", ctypes.c_uint64 * 2), ("ms", ctypes.c_double),
+                ("fill_min", ctypes.c_double), ("fill_max", ctypes.c_double),
+                ("idem_hist", ctypes.c_float * 128), ("fill_hist", ctypes.c_float * 128),
+                ("prod_ms", ctypes.c_double * 2), ("prod_count", ctypes.c_int * 2),
+                ("encode_ms", ctypes.c_double), ("post_ms", ctypes.c_double)]
+
+    def to_dict(self):
+        n = self.iterations
+        bits = [(self.branch_bits[k >> 6] >> (k & 63)) & 1 for k in range(max(n - 1, 0))]
+        return {"iterations": n, "status": ["converged", "stalled", "max_iter"][self.status],
+                "fp64_products": self.fp64_products, "head_switch": self.head_switch,
+                "eps_min": self.eps_min, "eps_max": self.eps_max, "idem_err": self.idem_err,
+                "trace": self.trace, "branches": bits, "ms": self.ms,
+                "fill_min": self.fill_min, "fill_max": self.fill_max,
+                "idem_hist": [float(self.idem_hist[k]) for k in range(n)],
+                "fill_hist": [float(self.fill_hist[k]) for k in range(n)],
+                "prod_ms": [self.prod_ms[0], self.prod_ms[1]],
+                "prod_count": [self.prod_count[0], self.prod_count[1]],
+                "encode_ms": self.encode_ms, "post_ms": self.post_ms}
+
+
+class TBParams(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in
+                ("eps_s", "eps_p", "t0", "r0", "lam", "r_cut", "r_tail", "hubbard_u",
+                 "coulomb_k", "pair_a", "pair_r0", "pair_rho", "mass", "z_val")]
+
+
+class XLOptions(ctypes.Structure):
+    _fields_ = [("dt_fs", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("K", ctypes.c_int),
+                ("c", ctypes.c_double * 9), ("sp2", Sp2Options)]
+
+
+class XLRecord(ctypes.Structure):
+    _fields_ = [("etot", ctypes.c_double), ("epot", ctypes.c_double),
+                ("ekin", ctypes.c_double), ("max_q_minus_n", ctypes.c_double),
+                ("sp2_iterations", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_SIGS = {
+    "sp2_options_default": (None, [ctypes.POINTER(Sp2Options)]),
+    "sp2_ctx_create": (_I, [ctypes.POINTER(_P), _I, _P]),
+    "sp2_ctx_destroy": (None, [_P]),
+    "sp2_ctx_set_stream": (_I, [_P, _P]),
+    "sp2_ctx_set_profiling": (_I, [_P, _I]),
+    "sp2_strerror": (ctypes.c_char_p, [_I]),
+    "sp2_last_error": (ctypes.c_char_p, [_P]),
+    "sp2_density_matrix": (_I, [_P, _I, _P, _I, ctypes.POINTER(Sp2Options), _P,
+                                ctypes.POINTER(Sp2Stats)]),
+    "sp2_mulliken": (_I, [_P, _I, _P, _D, _P]),
+    "sp2_band_energy": (_I, [_P, _I, _P, _P, ctypes.POINTER(_D)]),
+    "tb_hamiltonian": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P]),
+    "tb_forces": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P, _P,
+                       ctypes.POINTER(_D)]),
+    "xlbomd_create": (_I, [_P, ctypes.POINTER(TBParams), ctypes.POINTER(XLOptions), _I,
+                           _P, _P, _P, ctypes.POINTER(_P)]),
+    "xlbomd_run": (_I, [_P, _I, ctypes.POINTER(XLRecord)]),
+    "xlbomd_get": (_I, [_P, _P, _P, _P, _P]),
+    "xlbomd_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsp2qmd.so; raises if it is not built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_1203_6836_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class Sp2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def options(precision="fp64", **kw) -> Sp2Options:
+    o = Sp2Options()
+    lib().sp2_options_default(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def tb_params(model) -> TBParams:
+    """TBParams from any object with the synth.TBModel fields."""
+    p = TBParams()
+    for f, _ in TBParams._fields_:
+        setattr(p, f, float(getattr(model, f)))
+    return p
+
+
+class Context:
+    """A library context bound to a device and a stream (torch's current by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._h = ctypes.c_void_p()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        st = lib().sp2_ctx_create(ctypes.byref(self._h), int(device), ctypes.c_void_p(handle))
+        if st != SP2_OK:
+            raise Sp2Error(st, "sp2_ctx_create: " + lib().sp2_strerror(st).decode())
+        self.device = device
+
+    def _check(self, st, what):
+        if st != SP2_OK:
+            raise Sp2Error(st, f"{what}: {lib().sp2_last_error(self._h).decode()}")
+
+    def close(self):
+        if self._h:
+            lib().sp2_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- entry points (same names as the C-ABI) ----
+    def sp2_ctx_set_profiling(self, on: bool):
+        self._check(lib().sp2_ctx_set_profiling(self._h, 1 if on else 0), "sp2_ctx_set_profiling")
+
+    def sp2_density_matrix(self, H, n_occ: int, opts: Sp2Options | None = None, D_out=None):
+        import torch
+        N = H.shape[0]
+        if H.shape != (N, N):
+            raise ValueError("H must be square")
+        if D_out is None:
+            D_out = torch.empty_like(H)
+        stats = Sp2Stats()
+        st = lib().sp2_density_matrix(self._h, N, _ptr(H), int(n_occ),
+                                      ctypes.byref(opts) if opts is not None else None,
+                                      _ptr(D_out), ctypes.byref(stats))
+        self._check(st, "sp2_density_matrix")
+        return D_out, stats.to_dict()
+
+    def sp2_density_matrix_status(self, H, n_occ: int, opts: Sp2Options | None = None):
+        """Raw status + stats (for error-path tests)."""
+        import torch
+        D = torch.empty_like(H)
+        stats = Sp2Stats()
+        st = lib().sp2_density_matrix(self._h, H.shape[0], _ptr(H), int(n_occ),
+                                      ctypes.byref(opts) if opts is not None else None,
+                                      _ptr(D), ctypes.byref(stats))
+        return st, stats.to_dict()
+
+    def sp2_mulliken(self, D, n_atoms: int, z_val: float = 4.0, q_out=None):
+        import torch
+        if q_out is None:
+            q_out = torch.empty(n_atoms, dtype=torch.float64, device=D.device)
+        self._check(lib().sp2_mulliken(self._h, int(n_atoms), _ptr(D), float(z_val), _ptr(q_out)),
+                    "sp2_mulliken")
+        return q_out
+
+    def sp2_band_energy(self, D, H) -> float:
+        e = ctypes.c_double()
+        self._check(lib().sp2_band_energy(self._h, D.shape[0], _ptr(D), _ptr(H), ctypes.byref(e)),
+                    "sp2_band_energy")
+        return e.value
+
+    def tb_hamiltonian(self, model, xyz, n_aux=None, H_out=None):
+        import torch
+        nat = xyz.shape[0]
+        if H_out is None:
+            H_out = torch.empty((4 * nat, 4 * nat), dtype=torch.float64, device=xyz.device)
+        p = tb_params(model)
+        self._check(lib().tb_hamiltonian(self._h, ctypes.byref(p), nat, _ptr(xyz), _ptr(n_aux),
+                                         _ptr(H_out)), "tb_hamiltonian")
+        return H_out
+
+    def tb_forces(self, model, xyz, D, q, n_aux, F_out=None):
+        import torch
+        nat = xyz.shape[0]
+        if F_out is None:
+            F_out = torch.empty((nat, 3), dtype=torch.float64, device=xyz.device)
+        U = ctypes.c_double()
+        p = tb_params(model)
+        self._check(lib().tb_forces(self._h, ctypes.byref(p), nat, _ptr(xyz), _ptr(D), _ptr(q),
+                                    _ptr(n_aux), _ptr(F_out), ctypes.byref(U)), "tb_forces")
+        return F_out, U.value
+
+    def xlbomd_create(self, model, xyz, vel, n0, dt_fs=0.25, kappa=0.91, alpha=0.018,
+                      c=(-6.0, 14.0, -8.0, -3.0, 4.0, -1.0), sp2_opts=None):
+        return XLBOMD(self, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts)
+
+
+class XLBOMD:
+    """Handle of an xlbomd integrator; host numpy arrays in, host numpy arrays out."""
+
+    def __init__(self, ctx, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts):
+        self.ctx = ctx
+        self.nat = len(xyz)
+        o = XLOptions()
+        o.dt_fs, o.kappa, o.alpha, o.K = dt_fs, kappa, alpha, len(c) - 1
+        for k, ck in enumerate(c):
+            o.c[k] = ck
+        o.sp2 = sp2_opts if sp2_opts is not None else options("fp64")
+        p = tb_params(model)
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        n0 = np.ascontiguousarray(n0, dtype=np.float64)
+        self._h = ctypes.c_void_p()
+        st = lib().xlbomd_create(ctx._h, ctypes.byref(p), ctypes.byref(o), self.nat,
+                                 xyz.ctypes.data_as(_P), vel.ctypes.data_as(_P),
+                                 n0.ctypes.data_as(_P), ctypes.byref(self._h))
+        ctx._check(st, "xlbomd_create")
+
+    def xlbomd_run(self, n_steps: int):
+        recs = (XLRecord * max(n_steps, 1))()
+        self.ctx._check(lib().xlbomd_run(self._h, int(n_steps), recs), "xlbomd_run")
+        return [{"etot": r.etot, "epot": r.epot, "ekin": r.ekin,
+                 "max_q_minus_n": r.max_q_minus_n, "sp2_iterations": r.sp2_iterations}
+                for r in recs[:n_steps]]
+
+    def xlbomd_get(self):
+        xyz = np.empty((self.nat, 3))
+        vel = np.empty((self.nat, 3))
+        q = np.empty(self.nat)
+        n = np.empty(self.nat)
+        self.ctx._check(lib().xlbomd_get(self._h, xyz.ctypes.data_as(_P), vel.ctypes.data_as(_P),
+                                         q.ctypes.data_as(_P), n.ctypes.data_as(_P)), "xlbomd_get")
+        return xyz, vel, q, n
+
+    def close(self):
+        if self._h:
+            lib().xlbomd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

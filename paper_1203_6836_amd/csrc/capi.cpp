@@ -1,0 +1,589 @@
+// C-ABI of the sp2qmd library: argument checking, scratch management and the
+// host-side sequencing of the HIP kernels.  Every numerical step runs on the
+// GPU; the host only enqueues kernels and reads small control records.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sp2qmd.h"
+#include "sp2_internal.h"
+#include "split_internal.h"
+#include "tb_internal.h"
+
+using namespace sp2;
+
+namespace {
+
+// eV / A / amu / fs unit system
+constexpr double kAccAFs2 = 9.648533212e-3;  // 1 eV/(A amu) in A/fs^2
+constexpr double kKeEv = 103.6426965;        // 1 amu A^2/fs^2 in eV
+
+}  // namespace
+
+struct sp2_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // SP2 scratch
+    double* xbuf = nullptr;   // 2 * ld * ld
+    size_t xcap = 0;          // elements per buffer
+    double* part = nullptr;
+    size_t partcap = 0;
+    State* st = nullptr;
+    State* st_host = nullptr; // pinned
+    double* scal = nullptr;   // device scalars
+    double* scal_host = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    SplitScratch split;       // reduced-precision operands
+    bool profile = false;
+    std::vector<hipEvent_t> pev;  // 4 per product launch when profiling
+    // TB scratch
+    double* V = nullptr;
+    double* eatom = nullptr;
+    double* qtmp = nullptr;
+    size_t natcap = 0;
+};
+
+static sp2_status fail(sp2_ctx* c, sp2_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(c, expr)                                                                    \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return fail((c), SP2_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
+    } while (0)
+
+static sp2_status grow(sp2_ctx* c, void** p, size_t* cap, size_t need_bytes) {
+    if (*cap >= need_bytes && *p) return SP2_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc(p, need_bytes) != hipSuccess) {
+        *p = nullptr;
+        return fail(c, SP2_ENOMEM, "device allocation of " + std::to_string(need_bytes) + " bytes failed");
+    }
+    *cap = need_bytes;
+    return SP2_OK;
+}
+
+extern "C" {
+
+void sp2_options_default(sp2_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = SP2_PREC_FP64;
+    o->max_iter = 100;
+    o->idem_tol = 1e-10;
+    o->stall_tol = 1e-2;
+    o->fp64_head = 0;
+    o->slices = 5;
+    o->fp32_tail = 3;
+    o->tau = 0.0;
+}
+
+const char* sp2_strerror(int s) {
+    switch (s) {
+        case SP2_OK: return "ok";
+        case SP2_EINVAL: return "invalid argument";
+        case SP2_ENOMEM: return "device out of memory";
+        case SP2_EDEVICE: return "HIP runtime error";
+        case SP2_ENOCONV: return "SP2 did not converge within max_iter";
+        case SP2_EBUDGET: return "request exceeds the memory budget";
+        case SP2_ETIMEOUT: return "timed out";
+        default: return "unknown status";
+    }
+}
+
+const char* sp2_last_error(const sp2_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+sp2_status sp2_ctx_create(sp2_ctx** out, int device, void* stream) {
+    if (!out) return SP2_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SP2_EDEVICE;
+    if (device < 0 || device >= ndev) return SP2_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SP2_EDEVICE;
+    sp2_ctx* c = new sp2_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (hipMalloc((void**)&c->st, sizeof(State)) != hipSuccess ||
+        hipHostMalloc((void**)&c->st_host, sizeof(State), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&c->scal, 64 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&c->scal_host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        sp2_ctx_destroy(c);
+        return SP2_EDEVICE;
+    }
+    *out = c;
+    return SP2_OK;
+}
+
+void sp2_ctx_destroy(sp2_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->V, c->eatom, c->qtmp};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    split_free(c->split);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->scal_host) (void)hipHostFree(c->scal_host);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (hipEvent_t e : c->pev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+sp2_status sp2_ctx_set_stream(sp2_ctx* c, void* stream) {
+    if (!c) return SP2_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return SP2_OK;
+}
+
+sp2_status sp2_ctx_set_profiling(sp2_ctx* c, int on) {
+    if (!c) return SP2_EINVAL;
+    if (on && c->pev.empty()) {
+        if (hipSetDevice(c->device) != hipSuccess) return SP2_EDEVICE;
+        c->pev.resize(4 * kMaxIter, nullptr);
+        for (hipEvent_t& e : c->pev)
+            if (hipEventCreate(&e) != hipSuccess) return SP2_EDEVICE;
+    }
+    c->profile = on != 0;
+    return SP2_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- SP2 solve
+static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
+    if (o.precision < SP2_PREC_FP64 || o.precision > SP2_PREC_BF16X2)
+        return fail(c, SP2_EINVAL, "unknown precision");
+    if (o.max_iter < 1 || o.max_iter > kMaxIter)
+        return fail(c, SP2_EINVAL, "max_iter must be in [1, 128]");
+    if (!(o.idem_tol > 0.0) || !(o.stall_tol > 0.0)) return fail(c, SP2_EINVAL, "tolerances must be > 0");
+    if (o.precision == SP2_PREC_INT8X && (o.slices < 2 || o.slices > kMaxSlices))
+        return fail(c, SP2_EINVAL, "slices must be in [2, 6]");
+    if (o.fp64_head < 0) return fail(c, SP2_EINVAL, "fp64_head must be >= 0");
+    if (o.precision == SP2_PREC_BF16X2 && o.fp32_tail < 0) return fail(c, SP2_EINVAL, "fp32_tail must be >= 0");
+    if (!(o.tau >= 0.0)) return fail(c, SP2_EINVAL, "tau must be >= 0");
+    if (o.tau > 0.0 && o.precision != SP2_PREC_FP64)
+        return fail(c, SP2_EINVAL, "block thresholding runs with FP64 products only");
+    (void)N;
+    return SP2_OK;
+}
+
+// Enqueue and run one SP2 solve of H (device, N x N) into D (device).
+static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const sp2_options& o, double* D,
+                            sp2_stats* stats) {
+    const int ld = ((N + kTile - 1) / kTile) * kTile;
+    const size_t ld2 = (size_t)ld * ld;
+    const int nt = ld / kTile;
+    const size_t nslot_max = std::max<size_t>({(size_t)(N + 3) / 4 * 2, (size_t)ld / 4 * 3,
+                                               (size_t)tri_tiles(nt) * 3, 1024, split_part_slots(ld) * 3});
+    sp2_status s;
+    size_t xbytes = c->xcap * sizeof(double) * 2;
+    if ((s = grow(c, (void**)&c->xbuf, &xbytes, 2 * ld2 * sizeof(double))) != SP2_OK) return s;
+    c->xcap = xbytes / (2 * sizeof(double));
+    size_t pbytes = c->partcap * sizeof(double);
+    if ((s = grow(c, (void**)&c->part, &pbytes, nslot_max * sizeof(double))) != SP2_OK) return s;
+    c->partcap = pbytes / sizeof(double);
+    double* buf0 = c->xbuf;
+    double* buf1 = c->xbuf + ld2;
+    const bool int8x = o.precision == SP2_PREC_INT8X;
+    const bool bf16x = o.precision == SP2_PREC_BF16X2;
+    if (int8x || bf16x) {
+        if ((s = (sp2_status)split_reserve(c->split, ld, int8x ? o.slices : 0, bf16x)) != SP2_OK)
+            return fail(c, SP2_ENOMEM, "device allocation for split operands failed");
+    }
+
+    CtrlArgs a;
+    a.n_occ = (double)n_occ;
+    a.idem_tol = o.idem_tol;
+    a.stall_tol = o.stall_tol;
+    a.max_iter = o.max_iter;
+    a.fp64_head = (int8x || bf16x) ? o.fp64_head : -1;
+    a.fp32_tail = o.fp32_tail;
+    a.mixed = int8x ? 1 : (bf16x ? 2 : 0);
+    const double nb = (double)((N + 31) / 32);
+    a.total_blocks = o.tau > 0.0 ? nb * nb : 0.0;
+
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipEventRecord(c->ev0, st));
+    int ns = 0;
+    HIPCHK(c, launch_gershgorin(H, N, c->part, &ns, st));
+    HIPCHK(c, launch_bounds(c->part, ns, c->st, st));
+    HIPCHK(c, launch_init(H, N, ld, buf0, c->st, c->part, &ns, st));
+    if (o.tau > 0.0) HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 1, st));
+    HIPCHK(c, launch_ctrl_init(c->part, ns, c->st, a, st));
+
+    int launched = 0;
+    bool finished = false;
+    while (launched < o.max_iter) {
+        const int chunk = std::min(launched == 0 ? 24 : 8, o.max_iter - launched);
+        for (int k = 0; k < chunk; ++k) {
+            const int g = launched + k;
+            hipEvent_t* pe = c->profile ? &c->pev[4 * g] : nullptr;
+            if (pe) HIPCHK(c, hipEventRecord(pe[0], st));
+            if ((int8x || bf16x) && o.tau <= 0.0) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
+            if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
+            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st));
+            if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
+            if (o.tau > 0.0)
+                HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 0, st));
+            else if (int8x || bf16x)
+                HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st));
+            if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
+            HIPCHK(c, launch_ctrl_step(c->part, ns, c->st, a, st));
+        }
+        launched += chunk;
+        HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(State), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (c->st_host->done) {
+            finished = true;
+            break;
+        }
+    }
+    (void)finished;
+    const State& h = *c->st_host;
+    if (h.done != 3) HIPCHK(c, launch_finalize(buf0, buf1, ld, N, D, c->st, st));
+    HIPCHK(c, hipEventRecord(c->ev1, st));
+    HIPCHK(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iterations = h.iter;
+        stats->status = h.done == 1 ? 0 : (h.done == 2 ? 1 : 2);
+        stats->fp64_products = h.fp64_products;
+        stats->head_switch = h.head_switch;
+        stats->eps_min = h.eps_min;
+        stats->eps_max = h.eps_max;
+        stats->idem_err = h.iter > 0 ? h.idem[h.iter - 1] : 0.0;
+        stats->trace = h.t1;
+        stats->branch_bits[0] = h.bits[0];
+        stats->branch_bits[1] = h.bits[1];
+        stats->ms = ms;
+        stats->fill_min = h.fill_min;
+        stats->fill_max = h.fill_max;
+        for (int k = 0; k < kMaxIter && k < 128; ++k) {
+            stats->idem_hist[k] = (float)h.idem[k];
+            stats->fill_hist[k] = h.fill[k];
+        }
+        if (c->profile) {
+            for (int g = 0; g < h.iter; ++g) {
+                float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&t01, c->pev[4 * g], c->pev[4 * g + 1]));
+                HIPCHK(c, hipEventElapsedTime(&t12, c->pev[4 * g + 1], c->pev[4 * g + 2]));
+                HIPCHK(c, hipEventElapsedTime(&t23, c->pev[4 * g + 2], c->pev[4 * g + 3]));
+                if (g < h.fp64_products) {
+                    stats->prod_ms[0] += t12;
+                    stats->prod_count[0] += 1;
+                    stats->post_ms += t23;
+                } else {
+                    stats->encode_ms += t01;
+                    stats->prod_ms[1] += t23;
+                    stats->prod_count[1] += 1;
+                }
+            }
+        }
+    }
+    if (h.done == 3) return fail(c, SP2_ENOCONV, "SP2 reached max_iter without converging");
+    return SP2_OK;
+}
+
+extern "C" sp2_status sp2_density_matrix(sp2_ctx* c, int N, const double* H, int n_occ, const sp2_options* opt,
+                                         double* D_out, sp2_stats* stats) {
+    if (!c) return SP2_EINVAL;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (N < 1 || N > 65536) return fail(c, SP2_EINVAL, "N must be in [1, 65536]");
+    if (!H || !D_out) return fail(c, SP2_EINVAL, "null matrix pointer");
+    if (n_occ <= 0 || n_occ >= N) return fail(c, SP2_EINVAL, "need 0 < n_occ < N");
+    sp2_options o;
+    if (opt) o = *opt;
+    else sp2_options_default(&o);
+    sp2_status s = check_options(c, o, N);
+    if (s != SP2_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    return sp2_solve(c, N, H, n_occ, o, D_out, stats);
+}
+
+extern "C" sp2_status sp2_mulliken(sp2_ctx* c, int n_atoms, const double* D, double z_val, double* q_out) {
+    if (!c) return SP2_EINVAL;
+    if (n_atoms < 1 || n_atoms > 16384 || !D || !q_out) return fail(c, SP2_EINVAL, "bad mulliken arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_mulliken(D, n_atoms, z_val, q_out, c->stream));
+    return SP2_OK;
+}
+
+extern "C" sp2_status sp2_band_energy(sp2_ctx* c, int N, const double* D, const double* H, double* e_host) {
+    if (!c) return SP2_EINVAL;
+    if (N < 1 || N > 65536 || !D || !H || !e_host) return fail(c, SP2_EINVAL, "bad band-energy arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    sp2_status s;
+    size_t pbytes = c->partcap * sizeof(double);
+    if ((s = grow(c, (void**)&c->part, &pbytes, 1024 * sizeof(double))) != SP2_OK) return s;
+    c->partcap = pbytes / sizeof(double);
+    int ns = 0;
+    HIPCHK(c, launch_dot(D, H, (size_t)N * N, c->part, &ns, c->scal, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *e_host = 2.0 * c->scal_host[0];
+    return SP2_OK;
+}
+
+// ------------------------------------------------------------ tight binding
+// Quintic tail coefficients: B0..B2 match value, slope, curvature of the
+// exponential at r1; B3..B5 make value, slope, curvature vanish at rcut.
+static Radial make_radial(double amp, double r0, double decay, double r1, double rcut) {
+    Radial f;
+    f.amp = amp;
+    f.r0 = r0;
+    f.decay = decay;
+    f.r1 = r1;
+    f.rcut = rcut;
+    for (double& b : f.B) b = 0.0;
+    if (r1 < rcut) {
+        const double z = amp * std::exp(-(r1 - r0) / decay);
+        const double b0 = z, b1 = -z / decay, b2 = 0.5 * z / (decay * decay);
+        const double d = rcut - r1;
+        const double c0 = -(b0 + b1 * d + b2 * d * d);
+        const double c1 = -(b1 + 2.0 * b2 * d);
+        const double c2 = -2.0 * b2;
+        // u = B3 d^3, v = B4 d^4, w = B5 d^5:
+        // u + v + w = c0; 3u + 4v + 5w = c1 d; 6u + 12v + 20w = c2 d^2
+        const double a1 = c1 * d - 3.0 * c0;
+        const double a2 = c2 * d * d - 6.0 * c0;
+        const double w = 0.5 * (a2 - 6.0 * a1);
+        const double v = a1 - 2.0 * w;
+        const double u = c0 - v - w;
+        f.B[0] = b0;
+        f.B[1] = b1;
+        f.B[2] = b2;
+        f.B[3] = u / (d * d * d);
+        f.B[4] = v / (d * d * d * d);
+        f.B[5] = w / (d * d * d * d * d);
+    }
+    return f;
+}
+
+static bool params_ok(const tb_params* p) {
+    return p && p->lam > 0 && p->r_cut > 0 && p->r_tail > 0 && p->r_tail <= p->r_cut &&
+           (p->pair_a == 0.0 || p->pair_rho > 0) && std::isfinite(p->t0) && std::isfinite(p->hubbard_u);
+}
+
+static TBArgs make_tbargs(const tb_params* p) {
+    TBArgs a;
+    a.eps_s = p->eps_s;
+    a.eps_p = p->eps_p;
+    a.hubbard_u = p->hubbard_u;
+    a.coulomb_k = p->coulomb_k;
+    a.hop = make_radial(p->t0, p->r0, p->lam, p->r_tail, p->r_cut);
+    a.pair = make_radial(p->pair_a, p->pair_r0, p->pair_a != 0.0 ? p->pair_rho : 1.0, p->r_tail, p->r_cut);
+    return a;
+}
+
+static sp2_status ensure_atoms(sp2_ctx* c, int nat) {
+    if ((size_t)nat <= c->natcap) return SP2_OK;
+    void* ps[] = {c->V, c->eatom, c->qtmp};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    c->V = c->eatom = c->qtmp = nullptr;
+    c->natcap = 0;
+    if (hipMalloc((void**)&c->V, nat * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->eatom, nat * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->qtmp, nat * sizeof(double)) != hipSuccess)
+        return fail(c, SP2_ENOMEM, "atom scratch allocation failed");
+    c->natcap = nat;
+    return SP2_OK;
+}
+
+extern "C" sp2_status tb_hamiltonian(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz,
+                                     const double* n_aux, double* H_out) {
+    if (!c) return SP2_EINVAL;
+    if (!params_ok(p)) return fail(c, SP2_EINVAL, "bad tb_params");
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !H_out) return fail(c, SP2_EINVAL, "bad tb_hamiltonian arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    sp2_status s = ensure_atoms(c, n_atoms);
+    if (s != SP2_OK) return s;
+    const TBArgs a = make_tbargs(p);
+    const double* V = nullptr;
+    if (n_aux) {
+        HIPCHK(c, launch_potential(xyz, n_aux, n_atoms, p->hubbard_u, p->coulomb_k, c->V, c->stream));
+        V = c->V;
+    }
+    HIPCHK(c, launch_hamiltonian(xyz, n_atoms, a, V, H_out, c->stream));
+    return SP2_OK;
+}
+
+// Forces and energy; V must already hold gamma n (computed here).
+static sp2_status forces_impl(sp2_ctx* c, const tb_params* p, int nat, const double* xyz, const double* D,
+                              const double* q, const double* n, double* F, double* U_dev) {
+    const TBArgs a = make_tbargs(p);
+    HIPCHK(c, launch_potential(xyz, n, nat, p->hubbard_u, p->coulomb_k, c->V, c->stream));
+    HIPCHK(c, launch_forces(xyz, nat, a, D, q, n, c->V, F, c->eatom, U_dev, c->stream));
+    return SP2_OK;
+}
+
+extern "C" sp2_status tb_forces(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz, const double* D,
+                                const double* q, const double* n_aux, double* F_out, double* U_host) {
+    if (!c) return SP2_EINVAL;
+    if (!params_ok(p)) return fail(c, SP2_EINVAL, "bad tb_params");
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !D || !q || !n_aux)
+        return fail(c, SP2_EINVAL, "bad tb_forces arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    sp2_status s = ensure_atoms(c, n_atoms);
+    if (s != SP2_OK) return s;
+    if ((s = forces_impl(c, p, n_atoms, xyz, D, q, n_aux, F_out, c->scal)) != SP2_OK) return s;
+    if (U_host) {
+        HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *U_host = c->scal_host[0];
+    }
+    return SP2_OK;
+}
+
+// ------------------------------------------------------------------ XL-BOMD
+struct xlbomd {
+    sp2_ctx* c;
+    tb_params p;
+    xlbomd_options o;
+    int nat;
+    double *xyz, *vel, *F, *q, *hist, *H, *D, *dev, *dscal;
+    int head;
+    long step;
+    double U;
+};
+
+static sp2_status md_evaluate(xlbomd* m, int* iters) {
+    sp2_ctx* c = m->c;
+    const int nat = m->nat, N = 4 * nat;
+    const double* n_t = m->hist + (size_t)m->head * nat;
+    sp2_status s = tb_hamiltonian(c, &m->p, nat, m->xyz, n_t, m->H);
+    if (s != SP2_OK) return s;
+    sp2_stats st;
+    s = sp2_solve(c, N, m->H, 2 * nat, m->o.sp2, m->D, &st);
+    if (s != SP2_OK) return s;
+    if (iters) *iters = st.iterations;
+    HIPCHK(c, launch_mulliken(m->D, nat, m->p.z_val, m->q, c->stream));
+    return forces_impl(c, &m->p, nat, m->xyz, m->D, m->q, n_t, m->F, m->dscal);
+}
+
+extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd_options* o, int n_atoms,
+                                    const double* xyz_host, const double* vel_host, const double* n0_host,
+                                    xlbomd** out) {
+    if (!c) return SP2_EINVAL;
+    if (!out || !params_ok(p) || !o || !xyz_host || !vel_host || !n0_host)
+        return fail(c, SP2_EINVAL, "bad xlbomd_create arguments");
+    *out = nullptr;
+    if (n_atoms < 2 || n_atoms > 16384) return fail(c, SP2_EINVAL, "n_atoms out of range");
+    if (o->K < 1 || o->K > 8 || !(o->dt_fs > 0) || !(p->mass > 0)) return fail(c, SP2_EINVAL, "bad xlbomd options");
+    sp2_status s = check_options(c, o->sp2, 4 * n_atoms);
+    if (s != SP2_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((s = ensure_atoms(c, n_atoms)) != SP2_OK) return s;
+    xlbomd* m = new xlbomd();
+    m->c = c;
+    m->p = *p;
+    m->o = *o;
+    m->nat = n_atoms;
+    const size_t N = 4 * (size_t)n_atoms;
+    const int L = o->K + 1;
+    double** bufs[] = {&m->xyz, &m->vel, &m->F, &m->q, &m->dev};
+    bool ok = true;
+    for (double** b : bufs) ok = ok && hipMalloc((void**)b, 3 * n_atoms * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&m->hist, (size_t)L * n_atoms * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&m->H, N * N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&m->D, N * N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&m->dscal, 8 * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        xlbomd_destroy(m);
+        return fail(c, SP2_ENOMEM, "xlbomd allocation failed");
+    }
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipMemcpyAsync(m->xyz, xyz_host, 3 * n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(m->vel, vel_host, 3 * n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
+    for (int k = 0; k < L; ++k)
+        HIPCHK(c, hipMemcpyAsync(m->hist + (size_t)k * n_atoms, n0_host, n_atoms * sizeof(double),
+                                 hipMemcpyHostToDevice, st));
+    m->head = 0;
+    m->step = 0;
+    if ((s = md_evaluate(m, nullptr)) != SP2_OK) {
+        xlbomd_destroy(m);
+        return s;
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    *out = m;
+    return SP2_OK;
+}
+
+extern "C" sp2_status xlbomd_run(xlbomd* m, int n_steps, xlbomd_record* log) {
+    if (!m) return SP2_EINVAL;
+    sp2_ctx* c = m->c;
+    if (n_steps < 0) return fail(c, SP2_EINVAL, "n_steps < 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int nat = m->nat, K = m->o.K, L = K + 1;
+    const double hacc = 0.5 * m->o.dt_fs * kAccAFs2 / m->p.mass;
+    XLArgs xa;
+    xa.kappa = m->o.kappa;
+    xa.alpha = m->o.alpha;
+    for (int k = 0; k < 9; ++k) xa.c[k] = k <= K ? m->o.c[k] : 0.0;
+    hipStream_t st = c->stream;
+    for (int step = 0; step < n_steps; ++step) {
+        HIPCHK(c, launch_kick_drift(m->xyz, m->vel, m->F, 3 * nat, hacc, m->o.dt_fs, st));
+        HIPCHK(c, launch_xl_charges(m->hist, nat, K, m->head, m->q, xa, st));
+        m->head = (m->head + K) % L;
+        int iters = 0;
+        sp2_status s = md_evaluate(m, &iters);
+        if (s != SP2_OK) return s;
+        HIPCHK(c, launch_maxdiff(m->q, m->hist + (size_t)m->head * nat, nat, m->dev, m->dscal + 1, st));
+        HIPCHK(c, launch_kick_drift(m->xyz, m->vel, m->F, 3 * nat, hacc, 0.0, st));
+        HIPCHK(c, launch_sqsum(m->vel, 3 * nat, m->dscal + 2, st));
+        HIPCHK(c, hipMemcpyAsync(c->scal_host, m->dscal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        m->step += 1;
+        const double U = c->scal_host[0];
+        const double ke = 0.5 * m->p.mass * kKeEv * c->scal_host[2];
+        m->U = U;
+        if (log) {
+            log[step].epot = U;
+            log[step].ekin = ke;
+            log[step].etot = U + ke;
+            log[step].max_q_minus_n = c->scal_host[1];
+            log[step].sp2_iterations = iters;
+        }
+    }
+    return SP2_OK;
+}
+
+extern "C" sp2_status xlbomd_get(xlbomd* m, double* xyz_host, double* vel_host, double* q_host, double* n_host) {
+    if (!m) return SP2_EINVAL;
+    sp2_ctx* c = m->c;
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t b = m->nat * sizeof(double);
+    hipStream_t st = c->stream;
+    if (xyz_host) HIPCHK(c, hipMemcpyAsync(xyz_host, m->xyz, 3 * b, hipMemcpyDeviceToHost, st));
+    if (vel_host) HIPCHK(c, hipMemcpyAsync(vel_host, m->vel, 3 * b, hipMemcpyDeviceToHost, st));
+    if (q_host) HIPCHK(c, hipMemcpyAsync(q_host, m->q, b, hipMemcpyDeviceToHost, st));
+    if (n_host) HIPCHK(c, hipMemcpyAsync(n_host, m->hist + (size_t)m->head * m->nat, b, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return SP2_OK;
+}
+
+extern "C" void xlbomd_destroy(xlbomd* m) {
+    if (!m) return;
+    (void)hipSetDevice(m->c->device);
+    (void)hipStreamSynchronize(m->c->stream);
+    double* bufs[] = {m->xyz, m->vel, m->F, m->q, m->dev, m->hist, m->H, m->D, m->dscal};
+    for (double* b : bufs)
+        if (b) (void)hipFree(b);
+    delete m;
+}

@@ -1,0 +1,497 @@
+// Dense SP2 kernels for gfx950: spectral bounds, X_0, the FP64-MFMA
+// symmetric product with the fused purification update, the single-workgroup
+// control step, and small observables (Mulliken charges, traces).
+//
+// SP2 (second-order spectral projection, Linear scaling section) builds the
+// zero-temperature density matrix theta(mu0 I - H) as a sequence of squarings
+// X <- X^2 or X <- 2X - X^2 starting from X_0 = (eps_max I - H)/(eps_max - eps_min).
+//
+// Layout: the library keeps X in two padded ld x ld row-major FP64 buffers
+// (ld = N rounded up to 128, zero outside the N x N corner) used ping-pong;
+// the zero padding makes every tile of the product full, with no bounds
+// checks in the inner loop, and does not change X^2, traces or norms.
+#include "sp2_internal.h"
+
+namespace sp2 {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Deterministic fixed-order block sum of per-thread values (blockDim 256).
+__device__ double block_sum256(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------- bounds
+// One wave per row i: lo_i = H_ii - sum_{j != i} |H_ij|, hi_i = H_ii + same.
+// Each 256-thread workgroup covers 4 rows and writes (min lo, max hi).
+__global__ __launch_bounds__(256) void k_gershgorin(const double* __restrict__ H, int N,
+                                                     double* __restrict__ part) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + w;
+    double lo = 1.0e300, hi = -1.0e300;
+    if (i < N) {
+        const double* row = H + (size_t)i * N;
+        double s = 0.0;
+        for (int j = lane; j < N; j += 64) s += fabs(row[j]);
+        s = wave_sum(s);
+        const double d = row[i];
+        const double r = s - fabs(d);
+        lo = d - r;
+        hi = d + r;
+    }
+    __shared__ double sl[4], sh[4];
+    if (lane == 0) { sl[w] = lo; sh[w] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x + 0] = fmin(fmin(sl[0], sl[1]), fmin(sl[2], sl[3]));
+        part[2 * blockIdx.x + 1] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ part, int nslots,
+                                                State* __restrict__ st) {
+    double lo = 1.0e300, hi = -1.0e300;
+    for (int k = threadIdx.x; k < nslots; k += 256) {
+        lo = fmin(lo, part[2 * k]);
+        hi = fmax(hi, part[2 * k + 1]);
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    __shared__ double sl[4], sh[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sl[w] = lo; sh[w] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->eps_min = fmin(fmin(sl[0], sl[1]), fmin(sl[2], sl[3]));
+        st->eps_max = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+        st->t1 = st->t2 = 0.0;
+        st->fill_min = 1.0;
+        st->fill_max = 0.0;
+        st->bits[0] = st->bits[1] = 0ull;
+        st->iter = 0;
+        st->branch = 0;
+        st->done = 0;
+        st->cur = 0;
+        st->result = 0;
+        st->phase = 0;
+        st->fp64_products = 0;
+        st->head_switch = -1;
+        st->tail_left = 0;
+        st->kept = 0ull;
+    }
+    for (int k = threadIdx.x; k < kMaxIter; k += 256) {
+        st->idem[k] = 0.0;
+        st->fill[k] = 0.0f;
+    }
+}
+
+// ------------------------------------------------------------------ X_0
+// One wave per padded row.  Writes X_0 = (eps_max I - H)/(eps_max - eps_min)
+// in the N x N corner and zeros elsewhere; per-workgroup partials
+// (Tr X_0, ||X_0||_F^2, 0) into part[3 * block].
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ H, int N, int ld,
+                                              double* __restrict__ X, const State* __restrict__ st,
+                                              double* __restrict__ part) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + w;            // < ld by construction of the grid
+    const double emax = st->eps_max;
+    const double inv = 1.0 / (st->eps_max - st->eps_min);
+    double tr = 0.0, fro = 0.0;
+    double* xrow = X + (size_t)i * ld;
+    if (i < N) {
+        const double* hrow = H + (size_t)i * N;
+        for (int j = lane; j < ld; j += 64) {
+            double x = 0.0;
+            if (j < N) {
+                x = ((j == i ? emax : 0.0) - hrow[j]) * inv;
+                if (j == i) tr += x;
+            }
+            xrow[j] = x;
+            fro += x * x;
+        }
+    } else {
+        for (int j = lane; j < ld; j += 64) xrow[j] = 0.0;
+    }
+    __shared__ double sh[4];
+    const double btr = block_sum256(tr, sh);
+    const double bfr = block_sum256(fro, sh);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = btr;
+        part[3 * blockIdx.x + 1] = bfr;
+        part[3 * blockIdx.x + 2] = 0.0;
+    }
+}
+
+// --------------------------------------------------------------- control
+// Fixed-order reduction of nslots x 3 partials (trace, ||X||^2, ||P - X||^2).
+__device__ void reduce3(const double* __restrict__ part, int nslots, double out[3]) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < nslots; k += 256) {
+        a += part[3 * k];
+        b += part[3 * k + 1];
+        c += part[3 * k + 2];
+    }
+    __shared__ double sh[4];
+    out[0] = block_sum256(a, sh);
+    out[1] = block_sum256(b, sh);
+    out[2] = block_sum256(c, sh);
+}
+
+// Branch rule: X^2 if its trace is at least as close to n_occ as that of
+// 2X - X^2 (Tr X^2 = t2, Tr(2X - X^2) = 2 t1 - t2).
+__device__ __forceinline__ int choose_branch(double t1, double t2, double nocc) {
+    return fabs(t2 - nocc) <= fabs(2.0 * t1 - t2 - nocc) ? 0 : 1;
+}
+
+__device__ __forceinline__ void set_bit(State* st, int n, int b) {
+    if (n < 128 && b) st->bits[n >> 6] |= (1ull << (n & 63));
+}
+__device__ __forceinline__ void clear_bit(State* st, int n) {
+    if (n < 128) st->bits[n >> 6] &= ~(1ull << (n & 63));
+}
+
+// Kept-block fraction of the threshold pass that just ran (if any).
+__device__ __forceinline__ double take_fill(State* st, const CtrlArgs& a) {
+    if (a.total_blocks <= 0.0) return -1.0;
+    const double f = (double)st->kept / a.total_blocks;
+    st->kept = 0ull;
+    st->fill_min = fmin(st->fill_min, f);
+    st->fill_max = fmax(st->fill_max, f);
+    return f;
+}
+
+__global__ __launch_bounds__(256) void k_ctrl_init(const double* __restrict__ part, int nslots,
+                                                   State* __restrict__ st, CtrlArgs a) {
+    double r[3];
+    reduce3(part, nslots, r);
+    if (threadIdx.x == 0) {
+        (void)take_fill(st, a);
+        st->t1 = r[0];
+        st->t2 = r[1];
+        const int b = choose_branch(r[0], r[1], a.n_occ);
+        st->branch = b;
+        set_bit(st, 0, b);
+        st->phase = (a.mixed != 0 && a.fp64_head == 0) ? 1 : 0;
+        if (st->phase == 1) st->head_switch = 0;
+    }
+}
+
+// After product n: the partials hold Tr X_{n+1}, ||X_{n+1}||_F^2 and
+// ||X_n^2 - X_n||_F^2.  Stop rules: e_n < idem_tol (converged, D = X_n);
+// n >= 4, e_n >= e_{n-2}, e_n < stall_tol (stalled at the rounding floor,
+// D = X_n); n + 1 == max_iter (not converged).  Otherwise X_{n+1} becomes
+// current and the next branch is chosen from its traces.
+__global__ __launch_bounds__(256) void k_ctrl_step(const double* __restrict__ part, int nslots,
+                                                   State* __restrict__ st, CtrlArgs a) {
+    if (st->done) return;
+    double r[3];
+    reduce3(part, nslots, r);
+    if (threadIdx.x != 0) return;
+    const int n = st->iter;
+    const double e = sqrt(r[2]);
+    st->idem[n] = e;
+    const double f = take_fill(st, a);
+    if (f >= 0.0) st->fill[n] = (float)f;
+    st->iter = n + 1;
+    if (st->phase == 0) st->fp64_products += 1;
+    const bool stall = n >= 4 && e >= st->idem[n - 2] && e < a.stall_tol;
+    if (e < a.idem_tol || (stall && !(a.mixed == 2 && st->phase == 1))) {
+        st->done = (e < a.idem_tol) ? 1 : 2;
+        st->result = st->cur;
+        clear_bit(st, n);
+        return;
+    }
+    if (n + 1 >= a.max_iter) {
+        st->done = 3;
+        st->result = 1 - st->cur;
+        return;
+    }
+    // BF16X2: when the BF16 stage stalls, switch to a fixed number of FP32 products
+    if (a.mixed == 2 && st->phase == 1 && stall) {
+        st->phase = 2;
+        st->tail_left = a.fp32_tail;
+        st->head_switch = n + 1;
+    }
+    if (st->phase == 2) {
+        if (st->tail_left <= 0) {
+            st->done = 2;
+            st->result = st->cur;
+            clear_bit(st, n);
+            return;
+        }
+        st->tail_left -= 1;
+    }
+    st->cur = 1 - st->cur;
+    st->t1 = r[0];
+    st->t2 = r[1];
+    const int b = choose_branch(r[0], r[1], a.n_occ);
+    st->branch = b;
+    set_bit(st, n + 1, b);
+    if (a.mixed == 1 && st->phase == 0 && n + 1 >= a.fp64_head && a.fp64_head >= 0) {
+        st->phase = 1;
+        st->head_switch = n + 1;
+    }
+}
+
+// ------------------------------------------------- FP64 symmetric product
+// P = X X for symmetric X: P_ij = sum_k X_ki X_kj, so both MFMA operands are
+// read as contiguous row segments of X (rows k, columns i or j), and only
+// tiles with bi <= bj are computed; each is written to (bi,bj) and mirrored.
+// Tile 128 x 128, 4 waves in a 2 x 2 arrangement, each wave 64 x 64 as 4 x 4
+// blocks of v_mfma_f64_16x16x4f64.  K staged through LDS 16 at a time with
+// register prefetch of the next stage (double-buffered LDS).
+// Fused epilogue: X_{n+1} = P (branch 0) or 2 X_n - P (branch 1), written to
+// the other buffer; per-tile partials Tr X_{n+1}, ||X_{n+1}||_F^2,
+// ||P - X_n||_F^2 (off-diagonal tiles count twice) into part[3 * tile].
+constexpr int GB = 128;   // tile
+constexpr int GK = 16;    // k per stage
+constexpr int GS = GB;      // LDS row stride (doubles); 2 stages x 2 operands = 64 KiB
+
+// Tile id t -> (bi, bj), bi <= bj, row-major over the upper triangle.
+__device__ __forceinline__ void tri_coords(int t, int nt, int& bi, int& bj) {
+    int i = 0, off = 0;
+    while (t >= off + (nt - i)) { off += nt - i; ++i; }
+    bi = i;
+    bj = i + (t - off);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tile ids so tiles sharing row panels share an L2.
+__device__ __forceinline__ int xcd_remap(int w, int T) {
+    const int q = T >> 3, r = T & 7;
+    const int x = w & 7, k = w >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
+                                                     double* __restrict__ buf1, int ld,
+                                                     const State* __restrict__ st,
+                                                     double* __restrict__ part) {
+    if (st->done || st->phase != 0) return;
+    const int nt = ld / GB;
+    const int T = nt * (nt + 1) / 2;
+    const int t = xcd_remap(blockIdx.x, T);
+    int bi, bj;
+    tri_coords(t, nt, bi, bj);
+    const double* __restrict__ Xc = st->cur ? buf1 : buf0;
+    double* __restrict__ Xn = st->cur ? buf0 : buf1;
+    const int i0 = bi * GB, j0 = bj * GB;
+
+    __shared__ double As[2][GK][GS];
+    __shared__ double Bs[2][GK][GS];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wi = w >> 1, wj = w & 1;
+
+    // global -> register staging: 4 double2 per operand per thread
+    const int lrow = tid >> 6;           // + 4*s
+    const int lcol = 2 * (tid & 63);
+    double2 ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const size_t off = (size_t)(k0 + lrow + 4 * s) * ld;
+            ra[s] = *reinterpret_cast<const double2*>(Xc + off + i0 + lcol);
+            rb[s] = *reinterpret_cast<const double2*>(Xc + off + j0 + lcol);
+        }
+    };
+    auto sstore = [&](int stg) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            As[stg][lrow + 4 * s][lcol] = ra[s].x;
+            As[stg][lrow + 4 * s][lcol + 1] = ra[s].y;
+            Bs[stg][lrow + 4 * s][lcol] = rb[s].x;
+            Bs[stg][lrow + 4 * s][lcol + 1] = rb[s].y;
+        }
+    };
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = ld / GK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int stg = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * GK);
+#pragma unroll
+        for (int k4 = 0; k4 < GK / 4; ++k4) {
+            const int kr = k4 * 4 + (lane >> 4);
+            double av[4], bv[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) av[m] = As[stg][kr][wi * 64 + m * 16 + (lane & 15)];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) bv[n] = Bs[stg][kr][wj * 64 + n * 16 + (lane & 15)];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
+        }
+        if (kt + 1 < nk) sstore(stg ^ 1);
+        __syncthreads();
+    }
+
+    // fused SP2 update + partials
+    const int br = st->branch;
+    const bool mirror = bi != bj;
+    double tr = 0.0, fro = 0.0, idm = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int gj = j0 + wj * 64 + n * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // v_mfma_f64_16x16x4f64 result: lane l, element r is row (l >> 4) + 4 r, column l & 15
+                const int gi = i0 + wi * 64 + m * 16 + (lane >> 4) + 4 * r;
+                const double p = acc[m][n][r];
+                const double x = Xc[(size_t)gi * ld + gj];
+                const double xn = br ? 2.0 * x - p : p;
+                Xn[(size_t)gi * ld + gj] = xn;
+                if (mirror) Xn[(size_t)gj * ld + gi] = xn;
+                if (gi == gj) tr += xn;
+                fro += xn * xn;
+                idm += (p - x) * (p - x);
+            }
+        }
+    }
+    const double wgt = mirror ? 2.0 : 1.0;
+    __shared__ double sh[4];
+    const double btr = block_sum256(tr, sh);
+    const double bfr = block_sum256(fro, sh);
+    const double bid = block_sum256(idm, sh);
+    if (tid == 0) {
+        part[3 * t + 0] = btr;
+        part[3 * t + 1] = wgt * bfr;
+        part[3 * t + 2] = wgt * bid;
+    }
+}
+
+// ---------------------------------------------------------------- finalize
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ buf0,
+                                                  const double* __restrict__ buf1, int ld, int N,
+                                                  double* __restrict__ D,
+                                                  const State* __restrict__ st) {
+    const double* X = st->result ? buf1 : buf0;
+    const size_t total = (size_t)N * N;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const size_t i = e / N, j = e - i * N;
+        D[e] = X[i * ld + j];
+    }
+}
+
+// ------------------------------------------------------------ observables
+__global__ __launch_bounds__(256) void k_mulliken(const double* __restrict__ D, int n_atoms,
+                                                  double z, double* __restrict__ q) {
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= n_atoms) return;
+    const size_t N = 4 * (size_t)n_atoms;
+    double s = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const size_t o = 4 * (size_t)a + k;
+        s += D[o * N + o];
+    }
+    q[a] = 2.0 * s - z;
+}
+
+// sum_e A[e] B[e] with a fixed grid of 512 workgroups, then a one-workgroup
+// fixed-order reduction into *out (device).
+constexpr int kDotBlocks = 512;
+__global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ A,
+                                                  const double* __restrict__ B, size_t n,
+                                                  double* __restrict__ part) {
+    double s = 0.0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)kDotBlocks * 256)
+        s += A[e] * B[e];
+    __shared__ double sh[4];
+    const double b = block_sum256(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ part, int nslots,
+                                                   double* __restrict__ out) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nslots; k += 256) s += part[k];
+    __shared__ double sh[4];
+    const double b = block_sum256(s, sh);
+    if (threadIdx.x == 0) *out = b;
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_gershgorin(const double* H, int N, double* part, int* nslots, hipStream_t s) {
+    const int g = (N + 3) / 4;
+    *nslots = g;
+    hipLaunchKernelGGL(k_gershgorin, dim3(g), dim3(256), 0, s, H, N, part);
+    return hipGetLastError();
+}
+hipError_t launch_bounds(const double* part, int nslots, State* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_bounds, dim3(1), dim3(256), 0, s, part, nslots, st);
+    return hipGetLastError();
+}
+hipError_t launch_init(const double* H, int N, int ld, double* X0, State* st, double* part,
+                       int* nslots, hipStream_t s) {
+    const int g = ld / 4;
+    *nslots = g;
+    hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, s, H, N, ld, X0, st, part);
+    return hipGetLastError();
+}
+hipError_t launch_ctrl_init(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(256), 0, s, part, nslots, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_ctrl_step(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctrl_step, dim3(1), dim3(256), 0, s, part, nslots, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
+                           int* nslots, hipStream_t s) {
+    const int nt = ld / GB;
+    const int T = tri_tiles(nt);
+    *nslots = T;
+    hipLaunchKernelGGL(k_gemm_f64, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part);
+    return hipGetLastError();
+}
+hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
+                           const State* st, hipStream_t s) {
+    size_t total = (size_t)N * N;
+    int g = (int)((total + 255) / 256);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, buf0, buf1, ld, N, D, st);
+    return hipGetLastError();
+}
+hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hipStream_t s) {
+    hipLaunchKernelGGL(k_mulliken, dim3((n_atoms + 255) / 256), dim3(256), 0, s, D, n_atoms, z, q);
+    return hipGetLastError();
+}
+hipError_t launch_dot(const double* A, const double* B, size_t n, double* part, int* nslots,
+                      double* out, hipStream_t s) {
+    *nslots = kDotBlocks;
+    hipLaunchKernelGGL(k_dot_part, dim3(kDotBlocks), dim3(256), 0, s, A, B, n, part);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, part, kDotBlocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace sp2

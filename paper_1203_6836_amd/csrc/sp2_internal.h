@@ -1,0 +1,62 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sp2 {
+
+constexpr int kMaxIter = 128;      // products per solve (idempotency history)
+constexpr int kTile = 128;         // padded leading dimension multiple / GEMM tile
+
+// Device-resident control state of one SP2 solve.  Written only by the
+// control kernels (single workgroup), read by every other kernel.
+struct State {
+    double eps_min, eps_max;
+    double t1, t2;              // Tr X_n and Tr X_n^2 (= ||X_n||_F^2) of the current X_n
+    double idem[kMaxIter];      // ||X_n^2 - X_n||_F per product
+    double fill_min, fill_max;  // block-threshold kept fraction
+    float fill[kMaxIter];       // kept fraction after each update (and X_0 at the end slot)
+    unsigned long long kept;    // kept-block counter of the current threshold pass
+    unsigned long long bits[2]; // branch of each applied update
+    int iter;                   // products formed so far
+    int branch;                 // branch of the next update (0: X^2, 1: 2X - X^2)
+    int done;                   // 0 running, 1 converged, 2 stalled, 3 max_iter
+    int cur;                    // X buffer (0/1) holding X_n
+    int result;                 // X buffer holding D once done
+    int phase;                  // 0: FP64 products, 1: reduced-precision products, 2: FP32 tail
+    int fp64_products;
+    int head_switch;
+    int tail_left;              // FP32 tail products still to do (BF16X2)
+    int pad_;
+};
+
+struct CtrlArgs {
+    double n_occ;
+    double idem_tol;
+    double stall_tol;
+    int max_iter;
+    int fp64_head;   // products in FP64 before switching phase (-1: never switch)
+    int fp32_tail;   // BF16X2: FP32 products after the BF16 stage stalls
+    int mixed;       // 0: FP64 only, 1: INT8X, 2: BF16X2
+    double total_blocks;  // block threshold: number of 32 x 32 blocks of N x N (0: off)
+};
+
+// Number of upper-triangular tile pairs (bi <= bj) of an nt x nt tile grid.
+inline int tri_tiles(int nt) { return nt * (nt + 1) / 2; }
+
+// ---- launchers (sp2_dense.hip) ----
+hipError_t launch_gershgorin(const double* H, int N, double* part, int* nslots, hipStream_t s);
+hipError_t launch_bounds(const double* part, int nslots, State* st, hipStream_t s);
+hipError_t launch_init(const double* H, int N, int ld, double* X0, State* st, double* part,
+                       int* nslots, hipStream_t s);
+hipError_t launch_ctrl_init(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);
+hipError_t launch_ctrl_step(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);
+hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
+                           int* nslots, hipStream_t s);
+hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
+                           const State* st, hipStream_t s);
+hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hipStream_t s);
+hipError_t launch_dot(const double* A, const double* B, size_t n, double* part, int* nslots,
+                      double* out, hipStream_t s);
+
+}  // namespace sp2

@@ -1,0 +1,145 @@
+// Block thresholding of X (the block form of the elementwise threshold the
+// paper applies after each projection in its linear-scaling runs) and the
+// operand storage of the reduced-precision products.
+#include "split_internal.h"
+
+namespace sp2 {
+
+__device__ __forceinline__ double wsum64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void tri_coords_t(int t, int nt, int& bi, int& bj) {
+    int i = 0, off = 0;
+    while (t >= off + (nt - i)) { off += nt - i; ++i; }
+    bi = i;
+    bj = i + (t - off);
+}
+
+// One workgroup per upper-triangular 128 x 128 tile t (same numbering as the
+// dense product's partial slots); each wave owns four of its sixteen 32 x 32
+// blocks.  Blocks with ||B||_F < tau are zeroed (with their mirror).  The
+// tile's trace and ||X||_F^2 partials are rewritten for the thresholded X;
+// the idempotency partial of the product is kept (zeroed for X_0).
+__global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                         int ld, int N, double tau, State* __restrict__ st,
+                                                         double* __restrict__ part, int init) {
+    if (st->done) return;
+    double* X = init ? buf0 : (st->cur ? buf0 : buf1);
+    const int nt = ld / 128;
+    const int t = blockIdx.x;
+    int bi, bj;
+    tri_coords_t(t, nt, bi, bj);
+    const bool mirror = bi != bj;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nb = (N + 31) / 32;
+    double tr = 0.0, fro = 0.0;
+    int kept = 0;
+    for (int s = 0; s < 4; ++s) {
+        const int b = w * 4 + s, br = b >> 2, bc = b & 3;
+        const int r0 = bi * 128 + br * 32, c0 = bj * 128 + bc * 32;
+        double v[16];
+        double ss = 0.0;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int e = lane + 64 * m, r = e >> 5, c = e & 31;
+            v[m] = X[(size_t)(r0 + r) * ld + c0 + c];
+            ss += v[m] * v[m];
+        }
+        ss = wsum64(ss);
+        const bool keep = ss >= tau * tau;
+        if (!keep) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int e = lane + 64 * m, r = e >> 5, c = e & 31;
+                X[(size_t)(r0 + r) * ld + c0 + c] = 0.0;
+                if (mirror) X[(size_t)(c0 + c) * ld + r0 + r] = 0.0;
+            }
+        } else {
+            fro += ss;
+            if (r0 == c0) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    const int e = lane + 64 * m, r = e >> 5, c = e & 31;
+                    if (r == c) tr += v[m];
+                }
+            }
+            if ((r0 >> 5) < nb && (c0 >> 5) < nb) kept += 1;
+        }
+    }
+    tr = wsum64(tr);
+    __shared__ double s_tr[4], s_fr[4];
+    __shared__ int s_k[4];
+    if (lane == 0) {
+        s_tr[w] = tr;
+        s_fr[w] = fro;
+        s_k[w] = kept;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double wgt = mirror ? 2.0 : 1.0;
+        part[3 * t + 0] = (s_tr[0] + s_tr[1]) + (s_tr[2] + s_tr[3]);
+        part[3 * t + 1] = wgt * ((s_fr[0] + s_fr[1]) + (s_fr[2] + s_fr[3]));
+        if (init) part[3 * t + 2] = 0.0;
+        const int k = s_k[0] + s_k[1] + s_k[2] + s_k[3];
+        atomicAdd(&st->kept, (unsigned long long)(mirror ? 2 * k : k));
+    }
+}
+
+hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, State* st,
+                                  double* part, int* nslots, int init, hipStream_t stream) {
+    const int nt = ld / 128;
+    const int T = nt * (nt + 1) / 2;
+    *nslots = T;
+    hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, st, part, init);
+    return hipGetLastError();
+}
+
+int split_reserve(SplitScratch& s, int ld, int slices, bool bf16) {
+    size_t need = 0;
+    need += (size_t)slices * ld * ld;                 // int8 digits
+    need += (size_t)ld * sizeof(double) + 256;        // row scales
+    if (bf16) need += (size_t)2 * ld * ld * sizeof(uint16_t) + (size_t)ld * ld * sizeof(float) + 512;
+    if (s.bytes >= need && s.ld == ld && s.slices == slices && s.bf16 == bf16) return 0;
+    split_free(s);
+    char* base = nullptr;
+    if (hipMalloc((void**)&base, need) != hipSuccess) return -2;
+    s.bytes = need;
+    s.ld = ld;
+    s.slices = slices;
+    s.bf16 = bf16;
+    size_t off = 0;
+    s.digits = reinterpret_cast<int8_t*>(base + off);
+    off += (size_t)slices * ld * ld;
+    off = (off + 255) & ~(size_t)255;
+    s.scale = reinterpret_cast<double*>(base + off);
+    off += (size_t)ld * sizeof(double);
+    if (bf16) {
+        off = (off + 255) & ~(size_t)255;
+        s.bf = reinterpret_cast<uint16_t*>(base + off);
+        off += (size_t)2 * ld * ld * sizeof(uint16_t);
+        off = (off + 255) & ~(size_t)255;
+        s.x32 = reinterpret_cast<float*>(base + off);
+    }
+    return 0;
+}
+
+void split_free(SplitScratch& s) {
+    if (s.digits) (void)hipFree(s.digits);
+    s = SplitScratch();
+}
+
+size_t split_part_slots(int ld) {
+    const int nt = ld / 128;
+    return (size_t)nt * (nt + 1) / 2;
+}
+
+hipError_t launch_split_encode(SplitScratch&, const double*, const double*, int, State*, hipStream_t) {
+    return hipErrorNotSupported;
+}
+hipError_t launch_split_gemm(SplitScratch&, double*, double*, int, State*, double*, int*, hipStream_t) {
+    return hipErrorNotSupported;
+}
+
+}  // namespace sp2

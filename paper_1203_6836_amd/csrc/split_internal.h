@@ -1,0 +1,42 @@
+// Internal declarations of the reduced-precision (split) SP2 products and the
+// block threshold.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "sp2_internal.h"
+
+namespace sp2 {
+
+constexpr int kMaxSlices = 6;
+
+// Device operands of the split products, owned by the context.
+struct SplitScratch {
+    int ld = 0;
+    int slices = 0;
+    bool bf16 = false;
+    int8_t* digits = nullptr;   // slices x ld x ld int8 digit planes
+    double* scale = nullptr;    // ld row scales (powers of two)
+    uint16_t* bf = nullptr;     // 2 x ld x ld BF16 hi/lo planes
+    float* x32 = nullptr;       // ld x ld FP32 master (BF16X2)
+    size_t bytes = 0;
+};
+
+int split_reserve(SplitScratch& s, int ld, int slices, bool bf16);
+void split_free(SplitScratch& s);
+size_t split_part_slots(int ld);
+
+// Encode the current X_n (buffer st->cur) into the split operands when the
+// control state says the next product is a reduced-precision one.
+hipError_t launch_split_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
+                               hipStream_t stream);
+// Reduced-precision product with the fused SP2 update (no-op in FP64 phase).
+hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                             int* nslots, hipStream_t stream);
+// Zero every 32 x 32 block of the freshly written X (X_0 when init != 0,
+// else X_{n+1}) whose Frobenius norm is below tau; rewrite the trace and
+// norm partials of the 128 x 128 tiles (keeping the idempotency partial).
+hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, State* st,
+                                  double* part, int* nslots, int init, hipStream_t stream);
+
+}  // namespace sp2

@@ -1,0 +1,156 @@
+"""GPU parity of the dense SP2 path (through the C-ABI) against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import eig, observables, sp2 as osp2, tb as otb
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_1203_6836_amd as p
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = p.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def oracle_H(dims, seed, model=synth.STATIC_MODEL):
+    pos = synth.lattice_positions(dims, seed=seed)
+    return pos, otb.hamiltonian(pos, None, model)
+
+
+# sizes: one full tile, ragged single tile, several tiles with a ragged tail
+CASES = [((4, 4, 4), 0), ((3, 3, 3), 7), ((5, 5, 5), 11), ((6, 6, 5), 12)]
+
+
+@pytest.mark.parametrize("dims,seed", CASES)
+def test_fp64_density_matrix_matches_oracle(ctx, dims, seed):
+    import paper_1203_6836_amd as p
+    say(f"case fp64 dims={dims} seed={seed}")
+    pos, H = oracle_H(dims, seed)
+    nocc = 2 * len(pos)
+    ref = osp2.sp2(H, nocc, tol=1e-10)
+    D, st = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("fp64"))
+    D = D.cpu().numpy()
+    N = H.shape[0]
+    err = np.linalg.norm(D - ref.D) / np.sqrt(N)
+    say(f"  iters gpu={st['iterations']} oracle={ref.iterations} err/sqrtN={err:.2e} idem={st['idem_err']:.2e}")
+    assert err <= 1e-10
+    assert np.max(np.abs(D - ref.D)) < 1e-10
+    assert st["status"] == "converged"
+    assert abs(st["iterations"] - ref.iterations) <= 1
+    assert st["eps_min"] == pytest.approx(ref.eps_min, abs=1e-12)
+    assert st["eps_max"] == pytest.approx(ref.eps_max, abs=1e-12)
+    assert np.array_equal(D, D.T)
+    assert abs(np.trace(D) - nocc) < 1e-10
+    if st["iterations"] == ref.iterations:
+        assert st["branches"] == ref.branches
+
+
+def test_fp64_equals_jacobi_projector(ctx):
+    import paper_1203_6836_amd as p
+    say("case fp64 vs jacobi 4x4x4")
+    pos, H = oracle_H((4, 4, 4), 0)
+    nocc = 2 * len(pos)
+    rho, ev, gap = eig.density_matrix(H, nocc)
+    D, st = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("fp64"))
+    D = D.cpu().numpy()
+    assert np.linalg.norm(D - rho) / np.sqrt(H.shape[0]) < 1e-10
+    assert np.linalg.norm(H @ D - D @ H) < 1e-9
+
+
+def test_deterministic_repeat(ctx):
+    import paper_1203_6836_amd as p
+    say("case determinism 5x5x5")
+    _, H = oracle_H((5, 5, 5), 11)
+    Hd = to_dev(H)
+    D1, s1 = ctx.sp2_density_matrix(Hd, 250, p.options("fp64"))
+    D2, s2 = ctx.sp2_density_matrix(Hd, 250, p.options("fp64"))
+    assert bool((D1 == D2).all())
+    assert s1["branches"] == s2["branches"]
+
+
+def test_observables_match_oracle(ctx):
+    import paper_1203_6836_amd as p
+    say("case mulliken/band energy 4x4x4")
+    pos, H = oracle_H((4, 4, 4), 0)
+    nocc = 2 * len(pos)
+    Hd = to_dev(H)
+    D, _ = ctx.sp2_density_matrix(Hd, nocc, p.options("fp64"))
+    q = ctx.sp2_mulliken(D, len(pos)).cpu().numpy()
+    Dn = D.cpu().numpy()
+    np.testing.assert_allclose(q, observables.mulliken(Dn), atol=1e-13)
+    ref = osp2.sp2(H, nocc)
+    assert np.max(np.abs(q - observables.mulliken(ref.D))) <= 1e-9
+    e = ctx.sp2_band_energy(D, Hd)
+    assert e == pytest.approx(observables.band_energy(ref.D, H), abs=1e-8)
+
+
+def test_edge_cases_and_errors(ctx):
+    import paper_1203_6836_amd as p
+    say("case edge: diagonal, tiny, errors")
+    d = np.array([-3.0, 1.0, -2.0, 4.0, 0.0, -1.0, 2.5, -0.5])
+    D, st = ctx.sp2_density_matrix(to_dev(np.diag(d)), 4, p.options("fp64"))
+    np.testing.assert_allclose(np.diag(D.cpu().numpy()), (d <= -0.5).astype(float), atol=1e-12)
+    # N = 1 has no valid n_occ; n_occ out of range -> EINVAL
+    st_, _ = ctx.sp2_density_matrix_status(to_dev(np.diag(d)), 0)
+    assert st_ == p.SP2_EINVAL
+    st_, _ = ctx.sp2_density_matrix_status(to_dev(np.diag(d)), 8)
+    assert st_ == p.SP2_EINVAL
+    # too few products -> ENOCONV (outputs untouched)
+    _, H = oracle_H((3, 3, 3), 7)
+    st_, stats = ctx.sp2_density_matrix_status(to_dev(H), 54, p.options("fp64", max_iter=3))
+    assert st_ == p.SP2_ENOCONV and stats["iterations"] == 3
+    # bad option
+    st_, _ = ctx.sp2_density_matrix_status(to_dev(H), 54, p.options("fp64", max_iter=500))
+    assert st_ == p.SP2_EINVAL
+
+
+def test_fp64_n2048_against_oracle(ctx):
+    import paper_1203_6836_amd as p
+    say("case fp64 8x8x8 (N=2048)")
+    pos, H = oracle_H((8, 8, 8), 2)
+    nocc = 2 * len(pos)
+    ref = osp2.sp2(H, nocc)
+    D, st = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("fp64"))
+    err = np.linalg.norm(D.cpu().numpy() - ref.D) / np.sqrt(H.shape[0])
+    say(f"  iters={st['iterations']} err/sqrtN={err:.2e} ms={st['ms']:.1f}")
+    assert err <= 1e-10
+
+
+def test_fp64_full_size_properties(ctx):
+    """N = 8192 in the benchmark's configuration: properties that hold at any size."""
+    import torch
+    import paper_1203_6836_amd as p
+    say("case fp64 N=8192 properties")
+    w = synth.MIXED
+    xyz = to_dev(w.positions())
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, xyz)
+    D, st = ctx.sp2_density_matrix(H, w.n_occ, p.options("fp64"))
+    say(f"  iters={st['iterations']} ms={st['ms']:.1f} idem={st['idem_err']:.2e}")
+    assert st["status"] == "converged"
+    D2 = D @ D
+    assert float(torch.linalg.norm(D2 - D)) < 1e-9
+    assert abs(float(torch.trace(D)) - w.n_occ) < 1e-9
+    assert float(torch.linalg.norm(H @ D - D @ H)) < 1e-8
+    # sampled rows of H against the oracle's Slater-Koster construction
+    pos = w.positions()
+    Href = otb.hamiltonian0(pos[:64], synth.STATIC_MODEL)
+    np.testing.assert_allclose(H[:256, :256].cpu().numpy(), Href, atol=1e-14)
