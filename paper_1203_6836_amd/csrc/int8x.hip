@@ -1,0 +1,306 @@
+// Reduced-precision SP2 product on int8 MFMA with exact integer accumulation.
+//
+// The FP64 master X_n is split row by row into fixed-point digit planes:
+// with s_i = 2^e_i >= max_j |X_ij| (a power of two, so the scaling is exact),
+// y = X_ij / s_i in (-1, 1) is written as y ~ sum_t d_t 2^-(6 + 7 t) with
+// integer digits |d_t| <= 64 taken by successive round-to-nearest of the
+// remainder (each remainder is exact in FP64).  Because X is symmetric,
+//     (X^2)_ij = sum_k X_ik X_jk ~ s_i s_j sum_{t,u} 2^-(12 + 7(t+u)) sum_k d_t[i,k] d_u[j,k],
+// i.e. every digit product reads contiguous rows of the digit planes for both
+// operands.  Products with t + u < slices are kept; those of one level L = t+u
+// share an int32 accumulator, which is exact (|d| <= 64, at most 6 products
+// per level, K <= 65536: |acc| < 2^31).  Levels are combined in FP64 in the
+// epilogue, which then applies the SP2 update exactly like the FP64 product.
+//
+// Work layout: one 256-thread workgroup per upper-triangular 128 x 128 tile;
+// wave w covers rows 64 (w >> 1) .. +64 and columns 64 (w & 1) .. +64 as
+// 2 x 2 blocks of v_mfma_i32_32x32x32_i8 (one accumulator set per level).  K advances 32 bytes per stage;
+// both operands of a stage (slices x 128 rows x 32 bytes each) are staged
+// through LDS with a 48-byte row pitch (conflict-free 16-byte reads), double
+// buffered with a register prefetch of the next stage.
+#include "split_internal.h"
+
+namespace sp2 {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ double wred_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wred_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// --------------------------------------------------------------- encoding
+// One wave per padded row: row scale and `slices` digit planes.
+template <int S>
+__global__ __launch_bounds__(256) void k_encode_int8(const double* __restrict__ buf0,
+                                                     const double* __restrict__ buf1, int ld,
+                                                     const State* __restrict__ st,
+                                                     int8_t* __restrict__ digits,
+                                                     double* __restrict__ scale) {
+    if (st->done || st->phase != 1) return;
+    const double* X = st->cur ? buf1 : buf0;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const double* row = X + (size_t)i * ld;
+    double m = 0.0;
+    for (int j = 8 * lane; j < ld; j += 512) {
+        const double4 a = *reinterpret_cast<const double4*>(row + j);
+        const double4 b = *reinterpret_cast<const double4*>(row + j + 4);
+        m = fmax(m, fmax(fmax(fabs(a.x), fabs(a.y)), fmax(fabs(a.z), fabs(a.w))));
+        m = fmax(m, fmax(fmax(fabs(b.x), fabs(b.y)), fmax(fabs(b.z), fabs(b.w))));
+    }
+    m = wred_max(m);
+    int e = 0;
+    if (m > 0.0) (void)frexp(m, &e);     // m = f 2^e, f in [0.5, 1): |X_ij| / 2^e < 1
+    const double inv = ldexp(1.0, -e);
+    if (lane == 0) scale[i] = ldexp(1.0, e);
+    const size_t plane = (size_t)ld * ld;
+    for (int j = 8 * lane; j < ld; j += 512) {
+        double y[8];
+        const double4 a = *reinterpret_cast<const double4*>(row + j);
+        const double4 b = *reinterpret_cast<const double4*>(row + j + 4);
+        y[0] = a.x * inv; y[1] = a.y * inv; y[2] = a.z * inv; y[3] = a.w * inv;
+        y[4] = b.x * inv; y[5] = b.y * inv; y[6] = b.z * inv; y[7] = b.w * inv;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const double w = ldexp(1.0, 6 + 7 * t);      // digit weight 2^-(6+7t)
+            const double iw = ldexp(1.0, -(6 + 7 * t));
+            unsigned long long packed = 0ull;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double d = rint(y[q] * w);        // |d| <= 64
+                y[q] -= d * iw;                          // exact remainder
+                packed |= (unsigned long long)(uint8_t)(int8_t)d << (8 * q);
+            }
+            *reinterpret_cast<unsigned long long*>(digits + t * plane + (size_t)i * ld + j) = packed;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ product
+constexpr int QB = 128;          // tile
+constexpr int QK = 32;           // k bytes per stage
+constexpr int QP = 48;           // LDS row pitch (bytes)
+
+template <int S>
+struct I8Smem {
+    // [stage][operand][slice][row][QP]
+    int8_t buf[2][2][S][QB][QP];
+};
+
+__device__ __forceinline__ void tri_coords_q(int t, int nt, int& bi, int& bj) {
+    int i = 0, off = 0;
+    while (t >= off + (nt - i)) { off += nt - i; ++i; }
+    bi = i;
+    bj = i + (t - off);
+}
+__device__ __forceinline__ int xcd_remap_q(int w, int T) {
+    const int q = T >> 3, r = T & 7;
+    const int x = w & 7, k = w >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                    int ld, const State* __restrict__ st,
+                                                    const int8_t* __restrict__ digits,
+                                                    const double* __restrict__ scale,
+                                                    double* __restrict__ part) {
+    if (st->done || st->phase != 1) return;
+    extern __shared__ __align__(16) int8_t smem_raw[];
+    I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
+
+    const int nt = ld / QB;
+    const int T = nt * (nt + 1) / 2;
+    const int t = xcd_remap_q(blockIdx.x, T);
+    int bi, bj;
+    tri_coords_q(t, nt, bi, bj);
+    const int i0 = bi * QB, j0 = bj * QB;
+    const double* __restrict__ Xc = st->cur ? buf1 : buf0;
+    double* __restrict__ Xn = st->cur ? buf0 : buf1;
+    const size_t plane = (size_t)ld * ld;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+
+    // staging: 2 operands x S slices x 128 rows x 2 halves of 16 bytes
+    constexpr int CH = 2 * S * QB * 2;          // 16-byte chunks per stage
+    constexpr int PER = CH / 256;               // per thread (CH = 512 S)
+    static_assert(CH % 256 == 0, "stage must split evenly over 256 threads");
+    v4i pre[PER];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int c = tid + 256 * m;
+            const int op = c / (S * QB * 2);
+            const int rem = c - op * (S * QB * 2);
+            const int sl = rem / (QB * 2);
+            const int rr = (rem >> 1) & (QB - 1);
+            const int half = rem & 1;
+            const int grow = (op ? j0 : i0) + rr;
+            pre[m] = *reinterpret_cast<const v4i*>(digits + sl * plane + (size_t)grow * ld + k0 + 16 * half);
+        }
+    };
+    auto sstore = [&](int stg) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int c = tid + 256 * m;
+            const int op = c / (S * QB * 2);
+            const int rem = c - op * (S * QB * 2);
+            const int sl = rem / (QB * 2);
+            const int rr = (rem >> 1) & (QB - 1);
+            const int half = rem & 1;
+            *reinterpret_cast<v4i*>(&sm.buf[stg][op][sl][rr][16 * half]) = pre[m];
+        }
+    };
+
+    v16i acc[S][2][2];
+#pragma unroll
+    for (int L = 0; L < S; ++L)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[L][a2][c][r] = 0;
+
+    const int nk = ld / QK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    const int koff = 16 * (lane >> 5);
+    for (int kt = 0; kt < nk; ++kt) {
+        const int stg = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * QK);
+        v4i a[S][2];
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                a[sl][c] = *reinterpret_cast<const v4i*>(&sm.buf[stg][0][sl][wr * 64 + c * 32 + (lane & 31)][koff]);
+        // one B digit plane at a time: level tt + uu accumulates a[tt] b[uu]
+#pragma unroll
+        for (int uu = 0; uu < S; ++uu) {
+            v4i b[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                b[c] = *reinterpret_cast<const v4i*>(&sm.buf[stg][1][uu][wc * 64 + c * 32 + (lane & 31)][koff]);
+#pragma unroll
+            for (int tt = 0; tt < S - uu; ++tt)
+#pragma unroll
+                for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        acc[tt + uu][a2][c] =
+                            __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt][a2], b[c], acc[tt + uu][a2][c], 0, 0, 0);
+        }
+        if (kt + 1 < nk) sstore(stg ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: combine levels in FP64, apply the SP2 update, partials
+    const int br = st->branch;
+    const bool mirror = bi != bj;
+    double tr = 0.0, fro = 0.0, idm = 0.0;
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int gj = j0 + wc * 64 + c * 32 + (lane & 31);
+        const double sj = scale[gj];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            // v_mfma_i32_32x32x32_i8 result: lane l, element r is row 8 (r/4) + 4 (l/32) + r%4, column l%32
+            const int gi = i0 + wr * 64 + a2 * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            double v = 0.0;
+#pragma unroll
+            for (int L = S - 1; L >= 0; --L) v += ldexp((double)acc[L][a2][c][r], -(12 + 7 * L));
+            const double p = v * scale[gi] * sj;
+            const double x = Xc[(size_t)gi * ld + gj];
+            const double xn = br ? 2.0 * x - p : p;
+            Xn[(size_t)gi * ld + gj] = xn;
+            if (mirror) Xn[(size_t)gj * ld + gi] = xn;
+            if (gi == gj) tr += xn;
+            fro += xn * xn;
+            idm += (p - x) * (p - x);
+        }
+    }
+    tr = wred_sum(tr);
+    fro = wred_sum(fro);
+    idm = wred_sum(idm);
+    __shared__ double red[3][4];
+    if (lane == 0) {
+        red[0][w] = tr;
+        red[1][w] = fro;
+        red[2][w] = idm;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double s3[3];
+        for (int q = 0; q < 3; ++q)
+            s3[q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
+        const double wgt = mirror ? 2.0 : 1.0;
+        part[3 * t + 0] = s3[0];
+        part[3 * t + 1] = wgt * s3[1];
+        part[3 * t + 2] = wgt * s3[2];
+    }
+}
+
+template <int S>
+static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                            hipStream_t stream) {
+    const int nt = ld / QB;
+    const int T = nt * (nt + 1) / 2;
+    const size_t lds = sizeof(I8Smem<S>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_gemm_int8x<S>, dim3(T), dim3(256), lds, stream, buf0, buf1, ld, st, s.digits,
+                       s.scale, part);
+    return hipGetLastError();
+}
+
+template <int S>
+static hipError_t run_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
+                             hipStream_t stream) {
+    hipLaunchKernelGGL(k_encode_int8<S>, dim3(ld / 4), dim3(256), 0, stream, buf0, buf1, ld, st, s.digits,
+                       s.scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
+                               hipStream_t stream) {
+    switch (s.slices) {
+        case 2: return run_encode<2>(s, buf0, buf1, ld, st, stream);
+        case 3: return run_encode<3>(s, buf0, buf1, ld, st, stream);
+        case 4: return run_encode<4>(s, buf0, buf1, ld, st, stream);
+        case 5: return run_encode<5>(s, buf0, buf1, ld, st, stream);
+        case 6: return run_encode<6>(s, buf0, buf1, ld, st, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_int8x_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                             int* nslots, hipStream_t stream) {
+    const int nt = ld / QB;
+    *nslots = nt * (nt + 1) / 2;
+    switch (s.slices) {
+        case 2: return run_int8x<2>(s, buf0, buf1, ld, st, part, stream);
+        case 3: return run_int8x<3>(s, buf0, buf1, ld, st, part, stream);
+        case 4: return run_int8x<4>(s, buf0, buf1, ld, st, part, stream);
+        case 5: return run_int8x<5>(s, buf0, buf1, ld, st, part, stream);
+        case 6: return run_int8x<6>(s, buf0, buf1, ld, st, part, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sp2

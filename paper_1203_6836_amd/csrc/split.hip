@@ -135,10 +135,14 @@ size_t split_part_slots(int ld) {
     return (size_t)nt * (nt + 1) / 2;
 }
 
-hipError_t launch_split_encode(SplitScratch&, const double*, const double*, int, State*, hipStream_t) {
+hipError_t launch_split_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
+                               hipStream_t stream) {
+    if (s.slices > 0) return launch_int8x_encode(s, buf0, buf1, ld, st, stream);
     return hipErrorNotSupported;
 }
-hipError_t launch_split_gemm(SplitScratch&, double*, double*, int, State*, double*, int*, hipStream_t) {
+hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                             int* nslots, hipStream_t stream) {
+    if (s.slices > 0) return launch_int8x_gemm(s, buf0, buf1, ld, st, part, nslots, stream);
     return hipErrorNotSupported;
 }
 

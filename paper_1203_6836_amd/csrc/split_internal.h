@@ -39,4 +39,10 @@ hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, State* st,
                                   double* part, int* nslots, int init, hipStream_t stream);
 
+// int8 digit-plane product (int8x.hip)
+hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
+                               hipStream_t stream);
+hipError_t launch_int8x_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                             int* nslots, hipStream_t stream);
+
 }  // namespace sp2

@@ -1,0 +1,102 @@
+"""GPU parity of the reduced-precision SP2 products against the FP64 oracle (tolerance 1e-6)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import observables, sp2 as osp2, tb as otb
+
+pytestmark = pytest.mark.gpu
+TOL_D = 1e-6     # ||D - D_ref||_F / sqrt(N)
+TOL_Q = 1e-6     # max_i |q_i - q_i_ref| (e)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_1203_6836_amd as p
+    c = p.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("dims,seed", [((4, 4, 4), 0), ((3, 3, 3), 7), ((6, 6, 5), 12), ((8, 8, 8), 2)])
+def test_int8x_matches_oracle(ctx, dims, seed):
+    import paper_1203_6836_amd as p
+    say(f"case int8x dims={dims} seed={seed}")
+    pos = synth.lattice_positions(dims, seed=seed)
+    H = otb.hamiltonian(pos, None, synth.STATIC_MODEL)
+    nocc = 2 * len(pos)
+    ref = osp2.sp2(H, nocc)
+    D, st = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("int8x"))
+    q = ctx.sp2_mulliken(D, len(pos)).cpu().numpy()
+    D = D.cpu().numpy()
+    N = H.shape[0]
+    err = np.linalg.norm(D - ref.D) / np.sqrt(N)
+    dq = np.max(np.abs(q - observables.mulliken(ref.D)))
+    say(f"  iters={st['iterations']} (fp64 {ref.iterations}) status={st['status']} err/sqrtN={err:.2e} "
+        f"max|dq|={dq:.2e} idem={st['idem_err']:.2e}")
+    assert st["fp64_products"] == 0 and st["head_switch"] == 0
+    assert err <= TOL_D
+    assert dq <= TOL_Q
+    assert abs(np.trace(D) - nocc) < 1e-6
+    assert np.array_equal(D, D.T)
+
+
+def test_int8x_options_head_and_slices(ctx):
+    import paper_1203_6836_amd as p
+    say("case int8x head=3 / slices=6 / slices=3")
+    pos = synth.lattice_positions((5, 5, 5), seed=11)
+    H = otb.hamiltonian(pos, None, synth.STATIC_MODEL)
+    nocc = 2 * len(pos)
+    ref = osp2.sp2(H, nocc)
+    N = H.shape[0]
+    D, st = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("int8x", fp64_head=3))
+    assert st["fp64_products"] == 3 and st["head_switch"] == 3
+    assert np.linalg.norm(D.cpu().numpy() - ref.D) / np.sqrt(N) <= TOL_D
+    D6, st6 = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("int8x", slices=6))
+    e6 = np.linalg.norm(D6.cpu().numpy() - ref.D) / np.sqrt(N)
+    D3, st3 = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("int8x", slices=3))
+    e3 = np.linalg.norm(D3.cpu().numpy() - ref.D) / np.sqrt(N)
+    say(f"  slices=6 err {e6:.2e}; slices=3 err {e3:.2e}")
+    assert e6 <= 1e-8
+    assert e3 > e6          # fewer digit planes: visibly less accurate
+
+
+def test_int8x_deterministic(ctx):
+    import paper_1203_6836_amd as p
+    say("case int8x determinism")
+    pos = synth.lattice_positions((6, 6, 5), seed=12)
+    Hd = to_dev(otb.hamiltonian(pos, None, synth.STATIC_MODEL))
+    D1, s1 = ctx.sp2_density_matrix(Hd, 2 * len(pos), p.options("int8x"))
+    D2, s2 = ctx.sp2_density_matrix(Hd, 2 * len(pos), p.options("int8x"))
+    assert bool((D1 == D2).all()) and s1["branches"] == s2["branches"]
+
+
+def test_int8x_full_size_against_fp64_path(ctx):
+    """N = 8192 as benchmarked: against the FP64 GPU path (itself pinned to the oracle)."""
+    import torch
+    import paper_1203_6836_amd as p
+    say("case int8x N=8192 vs fp64 path")
+    w = synth.MIXED
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, to_dev(w.positions()))
+    D64, s64 = ctx.sp2_density_matrix(H, w.n_occ, p.options("fp64"))
+    D8, s8 = ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x"))
+    err = float(torch.linalg.norm(D8 - D64)) / w.n_orb ** 0.5
+    dq = float((ctx.sp2_mulliken(D8, w.n_atoms) - ctx.sp2_mulliken(D64, w.n_atoms)).abs().max())
+    idem = float(torch.linalg.norm(D8 @ D8 - D8))
+    say(f"  iters {s8['iterations']} vs {s64['iterations']}  ms {s8['ms']:.1f} vs {s64['ms']:.1f}  "
+        f"err/sqrtN={err:.2e} max|dq|={dq:.2e} idem={idem:.2e}")
+    assert err <= TOL_D and dq <= TOL_Q
