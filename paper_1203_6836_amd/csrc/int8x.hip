@@ -12,12 +12,7 @@
 // per level, K <= 65536: |acc| < 2^31).  Levels are combined in FP64 in the
 // epilogue, which then applies the SP2 update exactly like the FP64 product.
 //
-// Work layout: one 256-thread workgroup per upper-triangular 128 x 128 tile;
-// wave w covers rows 64 (w >> 1) .. +64 and columns 64 (w & 1) .. +64 as
-// 2 x 2 blocks of v_mfma_i32_32x32x32_i8 (one accumulator set per level).  K advances 32 bytes per stage;
-// both operands of a stage (slices x 128 rows x 32 bytes each) are staged
-// through LDS with a 48-byte row pitch (conflict-free 16-byte reads), double
-// buffered with a register prefetch of the next stage.
+// Work layout, storage and staging: see the comments at the kernels.
 #include "split_internal.h"
 
 namespace sp2 {
@@ -33,6 +28,15 @@ __device__ __forceinline__ double wred_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// Digit planes are stored blocked: plane t, row i, column j lives in the
+// 1 KiB block (i / 32, j / 32) (blocks row-major, ld / 32 per block row), at
+// byte (i % 32) * 32 + 16 * (((j / 16) % 2) ^ swz(i % 32)) + j % 16.  One
+// block is one MFMA operand fragment for 32 rows and 32 k: a wave stages it
+// with one contiguous 16-byte-per-lane load, and the swizzle
+// swz(r) = ((r >> 2) ^ (r >> 3)) & 1 makes the fragment reads (lane l: row
+// l % 32, k-half l / 32) free of LDS bank conflicts.
+__device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 
 // --------------------------------------------------------------- encoding
 // One wave per padded row: row scale and `slices` digit planes.
@@ -60,12 +64,15 @@ __global__ __launch_bounds__(256) void k_encode_int8(const double* __restrict__ 
     const double inv = ldexp(1.0, -e);
     if (lane == 0) scale[i] = ldexp(1.0, e);
     const size_t plane = (size_t)ld * ld;
+    const size_t rowblk = (size_t)(i >> 5) * (ld >> 5);
+    const int r32 = i & 31;
     for (int j = 8 * lane; j < ld; j += 512) {
         double y[8];
         const double4 a = *reinterpret_cast<const double4*>(row + j);
         const double4 b = *reinterpret_cast<const double4*>(row + j + 4);
         y[0] = a.x * inv; y[1] = a.y * inv; y[2] = a.z * inv; y[3] = a.w * inv;
         y[4] = b.x * inv; y[5] = b.y * inv; y[6] = b.z * inv; y[7] = b.w * inv;
+        const size_t off = (rowblk + (j >> 5)) * 1024 + r32 * 32 + 16 * (((j >> 4) & 1) ^ dswz(r32)) + (j & 15);
 #pragma unroll
         for (int t = 0; t < S; ++t) {
             const double w = ldexp(1.0, 6 + 7 * t);      // digit weight 2^-(6+7t)
@@ -77,36 +84,28 @@ __global__ __launch_bounds__(256) void k_encode_int8(const double* __restrict__ 
                 y[q] -= d * iw;                          // exact remainder
                 packed |= (unsigned long long)(uint8_t)(int8_t)d << (8 * q);
             }
-            *reinterpret_cast<unsigned long long*>(digits + t * plane + (size_t)i * ld + j) = packed;
+            *reinterpret_cast<unsigned long long*>(digits + t * plane + off) = packed;
         }
     }
 }
 
 // ------------------------------------------------------------------ product
+// One 512-thread workgroup per upper-triangular 128 x 128 tile; wave w
+// covers rows 32 (w >> 1) .. +32 and columns 64 (w & 1) .. +64 as two 32 x 32
+// blocks of v_mfma_i32_32x32x32_i8 per level (S x 2 accumulators of 16
+// int32).  Each K stage (32 bytes of k) stages 2 operands x S planes x 4 row
+// blocks of 1 KiB through LDS in the blocked layout, double buffered, with
+// the next stage's loads in flight in registers.
 constexpr int QB = 128;          // tile
 constexpr int QK = 32;           // k bytes per stage
-constexpr int QP = 48;           // LDS row pitch (bytes)
 
 template <int S>
 struct I8Smem {
-    // [stage][operand][slice][row][QP]
-    int8_t buf[2][2][S][QB][QP];
+    int8_t buf[2][2 * S * 4][1024];   // [stage][op * S * 4 + slice * 4 + row block][block]
 };
 
-__device__ __forceinline__ void tri_coords_q(int t, int nt, int& bi, int& bj) {
-    int i = 0, off = 0;
-    while (t >= off + (nt - i)) { off += nt - i; ++i; }
-    bi = i;
-    bj = i + (t - off);
-}
-__device__ __forceinline__ int xcd_remap_q(int w, int T) {
-    const int q = T >> 3, r = T & 7;
-    const int x = w & 7, k = w >> 3;
-    return x * q + (x < r ? x : r) + k;
-}
-
 template <int S>
-__global__ __launch_bounds__(256) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
+__global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
                                                     int ld, const State* __restrict__ st,
                                                     const int8_t* __restrict__ digits,
                                                     const double* __restrict__ scale,
@@ -116,88 +115,76 @@ __global__ __launch_bounds__(256) void k_gemm_int8x(double* __restrict__ buf0, d
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
 
     const int nt = ld / QB;
-    const int T = nt * (nt + 1) / 2;
-    const int t = xcd_remap_q(blockIdx.x, T);
     int bi, bj;
-    tri_coords_q(t, nt, bi, bj);
+    tile_of_block(blockIdx.x, nt, bi, bj);
+    const int t = tri_index(bi, bj, nt);
     const int i0 = bi * QB, j0 = bj * QB;
     const double* __restrict__ Xc = st->cur ? buf1 : buf0;
     double* __restrict__ Xn = st->cur ? buf0 : buf1;
     const size_t plane = (size_t)ld * ld;
+    const int nb = ld >> 5;          // blocks per block row
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
 
-    // staging: 2 operands x S slices x 128 rows x 2 halves of 16 bytes
-    constexpr int CH = 2 * S * QB * 2;          // 16-byte chunks per stage
-    constexpr int PER = CH / 256;               // per thread (CH = 512 S)
-    static_assert(CH % 256 == 0, "stage must split evenly over 256 threads");
+    constexpr int NBLK = 2 * S * 4;             // 1 KiB blocks per stage
+    constexpr int PER = NBLK * 64 / 512;        // 16-byte chunks per thread
+    static_assert((NBLK * 64) % 512 == 0, "stage must split evenly over 512 threads");
     v4i pre[PER];
-    auto gload = [&](int k0) {
+    auto gload = [&](int kb) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
-            const int c = tid + 256 * m;
-            const int op = c / (S * QB * 2);
-            const int rem = c - op * (S * QB * 2);
-            const int sl = rem / (QB * 2);
-            const int rr = (rem >> 1) & (QB - 1);
-            const int half = rem & 1;
-            const int grow = (op ? j0 : i0) + rr;
-            pre[m] = *reinterpret_cast<const v4i*>(digits + sl * plane + (size_t)grow * ld + k0 + 16 * half);
+            const int c = tid + 512 * m;
+            const int blk = c >> 6;
+            const int op = blk / (S * 4);
+            const int rem = blk - op * (S * 4);
+            const int sl = rem >> 2, rb = rem & 3;
+            const int grb = ((op ? j0 : i0) >> 5) + rb;
+            pre[m] = *reinterpret_cast<const v4i*>(digits + sl * plane + ((size_t)grb * nb + kb) * 1024 +
+                                                   16 * (c & 63));
         }
     };
     auto sstore = [&](int stg) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
-            const int c = tid + 256 * m;
-            const int op = c / (S * QB * 2);
-            const int rem = c - op * (S * QB * 2);
-            const int sl = rem / (QB * 2);
-            const int rr = (rem >> 1) & (QB - 1);
-            const int half = rem & 1;
-            *reinterpret_cast<v4i*>(&sm.buf[stg][op][sl][rr][16 * half]) = pre[m];
+            const int c = tid + 512 * m;
+            *reinterpret_cast<v4i*>(&sm.buf[stg][c >> 6][16 * (c & 63)]) = pre[m];
         }
     };
 
-    v16i acc[S][2][2];
+    v16i acc[S][2];
 #pragma unroll
     for (int L = 0; L < S; ++L)
 #pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2)
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[L][a2][c][r] = 0;
+            for (int r = 0; r < 16; ++r) acc[L][c][r] = 0;
 
+    // fragment address inside a block: row lane % 32, k-half lane / 32
+    const int fr = lane & 31;
+    const int foff = fr * 32 + 16 * ((lane >> 5) ^ dswz(fr));
     const int nk = ld / QK;
     gload(0);
     sstore(0);
     __syncthreads();
-    const int koff = 16 * (lane >> 5);
     for (int kt = 0; kt < nk; ++kt) {
         const int stg = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * QK);
-        v4i a[S][2];
+        if (kt + 1 < nk) gload(kt + 1);
+        v4i a[S];
 #pragma unroll
         for (int sl = 0; sl < S; ++sl)
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-                a[sl][c] = *reinterpret_cast<const v4i*>(&sm.buf[stg][0][sl][wr * 64 + c * 32 + (lane & 31)][koff]);
-        // one B digit plane at a time: level tt + uu accumulates a[tt] b[uu]
+            a[sl] = *reinterpret_cast<const v4i*>(&sm.buf[stg][sl * 4 + wr][foff]);
 #pragma unroll
         for (int uu = 0; uu < S; ++uu) {
             v4i b[2];
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-                b[c] = *reinterpret_cast<const v4i*>(&sm.buf[stg][1][uu][wc * 64 + c * 32 + (lane & 31)][koff]);
+                b[c] = *reinterpret_cast<const v4i*>(&sm.buf[stg][S * 4 + uu * 4 + wc * 2 + c][foff]);
 #pragma unroll
             for (int tt = 0; tt < S - uu; ++tt)
 #pragma unroll
-                for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-                        acc[tt + uu][a2][c] =
-                            __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt][a2], b[c], acc[tt + uu][a2][c], 0, 0, 0);
+                for (int c = 0; c < 2; ++c)
+                    acc[tt + uu][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt], b[c], acc[tt + uu][c], 0, 0, 0);
         }
         if (kt + 1 < nk) sstore(stg ^ 1);
         __syncthreads();
@@ -208,18 +195,16 @@ __global__ __launch_bounds__(256) void k_gemm_int8x(double* __restrict__ buf0, d
     const bool mirror = bi != bj;
     double tr = 0.0, fro = 0.0, idm = 0.0;
 #pragma unroll
-    for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int gj = j0 + wc * 64 + c * 32 + (lane & 31);
         const double sj = scale[gj];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             // v_mfma_i32_32x32x32_i8 result: lane l, element r is row 8 (r/4) + 4 (l/32) + r%4, column l%32
-            const int gi = i0 + wr * 64 + a2 * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int gi = i0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
             double v = 0.0;
 #pragma unroll
-            for (int L = S - 1; L >= 0; --L) v += ldexp((double)acc[L][a2][c][r], -(12 + 7 * L));
+            for (int L = S - 1; L >= 0; --L) v += ldexp((double)acc[L][c][r], -(12 + 7 * L));
             const double p = v * scale[gi] * sj;
             const double x = Xc[(size_t)gi * ld + gj];
             const double xn = br ? 2.0 * x - p : p;
@@ -233,7 +218,7 @@ __global__ __launch_bounds__(256) void k_gemm_int8x(double* __restrict__ buf0, d
     tr = wred_sum(tr);
     fro = wred_sum(fro);
     idm = wred_sum(idm);
-    __shared__ double red[3][4];
+    __shared__ double red[3][8];
     if (lane == 0) {
         red[0][w] = tr;
         red[1][w] = fro;
@@ -243,7 +228,8 @@ __global__ __launch_bounds__(256) void k_gemm_int8x(double* __restrict__ buf0, d
     if (tid == 0) {
         double s3[3];
         for (int q = 0; q < 3; ++q)
-            s3[q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
+            s3[q] = ((red[q][0] + red[q][1]) + (red[q][2] + red[q][3])) +
+                    ((red[q][4] + red[q][5]) + (red[q][6] + red[q][7]));
         const double wgt = mirror ? 2.0 : 1.0;
         part[3 * t + 0] = s3[0];
         part[3 * t + 1] = wgt * s3[1];
@@ -264,7 +250,7 @@ static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld,
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_gemm_int8x<S>, dim3(T), dim3(256), lds, stream, buf0, buf1, ld, st, s.digits,
+    hipLaunchKernelGGL(k_gemm_int8x<S>, dim3(T), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
                        s.scale, part);
     return hipGetLastError();
 }

@@ -288,10 +288,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
                                                      double* __restrict__ part) {
     if (st->done || st->phase != 0) return;
     const int nt = ld / GB;
-    const int T = nt * (nt + 1) / 2;
-    const int t = xcd_remap(blockIdx.x, T);
     int bi, bj;
-    tri_coords(t, nt, bi, bj);
+    tile_of_block(blockIdx.x, nt, bi, bj);
+    const int t = tri_index(bi, bj, nt);
     const double* __restrict__ Xc = st->cur ? buf1 : buf0;
     double* __restrict__ Xn = st->cur ? buf0 : buf1;
     const int i0 = bi * GB, j0 = bj * GB;

@@ -44,6 +44,51 @@ struct CtrlArgs {
 // Number of upper-triangular tile pairs (bi <= bj) of an nt x nt tile grid.
 inline int tri_tiles(int nt) { return nt * (nt + 1) / 2; }
 
+#ifndef SP2_SUPER_G
+#define SP2_SUPER_G 8
+#endif
+
+// Canonical slot of tile (bi, bj), bi <= bj: row-major over the upper triangle.
+__device__ __forceinline__ int tri_index(int bi, int bj, int nt) {
+    return bi * nt - bi * (bi - 1) / 2 + (bj - bi);
+}
+
+// Order of the upper-triangular tiles (bi <= bj) of the symmetric product:
+// the grid is cut into G x G super-tiles, visited row-major over the upper
+// super-triangle, tiles row-major inside each; workgroup ids are dealt so that
+// each of the 8 XCDs (which receive workgroups round-robin) owns a contiguous
+// run of this order.  Concurrent workgroups of one XCD then share a few row
+// panels on both operand sides, which keeps the panels in that XCD's L2.
+__device__ __forceinline__ void tile_of_block(int w, int nt, int& bi, int& bj) {
+    const int T = nt * (nt + 1) / 2;
+    const int q = T >> 3, r = T & 7;
+    const int x = w & 7, k = w >> 3;
+    int t = x * q + (x < r ? x : r) + k;   // position in the visiting order
+    const int G = SP2_SUPER_G > 0 ? SP2_SUPER_G : nt;
+    const int ns = (nt + G - 1) / G;
+    for (int I = 0; I < ns; ++I) {
+        const int gi = min(G, nt - I * G);
+        for (int J = I; J < ns; ++J) {
+            const int gj = min(G, nt - J * G);
+            const int cnt = (I == J) ? gi * (gi + 1) / 2 : gi * gj;
+            if (t < cnt) {
+                if (I == J) {
+                    int li = 0, off = 0;
+                    while (t >= off + (gi - li)) { off += gi - li; ++li; }
+                    bi = I * G + li;
+                    bj = I * G + li + (t - off);
+                } else {
+                    bi = I * G + t / gj;
+                    bj = J * G + t % gj;
+                }
+                return;
+            }
+            t -= cnt;
+        }
+    }
+    bi = bj = 0;   // unreachable for w < T
+}
+
 // ---- launchers (sp2_dense.hip) ----
 hipError_t launch_gershgorin(const double* H, int N, double* part, int* nslots, hipStream_t s);
 hipError_t launch_bounds(const double* part, int nslots, State* st, hipStream_t s);
