@@ -33,7 +33,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(H_np, n_occ, n_products=2):
+def cpu_baseline(H_np, n_occ, n_products=10):
     """The oracle's SP2 loop (numpy/OpenBLAS) on a bounded sample: n_products products."""
     from oracle import sp2 as osp2
     try:
