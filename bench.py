@@ -51,6 +51,83 @@ def cpu_baseline(H_np, n_occ, n_products=10):
                       f"Hamiltonian, {dt:.1f} s; GEMM-equivalent 2N^3 flops per product"}
 
 
+def serving(ctx, n_requests, rate):
+    """Serve a Poisson stream of SP2 solves (32-512 atoms each) open loop, then the
+    same stream with serial plain-FP64 solves; latency = arrival -> result in host memory."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1203_6836_amd as p
+    import synth
+
+    reqs = synth.request_stream(n_requests=n_requests, rate_per_s=rate)
+    log(f"serving: building {len(reqs)} Hamiltonians on the GPU")
+    Hs = []
+    for r in reqs:
+        xyz = torch.from_numpy(r.positions()).cuda()
+        Hs.append(ctx.tb_hamiltonian(synth.STATIC_MODEL, xyz).cpu().numpy())
+    torch.cuda.synchronize()
+
+    log("serving: continuous batching (int8 digit planes)")
+    srv = p.Server(ctx)
+    lag = [0.0] * len(reqs)
+    tickets = [None] * len(reqs)
+
+    def submitter():
+        t0 = time.perf_counter()
+        for k, r in enumerate(reqs):
+            dt = r.arrival_s - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            lag[k] = max(0.0, time.perf_counter() - t0 - r.arrival_s) * 1e3
+            tickets[k] = srv.sp2_server_submit(Hs[k], 2 * r.n_atoms)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    lat = []
+    iters = []
+    for k, r in enumerate(reqs):
+        _, _, st = srv.sp2_server_wait(tickets[k], r.n_orb, want_D=True)
+        # arrival -> result in host memory: submitter lag + (submit -> result) from the server
+        lat.append(lag[k] + st["ms"])
+        iters.append(st["iterations"])
+    span = max(r.arrival_s + l * 1e-3 for r, l in zip(reqs, lat))
+    rep = srv.sp2_server_report()
+    srv.close()
+    flops = sum(2.0 * r.n_orb ** 3 * it for r, it in zip(reqs, iters))
+
+    log("serving: serial FP64 baseline")
+    opts = p.options("fp64")
+    finish_times = [0.0] * len(reqs)
+
+    def run_serial():
+        # solve requests in arrival order, each as soon as it has arrived
+        t0 = time.perf_counter()
+        for k, r in enumerate(reqs):
+            dt = r.arrival_s - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            H = torch.from_numpy(Hs[k]).cuda()
+            D, _ = ctx.sp2_density_matrix(H, 2 * r.n_atoms, opts)
+            D.cpu()
+            finish_times[k] = time.perf_counter() - t0
+
+    run_serial()
+    lat64 = [(finish_times[k] - r.arrival_s) * 1e3 for k, r in enumerate(reqs)]
+    span64 = max(finish_times)
+    pc = lambda v, q: float(np.percentile(np.array(v), q))
+    return {"workload": f"{len(reqs)} requests, 32-512 atoms (N=128-2048), Poisson {rate:g}/s",
+            "p50_ms": round(pc(lat, 50), 3), "p99_ms": round(pc(lat, 99), 3),
+            "solves_per_s": round(len(reqs) / span, 2),
+            "useful_tflops": round(flops / span / 1e12, 3),
+            "server_report": {k: round(v, 3) for k, v in rep.items()},
+            "baseline_serial_fp64": {"p50_ms": round(pc(lat64, 50), 3), "p99_ms": round(pc(lat64, 99), 3),
+                                     "solves_per_s": round(len(reqs) / span64, 2)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +137,8 @@ def main():
     ap.add_argument("--slices", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -162,6 +241,8 @@ def main():
         "err_vs_fp64_per_sqrtN": err, "max_dq_vs_fp64": dq, "idempotency": idem,
         "roofline": roof,
     }
+    if args.serve_requests > 0 and prec == "int8x":
+        out["serving"] = serving(ctx, args.serve_requests, args.serve_rate)
     if not args.no_cpu:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(H.cpu().numpy(), nocc)

@@ -194,6 +194,53 @@ sp2_status xlbomd_get(xlbomd *md, double *xyz_host, double *vel_host,
                       double *q_host, double *n_host);
 void xlbomd_destroy(xlbomd *md);
 
+/* ---------------------------------------------------------------------
+ * Serving: continuous batching of SP2 solves (int8 digit-plane products)
+ * ------------------------------------------------------------------- */
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* device arena for admitted requests (default 8 GiB) */
+    int max_slots;             /* systems in flight at once, 1..64 (default 32)      */
+    int slices;                /* int8 digit planes, 2..6 (default 5)                */
+    int max_iter;              /* products per solve (default 100)                   */
+    double idem_tol;           /* converged when ||X^2 - X||_F < idem_tol (1e-10)    */
+    int iters_per_tick;        /* products per scheduler tick, 1..16 (default 1)     */
+} sp2_server_options;
+
+typedef struct sp2_server sp2_server;
+
+void sp2_server_options_default(sp2_server_options *opt);
+
+/* Start a server on the context's device with its own stream and scheduler
+ * thread.  Requests are admitted in arrival order whenever a slot is free and
+ * their device footprint (about 37 N^2 bytes for 5 planes) fits in the arena;
+ * every tick advances all admitted systems by one product in grouped,
+ * graph-replayed launches, and finished systems are retired and replaced
+ * between ticks.  Each result is independent of the other requests in flight. */
+sp2_status sp2_server_create(sp2_ctx *ctx, const sp2_server_options *opt, sp2_server **out);
+
+/* Queue one solve of the symmetric N x N host matrix H_host (copied before
+ * returning) with trace n_occ.  SP2_EBUDGET if it can never fit the arena.
+ * Thread-safe. */
+sp2_status sp2_server_submit(sp2_server *srv, int N, const double *H_host, int n_occ,
+                             uint64_t *ticket);
+
+/* Wait for a ticket (timeout_s < 0: forever) and copy D (N x N) and, when N is
+ * a multiple of 4, the Mulliken charges (N / 4) to host arrays (either may be
+ * NULL).  Returns the solve's status; SP2_ETIMEOUT leaves the ticket valid.
+ * stats->ms is the latency from submit to result in host memory.  Thread-safe. */
+sp2_status sp2_server_wait(sp2_server *srv, uint64_t ticket, double timeout_s,
+                           double *D_out_host, double *q_out_host, sp2_stats *stats);
+
+/* Latency percentiles (submit to result in host memory) over all completed
+ * requests, and completed requests per second since the first submit. */
+sp2_status sp2_server_report(sp2_server *srv, double *p50_ms, double *p99_ms,
+                             double *solves_per_s);
+
+/* Stop the scheduler (after the systems in flight finish) and free everything;
+ * queued requests that were not admitted are dropped. */
+void sp2_server_destroy(sp2_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

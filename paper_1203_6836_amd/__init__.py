@@ -72,6 +72,12 @@ class XLRecord(ctypes.Structure):
                 ("sp2_iterations", ctypes.c_int)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int),
+                ("slices", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("idem_tol", ctypes.c_double), ("iters_per_tick", ctypes.c_int)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int
@@ -95,6 +101,12 @@ _SIGS = {
     "xlbomd_run": (_I, [_P, _I, ctypes.POINTER(XLRecord)]),
     "xlbomd_get": (_I, [_P, _P, _P, _P, _P]),
     "xlbomd_destroy": (None, [_P]),
+    "sp2_server_options_default": (None, [ctypes.POINTER(ServerOptions)]),
+    "sp2_server_create": (_I, [_P, ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
+    "sp2_server_submit": (_I, [_P, _I, _P, _I, ctypes.POINTER(ctypes.c_uint64)]),
+    "sp2_server_wait": (_I, [_P, ctypes.c_uint64, _D, _P, _P, ctypes.POINTER(Sp2Stats)]),
+    "sp2_server_report": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "sp2_server_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -288,6 +300,58 @@ class XLBOMD:
     def close(self):
         if self._h:
             lib().xlbomd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching SP2 server (host numpy matrices in and out)."""
+
+    def __init__(self, ctx: Context, **kw):
+        o = ServerOptions()
+        lib().sp2_server_options_default(ctypes.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        self.ctx = ctx
+        self._h = ctypes.c_void_p()
+        st = lib().sp2_server_create(ctx._h, ctypes.byref(o), ctypes.byref(self._h))
+        if st != SP2_OK:
+            raise Sp2Error(st, "sp2_server_create: " + lib().sp2_strerror(st).decode())
+
+    def sp2_server_submit(self, H, n_occ: int) -> int:
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        t = ctypes.c_uint64()
+        st = lib().sp2_server_submit(self._h, H.shape[0], H.ctypes.data_as(_P), int(n_occ), ctypes.byref(t))
+        if st != SP2_OK:
+            raise Sp2Error(st, "sp2_server_submit: " + lib().sp2_strerror(st).decode())
+        return t.value
+
+    def sp2_server_wait(self, ticket: int, N: int, timeout_s: float = -1.0, want_D: bool = True):
+        D = np.empty((N, N)) if want_D else None
+        q = np.empty(N // 4) if N % 4 == 0 else None
+        stats = Sp2Stats()
+        st = lib().sp2_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout_s),
+                                   D.ctypes.data_as(_P) if D is not None else None,
+                                   q.ctypes.data_as(_P) if q is not None else None, ctypes.byref(stats))
+        if st != SP2_OK:
+            raise Sp2Error(st, "sp2_server_wait: " + lib().sp2_strerror(st).decode())
+        return D, q, stats.to_dict()
+
+    def sp2_server_report(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().sp2_server_report(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return {"p50_ms": a.value, "p99_ms": b.value, "solves_per_s": c.value}
+
+    def close(self):
+        if self._h:
+            lib().sp2_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

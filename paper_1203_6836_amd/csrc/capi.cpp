@@ -49,6 +49,8 @@ struct sp2_ctx {
     size_t natcap = 0;
 };
 
+int sp2_ctx_device_of(const sp2_ctx* c) { return c->device; }
+
 static sp2_status fail(sp2_ctx* c, sp2_status s, const std::string& msg) {
     if (c) c->err = msg;
     return s;

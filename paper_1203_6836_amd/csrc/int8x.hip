@@ -41,15 +41,8 @@ __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 // --------------------------------------------------------------- encoding
 // One wave per padded row: row scale and `slices` digit planes.
 template <int S>
-__global__ __launch_bounds__(256) void k_encode_int8(const double* __restrict__ buf0,
-                                                     const double* __restrict__ buf1, int ld,
-                                                     const State* __restrict__ st,
-                                                     int8_t* __restrict__ digits,
-                                                     double* __restrict__ scale) {
-    if (st->done || st->phase != 1) return;
-    const double* X = st->cur ? buf1 : buf0;
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ void encode_row(const double* __restrict__ X, int ld, int i, int lane, int8_t* __restrict__ digits,
+                           double* __restrict__ scale) {
     const double* row = X + (size_t)i * ld;
     double m = 0.0;
     for (int j = 8 * lane; j < ld; j += 512) {
@@ -89,6 +82,31 @@ __global__ __launch_bounds__(256) void k_encode_int8(const double* __restrict__ 
     }
 }
 
+// One wave per padded row: row scale and `slices` digit planes of X_n.
+template <int S>
+__global__ __launch_bounds__(256) void k_encode_int8(const double* __restrict__ buf0,
+                                                     const double* __restrict__ buf1, int ld,
+                                                     const State* __restrict__ st,
+                                                     int8_t* __restrict__ digits,
+                                                     double* __restrict__ scale) {
+    if (st->done || st->phase != 1) return;
+    encode_row<S>(st->cur ? buf1 : buf0, ld, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63, digits, scale);
+}
+
+// Grouped: work item = 4 rows of one system; fixed grid, grid-stride loop.
+template <int S>
+__global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __restrict__ g) {
+    const int total = g->total_rowq;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = group_find(g->row_off, g->nsys, item);
+        const SysView& v = g->sys[s];
+        const State* st = v.st;
+        if (st->done || st->phase != 1) continue;
+        const int i = (item - g->row_off[s]) * 4 + (threadIdx.x >> 6);
+        encode_row<S>(st->cur ? v.buf1 : v.buf0, v.ld, i, threadIdx.x & 63, v.digits, v.scale);
+    }
+}
+
 // ------------------------------------------------------------------ product
 // One 512-thread workgroup per upper-triangular 128 x 128 tile; wave w
 // covers rows 32 (w >> 1) .. +32 and columns 64 (w & 1) .. +64 as two 32 x 32
@@ -104,19 +122,14 @@ struct I8Smem {
     int8_t buf[2][2 * S * 4][1024];   // [stage][op * S * 4 + slice * 4 + row block][block]
 };
 
+// One 128 x 128 output tile (bi, bj) of one system; all 512 threads of the
+// workgroup take part (the body contains barriers).
 template <int S>
-__global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
-                                                    int ld, const State* __restrict__ st,
-                                                    const int8_t* __restrict__ digits,
-                                                    const double* __restrict__ scale,
-                                                    double* __restrict__ part) {
-    if (st->done || st->phase != 1) return;
-    extern __shared__ __align__(16) int8_t smem_raw[];
-    I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
-
+__device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1, int ld,
+                           const State* __restrict__ st, const int8_t* __restrict__ digits,
+                           const double* __restrict__ scale, double* __restrict__ part, int bi, int bj,
+                           I8Smem<S>& sm) {
     const int nt = ld / QB;
-    int bi, bj;
-    tile_of_block(blockIdx.x, nt, bi, bj);
     const int t = tri_index(bi, bj, nt);
     const int i0 = bi * QB, j0 = bj * QB;
     const double* __restrict__ Xc = st->cur ? buf1 : buf0;
@@ -238,6 +251,39 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
 }
 
 template <int S>
+__global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                    int ld, const State* __restrict__ st,
+                                                    const int8_t* __restrict__ digits,
+                                                    const double* __restrict__ scale,
+                                                    double* __restrict__ part) {
+    if (st->done || st->phase != 1) return;
+    extern __shared__ __align__(16) int8_t smem_raw[];
+    I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
+    int bi, bj;
+    tile_of_block(blockIdx.x, ld / QB, bi, bj);
+    int8x_tile<S>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm);
+}
+
+// Grouped: every upper-triangular tile of every system in the group; a fixed
+// grid loops over them (so the launch can be captured once and replayed).
+template <int S>
+__global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __restrict__ g) {
+    extern __shared__ __align__(16) int8_t smem_raw[];
+    I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
+    const int total = g->total_tiles;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = group_find(g->tile_off, g->nsys, item);
+        const SysView& v = g->sys[s];
+        if (v.st->done || v.st->phase != 1) continue;
+        int bi = 0, bj = 0, tl = item - g->tile_off[s], nt = v.ld / QB, off = 0;
+        while (tl >= off + (nt - bi)) { off += nt - bi; ++bi; }
+        bj = bi + (tl - off);
+        int8x_tile<S>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm);
+        __syncthreads();
+    }
+}
+
+template <int S>
 static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                             hipStream_t stream) {
     const int nt = ld / QB;
@@ -261,6 +307,32 @@ static hipError_t run_encode(SplitScratch& s, const double* buf0, const double* 
     hipLaunchKernelGGL(k_encode_int8<S>, dim3(ld / 4), dim3(256), 0, stream, buf0, buf1, ld, st, s.digits,
                        s.scale);
     return hipGetLastError();
+}
+
+template <int S>
+static hipError_t run_grouped(const GroupDesc* g, int gemm_blocks, hipStream_t stream) {
+    const size_t lds = sizeof(I8Smem<S>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x_grouped<S>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_encode_int8_grouped<S>, dim3(1024), dim3(256), 0, stream, g);
+    hipLaunchKernelGGL(k_gemm_int8x_grouped<S>, dim3(gemm_blocks), dim3(512), lds, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_int8x_grouped(int slices, const GroupDesc* g, int gemm_blocks, hipStream_t stream) {
+    switch (slices) {
+        case 2: return run_grouped<2>(g, gemm_blocks, stream);
+        case 3: return run_grouped<3>(g, gemm_blocks, stream);
+        case 4: return run_grouped<4>(g, gemm_blocks, stream);
+        case 5: return run_grouped<5>(g, gemm_blocks, stream);
+        case 6: return run_grouped<6>(g, gemm_blocks, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,

@@ -1,0 +1,529 @@
+// Continuous-batching server of SP2 solves.
+//
+// Requests (H on the host, any size) are queued by sp2_server_submit.  A
+// scheduler thread admits them into device "slots" whenever a slot is free
+// and the request's footprint fits in the device arena (one allocation of
+// hbm_budget_bytes made at creation, carved by a first-fit allocator), runs
+// the per-system start kernels (bounds, X_0, first branch), and then advances
+// every active system by one SP2 product per tick with three grouped launches
+// (encode, product, control) that cover all tiles of all active systems.  The
+// three launches are captured once in a hipGraph and replayed every tick;
+// only the device-side work description changes between ticks.  After each
+// tick the control states are read back; finished systems are retired (D and
+// charges copied to the request's pinned host buffers, arena space freed) and
+// waiting requests are admitted in their place, so new work joins systems
+// that are mid-solve.  Each request's result depends only on its own H
+// (tiling, reductions and branch decisions are per system), so it is the same
+// alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/sp2qmd.h"
+#include "sp2_internal.h"
+#include "split_internal.h"
+
+using namespace sp2;
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// First-fit allocator over one device allocation (offsets, 256-byte aligned).
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    void init(char* b, size_t n) {
+        base = b;
+        size = n;
+        free_.clear();
+        free_[0] = n;
+    }
+    bool alloc(size_t n, size_t* off) {
+        n = align_up(n, 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, o = it->first + n;
+                free_.erase(it);
+                if (rest) free_[o] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = align_up(n, 256);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+// Device footprint of one request and its layout inside its arena block.
+struct Layout {
+    size_t H, X, digits, scale, part, D, q, total;
+};
+Layout layout_for(int N, int slices) {
+    const size_t ld = align_up((size_t)N, kTile);
+    const size_t nt = ld / kTile;
+    Layout L;
+    size_t o = 0;
+    L.H = o;      o = align_up(o + (size_t)N * N * 8, 256);
+    L.X = o;      o = align_up(o + 2 * ld * ld * 8, 256);
+    L.digits = o; o = align_up(o + (size_t)slices * ld * ld, 256);
+    L.scale = o;  o = align_up(o + ld * 8, 256);
+    L.part = o;   o = align_up(o + std::max<size_t>(nt * (nt + 1) / 2, ld / 4) * 3 * 8, 256);
+    L.D = o;      o = align_up(o + (size_t)N * N * 8, 256);
+    L.q = o;      o = align_up(o + (size_t)(N / 4 + 1) * 8, 256);
+    L.total = o;
+    return L;
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    int N = 0, n_occ = 0;
+    double* H = nullptr;   // pinned host
+    double* D = nullptr;   // pinned host (result)
+    double* q = nullptr;   // pinned host (result)
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int status = 0;        // sp2_status of the solve
+    bool done = false;
+    size_t off = 0;        // arena block
+    Layout L{};
+    int slot = -1;
+    sp2_stats stats{};
+};
+
+}  // namespace
+
+struct sp2_server {
+    sp2_ctx* ctx = nullptr;
+    int device = 0;
+    sp2_server_options opt{};
+    hipStream_t stream = nullptr;
+    char* arena_mem = nullptr;
+    Arena arena;
+    GroupDesc* g_dev = nullptr;
+    GroupDesc* g_host = nullptr;   // pinned
+    State* st_dev = nullptr;       // kMaxGroup control states
+    State* st_host = nullptr;      // pinned
+    hipGraphExec_t graph = nullptr;
+    std::vector<Request*> slots;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::map<uint64_t, Request*> reqs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::string err;
+    // statistics
+    std::vector<double> lat_ms;
+    double first_submit = -1, last_done = -1;
+    long completed = 0, ticks = 0;
+    double busy_s = 0;
+
+    void loop();
+    bool admit_locked(std::vector<Request*>& fresh);
+    sp2_status start_system(Request* r);
+    sp2_status retire(std::vector<Request*>& finished);
+    void build_group();
+};
+
+static bool fits_int8(int N) { return N >= 2 && N <= 65536; }
+
+void sp2_server::build_group() {
+    GroupDesc& g = *g_host;
+    int n = 0, toff = 0, roff = 0;
+    for (int s = 0; s < (int)slots.size(); ++s) {
+        Request* r = slots[s];
+        if (!r) continue;
+        const int ld = (int)align_up((size_t)r->N, kTile);
+        const int nt = ld / kTile;
+        char* b = arena.base + r->off;
+        SysView& v = g.sys[n];
+        v.buf0 = reinterpret_cast<double*>(b + r->L.X);
+        v.buf1 = v.buf0 + (size_t)ld * ld;
+        v.digits = reinterpret_cast<int8_t*>(b + r->L.digits);
+        v.scale = reinterpret_cast<double*>(b + r->L.scale);
+        v.part = reinterpret_cast<double*>(b + r->L.part);
+        v.st = st_dev + s;
+        v.ld = ld;
+        v.ctrl.n_occ = (double)r->n_occ;
+        v.ctrl.idem_tol = opt.idem_tol;
+        v.ctrl.stall_tol = 1e-2;
+        v.ctrl.max_iter = opt.max_iter;
+        v.ctrl.fp64_head = 0;
+        v.ctrl.fp32_tail = 0;
+        v.ctrl.mixed = 1;
+        v.ctrl.total_blocks = 0.0;
+        g.tile_off[n] = toff;
+        g.row_off[n] = roff;
+        toff += nt * (nt + 1) / 2;
+        roff += ld / 4;
+        ++n;
+    }
+    g.tile_off[n] = toff;
+    g.row_off[n] = roff;
+    g.nsys = n;
+    g.total_tiles = toff;
+    g.total_rowq = roff;
+}
+
+bool sp2_server::admit_locked(std::vector<Request*>& fresh) {
+    bool any = false;
+    while (!queue.empty()) {
+        int free_slot = -1;
+        for (int s = 0; s < (int)slots.size(); ++s)
+            if (!slots[s]) { free_slot = s; break; }
+        if (free_slot < 0) break;
+        Request* r = queue.front();
+        size_t off = 0;
+        if (!arena.alloc(r->L.total, &off)) break;   // wait for memory to free up (FIFO)
+        queue.pop_front();
+        r->off = off;
+        r->slot = free_slot;
+        r->t_admit = now_s();
+        slots[free_slot] = r;
+        fresh.push_back(r);
+        any = true;
+    }
+    return any;
+}
+
+// Upload H and run the per-system start kernels (bounds, X_0, first branch).
+sp2_status sp2_server::start_system(Request* r) {
+    const int N = r->N;
+    const int ld = (int)align_up((size_t)N, kTile);
+    char* b = arena.base + r->off;
+    double* H = reinterpret_cast<double*>(b + r->L.H);
+    double* X0 = reinterpret_cast<double*>(b + r->L.X);
+    double* part = reinterpret_cast<double*>(b + r->L.part);
+    State* st = st_dev + r->slot;
+    if (hipMemcpyAsync(H, r->H, (size_t)N * N * 8, hipMemcpyHostToDevice, stream) != hipSuccess) return SP2_EDEVICE;
+    CtrlArgs a{};
+    a.n_occ = (double)r->n_occ;
+    a.idem_tol = opt.idem_tol;
+    a.stall_tol = 1e-2;
+    a.max_iter = opt.max_iter;
+    a.fp64_head = 0;
+    a.mixed = 1;
+    int ns = 0;
+    if (launch_gershgorin(H, N, part, &ns, stream) != hipSuccess) return SP2_EDEVICE;
+    if (launch_bounds(part, ns, st, stream) != hipSuccess) return SP2_EDEVICE;
+    if (launch_init(H, N, ld, X0, st, part, &ns, stream) != hipSuccess) return SP2_EDEVICE;
+    if (launch_ctrl_init(part, ns, st, a, stream) != hipSuccess) return SP2_EDEVICE;
+    return SP2_OK;
+}
+
+sp2_status sp2_server::retire(std::vector<Request*>& finished) {
+    for (Request* r : finished) {
+        const int N = r->N;
+        const int ld = (int)align_up((size_t)N, kTile);
+        char* b = arena.base + r->off;
+        double* X0 = reinterpret_cast<double*>(b + r->L.X);
+        double* D = reinterpret_cast<double*>(b + r->L.D);
+        double* q = reinterpret_cast<double*>(b + r->L.q);
+        const State& h = st_host[r->slot];
+        if (h.done != 3) {
+            if (launch_finalize(X0, X0 + (size_t)ld * ld, ld, N, D, st_dev + r->slot, stream) != hipSuccess)
+                return SP2_EDEVICE;
+            if (N % 4 == 0 && launch_mulliken(D, N / 4, 4.0, q, stream) != hipSuccess) return SP2_EDEVICE;
+            if (hipMemcpyAsync(r->D, D, (size_t)N * N * 8, hipMemcpyDeviceToHost, stream) != hipSuccess)
+                return SP2_EDEVICE;
+            if (N % 4 == 0 &&
+                hipMemcpyAsync(r->q, q, (size_t)(N / 4) * 8, hipMemcpyDeviceToHost, stream) != hipSuccess)
+                return SP2_EDEVICE;
+        }
+        sp2_stats& s = r->stats;
+        std::memset(&s, 0, sizeof(s));
+        s.iterations = h.iter;
+        s.status = h.done == 1 ? 0 : (h.done == 2 ? 1 : 2);
+        s.fp64_products = h.fp64_products;
+        s.head_switch = h.head_switch;
+        s.eps_min = h.eps_min;
+        s.eps_max = h.eps_max;
+        s.idem_err = h.iter > 0 ? h.idem[h.iter - 1] : 0.0;
+        s.trace = h.t1;
+        s.branch_bits[0] = h.bits[0];
+        s.branch_bits[1] = h.bits[1];
+        for (int k = 0; k < kMaxIter && k < 128; ++k) s.idem_hist[k] = (float)h.idem[k];
+        r->status = h.done == 3 ? SP2_ENOCONV : SP2_OK;
+    }
+    if (!finished.empty() && hipStreamSynchronize(stream) != hipSuccess) return SP2_EDEVICE;
+    const double t = now_s();
+    std::lock_guard<std::mutex> lk(mu);
+    for (Request* r : finished) {
+        arena.release(r->off, r->L.total);
+        slots[r->slot] = nullptr;
+        r->t_done = t;
+        r->stats.ms = (t - r->t_submit) * 1e3;
+        r->done = true;
+        lat_ms.push_back((t - r->t_submit) * 1e3);
+        last_done = t;
+        ++completed;
+    }
+    cv_done.notify_all();
+    return SP2_OK;
+}
+
+void sp2_server::loop() {
+    (void)hipSetDevice(device);
+    bool group_dirty = true;
+    for (;;) {
+        std::vector<Request*> fresh;
+        int active = 0;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (;;) {
+                admit_locked(fresh);
+                active = 0;
+                for (Request* r : slots) active += r != nullptr;
+                if (stop || active > 0) break;
+                cv_work.wait_for(lk, std::chrono::milliseconds(50));
+            }
+            if (stop && active == 0) return;
+        }
+        const double t0 = now_s();
+        sp2_status rc = SP2_OK;
+        for (Request* r : fresh) {
+            rc = start_system(r);
+            if (rc != SP2_OK) break;
+        }
+        if (!fresh.empty()) group_dirty = true;
+        if (rc == SP2_OK && group_dirty) {
+            build_group();
+            if (hipMemcpyAsync(g_dev, g_host, sizeof(GroupDesc), hipMemcpyHostToDevice, stream) != hipSuccess)
+                rc = SP2_EDEVICE;
+            group_dirty = false;
+        }
+        if (rc == SP2_OK && hipGraphLaunch(graph, stream) != hipSuccess) rc = SP2_EDEVICE;
+        if (rc == SP2_OK &&
+            hipMemcpyAsync(st_host, st_dev, sizeof(State) * slots.size(), hipMemcpyDeviceToHost, stream) != hipSuccess)
+            rc = SP2_EDEVICE;
+        if (rc == SP2_OK && hipStreamSynchronize(stream) != hipSuccess) rc = SP2_EDEVICE;
+        std::vector<Request*> finished;
+        for (Request* r : slots)
+            if (r && (rc != SP2_OK || st_host[r->slot].done)) finished.push_back(r);
+        if (rc != SP2_OK) {
+            std::lock_guard<std::mutex> lk(mu);
+            err = "device error in the serving loop";
+            for (Request* r : finished) r->status = rc;
+        }
+        if (!finished.empty()) {
+            if (retire(finished) != SP2_OK) {
+                std::lock_guard<std::mutex> lk(mu);
+                err = "device error while retiring requests";
+            }
+            group_dirty = true;
+        }
+        ++ticks;
+        busy_s += now_s() - t0;
+    }
+}
+
+extern "C" {
+
+void sp2_server_options_default(sp2_server_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->hbm_budget_bytes = (uint64_t)8 << 30;
+    o->max_slots = 32;
+    o->slices = 5;
+    o->max_iter = 100;
+    o->idem_tol = 1e-10;
+    o->iters_per_tick = 1;
+}
+
+sp2_status sp2_server_create(sp2_ctx* ctx, const sp2_server_options* opt, sp2_server** out) {
+    if (!ctx || !out) return SP2_EINVAL;
+    *out = nullptr;
+    sp2_server_options o;
+    if (opt) o = *opt;
+    else sp2_server_options_default(&o);
+    if (o.max_slots < 1 || o.max_slots > kMaxGroup || o.slices < 2 || o.slices > kMaxSlices ||
+        o.hbm_budget_bytes < ((uint64_t)1 << 20) || o.max_iter < 1 || o.max_iter > kMaxIter ||
+        !(o.idem_tol > 0) || o.iters_per_tick < 1 || o.iters_per_tick > 16)
+        return SP2_EINVAL;
+    const int dev = sp2_ctx_device_of(ctx);
+    if (hipSetDevice(dev) != hipSuccess) return SP2_EDEVICE;
+    sp2_server* s = new sp2_server();
+    s->ctx = ctx;
+    s->device = dev;
+    s->opt = o;
+    s->slots.assign(o.max_slots, nullptr);
+    bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->arena_mem, o.hbm_budget_bytes) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->g_dev, sizeof(GroupDesc)) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&s->g_host, sizeof(GroupDesc), hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->st_dev, sizeof(State) * kMaxGroup) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&s->st_host, sizeof(State) * kMaxGroup, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        sp2_server_destroy(s);
+        return SP2_ENOMEM;
+    }
+    s->arena.init(s->arena_mem, o.hbm_budget_bytes);
+    std::memset(s->g_host, 0, sizeof(GroupDesc));
+    // capture one tick: iters_per_tick x (grouped encode, product, control)
+    ok = hipMemcpy(s->g_dev, s->g_host, sizeof(GroupDesc), hipMemcpyHostToDevice) == hipSuccess;
+    // make the lazily set kernel attributes happen outside the capture
+    ok = ok && launch_int8x_grouped(o.slices, s->g_dev, 256, s->stream) == hipSuccess;
+    ok = ok && launch_ctrl_step_grouped(s->g_dev, s->stream) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+    hipGraph_t g = nullptr;
+    ok = ok && hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        for (int k = 0; k < o.iters_per_tick && ok; ++k) {
+            ok = launch_int8x_grouped(o.slices, s->g_dev, 256, s->stream) == hipSuccess;
+            ok = ok && launch_ctrl_step_grouped(s->g_dev, s->stream) == hipSuccess;
+        }
+        ok = (hipStreamEndCapture(s->stream, &g) == hipSuccess) && ok;
+    }
+    ok = ok && hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        sp2_server_destroy(s);
+        return SP2_EDEVICE;
+    }
+    s->worker = std::thread([s] { s->loop(); });
+    *out = s;
+    return SP2_OK;
+}
+
+sp2_status sp2_server_submit(sp2_server* s, int N, const double* H_host, int n_occ, uint64_t* ticket) {
+    if (!s || !H_host || !ticket) return SP2_EINVAL;
+    if (!fits_int8(N) || n_occ <= 0 || n_occ >= N) return SP2_EINVAL;
+    const double t_call = now_s();
+    Layout L = layout_for(N, s->opt.slices);
+    if (L.total > s->opt.hbm_budget_bytes) return SP2_EBUDGET;
+    Request* r = new Request();
+    r->N = N;
+    r->n_occ = n_occ;
+    r->L = L;
+    bool ok = hipHostMalloc((void**)&r->H, (size_t)N * N * 8, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&r->D, (size_t)N * N * 8, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&r->q, (size_t)(N / 4 + 1) * 8, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        if (r->H) (void)hipHostFree(r->H);
+        if (r->D) (void)hipHostFree(r->D);
+        if (r->q) (void)hipHostFree(r->q);
+        delete r;
+        return SP2_ENOMEM;
+    }
+    std::memcpy(r->H, H_host, (size_t)N * N * 8);
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->ticket = s->next_ticket++;
+    r->t_submit = t_call;
+    if (s->first_submit < 0) s->first_submit = r->t_submit;
+    s->reqs[r->ticket] = r;
+    s->queue.push_back(r);
+    *ticket = r->ticket;
+    s->cv_work.notify_one();
+    return SP2_OK;
+}
+
+sp2_status sp2_server_wait(sp2_server* s, uint64_t ticket, double timeout_s, double* D_out, double* q_out,
+                           sp2_stats* stats) {
+    if (!s) return SP2_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return SP2_EINVAL;
+    Request* r = it->second;
+    const auto pred = [r] { return r->done; };
+    if (timeout_s < 0) s->cv_done.wait(lk, pred);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return SP2_ETIMEOUT;
+    if (stats) *stats = r->stats;
+    const int status = r->status;
+    if (status == SP2_OK) {
+        if (D_out) std::memcpy(D_out, r->D, (size_t)r->N * r->N * 8);
+        if (q_out && r->N % 4 == 0) std::memcpy(q_out, r->q, (size_t)(r->N / 4) * 8);
+    }
+    s->reqs.erase(it);
+    lk.unlock();
+    (void)hipHostFree(r->H);
+    (void)hipHostFree(r->D);
+    (void)hipHostFree(r->q);
+    delete r;
+    return (sp2_status)status;
+}
+
+sp2_status sp2_server_report(sp2_server* s, double* p50_ms, double* p99_ms, double* solves_per_s) {
+    if (!s) return SP2_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<double> v = s->lat_ms;
+    if (v.empty()) {
+        if (p50_ms) *p50_ms = 0;
+        if (p99_ms) *p99_ms = 0;
+        if (solves_per_s) *solves_per_s = 0;
+        return SP2_OK;
+    }
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+        const double idx = p * (v.size() - 1);
+        const size_t lo = (size_t)idx, hi = std::min(lo + 1, v.size() - 1);
+        return v[lo] + (idx - lo) * (v[hi] - v[lo]);
+    };
+    if (p50_ms) *p50_ms = pct(0.50);
+    if (p99_ms) *p99_ms = pct(0.99);
+    if (solves_per_s) {
+        const double span = s->last_done - s->first_submit;
+        *solves_per_s = span > 0 ? s->completed / span : 0.0;
+    }
+    return SP2_OK;
+}
+
+void sp2_server_destroy(sp2_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->queue.clear();
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (auto& kv : s->reqs) {
+        Request* r = kv.second;
+        if (r->H) (void)hipHostFree(r->H);
+        if (r->D) (void)hipHostFree(r->D);
+        if (r->q) (void)hipHostFree(r->q);
+        delete r;
+    }
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    if (s->arena_mem) (void)hipFree(s->arena_mem);
+    if (s->g_dev) (void)hipFree(s->g_dev);
+    if (s->g_host) (void)hipHostFree(s->g_host);
+    if (s->st_dev) (void)hipFree(s->st_dev);
+    if (s->st_host) (void)hipHostFree(s->st_host);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+}  // extern "C"

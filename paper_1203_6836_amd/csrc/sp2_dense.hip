@@ -200,8 +200,8 @@ __global__ __launch_bounds__(256) void k_ctrl_init(const double* __restrict__ pa
 // n >= 4, e_n >= e_{n-2}, e_n < stall_tol (stalled at the rounding floor,
 // D = X_n); n + 1 == max_iter (not converged).  Otherwise X_{n+1} becomes
 // current and the next branch is chosen from its traces.
-__global__ __launch_bounds__(256) void k_ctrl_step(const double* __restrict__ part, int nslots,
-                                                   State* __restrict__ st, CtrlArgs a) {
+__device__ void ctrl_step_body(const double* __restrict__ part, int nslots, State* __restrict__ st,
+                               const CtrlArgs& a) {
     if (st->done) return;
     double r[3];
     reduce3(part, nslots, r);
@@ -250,6 +250,19 @@ __global__ __launch_bounds__(256) void k_ctrl_step(const double* __restrict__ pa
         st->phase = 1;
         st->head_switch = n + 1;
     }
+}
+
+__global__ __launch_bounds__(256) void k_ctrl_step(const double* __restrict__ part, int nslots,
+                                                   State* __restrict__ st, CtrlArgs a) {
+    ctrl_step_body(part, nslots, st, a);
+}
+
+// One workgroup per system of a grouped launch.
+__global__ __launch_bounds__(256) void k_ctrl_step_grouped(const GroupDesc* __restrict__ g) {
+    const int s = blockIdx.x;
+    if (s >= g->nsys) return;
+    const SysView& v = g->sys[s];
+    ctrl_step_body(v.part, g->tile_off[s + 1] - g->tile_off[s], v.st, v.ctrl);
 }
 
 // ------------------------------------------------- FP64 symmetric product
@@ -463,6 +476,10 @@ hipError_t launch_ctrl_init(const double* part, int nslots, State* st, CtrlArgs 
 }
 hipError_t launch_ctrl_step(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s) {
     hipLaunchKernelGGL(k_ctrl_step, dim3(1), dim3(256), 0, s, part, nslots, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctrl_step_grouped, dim3(kMaxGroup), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,

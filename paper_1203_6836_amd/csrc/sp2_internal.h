@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct sp2_ctx;
+int sp2_ctx_device_of(const sp2_ctx* c);   // defined with the context
+
 namespace sp2 {
 
 constexpr int kMaxIter = 128;      // products per solve (idempotency history)
@@ -40,6 +43,49 @@ struct CtrlArgs {
     int mixed;       // 0: FP64 only, 1: INT8X, 2: BF16X2
     double total_blocks;  // block threshold: number of 32 x 32 blocks of N x N (0: off)
 };
+
+// ---- grouped (multi-system) launches used by the serving loop ----
+constexpr int kMaxGroup = 64;
+
+// One system of a grouped launch: its padded X buffers, int8 digit planes,
+// row scales, partial slots, control state and control arguments.
+struct SysView {
+    double* buf0;
+    double* buf1;
+    int8_t* digits;
+    double* scale;
+    double* part;
+    State* st;
+    int ld;
+    int pad_;
+    CtrlArgs ctrl;
+};
+
+// Work description of a grouped launch (device resident, rewritten by the
+// host between ticks).  tile_off / row_off are prefix sums of each system's
+// upper-triangular 128 x 128 tiles and of its encode work items (ld / 4).
+struct GroupDesc {
+    int nsys;
+    int total_tiles;
+    int total_rowq;
+    int pad_;
+    int tile_off[kMaxGroup + 1];
+    int row_off[kMaxGroup + 1];
+    SysView sys[kMaxGroup];
+};
+
+#ifdef __HIPCC__
+// Index s with off[s] <= item < off[s + 1] (off non-decreasing, n entries + 1).
+__device__ __forceinline__ int group_find(const int* off, int n, int item) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+#endif
 
 // Number of upper-triangular tile pairs (bi <= bj) of an nt x nt tile grid.
 inline int tri_tiles(int nt) { return nt * (nt + 1) / 2; }
@@ -96,6 +142,7 @@ hipError_t launch_init(const double* H, int N, int ld, double* X0, State* st, do
                        int* nslots, hipStream_t s);
 hipError_t launch_ctrl_init(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);
 hipError_t launch_ctrl_step(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);
+hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s);
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
                            int* nslots, hipStream_t s);
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
