@@ -47,6 +47,8 @@ struct sp2_ctx {
     double* eatom = nullptr;
     double* qtmp = nullptr;
     size_t natcap = 0;
+    int* env = nullptr;        // per-panel surviving column-block ranges (thresholded X)
+    size_t envcap = 0;
 };
 
 int sp2_ctx_device_of(const sp2_ctx* c) { return c->device; }
@@ -133,7 +135,7 @@ void sp2_ctx_destroy(sp2_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->V, c->eatom, c->qtmp};
+    void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->V, c->eatom, c->qtmp, c->env};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     split_free(c->split);
@@ -155,7 +157,7 @@ sp2_status sp2_ctx_set_profiling(sp2_ctx* c, int on) {
     if (!c) return SP2_EINVAL;
     if (on && c->pev.empty()) {
         if (hipSetDevice(c->device) != hipSuccess) return SP2_EDEVICE;
-        c->pev.resize(4 * kMaxIter, nullptr);
+        c->pev.resize(5 * kMaxIter, nullptr);
         for (hipEvent_t& e : c->pev)
             if (hipEventCreate(&e) != hipSuccess) return SP2_EDEVICE;
     }
@@ -177,8 +179,8 @@ static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
     if (o.fp64_head < 0) return fail(c, SP2_EINVAL, "fp64_head must be >= 0");
     if (o.precision == SP2_PREC_BF16X2 && o.fp32_tail < 0) return fail(c, SP2_EINVAL, "fp32_tail must be >= 0");
     if (!(o.tau >= 0.0)) return fail(c, SP2_EINVAL, "tau must be >= 0");
-    if (o.tau > 0.0 && o.precision != SP2_PREC_FP64)
-        return fail(c, SP2_EINVAL, "block thresholding runs with FP64 products only");
+    if (o.tau > 0.0 && o.precision == SP2_PREC_BF16X2)
+        return fail(c, SP2_EINVAL, "block thresholding runs with FP64 or INT8X products");
     (void)N;
     return SP2_OK;
 }
@@ -218,13 +220,20 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     const double nb = (double)((N + 31) / 32);
     a.total_blocks = o.tau > 0.0 ? nb * nb : 0.0;
 
+    int* env = nullptr;
+    if (o.tau > 0.0) {
+        size_t eb = c->envcap;
+        if ((s = grow(c, (void**)&c->env, &eb, (size_t)nt * 2 * sizeof(int))) != SP2_OK) return s;
+        c->envcap = eb;
+        env = c->env;
+    }
     hipStream_t st = c->stream;
     HIPCHK(c, hipEventRecord(c->ev0, st));
     int ns = 0;
     HIPCHK(c, launch_gershgorin(H, N, c->part, &ns, st));
     HIPCHK(c, launch_bounds(c->part, ns, c->st, st));
     HIPCHK(c, launch_init(H, N, ld, buf0, c->st, c->part, &ns, st));
-    if (o.tau > 0.0) HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 1, st));
+    if (o.tau > 0.0) HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 1, st, env));
     HIPCHK(c, launch_ctrl_init(c->part, ns, c->st, a, st));
 
     int launched = 0;
@@ -233,17 +242,17 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
         const int chunk = std::min(launched == 0 ? 24 : 8, o.max_iter - launched);
         for (int k = 0; k < chunk; ++k) {
             const int g = launched + k;
-            hipEvent_t* pe = c->profile ? &c->pev[4 * g] : nullptr;
+            hipEvent_t* pe = c->profile ? &c->pev[5 * g] : nullptr;
             if (pe) HIPCHK(c, hipEventRecord(pe[0], st));
-            if ((int8x || bf16x) && o.tau <= 0.0) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
+            if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
-            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st));
+            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
-            if (o.tau > 0.0)
-                HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 0, st));
-            else if (int8x || bf16x)
-                HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st));
+            if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
+            if (o.tau > 0.0)
+                HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 0, st, env));
+            if (pe) HIPCHK(c, hipEventRecord(pe[4], st));
             HIPCHK(c, launch_ctrl_step(c->part, ns, c->st, a, st));
         }
         launched += chunk;
@@ -282,14 +291,15 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
         }
         if (c->profile) {
             for (int g = 0; g < h.iter; ++g) {
-                float t01 = 0.f, t12 = 0.f, t23 = 0.f;
-                HIPCHK(c, hipEventElapsedTime(&t01, c->pev[4 * g], c->pev[4 * g + 1]));
-                HIPCHK(c, hipEventElapsedTime(&t12, c->pev[4 * g + 1], c->pev[4 * g + 2]));
-                HIPCHK(c, hipEventElapsedTime(&t23, c->pev[4 * g + 2], c->pev[4 * g + 3]));
+                float t01 = 0.f, t12 = 0.f, t23 = 0.f, t34 = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&t01, c->pev[5 * g], c->pev[5 * g + 1]));
+                HIPCHK(c, hipEventElapsedTime(&t12, c->pev[5 * g + 1], c->pev[5 * g + 2]));
+                HIPCHK(c, hipEventElapsedTime(&t23, c->pev[5 * g + 2], c->pev[5 * g + 3]));
+                HIPCHK(c, hipEventElapsedTime(&t34, c->pev[5 * g + 3], c->pev[5 * g + 4]));
+                stats->post_ms += t34;
                 if (g < h.fp64_products) {
                     stats->prod_ms[0] += t12;
                     stats->prod_count[0] += 1;
-                    stats->post_ms += t23;
                 } else {
                     stats->encode_ms += t01;
                     stats->prod_ms[1] += t23;

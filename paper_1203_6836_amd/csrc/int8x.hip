@@ -128,7 +128,7 @@ template <int S>
 __device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1, int ld,
                            const State* __restrict__ st, const int8_t* __restrict__ digits,
                            const double* __restrict__ scale, double* __restrict__ part, int bi, int bj,
-                           I8Smem<S>& sm) {
+                           I8Smem<S>& sm, const int* __restrict__ env) {
     const int nt = ld / QB;
     const int t = tri_index(bi, bj, nt);
     const int i0 = bi * QB, j0 = bj * QB;
@@ -176,12 +176,19 @@ __device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1,
     // fragment address inside a block: row lane % 32, k-half lane / 32
     const int fr = lane & 31;
     const int foff = fr * 32 + 16 * ((lane >> 5) ^ dswz(fr));
-    const int nk = ld / QK;
-    gload(0);
-    sstore(0);
+    // K range: all of it, or the overlap of the two panels' surviving column
+    // blocks of a thresholded X (one 32-byte stage per 32-column block)
+    int ks = 0, nk = ld / QK;
+    if (env) {
+        const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
+        ks = lo;
+        nk = lo > hi ? lo : hi + 1;
+    }
+    if (ks < nk) gload(ks);
+    if (ks < nk) sstore(0);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int stg = kt & 1;
+    for (int kt = ks; kt < nk; ++kt) {
+        const int stg = (kt - ks) & 1;
         if (kt + 1 < nk) gload(kt + 1);
         v4i a[S];
 #pragma unroll
@@ -255,13 +262,13 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
                                                     int ld, const State* __restrict__ st,
                                                     const int8_t* __restrict__ digits,
                                                     const double* __restrict__ scale,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, const int* __restrict__ env) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
     int bi, bj;
     tile_of_block(blockIdx.x, ld / QB, bi, bj);
-    int8x_tile<S>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm);
+    int8x_tile<S>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env);
 }
 
 // Grouped: every upper-triangular tile of every system in the group; a fixed
@@ -278,14 +285,14 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __r
         int bi = 0, bj = 0, tl = item - g->tile_off[s], nt = v.ld / QB, off = 0;
         while (tl >= off + (nt - bi)) { off += nt - bi; ++bi; }
         bj = bi + (tl - off);
-        int8x_tile<S>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm);
+        int8x_tile<S>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr);
         __syncthreads();
     }
 }
 
 template <int S>
 static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
-                            hipStream_t stream) {
+                            hipStream_t stream, const int* env) {
     const int nt = ld / QB;
     const int T = nt * (nt + 1) / 2;
     const size_t lds = sizeof(I8Smem<S>);
@@ -297,7 +304,7 @@ static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld,
         attr_set = true;
     }
     hipLaunchKernelGGL(k_gemm_int8x<S>, dim3(T), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
-                       s.scale, part);
+                       s.scale, part, env);
     return hipGetLastError();
 }
 
@@ -348,15 +355,15 @@ hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double
 }
 
 hipError_t launch_int8x_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
-                             int* nslots, hipStream_t stream) {
+                             int* nslots, hipStream_t stream, const int* env) {
     const int nt = ld / QB;
     *nslots = nt * (nt + 1) / 2;
     switch (s.slices) {
-        case 2: return run_int8x<2>(s, buf0, buf1, ld, st, part, stream);
-        case 3: return run_int8x<3>(s, buf0, buf1, ld, st, part, stream);
-        case 4: return run_int8x<4>(s, buf0, buf1, ld, st, part, stream);
-        case 5: return run_int8x<5>(s, buf0, buf1, ld, st, part, stream);
-        case 6: return run_int8x<6>(s, buf0, buf1, ld, st, part, stream);
+        case 2: return run_int8x<2>(s, buf0, buf1, ld, st, part, stream, env);
+        case 3: return run_int8x<3>(s, buf0, buf1, ld, st, part, stream, env);
+        case 4: return run_int8x<4>(s, buf0, buf1, ld, st, part, stream, env);
+        case 5: return run_int8x<5>(s, buf0, buf1, ld, st, part, stream, env);
+        case 6: return run_int8x<6>(s, buf0, buf1, ld, st, part, stream, env);
         default: return hipErrorInvalidValue;
     }
 }

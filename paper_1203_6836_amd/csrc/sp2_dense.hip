@@ -298,7 +298,8 @@ __device__ __forceinline__ int xcd_remap(int w, int T) {
 __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
                                                      double* __restrict__ buf1, int ld,
                                                      const State* __restrict__ st,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part,
+                                                     const int* __restrict__ env) {
     if (st->done || st->phase != 0) return;
     const int nt = ld / GB;
     int bi, bj;
@@ -342,29 +343,39 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int nk = ld / GK;
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int stg = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * GK);
-#pragma unroll
-        for (int k4 = 0; k4 < GK / 4; ++k4) {
-            const int kr = k4 * 4 + (lane >> 4);
-            double av[4], bv[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) av[m] = As[stg][kr][wi * 64 + m * 16 + (lane & 15)];
-#pragma unroll
-            for (int n = 0; n < 4; ++n) bv[n] = Bs[stg][kr][wj * 64 + n * 16 + (lane & 15)];
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int n = 0; n < 4; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
-        }
-        if (kt + 1 < nk) sstore(stg ^ 1);
+    // K range: all of it, or (thresholded X) the overlap of the two row panels'
+    // ranges of 32-column blocks that survived the threshold; outside it one
+    // of the two operands is zero.
+    int ks = 0, ke = ld / GK;
+    if (env) {
+        const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
+        ks = lo * 2;                           // 16-wide stages, two per 32-column block
+        ke = lo > hi ? ks : (hi + 1) * 2;
+    }
+    if (ks < ke) {
+        gload(ks * GK);
+        sstore(0);
         __syncthreads();
+        for (int kt = ks; kt < ke; ++kt) {
+            const int stg = (kt - ks) & 1;
+            if (kt + 1 < ke) gload((kt + 1) * GK);
+#pragma unroll
+            for (int k4 = 0; k4 < GK / 4; ++k4) {
+                const int kr = k4 * 4 + (lane >> 4);
+                double av[4], bv[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) av[m] = As[stg][kr][wi * 64 + m * 16 + (lane & 15)];
+#pragma unroll
+                for (int n = 0; n < 4; ++n) bv[n] = Bs[stg][kr][wj * 64 + n * 16 + (lane & 15)];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
+            }
+            if (kt + 1 < ke) sstore(stg ^ 1);
+            __syncthreads();
+        }
     }
 
     // fused SP2 update + partials
@@ -483,11 +494,11 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
-                           int* nslots, hipStream_t s) {
+                           int* nslots, hipStream_t s, const int* env) {
     const int nt = ld / GB;
     const int T = tri_tiles(nt);
     *nslots = T;
-    hipLaunchKernelGGL(k_gemm_f64, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part);
+    hipLaunchKernelGGL(k_gemm_f64, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env);
     return hipGetLastError();
 }
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,

@@ -143,8 +143,10 @@ hipError_t launch_init(const double* H, int N, int ld, double* X0, State* st, do
 hipError_t launch_ctrl_init(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);
 hipError_t launch_ctrl_step(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);
 hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s);
+// env (may be null): per 128-row panel p, [env[2p], env[2p+1]] is the range
+// of 32-column blocks holding nonzeros of a thresholded X.
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
-                           int* nslots, hipStream_t s);
+                           int* nslots, hipStream_t s, const int* env = nullptr);
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
                            const State* st, hipStream_t s);
 hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hipStream_t s);

@@ -24,7 +24,8 @@ __device__ __forceinline__ void tri_coords_t(int t, int nt, int& bi, int& bj) {
 // the idempotency partial of the product is kept (zeroed for X_0).
 __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ buf0, double* __restrict__ buf1,
                                                          int ld, int N, double tau, State* __restrict__ st,
-                                                         double* __restrict__ part, int init) {
+                                                         double* __restrict__ part, int init,
+                                                         int* __restrict__ env) {
     if (st->done) return;
     double* X = init ? buf0 : (st->cur ? buf0 : buf1);
     const int nt = ld / 128;
@@ -36,6 +37,8 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
     const int nb = (N + 31) / 32;
     double tr = 0.0, fro = 0.0;
     int kept = 0;
+    // surviving 32-column blocks of panel bi (columns c0) and, by symmetry, of panel bj (rows r0)
+    int lo_i = 0x7fffffff, hi_i = -1, lo_j = 0x7fffffff, hi_j = -1;
     for (int s = 0; s < 4; ++s) {
         const int b = w * 4 + s, br = b >> 2, bc = b & 3;
         const int r0 = bi * 128 + br * 32, c0 = bj * 128 + bc * 32;
@@ -66,15 +69,23 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
                 }
             }
             if ((r0 >> 5) < nb && (c0 >> 5) < nb) kept += 1;
+            lo_i = min(lo_i, c0 >> 5);
+            hi_i = max(hi_i, c0 >> 5);
+            lo_j = min(lo_j, r0 >> 5);
+            hi_j = max(hi_j, r0 >> 5);
         }
     }
     tr = wsum64(tr);
     __shared__ double s_tr[4], s_fr[4];
-    __shared__ int s_k[4];
+    __shared__ int s_k[4], s_env[4][4];
     if (lane == 0) {
         s_tr[w] = tr;
         s_fr[w] = fro;
         s_k[w] = kept;
+        s_env[w][0] = lo_i;
+        s_env[w][1] = hi_i;
+        s_env[w][2] = lo_j;
+        s_env[w][3] = hi_j;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -84,15 +95,42 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
         if (init) part[3 * t + 2] = 0.0;
         const int k = s_k[0] + s_k[1] + s_k[2] + s_k[3];
         atomicAdd(&st->kept, (unsigned long long)(mirror ? 2 * k : k));
+        if (env) {
+            int e[4] = {s_env[0][0], s_env[0][1], s_env[0][2], s_env[0][3]};
+            for (int q = 1; q < 4; ++q) {
+                e[0] = min(e[0], s_env[q][0]);
+                e[1] = max(e[1], s_env[q][1]);
+                e[2] = min(e[2], s_env[q][2]);
+                e[3] = max(e[3], s_env[q][3]);
+            }
+            if (e[1] >= 0) {
+                atomicMin(&env[2 * bi], e[0]);
+                atomicMax(&env[2 * bi + 1], e[1]);
+                atomicMin(&env[2 * bj], e[2]);
+                atomicMax(&env[2 * bj + 1], e[3]);
+            }
+        }
+    }
+}
+
+// Empty ranges for every panel (before a threshold pass records new ones).
+__global__ void k_env_reset(int* __restrict__ env, int npanel, const State* __restrict__ st) {
+    if (st->done) return;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < npanel) {
+        env[2 * p] = 0x7fffffff;
+        env[2 * p + 1] = -1;
     }
 }
 
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, State* st,
-                                  double* part, int* nslots, int init, hipStream_t stream) {
+                                  double* part, int* nslots, int init, hipStream_t stream, int* env) {
     const int nt = ld / 128;
     const int T = nt * (nt + 1) / 2;
     *nslots = T;
-    hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, st, part, init);
+    if (env) hipLaunchKernelGGL(k_env_reset, dim3((nt + 255) / 256), dim3(256), 0, stream, env, nt, st);
+    hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, st, part, init,
+                       env);
     return hipGetLastError();
 }
 
@@ -141,8 +179,8 @@ hipError_t launch_split_encode(SplitScratch& s, const double* buf0, const double
     return hipErrorNotSupported;
 }
 hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
-                             int* nslots, hipStream_t stream) {
-    if (s.slices > 0) return launch_int8x_gemm(s, buf0, buf1, ld, st, part, nslots, stream);
+                             int* nslots, hipStream_t stream, const int* env) {
+    if (s.slices > 0) return launch_int8x_gemm(s, buf0, buf1, ld, st, part, nslots, stream, env);
     return hipErrorNotSupported;
 }
 

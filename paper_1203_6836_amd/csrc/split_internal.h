@@ -32,18 +32,20 @@ hipError_t launch_split_encode(SplitScratch& s, const double* buf0, const double
                                hipStream_t stream);
 // Reduced-precision product with the fused SP2 update (no-op in FP64 phase).
 hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
-                             int* nslots, hipStream_t stream);
+                             int* nslots, hipStream_t stream, const int* env = nullptr);
 // Zero every 32 x 32 block of the freshly written X (X_0 when init != 0,
 // else X_{n+1}) whose Frobenius norm is below tau; rewrite the trace and
 // norm partials of the 128 x 128 tiles (keeping the idempotency partial).
+// With env non-null, also records each panel's range of surviving 32-column
+// blocks (reset first), for the products' K ranges.
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, State* st,
-                                  double* part, int* nslots, int init, hipStream_t stream);
+                                  double* part, int* nslots, int init, hipStream_t stream, int* env = nullptr);
 
 // int8 digit-plane product (int8x.hip)
 hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
                                hipStream_t stream);
 hipError_t launch_int8x_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
-                             int* nslots, hipStream_t stream);
+                             int* nslots, hipStream_t stream, const int* env = nullptr);
 
 // Grouped encode + product over every system of g (fixed grids: 1024 encode
 // workgroups, gemm_blocks product workgroups), for the serving loop.
