@@ -96,6 +96,8 @@ void sp2_options_default(sp2_options *opt);
  * enqueue on (NULL: the null stream).  Library scratch (padded X buffers,
  * partial sums, control state) is owned by the context and grows on demand. */
 sp2_status sp2_ctx_create(sp2_ctx **out, int device, void *hip_stream);
+/* Destroy a context; every xlbomd and sp2_server made on it must be
+ * destroyed first. */
 void sp2_ctx_destroy(sp2_ctx *ctx);
 sp2_status sp2_ctx_set_stream(sp2_ctx *ctx, void *hip_stream);
 /* on != 0: bracket every product kernel with HIP events on the context's
@@ -170,6 +172,10 @@ typedef struct {
     int K;            /* dissipation order, history length K + 1 (<= 8)        */
     double c[9];      /* c_0 .. c_K                                            */
     sp2_options sp2;  /* density-matrix options for the one solve per step     */
+    double scf_beta;  /* SCF start: linear mixing n += beta (q - n) ...         */
+    double scf_tol;   /* ... until max_i |q_i - n_i| < scf_tol ...              */
+    int scf_max_iter; /* ... or SP2_ENOCONV after this many density matrices;
+                         0: no SCF, n0 is used as given                        */
 } xlbomd_options;
 
 typedef struct {
@@ -182,11 +188,16 @@ typedef struct xlbomd xlbomd;
 
 /* Create an XL-BOMD integrator (General remarks subsection: velocity Verlet
  * for the nuclei, Eq. Verl_n for the auxiliary charges, one density matrix
- * per step, no SCF).  xyz, vel (A, A/fs) and n0 are HOST arrays copied in;
- * n0 is used for the whole initial history (n = q from a converged start). */
+ * per step, no SCF during the run).  xyz, vel (A, A/fs) and n0 are HOST
+ * arrays copied in.  Start (General remarks): with scf_max_iter > 0 the
+ * charges are first converged self-consistently on the GPU from the guess n0
+ * (zeros when n0_host is NULL) and n = q is set for the whole history; with
+ * scf_max_iter == 0, n0_host (required) is the history as given. */
 sp2_status xlbomd_create(sp2_ctx *ctx, const tb_params *p, const xlbomd_options *o,
                          int n_atoms, const double *xyz_host, const double *vel_host,
                          const double *n0_host, xlbomd **out);
+/* SCF iterations and final residual max|q - n| of the start (0 if n0 given). */
+sp2_status xlbomd_info(const xlbomd *md, int *scf_iterations, double *scf_residual);
 /* Advance n_steps; log (host, n_steps entries) may be NULL. */
 sp2_status xlbomd_run(xlbomd *md, int n_steps, xlbomd_record *log);
 /* Copy current positions, velocities, charges q and n_t to host arrays (any may be NULL). */

@@ -63,7 +63,8 @@ class TBParams(ctypes.Structure):
 class XLOptions(ctypes.Structure):
     _fields_ = [("dt_fs", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("K", ctypes.c_int),
-                ("c", ctypes.c_double * 9), ("sp2", Sp2Options)]
+                ("c", ctypes.c_double * 9), ("sp2", Sp2Options),
+                ("scf_beta", ctypes.c_double), ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int)]
 
 
 class XLRecord(ctypes.Structure):
@@ -100,6 +101,7 @@ _SIGS = {
                            _P, _P, _P, ctypes.POINTER(_P)]),
     "xlbomd_run": (_I, [_P, _I, ctypes.POINTER(XLRecord)]),
     "xlbomd_get": (_I, [_P, _P, _P, _P, _P]),
+    "xlbomd_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
     "xlbomd_destroy": (None, [_P]),
     "sp2_server_options_default": (None, [ctypes.POINTER(ServerOptions)]),
     "sp2_server_create": (_I, [_P, ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
@@ -176,6 +178,9 @@ class Context:
         if st != SP2_OK:
             raise Sp2Error(st, "sp2_ctx_create: " + lib().sp2_strerror(st).decode())
         self.device = device
+        # servers and integrators hold the context: they are closed before it
+        import weakref
+        self._children = weakref.WeakSet()
 
     def _check(self, st, what):
         if st != SP2_OK:
@@ -183,6 +188,8 @@ class Context:
 
     def close(self):
         if self._h:
+            for child in list(getattr(self, "_children", ())):
+                child.close()
             lib().sp2_ctx_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -255,15 +262,21 @@ class Context:
                                     _ptr(n_aux), _ptr(F_out), ctypes.byref(U)), "tb_forces")
         return F_out, U.value
 
-    def xlbomd_create(self, model, xyz, vel, n0, dt_fs=0.25, kappa=0.91, alpha=0.018,
-                      c=(-6.0, 14.0, -8.0, -3.0, 4.0, -1.0), sp2_opts=None):
-        return XLBOMD(self, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts)
+    def xlbomd_create(self, model, xyz, vel, n0=None, dt_fs=0.25, kappa=0.91, alpha=0.018,
+                      c=(-6.0, 14.0, -8.0, -3.0, 4.0, -1.0), sp2_opts=None,
+                      scf_beta=0.3, scf_tol=1e-10, scf_max_iter=None):
+        """scf_max_iter None: 0 (use n0 as given) if n0 is given, else 500 (SCF from zeros)."""
+        if scf_max_iter is None:
+            scf_max_iter = 0 if n0 is not None else 500
+        return XLBOMD(self, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,
+                      scf_beta, scf_tol, scf_max_iter)
 
 
 class XLBOMD:
     """Handle of an xlbomd integrator; host numpy arrays in, host numpy arrays out."""
 
-    def __init__(self, ctx, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts):
+    def __init__(self, ctx, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,
+                 scf_beta=0.3, scf_tol=1e-10, scf_max_iter=500):
         self.ctx = ctx
         self.nat = len(xyz)
         o = XLOptions()
@@ -271,15 +284,17 @@ class XLBOMD:
         for k, ck in enumerate(c):
             o.c[k] = ck
         o.sp2 = sp2_opts if sp2_opts is not None else options("fp64")
+        o.scf_beta, o.scf_tol, o.scf_max_iter = scf_beta, scf_tol, scf_max_iter
         p = tb_params(model)
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)
-        n0 = np.ascontiguousarray(n0, dtype=np.float64)
+        n0 = None if n0 is None else np.ascontiguousarray(n0, dtype=np.float64)
         self._h = ctypes.c_void_p()
         st = lib().xlbomd_create(ctx._h, ctypes.byref(p), ctypes.byref(o), self.nat,
                                  xyz.ctypes.data_as(_P), vel.ctypes.data_as(_P),
-                                 n0.ctypes.data_as(_P), ctypes.byref(self._h))
+                                 None if n0 is None else n0.ctypes.data_as(_P), ctypes.byref(self._h))
         ctx._check(st, "xlbomd_create")
+        ctx._children.add(self)
 
     def xlbomd_run(self, n_steps: int):
         recs = (XLRecord * max(n_steps, 1))()
@@ -287,6 +302,11 @@ class XLBOMD:
         return [{"etot": r.etot, "epot": r.epot, "ekin": r.ekin,
                  "max_q_minus_n": r.max_q_minus_n, "sp2_iterations": r.sp2_iterations}
                 for r in recs[:n_steps]]
+
+    def xlbomd_info(self):
+        it, res = ctypes.c_int(), ctypes.c_double()
+        self.ctx._check(lib().xlbomd_info(self._h, ctypes.byref(it), ctypes.byref(res)), "xlbomd_info")
+        return it.value, res.value
 
     def xlbomd_get(self):
         xyz = np.empty((self.nat, 3))
@@ -324,6 +344,7 @@ class Server:
         st = lib().sp2_server_create(ctx._h, ctypes.byref(o), ctypes.byref(self._h))
         if st != SP2_OK:
             raise Sp2Error(st, "sp2_server_create: " + lib().sp2_strerror(st).decode())
+        ctx._children.add(self)
 
     def sp2_server_submit(self, H, n_occ: int) -> int:
         H = np.ascontiguousarray(H, dtype=np.float64)

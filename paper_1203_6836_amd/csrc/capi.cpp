@@ -473,9 +473,11 @@ struct xlbomd {
     int head;
     long step;
     double U;
+    int scf_iterations;
+    double scf_residual;
 };
 
-static sp2_status md_evaluate(xlbomd* m, int* iters) {
+static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true) {
     sp2_ctx* c = m->c;
     const int nat = m->nat, N = 4 * nat;
     const double* n_t = m->hist + (size_t)m->head * nat;
@@ -486,6 +488,7 @@ static sp2_status md_evaluate(xlbomd* m, int* iters) {
     if (s != SP2_OK) return s;
     if (iters) *iters = st.iterations;
     HIPCHK(c, launch_mulliken(m->D, nat, m->p.z_val, m->q, c->stream));
+    if (!with_forces) return SP2_OK;
     return forces_impl(c, &m->p, nat, m->xyz, m->D, m->q, n_t, m->F, m->dscal);
 }
 
@@ -493,8 +496,12 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
                                     const double* xyz_host, const double* vel_host, const double* n0_host,
                                     xlbomd** out) {
     if (!c) return SP2_EINVAL;
-    if (!out || !params_ok(p) || !o || !xyz_host || !vel_host || !n0_host)
+    if (!out || !params_ok(p) || !o || !xyz_host || !vel_host)
         return fail(c, SP2_EINVAL, "bad xlbomd_create arguments");
+    if (o->scf_max_iter < 0 || (o->scf_max_iter == 0 && !n0_host))
+        return fail(c, SP2_EINVAL, "scf_max_iter == 0 needs n0");
+    if (o->scf_max_iter > 0 && (!(o->scf_beta > 0.0 && o->scf_beta <= 1.0) || !(o->scf_tol > 0.0)))
+        return fail(c, SP2_EINVAL, "SCF start needs 0 < scf_beta <= 1 and scf_tol > 0");
     *out = nullptr;
     if (n_atoms < 2 || n_atoms > 16384) return fail(c, SP2_EINVAL, "n_atoms out of range");
     if (o->K < 1 || o->K > 8 || !(o->dt_fs > 0) || !(p->mass > 0)) return fail(c, SP2_EINVAL, "bad xlbomd options");
@@ -523,10 +530,44 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
     hipStream_t st = c->stream;
     HIPCHK(c, hipMemcpyAsync(m->xyz, xyz_host, 3 * n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(m->vel, vel_host, 3 * n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
-    for (int k = 0; k < L; ++k)
-        HIPCHK(c, hipMemcpyAsync(m->hist + (size_t)k * n_atoms, n0_host, n_atoms * sizeof(double),
-                                 hipMemcpyHostToDevice, st));
     m->head = 0;
+    m->scf_iterations = 0;
+    m->scf_residual = 0.0;
+    if (o->scf_max_iter == 0) {
+        for (int k = 0; k < L; ++k)
+            HIPCHK(c, hipMemcpyAsync(m->hist + (size_t)k * n_atoms, n0_host, n_atoms * sizeof(double),
+                                     hipMemcpyHostToDevice, st));
+    } else {
+        // self-consistent start: n <- n + beta (q[n] - n) from the guess n0 (or 0)
+        if (n0_host)
+            HIPCHK(c, hipMemcpyAsync(m->hist, n0_host, n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
+        else
+            HIPCHK(c, hipMemsetAsync(m->hist, 0, n_atoms * sizeof(double), st));
+        bool conv = false;
+        for (int it = 0; it < o->scf_max_iter; ++it) {
+            if ((s = md_evaluate(m, nullptr, false)) != SP2_OK) {
+                xlbomd_destroy(m);
+                return s;
+            }
+            HIPCHK(c, launch_maxdiff(m->q, m->hist, n_atoms, m->dev, m->dscal + 1, st));
+            HIPCHK(c, hipMemcpyAsync(c->scal_host, m->dscal + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            m->scf_iterations = it + 1;
+            m->scf_residual = c->scal_host[0];
+            if (m->scf_residual < o->scf_tol) {
+                conv = true;
+                break;
+            }
+            HIPCHK(c, launch_mix(m->hist, m->q, n_atoms, o->scf_beta, st));
+        }
+        if (!conv) {
+            xlbomd_destroy(m);
+            return fail(c, SP2_ENOCONV, "SCF start did not converge");
+        }
+        for (int k = 0; k < L; ++k)   // n = q for the whole history
+            HIPCHK(c, hipMemcpyAsync(m->hist + (size_t)k * n_atoms, m->q, n_atoms * sizeof(double),
+                                     hipMemcpyDeviceToDevice, st));
+    }
     m->step = 0;
     if ((s = md_evaluate(m, nullptr)) != SP2_OK) {
         xlbomd_destroy(m);
@@ -573,6 +614,13 @@ extern "C" sp2_status xlbomd_run(xlbomd* m, int n_steps, xlbomd_record* log) {
             log[step].sp2_iterations = iters;
         }
     }
+    return SP2_OK;
+}
+
+extern "C" sp2_status xlbomd_info(const xlbomd* m, int* scf_iterations, double* scf_residual) {
+    if (!m) return SP2_EINVAL;
+    if (scf_iterations) *scf_iterations = m->scf_iterations;
+    if (scf_residual) *scf_residual = m->scf_residual;
     return SP2_OK;
 }
 

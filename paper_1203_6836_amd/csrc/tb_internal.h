@@ -34,6 +34,7 @@ hipError_t launch_kick_drift(double* x, double* v, const double* F, int n3, doub
 hipError_t launch_xl_charges(double* hist, int nat, int K, int head, const double* q, const XLArgs& a,
                              hipStream_t s);
 hipError_t launch_maxdiff(const double* a, const double* b, int n, double* tmp, double* out, hipStream_t s);
+hipError_t launch_mix(double* n, const double* q, int nat, double beta, hipStream_t s);
 hipError_t launch_sqsum(const double* v, int n3, double* out, hipStream_t s);
 
 }  // namespace sp2

@@ -246,6 +246,12 @@ __global__ void k_absdiff(const double* __restrict__ a, const double* __restrict
     if (i < n) d[i] = fabs(a[i] - b[i]);
 }
 
+// Linear charge mixing n += beta (q - n).
+__global__ void k_mix(double* __restrict__ n, const double* __restrict__ q, int nat, double beta) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < nat) n[i] += beta * (q[i] - n[i]);
+}
+
 __global__ void k_max(const double* __restrict__ x, int n, double* __restrict__ out) {
     double m = 0.0;
     for (int k = threadIdx.x; k < n; k += 256) m = fmax(m, x[k]);
@@ -297,6 +303,10 @@ hipError_t launch_xl_charges(double* hist, int nat, int K, int head, const doubl
 hipError_t launch_maxdiff(const double* a, const double* b, int n, double* tmp, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_absdiff, dim3((n + 255) / 256), dim3(256), 0, s, a, b, n, tmp);
     hipLaunchKernelGGL(k_max, dim3(1), dim3(256), 0, s, tmp, n, out);
+    return hipGetLastError();
+}
+hipError_t launch_mix(double* n, const double* q, int nat, double beta, hipStream_t s) {
+    hipLaunchKernelGGL(k_mix, dim3((nat + 255) / 256), dim3(256), 0, s, n, q, nat, beta);
     return hipGetLastError();
 }
 hipError_t launch_sqsum(const double* v, int n3, double* out, hipStream_t s) {

@@ -60,9 +60,12 @@ class TBModel:
 
 
 # Static configurations use the literal hard cut-off at 4 A; molecular
-# dynamics uses the smooth tail on [3.5, 4.0] A so the energy is continuous.
+# dynamics uses the smooth tail on [3.5, 4.0] A so the energy is continuous,
+# and a pair repulsion whose force at the lattice spacing (A / rho = 100 eV/A)
+# balances the nearest-neighbour attraction of the +-4 e ions of the
+# charge-ordered ground state of this gamma (16 k_e / 1.5^2 = 102 eV/A).
 STATIC_MODEL = TBModel()
-MD_MODEL = TBModel(r_tail=3.5)
+MD_MODEL = TBModel(r_tail=3.5, pair_a=30.0)
 
 
 def lattice_positions(dims, spacing: float = 1.5, jitter: float = 0.1,
@@ -92,6 +95,18 @@ def maxwell_velocities(n_atoms: int, temperature_k: float, mass_amu: float,
     v = rng.normal(0.0, sigma, size=(n_atoms, 3))
     v -= v.mean(axis=0, keepdims=True)
     return v
+
+
+def checkerboard_charges(dims, amplitude: float = 4.0) -> np.ndarray:
+    """+-amplitude on the two sublattices of the cubic lattice (x fastest order).
+
+    A starting guess for the self-consistent charges: the literal gamma of the
+    model orders the charges this way at self-consistency.
+    """
+    nx, ny, nz = (int(d) for d in dims)
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    parity = ((ix + iy + iz) % 2).ravel()
+    return np.where(parity == 0, amplitude, -amplitude).astype(np.float64)
 
 
 def cube_dims_for(n_atoms: int):
