@@ -297,7 +297,8 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
                 HIPCHK(c, hipEventElapsedTime(&t23, c->pev[5 * g + 2], c->pev[5 * g + 3]));
                 HIPCHK(c, hipEventElapsedTime(&t34, c->pev[5 * g + 3], c->pev[5 * g + 4]));
                 stats->post_ms += t34;
-                if (g < h.fp64_products) {
+                // exactly one of the two product kernels did work in launch g
+                if (t12 >= t23) {
                     stats->prod_ms[0] += t12;
                     stats->prod_count[0] += 1;
                 } else {

@@ -212,9 +212,11 @@ __device__ void ctrl_step_body(const double* __restrict__ part, int nslots, Stat
     const double f = take_fill(st, a);
     if (f >= 0.0) st->fill[n] = (float)f;
     st->iter = n + 1;
-    if (st->phase == 0) st->fp64_products += 1;
+    if (st->phase != 1) st->fp64_products += 1;   // FP64-kernel products (head or FP32 tail)
     const bool stall = n >= 4 && e >= st->idem[n - 2] && e < a.stall_tol;
-    if (e < a.idem_tol || (stall && !(a.mixed == 2 && st->phase == 1))) {
+    // BF16X2 runs its own schedule: a stall of the BF16 stage starts a fixed
+    // FP32 tail instead of stopping
+    if (e < a.idem_tol || (stall && a.mixed != 2)) {
         st->done = (e < a.idem_tol) ? 1 : 2;
         st->result = st->cur;
         clear_bit(st, n);
@@ -225,20 +227,27 @@ __device__ void ctrl_step_body(const double* __restrict__ part, int nslots, Stat
         st->result = 1 - st->cur;
         return;
     }
-    // BF16X2: when the BF16 stage stalls, switch to a fixed number of FP32 products
-    if (a.mixed == 2 && st->phase == 1 && stall) {
-        st->phase = 2;
-        st->tail_left = a.fp32_tail;
-        st->head_switch = n + 1;
-    }
-    if (st->phase == 2) {
+    if (a.mixed == 2 && st->phase == 2) {
+        // tail product: its update X_{n+1} is applied; after fp32_tail of them, stop
+        st->tail_left -= 1;
         if (st->tail_left <= 0) {
+            st->done = 2;
+            st->result = 1 - st->cur;
+            st->t1 = r[0];
+            st->t2 = r[1];
+            return;
+        }
+    }
+    if (a.mixed == 2 && st->phase == 1 && stall) {
+        if (a.fp32_tail <= 0) {
             st->done = 2;
             st->result = st->cur;
             clear_bit(st, n);
             return;
         }
-        st->tail_left -= 1;
+        st->phase = 2;
+        st->tail_left = a.fp32_tail;
+        st->head_switch = n + 1;
     }
     st->cur = 1 - st->cur;
     st->t1 = r[0];
@@ -246,7 +255,7 @@ __device__ void ctrl_step_body(const double* __restrict__ part, int nslots, Stat
     const int b = choose_branch(r[0], r[1], a.n_occ);
     st->branch = b;
     set_bit(st, n + 1, b);
-    if (a.mixed == 1 && st->phase == 0 && n + 1 >= a.fp64_head && a.fp64_head >= 0) {
+    if (a.mixed != 0 && st->phase == 0 && n + 1 >= a.fp64_head && a.fp64_head >= 0) {
         st->phase = 1;
         st->head_switch = n + 1;
     }
@@ -300,7 +309,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
                                                      const State* __restrict__ st,
                                                      double* __restrict__ part,
                                                      const int* __restrict__ env) {
-    if (st->done || st->phase != 0) return;
+    // phase 0: FP64 products; phase 2: the FP32 tail of the BF16 hi+lo mode
+    // (FP32-valued operands, update rounded to FP32)
+    if (st->done || (st->phase != 0 && st->phase != 2)) return;
+    const bool r32 = st->phase == 2;
     const int nt = ld / GB;
     int bi, bj;
     tile_of_block(blockIdx.x, nt, bi, bj);
@@ -393,7 +405,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
                 const int gi = i0 + wi * 64 + m * 16 + (lane >> 4) + 4 * r;
                 const double p = acc[m][n][r];
                 const double x = Xc[(size_t)gi * ld + gj];
-                const double xn = br ? 2.0 * x - p : p;
+                double xn = br ? 2.0 * x - p : p;
+                if (r32) {
+                    const float pf = (float)p, xf = (float)x;
+                    xn = (double)(br ? 2.0f * xf - pf : pf);
+                }
                 Xn[(size_t)gi * ld + gj] = xn;
                 if (mirror) Xn[(size_t)gj * ld + gi] = xn;
                 if (gi == gj) tr += xn;

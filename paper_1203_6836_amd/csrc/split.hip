@@ -176,11 +176,13 @@ size_t split_part_slots(int ld) {
 hipError_t launch_split_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
                                hipStream_t stream) {
     if (s.slices > 0) return launch_int8x_encode(s, buf0, buf1, ld, st, stream);
+    if (s.bf16) return launch_bf16x2_encode(s, buf0, buf1, ld, st, stream);
     return hipErrorNotSupported;
 }
 hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                              int* nslots, hipStream_t stream, const int* env) {
     if (s.slices > 0) return launch_int8x_gemm(s, buf0, buf1, ld, st, part, nslots, stream, env);
+    if (s.bf16) return launch_bf16x2_gemm(s, buf0, buf1, ld, st, part, nslots, stream);
     return hipErrorNotSupported;
 }
 

@@ -47,6 +47,12 @@ hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double
 hipError_t launch_int8x_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                              int* nslots, hipStream_t stream, const int* env = nullptr);
 
+// BF16 hi + lo product (bf16x.hip)
+hipError_t launch_bf16x2_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
+                                hipStream_t stream);
+hipError_t launch_bf16x2_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                              int* nslots, hipStream_t stream);
+
 // Grouped encode + product over every system of g (fixed grids: 1024 encode
 // workgroups, gemm_blocks product workgroups), for the serving loop.
 hipError_t launch_int8x_grouped(int slices, const GroupDesc* g, int gemm_blocks, hipStream_t stream);

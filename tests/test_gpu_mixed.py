@@ -100,3 +100,28 @@ def test_int8x_full_size_against_fp64_path(ctx):
     say(f"  iters {s8['iterations']} vs {s64['iterations']}  ms {s8['ms']:.1f} vs {s64['ms']:.1f}  "
         f"err/sqrtN={err:.2e} max|dq|={dq:.2e} idem={idem:.2e}")
     assert err <= TOL_D and dq <= TOL_Q
+
+
+@pytest.mark.parametrize("dims,seed", [((4, 4, 4), 0), ((8, 8, 8), 2)])
+def test_bf16x2_configured_recipe_reported(ctx, dims, seed):
+    """The configured BF16 hi+lo / FP32-tail recipe: runs, ends idempotent, and its
+    error against the oracle is measured (it is not expected to reach 1e-6 on
+    this nearly gapless spectrum)."""
+    import paper_1203_6836_amd as p
+    say(f"case bf16x2 dims={dims}")
+    pos = synth.lattice_positions(dims, seed=seed)
+    H = otb.hamiltonian(pos, None, synth.STATIC_MODEL)
+    nocc = 2 * len(pos)
+    ref = osp2.sp2(H, nocc)
+    D, st = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("bf16x2"))
+    D = D.cpu().numpy()
+    N = H.shape[0]
+    err = np.linalg.norm(D - ref.D) / np.sqrt(N)
+    q = observables.mulliken(D)
+    dq = np.max(np.abs(q - observables.mulliken(ref.D)))
+    idem = np.linalg.norm(D @ D - D)
+    say(f"  iters={st['iterations']} tail from {st['head_switch']} err/sqrtN={err:.2e} max|dq|={dq:.2e} idem={idem:.2e}")
+    assert st["status"] == "stalled" and st["head_switch"] > 0
+    assert st["iterations"] - st["head_switch"] == 3        # three FP32 products
+    assert abs(np.trace(D) - nocc) < 1e-3
+    assert err < 1e-2
