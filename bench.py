@@ -86,14 +86,16 @@ def serving(ctx, n_requests, rate):
 
     th = threading.Thread(target=submitter)
     th.start()
-    th.join()
     lat = []
     iters = []
-    for k, r in enumerate(reqs):
+    for k, r in enumerate(reqs):          # consume results as they complete
+        while tickets[k] is None:
+            time.sleep(0.0005)
         _, _, st = srv.sp2_server_wait(tickets[k], r.n_orb, want_D=True)
         # arrival -> result in host memory: submitter lag + (submit -> result) from the server
         lat.append(lag[k] + st["ms"])
         iters.append(st["iterations"])
+    th.join()
     span = max(r.arrival_s + l * 1e-3 for r, l in zip(reqs, lat))
     rep = srv.sp2_server_report()
     srv.close()

@@ -41,7 +41,7 @@ __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 // --------------------------------------------------------------- encoding
 // One wave per padded row: row scale and `slices` digit planes.
 template <int S>
-__device__ void encode_row(const double* __restrict__ X, int ld, int i, int lane, int8_t* __restrict__ digits,
+__device__ __forceinline__ void encode_row(const double* __restrict__ X, int ld, int i, int lane, int8_t* __restrict__ digits,
                            double* __restrict__ scale) {
     const double* row = X + (size_t)i * ld;
     double m = 0.0;
@@ -117,15 +117,24 @@ __global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __
 constexpr int QB = 128;          // tile
 constexpr int QK = 32;           // k bytes per stage
 
+#ifndef SP2_I8_DMA
+#define SP2_I8_DMA 1
+#endif
+#if SP2_I8_DMA
+constexpr int I8_NST = 3;         // LDS ring depth (stages), filled by global->LDS loads
+#else
+constexpr int I8_NST = 2;
+#endif
+
 template <int S>
 struct I8Smem {
-    int8_t buf[2][2 * S * 4][1024];   // [stage][op * S * 4 + slice * 4 + row block][block]
+    int8_t buf[I8_NST][2 * S * 4][1024];   // [stage][op * S * 4 + slice * 4 + row block][block]
 };
 
 // One 128 x 128 output tile (bi, bj) of one system; all 512 threads of the
 // workgroup take part (the body contains barriers).
-template <int S>
-__device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1, int ld,
+template <int S, bool THR>
+__device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1, int ld,
                            const State* __restrict__ st, const int8_t* __restrict__ digits,
                            const double* __restrict__ scale, double* __restrict__ part, int bi, int bj,
                            I8Smem<S>& sm, const int* __restrict__ env) {
@@ -143,6 +152,7 @@ __device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1,
     constexpr int NBLK = 2 * S * 4;             // 1 KiB blocks per stage
     constexpr int PER = NBLK * 64 / 512;        // 16-byte chunks per thread
     static_assert((NBLK * 64) % 512 == 0, "stage must split evenly over 512 threads");
+#if !SP2_I8_DMA
     v4i pre[PER];
     auto gload = [&](int kb) {
 #pragma unroll
@@ -164,6 +174,7 @@ __device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1,
             *reinterpret_cast<v4i*>(&sm.buf[stg][c >> 6][16 * (c & 63)]) = pre[m];
         }
     };
+#endif
 
     v16i acc[S][2];
 #pragma unroll
@@ -179,21 +190,17 @@ __device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1,
     // K range: all of it, or the overlap of the two panels' surviving column
     // blocks of a thresholded X (one 32-byte stage per 32-column block)
     int ks = 0, nk = ld / QK;
-    if (env) {
+    if (THR) {
         const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
         ks = lo;
         nk = lo > hi ? lo : hi + 1;
     }
-    if (ks < nk) gload(ks);
-    if (ks < nk) sstore(0);
-    __syncthreads();
-    for (int kt = ks; kt < nk; ++kt) {
-        const int stg = (kt - ks) & 1;
-        if (kt + 1 < nk) gload(kt + 1);
+    auto compute = [&](int stg) {
         v4i a[S];
 #pragma unroll
         for (int sl = 0; sl < S; ++sl)
             a[sl] = *reinterpret_cast<const v4i*>(&sm.buf[stg][sl * 4 + wr][foff]);
+        // one B digit plane at a time: level tt + uu accumulates a[tt] b[uu]
 #pragma unroll
         for (int uu = 0; uu < S; ++uu) {
             v4i b[2];
@@ -206,9 +213,53 @@ __device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1,
                 for (int c = 0; c < 2; ++c)
                     acc[tt + uu][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt], b[c], acc[tt + uu][c], 0, 0, 0);
         }
+    };
+#if SP2_I8_DMA
+    // Global -> LDS loads without register staging: wave w moves blocks w,
+    // w + 8, ... of a stage, one 1 KiB block per instruction (16 bytes per
+    // lane).  Stage kt + 2 is issued while stage kt is multiplied; before
+    // reading stage kt a wave lets at most the PER loads of stage kt + 1 stay
+    // outstanding, and a barrier then makes every wave's blocks visible.
+    auto issue = [&](int kb, int stg) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int blk = w + 8 * m;
+            const int op = blk / (S * 4);
+            const int rem = blk - op * (S * 4);
+            const int sl = rem >> 2, rb = rem & 3;
+            const int grb = ((op ? j0 : i0) >> 5) + rb;
+            const int8_t* g = digits + sl * plane + ((size_t)grb * nb + kb) * 1024 + 16 * lane;
+            __builtin_amdgcn_global_load_lds((const void*)g,
+                                             (__attribute__((address_space(3))) void*)&sm.buf[stg][blk][0], 16, 0, 0);
+        }
+    };
+    if (ks < nk) issue(ks, 0);
+    if (ks + 1 < nk) issue(ks + 1, 1);
+    for (int kt = ks; kt < nk; ++kt) {
+        // this wave's blocks of stage kt have landed in LDS once at most the
+        // PER loads of stage kt + 1 are outstanding; the bare barrier (no
+        // fence, which would wait for every outstanding load) then covers the
+        // other waves' blocks, and every wave has finished reading the buffer
+        // that stage kt + 2 overwrites
+        if (kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                     // vmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        if (kt + 2 < nk) issue(kt + 2, (kt + 2 - ks) % I8_NST);
+        compute((kt - ks) % I8_NST);
+    }
+    __syncthreads();
+#else
+    if (ks < nk) gload(ks);
+    if (ks < nk) sstore(0);
+    __syncthreads();
+    for (int kt = ks; kt < nk; ++kt) {
+        const int stg = (kt - ks) & 1;
+        if (kt + 1 < nk) gload(kt + 1);
+        compute(stg);
         if (kt + 1 < nk) sstore(stg ^ 1);
         __syncthreads();
     }
+#endif
 
     // epilogue: combine levels in FP64, apply the SP2 update, partials
     const int br = st->branch;
@@ -257,7 +308,7 @@ __device__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1,
     }
 }
 
-template <int S>
+template <int S, bool THR>
 __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
                                                     int ld, const State* __restrict__ st,
                                                     const int8_t* __restrict__ digits,
@@ -268,7 +319,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
     int bi, bj;
     tile_of_block(blockIdx.x, ld / QB, bi, bj);
-    int8x_tile<S>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env);
+    int8x_tile<S, THR>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env);
 }
 
 // Grouped: every upper-triangular tile of every system in the group; a fixed
@@ -285,27 +336,34 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __r
         int bi = 0, bj = 0, tl = item - g->tile_off[s], nt = v.ld / QB, off = 0;
         while (tl >= off + (nt - bi)) { off += nt - bi; ++bi; }
         bj = bi + (tl - off);
-        int8x_tile<S>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr);
+        int8x_tile<S, false>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr);
         __syncthreads();
     }
 }
 
-template <int S>
-static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
-                            hipStream_t stream, const int* env) {
+template <int S, bool THR>
+static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                                     hipStream_t stream, const int* env) {
     const int nt = ld / QB;
     const int T = nt * (nt + 1) / 2;
     const size_t lds = sizeof(I8Smem<S>);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, THR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_gemm_int8x<S>, dim3(T), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
+    hipLaunchKernelGGL((k_gemm_int8x<S, THR>), dim3(T), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
                        s.scale, part, env);
     return hipGetLastError();
+}
+
+template <int S>
+static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                            hipStream_t stream, const int* env) {
+    if (env) return launch_tile_kernel<S, true>(s, buf0, buf1, ld, st, part, stream, env);
+    return launch_tile_kernel<S, false>(s, buf0, buf1, ld, st, part, stream, nullptr);
 }
 
 template <int S>

@@ -105,6 +105,39 @@ Layout layout_for(int N, int slices) {
     return L;
 }
 
+// Pinned host buffers recycled across requests (size classes of 1 MiB), so a
+// steady stream of submits does not pay a pinned allocation each time.
+struct PinnedPool {
+    std::mutex mu;
+    std::multimap<size_t, void*> free_;
+    static size_t cls(size_t n) { return align_up(std::max<size_t>(n, 1), (size_t)1 << 20); }
+    void* get(size_t n) {
+        const size_t c = cls(n);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = free_.find(c);
+            if (it != free_.end()) {
+                void* p = it->second;
+                free_.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) return nullptr;
+        return p;
+    }
+    void put(void* p, size_t n) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu);
+        free_.emplace(cls(n), p);
+    }
+    void clear() {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : free_) (void)hipHostFree(kv.second);
+        free_.clear();
+    }
+};
+
 struct Request {
     uint64_t ticket = 0;
     int N = 0, n_occ = 0;
@@ -134,6 +167,7 @@ struct sp2_server {
     State* st_dev = nullptr;       // kMaxGroup control states
     State* st_host = nullptr;      // pinned
     hipGraphExec_t graph = nullptr;
+    PinnedPool pinned;
     std::vector<Request*> slots;
     std::thread worker;
     std::mutex mu;
@@ -426,13 +460,13 @@ sp2_status sp2_server_submit(sp2_server* s, int N, const double* H_host, int n_o
     r->N = N;
     r->n_occ = n_occ;
     r->L = L;
-    bool ok = hipHostMalloc((void**)&r->H, (size_t)N * N * 8, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&r->D, (size_t)N * N * 8, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&r->q, (size_t)(N / 4 + 1) * 8, hipHostMallocDefault) == hipSuccess;
-    if (!ok) {
-        if (r->H) (void)hipHostFree(r->H);
-        if (r->D) (void)hipHostFree(r->D);
-        if (r->q) (void)hipHostFree(r->q);
+    r->H = (double*)s->pinned.get((size_t)N * N * 8);
+    r->D = (double*)s->pinned.get((size_t)N * N * 8);
+    r->q = (double*)s->pinned.get((size_t)(N / 4 + 1) * 8);
+    if (!r->H || !r->D || !r->q) {
+        s->pinned.put(r->H, (size_t)N * N * 8);
+        s->pinned.put(r->D, (size_t)N * N * 8);
+        s->pinned.put(r->q, (size_t)(N / 4 + 1) * 8);
         delete r;
         return SP2_ENOMEM;
     }
@@ -466,9 +500,9 @@ sp2_status sp2_server_wait(sp2_server* s, uint64_t ticket, double timeout_s, dou
     }
     s->reqs.erase(it);
     lk.unlock();
-    (void)hipHostFree(r->H);
-    (void)hipHostFree(r->D);
-    (void)hipHostFree(r->q);
+    s->pinned.put(r->H, (size_t)r->N * r->N * 8);
+    s->pinned.put(r->D, (size_t)r->N * r->N * 8);
+    s->pinned.put(r->q, (size_t)(r->N / 4 + 1) * 8);
     delete r;
     return (sp2_status)status;
 }
@@ -511,11 +545,12 @@ void sp2_server_destroy(sp2_server* s) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (auto& kv : s->reqs) {
         Request* r = kv.second;
-        if (r->H) (void)hipHostFree(r->H);
-        if (r->D) (void)hipHostFree(r->D);
-        if (r->q) (void)hipHostFree(r->q);
+        s->pinned.put(r->H, (size_t)r->N * r->N * 8);
+        s->pinned.put(r->D, (size_t)r->N * r->N * 8);
+        s->pinned.put(r->q, (size_t)(r->N / 4 + 1) * 8);
         delete r;
     }
+    s->pinned.clear();
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     if (s->arena_mem) (void)hipFree(s->arena_mem);
     if (s->g_dev) (void)hipFree(s->g_dev);

@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_ctrl_init(const double* __restrict__ pa
 // n >= 4, e_n >= e_{n-2}, e_n < stall_tol (stalled at the rounding floor,
 // D = X_n); n + 1 == max_iter (not converged).  Otherwise X_{n+1} becomes
 // current and the next branch is chosen from its traces.
-__device__ void ctrl_step_body(const double* __restrict__ part, int nslots, State* __restrict__ st,
+__device__ __forceinline__ void ctrl_step_body(const double* __restrict__ part, int nslots, State* __restrict__ st,
                                const CtrlArgs& a) {
     if (st->done) return;
     double r[3];
@@ -304,6 +304,7 @@ __device__ __forceinline__ int xcd_remap(int w, int T) {
     return x * q + (x < r ? x : r) + k;
 }
 
+template <bool THR>
 __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
                                                      double* __restrict__ buf1, int ld,
                                                      const State* __restrict__ st,
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
     // ranges of 32-column blocks that survived the threshold; outside it one
     // of the two operands is zero.
     int ks = 0, ke = ld / GK;
-    if (env) {
+    if (THR) {
         const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
         ks = lo * 2;                           // 16-wide stages, two per 32-column block
         ke = lo > hi ? ks : (hi + 1) * 2;
@@ -514,7 +515,8 @@ hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double
     const int nt = ld / GB;
     const int T = tri_tiles(nt);
     *nslots = T;
-    hipLaunchKernelGGL(k_gemm_f64, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env);
+    if (env) hipLaunchKernelGGL(k_gemm_f64<true>, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env);
+    else hipLaunchKernelGGL(k_gemm_f64<false>, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env);
     return hipGetLastError();
 }
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
