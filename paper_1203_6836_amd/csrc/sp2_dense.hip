@@ -286,7 +286,11 @@ __global__ __launch_bounds__(256) void k_ctrl_step_grouped(const GroupDesc* __re
 // ||P - X_n||_F^2 (off-diagonal tiles count twice) into part[3 * tile].
 constexpr int GB = 128;   // tile
 constexpr int GK = 16;    // k per stage
-constexpr int GS = GB;      // LDS row stride (doubles); 2 stages x 2 operands = 64 KiB
+constexpr int GS = GB;      // LDS row stride (doubles)
+#ifndef SP2_F64_DMA
+#define SP2_F64_DMA 0           // measured slower than register staging for FP64
+#endif
+constexpr int F64_NST = SP2_F64_DMA ? 3 : 2;   // 3 stages x 2 operands x 16 KiB = 96 KiB
 
 // Tile id t -> (bi, bj), bi <= bj, row-major over the upper triangle.
 __device__ __forceinline__ void tri_coords(int t, int nt, int& bi, int& bj) {
@@ -322,12 +326,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
     double* __restrict__ Xn = st->cur ? buf0 : buf1;
     const int i0 = bi * GB, j0 = bj * GB;
 
-    __shared__ double As[2][GK][GS];
-    __shared__ double Bs[2][GK][GS];
+    // LDS ring of F64_NST stages; each operand row of a stage is one contiguous
+    // 1 KiB row segment of X, moved by one wave-wide global->LDS load
+    __shared__ double As[F64_NST][GK][GS];
+    __shared__ double Bs[F64_NST][GK][GS];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wi = w >> 1, wj = w & 1;
 
+#if !SP2_F64_DMA
     // global -> register staging: 4 double2 per operand per thread
     const int lrow = tid >> 6;           // + 4*s
     const int lcol = 2 * (tid & 63);
@@ -349,6 +356,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
             Bs[stg][lrow + 4 * s][lcol + 1] = rb[s].y;
         }
     };
+#endif
 
     d4 acc[4][4];
 #pragma unroll
@@ -365,6 +373,50 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
         ks = lo * 2;                           // 16-wide stages, two per 32-column block
         ke = lo > hi ? ks : (hi + 1) * 2;
     }
+    auto compute = [&](int stg) {
+#pragma unroll
+        for (int k4 = 0; k4 < GK / 4; ++k4) {
+            const int kr = k4 * 4 + (lane >> 4);
+            double av[4], bv[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) av[m] = As[stg][kr][wi * 64 + m * 16 + (lane & 15)];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) bv[n] = Bs[stg][kr][wj * 64 + n * 16 + (lane & 15)];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
+        }
+    };
+#if SP2_F64_DMA
+    // wave w loads rows w, w + 4, w + 8, w + 12 of both operands of a stage
+    // (8 global->LDS loads of 1 KiB); stage kt + 2 is issued while stage kt is
+    // multiplied, and a wave waits only for its own loads of stage kt before a
+    // bare barrier (a fenced barrier would also wait for stage kt + 1).
+    auto issue = [&](int kt, int stg) {
+        const int k0 = kt * GK;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int kr = w + 4 * r;
+            const double* rowp = Xc + (size_t)(k0 + kr) * ld;
+            __builtin_amdgcn_global_load_lds((const void*)(rowp + i0 + 2 * lane),
+                                             (__attribute__((address_space(3))) void*)&As[stg][kr][0], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(rowp + j0 + 2 * lane),
+                                             (__attribute__((address_space(3))) void*)&Bs[stg][kr][0], 16, 0, 0);
+        }
+    };
+    if (ks < ke) issue(ks, 0);
+    if (ks + 1 < ke) issue(ks + 1, 1);
+    for (int kt = ks; kt < ke; ++kt) {
+        if (kt + 1 < ke) __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8): stage kt + 1 may be in flight
+        else __builtin_amdgcn_s_waitcnt(0x0F70);               // vmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        if (kt + 2 < ke) issue(kt + 2, (kt + 2 - ks) % F64_NST);
+        compute((kt - ks) % F64_NST);
+    }
+    __syncthreads();
+#else
     if (ks < ke) {
         gload(ks * GK);
         sstore(0);
@@ -372,24 +424,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
         for (int kt = ks; kt < ke; ++kt) {
             const int stg = (kt - ks) & 1;
             if (kt + 1 < ke) gload((kt + 1) * GK);
-#pragma unroll
-            for (int k4 = 0; k4 < GK / 4; ++k4) {
-                const int kr = k4 * 4 + (lane >> 4);
-                double av[4], bv[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) av[m] = As[stg][kr][wi * 64 + m * 16 + (lane & 15)];
-#pragma unroll
-                for (int n = 0; n < 4; ++n) bv[n] = Bs[stg][kr][wj * 64 + n * 16 + (lane & 15)];
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-#pragma unroll
-                    for (int n = 0; n < 4; ++n)
-                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
-            }
+            compute(stg);
             if (kt + 1 < ke) sstore(stg ^ 1);
             __syncthreads();
         }
     }
+#endif
 
     // fused SP2 update + partials
     const int br = st->branch;
