@@ -93,6 +93,75 @@ __global__ __launch_bounds__(256) void k_encode_int8(const double* __restrict__ 
     encode_row<S>(st->cur ? buf1 : buf0, ld, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63, digits, scale);
 }
 
+// One workgroup per padded row, the row held in registers between the max and
+// the digit pass (one HBM read of X instead of two).  Thread t takes columns
+// 8 t + 2048 c .. +8 for c < CH, so rows up to 2048 CH columns fit.  Blocks
+// are mapped to rows XCD-contiguously (block b runs on XCD b % 8 and takes
+// row (b % 8) ld / 8 + b / 8), so the four rows whose 32-byte pieces share a
+// 128-byte line of a digit block are written through one L2 at nearly the
+// same time.  Same digits as encode_row (the row maximum is order-free).
+constexpr int ENC_CH = 8;
+
+template <int S>
+__global__ __launch_bounds__(256) void k_encode_int8_reg(const double* __restrict__ buf0,
+                                                         const double* __restrict__ buf1, int ld,
+                                                         const State* __restrict__ st,
+                                                         int8_t* __restrict__ digits,
+                                                         double* __restrict__ scale) {
+    if (st->done || st->phase != 1) return;
+    const double* __restrict__ X = st->cur ? buf1 : buf0;
+    const int b = blockIdx.x;
+    const int i = (b & 7) * (ld >> 3) + (b >> 3);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const double* row = X + (size_t)i * ld;
+    double4 va[ENC_CH], vb[ENC_CH];
+    double m = 0.0;
+#pragma unroll
+    for (int c = 0; c < ENC_CH; ++c) {
+        const int j = 8 * tid + 2048 * c;
+        if (j < ld) {
+            va[c] = *reinterpret_cast<const double4*>(row + j);
+            vb[c] = *reinterpret_cast<const double4*>(row + j + 4);
+            m = fmax(m, fmax(fmax(fabs(va[c].x), fabs(va[c].y)), fmax(fabs(va[c].z), fabs(va[c].w))));
+            m = fmax(m, fmax(fmax(fabs(vb[c].x), fabs(vb[c].y)), fmax(fabs(vb[c].z), fabs(vb[c].w))));
+        }
+    }
+    m = wred_max(m);
+    __shared__ double wm[4];
+    if (lane == 0) wm[w] = m;
+    __syncthreads();
+    m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+    int e = 0;
+    if (m > 0.0) (void)frexp(m, &e);
+    const double inv = ldexp(1.0, -e);
+    if (tid == 0) scale[i] = ldexp(1.0, e);
+    const size_t plane = (size_t)ld * ld;
+    const size_t rowblk = (size_t)(i >> 5) * (ld >> 5);
+    const int r32 = i & 31;
+#pragma unroll
+    for (int c = 0; c < ENC_CH; ++c) {
+        const int j = 8 * tid + 2048 * c;
+        if (j < ld) {
+            double y[8] = {va[c].x * inv, va[c].y * inv, va[c].z * inv, va[c].w * inv,
+                           vb[c].x * inv, vb[c].y * inv, vb[c].z * inv, vb[c].w * inv};
+            const size_t off = (rowblk + (j >> 5)) * 1024 + r32 * 32 + 16 * (((j >> 4) & 1) ^ dswz(r32)) + (j & 15);
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                const double wt = ldexp(1.0, 6 + 7 * t);
+                const double iw = ldexp(1.0, -(6 + 7 * t));
+                unsigned long long packed = 0ull;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const double d = rint(y[q] * wt);
+                    y[q] -= d * iw;
+                    packed |= (unsigned long long)(uint8_t)(int8_t)d << (8 * q);
+                }
+                *reinterpret_cast<unsigned long long*>(digits + t * plane + off) = packed;
+            }
+        }
+    }
+}
+
 // Grouped: work item = 4 rows of one system; fixed grid, grid-stride loop.
 template <int S>
 __global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __restrict__ g) {
@@ -369,8 +438,12 @@ static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld,
 template <int S>
 static hipError_t run_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
                              hipStream_t stream) {
-    hipLaunchKernelGGL(k_encode_int8<S>, dim3(ld / 4), dim3(256), 0, stream, buf0, buf1, ld, st, s.digits,
-                       s.scale);
+    if (ld <= 2048 * ENC_CH)
+        hipLaunchKernelGGL(k_encode_int8_reg<S>, dim3(ld), dim3(256), 0, stream, buf0, buf1, ld, st, s.digits,
+                           s.scale);
+    else
+        hipLaunchKernelGGL(k_encode_int8<S>, dim3(ld / 4), dim3(256), 0, stream, buf0, buf1, ld, st, s.digits,
+                           s.scale);
     return hipGetLastError();
 }
 
