@@ -189,15 +189,27 @@ constexpr int QK = 32;           // k bytes per stage
 #ifndef SP2_I8_DMA
 #define SP2_I8_DMA 1
 #endif
+#ifndef SP2_I8_SCHED
+#define SP2_I8_SCHED 2           // 0: compiler's own order; n > 0: read lookahead
+#endif
 #if SP2_I8_DMA
 constexpr int I8_NST = 3;         // LDS ring depth (stages), filled by global->LDS loads
 #else
 constexpr int I8_NST = 2;
 #endif
 
+// The staging ring; after the K loop the same LDS holds half of the finished
+// tile, transposed, so the mirrored (lower-triangle) copy is written as
+// whole rows instead of one 8-byte element per row.  Row stride 129 doubles
+// spreads the column-wise LDS stores over the banks.
+constexpr int TR_LD = 129;
+
 template <int S>
 struct I8Smem {
-    int8_t buf[I8_NST][2 * S * 4][1024];   // [stage][op * S * 4 + slice * 4 + row block][block]
+    union {
+        int8_t buf[I8_NST][2 * S * 4][1024];   // [stage][op * S * 4 + slice * 4 + row block][block]
+        double tr[64][TR_LD];                  // [tile column (one half)][tile row]
+    };
 };
 
 // One 128 x 128 output tile (bi, bj) of one system; all 512 threads of the
@@ -264,24 +276,46 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
         ks = lo;
         nk = lo > hi ? lo : hi + 1;
     }
+    // Fragment reads are written in order of first use (B plane 0, the A
+    // planes, B planes 1 ..), the products in level order, and the scheduler
+    // is held to a pattern of one read per two products that keeps every
+    // read LA product pairs ahead of its first use, so a stage starts after
+    // 3 + LA reads instead of the whole set.
     auto compute = [&](int stg) {
-        v4i a[S];
+        auto rdA = [&](int sl) { return *reinterpret_cast<const v4i*>(&sm.buf[stg][sl * 4 + wr][foff]); };
+        auto rdB = [&](int uu, int c) {
+            return *reinterpret_cast<const v4i*>(&sm.buf[stg][S * 4 + uu * 4 + wc * 2 + c][foff]);
+        };
+        v4i a[S], b[S][2];
+        b[0][0] = rdB(0, 0);
+        b[0][1] = rdB(0, 1);
 #pragma unroll
-        for (int sl = 0; sl < S; ++sl)
-            a[sl] = *reinterpret_cast<const v4i*>(&sm.buf[stg][sl * 4 + wr][foff]);
-        // one B digit plane at a time: level tt + uu accumulates a[tt] b[uu]
+        for (int tt = 0; tt < S; ++tt) a[tt] = rdA(tt);
 #pragma unroll
-        for (int uu = 0; uu < S; ++uu) {
-            v4i b[2];
+        for (int uu = 1; uu < S; ++uu) {
+            b[uu][0] = rdB(uu, 0);
+            b[uu][1] = rdB(uu, 1);
+        }
+        // level tt + uu accumulates a[tt] b[uu]
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
-                b[c] = *reinterpret_cast<const v4i*>(&sm.buf[stg][S * 4 + uu * 4 + wc * 2 + c][foff]);
+        for (int uu = 0; uu < S; ++uu)
 #pragma unroll
             for (int tt = 0; tt < S - uu; ++tt)
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
-                    acc[tt + uu][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt], b[c], acc[tt + uu][c], 0, 0, 0);
+                    acc[tt + uu][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt], b[uu][c], acc[tt + uu][c], 0, 0, 0);
+#if SP2_I8_SCHED
+        constexpr int LA = SP2_I8_SCHED;                 // lookahead in reads
+        constexpr int R = 3 * S, P = S * (S + 1) / 2;   // reads, product pairs
+        constexpr int MID = R - 3 - LA;
+        __builtin_amdgcn_sched_group_barrier(0x100, 3 + LA, 0);
+#pragma unroll
+        for (int q = 0; q < MID; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         }
+        __builtin_amdgcn_sched_group_barrier(0x008, 2 * (P - MID), 0);
+#endif
     };
 #if SP2_I8_DMA
     // Global -> LDS loads without register staging: wave w moves blocks w,
@@ -349,10 +383,24 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
             const double x = Xc[(size_t)gi * ld + gj];
             const double xn = br ? 2.0 * x - p : p;
             Xn[(size_t)gi * ld + gj] = xn;
-            if (mirror) Xn[(size_t)gj * ld + gi] = xn;
+            if (mirror) sm.tr[wc * 32 + (lane & 31)][gi - i0] = xn;
             if (gi == gj) tr += xn;
             fro += xn * xn;
             idm += (p - x) * (p - x);
+        }
+        if (mirror) {
+            // columns j0 + 64 wc' + 32 c + (0..31) of every wave: 64 rows of
+            // the mirrored block, 128 doubles each, written one half row per
+            // wave and instruction
+            __syncthreads();
+#pragma unroll 4
+            for (int q = 0; q < 16; ++q) {
+                const int rh = w + 8 * q;
+                const int jj = rh >> 1, col = (rh & 1) * 64 + lane;
+                const int gr = j0 + (jj >> 5) * 64 + c * 32 + (jj & 31);
+                Xn[(size_t)gr * ld + i0 + col] = sm.tr[jj][col];
+            }
+            __syncthreads();
         }
     }
     tr = wred_sum(tr);
