@@ -17,6 +17,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision int8x|fp
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +32,51 @@ PEAK_HBM_GBS = 8000.0
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+# Kernel sources whose text fixes each product kernel's memory traffic.
+KERNEL_SOURCES = {
+    "k_gemm_int8x": ["int8x.hip", "split_internal.h", "sp2_internal.h"],
+    "k_gemm_f64": ["sp2_dense.hip", "sp2_internal.h"],
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1203_6836_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` at N = 8192 from its committed PMC summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the summary is missing or
+    the kernel's sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_counters_mixed_n8192.md")
+    try:
+        fields = {}
+        with open(path) as f:
+            for line in f:
+                k, sep, v = line.strip().partition(": ")
+                if sep:
+                    fields[k] = v.strip()
+        if fields.get("source_sha256") != kernel_source_hash(kernel):
+            return None
+        return int(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(H_np, n_occ, n_products=10):
@@ -48,7 +94,8 @@ def cpu_baseline(H_np, n_occ, n_products=10):
     return {"value": round(2.0 * N ** 3 * n_products / dt / 1e12, 4), "unit": "TFLOP/s",
             "cores": int(cores), "kind": "oracle",
             "sample": f"{n_products} SP2 products (X^2 via numpy/OpenBLAS FP64) of the same N={N} "
-                      f"Hamiltonian, {dt:.1f} s; GEMM-equivalent 2N^3 flops per product"}
+                      f"Hamiltonian, {dt:.1f} s, on {cpu_model()} ({os.cpu_count()} logical CPUs "
+                      f"visible); GEMM-equivalent 2N^3 flops per product"}
 
 
 def serving(ctx, n_requests, rate):
@@ -141,6 +188,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the counter-calibration kernels and one solve per precision "
+                         "(for rocprofv3 --pmc passes); prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -167,6 +217,27 @@ def main():
         q = ctx.sp2_mulliken(Dout, w.n_atoms)
         e = ctx.sp2_band_energy(Dout, H)
         return st, q, e
+
+    if args.traffic_probe:
+        # calibration for the HBM byte counters: kernels of known traffic
+        # (1 GiB written by a fill, 1 GiB read + 1 GiB written by an
+        # elementwise add and by a device-to-device copy)
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        torch.add(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        for prec in ("int8x", "fp64"):
+            log(f"traffic probe: one {prec} solve at N={N}")
+            solve(prec, D)
+            torch.cuda.synchronize()
+        log("traffic probe done")
+        ctx.close()
+        return
 
     # ---- plain FP64 GPU path (reference speed and D_fp64) ----
     log(f"fp64 path: N={N}")
@@ -219,10 +290,14 @@ def main():
     else:
         achieved = sym_flops / (kms * 1e-3) / 1e12
         unit = "TFLOP/s"
+    kname = "k_gemm_f64" if prec == "fp64" else ("k_gemm_int8x" if prec == "int8x" else "k_gemm_bf16x2")
+    traffic = recorded_traffic(kname) if kname in KERNEL_SOURCES else None
+    if prec == "int8x" and args.slices != 5:
+        traffic = None                      # counters are taken with 5 digit planes
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK[prec], "unit": unit,
-            "frac": round(achieved / PEAK[prec], 4), "traffic": None,
-            "kernel": "k_gemm_f64" if prec == "fp64" else ("k_gemm_int8x" if prec == "int8x" else "k_gemm_bf16x2"),
-            "kernel_ms_avg": round(kms, 4), "launches": cnt}
+            "frac": round(achieved / PEAK[prec], 4), "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+            "kernel": kname, "kernel_ms_avg": round(kms, 4), "launches": cnt}
 
     out = {
         "metric": "SP2 TFLOP/s & solves/s (mixed vs FP64) at N=8192; p50/p99 served latency",

@@ -35,6 +35,8 @@ typedef enum {
     SP2_ENOMEM = -2,    /* device allocation failed                          */
     SP2_EDEVICE = -3,   /* HIP runtime error                                 */
     SP2_ENOCONV = -4,   /* SP2 reached max_iter without converging/stalling  */
+    SP2_EGAP = -5,      /* no resolvable gap at the Fermi level: the set of
+                           n_occ occupied states is not unique               */
     SP2_EBUDGET = -6,   /* serving: request larger than the memory budget    */
     SP2_ETIMEOUT = -8   /* serving: wait timed out                           */
 } sp2_status;
@@ -67,7 +69,8 @@ typedef struct {
 
 typedef struct {
     int iterations;          /* products X_n^2 formed                            */
-    int status;              /* 0 converged, 1 stalled, 2 max_iter               */
+    int status;              /* 0 converged, 1 stalled, 2 max_iter, 3 gap,
+                                4 invalid H                                      */
     int fp64_products;       /* of which in FP64                                 */
     int head_switch;         /* product index where the precision switched (-1)  */
     double eps_min, eps_max; /* Gershgorin bounds used for X_0                   */
@@ -110,8 +113,15 @@ const char *sp2_last_error(const sp2_ctx *ctx);
  * (Linear scaling section; orthogonal T_e = 0 subsection: the step function
  * of the Hamiltonian).  H: N x N symmetric (device); D_out: N x N (device).
  * 0 < n_occ < N.  opt NULL = defaults.  stats may be NULL.
- * Returns SP2_ENOCONV if neither stop rule fired within max_iter products
- * (D_out is then not written). */
+ * H must be finite and symmetric to within 1e-12 max|H_ij|, else SP2_EINVAL
+ * (checked on the device before any product).
+ * Returns SP2_ENOCONV if neither stop rule fired within max_iter products,
+ * and SP2_EGAP when theta(mu0 I - H) is not defined at the available
+ * resolution (the paper assumes a gap; reading for a degenerate level): the
+ * iteration stopped at a projector whose trace is not n_occ, or at least
+ * 100 products left eigenvalues of X_n far from 0 and 1
+ * (||X_n^2 - X_n||_F >= 1/16), or H is a multiple of I.  On any error D_out
+ * is not written. */
 sp2_status sp2_density_matrix(sp2_ctx *ctx, int N, const double *H, int n_occ,
                               const sp2_options *opt, double *D_out,
                               sp2_stats *stats);
@@ -165,6 +175,19 @@ sp2_status tb_forces(sp2_ctx *ctx, const tb_params *p, int n_atoms,
                      const double *xyz, const double *D, const double *q,
                      const double *n_aux, double *F_out, double *U_host);
 
+/* One Born-Oppenheimer evaluation at auxiliary charges n (n = q at
+ * self-consistency): H[n] (Eq. DFTB_2, S = I), D = theta(mu0 I - H[n]) by
+ * SP2, net Mulliken charges q[D] (SCC-TB subsection), band energy
+ * 2 Tr[D H[n]] (Eq. DFT_POT), the potential energy U and the forces at
+ * constant n as in tb_forces.  xyz: 3 n_atoms device; n_aux: n_atoms device
+ * or NULL (n = 0); q_out: n_atoms device; F_out: 3 n_atoms device or NULL;
+ * e_band_host, e_pot_host: host scalars or NULL; stats may be NULL.  The
+ * H and D scratch is owned by the context.  Errors as sp2_density_matrix. */
+sp2_status qmd_evaluate(sp2_ctx *ctx, const tb_params *p, int n_atoms, const double *xyz,
+                        const double *n_aux, int n_occ, const sp2_options *opt, double *q_out,
+                        double *e_band_host, double *e_pot_host, double *F_out,
+                        sp2_stats *stats);
+
 typedef struct {
     double dt_fs;     /* time step (fs)                                        */
     double kappa;     /* delta t^2 omega^2 of Eq. Verl_n                        */
@@ -203,6 +226,14 @@ sp2_status xlbomd_run(xlbomd *md, int n_steps, xlbomd_record *log);
 /* Copy current positions, velocities, charges q and n_t to host arrays (any may be NULL). */
 sp2_status xlbomd_get(xlbomd *md, double *xyz_host, double *vel_host,
                       double *q_host, double *n_host);
+/* Checkpoint: the complete integrator state (positions, velocities, forces,
+ * charges q, the K + 1 auxiliary-charge history of Eq. Verl_n, step count)
+ * as a versioned byte image in caller memory.  With buf NULL, *bytes is set
+ * to the size needed; a smaller *bytes gives SP2_EINVAL (and the size). */
+sp2_status xlbomd_get_state(const xlbomd *md, void *buf, size_t *bytes);
+/* Resume from a checkpoint of an integrator with the same n_atoms and K;
+ * continuing is then bit-identical to continuing the original. */
+sp2_status xlbomd_set_state(xlbomd *md, const void *buf, size_t bytes);
 void xlbomd_destroy(xlbomd *md);
 
 /* ---------------------------------------------------------------------

@@ -19,6 +19,19 @@ the steps below are the standard SP2 recursion written from its definition:
   ||P - X_n||_F < stall (return X_n; the idempotency error has reached the
   rounding floor), or after max_iter iterations (not converged).
 
+Reading for a degenerate Fermi level (the paper is silent): theta(mu0 I - H)
+is undefined when the N_occ-th and (N_occ+1)-th eigenvalues coincide (or lie
+closer than the products can resolve).  Status "gap" is reported when
+* the run stops with an idempotent X_n whose trace is not N_occ
+  (|Tr X_n - N_occ| > 1/2: a projector has integer trace, so the occupied
+  set could not be chosen), e.g. X_0 already a projector of another rank;
+* at least GAP_MIN_ITER products were formed without convergence and
+  ||X_n^2 - X_n||_F >= 1/16 (eigenvalues still at least 0.067 from 0 and 1:
+  the trace-matching branch rule holds a degenerate cluster at a fraction,
+  1/2 for a pair, and the iteration never becomes idempotent);
+* eps_max == eps_min (H a multiple of I).
+A run stopped earlier by a smaller max_iter is "max_iter" (not converged).
+
 Each branch is a polynomial in X_0, so X_n = p_n(X_0) and the eigenvalues of
 X_n are p_n applied to those of X_0 (pinned, with the Jacobi projector, in
 tests/test_oracle_sp2.py).
@@ -42,6 +55,15 @@ class SP2Result:
     converged: bool
     stalled: bool
     fill: list = dataclasses.field(default_factory=list)
+    status: str = ""         # "converged", "stalled", "gap" or "max_iter"
+
+    def __post_init__(self):
+        if not self.status:
+            self.status = "converged" if self.converged else ("stalled" if self.stalled else "max_iter")
+
+
+GAP_IDEM = 1.0 / 16.0
+GAP_MIN_ITER = 100
 
 
 def gershgorin(H):
@@ -92,6 +114,8 @@ def sp2(H, n_occ, tol=1e-10, max_iter=100, stall=1e-2, tau=0.0, block=32,
     """
     H = np.asarray(H, dtype=np.float64)
     eps_min, eps_max = gershgorin(H) if bounds is None else bounds
+    if not eps_max > eps_min:
+        return SP2Result(np.zeros_like(H), 0, [], [], [], eps_min, eps_max, False, False, [], "gap")
     X = sp2_initial(H, eps_min, eps_max)
     fill = []
     if tau > 0.0:
@@ -104,20 +128,21 @@ def sp2(H, n_occ, tol=1e-10, max_iter=100, stall=1e-2, tau=0.0, block=32,
         e = float(np.linalg.norm(P - X))
         idem.append(e)
         traces.append((t1, t2))
-        if e < tol:
+        conv = e < tol
+        stalled = n >= 4 and e >= idem[n - 2] and e < stall
+        if conv or stalled:
+            status = "gap" if abs(t1 - n_occ) > 0.5 else ("converged" if conv else "stalled")
             return SP2Result(X, n + 1, branches, idem, traces, eps_min, eps_max,
-                             True, False, fill)
-        if n >= 4 and e >= idem[n - 2] and e < stall:
-            return SP2Result(X, n + 1, branches, idem, traces, eps_min, eps_max,
-                             False, True, fill)
+                             conv, stalled and not conv, fill, status)
         b = choose_branch(t1, t2, n_occ)
         branches.append(b)
         X = P if b == 0 else 2.0 * X - P
         if tau > 0.0:
             X, f = block_threshold(X, tau, block)
             fill.append(f)
+    status = "gap" if max_iter >= GAP_MIN_ITER and idem[-1] >= GAP_IDEM else "max_iter"
     return SP2Result(X, max_iter, branches, idem, traces, eps_min, eps_max,
-                     False, False, fill)
+                     False, False, fill, status)
 
 
 def scalar_sp2(x0, branches):

@@ -49,8 +49,8 @@ def density(H, n_occ, solver="sp2", tol=1e-10):
         D, _, _ = eig.density_matrix(H, n_occ)
         return D
     r = sp2.sp2(H, n_occ, tol=tol)
-    if not (r.converged or r.stalled):
-        raise RuntimeError("oracle SP2 did not converge")
+    if r.status not in ("converged", "stalled"):
+        raise RuntimeError(f"oracle SP2 ended with status {r.status}")
     return r.D
 
 

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsp2qmd.so")
 
-SP2_OK, SP2_EINVAL, SP2_ENOMEM, SP2_EDEVICE, SP2_ENOCONV = 0, -1, -2, -3, -4
+SP2_OK, SP2_EINVAL, SP2_ENOMEM, SP2_EDEVICE, SP2_ENOCONV, SP2_EGAP = 0, -1, -2, -3, -4, -5
 SP2_EBUDGET, SP2_ETIMEOUT = -6, -8
 PREC_FP64, PREC_INT8X, PREC_BF16X2 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "int8x": PREC_INT8X, "bf16x2": PREC_BF16X2}
@@ -42,7 +42,7 @@ class Sp2Stats(ctypes.Structure):
     def to_dict(self):
         n = self.iterations
         bits = [(self.branch_bits[k >> 6] >> (k & 63)) & 1 for k in range(max(n - 1, 0))]
-        return {"iterations": n, "status": ["converged", "stalled", "max_iter"][self.status],
+        return {"iterations": n, "status": ["converged", "stalled", "max_iter", "gap", "invalid"][self.status],
                 "fp64_products": self.fp64_products, "head_switch": self.head_switch,
                 "eps_min": self.eps_min, "eps_max": self.eps_max, "idem_err": self.idem_err,
                 "trace": self.trace, "branches": bits, "ms": self.ms,
@@ -97,11 +97,15 @@ _SIGS = {
     "tb_hamiltonian": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P]),
     "tb_forces": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P, _P,
                        ctypes.POINTER(_D)]),
+    "qmd_evaluate": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _I, ctypes.POINTER(Sp2Options), _P,
+                          ctypes.POINTER(_D), ctypes.POINTER(_D), _P, ctypes.POINTER(Sp2Stats)]),
     "xlbomd_create": (_I, [_P, ctypes.POINTER(TBParams), ctypes.POINTER(XLOptions), _I,
                            _P, _P, _P, ctypes.POINTER(_P)]),
     "xlbomd_run": (_I, [_P, _I, ctypes.POINTER(XLRecord)]),
     "xlbomd_get": (_I, [_P, _P, _P, _P, _P]),
     "xlbomd_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    "xlbomd_get_state": (_I, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "xlbomd_set_state": (_I, [_P, _P, ctypes.c_size_t]),
     "xlbomd_destroy": (None, [_P]),
     "sp2_server_options_default": (None, [ctypes.POINTER(ServerOptions)]),
     "sp2_server_create": (_I, [_P, ctypes.POINTER(ServerOptions), ctypes.POINTER(_P)]),
@@ -262,6 +266,26 @@ class Context:
                                     _ptr(n_aux), _ptr(F_out), ctypes.byref(U)), "tb_forces")
         return F_out, U.value
 
+    def qmd_evaluate(self, model, xyz, n_aux=None, n_occ=None, opts: Sp2Options | None = None,
+                     want_forces=True):
+        """One evaluation at auxiliary charges n_aux (device tensors; None = 0):
+        returns (q, e_band, e_pot, F or None, stats)."""
+        import torch
+        nat = xyz.shape[0]
+        if n_occ is None:
+            n_occ = int(round(model.z_val * nat / 2))
+        q = torch.empty(nat, dtype=torch.float64, device=xyz.device)
+        F = torch.empty((nat, 3), dtype=torch.float64, device=xyz.device) if want_forces else None
+        eb, ep = ctypes.c_double(), ctypes.c_double()
+        st = Sp2Stats()
+        p = tb_params(model)
+        o = opts if opts is not None else options("fp64")
+        self._check(lib().qmd_evaluate(self._h, ctypes.byref(p), nat, _ptr(xyz),
+                                       None if n_aux is None else _ptr(n_aux), int(n_occ), ctypes.byref(o),
+                                       _ptr(q), ctypes.byref(eb), ctypes.byref(ep),
+                                       None if F is None else _ptr(F), ctypes.byref(st)), "qmd_evaluate")
+        return q, eb.value, ep.value, F, st.to_dict()
+
     def xlbomd_create(self, model, xyz, vel, n0=None, dt_fs=0.25, kappa=0.91, alpha=0.018,
                       c=(-6.0, 14.0, -8.0, -3.0, 4.0, -1.0), sp2_opts=None,
                       scf_beta=0.3, scf_tol=1e-10, scf_max_iter=None):
@@ -316,6 +340,18 @@ class XLBOMD:
         self.ctx._check(lib().xlbomd_get(self._h, xyz.ctypes.data_as(_P), vel.ctypes.data_as(_P),
                                          q.ctypes.data_as(_P), n.ctypes.data_as(_P)), "xlbomd_get")
         return xyz, vel, q, n
+
+    def xlbomd_get_state(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        self.ctx._check(lib().xlbomd_get_state(self._h, None, ctypes.byref(n)), "xlbomd_get_state")
+        buf = ctypes.create_string_buffer(n.value)
+        self.ctx._check(lib().xlbomd_get_state(self._h, ctypes.cast(buf, _P), ctypes.byref(n)),
+                        "xlbomd_get_state")
+        return buf.raw[:n.value]
+
+    def xlbomd_set_state(self, state: bytes):
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        self.ctx._check(lib().xlbomd_set_state(self._h, ctypes.cast(buf, _P), len(state)), "xlbomd_set_state")
 
     def close(self):
         if self._h:

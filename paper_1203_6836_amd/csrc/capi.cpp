@@ -38,6 +38,7 @@ struct sp2_ctx {
     State* st_host = nullptr; // pinned
     double* scal = nullptr;   // device scalars
     double* scal_host = nullptr;
+    double* chk = nullptr;    // H check partials (2 per check workgroup)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     SplitScratch split;       // reduced-precision operands
     bool profile = false;
@@ -49,6 +50,13 @@ struct sp2_ctx {
     size_t natcap = 0;
     int* env = nullptr;        // per-panel surviving column-block ranges (thresholded X)
     size_t envcap = 0;
+    // qmd_evaluate scratch: H[n], D, zero charges, forces
+    double* eH = nullptr;
+    double* eD = nullptr;
+    size_t ecap = 0;           // bytes of each of eH, eD
+    double* ezero = nullptr;
+    double* eF = nullptr;
+    size_t eatcap = 0;         // atoms
 };
 
 int sp2_ctx_device_of(const sp2_ctx* c) { return c->device; }
@@ -100,6 +108,7 @@ const char* sp2_strerror(int s) {
         case SP2_ENOMEM: return "device out of memory";
         case SP2_EDEVICE: return "HIP runtime error";
         case SP2_ENOCONV: return "SP2 did not converge within max_iter";
+        case SP2_EGAP: return "no resolvable gap at the Fermi level (theta(mu0 I - H) undefined)";
         case SP2_EBUDGET: return "request exceeds the memory budget";
         case SP2_ETIMEOUT: return "timed out";
         default: return "unknown status";
@@ -121,6 +130,7 @@ sp2_status sp2_ctx_create(sp2_ctx** out, int device, void* stream) {
     if (hipMalloc((void**)&c->st, sizeof(State)) != hipSuccess ||
         hipHostMalloc((void**)&c->st_host, sizeof(State), hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&c->scal, 64 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->chk, 2 * kCheckGrid * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void**)&c->scal_host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         sp2_ctx_destroy(c);
@@ -135,7 +145,8 @@ void sp2_ctx_destroy(sp2_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->V, c->eatom, c->qtmp, c->env};
+    void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->chk, c->V, c->eatom, c->qtmp, c->env,
+                   c->eH, c->eD, c->ezero, c->eF};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     split_free(c->split);
@@ -229,9 +240,10 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     }
     hipStream_t st = c->stream;
     HIPCHK(c, hipEventRecord(c->ev0, st));
-    int ns = 0;
+    int ns = 0, nchk = 0;
+    HIPCHK(c, launch_check_h(H, N, c->chk, &nchk, st));
     HIPCHK(c, launch_gershgorin(H, N, c->part, &ns, st));
-    HIPCHK(c, launch_bounds(c->part, ns, c->st, st));
+    HIPCHK(c, launch_bounds(c->part, ns, c->chk, nchk, c->st, st));
     HIPCHK(c, launch_init(H, N, ld, buf0, c->st, c->part, &ns, st));
     if (o.tau > 0.0) HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 1, st, env));
     HIPCHK(c, launch_ctrl_init(c->part, ns, c->st, a, st));
@@ -265,7 +277,7 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     }
     (void)finished;
     const State& h = *c->st_host;
-    if (h.done != 3) HIPCHK(c, launch_finalize(buf0, buf1, ld, N, D, c->st, st));
+    if (h.done == 1 || h.done == 2) HIPCHK(c, launch_finalize(buf0, buf1, ld, N, D, c->st, st));
     HIPCHK(c, hipEventRecord(c->ev1, st));
     HIPCHK(c, hipEventSynchronize(c->ev1));
     float ms = 0.f;
@@ -273,7 +285,7 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->iterations = h.iter;
-        stats->status = h.done == 1 ? 0 : (h.done == 2 ? 1 : 2);
+        stats->status = h.done - 1;   // 0 converged, 1 stalled, 2 max_iter, 3 gap, 4 invalid H
         stats->fp64_products = h.fp64_products;
         stats->head_switch = h.head_switch;
         stats->eps_min = h.eps_min;
@@ -310,6 +322,9 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
         }
     }
     if (h.done == 3) return fail(c, SP2_ENOCONV, "SP2 reached max_iter without converging");
+    if (h.done == 4)
+        return fail(c, SP2_EGAP, "no resolvable HOMO-LUMO gap at the Fermi level: the occupied set is not unique");
+    if (h.done == 5) return fail(c, SP2_EINVAL, "H is not finite and symmetric (|H - H^T| > 1e-12 max|H|)");
     return SP2_OK;
 }
 
@@ -460,6 +475,58 @@ extern "C" sp2_status tb_forces(sp2_ctx* c, const tb_params* p, int n_atoms, con
         HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         *U_host = c->scal_host[0];
+    }
+    return SP2_OK;
+}
+
+extern "C" sp2_status qmd_evaluate(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz,
+                                   const double* n_aux, int n_occ, const sp2_options* opt, double* q_out,
+                                   double* e_band_host, double* e_pot_host, double* F_out, sp2_stats* stats) {
+    if (!c) return SP2_EINVAL;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (!params_ok(p)) return fail(c, SP2_EINVAL, "bad tb_params");
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !q_out) return fail(c, SP2_EINVAL, "bad qmd_evaluate arguments");
+    const int N = 4 * n_atoms;
+    if (n_occ <= 0 || n_occ >= N) return fail(c, SP2_EINVAL, "need 0 < n_occ < 4 n_atoms");
+    sp2_options o;
+    if (opt) o = *opt;
+    else sp2_options_default(&o);
+    sp2_status s = check_options(c, o, N);
+    if (s != SP2_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((s = ensure_atoms(c, n_atoms)) != SP2_OK) return s;
+    const size_t mat = (size_t)N * N * sizeof(double);
+    if (c->ecap < mat) {
+        size_t a = c->ecap, b = c->ecap;
+        if ((s = grow(c, (void**)&c->eH, &a, mat)) != SP2_OK) return s;
+        if ((s = grow(c, (void**)&c->eD, &b, mat)) != SP2_OK) return s;
+        c->ecap = mat;
+    }
+    if ((size_t)n_atoms > c->eatcap) {
+        size_t a = c->eatcap * sizeof(double), b = 3 * c->eatcap * sizeof(double);
+        if ((s = grow(c, (void**)&c->ezero, &a, n_atoms * sizeof(double))) != SP2_OK) return s;
+        if ((s = grow(c, (void**)&c->eF, &b, 3 * n_atoms * sizeof(double))) != SP2_OK) return s;
+        c->eatcap = n_atoms;
+    }
+    hipStream_t st = c->stream;
+    const double* n = n_aux;
+    if (!n) {
+        HIPCHK(c, hipMemsetAsync(c->ezero, 0, n_atoms * sizeof(double), st));
+        n = c->ezero;
+    }
+    if ((s = tb_hamiltonian(c, p, n_atoms, xyz, n, c->eH)) != SP2_OK) return s;
+    if ((s = sp2_solve(c, N, c->eH, n_occ, o, c->eD, stats)) != SP2_OK) return s;
+    HIPCHK(c, launch_mulliken(c->eD, n_atoms, p->z_val, q_out, st));
+    int ns = 0;
+    if (e_band_host) HIPCHK(c, launch_dot(c->eD, c->eH, (size_t)N * N, c->part, &ns, c->scal + 1, st));
+    if (F_out || e_pot_host)
+        if ((s = forces_impl(c, p, n_atoms, xyz, c->eD, q_out, n, F_out ? F_out : c->eF, c->scal)) != SP2_OK)
+            return s;
+    if (e_band_host || e_pot_host) {
+        HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (e_pot_host) *e_pot_host = c->scal_host[0];
+        if (e_band_host) *e_band_host = 2.0 * c->scal_host[1];
     }
     return SP2_OK;
 }
@@ -636,6 +703,89 @@ extern "C" sp2_status xlbomd_get(xlbomd* m, double* xyz_host, double* vel_host, 
     if (q_host) HIPCHK(c, hipMemcpyAsync(q_host, m->q, b, hipMemcpyDeviceToHost, st));
     if (n_host) HIPCHK(c, hipMemcpyAsync(n_host, m->hist + (size_t)m->head * m->nat, b, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    return SP2_OK;
+}
+
+namespace {
+// Checkpoint layout: header, then xyz, vel, F (3 n_atoms each), q (n_atoms)
+// and the K + 1 history slots of n (n_atoms each), all FP64.
+struct XlCheckpoint {
+    uint32_t magic;      // 'XLBS'
+    uint32_t version;
+    int32_t n_atoms;
+    int32_t K;
+    int64_t step;
+    int32_t head;
+    int32_t pad_;
+    double U;
+};
+constexpr uint32_t kXlMagic = 0x53424c58u;
+constexpr uint32_t kXlVersion = 1;
+size_t checkpoint_bytes(int nat, int K) {
+    return sizeof(XlCheckpoint) + (size_t)(10 + K + 1) * nat * sizeof(double);
+}
+}  // namespace
+
+extern "C" sp2_status xlbomd_get_state(const xlbomd* m, void* buf, size_t* bytes) {
+    if (!m || !bytes) return SP2_EINVAL;
+    sp2_ctx* c = m->c;
+    const size_t need = checkpoint_bytes(m->nat, m->o.K);
+    if (!buf) {
+        *bytes = need;
+        return SP2_OK;
+    }
+    if (*bytes < need) {
+        *bytes = need;
+        return fail(c, SP2_EINVAL, "checkpoint buffer too small");
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    XlCheckpoint h{};
+    h.magic = kXlMagic;
+    h.version = kXlVersion;
+    h.n_atoms = m->nat;
+    h.K = m->o.K;
+    h.step = m->step;
+    h.head = m->head;
+    h.U = m->U;
+    char* out = static_cast<char*>(buf);
+    std::memcpy(out, &h, sizeof(h));
+    double* d = reinterpret_cast<double*>(out + sizeof(h));
+    const size_t na = m->nat;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipMemcpyAsync(d, m->xyz, 3 * na * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(d + 3 * na, m->vel, 3 * na * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(d + 6 * na, m->F, 3 * na * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(d + 9 * na, m->q, na * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(d + 10 * na, m->hist, (size_t)(m->o.K + 1) * na * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    *bytes = need;
+    return SP2_OK;
+}
+
+extern "C" sp2_status xlbomd_set_state(xlbomd* m, const void* buf, size_t bytes) {
+    if (!m || !buf) return SP2_EINVAL;
+    sp2_ctx* c = m->c;
+    XlCheckpoint h;
+    if (bytes < sizeof(h)) return fail(c, SP2_EINVAL, "checkpoint too short");
+    std::memcpy(&h, buf, sizeof(h));
+    if (h.magic != kXlMagic || h.version != kXlVersion) return fail(c, SP2_EINVAL, "not an xlbomd checkpoint");
+    if (h.n_atoms != m->nat || h.K != m->o.K)
+        return fail(c, SP2_EINVAL, "checkpoint is for a different system size or history length");
+    if (bytes != checkpoint_bytes(m->nat, m->o.K) || h.head < 0 || h.head > h.K || h.step < 0)
+        return fail(c, SP2_EINVAL, "corrupt checkpoint");
+    HIPCHK(c, hipSetDevice(c->device));
+    const double* d = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(h));
+    const size_t na = m->nat;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipMemcpyAsync(m->xyz, d, 3 * na * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(m->vel, d + 3 * na, 3 * na * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(m->F, d + 6 * na, 3 * na * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(m->q, d + 9 * na, na * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(m->hist, d + 10 * na, (size_t)(h.K + 1) * na * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    m->step = h.step;
+    m->head = h.head;
+    m->U = h.U;
     return SP2_OK;
 }
 

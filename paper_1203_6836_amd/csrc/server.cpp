@@ -87,7 +87,7 @@ struct Arena {
 
 // Device footprint of one request and its layout inside its arena block.
 struct Layout {
-    size_t H, X, digits, scale, part, D, q, total;
+    size_t H, X, digits, scale, part, chk, D, q, total;
 };
 Layout layout_for(int N, int slices) {
     const size_t ld = align_up((size_t)N, kTile);
@@ -99,6 +99,7 @@ Layout layout_for(int N, int slices) {
     L.digits = o; o = align_up(o + (size_t)slices * ld * ld, 256);
     L.scale = o;  o = align_up(o + ld * 8, 256);
     L.part = o;   o = align_up(o + std::max<size_t>(nt * (nt + 1) / 2, ld / 4) * 3 * 8, 256);
+    L.chk = o;    o = align_up(o + 2 * (size_t)kCheckGrid * 8, 256);
     L.D = o;      o = align_up(o + (size_t)N * N * 8, 256);
     L.q = o;      o = align_up(o + (size_t)(N / 4 + 1) * 8, 256);
     L.total = o;
@@ -268,9 +269,11 @@ sp2_status sp2_server::start_system(Request* r) {
     a.max_iter = opt.max_iter;
     a.fp64_head = 0;
     a.mixed = 1;
-    int ns = 0;
+    double* chk = reinterpret_cast<double*>(b + r->L.chk);
+    int ns = 0, nchk = 0;
+    if (launch_check_h(H, N, chk, &nchk, stream) != hipSuccess) return SP2_EDEVICE;
     if (launch_gershgorin(H, N, part, &ns, stream) != hipSuccess) return SP2_EDEVICE;
-    if (launch_bounds(part, ns, st, stream) != hipSuccess) return SP2_EDEVICE;
+    if (launch_bounds(part, ns, chk, nchk, st, stream) != hipSuccess) return SP2_EDEVICE;
     if (launch_init(H, N, ld, X0, st, part, &ns, stream) != hipSuccess) return SP2_EDEVICE;
     if (launch_ctrl_init(part, ns, st, a, stream) != hipSuccess) return SP2_EDEVICE;
     return SP2_OK;
@@ -285,7 +288,7 @@ sp2_status sp2_server::retire(std::vector<Request*>& finished) {
         double* D = reinterpret_cast<double*>(b + r->L.D);
         double* q = reinterpret_cast<double*>(b + r->L.q);
         const State& h = st_host[r->slot];
-        if (h.done != 3) {
+        if (h.done == 1 || h.done == 2) {
             if (launch_finalize(X0, X0 + (size_t)ld * ld, ld, N, D, st_dev + r->slot, stream) != hipSuccess)
                 return SP2_EDEVICE;
             if (N % 4 == 0 && launch_mulliken(D, N / 4, 4.0, q, stream) != hipSuccess) return SP2_EDEVICE;
@@ -298,7 +301,7 @@ sp2_status sp2_server::retire(std::vector<Request*>& finished) {
         sp2_stats& s = r->stats;
         std::memset(&s, 0, sizeof(s));
         s.iterations = h.iter;
-        s.status = h.done == 1 ? 0 : (h.done == 2 ? 1 : 2);
+        s.status = h.done - 1;   // 0 converged, 1 stalled, 2 max_iter, 3 gap, 4 invalid H
         s.fp64_products = h.fp64_products;
         s.head_switch = h.head_switch;
         s.eps_min = h.eps_min;
@@ -308,7 +311,7 @@ sp2_status sp2_server::retire(std::vector<Request*>& finished) {
         s.branch_bits[0] = h.bits[0];
         s.branch_bits[1] = h.bits[1];
         for (int k = 0; k < kMaxIter && k < 128; ++k) s.idem_hist[k] = (float)h.idem[k];
-        r->status = h.done == 3 ? SP2_ENOCONV : SP2_OK;
+        r->status = h.done == 3 ? SP2_ENOCONV : (h.done == 4 ? SP2_EGAP : (h.done == 5 ? SP2_EINVAL : SP2_OK));
     }
     if (!finished.empty() && hipStreamSynchronize(stream) != hipSuccess) return SP2_EDEVICE;
     const double t = now_s();

@@ -67,22 +67,78 @@ __global__ __launch_bounds__(256) void k_gershgorin(const double* __restrict__ H
     }
 }
 
+// H check: every 32 x 32 tile (bi, bj), bi <= bj, of the upper triangle is
+// compared with the transpose of tile (bj, bi) through LDS; a fixed grid of
+// workgroups strides over the tiles and keeps running maxima.
+__global__ __launch_bounds__(256) void k_check_h(const double* __restrict__ H, int N,
+                                                 double* __restrict__ out) {
+    __shared__ double A[32][33], B[32][33];
+    const int nb = (N + 31) / 32;
+    const long long T = (long long)nb * (nb + 1) / 2;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    double dmax = 0.0, amax = 0.0;
+    bool bad = false;
+    for (long long t = blockIdx.x; t < T; t += gridDim.x) {
+        // row bi of the upper triangle starts at bi nb - bi (bi - 1) / 2
+        int bi = (int)((2.0 * nb + 1.0 - sqrt((2.0 * nb + 1.0) * (2.0 * nb + 1.0) - 8.0 * (double)t)) / 2.0);
+        bi = max(0, min(bi, nb - 1));
+        while (bi > 0 && (long long)bi * nb - (long long)bi * (bi - 1) / 2 > t) --bi;
+        while (bi + 1 < nb && (long long)(bi + 1) * nb - (long long)(bi + 1) * bi / 2 <= t) ++bi;
+        const int bj = bi + (int)(t - ((long long)bi * nb - (long long)bi * (bi - 1) / 2));
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = bi * 32 + r, j = bj * 32 + tx;      // tile (bi, bj)
+            const int i2 = bj * 32 + r, j2 = bi * 32 + tx;    // tile (bj, bi)
+            A[r][tx] = (i < N && j < N) ? H[(size_t)i * N + j] : 0.0;
+            B[r][tx] = (i2 < N && j2 < N) ? H[(size_t)i2 * N + j2] : 0.0;
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const double a = A[r][tx], b = B[tx][r];          // H_ij and H_ji
+            if (!isfinite(a) || !isfinite(b)) bad = true;
+            else {
+                dmax = fmax(dmax, fabs(a - b));
+                amax = fmax(amax, fabs(a));
+            }
+        }
+    }
+    dmax = wave_max(bad ? INFINITY : dmax);
+    amax = wave_max(amax);
+    __shared__ double sd[4], sa[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sd[w] = dmax; sa[w] = amax; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x + 0] = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
+        out[2 * blockIdx.x + 1] = fmax(fmax(sa[0], sa[1]), fmax(sa[2], sa[3]));
+    }
+}
+
 __global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ part, int nslots,
+                                                const double* __restrict__ chk, int nchk,
                                                 State* __restrict__ st) {
-    double lo = 1.0e300, hi = -1.0e300;
+    double lo = 1.0e300, hi = -1.0e300, dmax = 0.0, amax = 0.0;
     for (int k = threadIdx.x; k < nslots; k += 256) {
         lo = fmin(lo, part[2 * k]);
         hi = fmax(hi, part[2 * k + 1]);
     }
+    for (int k = threadIdx.x; k < nchk; k += 256) {
+        dmax = fmax(dmax, chk[2 * k]);
+        amax = fmax(amax, chk[2 * k + 1]);
+    }
     lo = wave_min(lo);
     hi = wave_max(hi);
-    __shared__ double sl[4], sh[4];
+    dmax = wave_max(dmax);
+    amax = wave_max(amax);
+    __shared__ double sl[4], sh[4], sd[4], sa[4];
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { sl[w] = lo; sh[w] = hi; }
+    if ((threadIdx.x & 63) == 0) { sl[w] = lo; sh[w] = hi; sd[w] = dmax; sa[w] = amax; }
     __syncthreads();
     if (threadIdx.x == 0) {
         st->eps_min = fmin(fmin(sl[0], sl[1]), fmin(sl[2], sl[3]));
         st->eps_max = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+        const double d = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
+        const double m = fmax(fmax(sa[0], sa[1]), fmax(sa[2], sa[3]));
         st->t1 = st->t2 = 0.0;
         st->fill_min = 1.0;
         st->fill_max = 0.0;
@@ -97,6 +153,8 @@ __global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ part,
         st->head_switch = -1;
         st->tail_left = 0;
         st->kept = 0ull;
+        if (!(d <= kSymTol * m)) st->done = 5;                          // also catches NaN / inf
+        else if (!(st->eps_max > st->eps_min)) st->done = 4;            // H = c I: no gap anywhere
     }
     for (int k = threadIdx.x; k < kMaxIter; k += 256) {
         st->idem[k] = 0.0;
@@ -216,14 +274,17 @@ __device__ __forceinline__ void ctrl_step_body(const double* __restrict__ part, 
     const bool stall = n >= 4 && e >= st->idem[n - 2] && e < a.stall_tol;
     // BF16X2 runs its own schedule: a stall of the BF16 stage starts a fixed
     // FP32 tail instead of stopping
+    // a projector whose trace is not n_occ could not pick the occupied set:
+    // the Fermi level is degenerate (done = 4)
+    const int gap_or = fabs(st->t1 - a.n_occ) > 0.5 ? 4 : 0;
     if (e < a.idem_tol || (stall && a.mixed != 2)) {
-        st->done = (e < a.idem_tol) ? 1 : 2;
+        st->done = gap_or ? gap_or : ((e < a.idem_tol) ? 1 : 2);
         st->result = st->cur;
         clear_bit(st, n);
         return;
     }
     if (n + 1 >= a.max_iter) {
-        st->done = 3;
+        st->done = (a.max_iter >= kGapMinIter && e >= kGapIdem) ? 4 : 3;
         st->result = 1 - st->cur;
         return;
     }
@@ -231,7 +292,7 @@ __device__ __forceinline__ void ctrl_step_body(const double* __restrict__ part, 
         // tail product: its update X_{n+1} is applied; after fp32_tail of them, stop
         st->tail_left -= 1;
         if (st->tail_left <= 0) {
-            st->done = 2;
+            st->done = fabs(r[0] - a.n_occ) > 0.5 ? 4 : 2;
             st->result = 1 - st->cur;
             st->t1 = r[0];
             st->t2 = r[1];
@@ -240,7 +301,7 @@ __device__ __forceinline__ void ctrl_step_body(const double* __restrict__ part, 
     }
     if (a.mixed == 2 && st->phase == 1 && stall) {
         if (a.fp32_tail <= 0) {
-            st->done = 2;
+            st->done = gap_or ? gap_or : 2;
             st->result = st->cur;
             clear_bit(st, n);
             return;
@@ -527,8 +588,15 @@ hipError_t launch_gershgorin(const double* H, int N, double* part, int* nslots, 
     hipLaunchKernelGGL(k_gershgorin, dim3(g), dim3(256), 0, s, H, N, part);
     return hipGetLastError();
 }
-hipError_t launch_bounds(const double* part, int nslots, State* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_bounds, dim3(1), dim3(256), 0, s, part, nslots, st);
+hipError_t launch_check_h(const double* H, int N, double* out, int* nout, hipStream_t s) {
+    const long long nb = (N + 31) / 32;
+    const int g = (int)std::min<long long>(nb * (nb + 1) / 2, kCheckGrid);
+    *nout = g;
+    hipLaunchKernelGGL(k_check_h, dim3(g), dim3(256), 0, s, H, N, out);
+    return hipGetLastError();
+}
+hipError_t launch_bounds(const double* part, int nslots, const double* chk, int nchk, State* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_bounds, dim3(1), dim3(256), 0, s, part, nslots, chk, nchk, st);
     return hipGetLastError();
 }
 hipError_t launch_init(const double* H, int N, int ld, double* X0, State* st, double* part,

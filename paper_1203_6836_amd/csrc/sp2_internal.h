@@ -23,7 +23,8 @@ struct State {
     unsigned long long bits[2]; // branch of each applied update
     int iter;                   // products formed so far
     int branch;                 // branch of the next update (0: X^2, 1: 2X - X^2)
-    int done;                   // 0 running, 1 converged, 2 stalled, 3 max_iter
+    int done;                   // 0 running, 1 converged, 2 stalled, 3 max_iter,
+                                // 4 no resolvable gap at mu, 5 H not finite and symmetric
     int cur;                    // X buffer (0/1) holding X_n
     int result;                 // X buffer holding D once done
     int phase;                  // 0: FP64 products, 1: reduced-precision products, 2: FP32 tail
@@ -135,9 +136,23 @@ __device__ __forceinline__ void tile_of_block(int w, int nt, int& bi, int& bj) {
     bi = bj = 0;   // unreachable for w < T
 }
 
+// Reading of a degenerate Fermi level: an idempotent X_n whose trace is not
+// n_occ, or >= kGapMinIter products without convergence and an idempotency
+// error still >= kGapIdem, or eps_max == eps_min, ends the solve with done = 4.
+constexpr double kGapIdem = 1.0 / 16.0;
+constexpr int kGapMinIter = 100;
+// H must be finite and symmetric to within kSymTol * max |H_ij|.
+constexpr double kSymTol = 1e-12;
+constexpr int kCheckGrid = 1024;   // workgroups (and partial pairs) of the H check
+
 // ---- launchers (sp2_dense.hip) ----
 hipError_t launch_gershgorin(const double* H, int N, double* part, int* nslots, hipStream_t s);
-hipError_t launch_bounds(const double* part, int nslots, State* st, hipStream_t s);
+// out[2 b] = max |H_ij - H_ji| (+inf if a non-finite entry was seen),
+// out[2 b + 1] = max |H_ij| over the 32 x 32 tile pairs of workgroup b.
+hipError_t launch_check_h(const double* H, int N, double* out, int* nout, hipStream_t s);
+// Resets the state, sets the Gershgorin bounds and flags an invalid H (done = 5)
+// or a flat spectrum (done = 4).
+hipError_t launch_bounds(const double* part, int nslots, const double* chk, int nchk, State* st, hipStream_t s);
 hipError_t launch_init(const double* H, int N, int ld, double* X0, State* st, double* part,
                        int* nslots, hipStream_t s);
 hipError_t launch_ctrl_init(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);

@@ -105,3 +105,24 @@ def test_server_poisson_stream(ctx):
     say(f"  {rep}")
     assert all(st["status"] in ("converged", "stalled") for _, _, st in res)
     assert rep["solves_per_s"] > 0
+
+
+def test_server_reports_gap_and_invalid_h(ctx):
+    import paper_1203_6836_amd as p
+    say("case serving: degenerate and invalid H next to a good one")
+    good = request_H(40, 1000)
+    degenerate = np.diag([-1.0, 0.0, 0.0, 1.0])
+    asym = good.copy()
+    asym[3, 100] += 1e-6
+    srv = p.Server(ctx, max_slots=4)
+    tg = srv.sp2_server_submit(good, 80)
+    td = srv.sp2_server_submit(degenerate, 2)
+    ta = srv.sp2_server_submit(asym, 80)
+    D, q, st = srv.sp2_server_wait(tg, good.shape[0])
+    for t, N, want in ((td, 4, p.SP2_EGAP), (ta, good.shape[0], p.SP2_EINVAL)):
+        with pytest.raises(p.Sp2Error) as ei:
+            srv.sp2_server_wait(t, N)
+        assert ei.value.status == want
+    srv.close()
+    ref = osp2.sp2(good, 80)
+    assert np.linalg.norm(D - ref.D) / np.sqrt(good.shape[0]) <= 1e-6

@@ -154,3 +154,56 @@ def test_fp64_full_size_properties(ctx):
     pos = w.positions()
     Href = otb.hamiltonian0(pos[:64], synth.STATIC_MODEL)
     np.testing.assert_allclose(H[:256, :256].cpu().numpy(), Href, atol=1e-14)
+
+
+def degenerate_cases():
+    two_atoms = otb.hamiltonian(np.array([[0.0, 0.0, 0.0], [10.0, 0.0, 0.0]]), None, synth.STATIC_MODEL)
+    return [(two_atoms, 3), (np.diag([-1.0, 0.0, 0.0, 1.0]), 2), (3.0 * np.eye(4), 2),
+            (np.diag([0.0, 1e-13, 2.0]), 1)]
+
+
+def test_gap_reported_like_the_oracle(ctx):
+    import paper_1203_6836_amd as p
+    say("case degenerate Fermi level -> SP2_EGAP (fp64, int8x)")
+    for H, nocc in degenerate_cases():
+        assert osp2.sp2(H, nocc).status == "gap"
+        for prec in ("fp64", "int8x"):
+            st, stats = ctx.sp2_density_matrix_status(to_dev(H), nocc, p.options(prec))
+            assert st == p.SP2_EGAP and stats["status"] == "gap", (H.shape, prec, st, stats["status"])
+    # a short budget on the same degenerate pair is ENOCONV, as in the oracle
+    H, nocc = degenerate_cases()[1]
+    assert osp2.sp2(H, nocc, max_iter=20).status == "max_iter"
+    st, stats = ctx.sp2_density_matrix_status(to_dev(H), nocc, p.options("fp64", max_iter=20))
+    assert st == p.SP2_ENOCONV and stats["status"] == "max_iter"
+
+
+def test_invalid_hamiltonian_rejected(ctx):
+    import paper_1203_6836_amd as p
+    say("case H not symmetric / not finite -> SP2_EINVAL")
+    pos = synth.lattice_positions((3, 3, 2), seed=4)
+    H = otb.hamiltonian(pos, None, synth.STATIC_MODEL)
+    nocc = len(pos) * 2
+    scale = np.abs(H).max()
+    ok = H.copy()
+    ok[0, 5] += 1e-14 * scale                       # within 1e-12 max|H|: accepted
+    asym = H.copy()
+    asym[7, 40] += 1e-9 * scale
+    nan = H.copy()
+    nan[3, 3] = np.nan
+    inf = H.copy()
+    inf[10, 60] = inf[60, 10] = np.inf
+    for prec in ("fp64", "int8x"):
+        st, stats = ctx.sp2_density_matrix_status(to_dev(ok), nocc, p.options(prec))
+        assert st == p.SP2_OK, prec
+        for bad in (asym, nan, inf):
+            st, stats = ctx.sp2_density_matrix_status(to_dev(bad), nocc, p.options(prec))
+            assert st == p.SP2_EINVAL and stats["status"] == "invalid", (prec, st)
+            assert stats["iterations"] == 0
+    # ragged N (not a multiple of the 32 x 32 check tile) and a large N
+    H5 = otb.hamiltonian(synth.lattice_positions((5, 5, 3), seed=9), None, synth.STATIC_MODEL)   # N = 300
+    bad5 = H5.copy()
+    bad5[299, 0] += 1e-6
+    st, _ = ctx.sp2_density_matrix_status(to_dev(bad5), 150, p.options("fp64"))
+    assert st == p.SP2_EINVAL
+    st, _ = ctx.sp2_density_matrix_status(to_dev(H5), 150, p.options("fp64"))
+    assert st == p.SP2_OK

@@ -90,3 +90,70 @@ def test_xlbomd_1024_atoms_200_steps(ctx, prec):
     assert n >= 40
     assert qn < 1e-2
     assert np.ptp(et) < 0.01 * (ek.max() - ek.min() + 1.0)
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("with_n", [False, True])
+def test_qmd_evaluate_matches_oracle(ctx, with_n):
+    import paper_1203_6836_amd as p
+    from oracle import observables
+    say(f"case qmd_evaluate 3x3x2 n_aux={'random' if with_n else 'none'}")
+    m = synth.MD_MODEL
+    pos = synth.lattice_positions((3, 3, 2), seed=4)
+    nat = len(pos)
+    n = np.random.default_rng(7).normal(0.0, 0.1, nat) if with_n else np.zeros(nat)
+    ref = oxl.evaluate(pos, n, m, 2 * nat, solver="jacobi")
+    q, eb, ep, F, st = ctx.qmd_evaluate(m, to_dev(pos), to_dev(n) if with_n else None, 2 * nat,
+                                        p.options("fp64"))
+    assert st["status"] == "converged"
+    np.testing.assert_allclose(q.cpu().numpy(), ref["q"], atol=1e-9)
+    assert eb == pytest.approx(observables.band_energy(ref["D"], ref["H"]), abs=1e-8)
+    assert ep == pytest.approx(ref["U"], abs=1e-8)
+    np.testing.assert_allclose(F.cpu().numpy(), ref["F"], atol=1e-8)
+    # without forces: same charges and energies
+    q2, eb2, ep2, F2, _ = ctx.qmd_evaluate(m, to_dev(pos), to_dev(n) if with_n else None, 2 * nat,
+                                           p.options("fp64"), want_forces=False)
+    assert F2 is None and eb2 == eb and ep2 == ep
+    assert float((q2 - q).abs().max()) == 0.0
+
+
+def test_checkpoint_resume_is_bit_identical(ctx):
+    import paper_1203_6836_amd as p
+    say("case xlbomd checkpoint / resume 3x3x2")
+    m = synth.MD_MODEL
+    pos = synth.lattice_positions((3, 3, 2), seed=4)
+    nat = len(pos)
+    vel = synth.maxwell_velocities(nat, 300.0, m.mass, seed=11)
+    md = ctx.xlbomd_create(m, pos, vel, None, sp2_opts=p.options("fp64"), scf_beta=0.3, scf_tol=1e-11,
+                           scf_max_iter=500)
+    md.xlbomd_run(5)
+    ck = md.xlbomd_get_state()
+    a = md.xlbomd_run(7)
+    xa = md.xlbomd_get()
+    md.xlbomd_set_state(ck)                      # rewind in place
+    b = md.xlbomd_run(7)
+    xb = md.xlbomd_get()
+    # a second integrator (other start, no SCF) resumed from the checkpoint
+    md2 = ctx.xlbomd_create(m, pos + 0.05, np.zeros_like(vel), np.zeros(nat), sp2_opts=p.options("fp64"),
+                            scf_max_iter=0)
+    md2.xlbomd_set_state(ck)
+    c = md2.xlbomd_run(7)
+    xc = md2.xlbomd_get()
+    assert a == b == c
+    for u, v, w in zip(xa, xb, xc):
+        assert np.array_equal(u, v) and np.array_equal(u, w)
+    # checkpoints of another size, corrupt or truncated ones are refused
+    md3 = ctx.xlbomd_create(m, pos[:10], vel[:10], np.zeros(10), sp2_opts=p.options("fp64"), scf_max_iter=0)
+    for bad in (ck[:-8], b"XXXX" + ck[4:]):
+        with pytest.raises(p.Sp2Error) as ei:
+            md2.xlbomd_set_state(bad)
+        assert ei.value.status == p.SP2_EINVAL
+    with pytest.raises(p.Sp2Error) as ei:
+        md3.xlbomd_set_state(ck)
+    assert ei.value.status == p.SP2_EINVAL
+    for h in (md, md2, md3):
+        h.close()

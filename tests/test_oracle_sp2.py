@@ -92,3 +92,26 @@ def test_thresholded_sp2_error_is_small_and_trace_kept():
     assert np.linalg.norm(t.D - d.D) / np.sqrt(H.shape[0]) < 1e-3
     assert abs(np.trace(t.D) - w.n_occ) < 1e-3
     assert t.fill[0] < 1.0
+
+
+def test_degenerate_fermi_level_is_reported_as_gap():
+    """The definition (Jacobi + aufbau) sees a zero gap in each case; SP2 must
+    say "gap" in each of the ways it can show one, and nothing else may."""
+    # two atoms beyond the hopping range: H diagonal, p levels six-fold at mu;
+    # X_0 is already a projector, of rank 2 instead of 3
+    H = tb.hamiltonian(np.array([[0.0, 0.0, 0.0], [10.0, 0.0, 0.0]]), None, synth.STATIC_MODEL)
+    assert eig.density_matrix(H, 3)[2] == 0.0
+    assert sp2.sp2(H, 3).status == "gap"
+    # a degenerate pair at mu is held near 1/2 by the trace rule
+    H2 = np.diag([-1.0, 0.0, 0.0, 1.0])
+    assert eig.density_matrix(H2, 2)[2] == 0.0
+    r = sp2.sp2(H2, 2)
+    assert r.status == "gap" and r.iterations == 100 and r.idem[-1] >= 1.0 / 16.0
+    assert sp2.sp2(H2, 2, max_iter=20).status == "max_iter"     # a short budget is not a gap
+    assert sp2.sp2(3.0 * np.eye(4), 2).status == "gap"            # flat spectrum
+    # a split of 1e-13 eV on a 2 eV range is below what the products resolve
+    assert sp2.sp2(np.diag([0.0, 1e-13, 2.0]), 1).status == "gap"
+    # the same spectrum with a gap converges to the aufbau projector
+    r3 = sp2.sp2(np.diag([-1.0, 0.0, 0.5, 1.0]), 2)
+    assert r3.status == "converged"
+    np.testing.assert_allclose(r3.D, np.diag([1.0, 1.0, 0.0, 0.0]), atol=1e-10)
