@@ -229,7 +229,11 @@ sp2_status xlbomd_get(xlbomd *md, double *xyz_host, double *vel_host,
 /* Checkpoint: the complete integrator state (positions, velocities, forces,
  * charges q, the K + 1 auxiliary-charge history of Eq. Verl_n, step count)
  * as a versioned byte image in caller memory.  With buf NULL, *bytes is set
- * to the size needed; a smaller *bytes gives SP2_EINVAL (and the size). */
+ * to the size needed; a smaller *bytes gives SP2_EINVAL (and the size).
+ * Layout (version 1, native byte order): a 40-byte header {uint32 magic
+ * 'XLBS', uint32 version, int32 n_atoms, int32 K, int64 step, int32 head,
+ * int32 pad, double U}, then FP64 arrays xyz[3 n_atoms], vel[3 n_atoms],
+ * F[3 n_atoms], q[n_atoms], n history[(K + 1) n_atoms] (slot `head` is n_t). */
 sp2_status xlbomd_get_state(const xlbomd *md, void *buf, size_t *bytes);
 /* Resume from a checkpoint of an integrator with the same n_atoms and K;
  * continuing is then bit-identical to continuing the original. */

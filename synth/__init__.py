@@ -61,11 +61,15 @@ class TBModel:
 
 # Static configurations use the literal hard cut-off at 4 A; molecular
 # dynamics uses the smooth tail on [3.5, 4.0] A so the energy is continuous,
-# and a pair repulsion whose force at the lattice spacing (A / rho = 100 eV/A)
-# balances the nearest-neighbour attraction of the +-4 e ions of the
-# charge-ordered ground state of this gamma (16 k_e / 1.5^2 = 102 eV/A).
+# and a pair repulsion.  With gamma_ij = k_e / r the self-consistent charges
+# order to +-4 e, so the repulsion must hold a +-4 e pair apart against a
+# Coulomb attraction that diverges at r -> 0: with rho = 0.3 A no amplitude
+# does both (at the zero-virial amplitude the pair energy falls all the way
+# to r -> 0), while rho = 0.15 A puts a wall near 1 A.  The amplitude is the
+# one for which the self-consistent unjittered 4 x 4 x 4 lattice has zero
+# mean virial (computed by oracle/calibrate_pair.py).
 STATIC_MODEL = TBModel()
-MD_MODEL = TBModel(r_tail=3.5, pair_a=30.0)
+MD_MODEL = TBModel(r_tail=3.5, pair_a=5.605396, pair_rho=0.15)
 
 
 def lattice_positions(dims, spacing: float = 1.5, jitter: float = 0.1,

@@ -111,3 +111,33 @@ def test_energy_error_scales_as_dt_squared():
         dev.append(np.max(np.abs(et - e0)))
         assert max(r["max_q_minus_n"] for r in log) < 1e-2   # n follows q without SCF
     assert dev[0] / dev[1] == pytest.approx(4.0, rel=0.25)
+
+
+def test_md_pair_amplitude_zeroes_the_virial():
+    """The frozen pair amplitude of the MD model is the zero-virial one."""
+    from oracle.calibrate_pair import virial_at, zero_virial_amplitude
+    m = synth.MD_MODEL
+    A, w0, q = zero_virial_amplitude(m)
+    assert A == pytest.approx(m.pair_a, abs=1e-5)
+    pos = synth.lattice_positions((4, 4, 4), jitter=0.0, seed=0)
+    assert abs(virial_at(pos, q, m, 2 * len(pos), m.pair_a)) < 1e-5 * abs(w0)
+    # the charge-ordered state this balances: +-4 e on the two sublattices
+    assert np.allclose(np.abs(q), 4.0, atol=0.05)
+
+
+def test_pair_repulsion_walls_off_ion_collapse():
+    """A +-4 e pair: with rho = 0.15 A the energy rises again below ~1 A; with
+    rho = 0.3 A at its own zero-virial amplitude it falls all the way in."""
+    from oracle.calibrate_pair import zero_virial_amplitude
+    k = synth.COULOMB_EV_A * 16.0
+
+    def pair(m, r):
+        return float(tb.pair_phi(np.array([r]), m)[0][0]) - k / r
+
+    m = synth.MD_MODEL
+    assert pair(m, 0.9) > pair(m, 1.5) and pair(m, 0.7) > pair(m, 0.9)
+    soft = m.with_(pair_rho=0.3)
+    soft = soft.with_(pair_a=zero_virial_amplitude(soft)[0])
+    rs = np.linspace(0.2, 1.5, 27)
+    e = np.array([pair(soft, r) for r in rs])
+    assert np.all(np.diff(e) > 0)            # monotonic: no barrier anywhere
