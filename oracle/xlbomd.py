@@ -42,6 +42,7 @@ class XLOptions:
     c: tuple = K5_C
     solver: str = "sp2"           # "sp2" or "jacobi"
     sp2_tol: float = 1e-10
+    check_stability: bool = False  # refuse kappa outside the stability bound at t = 0
 
 
 def density(H, n_occ, solver="sp2", tol=1e-10):
@@ -99,9 +100,47 @@ class XLState:
     step: int = 0
 
 
+def charge_response(pos, n, m, n_occ, h=1e-5, solver="sp2"):
+    """J = dq/dn at (R, n): the Mulliken charges of theta(mu0 I - H[n]) by
+    central differences in each n_k (2 n_atoms density matrices)."""
+    nat = len(pos)
+    J = np.zeros((nat, nat))
+    for k in range(nat):
+        e = np.zeros(nat)
+        e[k] = h
+        qp = observables.mulliken(density(tb.hamiltonian(pos, n + e, m), n_occ, solver), m.z_val)
+        qm = observables.mulliken(density(tb.hamiltonian(pos, n - e, m), n_occ, solver), m.z_val)
+        J[:, k] = (qp - qm) / (2.0 * h)
+    return J
+
+
+def stability_bound(J):
+    """Largest kappa for which the undamped auxiliary-charge step
+    n_{t+1} = 2 n_t - n_{t-1} + kappa (q[n_t] - n_t) is stable about a fixed
+    point (Eq. Verl_n without dissipation, linearised): along an eigenvector
+    of I - J with eigenvalue mu the step is z^2 - (2 - kappa mu) z + 1 = 0,
+    whose roots stay on the unit circle iff 0 <= kappa mu <= 4.  Returns
+    4 / max mu (0 if some mu < 0: no kappa is stable)."""
+    mu = np.linalg.eigvals(np.eye(len(J)) - J).real
+    if mu.min() < 0.0:
+        return 0.0
+    return 4.0 / mu.max()
+
+
+def check_stability(pos, n, m, n_occ, kappa, solver="sp2"):
+    """Raise ValueError when kappa is not below the stability bound at (R, n)."""
+    bound = stability_bound(charge_response(pos, n, m, n_occ, solver=solver))
+    if not kappa < bound:
+        raise ValueError(f"kappa = {kappa} is outside the stability bound {bound:.4g} of the "
+                         "auxiliary-charge integration")
+    return bound
+
+
 def init_state(pos, vel, m, n_occ, opts: XLOptions, n0):
     """State at t = 0 with n_{-k dt} = n0 for all k (n0 = SCF charges)."""
     n0 = np.array(n0, dtype=np.float64)
+    if opts.check_stability:
+        check_stability(pos, n0, m, n_occ, opts.kappa, opts.solver)
     ev = evaluate(pos, n0, m, n_occ, opts.solver, opts.sp2_tol)
     hist = [n0.copy() for _ in range(len(opts.c))]
     return XLState(pos.copy(), vel.copy(), hist, ev["q"], ev["F"], ev["U"])

@@ -141,3 +141,28 @@ def test_pair_repulsion_walls_off_ion_collapse():
     rs = np.linspace(0.2, 1.5, 27)
     e = np.array([pair(soft, r) for r in rs])
     assert np.all(np.diff(e) > 0)            # monotonic: no barrier anywhere
+
+
+def test_stability_bound_of_the_charge_integration():
+    """J = dq/dn by finite differences; the undamped Verlet step for n is
+    stable for kappa < 4 / max eig(I - J)."""
+    dims = (4, 4, 4)
+    pos = synth.lattice_positions(dims, seed=21)
+    m = synth.MD_MODEL
+    q, _ = xlbomd.scf(pos, m, 128, beta=1.0, tol=1e-11, n0=synth.checkerboard_charges(dims))
+    # no charge coupling: H does not depend on n, J = 0 and the bound is the
+    # free-oscillator limit kappa < 4
+    J0 = xlbomd.charge_response(pos, q, m.with_(hubbard_u=0.0, coulomb_k=0.0), 128)
+    assert np.abs(J0).max() == 0.0 and xlbomd.stability_bound(J0) == 4.0
+    # the scalar case reproduces the root condition of z^2 - (2 - kappa mu) z + 1
+    assert xlbomd.stability_bound(np.array([[-1.0]])) == pytest.approx(2.0)
+    assert xlbomd.stability_bound(np.array([[1.5]])) == 0.0
+    # the charge-ordered state: a small response, kappa = 0.91 well inside
+    bound = xlbomd.check_stability(pos, q, m, 128, 0.91)
+    assert 3.5 < bound <= 4.0
+    # a large on-site U (metallic charge response) leaves almost no room
+    with pytest.raises(ValueError):
+        xlbomd.check_stability(pos, np.zeros(64), m.with_(hubbard_u=40.0), 128, 0.91)
+    opts = xlbomd.XLOptions(check_stability=True)
+    with pytest.raises(ValueError):
+        xlbomd.init_state(pos, np.zeros((64, 3)), m.with_(hubbard_u=40.0), 128, opts, np.zeros(64))
