@@ -219,6 +219,10 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
         if ((s = (sp2_status)split_reserve(c->split, ld, int8x ? o.slices : 0, bf16x)) != SP2_OK)
             return fail(c, SP2_ENOMEM, "device allocation for split operands failed");
     }
+    // int8 products from the first one on, no threshold: the products write
+    // their upper tiles only and the encode reads the upper triangle
+    const bool upper = int8x && o.tau == 0.0 && o.fp64_head == 0;
+    c->split.upper = upper;
 
     CtrlArgs a;
     a.n_occ = (double)n_occ;
@@ -244,7 +248,7 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     HIPCHK(c, launch_check_h(H, N, c->chk, &nchk, st));
     HIPCHK(c, launch_gershgorin(H, N, c->part, &ns, st));
     HIPCHK(c, launch_bounds(c->part, ns, c->chk, nchk, c->st, st));
-    HIPCHK(c, launch_init(H, N, ld, buf0, c->st, c->part, &ns, st));
+    HIPCHK(c, launch_init(H, N, ld, buf0, c->st, c->part, &ns, st, upper ? c->split.rmax : nullptr));
     if (o.tau > 0.0) HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 1, st, env));
     HIPCHK(c, launch_ctrl_init(c->part, ns, c->st, a, st));
 
@@ -277,7 +281,9 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     }
     (void)finished;
     const State& h = *c->st_host;
-    if (h.done == 1 || h.done == 2) HIPCHK(c, launch_finalize(buf0, buf1, ld, N, D, c->st, st));
+    if (h.done == 1 || h.done == 2)
+        HIPCHK(c, upper ? launch_finalize_upper(buf0, buf1, ld, N, D, c->st, st)
+                        : launch_finalize(buf0, buf1, ld, N, D, c->st, st));
     HIPCHK(c, hipEventRecord(c->ev1, st));
     HIPCHK(c, hipEventSynchronize(c->ev1));
     float ms = 0.f;

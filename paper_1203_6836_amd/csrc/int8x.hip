@@ -162,6 +162,88 @@ __global__ __launch_bounds__(256) void k_encode_int8_reg(const double* __restric
     }
 }
 
+// Upper-triangle encode.  When the products write only their upper tiles
+// (upper-only mode), X_n is valid on and above the diagonal and rmax[i]
+// holds max_j |X_ij| as a bit pattern (accumulated by the product that wrote
+// X_n).  One workgroup per 32 x 32 block (I, J), I <= J: the block is read
+// once and written as digit block (I, J) with the scales of rows I and, read
+// back transposed from LDS, as digit block (J, I) with the scales of rows J.
+// Same digits as encode_row (same scale, same per-element arithmetic).  The
+// diagonal blocks also write the row scales and clear rmax_next, which the
+// next product fills.
+__device__ __forceinline__ void pack_digits4(const double (&x)[4], double inv, int S, int8_t* __restrict__ out,
+                                             size_t plane) {
+    double y[4] = {x[0] * inv, x[1] * inv, x[2] * inv, x[3] * inv};
+    for (int t = 0; t < S; ++t) {
+        const double wt = ldexp(1.0, 6 + 7 * t);
+        const double iw = ldexp(1.0, -(6 + 7 * t));
+        uint32_t packed = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double d = rint(y[q] * wt);
+            y[q] -= d * iw;
+            packed |= (uint32_t)(uint8_t)(int8_t)d << (8 * q);
+        }
+        *reinterpret_cast<uint32_t*>(out + t * plane) = packed;
+    }
+}
+
+__device__ __forceinline__ double scale_inv(unsigned long long bits, double* s_out) {
+    const double m = __longlong_as_double((long long)bits);
+    int e = 0;
+    if (m > 0.0) (void)frexp(m, &e);
+    if (s_out) *s_out = ldexp(1.0, e);
+    return ldexp(1.0, -e);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_encode_int8_upper(const double* __restrict__ buf0,
+                                                           const double* __restrict__ buf1, int ld,
+                                                           const State* __restrict__ st,
+                                                           int8_t* __restrict__ digits,
+                                                           double* __restrict__ scale,
+                                                           unsigned long long* __restrict__ rmax) {
+    if (st->done || st->phase != 1) return;
+    const double* __restrict__ X = st->cur ? buf1 : buf0;
+    const unsigned long long* __restrict__ rm = rmax + (size_t)st->cur * ld;
+    unsigned long long* __restrict__ rm_next = rmax + (size_t)(1 - st->cur) * ld;
+    const int nb = ld >> 5;
+    // block (I, J) of the upper triangle, row-major over I
+    const int t = blockIdx.x;
+    int I = (int)((2.0 * nb + 1.0 - sqrt((2.0 * nb + 1.0) * (2.0 * nb + 1.0) - 8.0 * (double)t)) / 2.0);
+    I = max(0, min(I, nb - 1));
+    while (I > 0 && I * nb - I * (I - 1) / 2 > t) --I;
+    while (I + 1 < nb && (I + 1) * nb - (I + 1) * I / 2 <= t) ++I;
+    const int J = I + (t - (I * nb - I * (I - 1) / 2));
+    const int tid = threadIdx.x;
+    const int r = tid >> 3, c0 = (tid & 7) * 4;
+    const size_t plane = (size_t)ld * ld;
+    const double4 v = *reinterpret_cast<const double4*>(X + (size_t)(I * 32 + r) * ld + J * 32 + c0);
+    const double x[4] = {v.x, v.y, v.z, v.w};
+    double sc;
+    const double inv = scale_inv(rm[I * 32 + r], &sc);
+    pack_digits4(x, inv, S, digits + ((size_t)I * nb + J) * 1024 + r * 32 + 16 * ((c0 >> 4) ^ dswz(r)) + (c0 & 15),
+                 plane);
+    if (I == J) {
+        if ((tid & 7) == 0) {
+            scale[I * 32 + r] = sc;
+            rm_next[I * 32 + r] = 0ull;
+        }
+        return;
+    }
+    __shared__ double T[32][33];
+    T[r][c0] = x[0];
+    T[r][c0 + 1] = x[1];
+    T[r][c0 + 2] = x[2];
+    T[r][c0 + 3] = x[3];
+    __syncthreads();
+    // row J*32 + r of X, columns I*32 + c0 .. + 3 = column r of the block, rows c0 ..
+    const double xt[4] = {T[c0][r], T[c0 + 1][r], T[c0 + 2][r], T[c0 + 3][r]};
+    const double invt = scale_inv(rm[J * 32 + r], nullptr);
+    pack_digits4(xt, invt, S, digits + ((size_t)J * nb + I) * 1024 + r * 32 + 16 * ((c0 >> 4) ^ dswz(r)) + (c0 & 15),
+                 plane);
+}
+
 // Grouped: work item = 4 rows of one system; fixed grid, grid-stride loop.
 template <int S>
 __global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __restrict__ g) {
@@ -209,16 +291,23 @@ struct I8Smem {
     union {
         int8_t buf[I8_NST][2 * S * 4][1024];   // [stage][op * S * 4 + slice * 4 + row block][block]
         double tr[64][TR_LD];                  // [tile column (one half)][tile row]
+        struct {
+            unsigned long long rm[128], cm[128];   // tile row / column maxima (upper-only mode)
+        } mx;
     };
 };
 
 // One 128 x 128 output tile (bi, bj) of one system; all 512 threads of the
-// workgroup take part (the body contains barriers).
-template <int S, bool THR>
+// workgroup take part (the body contains barriers).  UPPER: write the tile
+// only (no mirrored copy below the diagonal) and fold its row and column
+// maxima of |X_{n+1}| into rmax_next (bit patterns of non-negative doubles
+// order like the values, so atomicMax on them is exact and order-free).
+template <int S, bool THR, bool UPPER>
 __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1, int ld,
                            const State* __restrict__ st, const int8_t* __restrict__ digits,
                            const double* __restrict__ scale, double* __restrict__ part, int bi, int bj,
-                           I8Smem<S>& sm, const int* __restrict__ env) {
+                           I8Smem<S>& sm, const int* __restrict__ env,
+                           unsigned long long* __restrict__ rmax_next) {
     const int nt = ld / QB;
     const int t = tri_index(bi, bj, nt);
     const int i0 = bi * QB, j0 = bj * QB;
@@ -364,45 +453,89 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     }
 #endif
 
-    // epilogue: combine levels in FP64, apply the SP2 update, partials
+    // epilogue: combine levels in FP64, apply the SP2 update, partials.
+    // Partial sums are kept per column block c in row order and added at the
+    // end, the same order in both layouts (so both give identical partials).
     const int br = st->branch;
     const bool mirror = bi != bj;
-    double tr = 0.0, fro = 0.0, idm = 0.0;
+    double trc[2] = {0.0, 0.0}, froc[2] = {0.0, 0.0}, idmc[2] = {0.0, 0.0};
+    auto element = [&](int c, int r, int gi, int gj, double sj) -> double {
+        double v = 0.0;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int gj = j0 + wc * 64 + c * 32 + (lane & 31);
-        const double sj = scale[gj];
+        for (int L = S - 1; L >= 0; --L) v += ldexp((double)acc[L][c][r], -(12 + 7 * L));
+        const double p = v * scale[gi] * sj;
+        const double x = Xc[(size_t)gi * ld + gj];
+        const double xn = br ? 2.0 * x - p : p;
+        Xn[(size_t)gi * ld + gj] = xn;
+        if (gi == gj) trc[c] += xn;
+        froc[c] += xn * xn;
+        idmc[c] += (p - x) * (p - x);
+        return xn;
+    };
+    // v_mfma_i32_32x32x32_i8 result: lane l, element r is row 8 (r/4) + 4 (l/32) + r%4, column l%32
+    auto row_of = [&](int r) { return i0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); };
+    if (UPPER) {
+        // tile row and column maxima are combined in LDS, then one global
+        // atomic per row (and per column off the diagonal) of the tile
+        if (tid < 128) sm.mx.rm[tid] = 0ull;
+        else if (tid < 256) sm.mx.cm[tid - 128] = 0ull;
+        __syncthreads();
+        const int gj0 = j0 + wc * 64 + (lane & 31), gj1 = gj0 + 32;
+        const double sj0 = scale[gj0], sj1 = scale[gj1];
+        double cmx0 = 0.0, cmx1 = 0.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            // v_mfma_i32_32x32x32_i8 result: lane l, element r is row 8 (r/4) + 4 (l/32) + r%4, column l%32
-            const int gi = i0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            double v = 0.0;
-#pragma unroll
-            for (int L = S - 1; L >= 0; --L) v += ldexp((double)acc[L][c][r], -(12 + 7 * L));
-            const double p = v * scale[gi] * sj;
-            const double x = Xc[(size_t)gi * ld + gj];
-            const double xn = br ? 2.0 * x - p : p;
-            Xn[(size_t)gi * ld + gj] = xn;
-            if (mirror) sm.tr[wc * 32 + (lane & 31)][gi - i0] = xn;
-            if (gi == gj) tr += xn;
-            fro += xn * xn;
-            idm += (p - x) * (p - x);
+            const int gi = row_of(r);
+            const double a = fabs(element(0, r, gi, gj0, sj0));
+            const double b = fabs(element(1, r, gi, gj1, sj1));
+            cmx0 = fmax(cmx0, a);
+            cmx1 = fmax(cmx1, b);
+            // row maximum over the wave's 64 columns (32 lanes of this half)
+            double m = fmax(a, b);
+            for (int o = 16; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+            if ((lane & 31) == 0) atomicMax(&sm.mx.rm[gi - i0], (unsigned long long)__double_as_longlong(m));
         }
         if (mirror) {
-            // columns j0 + 64 wc' + 32 c + (0..31) of every wave: 64 rows of
-            // the mirrored block, 128 doubles each, written one half row per
-            // wave and instruction
-            __syncthreads();
-#pragma unroll 4
-            for (int q = 0; q < 16; ++q) {
-                const int rh = w + 8 * q;
-                const int jj = rh >> 1, col = (rh & 1) * 64 + lane;
-                const int gr = j0 + (jj >> 5) * 64 + c * 32 + (jj & 31);
-                Xn[(size_t)gr * ld + i0 + col] = sm.tr[jj][col];
+            // column maxima over the wave's 32 rows: row maxima of rows gj over
+            // these columns of their lower part (a diagonal tile is symmetric)
+            cmx0 = fmax(cmx0, __shfl_xor(cmx0, 32, 64));
+            cmx1 = fmax(cmx1, __shfl_xor(cmx1, 32, 64));
+            if (lane < 32) {
+                atomicMax(&sm.mx.cm[gj0 - j0], (unsigned long long)__double_as_longlong(cmx0));
+                atomicMax(&sm.mx.cm[gj1 - j0], (unsigned long long)__double_as_longlong(cmx1));
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        if (tid < 128) atomicMax(rmax_next + i0 + tid, sm.mx.rm[tid]);
+        else if (mirror && tid < 256) atomicMax(rmax_next + j0 + tid - 128, sm.mx.cm[tid - 128]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int gj = j0 + wc * 64 + c * 32 + (lane & 31);
+            const double sj = scale[gj];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int gi = row_of(r);
+                const double xn = element(c, r, gi, gj, sj);
+                if (mirror) sm.tr[wc * 32 + (lane & 31)][gi - i0] = xn;
+            }
+            if (mirror) {
+                // columns j0 + 64 wc' + 32 c + (0..31) of every wave: 64 rows of
+                // the mirrored block, 128 doubles each, written one half row per
+                // wave and instruction
+                __syncthreads();
+#pragma unroll 4
+                for (int q = 0; q < 16; ++q) {
+                    const int rh = w + 8 * q;
+                    const int jj = rh >> 1, col = (rh & 1) * 64 + lane;
+                    const int gr = j0 + (jj >> 5) * 64 + c * 32 + (jj & 31);
+                    Xn[(size_t)gr * ld + i0 + col] = sm.tr[jj][col];
+                }
+                __syncthreads();
+            }
         }
     }
+    double tr = trc[0] + trc[1], fro = froc[0] + froc[1], idm = idmc[0] + idmc[1];
     tr = wred_sum(tr);
     fro = wred_sum(fro);
     idm = wred_sum(idm);
@@ -425,18 +558,20 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     }
 }
 
-template <int S, bool THR>
+template <int S, bool THR, bool UPPER>
 __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
                                                     int ld, const State* __restrict__ st,
                                                     const int8_t* __restrict__ digits,
                                                     const double* __restrict__ scale,
-                                                    double* __restrict__ part, const int* __restrict__ env) {
+                                                    double* __restrict__ part, const int* __restrict__ env,
+                                                    unsigned long long* __restrict__ rmax) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
     int bi, bj;
     tile_of_block(blockIdx.x, ld / QB, bi, bj);
-    int8x_tile<S, THR>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env);
+    int8x_tile<S, THR, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
+                              UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr);
 }
 
 // Grouped: every upper-triangular tile of every system in the group; a fixed
@@ -453,12 +588,13 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __r
         int bi = 0, bj = 0, tl = item - g->tile_off[s], nt = v.ld / QB, off = 0;
         while (tl >= off + (nt - bi)) { off += nt - bi; ++bi; }
         bj = bi + (tl - off);
-        int8x_tile<S, false>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr);
+        int8x_tile<S, false, false>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr,
+                                    nullptr);
         __syncthreads();
     }
 }
 
-template <int S, bool THR>
+template <int S, bool THR, bool UPPER>
 static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                                      hipStream_t stream, const int* env) {
     const int nt = ld / QB;
@@ -466,27 +602,32 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     const size_t lds = sizeof(I8Smem<S>);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, THR>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, THR, UPPER>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_gemm_int8x<S, THR>), dim3(T), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
-                       s.scale, part, env);
+    hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER>), dim3(T), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
+                       s.scale, part, env, s.rmax);
     return hipGetLastError();
 }
 
 template <int S>
 static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                             hipStream_t stream, const int* env) {
-    if (env) return launch_tile_kernel<S, true>(s, buf0, buf1, ld, st, part, stream, env);
-    return launch_tile_kernel<S, false>(s, buf0, buf1, ld, st, part, stream, nullptr);
+    if (env) return launch_tile_kernel<S, true, false>(s, buf0, buf1, ld, st, part, stream, env);
+    if (s.upper) return launch_tile_kernel<S, false, true>(s, buf0, buf1, ld, st, part, stream, nullptr);
+    return launch_tile_kernel<S, false, false>(s, buf0, buf1, ld, st, part, stream, nullptr);
 }
 
 template <int S>
 static hipError_t run_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
                              hipStream_t stream) {
-    if (ld <= 2048 * ENC_CH)
+    if (s.upper) {
+        const int nb = ld / 32;
+        hipLaunchKernelGGL(k_encode_int8_upper<S>, dim3(nb * (nb + 1) / 2), dim3(256), 0, stream, buf0, buf1, ld,
+                           st, s.digits, s.scale, s.rmax);
+    } else if (ld <= 2048 * ENC_CH)
         hipLaunchKernelGGL(k_encode_int8_reg<S>, dim3(ld), dim3(256), 0, stream, buf0, buf1, ld, st, s.digits,
                            s.scale);
     else

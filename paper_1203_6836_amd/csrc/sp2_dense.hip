@@ -165,15 +165,16 @@ __global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ part,
 // ------------------------------------------------------------------ X_0
 // One wave per padded row.  Writes X_0 = (eps_max I - H)/(eps_max - eps_min)
 // in the N x N corner and zeros elsewhere; per-workgroup partials
-// (Tr X_0, ||X_0||_F^2, 0) into part[3 * block].
+// (Tr X_0, ||X_0||_F^2, 0) into part[3 * block]; with rmax non-null also the
+// row maxima max_j |X_0 ij| (as bit patterns) for the upper-only int8 path.
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ H, int N, int ld,
                                               double* __restrict__ X, const State* __restrict__ st,
-                                              double* __restrict__ part) {
+                                              double* __restrict__ part, unsigned long long* __restrict__ rmax) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = blockIdx.x * 4 + w;            // < ld by construction of the grid
     const double emax = st->eps_max;
     const double inv = 1.0 / (st->eps_max - st->eps_min);
-    double tr = 0.0, fro = 0.0;
+    double tr = 0.0, fro = 0.0, mx = 0.0;
     double* xrow = X + (size_t)i * ld;
     if (i < N) {
         const double* hrow = H + (size_t)i * N;
@@ -185,9 +186,14 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ H, int 
             }
             xrow[j] = x;
             fro += x * x;
+            mx = fmax(mx, fabs(x));
         }
     } else {
         for (int j = lane; j < ld; j += 64) xrow[j] = 0.0;
+    }
+    if (rmax) {
+        mx = wave_max(mx);
+        if (lane == 0) rmax[i] = (unsigned long long)__double_as_longlong(mx);
     }
     __shared__ double sh[4];
     const double btr = block_sum256(tr, sh);
@@ -545,6 +551,36 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ buf
     }
 }
 
+// D from an X whose upper triangle (32 x 32 blocks I <= J) is valid: each
+// workgroup copies block (I, J) and its transpose (through LDS) to D.
+__global__ __launch_bounds__(256) void k_finalize_upper(const double* __restrict__ buf0,
+                                                        const double* __restrict__ buf1, int ld, int N,
+                                                        double* __restrict__ D,
+                                                        const State* __restrict__ st) {
+    const double* X = st->result ? buf1 : buf0;
+    const int nb = (N + 31) / 32;
+    const int t = blockIdx.x;
+    int I = (int)((2.0 * nb + 1.0 - sqrt((2.0 * nb + 1.0) * (2.0 * nb + 1.0) - 8.0 * (double)t)) / 2.0);
+    I = max(0, min(I, nb - 1));
+    while (I > 0 && I * nb - I * (I - 1) / 2 > t) --I;
+    while (I + 1 < nb && (I + 1) * nb - (I + 1) * I / 2 <= t) ++I;
+    const int J = I + (t - (I * nb - I * (I - 1) / 2));
+    __shared__ double T[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = I * 32 + r, j = J * 32 + tx;      // i, j < ld: X is padded with zeros
+        const double x = X[(size_t)i * ld + j];
+        T[r][tx] = x;
+        if (i < N && j < N) D[(size_t)i * N + j] = x;
+    }
+    if (I == J) return;
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = J * 32 + r, j = I * 32 + tx;
+        if (i < N && j < N) D[(size_t)i * N + j] = T[tx][r];
+    }
+}
+
 // ------------------------------------------------------------ observables
 __global__ __launch_bounds__(256) void k_mulliken(const double* __restrict__ D, int n_atoms,
                                                   double z, double* __restrict__ q) {
@@ -600,10 +636,10 @@ hipError_t launch_bounds(const double* part, int nslots, const double* chk, int 
     return hipGetLastError();
 }
 hipError_t launch_init(const double* H, int N, int ld, double* X0, State* st, double* part,
-                       int* nslots, hipStream_t s) {
+                       int* nslots, hipStream_t s, unsigned long long* rmax0) {
     const int g = ld / 4;
     *nslots = g;
-    hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, s, H, N, ld, X0, st, part);
+    hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, s, H, N, ld, X0, st, part, rmax0);
     return hipGetLastError();
 }
 hipError_t launch_ctrl_init(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s) {
@@ -633,6 +669,12 @@ hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N
     int g = (int)((total + 255) / 256);
     if (g > 4096) g = 4096;
     hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, buf0, buf1, ld, N, D, st);
+    return hipGetLastError();
+}
+hipError_t launch_finalize_upper(const double* buf0, const double* buf1, int ld, int N, double* D,
+                                 const State* st, hipStream_t s) {
+    const int nb = (N + 31) / 32;
+    hipLaunchKernelGGL(k_finalize_upper, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, buf0, buf1, ld, N, D, st);
     return hipGetLastError();
 }
 hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hipStream_t s) {

@@ -154,7 +154,7 @@ hipError_t launch_check_h(const double* H, int N, double* out, int* nout, hipStr
 // or a flat spectrum (done = 4).
 hipError_t launch_bounds(const double* part, int nslots, const double* chk, int nchk, State* st, hipStream_t s);
 hipError_t launch_init(const double* H, int N, int ld, double* X0, State* st, double* part,
-                       int* nslots, hipStream_t s);
+                       int* nslots, hipStream_t s, unsigned long long* rmax0 = nullptr);
 hipError_t launch_ctrl_init(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);
 hipError_t launch_ctrl_step(const double* part, int nslots, State* st, CtrlArgs a, hipStream_t s);
 hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s);
@@ -164,6 +164,9 @@ hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double
                            int* nslots, hipStream_t s, const int* env = nullptr);
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
                            const State* st, hipStream_t s);
+// D from the upper triangle of the result buffer (upper-only int8 products).
+hipError_t launch_finalize_upper(const double* buf0, const double* buf1, int ld, int N, double* D,
+                                 const State* st, hipStream_t s);
 hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hipStream_t s);
 hipError_t launch_dot(const double* A, const double* B, size_t n, double* part, int* nslots,
                       double* out, hipStream_t s);

@@ -138,6 +138,7 @@ int split_reserve(SplitScratch& s, int ld, int slices, bool bf16) {
     size_t need = 0;
     need += (size_t)slices * ld * ld;                 // int8 digits
     need += (size_t)ld * sizeof(double) + 256;        // row scales
+    need += (size_t)2 * ld * sizeof(unsigned long long) + 256;   // row maxima
     if (bf16) need += (size_t)2 * ld * ld * sizeof(uint16_t) + (size_t)ld * ld * sizeof(float) + 512;
     if (s.bytes >= need && s.ld == ld && s.slices == slices && s.bf16 == bf16) return 0;
     split_free(s);
@@ -153,6 +154,9 @@ int split_reserve(SplitScratch& s, int ld, int slices, bool bf16) {
     off = (off + 255) & ~(size_t)255;
     s.scale = reinterpret_cast<double*>(base + off);
     off += (size_t)ld * sizeof(double);
+    off = (off + 255) & ~(size_t)255;
+    s.rmax = reinterpret_cast<unsigned long long*>(base + off);
+    off += (size_t)2 * ld * sizeof(unsigned long long);
     if (bf16) {
         off = (off + 255) & ~(size_t)255;
         s.bf = reinterpret_cast<uint16_t*>(base + off);

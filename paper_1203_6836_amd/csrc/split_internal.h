@@ -19,6 +19,8 @@ struct SplitScratch {
     double* scale = nullptr;    // ld row scales (powers of two)
     uint16_t* bf = nullptr;     // 2 x ld x ld BF16 hi/lo planes
     float* x32 = nullptr;       // ld x ld FP32 master (BF16X2)
+    unsigned long long* rmax = nullptr;  // 2 x ld row maxima of |X| (bit patterns), one row per X buffer
+    bool upper = false;         // int8 products write upper tiles only (set per solve)
     size_t bytes = 0;
 };
 
