@@ -218,6 +218,12 @@ def main():
         e = ctx.sp2_band_energy(Dout, H)
         return st, q, e
 
+    # product tile order for this size (timed on the device; not in the timed region)
+    tune = {"fp64": ctx.sp2_autotune(N, "fp64")}
+    if args.precision != "fp64":
+        tune[args.precision] = ctx.sp2_autotune(N, args.precision, args.slices)
+    log("autotune: " + ", ".join(f"{k} tile_group {v['tile_group']}" for k, v in tune.items()))
+
     if args.traffic_probe:
         # calibration for the HBM byte counters: kernels of known traffic
         # (1 GiB written by a fill, 1 GiB read + 1 GiB written by an
@@ -309,7 +315,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "mixed_n8192: 2048-atom 8x16x16 jittered sp tight-binding lattice, "
                                "N=8192, n_occ=4096", "precision": prec,
-                   "slices": args.slices if prec == "int8x" else None},
+                   "slices": args.slices if prec == "int8x" else None,
+                   "tile_group": tune[prec]["tile_group"]},
+        "autotune_ms_per_product": {k: {str(g): round(ms, 4) for g, ms in v["ms_per_product"].items()}
+                                    for k, v in tune.items()},
         "solves_per_s": round(1e3 / ms, 4),
         "products": iters,
         "fp64_path": {"ms_per_solve": round(ms64, 2), "tflops": round(tflops64, 3),

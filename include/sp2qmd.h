@@ -65,6 +65,11 @@ typedef struct {
                             (default 3)                                          */
     double tau;          /* block threshold: after every update zero each
                             32x32 block with Frobenius norm < tau (0 = dense)    */
+    int tile_group;      /* order of the 128x128 product tiles: G x G super-tiles
+                            dealt to the XCDs (G > 0), 0 = plain row-major, -1
+                            (default) = the value sp2_autotune chose for this
+                            size and precision, else 8.  Results do not depend
+                            on it.                                              */
 } sp2_options;
 
 typedef struct {
@@ -125,6 +130,20 @@ const char *sp2_last_error(const sp2_ctx *ctx);
 sp2_status sp2_density_matrix(sp2_ctx *ctx, int N, const double *H, int n_occ,
                               const sp2_options *opt, double *D_out,
                               sp2_stats *stats);
+
+/* Autotuner of the product tile order: times the SP2 product kernel of the
+ * given precision (and slices, for INT8X) at size N on the context's device
+ * for each candidate super-tile size, and keeps the fastest for later solves
+ * of the same padded size and precision that leave tile_group at -1.
+ * out (may be NULL): the choice and the measured ms per product of each
+ * candidate.  Uses the context's scratch; results of solves are unaffected. */
+typedef struct {
+    int tile_group;          /* chosen super-tile size (0 = row-major)            */
+    int n_candidates;
+    int candidates[8];
+    float ms_per_product[8];
+} sp2_tune_result;
+sp2_status sp2_autotune(sp2_ctx *ctx, int N, int precision, int slices, sp2_tune_result *out);
 
 /* Net Mulliken charges of an orthogonal basis (net-charge equation of the
  * SCC-TB subsection, S = I): q_i = 2 sum_{alpha in atom i} D_{i alpha,i alpha}

@@ -25,7 +25,13 @@ class Sp2Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("idem_tol", ctypes.c_double), ("stall_tol", ctypes.c_double),
                 ("fp64_head", ctypes.c_int), ("slices", ctypes.c_int),
-                ("fp32_tail", ctypes.c_int), ("tau", ctypes.c_double)]
+                ("fp32_tail", ctypes.c_int), ("tau", ctypes.c_double),
+                ("tile_group", ctypes.c_int)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile_group", ctypes.c_int), ("n_candidates", ctypes.c_int),
+                ("candidates", ctypes.c_int * 8), ("ms_per_product", ctypes.c_float * 8)]
 
 
 class Sp2Stats(ctypes.Structure):
@@ -93,6 +99,7 @@ _SIGS = {
     "sp2_density_matrix": (_I, [_P, _I, _P, _I, ctypes.POINTER(Sp2Options), _P,
                                 ctypes.POINTER(Sp2Stats)]),
     "sp2_mulliken": (_I, [_P, _I, _P, _D, _P]),
+    "sp2_autotune": (_I, [_P, _I, _I, _I, ctypes.POINTER(TuneResult)]),
     "sp2_band_energy": (_I, [_P, _I, _P, _P, ctypes.POINTER(_D)]),
     "tb_hamiltonian": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P]),
     "tb_forces": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P, _P,
@@ -230,6 +237,15 @@ class Context:
                                       ctypes.byref(opts) if opts is not None else None,
                                       _ptr(D), ctypes.byref(stats))
         return st, stats.to_dict()
+
+    def sp2_autotune(self, N: int, precision="int8x", slices: int = 5):
+        """Time the product kernel per tile order at size N; the choice is kept
+        for later solves of that size and precision (tile_group = -1)."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        r = TuneResult()
+        self._check(lib().sp2_autotune(self._h, int(N), prec, int(slices), ctypes.byref(r)), "sp2_autotune")
+        return {"tile_group": r.tile_group,
+                "ms_per_product": {r.candidates[k]: r.ms_per_product[k] for k in range(r.n_candidates)}}
 
     def sp2_mulliken(self, D, n_atoms: int, z_val: float = 4.0, q_out=None):
         import torch

@@ -71,13 +71,13 @@ struct BfSmem {
 __global__ __launch_bounds__(512) void k_gemm_bf16x2(double* __restrict__ buf0, double* __restrict__ buf1,
                                                      int ld, const State* __restrict__ st,
                                                      const uint16_t* __restrict__ planes,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, int tile_group) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) uint16_t bsm_raw[];
     BfSmem& sm = *reinterpret_cast<BfSmem*>(bsm_raw);
     const int nt = ld / BB;
     int bi, bj;
-    tile_of_block(blockIdx.x, nt, bi, bj);
+    tile_of_block(blockIdx.x, nt, tile_group, bi, bj);
     const int t = tri_index(bi, bj, nt);
     const int i0 = bi * BB, j0 = bj * BB;
     const double* __restrict__ Xc = st->cur ? buf1 : buf0;
@@ -205,7 +205,8 @@ hipError_t launch_bf16x2_gemm(SplitScratch& s, double* buf0, double* buf1, int l
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_gemm_bf16x2, dim3(T), dim3(512), sizeof(BfSmem), stream, buf0, buf1, ld, st, s.bf, part);
+    hipLaunchKernelGGL(k_gemm_bf16x2, dim3(T), dim3(512), sizeof(BfSmem), stream, buf0, buf1, ld, st, s.bf, part,
+                       s.tile_group);
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <tuple>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -57,6 +59,8 @@ struct sp2_ctx {
     double* ezero = nullptr;
     double* eF = nullptr;
     size_t eatcap = 0;         // atoms
+    // product tile order chosen by sp2_autotune, per (ld, precision, slices)
+    std::map<std::tuple<int, int, int>, int> tuned;
 };
 
 int sp2_ctx_device_of(const sp2_ctx* c) { return c->device; }
@@ -99,6 +103,7 @@ void sp2_options_default(sp2_options* o) {
     o->slices = 5;
     o->fp32_tail = 3;
     o->tau = 0.0;
+    o->tile_group = -1;
 }
 
 const char* sp2_strerror(int s) {
@@ -190,6 +195,7 @@ static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
     if (o.fp64_head < 0) return fail(c, SP2_EINVAL, "fp64_head must be >= 0");
     if (o.precision == SP2_PREC_BF16X2 && o.fp32_tail < 0) return fail(c, SP2_EINVAL, "fp32_tail must be >= 0");
     if (!(o.tau >= 0.0)) return fail(c, SP2_EINVAL, "tau must be >= 0");
+    if (o.tile_group < -1 || o.tile_group > 64) return fail(c, SP2_EINVAL, "tile_group must be in [-1, 64]");
     if (o.tau > 0.0 && o.precision == SP2_PREC_BF16X2)
         return fail(c, SP2_EINVAL, "block thresholding runs with FP64 or INT8X products");
     (void)N;
@@ -223,6 +229,12 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     // their upper tiles only and the encode reads the upper triangle
     const bool upper = int8x && o.tau == 0.0 && o.fp64_head == 0;
     c->split.upper = upper;
+    int tile_group = o.tile_group;
+    if (tile_group < 0) {
+        auto it = c->tuned.find(std::make_tuple(ld, o.precision, int8x ? o.slices : 0));
+        tile_group = it != c->tuned.end() ? it->second : 8;
+    }
+    c->split.tile_group = tile_group;
 
     CtrlArgs a;
     a.n_occ = (double)n_occ;
@@ -262,7 +274,7 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
             if (pe) HIPCHK(c, hipEventRecord(pe[0], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
-            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, env));
+            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, env, tile_group));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
@@ -348,6 +360,98 @@ extern "C" sp2_status sp2_density_matrix(sp2_ctx* c, int N, const double* H, int
     if (s != SP2_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
     return sp2_solve(c, N, H, n_occ, o, D_out, stats);
+}
+
+extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices, sp2_tune_result* out) {
+    if (!c) return SP2_EINVAL;
+    if (N < 1 || N > 65536) return fail(c, SP2_EINVAL, "N must be in [1, 65536]");
+    sp2_options o;
+    sp2_options_default(&o);
+    o.precision = precision;
+    if (precision == SP2_PREC_INT8X) o.slices = slices;
+    sp2_status s = check_options(c, o, N);
+    if (s != SP2_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    const int ld = ((N + kTile - 1) / kTile) * kTile;
+    const size_t ld2 = (size_t)ld * ld;
+    const int nt = ld / kTile;
+    size_t xbytes = c->xcap * sizeof(double) * 2;
+    if ((s = grow(c, (void**)&c->xbuf, &xbytes, 2 * ld2 * sizeof(double))) != SP2_OK) return s;
+    c->xcap = xbytes / (2 * sizeof(double));
+    size_t pbytes = c->partcap * sizeof(double);
+    if ((s = grow(c, (void**)&c->part, &pbytes, std::max<size_t>(tri_tiles(nt) * 3, 1024) * sizeof(double))) != SP2_OK)
+        return s;
+    c->partcap = pbytes / sizeof(double);
+    const bool int8x = precision == SP2_PREC_INT8X, bf16x = precision == SP2_PREC_BF16X2;
+    if (int8x || bf16x) {
+        if (split_reserve(c->split, ld, int8x ? slices : 0, bf16x) != 0)
+            return fail(c, SP2_ENOMEM, "device allocation for split operands failed");
+        c->split.upper = int8x;
+    }
+    double* buf0 = c->xbuf;
+    double* buf1 = c->xbuf + ld2;
+    hipStream_t st = c->stream;
+    // a symmetric operand with the bit activity of real data (the clock of the
+    // device depends on it), row maxima 1/2 for the int8 encode, and a state
+    // that enables the product of this precision
+    HIPCHK(c, launch_fill_test_matrix(buf0, ld, st));
+    if (int8x) {
+        std::vector<unsigned long long> half(2 * (size_t)ld);
+        const double h = 0.5;
+        unsigned long long bits;
+        std::memcpy(&bits, &h, sizeof(bits));
+        std::fill(half.begin(), half.end(), bits);
+        HIPCHK(c, hipMemcpy(c->split.rmax, half.data(), half.size() * sizeof(bits), hipMemcpyHostToDevice));
+    }
+    std::memset(c->st_host, 0, sizeof(State));
+    c->st_host->phase = precision == SP2_PREC_FP64 ? 0 : 1;
+    HIPCHK(c, hipMemcpyAsync(c->st, c->st_host, sizeof(State), hipMemcpyHostToDevice, st));
+    std::vector<int> cand;
+    for (int g : {0, 4, 8, 16, 32})
+        if (g == 0 || g < nt) cand.push_back(g);
+    // about 50 ms of products per candidate, at least 3
+    const double est_ms = (precision == SP2_PREC_FP64 ? 1.0 / 40e9 : 1.0 / 1.2e12) * (double)ld * ld * ld;
+    const int reps = std::max(3, std::min(50, (int)(50.0 / std::max(est_ms, 1e-3))));
+    auto launch = [&](int g) -> sp2_status {
+        int ns = 0;
+        c->split.tile_group = g;
+        if (precision == SP2_PREC_FP64) {
+            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, g));
+        } else {
+            HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
+            HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, nullptr));
+        }
+        return SP2_OK;
+    };
+    int best = 8;
+    float best_ms = 1e30f;
+    sp2_tune_result r{};
+    for (size_t k = 0; k < cand.size(); ++k) {
+        const int g = cand[k];
+        if ((s = launch(g)) != SP2_OK) return s;   // warm-up
+        HIPCHK(c, hipEventRecord(c->ev0, st));
+        for (int q = 0; q < reps; ++q)
+            if ((s = launch(g)) != SP2_OK) return s;
+        HIPCHK(c, hipEventRecord(c->ev1, st));
+        HIPCHK(c, hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        ms /= reps;
+        if (k < 8) {
+            r.candidates[k] = g;
+            r.ms_per_product[k] = ms;
+            r.n_candidates = (int)k + 1;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = g;
+        }
+    }
+    c->split.tile_group = best;
+    c->tuned[std::make_tuple(ld, precision, int8x ? slices : 0)] = best;
+    r.tile_group = best;
+    if (out) *out = r;
+    return SP2_OK;
 }
 
 extern "C" sp2_status sp2_mulliken(sp2_ctx* c, int n_atoms, const double* D, double z_val, double* q_out) {

@@ -564,12 +564,12 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
                                                     const int8_t* __restrict__ digits,
                                                     const double* __restrict__ scale,
                                                     double* __restrict__ part, const int* __restrict__ env,
-                                                    unsigned long long* __restrict__ rmax) {
+                                                    unsigned long long* __restrict__ rmax, int tile_group) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
     int bi, bj;
-    tile_of_block(blockIdx.x, ld / QB, bi, bj);
+    tile_of_block(blockIdx.x, ld / QB, tile_group, bi, bj);
     int8x_tile<S, THR, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
                               UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr);
 }
@@ -608,7 +608,7 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
         attr_set = true;
     }
     hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER>), dim3(T), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
-                       s.scale, part, env, s.rmax);
+                       s.scale, part, env, s.rmax, s.tile_group);
     return hipGetLastError();
 }
 

@@ -380,14 +380,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
                                                      double* __restrict__ buf1, int ld,
                                                      const State* __restrict__ st,
                                                      double* __restrict__ part,
-                                                     const int* __restrict__ env) {
+                                                     const int* __restrict__ env, int tile_group) {
     // phase 0: FP64 products; phase 2: the FP32 tail of the BF16 hi+lo mode
     // (FP32-valued operands, update rounded to FP32)
     if (st->done || (st->phase != 0 && st->phase != 2)) return;
     const bool r32 = st->phase == 2;
     const int nt = ld / GB;
     int bi, bj;
-    tile_of_block(blockIdx.x, nt, bi, bj);
+    tile_of_block(blockIdx.x, nt, tile_group, bi, bj);
     const int t = tri_index(bi, bj, nt);
     const double* __restrict__ Xc = st->cur ? buf1 : buf0;
     double* __restrict__ Xn = st->cur ? buf0 : buf1;
@@ -581,6 +581,21 @@ __global__ __launch_bounds__(256) void k_finalize_upper(const double* __restrict
     }
 }
 
+// Symmetric test operand for timing (the autotuner): X_ij = X_ji in (-1/2, 1/2)
+// from an integer hash of (min(i, j), max(i, j)), so that products switch as
+// many bits (and draw as much power) as on real data.
+__global__ __launch_bounds__(256) void k_fill_test_matrix(double* __restrict__ X, int ld) {
+    const size_t total = (size_t)ld * ld;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const unsigned i = (unsigned)(e / ld), j = (unsigned)(e % ld);
+        unsigned h = (i < j ? i : j) * 0x9E3779B1u ^ (i < j ? j : i) * 0x85EBCA77u;
+        h ^= h >> 15;
+        h *= 0x2C1B3C6Du;
+        h ^= h >> 12;
+        X[e] = (double)(h >> 8) / 16777216.0 - 0.5;
+    }
+}
+
 // ------------------------------------------------------------ observables
 __global__ __launch_bounds__(256) void k_mulliken(const double* __restrict__ D, int n_atoms,
                                                   double z, double* __restrict__ q) {
@@ -655,12 +670,14 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
-                           int* nslots, hipStream_t s, const int* env) {
+                           int* nslots, hipStream_t s, const int* env, int tile_group) {
     const int nt = ld / GB;
     const int T = tri_tiles(nt);
     *nslots = T;
-    if (env) hipLaunchKernelGGL(k_gemm_f64<true>, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env);
-    else hipLaunchKernelGGL(k_gemm_f64<false>, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env);
+    if (env)
+        hipLaunchKernelGGL(k_gemm_f64<true>, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env, tile_group);
+    else
+        hipLaunchKernelGGL(k_gemm_f64<false>, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env, tile_group);
     return hipGetLastError();
 }
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
@@ -675,6 +692,10 @@ hipError_t launch_finalize_upper(const double* buf0, const double* buf1, int ld,
                                  const State* st, hipStream_t s) {
     const int nb = (N + 31) / 32;
     hipLaunchKernelGGL(k_finalize_upper, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, buf0, buf1, ld, N, D, st);
+    return hipGetLastError();
+}
+hipError_t launch_fill_test_matrix(double* X, int ld, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_test_matrix, dim3(2048), dim3(256), 0, s, X, ld);
     return hipGetLastError();
 }
 hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hipStream_t s) {

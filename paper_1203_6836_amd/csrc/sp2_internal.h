@@ -91,10 +91,6 @@ __device__ __forceinline__ int group_find(const int* off, int n, int item) {
 // Number of upper-triangular tile pairs (bi <= bj) of an nt x nt tile grid.
 inline int tri_tiles(int nt) { return nt * (nt + 1) / 2; }
 
-#ifndef SP2_SUPER_G
-#define SP2_SUPER_G 8
-#endif
-
 // Canonical slot of tile (bi, bj), bi <= bj: row-major over the upper triangle.
 __device__ __forceinline__ int tri_index(int bi, int bj, int nt) {
     return bi * nt - bi * (bi - 1) / 2 + (bj - bi);
@@ -106,12 +102,14 @@ __device__ __forceinline__ int tri_index(int bi, int bj, int nt) {
 // each of the 8 XCDs (which receive workgroups round-robin) owns a contiguous
 // run of this order.  Concurrent workgroups of one XCD then share a few row
 // panels on both operand sides, which keeps the panels in that XCD's L2.
-__device__ __forceinline__ void tile_of_block(int w, int nt, int& bi, int& bj) {
+// G <= 0: a single super-tile (plain row-major order).  G is a launch
+// argument chosen per size by sp2_autotune (default 8).
+__device__ __forceinline__ void tile_of_block(int w, int nt, int G, int& bi, int& bj) {
     const int T = nt * (nt + 1) / 2;
     const int q = T >> 3, r = T & 7;
     const int x = w & 7, k = w >> 3;
     int t = x * q + (x < r ? x : r) + k;   // position in the visiting order
-    const int G = SP2_SUPER_G > 0 ? SP2_SUPER_G : nt;
+    if (G <= 0 || G > nt) G = nt;
     const int ns = (nt + G - 1) / G;
     for (int I = 0; I < ns; ++I) {
         const int gi = min(G, nt - I * G);
@@ -161,12 +159,14 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s);
 // env (may be null): per 128-row panel p, [env[2p], env[2p+1]] is the range
 // of 32-column blocks holding nonzeros of a thresholded X.
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
-                           int* nslots, hipStream_t s, const int* env = nullptr);
+                           int* nslots, hipStream_t s, const int* env = nullptr, int tile_group = 8);
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
                            const State* st, hipStream_t s);
 // D from the upper triangle of the result buffer (upper-only int8 products).
 hipError_t launch_finalize_upper(const double* buf0, const double* buf1, int ld, int N, double* D,
                                  const State* st, hipStream_t s);
+// Symmetric pseudo-random ld x ld operand in (-1/2, 1/2) (timing only).
+hipError_t launch_fill_test_matrix(double* X, int ld, hipStream_t s);
 hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hipStream_t s);
 hipError_t launch_dot(const double* A, const double* B, size_t n, double* part, int* nslots,
                       double* out, hipStream_t s);

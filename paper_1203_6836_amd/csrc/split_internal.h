@@ -21,6 +21,7 @@ struct SplitScratch {
     float* x32 = nullptr;       // ld x ld FP32 master (BF16X2)
     unsigned long long* rmax = nullptr;  // 2 x ld row maxima of |X| (bit patterns), one row per X buffer
     bool upper = false;         // int8 products write upper tiles only (set per solve)
+    int tile_group = 8;         // super-tile size of the product tile order (set per solve)
     size_t bytes = 0;
 };
 

@@ -125,3 +125,22 @@ def test_bf16x2_configured_recipe_reported(ctx, dims, seed):
     assert st["iterations"] - st["head_switch"] == 3        # three FP32 products
     assert abs(np.trace(D) - nocc) < 1e-3
     assert err < 1e-2
+
+
+def test_autotune_and_tile_order_invariance(ctx):
+    """The autotuner times each tile order; every order gives bitwise the same D."""
+    import torch
+    import paper_1203_6836_amd as p
+    say("case autotune + tile-order invariance N=2048")
+    pos = synth.lattice_positions((8, 8, 8), seed=2)
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, torch.from_numpy(pos).cuda())
+    nocc = 2 * len(pos)
+    for prec in ("int8x", "fp64"):
+        r = ctx.sp2_autotune(H.shape[0], prec)
+        say(f"  {prec}: chose {r['tile_group']} from {r['ms_per_product']}")
+        assert r["tile_group"] in r["ms_per_product"]
+        assert all(ms > 0 for ms in r["ms_per_product"].values())
+        assert r["ms_per_product"][r["tile_group"]] == min(r["ms_per_product"].values())
+        Ds = [ctx.sp2_density_matrix(H, nocc, p.options(prec, tile_group=g))[0] for g in (-1, 0, 4, 8)]
+        for D in Ds[1:]:
+            assert torch.equal(D, Ds[0])
