@@ -375,8 +375,12 @@ __device__ __forceinline__ int xcd_remap(int w, int T) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// At most 256 registers per lane: the accumulators then stay in VGPR form
+// (with the whole register file the compiler splits them between VGPRs and
+// AGPRs and copies them across on every K stage) and two workgroups fit on
+// a CU (LDS 64 KiB each), so one hides the other's barriers and epilogue.
 template <bool THR>
-__global__ __launch_bounds__(256) void k_gemm_f64(double* __restrict__ buf0,
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
                                                      double* __restrict__ buf1, int ld,
                                                      const State* __restrict__ st,
                                                      double* __restrict__ part,
