@@ -70,6 +70,12 @@ typedef struct {
                             (default) = the value sp2_autotune chose for this
                             size and precision, else 8.  Results do not depend
                             on it.                                              */
+    int tail_split;      /* INT8X, N >= 4096: when the tiles of the last wave
+                            of product workgroups would leave at least half of
+                            the compute units idle, split their K loops into up
+                            to 8 chunks run in parallel and summed exactly (-1
+                            default: on; 0: never).  Results do not depend on
+                            it.                                                 */
 } sp2_options;
 
 typedef struct {

@@ -104,6 +104,7 @@ void sp2_options_default(sp2_options* o) {
     o->fp32_tail = 3;
     o->tau = 0.0;
     o->tile_group = -1;
+    o->tail_split = -1;
 }
 
 const char* sp2_strerror(int s) {
@@ -196,6 +197,7 @@ static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
     if (o.precision == SP2_PREC_BF16X2 && o.fp32_tail < 0) return fail(c, SP2_EINVAL, "fp32_tail must be >= 0");
     if (!(o.tau >= 0.0)) return fail(c, SP2_EINVAL, "tau must be >= 0");
     if (o.tile_group < -1 || o.tile_group > 64) return fail(c, SP2_EINVAL, "tile_group must be in [-1, 64]");
+    if (o.tail_split < -1 || o.tail_split > 1) return fail(c, SP2_EINVAL, "tail_split must be -1, 0 or 1");
     if (o.tau > 0.0 && o.precision == SP2_PREC_BF16X2)
         return fail(c, SP2_EINVAL, "block thresholding runs with FP64 or INT8X products");
     (void)N;
@@ -235,6 +237,7 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
         tile_group = it != c->tuned.end() ? it->second : 8;
     }
     c->split.tile_group = tile_group;
+    c->split.tail_split = o.tail_split;
 
     CtrlArgs a;
     a.n_occ = (double)n_occ;

@@ -13,6 +13,8 @@
 // epilogue, which then applies the SP2 update exactly like the FP64 product.
 //
 // Work layout, storage and staging: see the comments at the kernels.
+#include <algorithm>
+
 #include "split_internal.h"
 
 namespace sp2 {
@@ -268,17 +270,7 @@ __global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __
 constexpr int QB = 128;          // tile
 constexpr int QK = 32;           // k bytes per stage
 
-#ifndef SP2_I8_DMA
-#define SP2_I8_DMA 1
-#endif
-#ifndef SP2_I8_SCHED
-#define SP2_I8_SCHED 2           // 0: compiler's own order; n > 0: read lookahead
-#endif
-#if SP2_I8_DMA
-constexpr int I8_NST = 3;         // LDS ring depth (stages), filled by global->LDS loads
-#else
-constexpr int I8_NST = 2;
-#endif
+constexpr int I8_NST = 3;        // LDS ring depth (stages), filled by global->LDS loads
 
 // The staging ring; after the K loop the same LDS holds half of the finished
 // tile, transposed, so the mirrored (lower-triangle) copy is written as
@@ -298,7 +290,14 @@ struct I8Smem {
 };
 
 // One 128 x 128 output tile (bi, bj) of one system; all 512 threads of the
-// workgroup take part (the body contains barriers).  UPPER: write the tile
+// workgroup take part (the body contains barriers).  kmode 0: the whole
+// tile; kmode 1: only K stages [kc0, kc1), whose int32 level accumulators are
+// stored to chunk_acc (one chunk of a tile split along K); kmode 2: no K
+// loop, the accumulators are the sum of the nchunks chunks at chunk_acc (the
+// integer sums are exact, so a split tile equals an unsplit one), then the
+// epilogue.  Chunk layout: int4 [S][2][4][512 threads] (accumulator elements
+// 4q .. 4q + 3 of level L, column block c), so that each wave moves 1 KiB
+// per instruction.  UPPER: write the tile
 // only (no mirrored copy below the diagonal) and fold its row and column
 // maxima of |X_{n+1}| into rmax_next (bit patterns of non-negative doubles
 // order like the values, so atomicMax on them is exact and order-free).
@@ -307,7 +306,8 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
                            const State* __restrict__ st, const int8_t* __restrict__ digits,
                            const double* __restrict__ scale, double* __restrict__ part, int bi, int bj,
                            I8Smem<S>& sm, const int* __restrict__ env,
-                           unsigned long long* __restrict__ rmax_next) {
+                           unsigned long long* __restrict__ rmax_next, int kmode = 0, int kc0 = 0,
+                           int kc1 = -1, int* __restrict__ chunk_acc = nullptr, int nchunks = 0) {
     const int nt = ld / QB;
     const int t = tri_index(bi, bj, nt);
     const int i0 = bi * QB, j0 = bj * QB;
@@ -322,29 +322,6 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     constexpr int NBLK = 2 * S * 4;             // 1 KiB blocks per stage
     constexpr int PER = NBLK * 64 / 512;        // 16-byte chunks per thread
     static_assert((NBLK * 64) % 512 == 0, "stage must split evenly over 512 threads");
-#if !SP2_I8_DMA
-    v4i pre[PER];
-    auto gload = [&](int kb) {
-#pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int c = tid + 512 * m;
-            const int blk = c >> 6;
-            const int op = blk / (S * 4);
-            const int rem = blk - op * (S * 4);
-            const int sl = rem >> 2, rb = rem & 3;
-            const int grb = ((op ? j0 : i0) >> 5) + rb;
-            pre[m] = *reinterpret_cast<const v4i*>(digits + sl * plane + ((size_t)grb * nb + kb) * 1024 +
-                                                   16 * (c & 63));
-        }
-    };
-    auto sstore = [&](int stg) {
-#pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int c = tid + 512 * m;
-            *reinterpret_cast<v4i*>(&sm.buf[stg][c >> 6][16 * (c & 63)]) = pre[m];
-        }
-    };
-#endif
 
     v16i acc[S][2];
 #pragma unroll
@@ -360,6 +337,10 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     // K range: all of it, or the overlap of the two panels' surviving column
     // blocks of a thresholded X (one 32-byte stage per 32-column block)
     int ks = 0, nk = ld / QK;
+    if (kc1 >= 0) {
+        ks = kc0;
+        nk = kc1;
+    }
     if (THR) {
         const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
         ks = lo;
@@ -393,8 +374,7 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
                     acc[tt + uu][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt], b[uu][c], acc[tt + uu][c], 0, 0, 0);
-#if SP2_I8_SCHED
-        constexpr int LA = SP2_I8_SCHED;                 // lookahead in reads
+        constexpr int LA = 2;                            // lookahead in reads
         constexpr int R = 3 * S, P = S * (S + 1) / 2;   // reads, product pairs
         constexpr int MID = R - 3 - LA;
         __builtin_amdgcn_sched_group_barrier(0x100, 3 + LA, 0);
@@ -404,9 +384,7 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         }
         __builtin_amdgcn_sched_group_barrier(0x008, 2 * (P - MID), 0);
-#endif
     };
-#if SP2_I8_DMA
     // Global -> LDS loads without register staging: wave w moves blocks w,
     // w + 8, ... of a stage, one 1 KiB block per instruction (16 bytes per
     // lane).  Stage kt + 2 is issued while stage kt is multiplied; before
@@ -425,6 +403,7 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
                                              (__attribute__((address_space(3))) void*)&sm.buf[stg][blk][0], 16, 0, 0);
         }
     };
+    if (kmode == 2) nk = ks;          // accumulators come from the chunks
     if (ks < nk) issue(ks, 0);
     if (ks + 1 < nk) issue(ks + 1, 1);
     for (int kt = ks; kt < nk; ++kt) {
@@ -440,18 +419,36 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
         compute((kt - ks) % I8_NST);
     }
     __syncthreads();
-#else
-    if (ks < nk) gload(ks);
-    if (ks < nk) sstore(0);
-    __syncthreads();
-    for (int kt = ks; kt < nk; ++kt) {
-        const int stg = (kt - ks) & 1;
-        if (kt + 1 < nk) gload(kt + 1);
-        compute(stg);
-        if (kt + 1 < nk) sstore(stg ^ 1);
-        __syncthreads();
+    constexpr int CH = S * 2 * 16 * 512;   // int32 per chunk
+    if (kmode == 1) {
+        int4* out = reinterpret_cast<int4*>(chunk_acc);
+#pragma unroll
+        for (int L = 0; L < S; ++L)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    out[((L * 2 + c) * 4 + q) * 512 + tid] =
+                        make_int4(acc[L][c][4 * q], acc[L][c][4 * q + 1], acc[L][c][4 * q + 2], acc[L][c][4 * q + 3]);
+        return;
     }
-#endif
+    if (kmode == 2) {
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int4* in = reinterpret_cast<const int4*>(chunk_acc + (size_t)ch * CH);
+#pragma unroll
+            for (int L = 0; L < S; ++L)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int4 v = in[((L * 2 + c) * 4 + q) * 512 + tid];
+                        acc[L][c][4 * q] += v.x;
+                        acc[L][c][4 * q + 1] += v.y;
+                        acc[L][c][4 * q + 2] += v.z;
+                        acc[L][c][4 * q + 3] += v.w;
+                    }
+        }
+    }
 
     // epilogue: combine levels in FP64, apply the SP2 update, partials.
     // Partial sums are kept per column block c in row order and added at the
@@ -558,20 +555,59 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     }
 }
 
+// Workgroups [0, t_full): whole tiles at visiting positions [0, t_full),
+// dealt over the XCDs.  Workgroups from t_full on: the tiles at positions
+// t_full, t_full + 1, ... (the last, partly filled wave of a launch), each
+// split into nsplit chunks of the K loop whose accumulators go to chunk_acc;
+// k_gemm_int8x_tail finishes them.
 template <int S, bool THR, bool UPPER>
 __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
                                                     int ld, const State* __restrict__ st,
                                                     const int8_t* __restrict__ digits,
                                                     const double* __restrict__ scale,
                                                     double* __restrict__ part, const int* __restrict__ env,
-                                                    unsigned long long* __restrict__ rmax, int tile_group) {
+                                                    unsigned long long* __restrict__ rmax, int tile_group,
+                                                    int t_full, int nsplit, int* __restrict__ chunk_acc) {
+    if (st->done || st->phase != 1) return;
+    extern __shared__ __align__(16) int8_t smem_raw[];
+    I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
+    const int nt = ld / QB, w = blockIdx.x;
+    int pos, kmode = 0, kc0 = 0, kc1 = -1;
+    int* cacc = nullptr;
+    if (w < t_full) {
+        pos = xcd_deal(w, t_full);
+    } else {
+        const int j = w - t_full, p = j / nsplit, ch = j - p * nsplit, nk = ld / QK;
+        pos = t_full + p;
+        kmode = 1;
+        kc0 = ch * nk / nsplit;
+        kc1 = (ch + 1) * nk / nsplit;
+        cacc = chunk_acc + (size_t)j * (S * 2 * 16 * 512);
+    }
+    int bi, bj;
+    order_tile(pos, nt, tile_group, bi, bj);
+    int8x_tile<S, THR, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
+                              UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, kmode, kc0, kc1, cacc, 0);
+}
+
+// Epilogue of the split tiles: workgroup p sums the nsplit chunks of the tile
+// at visiting position t_full + p and applies the update.
+template <int S, bool UPPER>
+__global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                         int ld, const State* __restrict__ st,
+                                                         const int8_t* __restrict__ digits,
+                                                         const double* __restrict__ scale,
+                                                         double* __restrict__ part,
+                                                         unsigned long long* __restrict__ rmax, int tile_group,
+                                                         int t_full, int nsplit, int* __restrict__ chunk_acc) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
     int bi, bj;
-    tile_of_block(blockIdx.x, ld / QB, tile_group, bi, bj);
-    int8x_tile<S, THR, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
-                              UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr);
+    order_tile(t_full + blockIdx.x, ld / QB, tile_group, bi, bj);
+    int8x_tile<S, false, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, nullptr,
+                                UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, 2, 0, -1,
+                                chunk_acc + (size_t)blockIdx.x * nsplit * (S * 2 * 16 * 512), nsplit);
 }
 
 // Grouped: every upper-triangular tile of every system in the group; a fixed
@@ -594,6 +630,18 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __r
     }
 }
 
+// Compute units of the current device (one product workgroup fits on a CU).
+static int device_cus() {
+    static int n = 0;
+    if (n <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                     hipSuccess || n <= 0)
+            n = 256;
+    }
+    return n;
+}
+
 template <int S, bool THR, bool UPPER>
 static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                                      hipStream_t stream, const int* env) {
@@ -604,11 +652,32 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, THR, UPPER>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess && !THR)
+            e = hipFuncSetAttribute((const void*)k_gemm_int8x_tail<S, UPPER>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER>), dim3(T), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
-                       s.scale, part, env, s.rmax, s.tile_group);
+    // Tiles of a last wave that would leave at least half of the CUs idle
+    // are split along K into nsplit <= 8 chunks (wave quantisation of the
+    // tail), when a tile has at least 128 K stages: shorter tiles cost less
+    // than summing their chunks.
+    int t_full = T, nsplit = 1;
+    if (!THR && s.tail_split != 0 && s.tail_acc && ld / QK >= 128) {
+        const int cus = device_cus();
+        const int r = T % cus;
+        if (r > 0 && 2 * r <= cus) {
+            nsplit = std::min(8, cus / r);
+            if (nsplit >= 2 && (size_t)r * nsplit * S * 2 * 16 * 512 * sizeof(int) <= s.tail_bytes) t_full = T - r;
+            else nsplit = 1;
+        }
+    }
+    const int grid = t_full + (T - t_full) * nsplit;
+    hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
+                       s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
+    if (t_full < T)
+        hipLaunchKernelGGL((k_gemm_int8x_tail<S, UPPER>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
+                           st, s.digits, s.scale, part, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
     return hipGetLastError();
 }
 

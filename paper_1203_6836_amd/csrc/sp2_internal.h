@@ -102,13 +102,19 @@ __device__ __forceinline__ int tri_index(int bi, int bj, int nt) {
 // each of the 8 XCDs (which receive workgroups round-robin) owns a contiguous
 // run of this order.  Concurrent workgroups of one XCD then share a few row
 // panels on both operand sides, which keeps the panels in that XCD's L2.
-// G <= 0: a single super-tile (plain row-major order).  G is a launch
-// argument chosen per size by sp2_autotune (default 8).
-__device__ __forceinline__ void tile_of_block(int w, int nt, int G, int& bi, int& bj) {
-    const int T = nt * (nt + 1) / 2;
+// Position in the visiting order of workgroup w of a launch of T workgroups:
+// each XCD (workgroups are dealt round-robin over the 8 XCDs) gets a
+// contiguous run of positions.
+__device__ __forceinline__ int xcd_deal(int w, int T) {
     const int q = T >> 3, r = T & 7;
     const int x = w & 7, k = w >> 3;
-    int t = x * q + (x < r ? x : r) + k;   // position in the visiting order
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Tile (bi, bj) at position t of the visiting order.  G <= 0: a single
+// super-tile (plain row-major order).  G is a launch argument chosen per
+// size by sp2_autotune (default 8).
+__device__ __forceinline__ void order_tile(int t, int nt, int G, int& bi, int& bj) {
     if (G <= 0 || G > nt) G = nt;
     const int ns = (nt + G - 1) / G;
     for (int I = 0; I < ns; ++I) {
@@ -131,7 +137,11 @@ __device__ __forceinline__ void tile_of_block(int w, int nt, int G, int& bi, int
             t -= cnt;
         }
     }
-    bi = bj = 0;   // unreachable for w < T
+    bi = bj = 0;   // unreachable for t < nt (nt + 1) / 2
+}
+
+__device__ __forceinline__ void tile_of_block(int w, int nt, int G, int& bi, int& bj) {
+    order_tile(xcd_deal(w, nt * (nt + 1) / 2), nt, G, bi, bj);
 }
 
 // Reading of a degenerate Fermi level: an idempotent X_n whose trace is not

@@ -139,6 +139,9 @@ int split_reserve(SplitScratch& s, int ld, int slices, bool bf16) {
     need += (size_t)slices * ld * ld;                 // int8 digits
     need += (size_t)ld * sizeof(double) + 256;        // row scales
     need += (size_t)2 * ld * sizeof(unsigned long long) + 256;   // row maxima
+    // K-chunk accumulators of split tiles: at most one chunk per CU (256)
+    const size_t tail = slices > 0 ? (size_t)256 * slices * 2 * 16 * 512 * sizeof(int) : 0;
+    need += tail + 256;
     if (bf16) need += (size_t)2 * ld * ld * sizeof(uint16_t) + (size_t)ld * ld * sizeof(float) + 512;
     if (s.bytes >= need && s.ld == ld && s.slices == slices && s.bf16 == bf16) return 0;
     split_free(s);
@@ -157,6 +160,10 @@ int split_reserve(SplitScratch& s, int ld, int slices, bool bf16) {
     off = (off + 255) & ~(size_t)255;
     s.rmax = reinterpret_cast<unsigned long long*>(base + off);
     off += (size_t)2 * ld * sizeof(unsigned long long);
+    off = (off + 255) & ~(size_t)255;
+    s.tail_acc = tail ? reinterpret_cast<int*>(base + off) : nullptr;
+    s.tail_bytes = tail;
+    off += tail;
     if (bf16) {
         off = (off + 255) & ~(size_t)255;
         s.bf = reinterpret_cast<uint16_t*>(base + off);

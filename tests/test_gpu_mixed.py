@@ -144,3 +144,20 @@ def test_autotune_and_tile_order_invariance(ctx):
         Ds = [ctx.sp2_density_matrix(H, nocc, p.options(prec, tile_group=g))[0] for g in (-1, 0, 4, 8)]
         for D in Ds[1:]:
             assert torch.equal(D, Ds[0])
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 16), (8, 8, 16)])
+def test_tail_split_is_exact(ctx, dims):
+    """Splitting the K loops of the last wave's tiles (all 36 tiles at N = 1024,
+    16 of 528 at N = 4096) and summing the int32 chunks changes nothing."""
+    import torch
+    import paper_1203_6836_amd as p
+    say(f"case int8x tail split on/off dims={dims}")
+    pos = synth.lattice_positions(dims, seed=5)
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, torch.from_numpy(pos).cuda())
+    nocc = 2 * len(pos)
+    D0, s0 = ctx.sp2_density_matrix(H, nocc, p.options("int8x", tail_split=0))
+    D1, s1 = ctx.sp2_density_matrix(H, nocc, p.options("int8x"))
+    say(f"  iters {s0['iterations']} / {s1['iterations']}  ms {s0['ms']:.1f} / {s1['ms']:.1f}")
+    assert s0["iterations"] == s1["iterations"]
+    assert torch.equal(D0, D1)
