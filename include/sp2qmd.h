@@ -38,7 +38,8 @@ typedef enum {
     SP2_EGAP = -5,      /* no resolvable gap at the Fermi level: the set of
                            n_occ occupied states is not unique               */
     SP2_EBUDGET = -6,   /* serving: request larger than the memory budget    */
-    SP2_ETIMEOUT = -8   /* serving: wait timed out                           */
+    SP2_ETIMEOUT = -8,  /* serving: wait timed out                           */
+    SP2_EDIVERGE = -9   /* XL-BOMD: auxiliary charges ran away from q        */
 } sp2_status;
 
 /* Arithmetic of the SP2 products X_n^2 (the update, traces, branch and stop
@@ -224,12 +225,18 @@ typedef struct {
     double scf_tol;   /* ... until max_i |q_i - n_i| < scf_tol ...              */
     int scf_max_iter; /* ... or SP2_ENOCONV after this many density matrices;
                          0: no SCF, n0 is used as given                        */
+    double diverge_q; /* stop with SP2_EDIVERGE after a step whose
+                         max_i |q_i - n_i| exceeds this (e), the sign of kappa
+                         outside the stability bound of Eq. Verl_n or of a too
+                         long time step; 0: no check                           */
 } xlbomd_options;
 
 typedef struct {
     double etot, epot, ekin;   /* eV                                           */
     double max_q_minus_n;      /* max_i |q_i - n_i| at the step                 */
     int sp2_iterations;
+    float fill_min;            /* smallest kept-block fraction over the step's
+                                  SP2 updates (1 if tau == 0)                  */
 } xlbomd_record;
 
 typedef struct xlbomd xlbomd;
@@ -246,6 +253,9 @@ sp2_status xlbomd_create(sp2_ctx *ctx, const tb_params *p, const xlbomd_options 
                          const double *n0_host, xlbomd **out);
 /* SCF iterations and final residual max|q - n| of the start (0 if n0 given). */
 sp2_status xlbomd_info(const xlbomd *md, int *scf_iterations, double *scf_residual);
+/* Steps taken and density matrices constructed since creation (the start
+ * builds one per SCF iteration plus one; each step builds exactly one). */
+sp2_status xlbomd_counters(const xlbomd *md, long long *steps, long long *density_matrices);
 /* Advance n_steps; log (host, n_steps entries) may be NULL. */
 sp2_status xlbomd_run(xlbomd *md, int n_steps, xlbomd_record *log);
 /* Copy current positions, velocities, charges q and n_t to host arrays (any may be NULL). */

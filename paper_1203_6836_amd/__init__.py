@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsp2qmd.so")
 
 SP2_OK, SP2_EINVAL, SP2_ENOMEM, SP2_EDEVICE, SP2_ENOCONV, SP2_EGAP = 0, -1, -2, -3, -4, -5
-SP2_EBUDGET, SP2_ETIMEOUT = -6, -8
+SP2_EBUDGET, SP2_ETIMEOUT, SP2_EDIVERGE = -6, -8, -9
 PREC_FP64, PREC_INT8X, PREC_BF16X2 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "int8x": PREC_INT8X, "bf16x2": PREC_BF16X2}
 
@@ -70,13 +70,14 @@ class XLOptions(ctypes.Structure):
     _fields_ = [("dt_fs", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("K", ctypes.c_int),
                 ("c", ctypes.c_double * 9), ("sp2", Sp2Options),
-                ("scf_beta", ctypes.c_double), ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int)]
+                ("scf_beta", ctypes.c_double), ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int),
+                ("diverge_q", ctypes.c_double)]
 
 
 class XLRecord(ctypes.Structure):
     _fields_ = [("etot", ctypes.c_double), ("epot", ctypes.c_double),
                 ("ekin", ctypes.c_double), ("max_q_minus_n", ctypes.c_double),
-                ("sp2_iterations", ctypes.c_int)]
+                ("sp2_iterations", ctypes.c_int), ("fill_min", ctypes.c_float)]
 
 
 class ServerOptions(ctypes.Structure):
@@ -111,6 +112,7 @@ _SIGS = {
     "xlbomd_run": (_I, [_P, _I, ctypes.POINTER(XLRecord)]),
     "xlbomd_get": (_I, [_P, _P, _P, _P, _P]),
     "xlbomd_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    "xlbomd_counters": (_I, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
     "xlbomd_get_state": (_I, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
     "xlbomd_set_state": (_I, [_P, _P, ctypes.c_size_t]),
     "xlbomd_destroy": (None, [_P]),
@@ -304,19 +306,20 @@ class Context:
 
     def xlbomd_create(self, model, xyz, vel, n0=None, dt_fs=0.25, kappa=0.91, alpha=0.018,
                       c=(-6.0, 14.0, -8.0, -3.0, 4.0, -1.0), sp2_opts=None,
-                      scf_beta=0.3, scf_tol=1e-10, scf_max_iter=None):
-        """scf_max_iter None: 0 (use n0 as given) if n0 is given, else 500 (SCF from zeros)."""
+                      scf_beta=0.3, scf_tol=1e-10, scf_max_iter=None, diverge_q=1.0):
+        """scf_max_iter None: 0 (use n0 as given) if n0 is given, else 500 (SCF from zeros).
+        diverge_q: stop with SP2_EDIVERGE when max|q - n| exceeds it (0: never)."""
         if scf_max_iter is None:
             scf_max_iter = 0 if n0 is not None else 500
         return XLBOMD(self, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,
-                      scf_beta, scf_tol, scf_max_iter)
+                      scf_beta, scf_tol, scf_max_iter, diverge_q)
 
 
 class XLBOMD:
     """Handle of an xlbomd integrator; host numpy arrays in, host numpy arrays out."""
 
     def __init__(self, ctx, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,
-                 scf_beta=0.3, scf_tol=1e-10, scf_max_iter=500):
+                 scf_beta=0.3, scf_tol=1e-10, scf_max_iter=500, diverge_q=1.0):
         self.ctx = ctx
         self.nat = len(xyz)
         o = XLOptions()
@@ -325,6 +328,7 @@ class XLBOMD:
             o.c[k] = ck
         o.sp2 = sp2_opts if sp2_opts is not None else options("fp64")
         o.scf_beta, o.scf_tol, o.scf_max_iter = scf_beta, scf_tol, scf_max_iter
+        o.diverge_q = diverge_q
         p = tb_params(model)
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)
@@ -340,8 +344,15 @@ class XLBOMD:
         recs = (XLRecord * max(n_steps, 1))()
         self.ctx._check(lib().xlbomd_run(self._h, int(n_steps), recs), "xlbomd_run")
         return [{"etot": r.etot, "epot": r.epot, "ekin": r.ekin,
-                 "max_q_minus_n": r.max_q_minus_n, "sp2_iterations": r.sp2_iterations}
+                 "max_q_minus_n": r.max_q_minus_n, "sp2_iterations": r.sp2_iterations,
+                 "fill_min": r.fill_min}
                 for r in recs[:n_steps]]
+
+    def xlbomd_counters(self):
+        """(steps, density matrices built) since creation."""
+        a, b = ctypes.c_longlong(), ctypes.c_longlong()
+        self.ctx._check(lib().xlbomd_counters(self._h, ctypes.byref(a), ctypes.byref(b)), "xlbomd_counters")
+        return a.value, b.value
 
     def xlbomd_info(self):
         it, res = ctypes.c_int(), ctypes.c_double()

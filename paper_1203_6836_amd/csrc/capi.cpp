@@ -117,6 +117,7 @@ const char* sp2_strerror(int s) {
         case SP2_EGAP: return "no resolvable gap at the Fermi level (theta(mu0 I - H) undefined)";
         case SP2_EBUDGET: return "request exceeds the memory budget";
         case SP2_ETIMEOUT: return "timed out";
+        case SP2_EDIVERGE: return "XL-BOMD auxiliary charges diverged from q";
         default: return "unknown status";
     }
 }
@@ -656,9 +657,10 @@ struct xlbomd {
     double U;
     int scf_iterations;
     double scf_residual;
+    long long dm_count;   // density matrices built
 };
 
-static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true) {
+static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true, float* fill = nullptr) {
     sp2_ctx* c = m->c;
     const int nat = m->nat, N = 4 * nat;
     const double* n_t = m->hist + (size_t)m->head * nat;
@@ -667,7 +669,9 @@ static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true) {
     sp2_stats st;
     s = sp2_solve(c, N, m->H, 2 * nat, m->o.sp2, m->D, &st);
     if (s != SP2_OK) return s;
+    m->dm_count += 1;
     if (iters) *iters = st.iterations;
+    if (fill) *fill = m->o.sp2.tau > 0.0 ? (float)st.fill_min : 1.0f;
     HIPCHK(c, launch_mulliken(m->D, nat, m->p.z_val, m->q, c->stream));
     if (!with_forces) return SP2_OK;
     return forces_impl(c, &m->p, nat, m->xyz, m->D, m->q, n_t, m->F, m->dscal);
@@ -685,7 +689,8 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
         return fail(c, SP2_EINVAL, "SCF start needs 0 < scf_beta <= 1 and scf_tol > 0");
     *out = nullptr;
     if (n_atoms < 2 || n_atoms > 16384) return fail(c, SP2_EINVAL, "n_atoms out of range");
-    if (o->K < 1 || o->K > 8 || !(o->dt_fs > 0) || !(p->mass > 0)) return fail(c, SP2_EINVAL, "bad xlbomd options");
+    if (o->K < 1 || o->K > 8 || !(o->dt_fs > 0) || !(p->mass > 0) || !(o->diverge_q >= 0))
+        return fail(c, SP2_EINVAL, "bad xlbomd options");
     sp2_status s = check_options(c, o->sp2, 4 * n_atoms);
     if (s != SP2_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
@@ -776,7 +781,8 @@ extern "C" sp2_status xlbomd_run(xlbomd* m, int n_steps, xlbomd_record* log) {
         HIPCHK(c, launch_xl_charges(m->hist, nat, K, m->head, m->q, xa, st));
         m->head = (m->head + K) % L;
         int iters = 0;
-        sp2_status s = md_evaluate(m, &iters);
+        float fill = 1.0f;
+        sp2_status s = md_evaluate(m, &iters, true, &fill);
         if (s != SP2_OK) return s;
         HIPCHK(c, launch_maxdiff(m->q, m->hist + (size_t)m->head * nat, nat, m->dev, m->dscal + 1, st));
         HIPCHK(c, launch_kick_drift(m->xyz, m->vel, m->F, 3 * nat, hacc, 0.0, st));
@@ -793,8 +799,21 @@ extern "C" sp2_status xlbomd_run(xlbomd* m, int n_steps, xlbomd_record* log) {
             log[step].etot = U + ke;
             log[step].max_q_minus_n = c->scal_host[1];
             log[step].sp2_iterations = iters;
+            log[step].fill_min = fill;
         }
+        if (m->o.diverge_q > 0.0 && !(c->scal_host[1] <= m->o.diverge_q))
+            return fail(c, SP2_EDIVERGE, "auxiliary charges diverged: max|q - n| = " +
+                                             std::to_string(c->scal_host[1]) + " e after step " +
+                                             std::to_string(m->step) +
+                                             " (kappa outside the stability bound, or too long a time step)");
     }
+    return SP2_OK;
+}
+
+extern "C" sp2_status xlbomd_counters(const xlbomd* m, long long* steps, long long* density_matrices) {
+    if (!m) return SP2_EINVAL;
+    if (steps) *steps = m->step;
+    if (density_matrices) *density_matrices = m->dm_count;
     return SP2_OK;
 }
 
