@@ -264,13 +264,20 @@ __global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __
 // One 512-thread workgroup per upper-triangular 128 x 128 tile; wave w
 // covers rows 32 (w >> 1) .. +32 and columns 64 (w & 1) .. +64 as two 32 x 32
 // blocks of v_mfma_i32_32x32x32_i8 per level (S x 2 accumulators of 16
-// int32).  Each K stage (32 bytes of k) stages 2 operands x S planes x 4 row
-// blocks of 1 KiB through LDS in the blocked layout, double buffered, with
-// the next stage's loads in flight in registers.
+// int32).  Each K stage stages 2 operands x S planes x 4 row blocks x KS
+// k blocks of 1 KiB through an LDS ring in the blocked layout, filled by
+// global -> LDS loads one stage ahead of the products.
 constexpr int QB = 128;          // tile
-constexpr int QK = 32;           // k bytes per stage
+constexpr int QK = 32;           // k bytes per block
 
-constexpr int I8_NST = 3;        // LDS ring depth (stages), filled by global->LDS loads
+// K stage: KS blocks of 32 k-bytes; ring depth NST.  Up to five planes fit a
+// 64-byte stage twice in LDS (2 x 80 KiB at five), which halves the
+// barriers per product against 32-byte stages; six planes keep 32-byte
+// stages three deep (3 x 48 KiB).
+template <int S> struct I8Stage {
+    static constexpr int KS = S <= 5 ? 2 : 1;
+    static constexpr int NST = S <= 5 ? 2 : 3;
+};
 
 // The staging ring; after the K loop the same LDS holds half of the finished
 // tile, transposed, so the mirrored (lower-triangle) copy is written as
@@ -281,10 +288,11 @@ constexpr int TR_LD = 129;
 template <int S>
 struct I8Smem {
     union {
-        int8_t buf[I8_NST][2 * S * 4][1024];   // [stage][op * S * 4 + slice * 4 + row block][block]
+        int8_t buf[I8Stage<S>::NST][2 * S * 4 * I8Stage<S>::KS][1024];   // [stage][((op S + slice) 4 + row block) KS + k block][block]
         double tr[64][TR_LD];                  // [tile column (one half)][tile row]
         struct {
             unsigned long long rm[128], cm[128];   // tile row / column maxima (upper-only mode)
+            double red[3][8];                      // per-wave partials, after the last use of tr / rm / cm
         } mx;
     };
 };
@@ -319,7 +327,8 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
 
-    constexpr int NBLK = 2 * S * 4;             // 1 KiB blocks per stage
+    constexpr int KS = I8Stage<S>::KS, NST = I8Stage<S>::NST;
+    constexpr int NBLK = 2 * S * 4 * KS;        // 1 KiB blocks per stage
     constexpr int PER = NBLK * 64 / 512;        // 16-byte chunks per thread
     static_assert((NBLK * 64) % 512 == 0, "stage must split evenly over 512 threads");
 
@@ -336,15 +345,16 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     const int foff = fr * 32 + 16 * ((lane >> 5) ^ dswz(fr));
     // K range: all of it, or the overlap of the two panels' surviving column
     // blocks of a thresholded X (one 32-byte stage per 32-column block)
-    int ks = 0, nk = ld / QK;
+    int ks = 0, nk = ld / (QK * KS);
     if (kc1 >= 0) {
         ks = kc0;
         nk = kc1;
     }
     if (THR) {
+        // rounded out to whole stages: the extra 32-column blocks are zero
         const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
-        ks = lo;
-        nk = lo > hi ? lo : hi + 1;
+        ks = lo / KS;
+        nk = lo > hi ? ks : hi / KS + 1;
     }
     // Fragment reads are written in order of first use (B plane 0, the A
     // planes, B planes 1 ..), the products in level order, and the scheduler
@@ -352,30 +362,36 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     // read LA product pairs ahead of its first use, so a stage starts after
     // 3 + LA reads instead of the whole set.
     auto compute = [&](int stg) {
-        auto rdA = [&](int sl) { return *reinterpret_cast<const v4i*>(&sm.buf[stg][sl * 4 + wr][foff]); };
-        auto rdB = [&](int uu, int c) {
-            return *reinterpret_cast<const v4i*>(&sm.buf[stg][S * 4 + uu * 4 + wc * 2 + c][foff]);
-        };
-        v4i a[S], b[S][2];
-        b[0][0] = rdB(0, 0);
-        b[0][1] = rdB(0, 1);
 #pragma unroll
-        for (int tt = 0; tt < S; ++tt) a[tt] = rdA(tt);
+        for (int kk = 0; kk < KS; ++kk) {
+            auto rdA = [&](int sl) {
+                return *reinterpret_cast<const v4i*>(&sm.buf[stg][(sl * 4 + wr) * KS + kk][foff]);
+            };
+            auto rdB = [&](int uu, int c) {
+                return *reinterpret_cast<const v4i*>(&sm.buf[stg][(S * 4 + uu * 4 + wc * 2 + c) * KS + kk][foff]);
+            };
+            v4i a[S], b[S][2];
+            b[0][0] = rdB(0, 0);
+            b[0][1] = rdB(0, 1);
 #pragma unroll
-        for (int uu = 1; uu < S; ++uu) {
-            b[uu][0] = rdB(uu, 0);
-            b[uu][1] = rdB(uu, 1);
+            for (int tt = 0; tt < S; ++tt) a[tt] = rdA(tt);
+#pragma unroll
+            for (int uu = 1; uu < S; ++uu) {
+                b[uu][0] = rdB(uu, 0);
+                b[uu][1] = rdB(uu, 1);
+            }
+            // level tt + uu accumulates a[tt] b[uu]
+#pragma unroll
+            for (int uu = 0; uu < S; ++uu)
+#pragma unroll
+                for (int tt = 0; tt < S - uu; ++tt)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        acc[tt + uu][c] =
+                            __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt], b[uu][c], acc[tt + uu][c], 0, 0, 0);
         }
-        // level tt + uu accumulates a[tt] b[uu]
-#pragma unroll
-        for (int uu = 0; uu < S; ++uu)
-#pragma unroll
-            for (int tt = 0; tt < S - uu; ++tt)
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    acc[tt + uu][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt], b[uu][c], acc[tt + uu][c], 0, 0, 0);
-        constexpr int LA = 2;                            // lookahead in reads
-        constexpr int R = 3 * S, P = S * (S + 1) / 2;   // reads, product pairs
+        constexpr int LA = 2;                                  // lookahead in reads
+        constexpr int R = 3 * S * KS, P = S * (S + 1) / 2 * KS;   // reads, product pairs
         constexpr int MID = R - 3 - LA;
         __builtin_amdgcn_sched_group_barrier(0x100, 3 + LA, 0);
 #pragma unroll
@@ -387,36 +403,39 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     };
     // Global -> LDS loads without register staging: wave w moves blocks w,
     // w + 8, ... of a stage, one 1 KiB block per instruction (16 bytes per
-    // lane).  Stage kt + 2 is issued while stage kt is multiplied; before
-    // reading stage kt a wave lets at most the PER loads of stage kt + 1 stay
-    // outstanding, and a barrier then makes every wave's blocks visible.
+    // lane).  Stage kt + NST - 1 is issued while stage kt is multiplied;
+    // before reading stage kt a wave waits for its own loads of stage kt (at
+    // most the PER loads of stage kt + 1 stay outstanding in a three-deep
+    // ring), and a barrier then makes every wave's blocks visible.
     auto issue = [&](int kb, int stg) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
             const int blk = w + 8 * m;
-            const int op = blk / (S * 4);
-            const int rem = blk - op * (S * 4);
+            const int kk = blk % KS, ob = blk / KS;
+            const int op = ob / (S * 4);
+            const int rem = ob - op * (S * 4);
             const int sl = rem >> 2, rb = rem & 3;
             const int grb = ((op ? j0 : i0) >> 5) + rb;
-            const int8_t* g = digits + sl * plane + ((size_t)grb * nb + kb) * 1024 + 16 * lane;
+            const int8_t* g = digits + sl * plane + ((size_t)grb * nb + kb * KS + kk) * 1024 + 16 * lane;
             __builtin_amdgcn_global_load_lds((const void*)g,
                                              (__attribute__((address_space(3))) void*)&sm.buf[stg][blk][0], 16, 0, 0);
         }
     };
     if (kmode == 2) nk = ks;          // accumulators come from the chunks
-    if (ks < nk) issue(ks, 0);
-    if (ks + 1 < nk) issue(ks + 1, 1);
+    for (int q = 0; q < NST - 1; ++q)
+        if (ks + q < nk) issue(ks + q, q);
     for (int kt = ks; kt < nk; ++kt) {
-        // this wave's blocks of stage kt have landed in LDS once at most the
-        // PER loads of stage kt + 1 are outstanding; the bare barrier (no
-        // fence, which would wait for every outstanding load) then covers the
-        // other waves' blocks, and every wave has finished reading the buffer
-        // that stage kt + 2 overwrites
-        if (kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                     // vmcnt(0)
+        // this wave's blocks of stage kt have landed in LDS once only stage
+        // kt + 1's loads (three-deep ring) or none (two-deep) are
+        // outstanding; the bare barrier (no fence, which would wait for every
+        // outstanding load) then covers the other waves' blocks, and every
+        // wave has finished reading the buffer that stage kt + NST - 1
+        // overwrites
+        if (NST == 3 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                                 // vmcnt(0)
         __builtin_amdgcn_s_barrier();
-        if (kt + 2 < nk) issue(kt + 2, (kt + 2 - ks) % I8_NST);
-        compute((kt - ks) % I8_NST);
+        if (kt + NST - 1 < nk) issue(kt + NST - 1, (kt + NST - 1 - ks) % NST);
+        compute((kt - ks) % NST);
     }
     __syncthreads();
     constexpr int CH = S * 2 * 16 * 512;   // int32 per chunk
@@ -536,7 +555,7 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     tr = wred_sum(tr);
     fro = wred_sum(fro);
     idm = wred_sum(idm);
-    __shared__ double red[3][8];
+    double (*red)[8] = sm.mx.red;
     if (lane == 0) {
         red[0][w] = tr;
         red[1][w] = fro;
@@ -577,7 +596,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
     if (w < t_full) {
         pos = xcd_deal(w, t_full);
     } else {
-        const int j = w - t_full, p = j / nsplit, ch = j - p * nsplit, nk = ld / QK;
+        const int j = w - t_full, p = j / nsplit, ch = j - p * nsplit, nk = ld / (QK * I8Stage<S>::KS);
         pos = t_full + p;
         kmode = 1;
         kc0 = ch * nk / nsplit;
@@ -660,8 +679,8 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     }
     // Tiles of a last wave that would leave at least half of the CUs idle
     // are split along K into nsplit <= 8 chunks (wave quantisation of the
-    // tail), when a tile has at least 128 K stages: shorter tiles cost less
-    // than summing their chunks.
+    // tail), when a tile's K loop covers at least 4096 columns: shorter tiles
+    // cost less than summing their chunks.
     int t_full = T, nsplit = 1;
     if (!THR && s.tail_split != 0 && s.tail_acc && ld / QK >= 128) {
         const int cus = device_cus();
