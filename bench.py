@@ -257,6 +257,11 @@ def main():
     ms64 = (time.perf_counter() - t0) * 1e3 / args.fp64_steps
     tflops64 = 2.0 * N ** 3 * st64["iterations"] / (ms64 * 1e-3) / 1e12
     log(f"  fp64: {ms64:.1f} ms/solve, {st64['iterations']} products, {tflops64:.2f} TFLOP/s")
+    # one more solve with the product kernel bracketed by HIP events (outside the timing above)
+    ctx.sp2_ctx_set_profiling(True)
+    st64p, _, _ = solve("fp64", D64)
+    ctx.sp2_ctx_set_profiling(False)
+    kms64 = st64p["prod_ms"][0] / max(st64p["prod_count"][0], 1)
 
     prec = args.precision
     log(f"{prec} path: warmup {args.warmup}, steps {args.steps}")
@@ -304,6 +309,15 @@ def main():
             "frac": round(achieved / PEAK[prec], 4), "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "kernel": kname, "kernel_ms_avg": round(kms, 4), "launches": cnt}
+    # the same instruction's rate with no memory traffic, measured on this device
+    # (pseudo-random operands: the power-limited clock of real data)
+    if prec == "int8x":
+        # the instruction's sustained rate on digit-range operands, measured here
+        # (the power-limited clock makes it data dependent)
+        log("int8 matrix-core rate probe")
+        pm = ctx.sp2_int8_mfma_rate() / 1e12
+        roof["peak_measured"] = round(pm, 1)
+        roof["frac_of_measured"] = round(achieved / pm, 4)
 
     out = {
         "metric": "SP2 TFLOP/s & solves/s (mixed vs FP64) at N=8192; p50/p99 served latency",
@@ -322,7 +336,10 @@ def main():
         "solves_per_s": round(1e3 / ms, 4),
         "products": iters,
         "fp64_path": {"ms_per_solve": round(ms64, 2), "tflops": round(tflops64, 3),
-                      "products": st64["iterations"]},
+                      "products": st64["iterations"],
+                      "kernel": "k_gemm_f64", "kernel_ms_avg": round(kms64, 4),
+                      "kernel_tflops": round(sym_flops / (kms64 * 1e-3) / 1e12, 2),
+                      "kernel_frac_of_peak": round(sym_flops / (kms64 * 1e-3) / 1e12 / PEAK["fp64"], 4)},
         "speedup_vs_fp64": round(ms64 / ms, 3),
         "err_vs_fp64_per_sqrtN": err, "max_dq_vs_fp64": dq, "idempotency": idem,
         "roofline": roof,

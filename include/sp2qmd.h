@@ -152,6 +152,17 @@ typedef struct {
 } sp2_tune_result;
 sp2_status sp2_autotune(sp2_ctx *ctx, int N, int precision, int slices, sp2_tune_result *out);
 
+/* Measurement aid, not a step of the path: the rate of the int8 product
+ * kernel's instruction (v_mfma_i32_32x32x32_i8; 2 ops per multiply-add) this
+ * device sustains with no memory traffic, the measured denominator beside
+ * the published peak in a roofline.  The rate depends on the data through the
+ * power-limited clock (zero operands run far faster), so every SIMD runs four
+ * accumulator chains on pseudo-random balanced 7-bit digits, the range of the
+ * digit planes, that change every product.  About 20 ms of work per launch
+ * on the context's stream; *ops_per_s gets the best of three launches after
+ * one warm-up.  SP2_EINVAL for a NULL output. */
+sp2_status sp2_int8_mfma_rate(sp2_ctx *ctx, double *ops_per_s);
+
 /* Net Mulliken charges of an orthogonal basis (net-charge equation of the
  * SCC-TB subsection, S = I): q_i = 2 sum_{alpha in atom i} D_{i alpha,i alpha}
  * - z_val (electron excess).  D: (4 n_atoms)^2 device; q_out: n_atoms device. */

@@ -101,6 +101,7 @@ _SIGS = {
                                 ctypes.POINTER(Sp2Stats)]),
     "sp2_mulliken": (_I, [_P, _I, _P, _D, _P]),
     "sp2_autotune": (_I, [_P, _I, _I, _I, ctypes.POINTER(TuneResult)]),
+    "sp2_int8_mfma_rate": (_I, [_P, ctypes.POINTER(_D)]),
     "sp2_band_energy": (_I, [_P, _I, _P, _P, ctypes.POINTER(_D)]),
     "tb_hamiltonian": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P]),
     "tb_forces": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P, _P,
@@ -239,6 +240,13 @@ class Context:
                                       ctypes.byref(opts) if opts is not None else None,
                                       _ptr(D), ctypes.byref(stats))
         return st, stats.to_dict()
+
+    def sp2_int8_mfma_rate(self) -> float:
+        """Sustained rate (ops/s) of v_mfma_i32_32x32x32_i8 on this device with no
+        memory traffic, on operands in the digit planes' range."""
+        v = _D()
+        self._check(lib().sp2_int8_mfma_rate(self._h, ctypes.byref(v)), "sp2_int8_mfma_rate")
+        return v.value
 
     def sp2_autotune(self, N: int, precision="int8x", slices: int = 5):
         """Time the product kernel per tile order at size N; the choice is kept

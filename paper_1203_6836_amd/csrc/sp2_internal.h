@@ -177,6 +177,10 @@ hipError_t launch_finalize_upper(const double* buf0, const double* buf1, int ld,
                                  const State* st, hipStream_t s);
 // Symmetric pseudo-random ld x ld operand in (-1/2, 1/2) (timing only).
 hipError_t launch_fill_test_matrix(double* X, int ld, hipStream_t s);
+// int8 matrix-core rate probe: 256 threads per workgroup, iters iterations
+// of kInt8RateOpsPerIter ops per wave
+constexpr double kInt8RateOpsPerIter = 4.0 * 65536.0;
+hipError_t launch_int8_rate(int grid, int iters, double* out, hipStream_t stream);
 hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hipStream_t s);
 hipError_t launch_dot(const double* A, const double* B, size_t n, double* part, int* nslots,
                       double* out, hipStream_t s);

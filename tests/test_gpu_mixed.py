@@ -161,3 +161,12 @@ def test_tail_split_is_exact(ctx, dims):
     say(f"  iters {s0['iterations']} / {s1['iterations']}  ms {s0['ms']:.1f} / {s1['ms']:.1f}")
     assert s0["iterations"] == s1["iterations"]
     assert torch.equal(D0, D1)
+
+
+def test_int8_mfma_rate_probe(ctx):
+    """The measured int8 matrix-core rate used beside the published peak is
+    plausible: above a third of the published 5.0 POP/s, at most 5 % over it."""
+    say("case sp2_int8_mfma_rate")
+    r = ctx.sp2_int8_mfma_rate() / 1e12
+    say(f"  int8 {r:.0f} TOP/s of 5000")
+    assert 5000.0 / 3 < r <= 5000.0 * 1.05
