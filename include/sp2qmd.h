@@ -69,14 +69,17 @@ typedef struct {
     int tile_group;      /* order of the 128x128 product tiles: G x G super-tiles
                             dealt to the XCDs (G > 0), 0 = plain row-major, -1
                             (default) = the value sp2_autotune chose for this
-                            size and precision, else 8.  Results do not depend
-                            on it.                                              */
-    int tail_split;      /* INT8X, N >= 4096: when the tiles of the last wave
-                            of product workgroups would leave at least half of
-                            the compute units idle, split their K loops into up
-                            to 8 chunks run in parallel and summed exactly (-1
-                            default: on; 0: never).  Results do not depend on
-                            it.                                                 */
+                            size and precision, else 8.  INT8X results do not
+                            depend on it; FP64 products with a tail split (see
+                            below) may differ in the last bits               */
+    int tail_split;      /* N >= 4096: when the tiles of the last wave of
+                            product workgroups would leave at least half of the
+                            workgroup slots idle, split their K loops into
+                            chunks run in parallel, then summed: INT8X up to 8
+                            chunks, summed exactly (results do not depend on
+                            it); FP64 up to 16 chunks, summed in chunk order
+                            (results change at the rounding level).  -1
+                            (default): on; 0: never.                          */
 } sp2_options;
 
 typedef struct {

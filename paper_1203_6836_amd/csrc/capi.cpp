@@ -52,6 +52,8 @@ struct sp2_ctx {
     size_t natcap = 0;
     int* env = nullptr;        // per-panel surviving column-block ranges (thresholded X)
     size_t envcap = 0;
+    double* f64tail = nullptr; // chunk accumulators of split last-wave FP64 tiles
+    size_t f64tailcap = 0;
     // qmd_evaluate scratch: H[n], D, zero charges, forces
     double* eH = nullptr;
     double* eD = nullptr;
@@ -87,6 +89,20 @@ static sp2_status grow(sp2_ctx* c, void** p, size_t* cap, size_t need_bytes) {
         return fail(c, SP2_ENOMEM, "device allocation of " + std::to_string(need_bytes) + " bytes failed");
     }
     *cap = need_bytes;
+    return SP2_OK;
+}
+
+// Chunk buffer of the FP64 product's tail split (two workgroups per CU, one
+// chunk each at most), for products whose K loop covers >= 4096 columns.
+static sp2_status f64_tail_buffer(sp2_ctx* c, int ld, int tail_split, double** buf, size_t* bytes) {
+    *buf = nullptr;
+    *bytes = 0;
+    if (tail_split == 0 || ld < 4096) return SP2_OK;
+    const size_t need = (size_t)2 * device_cus() * kF64Chunk * sizeof(double);
+    sp2_status s = grow(c, (void**)&c->f64tail, &c->f64tailcap, need);
+    if (s != SP2_OK) return s;
+    *buf = c->f64tail;
+    *bytes = c->f64tailcap;
     return SP2_OK;
 }
 
@@ -153,7 +169,7 @@ void sp2_ctx_destroy(sp2_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->chk, c->V, c->eatom, c->qtmp, c->env,
-                   c->eH, c->eD, c->ezero, c->eF};
+                   c->eH, c->eD, c->ezero, c->eF, c->f64tail};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     split_free(c->split);
@@ -251,6 +267,13 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     const double nb = (double)((N + 31) / 32);
     a.total_blocks = o.tau > 0.0 ? nb * nb : 0.0;
 
+    // the FP64 product runs in FP64 mode, in the FP64 head of INT8X and in the
+    // FP32 tail of BF16X2
+    double* f64tail = nullptr;
+    size_t f64tail_bytes = 0;
+    if (!int8x || o.fp64_head > 0)
+        if ((s = f64_tail_buffer(c, ld, o.tail_split, &f64tail, &f64tail_bytes)) != SP2_OK) return s;
+
     int* env = nullptr;
     if (o.tau > 0.0) {
         size_t eb = c->envcap;
@@ -278,7 +301,8 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
             if (pe) HIPCHK(c, hipEventRecord(pe[0], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
-            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, env, tile_group));
+            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, env, tile_group, f64tail,
+                                      f64tail_bytes));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
@@ -433,6 +457,12 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
     std::memset(c->st_host, 0, sizeof(State));
     c->st_host->phase = precision == SP2_PREC_FP64 ? 0 : 1;
     HIPCHK(c, hipMemcpyAsync(c->st, c->st_host, sizeof(State), hipMemcpyHostToDevice, st));
+    double* f64tail = nullptr;
+    size_t f64tail_bytes = 0;
+    if (precision == SP2_PREC_FP64) {
+        sp2_status s = f64_tail_buffer(c, ld, -1, &f64tail, &f64tail_bytes);
+        if (s != SP2_OK) return s;
+    }
     std::vector<int> cand;
     for (int g : {0, 4, 8, 16, 32})
         if (g == 0 || g < nt) cand.push_back(g);
@@ -443,7 +473,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         int ns = 0;
         c->split.tile_group = g;
         if (precision == SP2_PREC_FP64) {
-            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, g));
+            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, g, f64tail, f64tail_bytes));
         } else {
             HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, nullptr));

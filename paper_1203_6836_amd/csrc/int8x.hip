@@ -649,8 +649,8 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __r
     }
 }
 
-// Compute units of the current device (one product workgroup fits on a CU).
-static int device_cus() {
+// Compute units of the current device (one int8 product workgroup fits on a CU).
+int device_cus() {
     static int n = 0;
     if (n <= 0) {
         int dev = 0;

@@ -10,6 +10,8 @@
 // (ld = N rounded up to 128, zero outside the N x N corner) used ping-pong;
 // the zero padding makes every tile of the product full, with no bounds
 // checks in the inner loop, and does not change X^2, traces or norms.
+#include <type_traits>
+
 #include "sp2_internal.h"
 
 namespace sp2 {
@@ -375,23 +377,21 @@ __device__ __forceinline__ int xcd_remap(int w, int T) {
     return x * q + (x < r ? x : r) + k;
 }
 
-// At most 256 registers per lane: the accumulators then stay in VGPR form
-// (with the whole register file the compiler splits them between VGPRs and
-// AGPRs and copies them across on every K stage) and two workgroups fit on
-// a CU (LDS 64 KiB each), so one hides the other's barriers and epilogue.
+// One 128 x 128 output tile (bi, bj); all 256 threads take part.  kmode 0:
+// the whole tile; kmode 1: only K stages [kc0, kc1), whose accumulators are
+// stored to chunk (one chunk of a tile split along K); kmode 2: no K loop,
+// the accumulators are the sum of the nchunks chunks at chunk, added in
+// chunk order, then the epilogue.  Chunk layout: d4 [16 blocks][256
+// threads] (accumulator block m * 4 + n of each thread), 128 KiB.
 template <bool THR>
-__global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
-                                                     double* __restrict__ buf1, int ld,
-                                                     const State* __restrict__ st,
-                                                     double* __restrict__ part,
-                                                     const int* __restrict__ env, int tile_group) {
+__device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __restrict__ buf1, int ld,
+                                         const State* __restrict__ st, double* __restrict__ part,
+                                         const int* __restrict__ env, int bi, int bj, int kmode, int kc0,
+                                         int kc1, double* __restrict__ chunk, int nchunks) {
     // phase 0: FP64 products; phase 2: the FP32 tail of the BF16 hi+lo mode
     // (FP32-valued operands, update rounded to FP32)
-    if (st->done || (st->phase != 0 && st->phase != 2)) return;
     const bool r32 = st->phase == 2;
     const int nt = ld / GB;
-    int bi, bj;
-    tile_of_block(blockIdx.x, nt, tile_group, bi, bj);
     const int t = tri_index(bi, bj, nt);
     const double* __restrict__ Xc = st->cur ? buf1 : buf0;
     double* __restrict__ Xn = st->cur ? buf0 : buf1;
@@ -439,11 +439,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
     // ranges of 32-column blocks that survived the threshold; outside it one
     // of the two operands is zero.
     int ks = 0, ke = ld / GK;
+    if (kc1 >= 0) {
+        ks = kc0;
+        ke = kc1;
+    }
     if (THR) {
         const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
         ks = lo * 2;                           // 16-wide stages, two per 32-column block
         ke = lo > hi ? ks : (hi + 1) * 2;
     }
+    if (kmode == 2) ke = ks;                   // accumulators come from the chunks
     auto compute = [&](int stg) {
 #pragma unroll
         for (int k4 = 0; k4 < GK / 4; ++k4) {
@@ -502,33 +507,66 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
     }
 #endif
 
+    if (kmode == 1) {
+        d4* out = reinterpret_cast<d4*>(chunk);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) out[(m * 4 + n) * 256 + tid] = acc[m][n];
+        return;
+    }
+    if (kmode == 2) {
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const d4* in = reinterpret_cast<const d4*>(chunk + (size_t)ch * kF64Chunk);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) acc[m][n] += in[(m * 4 + n) * 256 + tid];
+        }
+    }
+
     // fused SP2 update + partials
     const int br = st->branch;
     const bool mirror = bi != bj;
     double tr = 0.0, fro = 0.0, idm = 0.0;
+    // one straight-line body per (FP32 rounding, mirrored) pair: both flags
+    // are uniform, and branching on them per element keeps many values live
+    // across blocks
+    auto epilogue = [&](auto r32c, auto mirc) {
+        constexpr bool R32 = decltype(r32c)::value, MIR = decltype(mirc)::value;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < 4; ++m) {
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const int gj = j0 + wj * 64 + n * 16 + (lane & 15);
+            for (int n = 0; n < 4; ++n) {
+                const int gj = j0 + wj * 64 + n * 16 + (lane & 15);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                // v_mfma_f64_16x16x4f64 result: lane l, element r is row (l >> 4) + 4 r, column l & 15
-                const int gi = i0 + wi * 64 + m * 16 + (lane >> 4) + 4 * r;
-                const double p = acc[m][n][r];
-                const double x = Xc[(size_t)gi * ld + gj];
-                double xn = br ? 2.0 * x - p : p;
-                if (r32) {
-                    const float pf = (float)p, xf = (float)x;
-                    xn = (double)(br ? 2.0f * xf - pf : pf);
+                for (int r = 0; r < 4; ++r) {
+                    // v_mfma_f64_16x16x4f64 result: lane l, element r is row (l >> 4) + 4 r, column l & 15
+                    const int gi = i0 + wi * 64 + m * 16 + (lane >> 4) + 4 * r;
+                    const double p = acc[m][n][r];
+                    const double x = Xc[(size_t)gi * ld + gj];
+                    double xn = br ? 2.0 * x - p : p;
+                    if constexpr (R32) {
+                        const float pf = (float)p, xf = (float)x;
+                        xn = (double)(br ? 2.0f * xf - pf : pf);
+                    }
+                    Xn[(size_t)gi * ld + gj] = xn;
+                    if constexpr (MIR) Xn[(size_t)gj * ld + gi] = xn;
+                    tr += gi == gj ? xn : 0.0;
+                    fro += xn * xn;
+                    idm += (p - x) * (p - x);
                 }
-                Xn[(size_t)gi * ld + gj] = xn;
-                if (mirror) Xn[(size_t)gj * ld + gi] = xn;
-                if (gi == gj) tr += xn;
-                fro += xn * xn;
-                idm += (p - x) * (p - x);
             }
         }
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (r32) {
+        if (mirror) epilogue(T_{}, T_{});
+        else epilogue(T_{}, F_{});
+    } else {
+        if (mirror) epilogue(F_{}, T_{});
+        else epilogue(F_{}, F_{});
     }
     const double wgt = mirror ? 2.0 : 1.0;
     __shared__ double sh[4];
@@ -540,6 +578,55 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
         part[3 * t + 1] = wgt * bfr;
         part[3 * t + 2] = wgt * bid;
     }
+}
+
+// At most 256 registers per lane: the accumulators then stay in VGPR form
+// (with the whole register file the compiler splits them between VGPRs and
+// AGPRs and copies them across on every K stage) and two workgroups fit on
+// a CU (LDS 64 KiB each), so one hides the other's barriers and epilogue.
+// Workgroups [0, t_full): whole tiles at visiting positions [0, t_full),
+// dealt over the XCDs.  Workgroups from t_full on: the tiles at positions
+// t_full, t_full + 1, ... (the last, partly filled wave of a launch), each
+// split into nsplit chunks of the K loop whose accumulators go to chunk;
+// k_gemm_f64_tail finishes them.
+template <bool THR>
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
+                                                     double* __restrict__ buf1, int ld,
+                                                     const State* __restrict__ st,
+                                                     double* __restrict__ part,
+                                                     const int* __restrict__ env, int tile_group, int t_full,
+                                                     int nsplit, double* __restrict__ chunk) {
+    if (st->done || (st->phase != 0 && st->phase != 2)) return;
+    const int nt = ld / GB, w = blockIdx.x;
+    int pos, kmode = 0, kc0 = 0, kc1 = -1;
+    double* cacc = nullptr;
+    if (w < t_full) {
+        pos = xcd_deal(w, t_full);
+    } else {
+        const int j = w - t_full, p = j / nsplit, ch = j - p * nsplit, nk = ld / GK;
+        pos = t_full + p;
+        kmode = 1;
+        kc0 = ch * nk / nsplit;
+        kc1 = (ch + 1) * nk / nsplit;
+        cacc = chunk + (size_t)j * kF64Chunk;
+    }
+    int bi, bj;
+    order_tile(pos, nt, tile_group, bi, bj);
+    f64_tile<THR>(buf0, buf1, ld, st, part, env, bi, bj, kmode, kc0, kc1, cacc, 0);
+}
+
+// Epilogue of the split tiles: workgroup p sums the nsplit chunks of the tile
+// at visiting position t_full + p and applies the update.
+__global__ __launch_bounds__(256, 2) void k_gemm_f64_tail(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                          int ld, const State* __restrict__ st,
+                                                          double* __restrict__ part, int tile_group, int t_full,
+                                                          int nsplit, double* __restrict__ chunk) {
+    if (st->done || (st->phase != 0 && st->phase != 2)) return;
+    const int nt = ld / GB, p = blockIdx.x;
+    int bi, bj;
+    order_tile(t_full + p, nt, tile_group, bi, bj);
+    f64_tile<false>(buf0, buf1, ld, st, part, nullptr, bi, bj, 2, 0, -1, chunk + (size_t)p * nsplit * kF64Chunk,
+                    nsplit);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -674,14 +761,34 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
-                           int* nslots, hipStream_t s, const int* env, int tile_group) {
+                           int* nslots, hipStream_t s, const int* env, int tile_group, double* tail_buf,
+                           size_t tail_bytes) {
     const int nt = ld / GB;
     const int T = tri_tiles(nt);
     *nslots = T;
+    // Tiles of a last wave that would leave at least half of the workgroup
+    // slots (two per CU) idle are split along K into nsplit <= 16 chunks,
+    // when a tile's K loop covers at least 4096 columns.
+    int t_full = T, nsplit = 1;
+    if (!env && tail_buf && ld / GK >= 256) {
+        const int slots = 2 * device_cus();
+        const int r = T % slots;
+        if (r > 0 && 2 * r <= slots) {
+            nsplit = std::min(16, slots / r);
+            if (nsplit >= 2 && (size_t)r * nsplit * kF64Chunk * sizeof(double) <= tail_bytes) t_full = T - r;
+            else nsplit = 1;
+        }
+    }
+    const int grid = t_full + (T - t_full) * nsplit;
     if (env)
-        hipLaunchKernelGGL(k_gemm_f64<true>, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env, tile_group);
+        hipLaunchKernelGGL(k_gemm_f64<true>, dim3(grid), dim3(256), 0, s, buf0, buf1, ld, st, part, env, tile_group,
+                           t_full, nsplit, tail_buf);
     else
-        hipLaunchKernelGGL(k_gemm_f64<false>, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, env, tile_group);
+        hipLaunchKernelGGL(k_gemm_f64<false>, dim3(grid), dim3(256), 0, s, buf0, buf1, ld, st, part, env,
+                           tile_group, t_full, nsplit, tail_buf);
+    if (t_full < T)
+        hipLaunchKernelGGL(k_gemm_f64_tail, dim3(T - t_full), dim3(256), 0, s, buf0, buf1, ld, st, part, tile_group,
+                           t_full, nsplit, tail_buf);
     return hipGetLastError();
 }
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,

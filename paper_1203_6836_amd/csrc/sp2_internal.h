@@ -168,8 +168,15 @@ hipError_t launch_ctrl_step(const double* part, int nslots, State* st, CtrlArgs 
 hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s);
 // env (may be null): per 128-row panel p, [env[2p], env[2p+1]] is the range
 // of 32-column blocks holding nonzeros of a thresholded X.
+// FP64 product.  tail_buf (tail_bytes, may be NULL: no split): chunk
+// accumulators of the last-wave tiles split along K, kF64Chunk doubles each;
+// 2 x CUs chunks at most.
+constexpr size_t kF64Chunk = 16 * 4 * 256;
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
-                           int* nslots, hipStream_t s, const int* env = nullptr, int tile_group = 8);
+                           int* nslots, hipStream_t s, const int* env = nullptr, int tile_group = 8,
+                           double* tail_buf = nullptr, size_t tail_bytes = 0);
+// compute units of the current device (cached on first use)
+int device_cus();
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
                            const State* st, hipStream_t s);
 // D from the upper triangle of the result buffer (upper-only int8 products).

@@ -135,6 +135,43 @@ def test_fp64_n2048_against_oracle(ctx):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("dims,seed", [((8, 8, 16), 1), ((8, 16, 16), 2)])
+def test_fp64_tail_split(ctx, dims, seed):
+    """FP64 products whose last wave of tiles is split along K (N = 4096: 16
+    of 528 tiles into 16 chunks; N = 8192: 32 of 2080) against the same solve
+    without the split: same products and branches, D equal to rounding."""
+    import torch
+    import paper_1203_6836_amd as p
+    say(f"case fp64 tail split on/off dims={dims}")
+    pos = synth.lattice_positions(dims, seed=seed)
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, to_dev(pos))
+    nocc = 2 * len(pos)
+    D0, s0 = ctx.sp2_density_matrix(H, nocc, p.options("fp64", tail_split=0))
+    D1, s1 = ctx.sp2_density_matrix(H, nocc, p.options("fp64"))
+    d = float(torch.linalg.norm(D1 - D0)) / H.shape[0] ** 0.5
+    say(f"  iters {s0['iterations']} / {s1['iterations']}  ms {s0['ms']:.1f} / {s1['ms']:.1f}  "
+        f"|dD|/sqrtN {d:.2e}")
+    assert s0["iterations"] == s1["iterations"]
+    assert s0["branches"] == s1["branches"]
+    assert d <= 1e-12
+    D2, _ = ctx.sp2_density_matrix(H, nocc, p.options("fp64"))
+    assert torch.equal(D1, D2)           # deterministic
+
+
+def test_fp64_n4096_split_against_oracle(ctx):
+    """The split FP64 path (N = 4096) against the oracle's SP2 loop."""
+    import paper_1203_6836_amd as p
+    say("case fp64 8x8x16 (N=4096, tail split) vs oracle")
+    pos, H = oracle_H((8, 8, 16), 1)
+    nocc = 2 * len(pos)
+    ref = osp2.sp2(H, nocc)
+    D, st = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("fp64"))
+    err = np.linalg.norm(D.cpu().numpy() - ref.D) / np.sqrt(H.shape[0])
+    say(f"  iters gpu={st['iterations']} oracle={ref.iterations} err/sqrtN={err:.2e}")
+    assert st["iterations"] == ref.iterations
+    assert err <= 1e-10
+
+
 def test_fp64_full_size_properties(ctx):
     """N = 8192 in the benchmark's configuration: properties that hold at any size."""
     import torch
