@@ -13,6 +13,7 @@
 // epilogue, which then applies the SP2 update exactly like the FP64 product.
 //
 // Work layout, storage and staging: see the comments at the kernels.
+#include <atomic>
 #include <algorithm>
 
 #include "split_internal.h"
@@ -649,14 +650,16 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __r
     }
 }
 
-// Compute units of the current device (one int8 product workgroup fits on a CU).
+// Compute units of the current device (cached per device; callers may be on
+// several threads).
 int device_cus() {
-    static int n = 0;
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cached[dev].load(std::memory_order_relaxed);
     if (n <= 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                     hipSuccess || n <= 0)
-            n = 256;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev].store(n, std::memory_order_relaxed);
     }
     return n;
 }
