@@ -228,7 +228,8 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     const size_t ld2 = (size_t)ld * ld;
     const int nt = ld / kTile;
     const size_t nslot_max = std::max<size_t>({(size_t)(N + 3) / 4 * 2, (size_t)ld / 4 * 3,
-                                               (size_t)tri_tiles(nt) * 3, 1024, split_part_slots(ld) * 3});
+                                               (size_t)tri_tiles(nt) * 3, 1024, (size_t)kDotBlocks,
+                                               split_part_slots(ld) * 3});
     sp2_status s;
     size_t xbytes = c->xcap * sizeof(double) * 2;
     if ((s = grow(c, (void**)&c->xbuf, &xbytes, 2 * ld2 * sizeof(double))) != SP2_OK) return s;
@@ -525,7 +526,8 @@ extern "C" sp2_status sp2_band_energy(sp2_ctx* c, int N, const double* D, const 
     HIPCHK(c, hipSetDevice(c->device));
     sp2_status s;
     size_t pbytes = c->partcap * sizeof(double);
-    if ((s = grow(c, (void**)&c->part, &pbytes, 1024 * sizeof(double))) != SP2_OK) return s;
+    if ((s = grow(c, (void**)&c->part, &pbytes, (size_t)std::max(1024, kDotBlocks) * sizeof(double))) != SP2_OK)
+        return s;
     c->partcap = pbytes / sizeof(double);
     int ns = 0;
     HIPCHK(c, launch_dot(D, H, (size_t)N * N, c->part, &ns, c->scal, c->stream));

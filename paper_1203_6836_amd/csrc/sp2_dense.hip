@@ -703,13 +703,26 @@ __global__ __launch_bounds__(256) void k_mulliken(const double* __restrict__ D, 
 
 // sum_e A[e] B[e] with a fixed grid of 512 workgroups, then a one-workgroup
 // fixed-order reduction into *out (device).
-constexpr int kDotBlocks = 512;
+// Partial sums of sum_e A_e B_e, one per workgroup, in a fixed order;
+// 16-byte loads when both operands are 16-byte aligned.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ A,
                                                   const double* __restrict__ B, size_t n,
                                                   double* __restrict__ part) {
     double s = 0.0;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)kDotBlocks * 256)
-        s += A[e] * B[e];
+    const size_t stride = (size_t)kDotBlocks * 256;
+    if (VEC) {
+        const double2* __restrict__ A2 = reinterpret_cast<const double2*>(A);
+        const double2* __restrict__ B2 = reinterpret_cast<const double2*>(B);
+        for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n / 2; e += stride) {
+            const double2 a = A2[e], b = B2[e];
+            s += a.x * b.x;
+            s += a.y * b.y;
+        }
+        if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) s += A[n - 1] * B[n - 1];
+    } else {
+        for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) s += A[e] * B[e];
+    }
     __shared__ double sh[4];
     const double b = block_sum256(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = b;
@@ -816,7 +829,10 @@ hipError_t launch_mulliken(const double* D, int n_atoms, double z, double* q, hi
 hipError_t launch_dot(const double* A, const double* B, size_t n, double* part, int* nslots,
                       double* out, hipStream_t s) {
     *nslots = kDotBlocks;
-    hipLaunchKernelGGL(k_dot_part, dim3(kDotBlocks), dim3(256), 0, s, A, B, n, part);
+    if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0)
+        hipLaunchKernelGGL(k_dot_part<true>, dim3(kDotBlocks), dim3(256), 0, s, A, B, n, part);
+    else
+        hipLaunchKernelGGL(k_dot_part<false>, dim3(kDotBlocks), dim3(256), 0, s, A, B, n, part);
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, part, kDotBlocks, out);
     return hipGetLastError();
 }

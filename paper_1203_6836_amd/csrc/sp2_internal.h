@@ -151,7 +151,8 @@ constexpr double kGapIdem = 1.0 / 16.0;
 constexpr int kGapMinIter = 100;
 // H must be finite and symmetric to within kSymTol * max |H_ij|.
 constexpr double kSymTol = 1e-12;
-constexpr int kCheckGrid = 1024;   // workgroups (and partial pairs) of the H check
+constexpr int kCheckGrid = 2048;   // workgroups (and partial pairs) of the H check
+constexpr int kDotBlocks = 2048;   // workgroups (and partials) of the trace-of-product kernel
 
 // ---- launchers (sp2_dense.hip) ----
 hipError_t launch_gershgorin(const double* H, int N, double* part, int* nslots, hipStream_t s);
