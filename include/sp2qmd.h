@@ -299,7 +299,10 @@ typedef struct {
     int slices;                /* int8 digit planes, 2..6 (default 5)                */
     int max_iter;              /* products per solve (default 100)                   */
     double idem_tol;           /* converged when ||X^2 - X||_F < idem_tol (1e-10)    */
-    int iters_per_tick;        /* products per scheduler tick, 1..16 (default 1)     */
+    int iters_per_tick;        /* products per scheduler tick, 1..16 (default 8):
+                                  more amortize the host round trip of a tick,
+                                  a finished system waits out the rest of its
+                                  tick (its launches return at once)            */
 } sp2_server_options;
 
 typedef struct sp2_server sp2_server;

@@ -4,21 +4,26 @@
 // scheduler thread admits them into device "slots" whenever a slot is free
 // and the request's footprint fits in the device arena (one allocation of
 // hbm_budget_bytes made at creation, carved by a first-fit allocator), runs
-// the per-system start kernels (bounds, X_0, first branch), and then advances
-// every active system by one SP2 product per tick with three grouped launches
-// (encode, product, control) that cover all tiles of all active systems.  The
-// three launches are captured once in a hipGraph and replayed every tick;
-// only the device-side work description changes between ticks.  After each
-// tick the control states are read back; finished systems are retired (D and
-// charges copied to the request's pinned host buffers, arena space freed) and
-// waiting requests are admitted in their place, so new work joins systems
-// that are mid-solve.  Each request's result depends only on its own H
+// H is uploaded on a copy stream; once it has landed, the per-system start
+// kernels (H check, bounds, X_0, first branch) run on the compute stream and
+// the system joins the group, which advances every started system by
+// iters_per_tick SP2 products per tick with grouped launches (encode,
+// product, control) that cover all tiles of all systems in the group.  The
+// launches are captured once in a hipGraph and replayed every tick; only the
+// device-side work description changes between ticks.  After each tick the
+// control states are read back; finished systems leave the group (D and the
+// charges are formed on the compute stream and copied to the request's
+// pinned host buffers on the copy stream), and waiting requests are admitted
+// in their place, so new work joins systems that are mid-solve and no tick
+// waits for a host transfer.  A completion thread waits for each download
+// and then frees the request's arena block and wakes its waiter.  Each request's result depends only on its own H
 // (tiling, reductions and branch decisions are per system), so it is the same
 // alone and in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <atomic>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -151,6 +156,9 @@ struct Request {
     size_t off = 0;        // arena block
     Layout L{};
     int slot = -1;
+    bool started = false;  // start kernels issued: part of the group
+    hipEvent_t ev_up = nullptr;    // H landed on the device / D formed (compute stream)
+    hipEvent_t ev_down = nullptr;  // D and q landed in host memory
     sp2_stats stats{};
 };
 
@@ -160,7 +168,8 @@ struct sp2_server {
     sp2_ctx* ctx = nullptr;
     int device = 0;
     sp2_server_options opt{};
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // kernels
+    hipStream_t copy = nullptr;         // host <-> device transfers of requests
     char* arena_mem = nullptr;
     Arena arena;
     GroupDesc* g_dev = nullptr;
@@ -170,10 +179,13 @@ struct sp2_server {
     hipGraphExec_t graph = nullptr;
     PinnedPool pinned;
     std::vector<Request*> slots;
-    std::thread worker;
+    std::vector<Request*> uploading;    // admitted, H in flight (worker thread only)
+    std::thread worker, completer;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_down;
     std::deque<Request*> queue;
+    std::deque<Request*> downloading;   // results in flight, in order of issue (under mu)
+    bool worker_done = false;
     std::map<uint64_t, Request*> reqs;
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -185,9 +197,12 @@ struct sp2_server {
     double busy_s = 0;
 
     void loop();
+    void complete_loop();
     bool admit_locked(std::vector<Request*>& fresh);
+    sp2_status begin_upload(Request* r);
     sp2_status start_system(Request* r);
     sp2_status retire(std::vector<Request*>& finished);
+    void finish_locked(Request* r, double t);
     void build_group();
 };
 
@@ -198,7 +213,7 @@ void sp2_server::build_group() {
     int n = 0, toff = 0, roff = 0;
     for (int s = 0; s < (int)slots.size(); ++s) {
         Request* r = slots[s];
-        if (!r) continue;
+        if (!r || !r->started) continue;
         const int ld = (int)align_up((size_t)r->N, kTile);
         const int nt = ld / kTile;
         char* b = arena.base + r->off;
@@ -252,7 +267,22 @@ bool sp2_server::admit_locked(std::vector<Request*>& fresh) {
     return any;
 }
 
-// Upload H and run the per-system start kernels (bounds, X_0, first branch).
+// Copy H to the request's arena block on the copy stream; ev_up marks its
+// arrival.
+sp2_status sp2_server::begin_upload(Request* r) {
+    const unsigned flags = hipEventDisableTiming | hipEventBlockingSync;
+    if (hipEventCreateWithFlags(&r->ev_up, flags) != hipSuccess ||
+        hipEventCreateWithFlags(&r->ev_down, flags) != hipSuccess)
+        return SP2_EDEVICE;
+    double* H = reinterpret_cast<double*>(arena.base + r->off + r->L.H);
+    if (hipMemcpyAsync(H, r->H, (size_t)r->N * r->N * 8, hipMemcpyHostToDevice, copy) != hipSuccess ||
+        hipEventRecord(r->ev_up, copy) != hipSuccess)
+        return SP2_EDEVICE;
+    return SP2_OK;
+}
+
+// Per-system start kernels (H check, bounds, X_0, first branch) on the
+// compute stream, once H has landed.
 sp2_status sp2_server::start_system(Request* r) {
     const int N = r->N;
     const int ld = (int)align_up((size_t)N, kTile);
@@ -261,7 +291,6 @@ sp2_status sp2_server::start_system(Request* r) {
     double* X0 = reinterpret_cast<double*>(b + r->L.X);
     double* part = reinterpret_cast<double*>(b + r->L.part);
     State* st = st_dev + r->slot;
-    if (hipMemcpyAsync(H, r->H, (size_t)N * N * 8, hipMemcpyHostToDevice, stream) != hipSuccess) return SP2_EDEVICE;
     CtrlArgs a{};
     a.n_occ = (double)r->n_occ;
     a.idem_tol = opt.idem_tol;
@@ -279,7 +308,13 @@ sp2_status sp2_server::start_system(Request* r) {
     return SP2_OK;
 }
 
+// Finished systems leave the group: statistics from the control state; for a
+// solved system D and the charges are formed on the compute stream and
+// copied out on the copy stream after it (ev_up, then ev_down), and the
+// completion thread finishes the request; a failed one finishes at once.
 sp2_status sp2_server::retire(std::vector<Request*>& finished) {
+    sp2_status rc = SP2_OK;
+    std::vector<Request*> failed;
     for (Request* r : finished) {
         const int N = r->N;
         const int ld = (int)align_up((size_t)N, kTile);
@@ -288,46 +323,86 @@ sp2_status sp2_server::retire(std::vector<Request*>& finished) {
         double* D = reinterpret_cast<double*>(b + r->L.D);
         double* q = reinterpret_cast<double*>(b + r->L.q);
         const State& h = st_host[r->slot];
-        if (h.done == 1 || h.done == 2) {
-            if (launch_finalize(X0, X0 + (size_t)ld * ld, ld, N, D, st_dev + r->slot, stream) != hipSuccess)
-                return SP2_EDEVICE;
-            if (N % 4 == 0 && launch_mulliken(D, N / 4, 4.0, q, stream) != hipSuccess) return SP2_EDEVICE;
-            if (hipMemcpyAsync(r->D, D, (size_t)N * N * 8, hipMemcpyDeviceToHost, stream) != hipSuccess)
-                return SP2_EDEVICE;
-            if (N % 4 == 0 &&
-                hipMemcpyAsync(r->q, q, (size_t)(N / 4) * 8, hipMemcpyDeviceToHost, stream) != hipSuccess)
-                return SP2_EDEVICE;
+        sp2_stats& st = r->stats;
+        std::memset(&st, 0, sizeof(st));
+        st.iterations = h.iter;
+        st.status = h.done - 1;   // 0 converged, 1 stalled, 2 max_iter, 3 gap, 4 invalid H
+        st.fp64_products = h.fp64_products;
+        st.head_switch = h.head_switch;
+        st.eps_min = h.eps_min;
+        st.eps_max = h.eps_max;
+        st.idem_err = h.iter > 0 ? h.idem[h.iter - 1] : 0.0;
+        st.trace = h.t1;
+        st.branch_bits[0] = h.bits[0];
+        st.branch_bits[1] = h.bits[1];
+        for (int k = 0; k < kMaxIter && k < 128; ++k) st.idem_hist[k] = (float)h.idem[k];
+        if (r->status == SP2_OK)
+            r->status = h.done == 3 ? SP2_ENOCONV : (h.done == 4 ? SP2_EGAP : (h.done == 5 ? SP2_EINVAL : SP2_OK));
+        bool issued = false;
+        if (r->status == SP2_OK && (h.done == 1 || h.done == 2)) {
+            issued = launch_finalize(X0, X0 + (size_t)ld * ld, ld, N, D, st_dev + r->slot, stream) == hipSuccess &&
+                     (N % 4 != 0 || launch_mulliken(D, N / 4, 4.0, q, stream) == hipSuccess) &&
+                     hipEventRecord(r->ev_up, stream) == hipSuccess &&
+                     hipStreamWaitEvent(copy, r->ev_up, 0) == hipSuccess &&
+                     hipMemcpyAsync(r->D, D, (size_t)N * N * 8, hipMemcpyDeviceToHost, copy) == hipSuccess &&
+                     (N % 4 != 0 ||
+                      hipMemcpyAsync(r->q, q, (size_t)(N / 4) * 8, hipMemcpyDeviceToHost, copy) == hipSuccess) &&
+                     hipEventRecord(r->ev_down, copy) == hipSuccess;
+            if (!issued) {
+                r->status = SP2_EDEVICE;
+                rc = SP2_EDEVICE;
+            }
         }
-        sp2_stats& s = r->stats;
-        std::memset(&s, 0, sizeof(s));
-        s.iterations = h.iter;
-        s.status = h.done - 1;   // 0 converged, 1 stalled, 2 max_iter, 3 gap, 4 invalid H
-        s.fp64_products = h.fp64_products;
-        s.head_switch = h.head_switch;
-        s.eps_min = h.eps_min;
-        s.eps_max = h.eps_max;
-        s.idem_err = h.iter > 0 ? h.idem[h.iter - 1] : 0.0;
-        s.trace = h.t1;
-        s.branch_bits[0] = h.bits[0];
-        s.branch_bits[1] = h.bits[1];
-        for (int k = 0; k < kMaxIter && k < 128; ++k) s.idem_hist[k] = (float)h.idem[k];
-        r->status = h.done == 3 ? SP2_ENOCONV : (h.done == 4 ? SP2_EGAP : (h.done == 5 ? SP2_EINVAL : SP2_OK));
+        if (!issued) failed.push_back(r);
     }
-    if (!finished.empty() && hipStreamSynchronize(stream) != hipSuccess) return SP2_EDEVICE;
     const double t = now_s();
-    std::lock_guard<std::mutex> lk(mu);
-    for (Request* r : finished) {
-        arena.release(r->off, r->L.total);
-        slots[r->slot] = nullptr;
-        r->t_done = t;
-        r->stats.ms = (t - r->t_submit) * 1e3;
-        r->done = true;
-        lat_ms.push_back((t - r->t_submit) * 1e3);
-        last_done = t;
-        ++completed;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (Request* r : finished) {
+            slots[r->slot] = nullptr;
+            r->slot = -1;
+        }
+        for (Request* r : finished)
+            if (std::find(failed.begin(), failed.end(), r) == failed.end()) downloading.push_back(r);
+        for (Request* r : failed) finish_locked(r, t);
     }
+    cv_down.notify_all();
     cv_done.notify_all();
-    return SP2_OK;
+    return rc;
+}
+
+// Under mu: the request's arena block is free again and its waiter may go.
+void sp2_server::finish_locked(Request* r, double t) {
+    arena.release(r->off, r->L.total);
+    r->t_done = t;
+    r->stats.ms = (t - r->t_submit) * 1e3;
+    r->done = true;
+    lat_ms.push_back((t - r->t_submit) * 1e3);
+    last_done = t;
+    ++completed;
+}
+
+// Completion thread: waits for the downloads in the order they were issued.
+void sp2_server::complete_loop() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        Request* r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_down.wait(lk, [this] { return !downloading.empty() || worker_done; });
+            if (downloading.empty()) return;   // the worker has stopped and nothing is in flight
+            r = downloading.front();
+        }
+        const bool ok = hipEventSynchronize(r->ev_down) == hipSuccess;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            downloading.pop_front();
+            if (!ok) r->status = SP2_EDEVICE;
+            finish_locked(r, now_s());
+        }
+        cv_done.notify_all();
+        cv_work.notify_all();   // freed arena space may admit a queued request
+    }
 }
 
 void sp2_server::loop() {
@@ -335,40 +410,72 @@ void sp2_server::loop() {
     bool group_dirty = true;
     for (;;) {
         std::vector<Request*> fresh;
-        int active = 0;
         {
             std::unique_lock<std::mutex> lk(mu);
             for (;;) {
                 admit_locked(fresh);
-                active = 0;
-                for (Request* r : slots) active += r != nullptr;
-                if (stop || active > 0) break;
+                bool busy = !fresh.empty() || !uploading.empty();
+                for (Request* r : slots) busy = busy || r != nullptr;
+                if (busy) break;
+                if (stop) {
+                    worker_done = true;
+                    lk.unlock();
+                    cv_down.notify_all();
+                    return;
+                }
                 cv_work.wait_for(lk, std::chrono::milliseconds(50));
             }
-            if (stop && active == 0) return;
         }
         const double t0 = now_s();
         sp2_status rc = SP2_OK;
         for (Request* r : fresh) {
-            rc = start_system(r);
-            if (rc != SP2_OK) break;
+            uploading.push_back(r);
+            if (rc == SP2_OK) rc = begin_upload(r);
         }
-        if (!fresh.empty()) group_dirty = true;
-        if (rc == SP2_OK && group_dirty) {
-            build_group();
-            if (hipMemcpyAsync(g_dev, g_host, sizeof(GroupDesc), hipMemcpyHostToDevice, stream) != hipSuccess)
-                rc = SP2_EDEVICE;
-            group_dirty = false;
+        // systems whose H has landed start and join the group
+        for (auto it = uploading.begin(); rc == SP2_OK && it != uploading.end();) {
+            const hipError_t e = hipEventQuery((*it)->ev_up);
+            if (e == hipErrorNotReady) {
+                ++it;
+                continue;
+            }
+            if (e != hipSuccess || (rc = start_system(*it)) != SP2_OK) {
+                rc = rc == SP2_OK ? SP2_EDEVICE : rc;
+                break;
+            }
+            (*it)->started = true;
+            group_dirty = true;
+            it = uploading.erase(it);
         }
-        if (rc == SP2_OK && hipGraphLaunch(graph, stream) != hipSuccess) rc = SP2_EDEVICE;
-        if (rc == SP2_OK &&
-            hipMemcpyAsync(st_host, st_dev, sizeof(State) * slots.size(), hipMemcpyDeviceToHost, stream) != hipSuccess)
-            rc = SP2_EDEVICE;
-        if (rc == SP2_OK && hipStreamSynchronize(stream) != hipSuccess) rc = SP2_EDEVICE;
+        bool any_started = false;
+        for (Request* r : slots) any_started = any_started || (r && r->started);
         std::vector<Request*> finished;
+        if (rc == SP2_OK && any_started) {
+            if (group_dirty) {
+                build_group();
+                if (hipMemcpyAsync(g_dev, g_host, sizeof(GroupDesc), hipMemcpyHostToDevice, stream) != hipSuccess)
+                    rc = SP2_EDEVICE;
+                group_dirty = false;
+            }
+            if (rc == SP2_OK && hipGraphLaunch(graph, stream) != hipSuccess) rc = SP2_EDEVICE;
+            if (rc == SP2_OK &&
+                hipMemcpyAsync(st_host, st_dev, sizeof(State) * slots.size(), hipMemcpyDeviceToHost, stream) !=
+                    hipSuccess)
+                rc = SP2_EDEVICE;
+            if (rc == SP2_OK && hipStreamSynchronize(stream) != hipSuccess) rc = SP2_EDEVICE;
+            ++ticks;
+        } else if (rc == SP2_OK) {
+            // only uploads in flight: wait for the oldest
+            if (!uploading.empty() && hipEventSynchronize(uploading.front()->ev_up) != hipSuccess) rc = SP2_EDEVICE;
+        }
         for (Request* r : slots)
-            if (r && (rc != SP2_OK || st_host[r->slot].done)) finished.push_back(r);
+            if (r && r->started && (rc != SP2_OK || st_host[r->slot].done)) finished.push_back(r);
         if (rc != SP2_OK) {
+            // a device error ends every request the worker holds
+            for (Request* r : slots)
+                if (r && !r->started) finished.push_back(r);
+            uploading.clear();
+            (void)hipStreamSynchronize(copy);   // no transfer may still target a block about to be freed
             std::lock_guard<std::mutex> lk(mu);
             err = "device error in the serving loop";
             for (Request* r : finished) r->status = rc;
@@ -380,7 +487,6 @@ void sp2_server::loop() {
             }
             group_dirty = true;
         }
-        ++ticks;
         busy_s += now_s() - t0;
     }
 }
@@ -395,7 +501,7 @@ void sp2_server_options_default(sp2_server_options* o) {
     o->slices = 5;
     o->max_iter = 100;
     o->idem_tol = 1e-10;
-    o->iters_per_tick = 1;
+    o->iters_per_tick = 8;
 }
 
 sp2_status sp2_server_create(sp2_ctx* ctx, const sp2_server_options* opt, sp2_server** out) {
@@ -416,6 +522,7 @@ sp2_status sp2_server_create(sp2_ctx* ctx, const sp2_server_options* opt, sp2_se
     s->opt = o;
     s->slots.assign(o.max_slots, nullptr);
     bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->arena_mem, o.hbm_budget_bytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->g_dev, sizeof(GroupDesc)) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&s->g_host, sizeof(GroupDesc), hipHostMallocDefault) == hipSuccess;
@@ -449,6 +556,7 @@ sp2_status sp2_server_create(sp2_ctx* ctx, const sp2_server_options* opt, sp2_se
         return SP2_EDEVICE;
     }
     s->worker = std::thread([s] { s->loop(); });
+    s->completer = std::thread([s] { s->complete_loop(); });
     *out = s;
     return SP2_OK;
 }
@@ -503,6 +611,8 @@ sp2_status sp2_server_wait(sp2_server* s, uint64_t ticket, double timeout_s, dou
     }
     s->reqs.erase(it);
     lk.unlock();
+    if (r->ev_up) (void)hipEventDestroy(r->ev_up);
+    if (r->ev_down) (void)hipEventDestroy(r->ev_down);
     s->pinned.put(r->H, (size_t)r->N * r->N * 8);
     s->pinned.put(r->D, (size_t)r->N * r->N * 8);
     s->pinned.put(r->q, (size_t)(r->N / 4 + 1) * 8);
@@ -544,10 +654,19 @@ void sp2_server_destroy(sp2_server* s) {
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->worker_done = true;   // also when the worker never ran
+    }
+    s->cv_down.notify_all();
+    if (s->completer.joinable()) s->completer.join();
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->copy) (void)hipStreamSynchronize(s->copy);
     for (auto& kv : s->reqs) {
         Request* r = kv.second;
+        if (r->ev_up) (void)hipEventDestroy(r->ev_up);
+        if (r->ev_down) (void)hipEventDestroy(r->ev_down);
         s->pinned.put(r->H, (size_t)r->N * r->N * 8);
         s->pinned.put(r->D, (size_t)r->N * r->N * 8);
         s->pinned.put(r->q, (size_t)(r->N / 4 + 1) * 8);
@@ -561,6 +680,7 @@ void sp2_server_destroy(sp2_server* s) {
     if (s->st_dev) (void)hipFree(s->st_dev);
     if (s->st_host) (void)hipHostFree(s->st_host);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->copy) (void)hipStreamDestroy(s->copy);
     delete s;
 }
 
