@@ -372,3 +372,38 @@ def test_energy_drift_with_block_threshold(ctx):
     say(f"  max |E_tot(tau) - E_tot(0)| {dev:.1e} eV")
     assert fmin[1e-5] < 0.9 and fmin[0.0] == 1.0
     assert dev > 1e-9      # dropping only exactly-zero blocks would leave the runs bitwise equal
+
+
+def test_energy_drift_int8(ctx):
+    """The int8 digit-plane density matrices (error ~1e-7 per sqrt N) in the
+    same 1000-step run as the FP64 drift test: no systematic drift, and the
+    fluctuation within twice that of the FP64 run."""
+    import paper_1203_6836_amd as p
+    say("case xlbomd 64 atoms, int8x, 1000 steps")
+    m = synth.MD_MODEL
+    x0 = relaxed_cluster(ctx, m)
+    nat = len(x0)
+    vel = synth.maxwell_velocities(nat, 300.0, m.mass, seed=22)
+    # both runs start from the FP64 self-consistent charges (the int8 charges
+    # carry ~1e-7 of error, so an int8 SCF cannot reach 1e-10)
+    md = ctx.xlbomd_create(m, x0, vel, synth.checkerboard_charges((4, 4, 4)), sp2_opts=p.options("fp64"),
+                           scf_beta=1.0, scf_tol=1e-10, scf_max_iter=100)
+    q0 = md.xlbomd_get()[2]
+    md.close()
+    sig = {}
+    for prec in ("fp64", "int8x"):
+        md = ctx.xlbomd_create(m, x0, vel, q0, sp2_opts=p.options(prec), scf_max_iter=0)
+        log = []
+        while len(log) < 1000:
+            log += md.xlbomd_run(200)
+        md.close()
+        et = np.array([r["etot"] for r in log])
+        t = np.arange(len(et))
+        fit = np.polyfit(t, et, 1)
+        sigma = float((et - np.polyval(fit, t)).std())
+        drift = abs(fit[0]) * len(et)
+        say(f"  {prec}: sigma {sigma:.2e} eV ({sigma / nat:.1e}/atom), drift {drift:.1e} eV")
+        assert sigma / nat <= 1e-4
+        assert drift <= 2.0 * sigma
+        sig[prec] = sigma
+    assert sig["int8x"] <= 2.0 * sig["fp64"]
