@@ -244,3 +244,60 @@ def test_invalid_hamiltonian_rejected(ctx):
     assert st == p.SP2_EINVAL
     st, _ = ctx.sp2_density_matrix_status(to_dev(H5), 150, p.options("fp64"))
     assert st == p.SP2_OK
+
+
+def test_smallest_system_and_unaligned_trace(ctx):
+    """N = 2 with one occupied state (both precisions) against the eigenvector
+    projector; the band energy on operands that are not 16-byte aligned (the
+    scalar branch) equals the aligned one."""
+    import torch
+    import paper_1203_6836_amd as p
+    say("case N=2, unaligned band energy")
+    H = np.array([[-1.0, 0.3], [0.3, 0.5]])
+    w, V = np.linalg.eigh(H)
+    ref = np.outer(V[:, 0], V[:, 0])
+    for prec in ("fp64", "int8x"):
+        D, st = ctx.sp2_density_matrix(to_dev(H), 1, p.options(prec))
+        err = np.abs(D.cpu().numpy() - ref).max()
+        say(f"  {prec}: iters {st['iterations']} max err {err:.1e}")
+        assert err <= (1e-12 if prec == "fp64" else 1e-7)
+    pos, H = oracle_H((4, 4, 4), 0)
+    Hd = to_dev(H)
+    D, _ = ctx.sp2_density_matrix(Hd, 2 * len(pos), p.options("fp64"))
+    e0 = ctx.sp2_band_energy(D, Hd)
+    n = H.shape[0]
+    # copies that start one element into a larger buffer: 8-byte but not 16-byte aligned
+    bufD = torch.zeros(n * n + 1, dtype=torch.float64, device="cuda")
+    bufH = torch.zeros(n * n + 1, dtype=torch.float64, device="cuda")
+    Du = bufD[1:].view(n, n)
+    Hu = bufH[1:].view(n, n)
+    Du.copy_(D)
+    Hu.copy_(Hd)
+    assert Du.data_ptr() % 16 == 8
+    e1 = ctx.sp2_band_energy(Du, Hu)
+    ref_e = 2.0 * float(np.sum(D.cpu().numpy() * H))
+    say(f"  band energy aligned {e0:.12f} unaligned {e1:.12f} numpy {ref_e:.12f}")
+    assert abs(e0 - ref_e) <= 1e-9 * abs(ref_e)
+    assert abs(e1 - ref_e) <= 1e-9 * abs(ref_e)
+
+
+def test_context_reuse_across_sizes(ctx):
+    """One context solving large, small, then medium systems gives bitwise the
+    results of a fresh context per system (scratch grows and is reused)."""
+    import torch
+    import paper_1203_6836_amd as p
+    say("case context reuse across sizes")
+    systems = [((8, 8, 16), 1), ((3, 3, 3), 7), ((6, 6, 5), 12)]
+    Hs = []
+    for dims, seed in systems:
+        pos = synth.lattice_positions(dims, seed=seed)
+        Hs.append((ctx.tb_hamiltonian(synth.STATIC_MODEL, to_dev(pos)), 2 * len(pos)))
+    for prec in ("int8x", "fp64"):
+        shared = [ctx.sp2_density_matrix(H, n, p.options(prec))[0] for H, n in Hs]
+        for (H, n), D in zip(Hs, shared):
+            fresh = p.Context(0)
+            D1, _ = fresh.sp2_density_matrix(H, n, p.options(prec, tile_group=8))
+            D0, _ = ctx.sp2_density_matrix(H, n, p.options(prec, tile_group=8))
+            torch.cuda.synchronize()
+            fresh.close()
+            assert torch.equal(D0, D1), (prec, H.shape)
