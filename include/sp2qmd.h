@@ -78,8 +78,10 @@ typedef struct {
                             chunks run in parallel, then summed: INT8X up to 8
                             chunks, summed exactly (results do not depend on
                             it); FP64 up to 16 chunks, summed in chunk order
-                            (results change at the rounding level).  -1
-                            (default): on; 0: never.                          */
+                            (results change at the rounding level).  FP64
+                            products whose tiles fill at most half of the slots
+                            (N <= 2816 on 256 CUs) split every tile into about
+                            sqrt(1.4 K/16) chunks.  -1 (default): on; 0: never. */
 } sp2_options;
 
 typedef struct {

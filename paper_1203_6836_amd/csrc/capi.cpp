@@ -92,12 +92,14 @@ static sp2_status grow(sp2_ctx* c, void** p, size_t* cap, size_t need_bytes) {
     return SP2_OK;
 }
 
-// Chunk buffer of the FP64 product's tail split (two workgroups per CU, one
-// chunk each at most), for products whose K loop covers >= 4096 columns.
+// Chunk buffer of the FP64 product's K split (two workgroups per CU, one
+// chunk each at most): the sparse last wave of large products and every tile
+// of small ones.
 static sp2_status f64_tail_buffer(sp2_ctx* c, int ld, int tail_split, double** buf, size_t* bytes) {
+    (void)ld;
     *buf = nullptr;
     *bytes = 0;
-    if (tail_split == 0 || ld < 4096) return SP2_OK;
+    if (tail_split == 0) return SP2_OK;
     const size_t need = (size_t)2 * device_cus() * kF64Chunk * sizeof(double);
     sp2_status s = grow(c, (void**)&c->f64tail, &c->f64tailcap, need);
     if (s != SP2_OK) return s;

@@ -10,6 +10,8 @@
 // (ld = N rounded up to 128, zero outside the N x N corner) used ping-pong;
 // the zero padding makes every tile of the product full, with no bounds
 // checks in the inner loop, and does not change X^2, traces or norms.
+#include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "sp2_internal.h"
@@ -781,16 +783,26 @@ hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double
     *nslots = T;
     // Tiles of a last wave that would leave at least half of the workgroup
     // slots (two per CU) idle are split along K into nsplit <= 16 chunks,
-    // when a tile's K loop covers at least 4096 columns.
+    // when a tile's K loop covers at least 4096 columns.  A smaller product
+    // whose tiles fill at most half of the slots is latency-bound (each
+    // workgroup walks its K stages one after another): all of its tiles are
+    // split.  The chunk count balances the stages a chunk walks (~2.8 us
+    // each) against the chunks the tail kernel reads back one after another
+    // (~2 us each): about sqrt(1.4 nk), at most 16 and no more than fit.
     int t_full = T, nsplit = 1;
-    if (!env && tail_buf && ld / GK >= 256) {
+    if (!env && tail_buf) {
         const int slots = 2 * device_cus();
-        const int r = T % slots;
-        if (r > 0 && 2 * r <= slots) {
-            nsplit = std::min(16, slots / r);
-            if (nsplit >= 2 && (size_t)r * nsplit * kF64Chunk * sizeof(double) <= tail_bytes) t_full = T - r;
-            else nsplit = 1;
+        const int nk = ld / GK;
+        int r = 0;
+        if (nk >= 256) {
+            r = T % slots;
+            if (r > 0 && 2 * r <= slots) nsplit = std::min(16, slots / r);
+        } else if (2 * T <= slots) {
+            r = T;
+            nsplit = std::min({16, slots / T, nk, (int)std::lround(std::sqrt(1.4 * nk))});
         }
+        if (nsplit >= 2 && (size_t)r * nsplit * kF64Chunk * sizeof(double) <= tail_bytes) t_full = T - r;
+        else nsplit = 1;
     }
     const int grid = t_full + (T - t_full) * nsplit;
     if (env)
