@@ -166,3 +166,38 @@ def test_stability_bound_of_the_charge_integration():
     opts = xlbomd.XLOptions(check_stability=True)
     with pytest.raises(ValueError):
         xlbomd.init_state(pos, np.zeros((64, 3)), m.with_(hubbard_u=40.0), 128, opts, np.zeros(64))
+
+
+def test_mulliken_charges_of_a_diagonal_projector():
+    """Atom-major orbitals (s, px, py, pz of atom 0, then atom 1, ...): charges of
+    a diagonal D worked by hand, q_i = 2 (sum of atom i's occupations) - 4."""
+    D = np.diag([1, 1, 0, 0,  1, 1, 1, 1,  0, 0, 0.5, 0.5,  0.25, 0, 0, 0.75]).astype(float)
+    np.testing.assert_array_equal(observables.mulliken(D), [0.0, 4.0, -2.0, -2.0])
+
+
+def test_auxiliary_charge_verlet_closed_form():
+    """With q held fixed and no dissipation, Eq. Verl_n reads
+    e_{t+1} = (2 - kappa) e_t - e_{t-1} for e = n - q, solved exactly by
+    e_t = cos(theta t) with cos(theta) = 1 - kappa / 2 when e_0 = 1 and
+    e_{-1} = cos(theta).  A wrong sign of the kappa term grows instead."""
+    kappa = 0.91
+    theta = np.arccos(1.0 - kappa / 2.0)
+    q = np.array([0.3, -0.7])
+    hist = [q + 1.0, q + np.cos(theta)] + [q] * 4
+    c = np.array(xlbomd.K5_C)
+    for t in range(1, 60):
+        n_next = xlbomd.verlet_n(hist, q, kappa, 0.0, c)
+        hist = [n_next] + hist[:-1]
+        np.testing.assert_allclose(hist[0] - q, np.cos(theta * t), atol=1e-12)
+
+
+def test_dissipation_applies_c_k_to_n_t_minus_k():
+    """The K = 5 coefficients on histories n_{t-k dt} = k^2 and k^3, worked by
+    hand: sum_k c_k k^2 = -6 and sum_k c_k k^3 = 0; with the coefficients
+    applied in reverse order the cubic history would give -90."""
+    c = np.array(xlbomd.K5_C)
+    alpha = 0.018
+    quad = [np.full(2, float(k * k)) for k in range(6)]
+    cube = [np.full(2, float(k ** 3)) for k in range(6)]
+    np.testing.assert_allclose(xlbomd.nvt_dissipation(quad, alpha, c), -6.0 * alpha, atol=1e-15)
+    np.testing.assert_allclose(xlbomd.nvt_dissipation(cube, alpha, c), 0.0, atol=1e-13)
