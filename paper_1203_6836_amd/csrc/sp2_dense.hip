@@ -358,10 +358,7 @@ __global__ __launch_bounds__(256) void k_ctrl_step_grouped(const GroupDesc* __re
 constexpr int GB = 128;   // tile
 constexpr int GK = 16;    // k per stage
 constexpr int GS = GB;      // LDS row stride (doubles)
-#ifndef SP2_F64_DMA
-#define SP2_F64_DMA 0           // measured slower than register staging for FP64
-#endif
-constexpr int F64_NST = SP2_F64_DMA ? 3 : 2;   // 3 stages x 2 operands x 16 KiB = 96 KiB
+constexpr int F64_NST = 2;  // LDS stages (double buffer: 2 stages x 2 operands x 16 KiB)
 
 // Tile id t -> (bi, bj), bi <= bj, row-major over the upper triangle.
 __device__ __forceinline__ void tri_coords(int t, int nt, int& bi, int& bj) {
@@ -399,16 +396,16 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
     double* __restrict__ Xn = st->cur ? buf0 : buf1;
     const int i0 = bi * GB, j0 = bj * GB;
 
-    // LDS ring of F64_NST stages; each operand row of a stage is one contiguous
-    // 1 KiB row segment of X, moved by one wave-wide global->LDS load
+    // LDS double buffer; each operand row of a stage is one contiguous 1 KiB
+    // row segment of X
     __shared__ double As[F64_NST][GK][GS];
     __shared__ double Bs[F64_NST][GK][GS];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wi = w >> 1, wj = w & 1;
 
-#if !SP2_F64_DMA
-    // global -> register staging: 4 double2 per operand per thread
+    // global -> register staging: 4 double2 per operand per thread (loads
+    // straight into LDS were measured slower for FP64)
     const int lrow = tid >> 6;           // + 4*s
     const int lcol = 2 * (tid & 63);
     double2 ra[4], rb[4];
@@ -429,7 +426,6 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
             Bs[stg][lrow + 4 * s][lcol + 1] = rb[s].y;
         }
     };
-#endif
 
     d4 acc[4][4];
 #pragma unroll
@@ -467,34 +463,6 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
         }
     };
-#if SP2_F64_DMA
-    // wave w loads rows w, w + 4, w + 8, w + 12 of both operands of a stage
-    // (8 global->LDS loads of 1 KiB); stage kt + 2 is issued while stage kt is
-    // multiplied, and a wave waits only for its own loads of stage kt before a
-    // bare barrier (a fenced barrier would also wait for stage kt + 1).
-    auto issue = [&](int kt, int stg) {
-        const int k0 = kt * GK;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int kr = w + 4 * r;
-            const double* rowp = Xc + (size_t)(k0 + kr) * ld;
-            __builtin_amdgcn_global_load_lds((const void*)(rowp + i0 + 2 * lane),
-                                             (__attribute__((address_space(3))) void*)&As[stg][kr][0], 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((const void*)(rowp + j0 + 2 * lane),
-                                             (__attribute__((address_space(3))) void*)&Bs[stg][kr][0], 16, 0, 0);
-        }
-    };
-    if (ks < ke) issue(ks, 0);
-    if (ks + 1 < ke) issue(ks + 1, 1);
-    for (int kt = ks; kt < ke; ++kt) {
-        if (kt + 1 < ke) __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8): stage kt + 1 may be in flight
-        else __builtin_amdgcn_s_waitcnt(0x0F70);               // vmcnt(0)
-        __builtin_amdgcn_s_barrier();
-        if (kt + 2 < ke) issue(kt + 2, (kt + 2 - ks) % F64_NST);
-        compute((kt - ks) % F64_NST);
-    }
-    __syncthreads();
-#else
     if (ks < ke) {
         gload(ks * GK);
         sstore(0);
@@ -507,7 +475,6 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
             __syncthreads();
         }
     }
-#endif
 
     if (kmode == 1) {
         d4* out = reinterpret_cast<d4*>(chunk);
