@@ -177,6 +177,7 @@ struct sp2_server {
     State* st_dev = nullptr;       // kMaxGroup control states
     State* st_host = nullptr;      // pinned
     hipGraphExec_t graph = nullptr;
+    hipEvent_t ev_tick = nullptr;       // end of a tick's state read-back
     PinnedPool pinned;
     std::vector<Request*> slots;
     std::vector<Request*> uploading;    // admitted, H in flight (worker thread only)
@@ -462,7 +463,14 @@ void sp2_server::loop() {
                 hipMemcpyAsync(st_host, st_dev, sizeof(State) * slots.size(), hipMemcpyDeviceToHost, stream) !=
                     hipSuccess)
                 rc = SP2_EDEVICE;
-            if (rc == SP2_OK && hipStreamSynchronize(stream) != hipSuccess) rc = SP2_EDEVICE;
+            // the worker waits for the tick by polling (a blocking wait wakes up
+            // late and leaves the GPU idle until the next tick is launched)
+            if (rc == SP2_OK && hipEventRecord(ev_tick, stream) != hipSuccess) rc = SP2_EDEVICE;
+            while (rc == SP2_OK) {
+                const hipError_t e = hipEventQuery(ev_tick);
+                if (e == hipSuccess) break;
+                if (e != hipErrorNotReady) rc = SP2_EDEVICE;
+            }
             ++ticks;
         } else if (rc == SP2_OK) {
             // only uploads in flight: wait for the oldest
@@ -523,6 +531,7 @@ sp2_status sp2_server_create(sp2_ctx* ctx, const sp2_server_options* opt, sp2_se
     s->slots.assign(o.max_slots, nullptr);
     bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&s->ev_tick, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->arena_mem, o.hbm_budget_bytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->g_dev, sizeof(GroupDesc)) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&s->g_host, sizeof(GroupDesc), hipHostMallocDefault) == hipSuccess;
@@ -605,12 +614,14 @@ sp2_status sp2_server_wait(sp2_server* s, uint64_t ticket, double timeout_s, dou
     else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return SP2_ETIMEOUT;
     if (stats) *stats = r->stats;
     const int status = r->status;
+    s->reqs.erase(it);
+    lk.unlock();
+    // the request is finished and no longer known to the server: copy the
+    // results out without holding the lock the scheduler needs every tick
     if (status == SP2_OK) {
         if (D_out) std::memcpy(D_out, r->D, (size_t)r->N * r->N * 8);
         if (q_out && r->N % 4 == 0) std::memcpy(q_out, r->q, (size_t)(r->N / 4) * 8);
     }
-    s->reqs.erase(it);
-    lk.unlock();
     if (r->ev_up) (void)hipEventDestroy(r->ev_up);
     if (r->ev_down) (void)hipEventDestroy(r->ev_down);
     s->pinned.put(r->H, (size_t)r->N * r->N * 8);
@@ -681,6 +692,7 @@ void sp2_server_destroy(sp2_server* s) {
     if (s->st_host) (void)hipHostFree(s->st_host);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     if (s->copy) (void)hipStreamDestroy(s->copy);
+    if (s->ev_tick) (void)hipEventDestroy(s->ev_tick);
     delete s;
 }
 
