@@ -210,6 +210,56 @@ def serving(ctx, n_requests, rate):
                                      "solves_per_s": round(len(reqs) / span64, 2)}}
 
 
+def thresholded_scaling(ctx, layers=(128, 256, 512), dense_max=16384):
+    """Gapped 4 x 4 x L wires (5 eV gap, D decays exponentially): int8
+    products with the elementwise threshold tau = 1e-5, per-solve time,
+    products, kept-block fraction and the time split over the steps, against
+    the dense int8 solve up to dense_max orbitals."""
+    import torch
+
+    import paper_1203_6836_amd as p
+    import synth
+
+    rows = []
+    for L in layers:
+        w = synth.gapped_workload(L)
+        log(f"thresholded scaling: gapped wire N={w.n_orb}")
+        H = ctx.tb_hamiltonian(synth.GAPPED_MODEL, torch.from_numpy(w.positions()).cuda())
+        D = torch.empty_like(H)
+        opt = p.options("int8x", tau=1e-5, threshold=1)
+        ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        ctx.sp2_ctx_set_profiling(True)
+        _, sp = ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
+        ctx.sp2_ctx_set_profiling(False)
+        row = {"n": w.n_orb, "ms_per_solve": round(ms, 2), "products": st["iterations"],
+               "fill_max": round(st["fill_max"], 5), "fill_min": round(st["fill_min"], 5),
+               "trace_err": float(torch.trace(D)) - w.n_occ,
+               "profiled_ms": {"products": round(sum(sp["prod_ms"]), 2), "encode": round(sp["encode_ms"], 2),
+                               "threshold": round(sp["post_ms"], 2)}}
+        if w.n_orb <= dense_max:
+            Dd = torch.empty_like(H)
+            ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x"), D_out=Dd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sd = ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x"), D_out=Dd)
+            torch.cuda.synchronize()
+            row["dense_ms_per_solve"] = round((time.perf_counter() - t0) * 1e3, 2)
+            row["dense_products"] = sd["iterations"]
+            row["err_vs_dense_per_sqrtN"] = float(torch.linalg.norm(D - Dd)) / w.n_orb ** 0.5
+            del Dd
+        log(f"  {row}")
+        rows.append(row)
+        del D, H
+        torch.cuda.empty_cache()
+    return {"workload": "gapped sp wire 4x4xL, 2.0 A, p level +4 eV, 2 electrons per atom",
+            "precision": "int8x", "tau": 1e-5, "threshold": "element", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +271,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-scaling", action="store_true",
+                    help="skip the thresholded gapped-wire scaling leg")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the counter-calibration kernels and one solve per precision "
                          "(for rocprofv3 --pmc passes); prints no JSON")
@@ -379,6 +431,10 @@ def main():
     }
     if args.serve_requests > 0 and prec == "int8x":
         out["serving"] = serving(ctx, args.serve_requests, args.serve_rate)
+    if not args.no_scaling:
+        del D64
+        torch.cuda.empty_cache()
+        out["thresholded_scaling"] = thresholded_scaling(ctx)
     if not args.no_cpu:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(H.cpu().numpy(), nocc)

@@ -58,14 +58,18 @@ typedef struct {
     int precision;       /* sp2_precision                                        */
     int max_iter;        /* products before SP2_ENOCONV (default 100)            */
     double idem_tol;     /* stop when ||X_n^2 - X_n||_F < idem_tol (1e-10)       */
-    double stall_tol;    /* also stop when n >= 4, e_n >= e_{n-2}, e_n < stall_tol
-                            (idempotency error at its rounding floor; 1e-2)      */
+    double stall_tol;    /* also stop when n >= 4, e_n >= r e_{n-2}, e_n <
+                            stall_tol (idempotency error at its floor; 1e-2);
+                            r = 1, or 1/2 when tau > 0 (the floor set by the
+                            threshold keeps creeping down)                       */
     int fp64_head;       /* INT8X: first products done in FP64 (default 0)      */
     int slices;          /* INT8X: digit planes, 2..6 (default 5)                */
     int fp32_tail;       /* BF16X2: FP32 iterations after the BF16 stage stalls
                             (default 3)                                          */
-    double tau;          /* block threshold: after every update zero each
-                            32x32 block with Frobenius norm < tau (0 = dense)    */
+    double tau;          /* threshold applied to X_0 and after every update
+                            (Linear scaling section), 0 = dense; the rule is
+                            set by `threshold`. Products skip the 32-column
+                            blocks outside each panel's nonzero range         */
     int tile_group;      /* order of the 128x128 product tiles: G x G super-tiles
                             dealt to the XCDs (G > 0), 0 = plain row-major, -1
                             (default) = the value sp2_autotune chose for this
@@ -82,6 +86,10 @@ typedef struct {
                             products whose tiles fill at most half of the slots
                             (N <= 2816 on 256 CUs) split every tile into about
                             sqrt(1.4 K/16) chunks.  -1 (default): on; 0: never. */
+    int threshold;       /* tau > 0: 0 (default) zero each 32x32 block whose
+                            Frobenius norm is < tau; 1 zero each element with
+                            |x| < tau (the paper's rule). Fill fractions count
+                            the 32x32 blocks that still hold a nonzero       */
 } sp2_options;
 
 typedef struct {

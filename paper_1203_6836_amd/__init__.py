@@ -26,7 +26,8 @@ class Sp2Options(ctypes.Structure):
                 ("idem_tol", ctypes.c_double), ("stall_tol", ctypes.c_double),
                 ("fp64_head", ctypes.c_int), ("slices", ctypes.c_int),
                 ("fp32_tail", ctypes.c_int), ("tau", ctypes.c_double),
-                ("tile_group", ctypes.c_int), ("tail_split", ctypes.c_int)]
+                ("tile_group", ctypes.c_int), ("tail_split", ctypes.c_int),
+                ("threshold", ctypes.c_int)]
 
 
 class TuneResult(ctypes.Structure):

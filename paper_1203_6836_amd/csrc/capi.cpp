@@ -52,6 +52,8 @@ struct sp2_ctx {
     size_t natcap = 0;
     int* env = nullptr;        // per-panel surviving column-block ranges (thresholded X)
     size_t envcap = 0;
+    int* tz = nullptr;         // per X buffer and upper tile: known all zero (thresholded int8)
+    size_t tzcap = 0;
     double* f64tail = nullptr; // chunk accumulators of split last-wave FP64 tiles
     size_t f64tailcap = 0;
     // qmd_evaluate scratch: H[n], D, zero charges, forces
@@ -121,6 +123,7 @@ void sp2_options_default(sp2_options* o) {
     o->slices = 5;
     o->fp32_tail = 3;
     o->tau = 0.0;
+    o->threshold = 0;
     o->tile_group = -1;
     o->tail_split = -1;
 }
@@ -170,7 +173,7 @@ void sp2_ctx_destroy(sp2_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->chk, c->V, c->eatom, c->qtmp, c->env,
+    void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->chk, c->V, c->eatom, c->qtmp, c->env, c->tz,
                    c->eH, c->eD, c->ezero, c->eF, c->f64tail};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -217,6 +220,7 @@ static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
     if (!(o.tau >= 0.0)) return fail(c, SP2_EINVAL, "tau must be >= 0");
     if (o.tile_group < -1 || o.tile_group > 64) return fail(c, SP2_EINVAL, "tile_group must be in [-1, 64]");
     if (o.tail_split < -1 || o.tail_split > 1) return fail(c, SP2_EINVAL, "tail_split must be -1, 0 or 1");
+    if (o.threshold < 0 || o.threshold > 1) return fail(c, SP2_EINVAL, "threshold must be 0 (block) or 1 (element)");
     if (o.tau > 0.0 && o.precision == SP2_PREC_BF16X2)
         return fail(c, SP2_EINVAL, "block thresholding runs with FP64 or INT8X products");
     (void)N;
@@ -263,6 +267,7 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     a.n_occ = (double)n_occ;
     a.idem_tol = o.idem_tol;
     a.stall_tol = o.stall_tol;
+    a.stall_ratio = o.tau > 0.0 ? 0.5 : 1.0;
     a.max_iter = o.max_iter;
     a.fp64_head = (int8x || bf16x) ? o.fp64_head : -1;
     a.fp32_tail = o.fp32_tail;
@@ -284,6 +289,17 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
         c->envcap = eb;
         env = c->env;
     }
+    // zero-tile flags: int8 products from the first product on (the FP64
+    // product does not keep them)
+    int* tz = nullptr;
+    if (o.tau > 0.0 && int8x && o.fp64_head == 0) {
+        size_t zb = c->tzcap;
+        if ((s = grow(c, (void**)&c->tz, &zb, (size_t)2 * tri_tiles(nt) * sizeof(int))) != SP2_OK) return s;
+        c->tzcap = zb;
+        tz = c->tz;
+    }
+    c->split.env = int8x ? env : nullptr;
+    c->split.tz = tz;
     hipStream_t st = c->stream;
     HIPCHK(c, hipEventRecord(c->ev0, st));
     int ns = 0, nchk = 0;
@@ -291,7 +307,8 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     HIPCHK(c, launch_gershgorin(H, N, c->part, &ns, st));
     HIPCHK(c, launch_bounds(c->part, ns, c->chk, nchk, c->st, st));
     HIPCHK(c, launch_init(H, N, ld, buf0, c->st, c->part, &ns, st, upper ? c->split.rmax : nullptr));
-    if (o.tau > 0.0) HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 1, st, env));
+    if (o.tau > 0.0)
+        HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, c->part, &ns, 1, st, env, tz));
     HIPCHK(c, launch_ctrl_init(c->part, ns, c->st, a, st));
 
     int launched = 0;
@@ -310,7 +327,8 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
             if (o.tau > 0.0)
-                HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, c->st, c->part, &ns, 0, st, env));
+                HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, c->part, &ns, 0, st,
+                                                 env, tz));
             if (pe) HIPCHK(c, hipEventRecord(pe[4], st));
             HIPCHK(c, launch_ctrl_step(c->part, ns, c->st, a, st));
         }
@@ -441,6 +459,8 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         if (split_reserve(c->split, ld, int8x ? slices : 0, bf16x) != 0)
             return fail(c, SP2_ENOMEM, "device allocation for split operands failed");
         c->split.upper = int8x;
+        c->split.env = nullptr;
+        c->split.tz = nullptr;
     }
     double* buf0 = c->xbuf;
     double* buf1 = c->xbuf + ld2;

@@ -42,13 +42,14 @@ __device__ __forceinline__ double wred_sum(double v) {
 __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 
 // --------------------------------------------------------------- encoding
-// One wave per padded row: row scale and `slices` digit planes.
+// One wave per padded row: row scale and `slices` digit planes of columns
+// [c0, c1) (multiples of 32; the row is zero outside them).
 template <int S>
 __device__ __forceinline__ void encode_row(const double* __restrict__ X, int ld, int i, int lane, int8_t* __restrict__ digits,
-                           double* __restrict__ scale) {
+                           double* __restrict__ scale, int c0, int c1) {
     const double* row = X + (size_t)i * ld;
     double m = 0.0;
-    for (int j = 8 * lane; j < ld; j += 512) {
+    for (int j = c0 + 8 * lane; j < c1; j += 512) {
         const double4 a = *reinterpret_cast<const double4*>(row + j);
         const double4 b = *reinterpret_cast<const double4*>(row + j + 4);
         m = fmax(m, fmax(fmax(fabs(a.x), fabs(a.y)), fmax(fabs(a.z), fabs(a.w))));
@@ -62,7 +63,7 @@ __device__ __forceinline__ void encode_row(const double* __restrict__ X, int ld,
     const size_t plane = (size_t)ld * ld;
     const size_t rowblk = (size_t)(i >> 5) * (ld >> 5);
     const int r32 = i & 31;
-    for (int j = 8 * lane; j < ld; j += 512) {
+    for (int j = c0 + 8 * lane; j < c1; j += 512) {
         double y[8];
         const double4 a = *reinterpret_cast<const double4*>(row + j);
         const double4 b = *reinterpret_cast<const double4*>(row + j + 4);
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(256) void k_encode_int8(const double* __restrict__ 
                                                      int8_t* __restrict__ digits,
                                                      double* __restrict__ scale) {
     if (st->done || st->phase != 1) return;
-    encode_row<S>(st->cur ? buf1 : buf0, ld, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63, digits, scale);
+    encode_row<S>(st->cur ? buf1 : buf0, ld, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63, digits, scale,
+                  0, ld);
 }
 
 // One workgroup per padded row, the row held in registers between the max and
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __
         const State* st = v.st;
         if (st->done || st->phase != 1) continue;
         const int i = (item - g->row_off[s]) * 4 + (threadIdx.x >> 6);
-        encode_row<S>(st->cur ? v.buf1 : v.buf0, v.ld, i, threadIdx.x & 63, v.digits, v.scale);
+        encode_row<S>(st->cur ? v.buf1 : v.buf0, v.ld, i, threadIdx.x & 63, v.digits, v.scale, 0, v.ld);
     }
 }
 
@@ -580,6 +582,29 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
 // t_full, t_full + 1, ... (the last, partly filled wave of a launch), each
 // split into nsplit chunks of the K loop whose accumulators go to chunk_acc;
 // k_gemm_int8x_tail finishes them.
+//
+// THR: tiles are visited diagonal by diagonal (bj - bi = 0, 1, ..), so the
+// tiles of a banded X, the only ones with a K range, are the first ones
+// dispatched and spread over every CU (the XCD-dealt super-tile order would
+// put most of them on the XCDs that take the short rows near the end of the
+// triangle); tile_group does not apply.
+// THR with tz (zero-tile flags, one row of T per X buffer): a tile whose K
+// range is empty and whose X_n tile is all zero has X_{n+1} = 0 there under
+// either branch; it gets zero partials and, unless the destination tile is
+// already all zero, plain zero stores (no reads), and its destination flag
+// is set.  Every other tile is computed and its flag cleared.
+// Tile at position pos of the diagonal-major order of the upper triangle of
+// nt x nt tiles: diagonal d starts at d nt - d (d - 1) / 2.
+__device__ __forceinline__ void diag_tile(int pos, int nt, int& bi, int& bj) {
+    const double b = 2.0 * nt + 1.0;
+    int d = (int)((b - sqrt(b * b - 8.0 * pos)) * 0.5);
+    auto start = [nt](int e) { return e * nt - e * (e - 1) / 2; };
+    while (d > 0 && start(d) > pos) --d;
+    while (d + 1 < nt && start(d + 1) <= pos) ++d;
+    bi = pos - start(d);
+    bj = bi + d;
+}
+
 template <int S, bool THR, bool UPPER>
 __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
                                                     int ld, const State* __restrict__ st,
@@ -587,14 +612,17 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
                                                     const double* __restrict__ scale,
                                                     double* __restrict__ part, const int* __restrict__ env,
                                                     unsigned long long* __restrict__ rmax, int tile_group,
-                                                    int t_full, int nsplit, int* __restrict__ chunk_acc) {
+                                                    int t_full, int nsplit, int* __restrict__ chunk_acc,
+                                                    int* __restrict__ tz) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
     const int nt = ld / QB, w = blockIdx.x;
     int pos, kmode = 0, kc0 = 0, kc1 = -1;
     int* cacc = nullptr;
-    if (w < t_full) {
+    if (THR) {
+        pos = w;
+    } else if (w < t_full) {
         pos = xcd_deal(w, t_full);
     } else {
         const int j = w - t_full, p = j / nsplit, ch = j - p * nsplit, nk = ld / (QK * I8Stage<S>::KS);
@@ -605,9 +633,39 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
         cacc = chunk_acc + (size_t)j * (S * 2 * 16 * 512);
     }
     int bi, bj;
-    order_tile(pos, nt, tile_group, bi, bj);
+    if (THR) diag_tile(pos, nt, bi, bj);
+    else order_tile(pos, nt, tile_group, bi, bj);
+    int* tzn = nullptr;
+    bool zero_next = false;
+    int t = 0;
+    if (THR && tz) {
+        const int T = nt * (nt + 1) / 2;
+        t = tri_index(bi, bj, nt);
+        const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
+        zero_next = lo > hi && tz[(size_t)st->cur * T + t] != 0;
+        tzn = tz + (size_t)(1 - st->cur) * T;
+        if (zero_next) {
+            if (tzn[t] == 0) {
+                double* __restrict__ Xn = st->cur ? buf0 : buf1;
+                const double2 z = make_double2(0.0, 0.0);
+                for (int e = threadIdx.x; e < QB * QB / 2; e += 512) {
+                    const int r = e / (QB / 2), c = 2 * (e % (QB / 2));
+                    *reinterpret_cast<double2*>(Xn + (size_t)(bi * QB + r) * ld + bj * QB + c) = z;
+                    if (bi != bj) *reinterpret_cast<double2*>(Xn + (size_t)(bj * QB + r) * ld + bi * QB + c) = z;
+                }
+            }
+            if (threadIdx.x == 0) {
+                part[3 * t + 0] = 0.0;
+                part[3 * t + 1] = 0.0;
+                part[3 * t + 2] = 0.0;
+                tzn[t] = 1;
+            }
+            return;
+        }
+    }
     int8x_tile<S, THR, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
                               UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, kmode, kc0, kc1, cacc, 0);
+    if (tzn && threadIdx.x == 0) tzn[t] = 0;
 }
 
 // Epilogue of the split tiles: workgroup p sums the nsplit chunks of the tile
@@ -696,7 +754,7 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     }
     const int grid = t_full + (T - t_full) * nsplit;
     hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
-                       s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
+                       s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc, THR ? s.tz : nullptr);
     if (t_full < T)
         hipLaunchKernelGGL((k_gemm_int8x_tail<S, UPPER>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
                            st, s.digits, s.scale, part, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
@@ -711,9 +769,38 @@ static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld,
     return launch_tile_kernel<S, false, false>(s, buf0, buf1, ld, st, part, stream, nullptr);
 }
 
+// Thresholded X: one wave per padded row, over the columns of its row panel's
+// range of nonzero 32-column blocks only, rounded out to whole K stages the
+// way the product rounds its K range (X is zero outside the range, and no
+// product reads digits outside it).  Same digits as encode_row.  A panel with
+// no nonzero block is read by no product.
+template <int S>
+__global__ __launch_bounds__(256) void k_encode_int8_env(const double* __restrict__ buf0,
+                                                         const double* __restrict__ buf1, int ld,
+                                                         const State* __restrict__ st,
+                                                         int8_t* __restrict__ digits,
+                                                         double* __restrict__ scale, const int* __restrict__ env) {
+    if (st->done || st->phase != 1) return;
+    constexpr int KS = I8Stage<S>::KS;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int p = i / QB;
+    const int lo = env[2 * p], hi = env[2 * p + 1];
+    if (lo > hi) {
+        if (lane == 0) scale[i] = 1.0;
+        return;
+    }
+    const int c0 = (lo / KS) * KS * 32, c1 = min(ld, (hi / KS + 1) * KS * 32);
+    encode_row<S>(st->cur ? buf1 : buf0, ld, i, lane, digits, scale, c0, c1);
+}
+
 template <int S>
 static hipError_t run_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
                              hipStream_t stream) {
+    if (s.env) {
+        hipLaunchKernelGGL(k_encode_int8_env<S>, dim3(ld / 4), dim3(256), 0, stream, buf0, buf1, ld, st, s.digits,
+                           s.scale, s.env);
+        return hipGetLastError();
+    }
     if (s.upper) {
         const int nb = ld / 32;
         hipLaunchKernelGGL(k_encode_int8_upper<S>, dim3(nb * (nb + 1) / 2), dim3(256), 0, stream, buf0, buf1, ld,

@@ -265,8 +265,9 @@ __global__ __launch_bounds__(256) void k_ctrl_init(const double* __restrict__ pa
 
 // After product n: the partials hold Tr X_{n+1}, ||X_{n+1}||_F^2 and
 // ||X_n^2 - X_n||_F^2.  Stop rules: e_n < idem_tol (converged, D = X_n);
-// n >= 4, e_n >= e_{n-2}, e_n < stall_tol (stalled at the rounding floor,
-// D = X_n); n + 1 == max_iter (not converged).  Otherwise X_{n+1} becomes
+// n >= 4, e_n >= r e_{n-2}, e_n < stall_tol (stalled at the floor of the
+// idempotency error, D = X_n; r = 1, or 1/2 with a threshold, whose floor
+// keeps creeping down); n + 1 == max_iter (not converged).  Otherwise X_{n+1} becomes
 // current and the next branch is chosen from its traces.
 __device__ __forceinline__ void ctrl_step_body(const double* __restrict__ part, int nslots, State* __restrict__ st,
                                const CtrlArgs& a) {
@@ -281,7 +282,7 @@ __device__ __forceinline__ void ctrl_step_body(const double* __restrict__ part, 
     if (f >= 0.0) st->fill[n] = (float)f;
     st->iter = n + 1;
     if (st->phase != 1) st->fp64_products += 1;   // FP64-kernel products (head or FP32 tail)
-    const bool stall = n >= 4 && e >= st->idem[n - 2] && e < a.stall_tol;
+    const bool stall = n >= 4 && e >= a.stall_ratio * st->idem[n - 2] && e < a.stall_tol;
     // BF16X2 runs its own schedule: a stall of the BF16 stage starts a fixed
     // FP32 tail instead of stopping
     // a projector whose trace is not n_occ could not pick the occupied set:

@@ -38,6 +38,7 @@ struct CtrlArgs {
     double n_occ;
     double idem_tol;
     double stall_tol;
+    double stall_ratio;   // stall when e_n >= stall_ratio * e_{n-2} (1; 1/2 with a threshold)
     int max_iter;
     int fp64_head;   // products in FP64 before switching phase (-1: never switch)
     int fp32_tail;   // BF16X2: FP32 products after the BF16 stage stalls

@@ -1,6 +1,7 @@
-// Block thresholding of X (the block form of the elementwise threshold the
-// paper applies after each projection in its linear-scaling runs) and the
-// operand storage of the reduced-precision products.
+// Thresholding of X after each projection (the paper's linear-scaling runs
+// zero every element below tau; the block form zeroes whole 32 x 32 blocks
+// whose Frobenius norm is below tau) and the operand storage of the
+// reduced-precision products.
 #include "split_internal.h"
 
 namespace sp2 {
@@ -19,17 +20,31 @@ __device__ __forceinline__ void tri_coords_t(int t, int nt, int& bi, int& bj) {
 
 // One workgroup per upper-triangular 128 x 128 tile t (same numbering as the
 // dense product's partial slots); each wave owns four of its sixteen 32 x 32
-// blocks.  Blocks with ||B||_F < tau are zeroed (with their mirror).  The
-// tile's trace and ||X||_F^2 partials are rewritten for the thresholded X;
-// the idempotency partial of the product is kept (zeroed for X_0).
+// blocks.  Block rule (elem == 0): blocks with ||B||_F < tau are zeroed (with
+// their mirror).  Elementwise rule (elem != 0): elements with |x| < tau are
+// zeroed (with their mirror; X is stored exactly symmetric, so both copies
+// take the same decision), and a block counts as kept while any element of
+// it survives.  The tile's trace and ||X||_F^2 partials are rewritten for the
+// thresholded X; the idempotency partial of the product is kept (zeroed for
+// X_0).
 __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ buf0, double* __restrict__ buf1,
-                                                         int ld, int N, double tau, State* __restrict__ st,
-                                                         double* __restrict__ part, int init,
-                                                         int* __restrict__ env) {
+                                                         int ld, int N, double tau, int elem,
+                                                         State* __restrict__ st, double* __restrict__ part,
+                                                         int init, int* __restrict__ env, int* __restrict__ tz) {
     if (st->done) return;
-    double* X = init ? buf0 : (st->cur ? buf0 : buf1);
+    const int xb = init ? 0 : (st->cur ? 0 : 1);
+    double* X = xb == 0 ? buf0 : buf1;
     const int nt = ld / 128;
     const int t = blockIdx.x;
+    const int T = nt * (nt + 1) / 2;
+    // a tile the product wrote as all zero: nothing to threshold or record
+    if (tz && !init && tz[(size_t)xb * T + t]) {
+        if (threadIdx.x == 0) {
+            part[3 * t + 0] = 0.0;
+            part[3 * t + 1] = 0.0;
+        }
+        return;
+    }
     int bi, bj;
     tri_coords_t(t, nt, bi, bj);
     const bool mirror = bi != bj;
@@ -44,22 +59,29 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
         const int r0 = bi * 128 + br * 32, c0 = bj * 128 + bc * 32;
         double v[16];
         double ss = 0.0;
+        bool nz = false;
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             const int e = lane + 64 * m, r = e >> 5, c = e & 31;
             v[m] = X[(size_t)(r0 + r) * ld + c0 + c];
+            if (elem && v[m] != 0.0 && fabs(v[m]) < tau) {
+                v[m] = 0.0;
+                X[(size_t)(r0 + r) * ld + c0 + c] = 0.0;
+                if (mirror) X[(size_t)(c0 + c) * ld + r0 + r] = 0.0;
+            }
+            nz = nz || v[m] != 0.0;
             ss += v[m] * v[m];
         }
         ss = wsum64(ss);
-        const bool keep = ss >= tau * tau;
-        if (!keep) {
+        const bool keep = elem ? __any(nz) : ss >= tau * tau;
+        if (!keep && !elem) {
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
                 const int e = lane + 64 * m, r = e >> 5, c = e & 31;
                 X[(size_t)(r0 + r) * ld + c0 + c] = 0.0;
                 if (mirror) X[(size_t)(c0 + c) * ld + r0 + r] = 0.0;
             }
-        } else {
+        } else if (keep) {
             fro += ss;
             if (r0 == c0) {
 #pragma unroll
@@ -95,6 +117,10 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
         if (init) part[3 * t + 2] = 0.0;
         const int k = s_k[0] + s_k[1] + s_k[2] + s_k[3];
         atomicAdd(&st->kept, (unsigned long long)(mirror ? 2 * k : k));
+        if (tz) {
+            tz[(size_t)xb * T + t] = k == 0 ? 1 : 0;
+            if (init) tz[(size_t)T + t] = 0;
+        }
         if (env) {
             int e[4] = {s_env[0][0], s_env[0][1], s_env[0][2], s_env[0][3]};
             for (int q = 1; q < 4; ++q) {
@@ -123,14 +149,14 @@ __global__ void k_env_reset(int* __restrict__ env, int npanel, const State* __re
     }
 }
 
-hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, State* st,
-                                  double* part, int* nslots, int init, hipStream_t stream, int* env) {
+hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
+                                  double* part, int* nslots, int init, hipStream_t stream, int* env, int* tz) {
     const int nt = ld / 128;
     const int T = nt * (nt + 1) / 2;
     *nslots = T;
     if (env) hipLaunchKernelGGL(k_env_reset, dim3((nt + 255) / 256), dim3(256), 0, stream, env, nt, st);
-    hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, st, part, init,
-                       env);
+    hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, elem, st, part,
+                       init, env, tz);
     return hipGetLastError();
 }
 

@@ -26,6 +26,12 @@ struct SplitScratch {
     int* tail_acc = nullptr;    // int32 accumulators of the K chunks of split tiles
     size_t tail_bytes = 0;
     size_t bytes = 0;
+    // thresholded solves (set per solve, owned by the context): each row
+    // panel's range of nonzero 32-column blocks, and per X buffer and
+    // upper-triangular 128 x 128 tile a flag "known to be all zero" (int8
+    // products from the first product on only; null otherwise)
+    const int* env = nullptr;
+    int* tz = nullptr;
 };
 
 int split_reserve(SplitScratch& s, int ld, int slices, bool bf16);
@@ -39,13 +45,19 @@ hipError_t launch_split_encode(SplitScratch& s, const double* buf0, const double
 // Reduced-precision product with the fused SP2 update (no-op in FP64 phase).
 hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                              int* nslots, hipStream_t stream, const int* env = nullptr);
-// Zero every 32 x 32 block of the freshly written X (X_0 when init != 0,
-// else X_{n+1}) whose Frobenius norm is below tau; rewrite the trace and
-// norm partials of the 128 x 128 tiles (keeping the idempotency partial).
-// With env non-null, also records each panel's range of surviving 32-column
-// blocks (reset first), for the products' K ranges.
-hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, State* st,
-                                  double* part, int* nslots, int init, hipStream_t stream, int* env = nullptr);
+// Threshold the freshly written X (X_0 when init != 0, else X_{n+1}): zero
+// every 32 x 32 block whose Frobenius norm is below tau (elem == 0) or every
+// element below tau (elem != 0); rewrite the trace and norm partials of the
+// 128 x 128 tiles (keeping the idempotency partial).  With env non-null, also
+// records each panel's range of 32-column blocks that still hold a nonzero
+// (reset first), for the products' K ranges.  With tz non-null (2 x T flags,
+// T upper-triangular tiles, one row per X buffer): tiles the product marked
+// as written all zero are skipped, and every other tile's flag is set to
+// whether it is all zero after thresholding; the X_0 pass reads no flags,
+// sets those of buffer 0 and clears those of buffer 1.
+hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
+                                  double* part, int* nslots, int init, hipStream_t stream, int* env = nullptr,
+                                  int* tz = nullptr);
 
 // int8 digit-plane product (int8x.hip)
 hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,

@@ -13,6 +13,9 @@ parameters and structures are not published):
   orthogonal valence orbitals (s, px, py, pz) each, spacing 1.5 A, Gaussian
   jitter sigma = 0.1 A per coordinate, atoms ordered x fastest, then y, then z,
   so orbital index = 4 * atom + {0: s, 1: px, 2: py, 3: pz};
+* its gapped variant: closed-shell atoms with two valence electrons (s^2) and
+  the p level at +4 eV on a 2.0 A lattice, a wire of 4 x 4 atoms in
+  cross-section;
 * Maxwell-Boltzmann velocities at a given temperature (centre-of-mass
   momentum removed);
 * a Poisson stream of solve requests with uniformly drawn system sizes.
@@ -155,6 +158,8 @@ class Workload:
     name: str
     dims: tuple
     seed: int
+    spacing: float = 1.5
+    electrons_per_atom: int = 4
 
     @property
     def n_atoms(self) -> int:
@@ -166,11 +171,11 @@ class Workload:
 
     @property
     def n_occ(self) -> int:
-        # neutral atoms with four valence electrons, doubly occupied orbitals
-        return 2 * self.n_atoms
+        # neutral atoms, doubly occupied orbitals
+        return self.electrons_per_atom * self.n_atoms // 2
 
     def positions(self) -> np.ndarray:
-        return lattice_positions(self.dims, seed=self.seed)
+        return lattice_positions(self.dims, spacing=self.spacing, seed=self.seed)
 
 
 # The five workloads: a 256-orbital FP64 solve, a 4096-orbital XL-BOMD run,
@@ -181,6 +186,22 @@ XLBOMD = Workload("xlbomd_n4096", (8, 8, 16), 1)
 XLBOMD_VEL_SEED = 101
 MIXED = Workload("mixed_n8192", (8, 16, 16), 2)
 SPARSE = Workload("blocksparse_n16384", (8, 8, 64), 3)
+
+
+# Gapped variant for the thresholded (linear-scaling) solver.  Atoms with two
+# valence electrons (a closed s^2 shell) fill one orbital each: the Fermi
+# level sits at quarter filling, between the s band and the p bands.  On the
+# 1.5 A lattice the bands overlap (no gap); raising the p level to +4 eV and
+# stretching the lattice to 2.0 A opens a gap of about 5 eV (band width about
+# 21 eV), so D decays exponentially with distance, as in the insulating
+# hydrocarbons of the paper.  The wire is 4 x 4 atoms in cross-section
+# (64 orbitals per layer) and grows along z.
+GAPPED_MODEL = TBModel(eps_p=4.0, z_val=2)
+GAPPED_SPACING = 2.0
+
+
+def gapped_workload(n_layers: int, seed: int = 3) -> Workload:
+    return Workload(f"gapped_wire_4x4x{n_layers}", (4, 4, int(n_layers)), seed, GAPPED_SPACING, 2)
 
 
 def small_workload(dims, seed) -> Workload:

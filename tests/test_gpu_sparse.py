@@ -1,4 +1,5 @@
-"""Block-thresholded SP2 (32 x 32 blocks, Frobenius norm < tau dropped after every update)."""
+"""Thresholded SP2: 32 x 32 blocks with Frobenius norm < tau, or elements below
+tau (the paper's rule), dropped after every update."""
 import sys
 
 import numpy as np
@@ -85,3 +86,100 @@ def test_int8x_threshold_full_size(ctx):
     assert e_thr <= 1e-3
     assert fills[0] < 0.5 and ss["fill_min"] < 0.2
     assert abs(float(torch.trace(Ds)) - w.n_occ) < 1e-3
+
+
+def test_threshold_rule_is_validated(ctx):
+    import paper_1203_6836_amd as p
+    H = to_dev(np.diag(np.arange(8.0)))
+    st, _ = ctx.sp2_density_matrix_status(H, 4, p.options("fp64", tau=1e-5, threshold=2))
+    assert st == p.SP2_EINVAL
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_fp64_threshold_gapped_wire_matches_oracle(ctx, rule):
+    """Gapped 4 x 4 x 32 wire (N = 2048): both rules, FP64 products, against the
+    oracle step by step (iterations, fill after every update, D)."""
+    import paper_1203_6836_amd as p
+    name = ("block", "element")[rule]
+    say(f"case fp64 tau=1e-5 {name} rule, gapped wire N=2048")
+    w = synth.gapped_workload(32)
+    H = otb.hamiltonian0(w.positions(), synth.GAPPED_MODEL)
+    ref = osp2.sp2(H, w.n_occ, tau=1e-5, threshold=name)
+    D, st = ctx.sp2_density_matrix(to_dev(H), w.n_occ, p.options("fp64", tau=1e-5, threshold=rule))
+    D = D.cpu().numpy()
+    err = np.linalg.norm(D - ref.D) / np.sqrt(H.shape[0])
+    n_upd = st["iterations"] - 1
+    say(f"  iters gpu={st['iterations']} oracle={ref.iterations} status {st['status']} ({ref.status}) "
+        f"err/sqrtN={err:.2e} fill {ref.fill[0]:.3f} -> {ref.fill[-1]:.3f}")
+    assert st["iterations"] == ref.iterations
+    assert st["status"] == ref.status
+    assert err <= 1e-9
+    np.testing.assert_allclose(st["fill_hist"][:n_upd], ref.fill[1:1 + n_upd], atol=1e-7)
+    assert st["fill_min"] == pytest.approx(min(ref.fill), abs=1e-7)
+    if rule == 1:
+        # every surviving element is at least tau in magnitude, the rest are zero
+        nz = D[D != 0.0]
+        assert np.abs(nz).min() >= 1e-5 or nz.size == 0
+
+
+def test_int8x_elementwise_gapped_wire_vs_oracle(ctx):
+    """int8 products with the elementwise rule on the gapped wire: the products
+    differ from FP64 by ~1e-7 relative, which moves a few elements across
+    tau; the result stays within the error the threshold itself makes."""
+    import paper_1203_6836_amd as p
+    say("case int8x tau=1e-5 element rule, gapped wire N=2048")
+    w = synth.gapped_workload(32)
+    H = otb.hamiltonian0(w.positions(), synth.GAPPED_MODEL)
+    ref = osp2.sp2(H, w.n_occ, tau=1e-5, threshold="element")
+    dense = osp2.sp2(H, w.n_occ)
+    D, st = ctx.sp2_density_matrix(to_dev(H), w.n_occ, p.options("int8x", tau=1e-5, threshold=1))
+    D = D.cpu().numpy()
+    rn = np.sqrt(H.shape[0])
+    err = np.linalg.norm(D - ref.D) / rn
+    err_thr = np.linalg.norm(ref.D - dense.D) / rn
+    say(f"  iters gpu={st['iterations']} oracle={ref.iterations}; err vs oracle {err:.2e}, "
+        f"oracle thresholded vs dense {err_thr:.2e}, trace {np.trace(D) - w.n_occ:+.1e}")
+    assert abs(st["iterations"] - ref.iterations) <= 1
+    assert err <= 0.25 * err_thr
+    assert abs(np.trace(D) - w.n_occ) < 1e-4
+
+
+def test_gapped_wire_thresholded_scaling(ctx):
+    """Gapped wires of N = 8192, 16384 and 32768 orbitals: int8 products, the
+    elementwise rule at tau = 1e-5.  The kept fraction falls as 1/N and the
+    thresholded solve beats the dense one by a growing factor."""
+    import torch
+    import paper_1203_6836_amd as p
+    rows = []
+    for L in (128, 256, 512):
+        w = synth.gapped_workload(L)
+        say(f"case gapped wire N={w.n_orb} int8x tau=1e-5 element")
+        H = ctx.tb_hamiltonian(synth.GAPPED_MODEL, to_dev(w.positions()))
+        opt = p.options("int8x", tau=1e-5, threshold=1)
+        ctx.sp2_density_matrix(H, w.n_occ, opt)            # warm (allocation)
+        D, st = ctx.sp2_density_matrix(H, w.n_occ, opt)
+        tr = float(torch.trace(D)) - w.n_occ
+        dense_ms = None
+        if w.n_orb <= 16384:
+            Dd, sd = ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x"))
+            dense_ms = sd["ms"]
+            e = float(torch.linalg.norm(D - Dd)) / w.n_orb ** 0.5
+            say(f"  dense int8 {dense_ms:.0f} ms ({sd['iterations']} products); err vs dense {e:.2e}")
+            assert e < 1e-3
+            del Dd
+        say(f"  thresholded {st['ms']:.1f} ms ({st['iterations']} products), fill min {st['fill_min']:.4f} "
+            f"max {st['fill_max']:.4f}, trace {tr:+.1e}")
+        rows.append((w.n_orb, st["ms"], st["fill_max"], dense_ms, st["iterations"]))
+        assert st["status"] in ("converged", "stalled")
+        assert abs(tr) < 1e-3
+        del D, H
+        torch.cuda.empty_cache()
+    # kept fraction ~ 1/N: doubling N halves it (to within 20 %)
+    for r0, r1 in zip(rows, rows[1:]):
+        assert r1[2] < 0.6 * r0[2]
+    # measured 48x at N = 16384 (dense products cost 8x per doubling of N,
+    # the thresholded solve about 2.5x per product, dense H and D passes
+    # included)
+    assert rows[1][3] > 20.0 * rows[1][1]
+    per_product = [r[1] / r[4] for r in rows]
+    assert per_product[2] < 4.0 * per_product[1]
