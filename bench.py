@@ -210,7 +210,7 @@ def serving(ctx, n_requests, rate):
                                      "solves_per_s": round(len(reqs) / span64, 2)}}
 
 
-def thresholded_scaling(ctx, layers=(128, 256, 512), dense_max=16384):
+def thresholded_scaling(ctx, layers=(128, 256, 512, 1024), dense_max=16384):
     """Gapped 4 x 4 x L wires (5 eV gap, D decays exponentially): int8
     products with the elementwise threshold tau = 1e-5, per-solve time,
     products, kept-block fraction and the time split over the steps, against

@@ -60,8 +60,9 @@ typedef struct {
     double idem_tol;     /* stop when ||X_n^2 - X_n||_F < idem_tol (1e-10)       */
     double stall_tol;    /* also stop when n >= 4, e_n >= r e_{n-2}, e_n <
                             stall_tol (idempotency error at its floor; 1e-2);
-                            r = 1, or 1/2 when tau > 0 (the floor set by the
-                            threshold keeps creeping down)                       */
+                            r = 1, or when tau > 0 r = 1/2 and the bound is
+                            max(stall_tol, 0.1) (the floor set by the
+                            threshold keeps creeping down and grows with N) */
     int fp64_head;       /* INT8X: first products done in FP64 (default 0)      */
     int slices;          /* INT8X: digit planes, 2..6 (default 5)                */
     int fp32_tail;       /* BF16X2: FP32 iterations after the BF16 stage stalls

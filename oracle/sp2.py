@@ -23,11 +23,13 @@ the steps below are the standard SP2 recursion written from its definition:
 Reading for the thresholded runs (the paper is silent on the stop rule): the
 dropped elements perturb every X_n, so the idempotency error settles on a
 floor set by tau, not by rounding, and there it keeps shrinking by a tiny
-amount per product, so "the error no longer falls" (r = 1) may never hold.
-Once e_n < 1e-2 every eigenvalue lies within about 0.01 of 0 or 1, where one
-product of each branch takes a deviation d to at most about 4 d^2: an error
-that falls by less than half over two products has left the quadratic regime.
-With tau > 0, r = 1/2.
+amount per product, so "the error no longer falls" (r = 1) may never hold;
+the floor also grows with N (about sqrt of the number of elements near tau),
+past 1e-2 on the largest systems.  Once e_n < 0.1 every eigenvalue lies
+within d < 0.113 of 0 or 1 (lambda (1 - lambda) <= e_n), where one product
+of each branch takes d to at most about 4 d^2 < d / 2: an error that falls by
+less than half over two products has left the quadratic regime.  With
+tau > 0, r = 1/2 and the bound on e_n is max(stall, 0.1).
 
 The paper's threshold zeroes every element whose magnitude is below tau
 (threshold="element").  threshold="block" zeroes each 32 x 32 block whose
@@ -137,6 +139,7 @@ def element_threshold(X, tau, bs=32):
 
 
 STALL_RATIO_THRESHOLDED = 0.5
+STALL_GUARD_THRESHOLDED = 0.1
 
 
 def sp2(H, n_occ, tol=1e-10, max_iter=100, stall=1e-2, tau=0.0, block=32,
@@ -146,12 +149,15 @@ def sp2(H, n_occ, tol=1e-10, max_iter=100, stall=1e-2, tau=0.0, block=32,
     tau > 0 selects the thresholded variant: after X_0 and after every
     update, blocks of size ``block`` with Frobenius norm below tau are zeroed
     (threshold="block") or elements below tau are zeroed (threshold="element",
-    the paper's rule); the stall test then uses r = 1/2.
+    the paper's rule); the stall test then uses r = 1/2 and the bound
+    max(stall, 0.1).
     """
     if threshold not in ("block", "element"):
         raise ValueError(threshold)
     thr = block_threshold if threshold == "block" else element_threshold
     ratio = STALL_RATIO_THRESHOLDED if tau > 0.0 else 1.0
+    if tau > 0.0:
+        stall = max(stall, STALL_GUARD_THRESHOLDED)
     H = np.asarray(H, dtype=np.float64)
     eps_min, eps_max = gershgorin(H) if bounds is None else bounds
     if not eps_max > eps_min:

@@ -266,7 +266,10 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     CtrlArgs a;
     a.n_occ = (double)n_occ;
     a.idem_tol = o.idem_tol;
-    a.stall_tol = o.stall_tol;
+    // with a threshold the floor of e_n grows with N; below 0.1 every
+    // eigenvalue is within 0.113 of 0 or 1, where two products of opposite
+    // branches shrink its deviation by more than half
+    a.stall_tol = o.tau > 0.0 ? std::max(o.stall_tol, 0.1) : o.stall_tol;
     a.stall_ratio = o.tau > 0.0 ? 0.5 : 1.0;
     a.max_iter = o.max_iter;
     a.fp64_head = (int8x || bf16x) ? o.fp64_head : -1;
@@ -294,7 +297,8 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     int* tz = nullptr;
     if (o.tau > 0.0 && int8x && o.fp64_head == 0) {
         size_t zb = c->tzcap;
-        if ((s = grow(c, (void**)&c->tz, &zb, (size_t)2 * tri_tiles(nt) * sizeof(int))) != SP2_OK) return s;
+        // 2 T flags, then the product's work list (T entries) and its 2 counters
+        if ((s = grow(c, (void**)&c->tz, &zb, ((size_t)3 * tri_tiles(nt) + 2) * sizeof(int))) != SP2_OK) return s;
         c->tzcap = zb;
         tz = c->tz;
     }

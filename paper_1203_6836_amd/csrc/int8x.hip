@@ -588,11 +588,6 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
 // dispatched and spread over every CU (the XCD-dealt super-tile order would
 // put most of them on the XCDs that take the short rows near the end of the
 // triangle); tile_group does not apply.
-// THR with tz (zero-tile flags, one row of T per X buffer): a tile whose K
-// range is empty and whose X_n tile is all zero has X_{n+1} = 0 there under
-// either branch; it gets zero partials and, unless the destination tile is
-// already all zero, plain zero stores (no reads), and its destination flag
-// is set.  Every other tile is computed and its flag cleared.
 // Tile at position pos of the diagonal-major order of the upper triangle of
 // nt x nt tiles: diagonal d starts at d nt - d (d - 1) / 2.
 __device__ __forceinline__ void diag_tile(int pos, int nt, int& bi, int& bj) {
@@ -612,8 +607,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
                                                     const double* __restrict__ scale,
                                                     double* __restrict__ part, const int* __restrict__ env,
                                                     unsigned long long* __restrict__ rmax, int tile_group,
-                                                    int t_full, int nsplit, int* __restrict__ chunk_acc,
-                                                    int* __restrict__ tz) {
+                                                    int t_full, int nsplit, int* __restrict__ chunk_acc) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
@@ -635,24 +629,93 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
     int bi, bj;
     if (THR) diag_tile(pos, nt, bi, bj);
     else order_tile(pos, nt, tile_group, bi, bj);
-    int* tzn = nullptr;
-    bool zero_next = false;
-    int t = 0;
-    if (THR && tz) {
-        const int T = nt * (nt + 1) / 2;
-        t = tri_index(bi, bj, nt);
+    int8x_tile<S, THR, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
+                              UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, kmode, kc0, kc1, cacc, 0);
+}
+
+// ---- thresholded products driven by a work list (int8 from the first product on)
+//
+// Zero-tile flags tz (one row of T upper tiles per X buffer, kept with the
+// threshold pass): a tile whose K range is empty and whose X_n tile is all
+// zero has X_{n+1} = 0 there under either branch.  k_tile_list visits the
+// tiles in diagonal-major order; such a tile gets zero partials and is left
+// out when its destination tile is already all zero, or is listed for plain
+// zero stores (no reads) when it is not; every other tile is listed for the
+// product.  The list holds (zero_store << 30) | (bi << 15) | bj; list_ctr[0]
+// counts entries, list_ctr[1] hands them out.
+__global__ void k_list_reset(int* __restrict__ list_ctr, const State* __restrict__ st) {
+    if (st->done || st->phase != 1) return;
+    if (threadIdx.x < 2) list_ctr[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_tile_list(const State* __restrict__ st, const int* __restrict__ env,
+                                                   const int* __restrict__ tz, int nt, double* __restrict__ part,
+                                                   int* __restrict__ list, int* __restrict__ list_ctr) {
+    if (st->done || st->phase != 1) return;
+    const int T = nt * (nt + 1) / 2;
+    const int pos = blockIdx.x * 256 + threadIdx.x;
+    bool listed = false;
+    int item = 0;
+    if (pos < T) {
+        int bi, bj;
+        diag_tile(pos, nt, bi, bj);
+        const int t = tri_index(bi, bj, nt);
         const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
-        zero_next = lo > hi && tz[(size_t)st->cur * T + t] != 0;
-        tzn = tz + (size_t)(1 - st->cur) * T;
-        if (zero_next) {
-            if (tzn[t] == 0) {
-                double* __restrict__ Xn = st->cur ? buf0 : buf1;
-                const double2 z = make_double2(0.0, 0.0);
-                for (int e = threadIdx.x; e < QB * QB / 2; e += 512) {
-                    const int r = e / (QB / 2), c = 2 * (e % (QB / 2));
-                    *reinterpret_cast<double2*>(Xn + (size_t)(bi * QB + r) * ld + bj * QB + c) = z;
-                    if (bi != bj) *reinterpret_cast<double2*>(Xn + (size_t)(bj * QB + r) * ld + bi * QB + c) = z;
-                }
+        const bool zero_next = lo > hi && tz[(size_t)st->cur * T + t] != 0;
+        if (zero_next && tz[(size_t)(1 - st->cur) * T + t] != 0) {
+            part[3 * t + 0] = 0.0;
+            part[3 * t + 1] = 0.0;
+            part[3 * t + 2] = 0.0;
+        } else {
+            listed = true;
+            item = ((zero_next ? 1 : 0) << 30) | (bi << 15) | bj;
+        }
+    }
+    // one atomic per wave
+    const unsigned long long m = __ballot(listed);
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(&list_ctr[0], __popcll(m));
+    base = __shfl(base, 0, 64);
+    if (listed) list[base + __popcll(m & ((1ull << lane) - 1ull))] = item;
+}
+
+// One workgroup per CU takes list entries until none is left (every
+// workgroup leaves once the shared counter passes the entry count).
+template <int S>
+__global__ __launch_bounds__(512) void k_gemm_int8x_list(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                         int ld, const State* __restrict__ st,
+                                                         const int8_t* __restrict__ digits,
+                                                         const double* __restrict__ scale,
+                                                         double* __restrict__ part, const int* __restrict__ env,
+                                                         int* __restrict__ tz, const int* __restrict__ list,
+                                                         int* __restrict__ list_ctr) {
+    if (st->done || st->phase != 1) return;
+    extern __shared__ __align__(16) int8_t smem_raw[];
+    I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
+    // the entry index is passed through the first word of the staging ring,
+    // which no tile uses between the barriers around it (the ring fills the
+    // 160 KiB of LDS; a separate shared variable would not fit)
+    volatile int& s_k = *reinterpret_cast<int*>(smem_raw);
+    const int nt = ld / QB, T = nt * (nt + 1) / 2;
+    const int n = list_ctr[0];
+    int* __restrict__ tzn = tz + (size_t)(1 - st->cur) * T;
+    double* __restrict__ Xn = st->cur ? buf0 : buf1;
+    for (;;) {
+        if (threadIdx.x == 0) s_k = atomicAdd(&list_ctr[1], 1);
+        __syncthreads();
+        const int k = s_k;
+        __syncthreads();
+        if (k >= n) break;
+        const int it = list[k];
+        const int bi = (it >> 15) & 0x7fff, bj = it & 0x7fff;
+        const int t = tri_index(bi, bj, nt);
+        if (it >> 30) {
+            const double2 z = make_double2(0.0, 0.0);
+            for (int e = threadIdx.x; e < QB * QB / 2; e += 512) {
+                const int r = e / (QB / 2), c = 2 * (e % (QB / 2));
+                *reinterpret_cast<double2*>(Xn + (size_t)(bi * QB + r) * ld + bj * QB + c) = z;
+                if (bi != bj) *reinterpret_cast<double2*>(Xn + (size_t)(bj * QB + r) * ld + bi * QB + c) = z;
             }
             if (threadIdx.x == 0) {
                 part[3 * t + 0] = 0.0;
@@ -660,12 +723,12 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
                 part[3 * t + 2] = 0.0;
                 tzn[t] = 1;
             }
-            return;
+        } else {
+            int8x_tile<S, true, false>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env, nullptr);
+            if (threadIdx.x == 0) tzn[t] = 0;
         }
+        __syncthreads();
     }
-    int8x_tile<S, THR, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
-                              UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, kmode, kc0, kc1, cacc, 0);
-    if (tzn && threadIdx.x == 0) tzn[t] = 0;
 }
 
 // Epilogue of the split tiles: workgroup p sums the nsplit chunks of the tile
@@ -754,7 +817,7 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     }
     const int grid = t_full + (T - t_full) * nsplit;
     hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
-                       s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc, THR ? s.tz : nullptr);
+                       s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
     if (t_full < T)
         hipLaunchKernelGGL((k_gemm_int8x_tail<S, UPPER>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
                            st, s.digits, s.scale, part, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
@@ -762,8 +825,32 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
 }
 
 template <int S>
+static hipError_t launch_list_kernel(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
+                                     hipStream_t stream, const int* env) {
+    const int nt = ld / QB;
+    const int T = nt * (nt + 1) / 2;
+    const size_t lds = sizeof(I8Smem<S>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x_list<S>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    int* list = s.tz + (size_t)2 * T;
+    int* ctr = list + T;
+    hipLaunchKernelGGL(k_list_reset, dim3(1), dim3(64), 0, stream, ctr, st);
+    hipLaunchKernelGGL(k_tile_list, dim3((T + 255) / 256), dim3(256), 0, stream, st, env, s.tz, nt, part, list, ctr);
+    const int grid = std::min(T, device_cus());
+    hipLaunchKernelGGL(k_gemm_int8x_list<S>, dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits, s.scale,
+                       part, env, s.tz, list, ctr);
+    return hipGetLastError();
+}
+
+template <int S>
 static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                             hipStream_t stream, const int* env) {
+    if (env && s.tz) return launch_list_kernel<S>(s, buf0, buf1, ld, st, part, stream, env);
     if (env) return launch_tile_kernel<S, true, false>(s, buf0, buf1, ld, st, part, stream, env);
     if (s.upper) return launch_tile_kernel<S, false, true>(s, buf0, buf1, ld, st, part, stream, nullptr);
     return launch_tile_kernel<S, false, false>(s, buf0, buf1, ld, st, part, stream, nullptr);

@@ -29,7 +29,8 @@ struct SplitScratch {
     // thresholded solves (set per solve, owned by the context): each row
     // panel's range of nonzero 32-column blocks, and per X buffer and
     // upper-triangular 128 x 128 tile a flag "known to be all zero" (int8
-    // products from the first product on only; null otherwise)
+    // products from the first product on only; null otherwise), followed by
+    // room for the product's work list (T entries) and 2 counters
     const int* env = nullptr;
     int* tz = nullptr;
 };

@@ -147,10 +147,12 @@ def test_element_threshold_brute_force():
 
 
 def test_stall_reading_two_branch_contraction():
-    """Reading behind r = 1/2 with a threshold: once eigenvalues lie within
-    0.01 of 0 or 1, one product of each branch maps a deviation d to at most
-    about 4 d^2, far below d/2."""
-    for d in (1e-2, 1e-3, 1e-5):
+    """Reading behind r = 1/2 and the bound 0.1 with a threshold: e < 0.1
+    puts every eigenvalue within d < 0.113 of 0 or 1, and there one product
+    of each branch maps d to at most about 4 d^2, below d/2."""
+    lam = 0.5 - np.sqrt(0.25 - 0.1)         # lambda (1 - lambda) = 0.1
+    assert lam < 0.113
+    for d in (0.113, 1e-2, 1e-3, 1e-5):
         for x0 in (d, 1.0 - d):
             for br in ([0, 1], [1, 0]):
                 x = float(sp2.scalar_sp2([x0], br)[0])
