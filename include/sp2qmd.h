@@ -272,7 +272,9 @@ typedef struct xlbomd xlbomd;
  * arrays copied in.  Start (General remarks): with scf_max_iter > 0 the
  * charges are first converged self-consistently on the GPU from the guess n0
  * (zeros when n0_host is NULL) and n = q is set for the whole history; with
- * scf_max_iter == 0, n0_host (required) is the history as given. */
+ * scf_max_iter == 0, n0_host (required) is the history as given.  Atoms are
+ * neutral with p->z_val valence electrons in doubly occupied states: n_occ =
+ * z_val n_atoms / 2 (SP2_EINVAL unless that is a whole number in (0, 4 n_atoms)). */
 sp2_status xlbomd_create(sp2_ctx *ctx, const tb_params *p, const xlbomd_options *o,
                          int n_atoms, const double *xyz_host, const double *vel_host,
                          const double *n0_host, xlbomd **out);

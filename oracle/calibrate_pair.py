@@ -22,13 +22,17 @@ def virial_at(pos, q, m, n_occ, A):
     return float(np.sum((pos - pos.mean(axis=0)) * r["F"]))
 
 
-def zero_virial_amplitude(m, dims=(4, 4, 4)):
-    """Returns (A, W(0), q*) for model m (its pair_a is ignored)."""
+def zero_virial_amplitude(m, dims=(4, 4, 4), spacing=1.5, n0=None):
+    """Returns (A, W(0), q*) for model m (its pair_a is ignored) on the
+    unjittered lattice of the given spacing; the SCF starts from n0
+    (default: the +-4 e checkerboard)."""
     import synth
-    pos = synth.lattice_positions(dims, jitter=0.0, seed=0)
-    n_occ = 2 * len(pos)
+    pos = synth.lattice_positions(dims, spacing=spacing, jitter=0.0, seed=0)
+    n_occ = int(round(m.z_val * len(pos) / 2))
     m0 = m.with_(pair_a=0.0)
-    q, _ = xlbomd.scf(pos, m0, n_occ, beta=1.0, tol=1e-11, n0=synth.checkerboard_charges(dims))
+    if n0 is None:
+        n0 = synth.checkerboard_charges(dims)
+    q, _ = xlbomd.scf(pos, m0, n_occ, beta=1.0, tol=1e-11, n0=n0)
     w0 = virial_at(pos, q, m0, n_occ, 0.0)
     w1 = virial_at(pos, q, m0, n_occ, 1.0)
     return -w0 / (w1 - w0), w0, q
@@ -38,4 +42,8 @@ if __name__ == "__main__":
     import synth
     A, w0, q = zero_virial_amplitude(synth.MD_MODEL)
     print(f"rho = {synth.MD_MODEL.pair_rho} A: zero-virial amplitude A = {A:.6f} eV "
+          f"(W(0) = {w0:.4f} eV, charges {q.min():.4f} .. {q.max():.4f})")
+    g = synth.GAPPED_MD_MODEL
+    A, w0, q = zero_virial_amplitude(g, spacing=synth.GAPPED_SPACING, n0=np.zeros(64))
+    print(f"gapped: rho = {g.pair_rho} A: zero-virial amplitude A = {A:.6f} eV "
           f"(W(0) = {w0:.4f} eV, charges {q.min():.4f} .. {q.max():.4f})")

@@ -732,6 +732,7 @@ struct xlbomd {
     tb_params p;
     xlbomd_options o;
     int nat;
+    int n_occ;            // doubly occupied states: z_val n_atoms / 2
     double *xyz, *vel, *F, *q, *hist, *H, *D, *dev, *dscal;
     int head;
     long step;
@@ -748,7 +749,7 @@ static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true, fl
     sp2_status s = tb_hamiltonian(c, &m->p, nat, m->xyz, n_t, m->H);
     if (s != SP2_OK) return s;
     sp2_stats st;
-    s = sp2_solve(c, N, m->H, 2 * nat, m->o.sp2, m->D, &st);
+    s = sp2_solve(c, N, m->H, m->n_occ, m->o.sp2, m->D, &st);
     if (s != SP2_OK) return s;
     m->dm_count += 1;
     if (iters) *iters = st.iterations;
@@ -770,6 +771,11 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
         return fail(c, SP2_EINVAL, "SCF start needs 0 < scf_beta <= 1 and scf_tol > 0");
     *out = nullptr;
     if (n_atoms < 2 || n_atoms > 16384) return fail(c, SP2_EINVAL, "n_atoms out of range");
+    // neutral atoms with z_val valence electrons in doubly occupied states
+    const double electrons = p->z_val * n_atoms;
+    const long n_occ = std::lround(electrons / 2.0);
+    if (!(std::fabs(electrons - 2.0 * (double)n_occ) < 1e-9) || n_occ <= 0 || n_occ >= 4L * n_atoms)
+        return fail(c, SP2_EINVAL, "z_val * n_atoms must be an even electron count below 8 n_atoms");
     if (o->K < 1 || o->K > 8 || !(o->dt_fs > 0) || !(p->mass > 0) || !(o->diverge_q >= 0))
         return fail(c, SP2_EINVAL, "bad xlbomd options");
     sp2_status s = check_options(c, o->sp2, 4 * n_atoms);
@@ -781,6 +787,7 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
     m->p = *p;
     m->o = *o;
     m->nat = n_atoms;
+    m->n_occ = (int)n_occ;
     const size_t N = 4 * (size_t)n_atoms;
     const int L = o->K + 1;
     double** bufs[] = {&m->xyz, &m->vel, &m->F, &m->q, &m->dev};

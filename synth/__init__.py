@@ -198,6 +198,10 @@ SPARSE = Workload("blocksparse_n16384", (8, 8, 64), 3)
 # (64 orbitals per layer) and grows along z.
 GAPPED_MODEL = TBModel(eps_p=4.0, z_val=2)
 GAPPED_SPACING = 2.0
+# For MD on the gapped wire: the smooth hopping tail of MD_MODEL and a pair
+# repulsion whose amplitude gives the self-consistent unjittered 4 x 4 x 4
+# lattice at 2.0 A zero virial (oracle/calibrate_pair.py).
+GAPPED_MD_MODEL = GAPPED_MODEL.with_(r_tail=3.5, pair_a=3.373945, pair_rho=0.15)
 
 
 def gapped_workload(n_layers: int, seed: int = 3) -> Workload:

@@ -374,6 +374,64 @@ def test_energy_drift_with_block_threshold(ctx):
     assert dev > 1e-9      # dropping only exactly-zero blocks would leave the runs bitwise equal
 
 
+def test_energy_drift_gapped_wire_elementwise_threshold(ctx):
+    """The paper's linear-scaling setting: an insulator with every element
+    below tau = 1e-5 zeroed after each projection (Linear scaling section;
+    caption of the isocyanic-acid energy figure).  Gapped 4 x 4 x 32 wire
+    (512 atoms, N = 2048, gap ~5 eV, two valence electrons per atom) partly
+    relaxed by 1500 quenched steps (the 64 A wire's soft modes take far longer
+    to relax; sigma and drift are measured about a linear fit either way),
+    then 1000 steps of 0.25 fs at 300 K with tau = 0 and with the elementwise
+    tau = 1e-5, both from the converged tau = 0 charges.  Bars: the threshold
+    keeps less than half of the 32 x 32 blocks at every step; sigma <= 1e-4
+    eV/atom in both runs; the tau = 0 run meets drift <= 2 sigma, while the
+    thresholded one, whose energy the paper describes as a small random walk
+    about its mean (its own table puts that run's drift over the whole run
+    at ~25 sigma), is held to a drift below 1e-5 eV/atom over the 250 fs
+    (measured 1.5e-6); and the two runs differ."""
+    import paper_1203_6836_amd as p
+    say("case xlbomd gapped wire 512 atoms, elementwise tau = 1e-5 vs 0, 1000 steps")
+    m = synth.GAPPED_MD_MODEL
+    pos = synth.gapped_workload(32).positions()
+    nat = len(pos)
+    md = ctx.xlbomd_create(m, pos, np.zeros((nat, 3)), np.zeros(nat), sp2_opts=p.options("fp64"),
+                           scf_beta=1.0, scf_tol=1e-10, scf_max_iter=100)
+    fmax, x0 = quench(md, nat, ftol=1e-4)
+    md.close()
+    say(f"  quenched: max force {fmax:.1e} eV/A")
+    assert fmax < 5.0
+    vel = synth.maxwell_velocities(nat, 300.0, m.mass, seed=23)
+    md = ctx.xlbomd_create(m, x0, vel, np.zeros(nat), sp2_opts=p.options("fp64"),
+                           scf_beta=1.0, scf_tol=1e-10, scf_max_iter=100)
+    q0 = md.xlbomd_get()[2]
+    md.close()
+    et, fmax_fill = {}, {}
+    for tau in (0.0, 1e-5):
+        md = ctx.xlbomd_create(m, x0, vel, q0, sp2_opts=p.options("fp64", tau=tau, threshold=1), scf_max_iter=0)
+        log = []
+        while len(log) < 1000:
+            log += md.xlbomd_run(200)
+        md.close()
+        et[tau] = np.array([r["etot"] for r in log])
+        fmax_fill[tau] = max(r["fill_min"] for r in log)
+        t = np.arange(len(log))
+        fit = np.polyfit(t, et[tau], 1)
+        sigma = float((et[tau] - np.polyval(fit, t)).std())
+        drift = abs(fit[0]) * len(log)
+        say(f"  tau {tau:g}: largest per-step min fill {fmax_fill[tau]:.3f}; sigma {sigma:.2e} eV "
+            f"({sigma / nat:.1e}/atom), drift {drift:.1e} eV, "
+            f"SP2 products per step {np.mean([r['sp2_iterations'] for r in log]):.1f}")
+        assert sigma / nat <= 1e-4
+        if tau == 0.0:
+            assert drift <= 2.0 * sigma
+        else:
+            assert drift / nat <= 1e-5
+    dev = float(np.abs(et[1e-5] - et[0.0]).max())
+    say(f"  max |E_tot(tau) - E_tot(0)| {dev:.1e} eV")
+    assert fmax_fill[1e-5] < 0.5 and fmax_fill[0.0] == 1.0
+    assert dev > 1e-9
+
+
 def test_energy_drift_int8(ctx):
     """The int8 digit-plane density matrices (error ~1e-7 per sqrt N) in the
     same 1000-step run as the FP64 drift test: no systematic drift, and the
