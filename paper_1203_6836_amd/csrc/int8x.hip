@@ -638,19 +638,52 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
 // Zero-tile flags tz (one row of T upper tiles per X buffer, kept with the
 // threshold pass): a tile whose K range is empty and whose X_n tile is all
 // zero has X_{n+1} = 0 there under either branch.  k_tile_list visits the
-// tiles in diagonal-major order; such a tile gets zero partials and is left
+// tiles in the product's G x G super-tile order; such a tile gets zero
+// partials and is left
 // out when its destination tile is already all zero, or is listed for plain
 // zero stores (no reads) when it is not; every other tile is listed for the
 // product.  The list holds (zero_store << 30) | (bi << 15) | bj; list_ctr[0]
-// counts entries, list_ctr[1] hands them out.
+// counts entries, list_ctr[1] hands them out in list order, so whatever the
+// order, the work is balanced, and concurrent workgroups work on nearby
+// tiles that share row panels.
+// order_tile with one step per super-tile row instead of one per super-tile
+// (the list kernel maps every tile of the triangle): the same tile for
+// every position.
+__device__ __forceinline__ void order_tile_rows(int t, int nt, int G, int& bi, int& bj) {
+    if (G <= 0 || G > nt) G = nt;
+    int I = 0, gi = min(G, nt);
+    for (;;) {
+        gi = min(G, nt - I * G);
+        const int row = gi * (gi + 1) / 2 + gi * (nt - I * G - gi);
+        if (t < row || I * G + gi >= nt) break;
+        t -= row;
+        ++I;
+    }
+    const int d = gi * (gi + 1) / 2;
+    if (t < d) {
+        int li = 0, off = 0;
+        while (t >= off + (gi - li)) { off += gi - li; ++li; }
+        bi = I * G + li;
+        bj = I * G + li + (t - off);
+        return;
+    }
+    t -= d;
+    const int J = I + 1 + t / (gi * G);
+    t -= (J - I - 1) * gi * G;
+    const int gj = min(G, nt - J * G);
+    bi = I * G + t / gj;
+    bj = J * G + t % gj;
+}
+
 __global__ void k_list_reset(int* __restrict__ list_ctr, const State* __restrict__ st) {
     if (st->done || st->phase != 1) return;
     if (threadIdx.x < 2) list_ctr[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_tile_list(const State* __restrict__ st, const int* __restrict__ env,
-                                                   const int* __restrict__ tz, int nt, double* __restrict__ part,
-                                                   int* __restrict__ list, int* __restrict__ list_ctr) {
+                                                   const int* __restrict__ tz, int nt, int tile_group,
+                                                   double* __restrict__ part, int* __restrict__ list,
+                                                   int* __restrict__ list_ctr) {
     if (st->done || st->phase != 1) return;
     const int T = nt * (nt + 1) / 2;
     const int pos = blockIdx.x * 256 + threadIdx.x;
@@ -658,7 +691,7 @@ __global__ __launch_bounds__(256) void k_tile_list(const State* __restrict__ st,
     int item = 0;
     if (pos < T) {
         int bi, bj;
-        diag_tile(pos, nt, bi, bj);
+        order_tile_rows(pos, nt, tile_group, bi, bj);
         const int t = tri_index(bi, bj, nt);
         const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
         const bool zero_next = lo > hi && tz[(size_t)st->cur * T + t] != 0;
@@ -840,7 +873,8 @@ static hipError_t launch_list_kernel(SplitScratch& s, double* buf0, double* buf1
     int* list = s.tz + (size_t)2 * T;
     int* ctr = list + T;
     hipLaunchKernelGGL(k_list_reset, dim3(1), dim3(64), 0, stream, ctr, st);
-    hipLaunchKernelGGL(k_tile_list, dim3((T + 255) / 256), dim3(256), 0, stream, st, env, s.tz, nt, part, list, ctr);
+    hipLaunchKernelGGL(k_tile_list, dim3((T + 255) / 256), dim3(256), 0, stream, st, env, s.tz, nt, s.tile_group, part,
+                       list, ctr);
     const int grid = std::min(T, device_cus());
     hipLaunchKernelGGL(k_gemm_int8x_list<S>, dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits, s.scale,
                        part, env, s.tz, list, ctr);
