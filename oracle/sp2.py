@@ -101,24 +101,28 @@ def choose_branch(t1, t2, n_occ):
     return 0 if abs(t2 - n_occ) <= abs(2.0 * t1 - t2 - n_occ) else 1
 
 
+def _blocks(A, bs):
+    """A (N x N) zero-padded to whole bs x bs blocks, viewed as
+    [block row, row in block, block column, column in block]."""
+    N = A.shape[0]
+    nb = (N + bs - 1) // bs
+    P = np.zeros((nb * bs, nb * bs), dtype=A.dtype)
+    P[:N, :N] = A
+    return P.reshape(nb, bs, nb, bs), nb
+
+
 def block_threshold(X, tau, bs=32):
     """Zero every bs x bs block whose Frobenius norm is below tau.
 
     Returns (thresholded copy, fraction of blocks kept).  Blocks on the
-    ragged edge are the partial blocks of the grid.
+    ragged edge are the partial blocks of the grid (zero padding adds
+    nothing to their norms).
     """
     N = X.shape[0]
-    nb = (N + bs - 1) // bs
-    Y = X.copy()
-    kept = 0
-    for bi in range(nb):
-        for bj in range(nb):
-            blk = Y[bi * bs:(bi + 1) * bs, bj * bs:(bj + 1) * bs]
-            if np.sqrt(np.sum(blk * blk)) < tau:
-                blk[...] = 0.0
-            else:
-                kept += 1
-    return Y, kept / (nb * nb)
+    B, nb = _blocks(X, bs)
+    keep = np.sqrt(np.sum(B * B, axis=(1, 3))) >= tau          # nb x nb
+    mask = np.repeat(np.repeat(keep, bs, axis=0), bs, axis=1)[:N, :N]
+    return np.where(mask, X, 0.0), int(keep.sum()) / (nb * nb)
 
 
 def element_threshold(X, tau, bs=32):
@@ -128,14 +132,8 @@ def element_threshold(X, tau, bs=32):
     nonzero element), the fill measure of the block form.
     """
     Y = np.where(np.abs(X) < tau, 0.0, X)
-    N = X.shape[0]
-    nb = (N + bs - 1) // bs
-    kept = 0
-    for bi in range(nb):
-        for bj in range(nb):
-            if np.any(Y[bi * bs:(bi + 1) * bs, bj * bs:(bj + 1) * bs] != 0.0):
-                kept += 1
-    return Y, kept / (nb * nb)
+    B, nb = _blocks(Y != 0.0, bs)
+    return Y, int(B.any(axis=(1, 3)).sum()) / (nb * nb)
 
 
 STALL_RATIO_THRESHOLDED = 0.5
