@@ -102,6 +102,28 @@ def test_int8x_full_size_against_fp64_path(ctx):
     assert err <= TOL_D and dq <= TOL_Q
 
 
+def test_int8x_full_size_against_oracle(ctx):
+    """N = 8192 as benchmarked (int8, 5 planes, default launch): against the
+    oracle's FP64 SP2 of the same Hamiltonian, built by the oracle (about a
+    minute of host BLAS)."""
+    import time
+    import paper_1203_6836_amd as p
+    say("case int8x N=8192 vs oracle (full size)")
+    w = synth.MIXED
+    t0 = time.perf_counter()
+    H = otb.hamiltonian(w.positions(), None, synth.STATIC_MODEL)
+    ref = osp2.sp2(H, w.n_occ)
+    say(f"  oracle: {ref.iterations} products in {time.perf_counter() - t0:.0f} s, status {ref.status}")
+    D8, s8 = ctx.sp2_density_matrix(to_dev(H), w.n_occ, p.options("int8x"))
+    D8 = D8.cpu().numpy()
+    err = np.linalg.norm(D8 - ref.D) / np.sqrt(w.n_orb)
+    dq = float(np.abs(observables.mulliken(D8) - observables.mulliken(ref.D)).max())
+    say(f"  iters gpu={s8['iterations']} oracle={ref.iterations} err/sqrtN={err:.2e} max|dq|={dq:.2e}")
+    assert ref.status == "converged"
+    assert abs(s8["iterations"] - ref.iterations) <= 2
+    assert err <= TOL_D and dq <= TOL_Q
+
+
 @pytest.mark.parametrize("dims,seed", [((4, 4, 4), 0), ((8, 8, 8), 2)])
 def test_bf16x2_configured_recipe_reported(ctx, dims, seed):
     """The configured BF16 hi+lo / FP32-tail recipe: runs, ends idempotent, and its

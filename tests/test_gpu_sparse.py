@@ -144,6 +144,40 @@ def test_int8x_elementwise_gapped_wire_vs_oracle(ctx):
     assert abs(np.trace(D) - w.n_occ) < 1e-4
 
 
+def test_gapped_wire_full_size_against_oracle(ctx):
+    """The smallest size of the benchmark's thresholded-scaling leg (gapped
+    wire, N = 8192, elementwise tau = 1e-5) against the oracle's thresholded
+    SP2: FP64 products step by step (iterations, fill after every update, D),
+    and the benchmark's int8 products within 1e-5 per sqrt N (a twentieth of
+    what the threshold itself moves D, 2.2e-4: the int8 products differ from
+    FP64 by ~1e-7 relative and move a few elements across tau)."""
+    import time
+    import paper_1203_6836_amd as p
+    say("case gapped wire N=8192 elementwise tau=1e-5 vs oracle (full size)")
+    w = synth.gapped_workload(128)
+    t0 = time.perf_counter()
+    H = otb.hamiltonian0(w.positions(), synth.GAPPED_MODEL)
+    ref = osp2.sp2(H, w.n_occ, tau=1e-5, threshold="element")
+    say(f"  oracle: {ref.iterations} products in {time.perf_counter() - t0:.0f} s, status {ref.status}, "
+        f"fill {ref.fill[0]:.4f} -> {max(ref.fill):.4f}")
+    Hd = to_dev(H)
+    D, st = ctx.sp2_density_matrix(Hd, w.n_occ, p.options("fp64", tau=1e-5, threshold=1))
+    D = D.cpu().numpy()
+    rn = np.sqrt(w.n_orb)
+    err = np.linalg.norm(D - ref.D) / rn
+    n_upd = st["iterations"] - 1
+    say(f"  fp64: iters {st['iterations']} err/sqrtN {err:.2e}")
+    assert st["iterations"] == ref.iterations and st["status"] == ref.status
+    assert err <= 1e-9
+    np.testing.assert_allclose(st["fill_hist"][:n_upd], ref.fill[1:1 + n_upd], atol=1e-7)
+    D8, s8 = ctx.sp2_density_matrix(Hd, w.n_occ, p.options("int8x", tau=1e-5, threshold=1))
+    D8 = D8.cpu().numpy()
+    err8 = np.linalg.norm(D8 - ref.D) / rn
+    say(f"  int8: iters {s8['iterations']} err/sqrtN {err8:.2e}, trace {np.trace(D8) - w.n_occ:+.1e}")
+    assert abs(s8["iterations"] - ref.iterations) <= 1
+    assert err8 <= 1e-5
+
+
 def test_gapped_wire_thresholded_scaling(ctx):
     """Gapped wires of N = 8192, 16384 and 32768 orbitals: int8 products, the
     elementwise rule at tau = 1e-5.  The kept fraction falls as 1/N and the
