@@ -332,7 +332,7 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
             if (o.tau > 0.0)
                 HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, c->part, &ns, 0, st,
-                                                 env, tz));
+                                                 env, tz, tz ? tz + (size_t)2 * tri_tiles(nt) : nullptr));
             if (pe) HIPCHK(c, hipEventRecord(pe[4], st));
             HIPCHK(c, launch_ctrl_step(c->part, ns, c->st, a, st));
         }

@@ -2,6 +2,8 @@
 // zero every element below tau; the block form zeroes whole 32 x 32 blocks
 // whose Frobenius norm is below tau) and the operand storage of the
 // reduced-precision products.
+#include <algorithm>
+
 #include "split_internal.h"
 
 namespace sp2 {
@@ -18,35 +20,19 @@ __device__ __forceinline__ void tri_coords_t(int t, int nt, int& bi, int& bj) {
     bj = i + (t - off);
 }
 
-// One workgroup per upper-triangular 128 x 128 tile t (same numbering as the
-// dense product's partial slots); each wave owns four of its sixteen 32 x 32
-// blocks.  Block rule (elem == 0): blocks with ||B||_F < tau are zeroed (with
-// their mirror).  Elementwise rule (elem != 0): elements with |x| < tau are
-// zeroed (with their mirror; X is stored exactly symmetric, so both copies
-// take the same decision), and a block counts as kept while any element of
-// it survives.  The tile's trace and ||X||_F^2 partials are rewritten for the
-// thresholded X; the idempotency partial of the product is kept (zeroed for
-// X_0).
-__global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ buf0, double* __restrict__ buf1,
-                                                         int ld, int N, double tau, int elem,
-                                                         State* __restrict__ st, double* __restrict__ part,
-                                                         int init, int* __restrict__ env, int* __restrict__ tz) {
-    if (st->done) return;
-    const int xb = init ? 0 : (st->cur ? 0 : 1);
-    double* X = xb == 0 ? buf0 : buf1;
-    const int nt = ld / 128;
-    const int t = blockIdx.x;
-    const int T = nt * (nt + 1) / 2;
-    // a tile the product wrote as all zero: nothing to threshold or record
-    if (tz && !init && tz[(size_t)xb * T + t]) {
-        if (threadIdx.x == 0) {
-            part[3 * t + 0] = 0.0;
-            part[3 * t + 1] = 0.0;
-        }
-        return;
-    }
-    int bi, bj;
-    tri_coords_t(t, nt, bi, bj);
+// One upper-triangular 128 x 128 tile t = (bi, bj) of X (buffer index xb;
+// same numbering as the dense product's partial slots), all 256 threads of
+// the workgroup (the body contains a barrier); each wave owns four of its
+// sixteen 32 x 32 blocks.  Block rule (elem == 0): blocks with ||B||_F < tau
+// are zeroed (with their mirror).  Elementwise rule (elem != 0): elements
+// with |x| < tau are zeroed (with their mirror; X is stored exactly
+// symmetric, so both copies take the same decision), and a block counts as
+// kept while any element of it survives.  The tile's trace and ||X||_F^2
+// partials are rewritten for the thresholded X; the idempotency partial of
+// the product is kept (zeroed for X_0).
+__device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau, int elem, State* __restrict__ st,
+                               double* __restrict__ part, int init, int* __restrict__ env, int* __restrict__ tz,
+                               int xb, int T, int t, int bi, int bj) {
     const bool mirror = bi != bj;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nb = (N + 31) / 32;
@@ -54,20 +40,22 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
     int kept = 0;
     // surviving 32-column blocks of panel bi (columns c0) and, by symmetry, of panel bj (rows r0)
     int lo_i = 0x7fffffff, hi_i = -1, lo_j = 0x7fffffff, hi_j = -1;
+    // transposed copy of each wave's block, for coalesced writes of the
+    // mirrored block (row stride 33 spreads the column-wise stores over banks)
+    __shared__ double tb[4][32][33];
     for (int s = 0; s < 4; ++s) {
         const int b = w * 4 + s, br = b >> 2, bc = b & 3;
         const int r0 = bi * 128 + br * 32, c0 = bj * 128 + bc * 32;
         double v[16];
         double ss = 0.0;
-        bool nz = false;
+        bool nz = false, changed = false;
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             const int e = lane + 64 * m, r = e >> 5, c = e & 31;
             v[m] = X[(size_t)(r0 + r) * ld + c0 + c];
             if (elem && v[m] != 0.0 && fabs(v[m]) < tau) {
                 v[m] = 0.0;
-                X[(size_t)(r0 + r) * ld + c0 + c] = 0.0;
-                if (mirror) X[(size_t)(c0 + c) * ld + r0 + r] = 0.0;
+                changed = true;
             }
             nz = nz || v[m] != 0.0;
             ss += v[m] * v[m];
@@ -77,11 +65,37 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
         if (!keep && !elem) {
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
-                const int e = lane + 64 * m, r = e >> 5, c = e & 31;
-                X[(size_t)(r0 + r) * ld + c0 + c] = 0.0;
-                if (mirror) X[(size_t)(c0 + c) * ld + r0 + r] = 0.0;
+                changed = changed || v[m] != 0.0;
+                v[m] = 0.0;
             }
-        } else if (keep) {
+        }
+        // write back only blocks that changed: the block row by row, and its
+        // mirror (X is exactly symmetric, so the mirror is the transpose)
+        const bool wchanged = __any(changed);
+        if (wchanged) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int e = lane + 64 * m, r = e >> 5, c = e & 31;
+                X[(size_t)(r0 + r) * ld + c0 + c] = v[m];
+            }
+        }
+        if (mirror) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int e = lane + 64 * m, r = e >> 5, c = e & 31;
+                tb[w][c][r] = v[m];
+            }
+            __syncthreads();
+            if (wchanged) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    const int e = lane + 64 * m, r = e >> 5, c = e & 31;
+                    X[(size_t)(c0 + r) * ld + r0 + c] = tb[w][r][c];
+                }
+            }
+            __syncthreads();
+        }
+        if (keep) {
             fro += ss;
             if (r0 == c0) {
 #pragma unroll
@@ -139,6 +153,52 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
     }
 }
 
+__global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                         int ld, int N, double tau, int elem,
+                                                         State* __restrict__ st, double* __restrict__ part,
+                                                         int init, int* __restrict__ env, int* __restrict__ tz) {
+    if (st->done) return;
+    const int xb = init ? 0 : (st->cur ? 0 : 1);
+    const int nt = ld / 128;
+    const int t = blockIdx.x;
+    const int T = nt * (nt + 1) / 2;
+    // a tile the product wrote as all zero: nothing to threshold or record
+    if (tz && !init && tz[(size_t)xb * T + t]) {
+        if (threadIdx.x == 0) {
+            part[3 * t + 0] = 0.0;
+            part[3 * t + 1] = 0.0;
+        }
+        return;
+    }
+    int bi, bj;
+    tri_coords_t(t, nt, bi, bj);
+    threshold_tile(xb == 0 ? buf0 : buf1, ld, N, tau, elem, st, part, init, env, tz, xb, T, t, bi, bj);
+}
+
+// Thresholded int8 products driven by a work list (entries (zero_store << 30)
+// | (bi << 15) | bj, list_ctr[0] of them): only the tiles the product
+// computed are visited.  Every other tile is all zero, with zero partials
+// and its flag set, by the list kernel or by the product's zero stores.
+__global__ __launch_bounds__(256) void k_block_threshold_list(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                              int ld, int N, double tau, int elem,
+                                                              State* __restrict__ st, double* __restrict__ part,
+                                                              int* __restrict__ env, int* __restrict__ tz,
+                                                              const int* __restrict__ list,
+                                                              const int* __restrict__ list_ctr) {
+    if (st->done) return;
+    const int xb = st->cur ? 0 : 1;
+    double* X = xb == 0 ? buf0 : buf1;
+    const int nt = ld / 128, T = nt * (nt + 1) / 2;
+    const int n = list_ctr[0];
+    for (int k = blockIdx.x; k < n; k += gridDim.x) {
+        const int it = list[k];
+        if (it >> 30) continue;
+        const int bi = (it >> 15) & 0x7fff, bj = it & 0x7fff;
+        threshold_tile(X, ld, N, tau, elem, st, part, 0, env, tz, xb, T, tri_index(bi, bj, nt), bi, bj);
+        __syncthreads();   // the tile's shared sums are reused by the next entry
+    }
+}
+
 // Empty ranges for every panel (before a threshold pass records new ones).
 __global__ void k_env_reset(int* __restrict__ env, int npanel, const State* __restrict__ st) {
     if (st->done) return;
@@ -150,13 +210,18 @@ __global__ void k_env_reset(int* __restrict__ env, int npanel, const State* __re
 }
 
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
-                                  double* part, int* nslots, int init, hipStream_t stream, int* env, int* tz) {
+                                  double* part, int* nslots, int init, hipStream_t stream, int* env, int* tz,
+                                  const int* list) {
     const int nt = ld / 128;
     const int T = nt * (nt + 1) / 2;
     *nslots = T;
     if (env) hipLaunchKernelGGL(k_env_reset, dim3((nt + 255) / 256), dim3(256), 0, stream, env, nt, st);
-    hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, elem, st, part,
-                       init, env, tz);
+    if (list && tz && env && !init)
+        hipLaunchKernelGGL(k_block_threshold_list, dim3(std::min(T, 2048)), dim3(256), 0, stream, buf0, buf1, ld, N,
+                           tau, elem, st, part, env, tz, list, list + T);
+    else
+        hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, elem, st, part,
+                           init, env, tz);
     return hipGetLastError();
 }
 

@@ -55,10 +55,12 @@ hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld
 // T upper-triangular tiles, one row per X buffer): tiles the product marked
 // as written all zero are skipped, and every other tile's flag is set to
 // whether it is all zero after thresholding; the X_0 pass reads no flags,
-// sets those of buffer 0 and clears those of buffer 1.
+// sets those of buffer 0 and clears those of buffer 1.  With list non-null
+// as well (the int8 product's work list: T entries, then its entry count),
+// updates visit only the tiles the product computed.
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
                                   double* part, int* nslots, int init, hipStream_t stream, int* env = nullptr,
-                                  int* tz = nullptr);
+                                  int* tz = nullptr, const int* list = nullptr);
 
 // int8 digit-plane product (int8x.hip)
 hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
