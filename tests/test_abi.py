@@ -51,3 +51,37 @@ def test_host_side_argument_checks_without_gpu(libh):
     assert libh.sp2_density_matrix(None, 16, None, 8, None, None, None) == -1
     libh.xlbomd_run.restype = ctypes.c_int
     assert libh.xlbomd_run(None, 1, None) == -1
+
+
+STRUCTS = {"sp2_options": "Sp2Options", "sp2_stats": "Sp2Stats", "sp2_tune_result": "TuneResult",
+           "tb_params": "TBParams", "xlbomd_options": "XLOptions", "xlbomd_record": "XLRecord",
+           "sp2_server_options": "ServerOptions"}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (a C program built with the host compiler prints them)."""
+    import shutil
+    import subprocess
+    import paper_1203_6836_amd as p
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "sp2qmd.h"', 'int main(void) {']
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(p, pyname)
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(p, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
