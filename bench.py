@@ -257,7 +257,44 @@ def thresholded_scaling(ctx, layers=(128, 256, 512, 1024), dense_max=16384):
         del D, H
         torch.cuda.empty_cache()
     return {"workload": "gapped sp wire 4x4xL, 2.0 A, p level +4 eV, 2 electrons per atom",
-            "precision": "int8x", "tau": 1e-5, "threshold": "element", "rows": rows}
+            "precision": "int8x", "tau": 1e-5, "threshold": "element", "rows": rows,
+            "xlbomd": thresholded_md(ctx)}
+
+
+def thresholded_md(ctx, layers=(128, 256), steps=20):
+    """XL-BOMD steps on the gapped wire (2048 and 4096 atoms; one SP2 solve,
+    charges, forces and the Verlet updates per step), int8 products, without
+    and with the elementwise threshold tau = 1e-5: milliseconds per MD step.
+    The closed-shell atoms start from zero charges (no SCF), at 300 K."""
+    import numpy as np
+
+    import paper_1203_6836_amd as p
+    import synth
+
+    out = []
+    for L in layers:
+        w = synth.gapped_workload(L)
+        m = synth.GAPPED_MD_MODEL
+        xyz = w.positions()
+        vel = synth.maxwell_velocities(w.n_atoms, 300.0, m.mass, seed=31)
+        row = {"n_atoms": w.n_atoms, "n": w.n_orb, "steps": steps}
+        for name, opt in (("tau0", p.options("int8x")), ("tau1e-5", p.options("int8x", tau=1e-5, threshold=1))):
+            log(f"thresholded MD: {w.n_atoms} atoms, {name}")
+            md = ctx.xlbomd_create(m, xyz, vel, np.zeros(w.n_atoms), sp2_opts=opt, scf_max_iter=0)
+            md.xlbomd_run(2)                          # warm (allocation, first solves)
+            t0 = time.perf_counter()
+            rec = md.xlbomd_run(steps)
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            md.close()
+            et = [r["etot"] for r in rec]
+            row[name] = {"ms_per_step": round(ms, 2),
+                         "sp2_products_per_step": round(float(np.mean([r["sp2_iterations"] for r in rec])), 1),
+                         "fill_min": round(min(r["fill_min"] for r in rec), 4),
+                         "etot_span_ev": float(max(et) - min(et))}
+        row["speedup"] = round(row["tau0"]["ms_per_step"] / row["tau1e-5"]["ms_per_step"], 2)
+        log(f"  {row}")
+        out.append(row)
+    return out
 
 
 def main():
