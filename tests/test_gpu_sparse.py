@@ -144,6 +144,33 @@ def test_int8x_elementwise_gapped_wire_vs_oracle(ctx):
     assert abs(np.trace(D) - w.n_occ) < 1e-4
 
 
+def test_int8x_threshold_after_fp64_head_vs_oracle(ctx):
+    """Thresholded int8 solve whose first 3 products are FP64 (fp64_head = 3):
+    the int8 products then run on the full grid of tiles, diagonal by
+    diagonal, without zero-tile flags, from the band-limited encode.  Both
+    rules against the oracle on the gapped 4 x 4 x 32 wire (N = 2048), to the
+    same bar as the list-driven path."""
+    import paper_1203_6836_amd as p
+    w = synth.gapped_workload(32)
+    H = otb.hamiltonian0(w.positions(), synth.GAPPED_MODEL)
+    dense = osp2.sp2(H, w.n_occ)
+    rn = np.sqrt(H.shape[0])
+    for rule, name in ((0, "block"), (1, "element")):
+        say(f"case int8x fp64_head=3 tau=1e-5 {name} rule, gapped wire N=2048")
+        ref = osp2.sp2(H, w.n_occ, tau=1e-5, threshold=name)
+        D, st = ctx.sp2_density_matrix(to_dev(H), w.n_occ,
+                                       p.options("int8x", tau=1e-5, threshold=rule, fp64_head=3))
+        D = D.cpu().numpy()
+        err = np.linalg.norm(D - ref.D) / rn
+        err_thr = np.linalg.norm(ref.D - dense.D) / rn
+        say(f"  iters gpu={st['iterations']} ({st['fp64_products']} FP64) oracle={ref.iterations}; "
+            f"err vs oracle {err:.2e}, threshold's own {err_thr:.2e}")
+        assert st["fp64_products"] == 3
+        assert abs(st["iterations"] - ref.iterations) <= 1
+        assert err <= 0.25 * err_thr
+        assert abs(np.trace(D) - w.n_occ) < 1e-4
+
+
 def test_gapped_wire_full_size_against_oracle(ctx):
     """The smallest size of the benchmark's thresholded-scaling leg (gapped
     wire, N = 8192, elementwise tau = 1e-5) against the oracle's thresholded
