@@ -104,9 +104,10 @@ typedef struct {
     double trace;            /* Tr D                                             */
     uint64_t branch_bits[2]; /* bit n set: update n was X <- 2X - X^2            */
     double ms;               /* wall time of the solve on the stream (ms)        */
-    double fill_min, fill_max; /* block-thresholded: kept-block fraction range   */
+    double fill_min, fill_max; /* tau > 0: range of the fraction of 32x32 blocks
+                                  holding a nonzero after each update (X_0 incl.) */
     float idem_hist[128];    /* ||X_n^2 - X_n||_F of product n                   */
-    float fill_hist[128];    /* kept-block fraction after update n (tau > 0)     */
+    float fill_hist[128];    /* that fraction after update n (tau > 0)         */
     /* Filled only when profiling is on (sp2_ctx_set_profiling): summed HIP-event
      * durations of the product kernels that formed products, [0] FP64 product
      * kernel, [1] reduced-precision product kernel, and their launch counts;
