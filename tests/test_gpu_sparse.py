@@ -95,14 +95,15 @@ def test_threshold_rule_is_validated(ctx):
     assert st == p.SP2_EINVAL
 
 
-@pytest.mark.parametrize("rule", [0, 1])
-def test_fp64_threshold_gapped_wire_matches_oracle(ctx, rule):
-    """Gapped 4 x 4 x 32 wire (N = 2048): both rules, FP64 products, against the
-    oracle step by step (iterations, fill after every update, D)."""
+@pytest.mark.parametrize("rule,layers", [(0, 32), (1, 32), (1, 33)])
+def test_fp64_threshold_gapped_wire_matches_oracle(ctx, rule, layers):
+    """Gapped 4 x 4 x 32 wire (N = 2048), and a ragged 4 x 4 x 33 one
+    (N = 2112): FP64 products, against the oracle step by step (iterations,
+    fill after every update, D)."""
     import paper_1203_6836_amd as p
     name = ("block", "element")[rule]
-    say(f"case fp64 tau=1e-5 {name} rule, gapped wire N=2048")
-    w = synth.gapped_workload(32)
+    w = synth.gapped_workload(layers)
+    say(f"case fp64 tau=1e-5 {name} rule, gapped wire N={w.n_orb}")
     H = otb.hamiltonian0(w.positions(), synth.GAPPED_MODEL)
     ref = osp2.sp2(H, w.n_occ, tau=1e-5, threshold=name)
     D, st = ctx.sp2_density_matrix(to_dev(H), w.n_occ, p.options("fp64", tau=1e-5, threshold=rule))
@@ -122,13 +123,16 @@ def test_fp64_threshold_gapped_wire_matches_oracle(ctx, rule):
         assert np.abs(nz).min() >= 1e-5 or nz.size == 0
 
 
-def test_int8x_elementwise_gapped_wire_vs_oracle(ctx):
-    """int8 products with the elementwise rule on the gapped wire: the products
-    differ from FP64 by ~1e-7 relative, which moves a few elements across
-    tau; the result stays within the error the threshold itself makes."""
+@pytest.mark.parametrize("layers", [32, 33, 1])
+def test_int8x_elementwise_gapped_wire_vs_oracle(ctx, layers):
+    """int8 products with the elementwise rule on the gapped wire (N = 2048; a
+    ragged N = 2112 whose last tiles are mostly padding; a one-tile N = 64):
+    the products differ from FP64 by ~1e-7 relative, which moves a few
+    elements across tau; the result stays within the error the threshold
+    itself makes."""
     import paper_1203_6836_amd as p
-    say("case int8x tau=1e-5 element rule, gapped wire N=2048")
-    w = synth.gapped_workload(32)
+    w = synth.gapped_workload(layers)
+    say(f"case int8x tau=1e-5 element rule, gapped wire N={w.n_orb}")
     H = otb.hamiltonian0(w.positions(), synth.GAPPED_MODEL)
     ref = osp2.sp2(H, w.n_occ, tau=1e-5, threshold="element")
     dense = osp2.sp2(H, w.n_occ)
