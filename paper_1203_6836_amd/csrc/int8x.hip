@@ -633,19 +633,6 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
                               UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, kmode, kc0, kc1, cacc, 0);
 }
 
-// ---- thresholded products driven by a work list (int8 from the first product on)
-//
-// Zero-tile flags tz (one row of T upper tiles per X buffer, kept with the
-// threshold pass): a tile whose K range is empty and whose X_n tile is all
-// zero has X_{n+1} = 0 there under either branch.  k_tile_list visits the
-// tiles in the product's G x G super-tile order; such a tile gets zero
-// partials and is left
-// out when its destination tile is already all zero, or is listed for plain
-// zero stores (no reads) when it is not; every other tile is listed for the
-// product.  The list holds (zero_store << 30) | (bi << 15) | bj; list_ctr[0]
-// counts entries, list_ctr[1] hands them out in list order, so whatever the
-// order, the work is balanced, and concurrent workgroups work on nearby
-// tiles that share row panels.
 // order_tile with one step per super-tile row instead of one per super-tile
 // (the list kernel maps every tile of the triangle): the same tile for
 // every position.
@@ -675,6 +662,18 @@ __device__ __forceinline__ void order_tile_rows(int t, int nt, int G, int& bi, i
     bj = J * G + t % gj;
 }
 
+// ---- thresholded products driven by a work list (int8 from the first product on)
+//
+// Zero-tile flags tz (one row of T upper tiles per X buffer, kept with the
+// threshold pass): a tile whose K range is empty and whose X_n tile is all
+// zero has X_{n+1} = 0 there under either branch.  k_tile_list visits the
+// tiles in the product's G x G super-tile order; such a tile gets zero
+// partials and is left out when its destination tile is already all zero,
+// or is listed for plain zero stores (no reads) when it is not; every other
+// tile is listed for the product.  The list holds (zero_store << 30) |
+// (bi << 15) | bj; list_ctr[0] counts entries, list_ctr[1] hands them out in
+// list order, so whatever the order the work is balanced, and concurrent
+// workgroups work on nearby tiles that share row panels.
 __global__ void k_list_reset(int* __restrict__ list_ctr, const State* __restrict__ st) {
     if (st->done || st->phase != 1) return;
     if (threadIdx.x < 2) list_ctr[threadIdx.x] = 0;

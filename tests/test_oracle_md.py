@@ -125,6 +125,18 @@ def test_md_pair_amplitude_zeroes_the_virial():
     assert np.allclose(np.abs(q), 4.0, atol=0.05)
 
 
+
+def test_gapped_md_pair_amplitude_zeroes_the_virial():
+    """The gapped MD model's frozen pair amplitude gives its self-consistent
+    unjittered 2.0 A lattice zero virial (closed-shell atoms, 2 electrons)."""
+    from oracle.calibrate_pair import virial_at, zero_virial_amplitude
+    m = synth.GAPPED_MD_MODEL
+    A, w0, q = zero_virial_amplitude(m, spacing=synth.GAPPED_SPACING, n0=np.zeros(64))
+    assert A == pytest.approx(m.pair_a, abs=1e-5)
+    pos = synth.lattice_positions((4, 4, 4), spacing=synth.GAPPED_SPACING, jitter=0.0, seed=0)
+    assert abs(virial_at(pos, q, m, len(pos), m.pair_a)) < 1e-5 * abs(w0)
+    assert np.abs(q).max() < 1e-2          # closed shells stay nearly neutral
+
 def test_pair_repulsion_walls_off_ion_collapse():
     """A +-4 e pair: with rho = 0.15 A the energy rises again below ~1 A; with
     rho = 0.3 A at its own zero-virial amplitude it falls all the way in."""
