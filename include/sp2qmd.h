@@ -189,6 +189,33 @@ sp2_status sp2_mulliken(sp2_ctx *ctx, int n_atoms, const double *D, double z_val
 sp2_status sp2_band_energy(sp2_ctx *ctx, int N, const double *D, const double *H,
                            double *e_host);
 
+/* Density matrix in a non-orthogonal basis (Non-orthogonal formulation
+ * subsection: H_perp = Z^T H Z with the congruence factor Z^T S Z = I of
+ * Eq. Congr, the T_e = 0 density matrix of H_perp as in Eq. DM_perp, and the
+ * de-orthogonalised rho = Z rho_perp Z^T).  Z is the Loewdin factor
+ * S^(-1/2), built by a coupled Newton-Schulz iteration (its products are
+ * plain rocBLAS FP64 GEMMs, as are the four products of the transforms);
+ * H_perp and rho are symmetrised; rho_perp is an SP2 solve with *opt (any
+ * precision and threshold), whose statistics go to *stats.  rho satisfies
+ * Tr[rho S] = n_occ and rho S rho = rho.
+ * H, S: N x N row-major FP64 device arrays (S symmetric positive definite;
+ * the caller keeps ownership); D_out: N x N device; factor_iterations (host,
+ * may be NULL): Newton-Schulz steps taken.  Scratch: 4 N^2 doubles owned by
+ * the context.  Errors: SP2_EINVAL (arguments, non-finite factor), SP2_ENOCONV
+ * (the factor did not converge in 40 steps: S not positive definite or badly
+ * conditioned), and those of sp2_density_matrix.  Blocks the host until D_out
+ * is written. */
+sp2_status sp2_density_matrix_nonorth(sp2_ctx *ctx, int N, const double *H, const double *S,
+                                      int n_occ, const sp2_options *opt, double *D_out,
+                                      sp2_stats *stats, int *factor_iterations);
+
+/* Net Mulliken charges in a non-orthogonal basis: q_i = 2 sum_{alpha in i}
+ * (D S)_{i alpha, i alpha} - z_val (the charges whose derivative the
+ * non-orthogonal force equation uses).  D, S: (4 n_atoms)^2 device, S
+ * symmetric; q_out: n_atoms device. */
+sp2_status sp2_mulliken_overlap(sp2_ctx *ctx, int n_atoms, const double *D, const double *S,
+                                double z_val, double *q_out);
+
 /* ---------------------------------------------------------------------
  * Tight-binding model, forces and XL-BOMD
  * ------------------------------------------------------------------- */

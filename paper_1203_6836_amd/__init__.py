@@ -104,6 +104,9 @@ _SIGS = {
     "sp2_autotune": (_I, [_P, _I, _I, _I, ctypes.POINTER(TuneResult)]),
     "sp2_int8_mfma_rate": (_I, [_P, ctypes.POINTER(_D)]),
     "sp2_band_energy": (_I, [_P, _I, _P, _P, ctypes.POINTER(_D)]),
+    "sp2_density_matrix_nonorth": (_I, [_P, _I, _P, _P, _I, ctypes.POINTER(Sp2Options), _P,
+                                        ctypes.POINTER(Sp2Stats), ctypes.POINTER(_I)]),
+    "sp2_mulliken_overlap": (_I, [_P, _I, _P, _P, ctypes.c_double, _P]),
     "tb_hamiltonian": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P]),
     "tb_forces": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P, _P,
                        ctypes.POINTER(_D)]),
@@ -241,6 +244,30 @@ class Context:
                                       ctypes.byref(opts) if opts is not None else None,
                                       _ptr(D), ctypes.byref(stats))
         return st, stats.to_dict()
+
+    def sp2_density_matrix_nonorth(self, H, S, n_occ: int, opts: Sp2Options | None = None, D_out=None):
+        """rho = Z theta(mu0 I - Z^T H Z) Z^T with Z^T S Z = I; returns (rho, stats, factor steps)."""
+        import torch
+        N = H.shape[0]
+        if H.shape != (N, N) or S.shape != (N, N):
+            raise ValueError("H and S must be N x N")
+        if D_out is None:
+            D_out = torch.empty_like(H)
+        stats = Sp2Stats()
+        its = _I(0)
+        st = lib().sp2_density_matrix_nonorth(self._h, N, _ptr(H), _ptr(S), int(n_occ),
+                                              ctypes.byref(opts) if opts is not None else None,
+                                              _ptr(D_out), ctypes.byref(stats), ctypes.byref(its))
+        self._check(st, "sp2_density_matrix_nonorth")
+        return D_out, stats.to_dict(), its.value
+
+    def sp2_mulliken_overlap(self, D, S, n_atoms: int, z_val: float = 4.0, q_out=None):
+        import torch
+        if q_out is None:
+            q_out = torch.empty(n_atoms, dtype=torch.float64, device=D.device)
+        self._check(lib().sp2_mulliken_overlap(self._h, int(n_atoms), _ptr(D), _ptr(S), float(z_val),
+                                               _ptr(q_out)), "sp2_mulliken_overlap")
+        return q_out
 
     def sp2_int8_mfma_rate(self) -> float:
         """Sustained rate (ops/s) of v_mfma_i32_32x32x32_i8 on this device with no

@@ -12,7 +12,10 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "../../include/sp2qmd.h"
+#include "nonorth_internal.h"
 #include "sp2_internal.h"
 #include "split_internal.h"
 #include "tb_internal.h"
@@ -54,6 +57,11 @@ struct sp2_ctx {
     size_t envcap = 0;
     int* tz = nullptr;         // per X buffer and upper tile: known all zero (thresholded int8)
     size_t tzcap = 0;
+    // non-orthogonal solves: rocBLAS handle (created on first use) and four
+    // N x N buffers (Z, Y / H_perp, T / D_perp, W) plus reduction slots
+    rocblas_handle blas = nullptr;
+    double* nobuf = nullptr;
+    size_t nocap = 0;
     double* f64tail = nullptr; // chunk accumulators of split last-wave FP64 tiles
     size_t f64tailcap = 0;
     // qmd_evaluate scratch: H[n], D, zero charges, forces
@@ -174,7 +182,8 @@ void sp2_ctx_destroy(sp2_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->chk, c->V, c->eatom, c->qtmp, c->env, c->tz,
-                   c->eH, c->eD, c->ezero, c->eF, c->f64tail};
+                   c->eH, c->eD, c->ezero, c->eF, c->f64tail, c->nobuf};
+    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     for (void* p : dev)
         if (p) (void)hipFree(p);
     split_free(c->split);
@@ -535,6 +544,109 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
     c->tuned[std::make_tuple(ld, precision, int8x ? slices : 0)] = best;
     r.tile_group = best;
     if (out) *out = r;
+    return SP2_OK;
+}
+
+// ------------------------------------------------ non-orthogonal formulation
+// Row-major C = alpha A B + beta C for N x N matrices: a row-major matrix read
+// as column-major is its transpose, so this is the column-major product
+// C^T = alpha B^T A^T + beta C^T.
+static sp2_status gemm_rm(sp2_ctx* c, int N, const double* A, const double* B, double* C, double alpha = 1.0,
+                          double beta = 0.0) {
+    const rocblas_status r = rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, N, N, N, &alpha,
+                                           B, N, A, N, &beta, C, N);
+    if (r != rocblas_status_success)
+        return fail(c, SP2_EDEVICE, std::string("rocblas_dgemm failed: ") + rocblas_status_to_string(r));
+    return SP2_OK;
+}
+
+constexpr int kNsMaxIter = 40;
+
+extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double* H, const double* S, int n_occ,
+                                                  const sp2_options* opt, double* D_out, sp2_stats* stats,
+                                                  int* factor_iterations) {
+    if (!c) return SP2_EINVAL;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (factor_iterations) *factor_iterations = 0;
+    if (N < 1 || N > 65536 || !H || !S || !D_out) return fail(c, SP2_EINVAL, "bad non-orthogonal solve arguments");
+    if (n_occ <= 0 || n_occ >= N) return fail(c, SP2_EINVAL, "need 0 < n_occ < N");
+    sp2_options o;
+    if (opt) o = *opt;
+    else sp2_options_default(&o);
+    sp2_status s = check_options(c, o, N);
+    if (s != SP2_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!c->blas) {
+        if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+            c->blas = nullptr;
+            return fail(c, SP2_EDEVICE, "rocblas_create_handle failed");
+        }
+    }
+    if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
+        return fail(c, SP2_EDEVICE, "rocblas_set_stream failed");
+    const size_t n2 = (size_t)N * N;
+    size_t nb = c->nocap;
+    if ((s = grow(c, (void**)&c->nobuf, &nb, (4 * n2 + kNsBlocks + 64) * sizeof(double))) != SP2_OK) return s;
+    c->nocap = nb;
+    double* Zm = c->nobuf;
+    double* Y = Zm + n2;
+    double* T = Y + n2;
+    double* W = T + n2;
+    double* part = W + n2;
+    double* res = part + kNsBlocks;
+    unsigned long long* mx = reinterpret_cast<unsigned long long*>(res + 8);
+    hipStream_t st = c->stream;
+    // Loewdin factor Z = S^(-1/2) (Eq. Congr) by the coupled Newton-Schulz iteration
+    HIPCHK(c, launch_zero_word(mx, st));
+    HIPCHK(c, launch_row_abs_max(S, N, mx, st));
+    HIPCHK(c, launch_ns_init(S, N, mx, Y, Zm, st));
+    const double tol = 1e-11 * N;   // ||Z_k Y_k - I||_F: about 1e-11 per element
+    double prev = 1e300;
+    int it = 0;
+    bool converged = false;
+    for (; it < kNsMaxIter; ++it) {
+        if ((s = gemm_rm(c, N, Zm, Y, T)) != SP2_OK) return s;          // T = Z_k Y_k
+        HIPCHK(c, launch_ns_step(T, N, part, st));                      // residual; T = (3 I - T) / 2
+        HIPCHK(c, launch_sum_sqrt(part, kNsBlocks, res, st));
+        HIPCHK(c, hipMemcpyAsync(c->scal_host, res, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        const double r = c->scal_host[0];
+        if (!(r == r)) return fail(c, SP2_EINVAL, "overlap matrix gives a non-finite inverse factor");
+        if (r < tol || (it >= 4 && r >= prev && r < 1e-6 * N)) {   // converged, or at its rounding floor
+            converged = true;
+            break;
+        }
+        prev = r;
+        if ((s = gemm_rm(c, N, Y, T, W)) != SP2_OK) return s;           // Y_{k+1} = Y_k T_k
+        std::swap(Y, W);
+        if ((s = gemm_rm(c, N, T, Zm, W)) != SP2_OK) return s;          // Z_{k+1} = T_k Z_k
+        std::swap(Zm, W);
+    }
+    if (factor_iterations) *factor_iterations = it + 1;
+    if (!converged) return fail(c, SP2_ENOCONV, "inverse factor of S did not converge (S not positive definite?)");
+    HIPCHK(c, launch_scale_inv_sqrt(Zm, N, mx, st));
+    // H_perp = Z^T H Z (Z symmetric), made exactly symmetric
+    double* Hp = Y;
+    double* Dp = T;
+    if ((s = gemm_rm(c, N, Zm, H, W)) != SP2_OK) return s;
+    if ((s = gemm_rm(c, N, W, Zm, Hp)) != SP2_OK) return s;
+    HIPCHK(c, launch_symmetrize(Hp, N, st));
+    // rho_perp = theta(mu0 I - H_perp) by SP2, then rho = Z rho_perp Z^T
+    if ((s = sp2_solve(c, N, Hp, n_occ, o, Dp, stats)) != SP2_OK) return s;
+    if ((s = gemm_rm(c, N, Zm, Dp, W)) != SP2_OK) return s;
+    if ((s = gemm_rm(c, N, W, Zm, D_out)) != SP2_OK) return s;
+    HIPCHK(c, launch_symmetrize(D_out, N, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return SP2_OK;
+}
+
+extern "C" sp2_status sp2_mulliken_overlap(sp2_ctx* c, int n_atoms, const double* D, const double* S, double z_val,
+                                           double* q_out) {
+    if (!c) return SP2_EINVAL;
+    if (n_atoms < 1 || n_atoms > 16384 || !D || !S || !q_out)
+        return fail(c, SP2_EINVAL, "bad mulliken arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_mulliken_overlap(D, S, n_atoms, z_val, q_out, c->stream));
     return SP2_OK;
 }
 

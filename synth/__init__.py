@@ -57,6 +57,10 @@ class TBModel:
     pair_rho: float = 0.3
     mass: float = 12.0         # amu
     z_val: int = 4             # valence electrons per neutral atom
+    # overlap of the non-orthogonal variant: s(r) = overlap_s0 exp(-(r - r0)/overlap_lam)
+    # with the hopping's tail (0: orthogonal basis, S = I)
+    overlap_s0: float = 0.0
+    overlap_lam: float = 0.5
 
     def with_(self, **kw) -> "TBModel":
         return dataclasses.replace(self, **kw)
@@ -202,6 +206,12 @@ GAPPED_SPACING = 2.0
 # repulsion whose amplitude gives the self-consistent unjittered 4 x 4 x 4
 # lattice at 2.0 A zero virial (oracle/calibrate_pair.py).
 GAPPED_MD_MODEL = GAPPED_MODEL.with_(r_tail=3.5, pair_a=3.373945, pair_rho=0.15)
+
+
+# Non-orthogonal variant: the static model with overlap integrals of
+# magnitude 0.05 at 1.5 A (dimensionless), decaying like the hopping; S stays
+# well conditioned (smallest eigenvalue about 0.72 on these lattices).
+NONORTH_MODEL = STATIC_MODEL.with_(overlap_s0=0.05)
 
 
 def gapped_workload(n_layers: int, seed: int = 3) -> Workload:

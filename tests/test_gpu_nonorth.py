@@ -1,0 +1,129 @@
+"""Non-orthogonal formulation on the GPU (Loewdin factor by Newton-Schulz over
+rocBLAS GEMMs, SP2 of Z^T H Z, rho = Z rho_perp Z^T, Mulliken charges with S)
+against the oracle."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import nonorth, tb as otb
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_1203_6836_amd as p
+    c = p.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def system(dims, seed, model=None):
+    m = model or synth.NONORTH_MODEL
+    w = synth.small_workload(dims, seed)
+    pos = w.positions()
+    return w, otb.hamiltonian(pos, None, m), nonorth.overlap(pos, m)
+
+
+@pytest.mark.parametrize("dims,seed", [((3, 3, 3), 4), ((4, 4, 8), 5)])
+def test_fp64_nonorth_matches_oracle(ctx, dims, seed):
+    import paper_1203_6836_amd as p
+    w, H, S = system(dims, seed)
+    say(f"case nonorth fp64 N={w.n_orb}")
+    rho_ref, _, _, r = nonorth.density_matrix(H, S, w.n_occ)
+    Sd = to_dev(S)
+    D, st, its = ctx.sp2_density_matrix_nonorth(to_dev(H), Sd, w.n_occ, p.options("fp64"))
+    q = ctx.sp2_mulliken_overlap(D, Sd, w.n_atoms).cpu().numpy()
+    D = D.cpu().numpy()
+    err = np.linalg.norm(D - rho_ref) / np.sqrt(w.n_orb)
+    dq = float(np.abs(q - nonorth.mulliken(rho_ref, S)).max())
+    say(f"  factor steps {its}, SP2 iterations gpu={st['iterations']} oracle={r.iterations}, "
+        f"err/sqrtN {err:.2e}, max|dq| {dq:.2e}, Tr[DS] - n_occ {np.trace(D @ S) - w.n_occ:+.1e}")
+    assert st["iterations"] == r.iterations
+    assert err <= 1e-9 and dq <= 1e-9
+    assert abs(np.trace(D @ S) - w.n_occ) < 1e-8
+
+
+def test_int8x_nonorth_matches_oracle(ctx):
+    import paper_1203_6836_amd as p
+    w, H, S = system((8, 8, 8), 2)
+    say(f"case nonorth int8x N={w.n_orb}")
+    rho_ref, _, _, _ = nonorth.density_matrix(H, S, w.n_occ)
+    Sd = to_dev(S)
+    D, st, its = ctx.sp2_density_matrix_nonorth(to_dev(H), Sd, w.n_occ, p.options("int8x"))
+    q = ctx.sp2_mulliken_overlap(D, Sd, w.n_atoms).cpu().numpy()
+    D = D.cpu().numpy()
+    err = np.linalg.norm(D - rho_ref) / np.sqrt(w.n_orb)
+    dq = float(np.abs(q - nonorth.mulliken(rho_ref, S)).max())
+    say(f"  factor steps {its}, SP2 iterations {st['iterations']}, err/sqrtN {err:.2e}, max|dq| {dq:.2e}")
+    assert err <= 1e-6 and dq <= 1e-6
+
+
+def test_identity_overlap_is_the_orthogonal_solve(ctx):
+    """S = I: the factor is I after one step and the result is bitwise the
+    orthogonal solve's."""
+    import torch
+    import paper_1203_6836_amd as p
+    w, H, _ = system((4, 4, 4), 0)
+    say("case nonorth with S = I vs orthogonal solve")
+    Hd = to_dev(H)
+    I = torch.eye(w.n_orb, dtype=torch.float64, device="cuda")
+    D0, s0 = ctx.sp2_density_matrix(Hd, w.n_occ, p.options("fp64"))
+    D1, s1, its = ctx.sp2_density_matrix_nonorth(Hd, I, w.n_occ, p.options("fp64"))
+    assert its == 1 and s0["iterations"] == s1["iterations"]
+    assert torch.equal(D0, D1)
+    q0 = ctx.sp2_mulliken(D0, w.n_atoms)
+    q1 = ctx.sp2_mulliken_overlap(D1, I, w.n_atoms)
+    assert float((q0 - q1).abs().max()) < 1e-13
+
+
+def test_nonorth_rejects_indefinite_overlap(ctx):
+    import paper_1203_6836_amd as p
+    w, H, S = system((3, 3, 3), 4)
+    S = S.copy()
+    S[0, 0] = -1.0                      # not positive definite
+    st, _ = ctx.sp2_density_matrix_status(to_dev(H), w.n_occ)  # context still usable afterwards
+    assert st == p.SP2_OK
+    with pytest.raises(p.Sp2Error) as ei:
+        ctx.sp2_density_matrix_nonorth(to_dev(H), to_dev(S), w.n_occ, p.options("fp64"))
+    assert ei.value.status in (p.SP2_ENOCONV, p.SP2_EINVAL)
+
+
+def test_nonorth_full_size_timing(ctx):
+    """N = 8192 (the benchmark's lattice with the overlap model), int8: the
+    transforms' cost beside the SP2 solve."""
+    import torch
+    import paper_1203_6836_amd as p
+    w = synth.MIXED
+    pos = w.positions()
+    m = synth.NONORTH_MODEL
+    H = to_dev(otb.hamiltonian(pos, None, m))
+    S = to_dev(nonorth.overlap(pos, m))
+    say(f"case nonorth int8x N={w.n_orb} timing")
+    ctx.sp2_density_matrix_nonorth(H, S, w.n_occ, p.options("int8x"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    D, st, its = ctx.sp2_density_matrix_nonorth(H, S, w.n_occ, p.options("int8x"))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    SD = S @ D
+    tr = float(torch.trace(SD)) - w.n_occ
+    idem = float(torch.linalg.norm(D @ SD - D)) / w.n_orb ** 0.5
+    say(f"  {ms:.0f} ms total, SP2 {st['ms']:.0f} ms ({st['iterations']} products), factor steps {its}; "
+        f"Tr[DS] - n_occ {tr:+.1e}, ||D S D - D||/sqrtN {idem:.1e}")
+    assert abs(tr) < 1e-5 and idem < 1e-5

@@ -1,0 +1,66 @@
+"""Pins of the non-orthogonal oracle against the generalized eigenproblem and its invariants."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import synth
+from oracle import nonorth, sp2, tb
+
+
+@pytest.fixture(scope="module")
+def system():
+    w = synth.small_workload((3, 3, 3), 4)          # 27 atoms, N = 108
+    pos = w.positions()
+    m = synth.NONORTH_MODEL
+    H = tb.hamiltonian(pos, None, m)
+    S = nonorth.overlap(pos, m)
+    return w, pos, m, H, S
+
+
+def test_overlap_is_symmetric_positive_definite(system):
+    _, _, _, _, S = system
+    assert np.array_equal(S, S.T)
+    assert np.allclose(np.diag(S), 1.0)
+    assert np.linalg.eigvalsh(S).min() > 0.3
+    assert np.abs(S - np.eye(len(S))).max() > 0.01      # not the identity
+
+
+def test_loewdin_factor_is_a_congruence_factor(system):
+    _, _, _, _, S = system
+    Z = nonorth.loewdin_factor(S)
+    assert np.allclose(Z.T @ S @ Z, np.eye(len(S)), atol=1e-12)
+    assert np.allclose(Z, Z.T, atol=1e-14)
+
+
+def test_density_matrix_equals_generalized_eigenproblem(system):
+    """Definition: rho = C_occ C_occ^T with H C = S C E, C^T S C = I."""
+    w, _, _, H, S = system
+    rho, rho_p, Z, r = nonorth.density_matrix(H, S, w.n_occ)
+    E, C = scipy.linalg.eigh(H, S)
+    assert E[w.n_occ] - E[w.n_occ - 1] > 1e-4
+    ref = C[:, :w.n_occ] @ C[:, :w.n_occ].T
+    assert r.status == "converged"
+    np.testing.assert_allclose(rho, ref, atol=1e-9)
+    # invariants: idempotent in the S metric, S-trace = n_occ, neutral charges sum to 0
+    np.testing.assert_allclose(rho @ S @ rho, rho, atol=1e-9)
+    assert np.trace(rho @ S) == pytest.approx(w.n_occ, abs=1e-9)
+    assert nonorth.mulliken(rho, S).sum() == pytest.approx(0.0, abs=1e-9)
+
+
+def test_orthogonal_limit_is_the_orthogonal_path(system):
+    w, pos, m, H, _ = system
+    S0 = nonorth.overlap(pos, m.with_(overlap_s0=0.0))
+    assert np.array_equal(S0, np.eye(len(S0)))
+    rho, _, _, _ = nonorth.density_matrix(H, S0, w.n_occ)
+    assert np.array_equal(rho, sp2.sp2(H, w.n_occ).D)
+
+
+def test_mulliken_brute_force(system):
+    w, _, _, H, S = system
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal(S.shape)
+    rho = A + A.T
+    q = nonorth.mulliken(rho, S, z_val=4)
+    for i in range(w.n_atoms):
+        pop = sum(rho[a, b] * S[b, a] for a in range(4 * i, 4 * i + 4) for b in range(len(S)))
+        assert q[i] == pytest.approx(2.0 * pop - 4.0, abs=1e-10)
