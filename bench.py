@@ -297,6 +297,38 @@ def thresholded_md(ctx, layers=(128, 256), steps=20):
     return out
 
 
+def nonorthogonal(ctx):
+    """The non-orthogonal solve on the benchmark's lattice with the overlap
+    model (N = 8192, int8 SP2 of H_perp): total time, the SP2 solve's share,
+    Newton-Schulz steps of the Loewdin factor, and the S-metric invariants."""
+    import torch
+
+    import paper_1203_6836_amd as p
+    import synth
+
+    w = synth.MIXED
+    m = synth.NONORTH_MODEL
+    xyz = torch.from_numpy(w.positions()).cuda()
+    log("non-orthogonal solve: N=8192")
+    H = ctx.tb_hamiltonian(m, xyz)
+    S = ctx.tb_overlap(m, xyz)
+    D = torch.empty_like(H)
+    opt = p.options("int8x")
+    ctx.sp2_density_matrix_nonorth(H, S, w.n_occ, opt, D_out=D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st, its = ctx.sp2_density_matrix_nonorth(H, S, w.n_occ, opt, D_out=D)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    SD = S @ D
+    out = {"n": w.n_orb, "ms_per_solve": round(ms, 1), "sp2_ms": round(st["ms"], 1),
+           "sp2_products": st["iterations"], "factor_steps": its,
+           "trace_DS_minus_nocc": float(torch.trace(SD)) - w.n_occ,
+           "idempotency_DSD_per_sqrtN": float(torch.linalg.norm(D @ SD - D)) / w.n_orb ** 0.5}
+    log(f"  {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -472,6 +504,7 @@ def main():
         del D64
         torch.cuda.empty_cache()
         out["thresholded_scaling"] = thresholded_scaling(ctx)
+        out["nonorthogonal"] = nonorthogonal(ctx)
     if not args.no_cpu:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(H.cpu().numpy(), nocc)

@@ -243,6 +243,16 @@ typedef struct {
 sp2_status tb_hamiltonian(sp2_ctx *ctx, const tb_params *p, int n_atoms,
                           const double *xyz, const double *n_aux, double *H_out);
 
+/* Overlap matrix of the non-orthogonal variant of the model (the paper's S of
+ * the Non-orthogonal formulation subsection; its parameters are not given, so
+ * the synthetic form is: identity blocks on the diagonal, and per pair within
+ * r_cut the Slater-Koster block of overlap integrals of magnitude
+ * s(r) = s0 exp(-(r - r0)/lam_s) with the hopping's tail from r_tail, with
+ * the sign pattern opposite to the hopping's).  p supplies r0, r_tail, r_cut;
+ * xyz: 3 n_atoms device (A); S_out: (4 n_atoms)^2 row-major device. */
+sp2_status tb_overlap(sp2_ctx *ctx, const tb_params *p, double s0, double lam_s, int n_atoms,
+                      const double *xyz, double *S_out);
+
 /* Forces at constant auxiliary charges n (Eq. EL_Orth_a with Eq. EL_Orth_c,
  * on-site term read with rho - rho0):
  *   F_k = -2 Tr[D dh/dR_k] - sum_ij (q_i n_j - n_i n_j / 2) dgamma_ij/dR_k

@@ -107,6 +107,7 @@ _SIGS = {
     "sp2_density_matrix_nonorth": (_I, [_P, _I, _P, _P, _I, ctypes.POINTER(Sp2Options), _P,
                                         ctypes.POINTER(Sp2Stats), ctypes.POINTER(_I)]),
     "sp2_mulliken_overlap": (_I, [_P, _I, _P, _P, ctypes.c_double, _P]),
+    "tb_overlap": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P]),
     "tb_hamiltonian": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P]),
     "tb_forces": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P, _P,
                        ctypes.POINTER(_D)]),
@@ -260,6 +261,17 @@ class Context:
                                               _ptr(D_out), ctypes.byref(stats), ctypes.byref(its))
         self._check(st, "sp2_density_matrix_nonorth")
         return D_out, stats.to_dict(), its.value
+
+    def tb_overlap(self, model, xyz, S_out=None):
+        """S of the non-orthogonal variant (model.overlap_s0, model.overlap_lam)."""
+        import torch
+        nat = xyz.shape[0]
+        if S_out is None:
+            S_out = torch.empty((4 * nat, 4 * nat), dtype=torch.float64, device=xyz.device)
+        p = tb_params(model)
+        self._check(lib().tb_overlap(self._h, ctypes.byref(p), float(model.overlap_s0), float(model.overlap_lam),
+                                     nat, _ptr(xyz), _ptr(S_out)), "tb_overlap")
+        return S_out
 
     def sp2_mulliken_overlap(self, D, S, n_atoms: int, z_val: float = 4.0, q_out=None):
         import torch

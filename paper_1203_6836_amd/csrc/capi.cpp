@@ -759,6 +759,16 @@ extern "C" sp2_status tb_hamiltonian(sp2_ctx* c, const tb_params* p, int n_atoms
     return SP2_OK;
 }
 
+extern "C" sp2_status tb_overlap(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
+                                 const double* xyz, double* S_out) {
+    if (!c) return SP2_EINVAL;
+    if (!params_ok(p) || !(s0 >= 0.0) || !(lam_s > 0.0)) return fail(c, SP2_EINVAL, "bad overlap parameters");
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !S_out) return fail(c, SP2_EINVAL, "bad tb_overlap arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_overlap(xyz, n_atoms, make_radial(s0, p->r0, lam_s, p->r_tail, p->r_cut), S_out, c->stream));
+    return SP2_OK;
+}
+
 // Forces and energy; V must already hold gamma n (computed here).
 static sp2_status forces_impl(sp2_ctx* c, const tb_params* p, int nat, const double* xyz, const double* D,
                               const double* q, const double* n, double* F, double* U_dev) {

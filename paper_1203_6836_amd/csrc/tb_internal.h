@@ -26,6 +26,8 @@ hipError_t launch_potential(const double* xyz, const double* n, int nat, double 
                             hipStream_t s);
 hipError_t launch_hamiltonian(const double* xyz, int nat, const TBArgs& a, const double* V, double* H,
                               hipStream_t s);
+// S of the non-orthogonal variant for overlap radial function ov.
+hipError_t launch_overlap(const double* xyz, int nat, const Radial& ov, double* S, hipStream_t s);
 hipError_t launch_forces(const double* xyz, int nat, const TBArgs& a, const double* D, const double* q,
                          const double* n, const double* V, double* F, double* e_atom, double* e_out,
                          hipStream_t s);

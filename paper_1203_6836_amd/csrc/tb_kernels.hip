@@ -100,6 +100,42 @@ __global__ __launch_bounds__(256) void k_hamiltonian(const double* __restrict__ 
     }
 }
 
+// Overlap of the non-orthogonal variant, laid out like H: identity blocks on
+// the diagonal, and for each pair the Slater-Koster block of the overlap
+// integrals s(r) with the sign pattern opposite to the hopping's (-sk_block).
+__global__ __launch_bounds__(256) void k_overlap(const double* __restrict__ xyz, int nat, Radial ov,
+                                                 double* __restrict__ S) {
+    const int i = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nat) return;
+    const size_t N = 4 * (size_t)nat;
+    double B[4][4];
+    if (i == j) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) B[p][q] = p == q ? 1.0 : 0.0;
+    } else {
+        const double dx = xyz[3 * j] - xyz[3 * i], dy = xyz[3 * j + 1] - xyz[3 * i + 1],
+                     dz = xyz[3 * j + 2] - xyz[3 * i + 2];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double s = 0.0, ds;
+        if (r < ov.rcut) radial(ov, r, s, ds);
+        const double c[3] = {dx / r, dy / r, dz / r};
+        sk_block(c, s, B);
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) B[p][q] = -B[p][q];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        double* row = S + (4 * (size_t)i + p) * N + 4 * (size_t)j;
+        *reinterpret_cast<double2*>(row) = make_double2(B[p][0], B[p][1]);
+        *reinterpret_cast<double2*>(row + 2) = make_double2(B[p][2], B[p][3]);
+    }
+}
+
 // Forces and per-atom energy terms at constant n; one wave per atom k.
 //   F_k = 4 sum_j sum_ab D_{ka,jb} dB_kj/d(R_j - R_k)          (band)
 //       - sum_j (q_k n_j + q_j n_k - n_k n_j) k_e (R_j - R_k)/r^3 (Coulomb)
@@ -281,6 +317,10 @@ hipError_t launch_potential(const double* xyz, const double* n, int nat, double 
 hipError_t launch_hamiltonian(const double* xyz, int nat, const TBArgs& a, const double* V, double* H,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_hamiltonian, dim3((nat + 255) / 256, nat), dim3(256), 0, s, xyz, nat, a, V, H);
+    return hipGetLastError();
+}
+hipError_t launch_overlap(const double* xyz, int nat, const Radial& ov, double* S, hipStream_t s) {
+    hipLaunchKernelGGL(k_overlap, dim3((nat + 255) / 256, nat), dim3(256), 0, s, xyz, nat, ov, S);
     return hipGetLastError();
 }
 hipError_t launch_forces(const double* xyz, int nat, const TBArgs& a, const double* D, const double* q,

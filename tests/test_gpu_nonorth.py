@@ -92,6 +92,17 @@ def test_identity_overlap_is_the_orthogonal_solve(ctx):
     assert float((q0 - q1).abs().max()) < 1e-13
 
 
+@pytest.mark.parametrize("dims,seed", [((3, 3, 3), 4), ((5, 4, 3), 9)])
+def test_overlap_builder_matches_oracle(ctx, dims, seed):
+    w = synth.small_workload(dims, seed)
+    pos = w.positions()
+    say(f"case tb_overlap N={w.n_orb}")
+    S = ctx.tb_overlap(synth.NONORTH_MODEL, to_dev(pos)).cpu().numpy()
+    ref = nonorth.overlap(pos, synth.NONORTH_MODEL)
+    assert np.abs(S - ref).max() < 1e-14
+    assert np.array_equal(S, S.T)
+
+
 def test_nonorth_rejects_indefinite_overlap(ctx):
     import paper_1203_6836_amd as p
     w, H, S = system((3, 3, 3), 4)
@@ -110,11 +121,11 @@ def test_nonorth_full_size_timing(ctx):
     import torch
     import paper_1203_6836_amd as p
     w = synth.MIXED
-    pos = w.positions()
     m = synth.NONORTH_MODEL
-    H = to_dev(otb.hamiltonian(pos, None, m))
-    S = to_dev(nonorth.overlap(pos, m))
-    say(f"case nonorth int8x N={w.n_orb} timing")
+    xyz = to_dev(w.positions())
+    H = ctx.tb_hamiltonian(m, xyz)
+    S = ctx.tb_overlap(m, xyz)
+    say(f"case nonorth int8x N={w.n_orb} timing (H and S built on the GPU)")
     ctx.sp2_density_matrix_nonorth(H, S, w.n_occ, p.options("int8x"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
