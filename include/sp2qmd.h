@@ -253,6 +253,29 @@ sp2_status tb_hamiltonian(sp2_ctx *ctx, const tb_params *p, int n_atoms,
 sp2_status tb_overlap(sp2_ctx *ctx, const tb_params *p, double s0, double lam_s, int n_atoms,
                       const double *xyz, double *S_out);
 
+/* Non-orthogonal H[n] = h + (S L + L S)/2, L the diagonal holding
+ * V_i = sum_j gamma_ij n_j on the orbitals of atom i (the charge shift of the
+ * non-orthogonal SCC-TB Hamiltonian, Eq. DFTB_2 with S != I); h alone when
+ * n_aux is NULL.  S: (4 n_atoms)^2 device (from tb_overlap); n_aux: n_atoms
+ * device or NULL; H_out: (4 n_atoms)^2 device. */
+sp2_status tb_hamiltonian_nonorth(sp2_ctx *ctx, const tb_params *p, int n_atoms, const double *xyz,
+                                  const double *n_aux, const double *S, double *H_out);
+
+/* Non-orthogonal forces at constant auxiliary charges n (the role of the
+ * non-orthogonal force equation, EL_Nonorth_a, at T_e = 0): with
+ * U(R; n) = 2 Tr[D h] + sum_i q_i V_i - 1/2 n^T gamma n + E_pair and the
+ * overlap charges q (sp2_mulliken_overlap), F_k = -dU/dR_k is the orthogonal
+ * force of tb_forces with these q plus sum_ab M_ab dS_ab/dR_k, where
+ * M = 2 D H D - (V_a + V_b) D_ab (the energy-weighted density matrix of the
+ * generalized eigenproblem and the overlap inside H[n] and q).  D: the
+ * density matrix of H = H[n] (sp2_density_matrix_nonorth); S, H, D:
+ * (4 n_atoms)^2 device; q, n_aux: n_atoms device; s0, lam_s: the overlap
+ * parameters of tb_overlap; F_out: 3 n_atoms device; U_host: host or NULL.
+ * Uses two N^2 scratch buffers of the context (two rocBLAS GEMMs form D H D). */
+sp2_status tb_forces_nonorth(sp2_ctx *ctx, const tb_params *p, double s0, double lam_s, int n_atoms,
+                             const double *xyz, const double *D, const double *S, const double *H,
+                             const double *q, const double *n_aux, double *F_out, double *U_host);
+
 /* Forces at constant auxiliary charges n (Eq. EL_Orth_a with Eq. EL_Orth_c,
  * on-site term read with rho - rho0):
  *   F_k = -2 Tr[D dh/dR_k] - sum_ij (q_i n_j - n_i n_j / 2) dgamma_ij/dR_k

@@ -20,12 +20,30 @@ Readings (the paper leaves these open):
   2 sum (rho S_R) (the charge-derivative equation), which is the derivative
   of these; its printed charge formula, with the diagonal of rho_perp, would
   give Loewdin charges for Z = S^(-1/2).
+
+Energy and forces at constant auxiliary charges n, written for the overlap
+the way the orthogonal oracle writes them (observables module):
+* H[n] = h + (S L + L S) / 2, L the diagonal of V_i = (gamma n)_i on the
+  orbitals of atom i (the charge shift of a non-orthogonal basis);
+* U(R; n) = 2 Tr[rho h] + sum_i q_i V_i - 1/2 n^T gamma n + E_pair, q the
+  Mulliken charges above (equal to 2 Tr[rho H] - z sum_i V_i - 1/2 n^T gamma n
+  + E_pair);
+* F_k = -dU/dR_k.  rho is the generalized projector of H[n] (H c = e S c),
+  so the generalized Hellmann-Feynman theorem removes d rho and adds the
+  energy-weighted term -2 Tr[W dS/dR_k], W = rho H rho; the S inside H[n]
+  and inside q add (V_a + V_b) rho_ab dS_ab/dR_k.  Result: the orthogonal
+  force with these charges, plus sum_ab M_ab dS_ab/dR_k with
+  M = 2 W - (V_a + V_b) rho_ab (a, b orbital indices; V of their atoms).
+  This is the role of the Pulay term Tr[(S^-1 H rho + rho H S^-1) S_R] and
+  of the charge-derivative term of the paper's non-orthogonal force equation
+  (at T_e = 0 and idempotent rho, W = rho H rho).  Pinned by central finite
+  differences of U with rho recomputed at each displaced geometry.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import sp2, tb
+from . import observables, sp2, tb
 
 
 def overlap(pos, m):
@@ -65,3 +83,50 @@ def mulliken(rho, S, z_val=4):
     """Net Mulliken charges 2 sum_{alpha in i} (rho S)_{alpha alpha} - z_val."""
     pop = np.einsum("ab,ba->a", rho, S)
     return 2.0 * pop.reshape(-1, 4).sum(axis=1) - z_val
+
+
+def potential(pos, n, m):
+    """V_i = (gamma n)_i repeated on the four orbitals of each atom."""
+    return np.repeat(tb.onsite_potential(pos, np.asarray(n, dtype=np.float64), m), 4)
+
+
+def hamiltonian(pos, n, m, S=None):
+    """H[n] = h + (S L + L S) / 2 (h alone for n = None)."""
+    h = tb.hamiltonian0(pos, m)
+    if n is None:
+        return h
+    S = overlap(pos, m) if S is None else S
+    v = potential(pos, n, m)
+    return h + 0.5 * S * (v[:, None] + v[None, :])
+
+
+def potential_energy(pos, n, rho, m, S=None):
+    S = overlap(pos, m) if S is None else S
+    q = mulliken(rho, S, m.z_val)
+    g = tb.gamma_matrix(pos, m)
+    h = tb.hamiltonian0(pos, m)
+    return 2.0 * float(np.sum(rho * h)) + observables.coulomb_energy(q, n, g) + tb.pair_energy(pos, m)
+
+
+def overlap_block_grad(dv, m):
+    """d S_ij / d(R_j - R_i) of one pair block, shape (3, 4, 4): the gradient of
+    -sk_block with the overlap's radial function."""
+    ms = m.with_(t0=m.overlap_s0, lam=m.overlap_lam)
+    return -tb.sk_block_grad(dv, ms)
+
+
+def forces(pos, n, rho, m, S=None):
+    """F_k = -dU/dR_k at constant n; shape (n_atoms, 3)."""
+    S = overlap(pos, m) if S is None else S
+    q = mulliken(rho, S, m.z_val)
+    F = observables.forces(pos, n, rho, m, q=q)
+    H = hamiltonian(pos, n, m, S)
+    v = potential(pos, n, m)
+    M = 2.0 * (rho @ H @ rho) - (v[:, None] + v[None, :]) * rho
+    ii, jj, d, r = tb.neighbour_pairs(pos, m.r_cut)
+    for a, b, dv in zip(ii, jj, d):
+        G = overlap_block_grad(dv, m)
+        g = 2.0 * np.einsum("xij,ij->x", G, M[4 * a:4 * a + 4, 4 * b:4 * b + 4])
+        F[b] += g
+        F[a] -= g
+    return F

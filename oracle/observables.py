@@ -54,11 +54,13 @@ def potential_energy(pos, n, D, m):
     return 2.0 * float(np.sum(D * h)) + coulomb_energy(q, n, g) + tb.pair_energy(pos, m)
 
 
-def forces(pos, n, D, m):
-    """F_k = -dU/dR_k at constant n (see module docstring); shape (n_atoms, 3)."""
+def forces(pos, n, D, m, q=None):
+    """F_k = -dU/dR_k at constant n (see module docstring); shape (n_atoms, 3).
+    q: the charges of D (default: the orthogonal Mulliken charges)."""
     nat = len(pos)
     F = np.zeros((nat, 3))
-    q = mulliken(D, m.z_val)
+    if q is None:
+        q = mulliken(D, m.z_val)
     # band term: -2 Tr[rho dh/dR_k]; each pair (i, j) appears as the block
     # h_ij and its transpose h_ji, hence the factor 4 with symmetric rho.
     ii, jj, d, r = tb.neighbour_pairs(pos, m.r_cut)

@@ -108,6 +108,9 @@ _SIGS = {
                                         ctypes.POINTER(Sp2Stats), ctypes.POINTER(_I)]),
     "sp2_mulliken_overlap": (_I, [_P, _I, _P, _P, ctypes.c_double, _P]),
     "tb_overlap": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P]),
+    "tb_hamiltonian_nonorth": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P]),
+    "tb_forces_nonorth": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P, _P,
+                               _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "tb_hamiltonian": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P]),
     "tb_forces": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P, _P,
                        ctypes.POINTER(_D)]),
@@ -272,6 +275,32 @@ class Context:
         self._check(lib().tb_overlap(self._h, ctypes.byref(p), float(model.overlap_s0), float(model.overlap_lam),
                                      nat, _ptr(xyz), _ptr(S_out)), "tb_overlap")
         return S_out
+
+    def tb_hamiltonian_nonorth(self, model, xyz, S, n_aux=None, H_out=None):
+        """H[n] = h + (S L + L S)/2 of the non-orthogonal variant (h for n_aux None)."""
+        import torch
+        nat = xyz.shape[0]
+        if H_out is None:
+            H_out = torch.empty((4 * nat, 4 * nat), dtype=torch.float64, device=xyz.device)
+        p = tb_params(model)
+        self._check(lib().tb_hamiltonian_nonorth(self._h, ctypes.byref(p), nat, _ptr(xyz),
+                                                 _ptr(n_aux) if n_aux is not None else None, _ptr(S),
+                                                 _ptr(H_out)), "tb_hamiltonian_nonorth")
+        return H_out
+
+    def tb_forces_nonorth(self, model, xyz, D, S, H, q, n_aux, F_out=None):
+        """(F, U): forces at constant n and the potential energy, non-orthogonal basis."""
+        import torch
+        nat = xyz.shape[0]
+        if F_out is None:
+            F_out = torch.empty((nat, 3), dtype=torch.float64, device=xyz.device)
+        p = tb_params(model)
+        U = ctypes.c_double()
+        self._check(lib().tb_forces_nonorth(self._h, ctypes.byref(p), float(model.overlap_s0),
+                                            float(model.overlap_lam), nat, _ptr(xyz), _ptr(D), _ptr(S), _ptr(H),
+                                            _ptr(q), _ptr(n_aux), _ptr(F_out), ctypes.byref(U)),
+                    "tb_forces_nonorth")
+        return F_out, U.value
 
     def sp2_mulliken_overlap(self, D, S, n_atoms: int, z_val: float = 4.0, q_out=None):
         import torch

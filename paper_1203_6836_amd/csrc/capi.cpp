@@ -562,6 +562,18 @@ static sp2_status gemm_rm(sp2_ctx* c, int N, const double* A, const double* B, d
 
 constexpr int kNsMaxIter = 40;
 
+static sp2_status ensure_blas(sp2_ctx* c) {
+    if (!c->blas) {
+        if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+            c->blas = nullptr;
+            return fail(c, SP2_EDEVICE, "rocblas_create_handle failed");
+        }
+    }
+    if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
+        return fail(c, SP2_EDEVICE, "rocblas_set_stream failed");
+    return SP2_OK;
+}
+
 extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double* H, const double* S, int n_occ,
                                                   const sp2_options* opt, double* D_out, sp2_stats* stats,
                                                   int* factor_iterations) {
@@ -576,14 +588,7 @@ extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double
     sp2_status s = check_options(c, o, N);
     if (s != SP2_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
-    if (!c->blas) {
-        if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
-            c->blas = nullptr;
-            return fail(c, SP2_EDEVICE, "rocblas_create_handle failed");
-        }
-    }
-    if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
-        return fail(c, SP2_EDEVICE, "rocblas_set_stream failed");
+    if ((s = ensure_blas(c)) != SP2_OK) return s;
     const size_t n2 = (size_t)N * N;
     size_t nb = c->nocap;
     if ((s = grow(c, (void**)&c->nobuf, &nb, (4 * n2 + kNsBlocks + 64) * sizeof(double))) != SP2_OK) return s;
@@ -769,12 +774,68 @@ extern "C" sp2_status tb_overlap(sp2_ctx* c, const tb_params* p, double s0, doub
     return SP2_OK;
 }
 
+// Non-orthogonal H[n] = h + (S L + L S)/2, L = V_i = (gamma n)_i on the orbitals
+// of atom i (h alone when n_aux is NULL).
+extern "C" sp2_status tb_hamiltonian_nonorth(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz,
+                                             const double* n_aux, const double* S, double* H_out) {
+    if (!c) return SP2_EINVAL;
+    if (!params_ok(p)) return fail(c, SP2_EINVAL, "bad tb_params");
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !S || !H_out)
+        return fail(c, SP2_EINVAL, "bad tb_hamiltonian_nonorth arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    sp2_status s = ensure_atoms(c, n_atoms);
+    if (s != SP2_OK) return s;
+    HIPCHK(c, launch_hamiltonian(xyz, n_atoms, make_tbargs(p), nullptr, H_out, c->stream));
+    if (n_aux) {
+        HIPCHK(c, launch_potential(xyz, n_aux, n_atoms, p->hubbard_u, p->coulomb_k, c->V, c->stream));
+        HIPCHK(c, launch_overlap_shift(H_out, S, c->V, n_atoms, c->stream));
+    }
+    return SP2_OK;
+}
+
 // Forces and energy; V must already hold gamma n (computed here).
 static sp2_status forces_impl(sp2_ctx* c, const tb_params* p, int nat, const double* xyz, const double* D,
                               const double* q, const double* n, double* F, double* U_dev) {
     const TBArgs a = make_tbargs(p);
     HIPCHK(c, launch_potential(xyz, n, nat, p->hubbard_u, p->coulomb_k, c->V, c->stream));
     HIPCHK(c, launch_forces(xyz, nat, a, D, q, n, c->V, F, c->eatom, U_dev, c->stream));
+    return SP2_OK;
+}
+
+// Non-orthogonal forces at constant n: the orthogonal terms with the overlap
+// charges q, plus sum_ab M_ab dS_ab/dR_k with M = 2 D H D - (V_a + V_b) D_ab.
+extern "C" sp2_status tb_forces_nonorth(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
+                                        const double* xyz, const double* D, const double* S, const double* H,
+                                        const double* q, const double* n_aux, double* F_out, double* U_host) {
+    if (!c) return SP2_EINVAL;
+    if (!params_ok(p) || !(s0 >= 0.0) || !(lam_s > 0.0)) return fail(c, SP2_EINVAL, "bad overlap parameters");
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !D || !S || !H || !q || !n_aux || !F_out)
+        return fail(c, SP2_EINVAL, "bad tb_forces_nonorth arguments");
+    (void)S;
+    HIPCHK(c, hipSetDevice(c->device));
+    sp2_status s = ensure_atoms(c, n_atoms);
+    if (s != SP2_OK) return s;
+    if ((s = ensure_blas(c)) != SP2_OK) return s;
+    const int N = 4 * n_atoms;
+    const size_t n2 = (size_t)N * N;
+    size_t nb = c->nocap;
+    if ((s = grow(c, (void**)&c->nobuf, &nb, (4 * n2 + kNsBlocks + 64) * sizeof(double))) != SP2_OK) return s;
+    c->nocap = nb;
+    double* W1 = c->nobuf;
+    double* W2 = W1 + n2;
+    // orthogonal terms (band with h, Coulomb with q, pair) and U; V = gamma n
+    if ((s = forces_impl(c, p, n_atoms, xyz, D, q, n_aux, F_out, c->scal)) != SP2_OK) return s;
+    // energy-weighted density matrix W = D H D, then M in place
+    if ((s = gemm_rm(c, N, D, H, W1)) != SP2_OK) return s;
+    if ((s = gemm_rm(c, N, W1, D, W2)) != SP2_OK) return s;
+    HIPCHK(c, launch_force_matrix(W2, D, c->V, n_atoms, c->stream));
+    HIPCHK(c, launch_forces_overlap(xyz, n_atoms, make_radial(s0, p->r0, lam_s, p->r_tail, p->r_cut), W2, F_out,
+                                    c->stream));
+    if (U_host) {
+        HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *U_host = c->scal_host[0];
+    }
     return SP2_OK;
 }
 

@@ -26,6 +26,13 @@ hipError_t launch_potential(const double* xyz, const double* n, int nat, double 
                             hipStream_t s);
 hipError_t launch_hamiltonian(const double* xyz, int nat, const TBArgs& a, const double* V, double* H,
                               hipStream_t s);
+// Non-orthogonal charge shift H += (S L + L S)/2 (V per atom); the force
+// matrix M = 2 W - (V_a + V_b) D in place of W = D H D; the overlap term of
+// the force added to F.
+hipError_t launch_overlap_shift(double* H, const double* S, const double* V, int nat, hipStream_t s);
+hipError_t launch_force_matrix(double* W, const double* D, const double* V, int nat, hipStream_t s);
+hipError_t launch_forces_overlap(const double* xyz, int nat, const Radial& ov, const double* M, double* F,
+                                 hipStream_t s);
 // S of the non-orthogonal variant for overlap radial function ov.
 hipError_t launch_overlap(const double* xyz, int nat, const Radial& ov, double* S, hipStream_t s);
 hipError_t launch_forces(const double* xyz, int nat, const TBArgs& a, const double* D, const double* q,

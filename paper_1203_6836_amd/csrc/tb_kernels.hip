@@ -47,6 +47,33 @@ __device__ __forceinline__ void sk_block(const double c[3], double t, double B[4
     }
 }
 
+// g_x = sum_ab W[a][b] dB_ab/dd_x for the block B = sk_block(c, t(r)) of the
+// pair vector d (|d| = r, c = d / r, dt = t'(r)): direction-cosine part
+// dc_m/dd_x = (delta_mx - c_m c_x)/r and radial part dt/dd_x = dt c_x.
+__device__ __forceinline__ void sk_grad_dot(const double c[3], double r, double t, double dt, const double W[4][4],
+                                            double g[3]) {
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        double dc[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) dc[m] = ((m == x ? 1.0 : 0.0) - c[m] * c[x]) / r;
+        const double dtt = dt * c[x];
+        double s = -dtt * W[0][0];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const double dsp = dc[m] * t + c[m] * dtt;   // d(c_m t)
+            s += dsp * (W[0][m + 1] - W[m + 1][0]);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const double dpp = 2.0 * (dtt * c[m] * c[l] + t * (dc[m] * c[l] + c[m] * dc[l]))
+                                   - (m == l ? dtt : 0.0);
+                s += dpp * W[m + 1][l + 1];
+            }
+        }
+        g[x] = s;
+    }
+}
+
 // V_i = sum_l gamma_il n_l: one wave per atom i.
 __global__ __launch_bounds__(256) void k_potential(const double* __restrict__ xyz, const double* __restrict__ n,
                                                    int nat, double U, double ke, double* __restrict__ V) {
@@ -136,6 +163,67 @@ __global__ __launch_bounds__(256) void k_overlap(const double* __restrict__ xyz,
     }
 }
 
+// Non-orthogonal charge shift: H_ab += (S_ab / 2)(V_atom(a) + V_atom(b)).
+__global__ __launch_bounds__(256) void k_overlap_shift(double* __restrict__ H, const double* __restrict__ S,
+                                                       const double* __restrict__ V, int nat) {
+    const size_t N = 4 * (size_t)nat, n2 = N * N;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 256) {
+        const size_t a = e / N, b = e % N;
+        H[e] += 0.5 * S[e] * (V[a >> 2] + V[b >> 2]);
+    }
+}
+
+// M = 2 W - (V_atom(a) + V_atom(b)) D_ab in place of W (W = D H D).
+__global__ __launch_bounds__(256) void k_force_matrix(double* __restrict__ W, const double* __restrict__ D,
+                                                      const double* __restrict__ V, int nat) {
+    const size_t N = 4 * (size_t)nat, n2 = N * N;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 256) {
+        const size_t a = e / N, b = e % N;
+        W[e] = 2.0 * W[e] - (V[a >> 2] + V[b >> 2]) * D[e];
+    }
+}
+
+// Overlap term of the non-orthogonal force: F_k += 2 sum_j sum_ab M_{ka,jb}
+// d sk_block(c_kj, s(r_kj))_ab / d(R_j - R_k) (the overlap block is
+// -sk_block with the overlap's radial function s); one wave per atom k.
+__global__ __launch_bounds__(256) void k_forces_overlap(const double* __restrict__ xyz, int nat, Radial ov,
+                                                        const double* __restrict__ M, double* __restrict__ F) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= nat) return;
+    const size_t N = 4 * (size_t)nat;
+    const double xk = xyz[3 * k], yk = xyz[3 * k + 1], zk = xyz[3 * k + 2];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int j = lane; j < nat; j += 64) {
+        if (j == k) continue;
+        const double dx = xyz[3 * j] - xk, dy = xyz[3 * j + 1] - yk, dz = xyz[3 * j + 2] - zk;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r >= ov.rcut) continue;
+        double s, ds;
+        radial(ov, r, s, ds);
+        const double c[3] = {dx / r, dy / r, dz / r};
+        double Mkj[4][4];
+        const double* Mp = M + 4 * (size_t)k * N + 4 * (size_t)j;
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) Mkj[p][qq] = Mp[p * N + qq];
+        double g[3];
+        sk_grad_dot(c, r, s, ds, Mkj, g);
+        fx += 2.0 * g[0];
+        fy += 2.0 * g[1];
+        fz += 2.0 * g[2];
+    }
+    fx = wsum(fx);
+    fy = wsum(fy);
+    fz = wsum(fz);
+    if (lane == 0) {
+        F[3 * k] += fx;
+        F[3 * k + 1] += fy;
+        F[3 * k + 2] += fz;
+    }
+}
+
 // Forces and per-atom energy terms at constant n; one wave per atom k.
 //   F_k = 4 sum_j sum_ab D_{ka,jb} dB_kj/d(R_j - R_k)          (band)
 //       - sum_j (q_k n_j + q_j n_k - n_k n_j) k_e (R_j - R_k)/r^3 (Coulomb)
@@ -197,29 +285,8 @@ __global__ __launch_bounds__(256) void k_forces(const double* __restrict__ xyz, 
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) eb += Dkj[p][qq] * B[p][qq];
         e += 2.0 * eb;
-        // dB/dd_x: direction-cosine part dc_m/dd_x = (delta_mx - c_m c_x)/r and
-        // radial part dt/dd_x = dt * c_x; B depends on (c, t) as in sk_block.
         double g[3];
-#pragma unroll
-        for (int x = 0; x < 3; ++x) {
-            double dc[3];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) dc[m] = ((m == x ? 1.0 : 0.0) - c[m] * c[x]) / r;
-            const double dtt = dt * c[x];
-            double s = -dtt * Dkj[0][0];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const double dsp = dc[m] * t + c[m] * dtt;   // d(c_m t)
-                s += dsp * (Dkj[0][m + 1] - Dkj[m + 1][0]);
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                    const double dpp = 2.0 * (dtt * c[m] * c[l] + t * (dc[m] * c[l] + c[m] * dc[l]))
-                                       - (m == l ? dtt : 0.0);
-                    s += dpp * Dkj[m + 1][l + 1];
-                }
-            }
-            g[x] = s;
-        }
+        sk_grad_dot(c, r, t, dt, Dkj, g);
         fx += 4.0 * g[0];
         fy += 4.0 * g[1];
         fz += 4.0 * g[2];
@@ -317,6 +384,23 @@ hipError_t launch_potential(const double* xyz, const double* n, int nat, double 
 hipError_t launch_hamiltonian(const double* xyz, int nat, const TBArgs& a, const double* V, double* H,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_hamiltonian, dim3((nat + 255) / 256, nat), dim3(256), 0, s, xyz, nat, a, V, H);
+    return hipGetLastError();
+}
+static int grid_n2(int nat) {
+    const size_t n2 = 16 * (size_t)nat * nat, g = (n2 + 255) / 256;
+    return (int)(g < 4096 ? g : 4096);
+}
+hipError_t launch_overlap_shift(double* H, const double* S, const double* V, int nat, hipStream_t s) {
+    hipLaunchKernelGGL(k_overlap_shift, dim3(grid_n2(nat)), dim3(256), 0, s, H, S, V, nat);
+    return hipGetLastError();
+}
+hipError_t launch_force_matrix(double* W, const double* D, const double* V, int nat, hipStream_t s) {
+    hipLaunchKernelGGL(k_force_matrix, dim3(grid_n2(nat)), dim3(256), 0, s, W, D, V, nat);
+    return hipGetLastError();
+}
+hipError_t launch_forces_overlap(const double* xyz, int nat, const Radial& ov, const double* M, double* F,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_forces_overlap, dim3((nat + 3) / 4), dim3(256), 0, s, xyz, nat, ov, M, F);
     return hipGetLastError();
 }
 hipError_t launch_overlap(const double* xyz, int nat, const Radial& ov, double* S, hipStream_t s) {

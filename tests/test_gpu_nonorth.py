@@ -138,3 +138,34 @@ def test_nonorth_full_size_timing(ctx):
     say(f"  {ms:.0f} ms total, SP2 {st['ms']:.0f} ms ({st['iterations']} products), factor steps {its}; "
         f"Tr[DS] - n_occ {tr:+.1e}, ||D S D - D||/sqrtN {idem:.1e}")
     assert abs(tr) < 1e-5 and idem < 1e-5
+
+
+def test_nonorth_hamiltonian_and_forces_match_oracle(ctx):
+    """The non-orthogonal H[n] and the forces at constant n (orthogonal terms with
+    the overlap charges plus the overlap term) on the 3 x 3 x 2 cluster of the
+    MD model with overlap, against the oracle (whose forces are pinned by finite
+    differences of U)."""
+    import paper_1203_6836_amd as p
+    m = synth.MD_MODEL.with_(overlap_s0=0.05)
+    pos = synth.lattice_positions((3, 3, 2), seed=4)
+    nat = len(pos)
+    nocc = 2 * nat
+    n = np.random.default_rng(7).normal(0.0, 0.1, nat)
+    say("case nonorth H[n], forces 3x3x2")
+    xyz, nd = to_dev(pos), to_dev(n)
+    S = ctx.tb_overlap(m, xyz)
+    H = ctx.tb_hamiltonian_nonorth(m, xyz, S, nd)
+    S_o = nonorth.overlap(pos, m)
+    H_o = nonorth.hamiltonian(pos, n, m, S_o)
+    assert np.abs(H.cpu().numpy() - H_o).max() < 1e-13
+    D, st, _ = ctx.sp2_density_matrix_nonorth(H, S, nocc, p.options("fp64"))
+    q = ctx.sp2_mulliken_overlap(D, S, nat)
+    F, U = ctx.tb_forces_nonorth(m, xyz, D, S, H, q, nd)
+    rho_o, _, _, r = nonorth.density_matrix(H_o, S_o, nocc)
+    F_o = nonorth.forces(pos, n, rho_o, m, S_o)
+    U_o = nonorth.potential_energy(pos, n, rho_o, m, S_o)
+    dF = float(np.abs(F.cpu().numpy() - F_o).max())
+    say(f"  SP2 iterations gpu={st['iterations']} oracle={r.iterations}; max|dF| {dF:.1e} "
+        f"(max|F| {np.abs(F_o).max():.1f}), dU {abs(U - U_o):.1e}")
+    assert dF < 1e-8
+    assert U == pytest.approx(U_o, abs=1e-8)

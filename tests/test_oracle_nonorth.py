@@ -64,3 +64,48 @@ def test_mulliken_brute_force(system):
     for i in range(w.n_atoms):
         pop = sum(rho[a, b] * S[b, a] for a in range(4 * i, 4 * i + 4) for b in range(len(S)))
         assert q[i] == pytest.approx(2.0 * pop - 4.0, abs=1e-10)
+
+
+def _md_system():
+    m = synth.NONORTH_MODEL.with_(r_tail=3.5, pair_a=5.605396, pair_rho=0.15, overlap_s0=0.08)
+    pos = synth.lattice_positions((2, 2, 2), seed=21)
+    n = np.linspace(-0.3, 0.25, len(pos))
+    return m, pos, n, 2 * len(pos)
+
+
+def _rho(pos, n, m, nocc):
+    E, C = scipy.linalg.eigh(nonorth.hamiltonian(pos, n, m), nonorth.overlap(pos, m))
+    return C[:, :nocc] @ C[:, :nocc].T
+
+
+def test_nonorth_forces_are_gradient_of_energy():
+    """Central finite differences of U(R; n), rho the exact generalized
+    projector at each displaced geometry; and the overlap term is needed."""
+    from oracle import observables
+    m, pos, n, nocc = _md_system()
+    rho = _rho(pos, n, m, nocc)
+    F = nonorth.forces(pos, n, rho, m)
+    q = nonorth.mulliken(rho, nonorth.overlap(pos, m), m.z_val)
+    F_no_overlap_term = observables.forces(pos, n, rho, m, q=q)
+    h = 1e-5
+    fd = np.zeros_like(F)
+    for k in range(len(pos)):
+        for a in range(3):
+            pp = pos.copy()
+            pp[k, a] += h
+            pm = pos.copy()
+            pm[k, a] -= h
+            fd[k, a] = -(nonorth.potential_energy(pp, n, _rho(pp, n, m, nocc), m)
+                         - nonorth.potential_energy(pm, n, _rho(pm, n, m, nocc), m)) / (2 * h)
+    assert np.abs(F - fd).max() < 1e-5
+    assert np.abs(F_no_overlap_term - fd).max() > 1e-2
+
+
+def test_nonorth_energy_and_forces_reduce_to_orthogonal():
+    from oracle import observables
+    m, pos, n, nocc = _md_system()
+    m0 = m.with_(overlap_s0=0.0)
+    rho = _rho(pos, n, m0, nocc)
+    assert np.array_equal(nonorth.hamiltonian(pos, n, m0), tb.hamiltonian(pos, n, m0))
+    assert nonorth.potential_energy(pos, n, rho, m0) == observables.potential_energy(pos, n, rho, m0)
+    np.testing.assert_allclose(nonorth.forces(pos, n, rho, m0), observables.forces(pos, n, rho, m0), atol=1e-12)
