@@ -315,6 +315,12 @@ typedef struct {
                          max_i |q_i - n_i| exceeds this (e), the sign of kappa
                          outside the stability bound of Eq. Verl_n or of a too
                          long time step; 0: no check                           */
+    double overlap_s0;  /* > 0: non-orthogonal basis with the overlap of
+                           tb_overlap(s0, overlap_lam): H[n], the density
+                           matrix, charges and forces of the non-orthogonal
+                           entry points each step; 0 (zero-initialised
+                           options): orthogonal                              */
+    double overlap_lam;
 } xlbomd_options;
 
 typedef struct {

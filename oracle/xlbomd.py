@@ -18,6 +18,9 @@ Test infrastructure only.
 * Constant of motion: E_tot = kinetic + U(R; n) (Eq. EtotOrth, S = 0).
 
 The density matrix comes from the oracle SP2 (or Jacobi when requested).
+A model with a nonzero overlap (overlap_s0 > 0) takes the non-orthogonal
+H[n], density matrix, charges, energy and forces of the nonorth module (its
+readings); the integrators are unchanged.
 """
 from __future__ import annotations
 
@@ -27,7 +30,7 @@ import numpy as np
 
 import synth
 
-from . import eig, observables, sp2, tb
+from . import eig, nonorth, observables, sp2, tb
 
 K5_KAPPA = 1.82
 K5_ALPHA = 0.018
@@ -55,8 +58,39 @@ def density(H, n_occ, solver="sp2", tol=1e-10):
     return r.D
 
 
+def _nonorth(m):
+    return getattr(m, "overlap_s0", 0.0) > 0.0
+
+
+def nonorth_density(H, S, n_occ, solver="sp2", tol=1e-10):
+    if solver == "jacobi":
+        import scipy.linalg
+        _, C = scipy.linalg.eigh(H, S)
+        return C[:, :n_occ] @ C[:, :n_occ].T
+    rho, _, _, r = nonorth.density_matrix(H, S, n_occ, tol=tol)
+    if r.status not in ("converged", "stalled"):
+        raise RuntimeError(f"oracle SP2 ended with status {r.status}")
+    return rho
+
+
+def charges(pos, n, m, n_occ, solver="sp2"):
+    """Charges of the density matrix of H[n] (either basis)."""
+    if _nonorth(m):
+        S = nonorth.overlap(pos, m)
+        return nonorth.mulliken(nonorth_density(nonorth.hamiltonian(pos, n, m, S), S, n_occ, solver), S, m.z_val)
+    return observables.mulliken(density(tb.hamiltonian(pos, n, m), n_occ, solver), m.z_val)
+
+
 def evaluate(pos, n, m, n_occ, solver="sp2", tol=1e-10, want_forces=True):
     """One density-matrix construction at (R, n): returns dict of q, U, F, D."""
+    if _nonorth(m):
+        S = nonorth.overlap(pos, m)
+        H = nonorth.hamiltonian(pos, n, m, S)
+        D = nonorth_density(H, S, n_occ, solver, tol)
+        q = nonorth.mulliken(D, S, m.z_val)
+        U = nonorth.potential_energy(pos, n, D, m, S)
+        F = nonorth.forces(pos, n, D, m, S) if want_forces else None
+        return {"q": q, "U": U, "F": F, "D": D, "H": H, "S": S}
     H = tb.hamiltonian(pos, n, m)
     D = density(H, n_occ, solver, tol)
     q = observables.mulliken(D, m.z_val)
@@ -70,8 +104,7 @@ def scf(pos, m, n_occ, beta=0.02, tol=1e-10, max_iter=20000, n0=None,
     """Self-consistent charges by linear mixing; returns (q*, iterations)."""
     n = np.zeros(len(pos)) if n0 is None else np.array(n0, dtype=np.float64)
     for it in range(max_iter):
-        H = tb.hamiltonian(pos, n, m)
-        q = observables.mulliken(density(H, n_occ, solver), m.z_val)
+        q = charges(pos, n, m, n_occ, solver)
         if np.max(np.abs(q - n)) < tol:
             return q, it + 1
         n = n + beta * (q - n)

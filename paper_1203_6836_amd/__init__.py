@@ -72,7 +72,7 @@ class XLOptions(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("K", ctypes.c_int),
                 ("c", ctypes.c_double * 9), ("sp2", Sp2Options),
                 ("scf_beta", ctypes.c_double), ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int),
-                ("diverge_q", ctypes.c_double)]
+                ("diverge_q", ctypes.c_double), ("overlap_s0", ctypes.c_double), ("overlap_lam", ctypes.c_double)]
 
 
 class XLRecord(ctypes.Structure):
@@ -406,6 +406,8 @@ class XLBOMD:
         o.sp2 = sp2_opts if sp2_opts is not None else options("fp64")
         o.scf_beta, o.scf_tol, o.scf_max_iter = scf_beta, scf_tol, scf_max_iter
         o.diverge_q = diverge_q
+        o.overlap_s0 = float(getattr(model, "overlap_s0", 0.0))
+        o.overlap_lam = float(getattr(model, "overlap_lam", 0.5))
         p = tb_params(model)
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)

@@ -803,16 +803,11 @@ static sp2_status forces_impl(sp2_ctx* c, const tb_params* p, int nat, const dou
 }
 
 // Non-orthogonal forces at constant n: the orthogonal terms with the overlap
-// charges q, plus sum_ab M_ab dS_ab/dR_k with M = 2 D H D - (V_a + V_b) D_ab.
-extern "C" sp2_status tb_forces_nonorth(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
-                                        const double* xyz, const double* D, const double* S, const double* H,
-                                        const double* q, const double* n_aux, double* F_out, double* U_host) {
-    if (!c) return SP2_EINVAL;
-    if (!params_ok(p) || !(s0 >= 0.0) || !(lam_s > 0.0)) return fail(c, SP2_EINVAL, "bad overlap parameters");
-    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !D || !S || !H || !q || !n_aux || !F_out)
-        return fail(c, SP2_EINVAL, "bad tb_forces_nonorth arguments");
-    (void)S;
-    HIPCHK(c, hipSetDevice(c->device));
+// charges q, plus sum_ab M_ab dS_ab/dR_k with M = 2 D H D - (V_a + V_b) D_ab;
+// U to the device slot U_dev.
+static sp2_status tb_forces_nonorth_impl(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
+                                         const double* xyz, const double* D, const double* H, const double* q,
+                                         const double* n, double* F, double* U_dev) {
     sp2_status s = ensure_atoms(c, n_atoms);
     if (s != SP2_OK) return s;
     if ((s = ensure_blas(c)) != SP2_OK) return s;
@@ -824,13 +819,29 @@ extern "C" sp2_status tb_forces_nonorth(sp2_ctx* c, const tb_params* p, double s
     double* W1 = c->nobuf;
     double* W2 = W1 + n2;
     // orthogonal terms (band with h, Coulomb with q, pair) and U; V = gamma n
-    if ((s = forces_impl(c, p, n_atoms, xyz, D, q, n_aux, F_out, c->scal)) != SP2_OK) return s;
+    if ((s = forces_impl(c, p, n_atoms, xyz, D, q, n, F, U_dev)) != SP2_OK) return s;
     // energy-weighted density matrix W = D H D, then M in place
     if ((s = gemm_rm(c, N, D, H, W1)) != SP2_OK) return s;
     if ((s = gemm_rm(c, N, W1, D, W2)) != SP2_OK) return s;
     HIPCHK(c, launch_force_matrix(W2, D, c->V, n_atoms, c->stream));
-    HIPCHK(c, launch_forces_overlap(xyz, n_atoms, make_radial(s0, p->r0, lam_s, p->r_tail, p->r_cut), W2, F_out,
+    HIPCHK(c, launch_forces_overlap(xyz, n_atoms, make_radial(s0, p->r0, lam_s, p->r_tail, p->r_cut), W2, F,
                                     c->stream));
+    return SP2_OK;
+}
+
+extern "C" sp2_status tb_forces_nonorth(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
+                                        const double* xyz, const double* D, const double* S, const double* H,
+                                        const double* q, const double* n_aux, double* F_out, double* U_host) {
+    if (!c) return SP2_EINVAL;
+    if (!params_ok(p) || !(s0 >= 0.0) || !(lam_s > 0.0)) return fail(c, SP2_EINVAL, "bad overlap parameters");
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !D || !S || !H || !q || !n_aux || !F_out)
+        return fail(c, SP2_EINVAL, "bad tb_forces_nonorth arguments");
+    (void)S;
+    HIPCHK(c, hipSetDevice(c->device));
+    sp2_status s = ensure_atoms(c, n_atoms);
+    if (s != SP2_OK) return s;
+    if ((s = tb_forces_nonorth_impl(c, p, s0, lam_s, n_atoms, xyz, D, H, q, n_aux, F_out, c->scal)) != SP2_OK)
+        return s;
     if (U_host) {
         HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -917,6 +928,7 @@ struct xlbomd {
     int nat;
     int n_occ;            // doubly occupied states: z_val n_atoms / 2
     double *xyz, *vel, *F, *q, *hist, *H, *D, *dev, *dscal;
+    double* S = nullptr;  // overlap (non-orthogonal basis only)
     int head;
     long step;
     double U;
@@ -932,6 +944,21 @@ static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true, fl
     sp2_status s = tb_hamiltonian(c, &m->p, nat, m->xyz, n_t, m->H);
     if (s != SP2_OK) return s;
     sp2_stats st;
+    if (m->S) {
+        // non-orthogonal basis: overlap at these positions, H[n] with it, the
+        // density matrix through the Loewdin factor, charges and forces with S
+        if ((s = tb_overlap(c, &m->p, m->o.overlap_s0, m->o.overlap_lam, nat, m->xyz, m->S)) != SP2_OK) return s;
+        if ((s = tb_hamiltonian_nonorth(c, &m->p, nat, m->xyz, n_t, m->S, m->H)) != SP2_OK) return s;
+        if ((s = sp2_density_matrix_nonorth(c, N, m->H, m->S, m->n_occ, &m->o.sp2, m->D, &st, nullptr)) != SP2_OK)
+            return s;
+        m->dm_count += 1;
+        if (iters) *iters = st.iterations;
+        if (fill) *fill = m->o.sp2.tau > 0.0 ? (float)st.fill_min : 1.0f;
+        HIPCHK(c, launch_mulliken_overlap(m->D, m->S, nat, m->p.z_val, m->q, c->stream));
+        if (!with_forces) return SP2_OK;
+        return tb_forces_nonorth_impl(c, &m->p, m->o.overlap_s0, m->o.overlap_lam, nat, m->xyz, m->D, m->H, m->q,
+                                      n_t, m->F, m->dscal);
+    }
     s = sp2_solve(c, N, m->H, m->n_occ, m->o.sp2, m->D, &st);
     if (s != SP2_OK) return s;
     m->dm_count += 1;
@@ -961,6 +988,8 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
         return fail(c, SP2_EINVAL, "z_val * n_atoms must be an even electron count below 8 n_atoms");
     if (o->K < 1 || o->K > 8 || !(o->dt_fs > 0) || !(p->mass > 0) || !(o->diverge_q >= 0))
         return fail(c, SP2_EINVAL, "bad xlbomd options");
+    if (!(o->overlap_s0 >= 0.0) || (o->overlap_s0 > 0.0 && !(o->overlap_lam > 0.0)))
+        return fail(c, SP2_EINVAL, "bad overlap parameters");
     sp2_status s = check_options(c, o->sp2, 4 * n_atoms);
     if (s != SP2_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
@@ -980,6 +1009,7 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
     ok = ok && hipMalloc((void**)&m->H, N * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void**)&m->D, N * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void**)&m->dscal, 8 * sizeof(double)) == hipSuccess;
+    if (o->overlap_s0 > 0.0) ok = ok && hipMalloc((void**)&m->S, N * N * sizeof(double)) == hipSuccess;
     if (!ok) {
         xlbomd_destroy(m);
         return fail(c, SP2_ENOMEM, "xlbomd allocation failed");
@@ -1196,7 +1226,7 @@ extern "C" void xlbomd_destroy(xlbomd* m) {
     if (!m) return;
     (void)hipSetDevice(m->c->device);
     (void)hipStreamSynchronize(m->c->stream);
-    double* bufs[] = {m->xyz, m->vel, m->F, m->q, m->dev, m->hist, m->H, m->D, m->dscal};
+    double* bufs[] = {m->xyz, m->vel, m->F, m->q, m->dev, m->hist, m->H, m->D, m->dscal, m->S};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     delete m;
