@@ -256,3 +256,31 @@ def test_nonorth_xlbomd_energy_conservation(ctx):
         assert drift <= 2.0 * sigma
         sig[s0] = sigma
     assert sig[0.05] <= 2.0 * sig[0.0]
+
+
+def test_nonorth_thresholded_gapped_wire_vs_oracle(ctx):
+    """The SP2 of H_perp with the elementwise threshold (tau = 1e-5, int8 and
+    FP64 products) on the gapped 4 x 4 x 16 wire with an overlap, against the
+    oracle's thresholded non-orthogonal solve: FP64 step by step, int8 within
+    a quarter of what the threshold itself moves rho."""
+    import paper_1203_6836_amd as p
+    m = synth.GAPPED_MODEL.with_(overlap_s0=0.05)
+    w = synth.gapped_workload(16)
+    pos = w.positions()
+    say(f"case nonorth tau=1e-5 element, gapped wire N={w.n_orb}")
+    H = otb.hamiltonian0(pos, m)
+    S = nonorth.overlap(pos, m)
+    ref, _, _, r = nonorth.density_matrix(H, S, w.n_occ, tau=1e-5, threshold="element")
+    dense, _, _, _ = nonorth.density_matrix(H, S, w.n_occ)
+    rn = np.sqrt(w.n_orb)
+    err_thr = np.linalg.norm(ref - dense) / rn
+    Hd, Sd = to_dev(H), to_dev(S)
+    D64, s64, _ = ctx.sp2_density_matrix_nonorth(Hd, Sd, w.n_occ, p.options("fp64", tau=1e-5, threshold=1))
+    D8, s8, _ = ctx.sp2_density_matrix_nonorth(Hd, Sd, w.n_occ, p.options("int8x", tau=1e-5, threshold=1))
+    e64 = np.linalg.norm(D64.cpu().numpy() - ref) / rn
+    e8 = np.linalg.norm(D8.cpu().numpy() - ref) / rn
+    say(f"  iters oracle={r.iterations} fp64={s64['iterations']} int8={s8['iterations']}; err fp64 {e64:.1e}, "
+        f"int8 {e8:.1e}, threshold's own {err_thr:.1e}, fill min {s8['fill_min']:.3f}")
+    assert s64["iterations"] == r.iterations
+    assert e64 <= 1e-9
+    assert e8 <= 0.25 * err_thr
