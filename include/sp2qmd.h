@@ -267,14 +267,15 @@ sp2_status tb_hamiltonian_nonorth(sp2_ctx *ctx, const tb_params *p, int n_atoms,
  * overlap charges q (sp2_mulliken_overlap), F_k = -dU/dR_k is the orthogonal
  * force of tb_forces with these q plus sum_ab M_ab dS_ab/dR_k, where
  * M = 2 D H D - (V_a + V_b) D_ab (the energy-weighted density matrix of the
- * generalized eigenproblem and the overlap inside H[n] and q).  D: the
- * density matrix of H = H[n] (sp2_density_matrix_nonorth); S, H, D:
- * (4 n_atoms)^2 device; q, n_aux: n_atoms device; s0, lam_s: the overlap
- * parameters of tb_overlap; F_out: 3 n_atoms device; U_host: host or NULL.
- * Uses two N^2 scratch buffers of the context (two rocBLAS GEMMs form D H D). */
+ * generalized eigenproblem and the overlap inside H[n] and q; dS/dR_k is
+ * evaluated from the positions).  D: the density matrix of H = H[n]
+ * (sp2_density_matrix_nonorth); H, D: (4 n_atoms)^2 device; q, n_aux:
+ * n_atoms device; s0, lam_s: the overlap parameters of tb_overlap; F_out:
+ * 3 n_atoms device; U_host: host or NULL.  Uses two N^2 scratch buffers of
+ * the context (two rocBLAS GEMMs form D H D). */
 sp2_status tb_forces_nonorth(sp2_ctx *ctx, const tb_params *p, double s0, double lam_s, int n_atoms,
-                             const double *xyz, const double *D, const double *S, const double *H,
-                             const double *q, const double *n_aux, double *F_out, double *U_host);
+                             const double *xyz, const double *D, const double *H, const double *q,
+                             const double *n_aux, double *F_out, double *U_host);
 
 /* Forces at constant auxiliary charges n (Eq. EL_Orth_a with Eq. EL_Orth_c,
  * on-site term read with rho - rho0):

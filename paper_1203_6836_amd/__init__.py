@@ -110,7 +110,7 @@ _SIGS = {
     "tb_overlap": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P]),
     "tb_hamiltonian_nonorth": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P]),
     "tb_forces_nonorth": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P, _P,
-                               _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+                               _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "tb_hamiltonian": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P]),
     "tb_forces": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P, _P,
                        ctypes.POINTER(_D)]),
@@ -288,7 +288,7 @@ class Context:
                                                  _ptr(H_out)), "tb_hamiltonian_nonorth")
         return H_out
 
-    def tb_forces_nonorth(self, model, xyz, D, S, H, q, n_aux, F_out=None):
+    def tb_forces_nonorth(self, model, xyz, D, H, q, n_aux, F_out=None):
         """(F, U): forces at constant n and the potential energy, non-orthogonal basis."""
         import torch
         nat = xyz.shape[0]
@@ -297,7 +297,7 @@ class Context:
         p = tb_params(model)
         U = ctypes.c_double()
         self._check(lib().tb_forces_nonorth(self._h, ctypes.byref(p), float(model.overlap_s0),
-                                            float(model.overlap_lam), nat, _ptr(xyz), _ptr(D), _ptr(S), _ptr(H),
+                                            float(model.overlap_lam), nat, _ptr(xyz), _ptr(D), _ptr(H),
                                             _ptr(q), _ptr(n_aux), _ptr(F_out), ctypes.byref(U)),
                     "tb_forces_nonorth")
         return F_out, U.value

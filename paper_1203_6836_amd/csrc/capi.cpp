@@ -830,13 +830,12 @@ static sp2_status tb_forces_nonorth_impl(sp2_ctx* c, const tb_params* p, double 
 }
 
 extern "C" sp2_status tb_forces_nonorth(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
-                                        const double* xyz, const double* D, const double* S, const double* H,
-                                        const double* q, const double* n_aux, double* F_out, double* U_host) {
+                                        const double* xyz, const double* D, const double* H, const double* q,
+                                        const double* n_aux, double* F_out, double* U_host) {
     if (!c) return SP2_EINVAL;
     if (!params_ok(p) || !(s0 >= 0.0) || !(lam_s > 0.0)) return fail(c, SP2_EINVAL, "bad overlap parameters");
-    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !D || !S || !H || !q || !n_aux || !F_out)
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !D || !H || !q || !n_aux || !F_out)
         return fail(c, SP2_EINVAL, "bad tb_forces_nonorth arguments");
-    (void)S;
     HIPCHK(c, hipSetDevice(c->device));
     sp2_status s = ensure_atoms(c, n_atoms);
     if (s != SP2_OK) return s;

@@ -160,7 +160,7 @@ def test_nonorth_hamiltonian_and_forces_match_oracle(ctx):
     assert np.abs(H.cpu().numpy() - H_o).max() < 1e-13
     D, st, _ = ctx.sp2_density_matrix_nonorth(H, S, nocc, p.options("fp64"))
     q = ctx.sp2_mulliken_overlap(D, S, nat)
-    F, U = ctx.tb_forces_nonorth(m, xyz, D, S, H, q, nd)
+    F, U = ctx.tb_forces_nonorth(m, xyz, D, H, q, nd)
     rho_o, _, _, r = nonorth.density_matrix(H_o, S_o, nocc)
     F_o = nonorth.forces(pos, n, rho_o, m, S_o)
     U_o = nonorth.potential_energy(pos, n, rho_o, m, S_o)
