@@ -1,0 +1,83 @@
+"""Oracle: the finite electronic temperature density matrix, FP64.
+
+Test infrastructure only.  At T_e > 0 the paper's density is the Fermi
+operator of H (Eq. EL_4c; Eq. DM_perp for the orthogonalised H), f(H) =
+(exp(beta (H - mu I)) + 1)^(-1), beta = 1 / (k_B T_e), built by the
+recursive Fermi-operator expansion it cites.  Readings (the paper cites the
+method without printing it, and leaves mu open):
+
+* definition: f(H) = V diag(f_i) V^T from the eigen-decomposition of H,
+  f_i = 1 / (1 + exp(beta (e_i - mu))), with mu the canonical chemical
+  potential, sum_i f_i = N_occ (solved by bisection);
+* the recursion: with y = beta (H - mu I) / 2^(n+2), X_0 = I/2 - y; then n
+  times X_{k+1} = X_k^2 (X_k^2 + (I - X_k)^2)^(-1).  The ratio (I - X)/X
+  squares at every step and starts at (I/2 + y)/(I/2 - y) ~ exp(4y), so X_n
+  approaches (exp(beta (H - mu I)) + 1)^(-1): its exponent carries a relative
+  error of about (4y)^2 / 12, i.e. (beta |e - mu| / 2^n)^2 / 12;
+* mu for the recursion: Newton steps on Tr X_n = N_occ with
+  d Tr X_n / d mu ~ beta Tr[X_n (I - X_n)] (the derivative of the Fermi
+  function), from mu = the midpoint of the Gershgorin bounds.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import sp2
+
+KB_EV_PER_K = 8.617333262e-5
+
+
+def fermi_occupations(e, mu, beta):
+    x = np.clip(beta * (np.asarray(e) - mu), -700.0, 700.0)
+    return 1.0 / (1.0 + np.exp(x))
+
+
+def canonical_mu(e, n_occ, beta, tol=1e-14):
+    """mu with sum_i f(e_i) = n_occ, by bisection."""
+    lo, hi = float(np.min(e)) - 50.0 / beta, float(np.max(e)) + 50.0 / beta
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if fermi_occupations(e, mid, beta).sum() > n_occ:
+            hi = mid
+        else:
+            lo = mid
+        if hi - lo < tol:
+            break
+    return 0.5 * (lo + hi)
+
+
+def fermi_density(H, n_occ, kT):
+    """(D, mu, occupations) of the definition (kT in eV)."""
+    beta = 1.0 / kT
+    e, V = np.linalg.eigh(H)
+    mu = canonical_mu(e, n_occ, beta)
+    f = fermi_occupations(e, mu, beta)
+    return (V * f) @ V.T, mu, f
+
+
+def recursive_fermi(H, mu, kT, n_steps):
+    """X_n of the recursive expansion at chemical potential mu."""
+    N = H.shape[0]
+    y = (H - mu * np.eye(N)) / (kT * 2.0 ** (n_steps + 2))
+    X = 0.5 * np.eye(N) - y
+    for _ in range(n_steps):
+        X2 = X @ X
+        A = 2.0 * X2 - 2.0 * X + np.eye(N)        # X^2 + (I - X)^2
+        X = X2 @ np.linalg.inv(A)
+        X = 0.5 * (X + X.T)
+    return X
+
+
+def recursive_fermi_canonical(H, n_occ, kT, n_steps, tol=1e-10, max_newton=50):
+    """(X_n, mu, Newton steps) with Tr X_n = n_occ."""
+    beta = 1.0 / kT
+    lo, hi = sp2.gershgorin(H)
+    mu = 0.5 * (lo + hi)
+    for it in range(max_newton):
+        X = recursive_fermi(H, mu, kT, n_steps)
+        t = float(np.trace(X))
+        if abs(t - n_occ) < tol:
+            return X, mu, it + 1
+        d = beta * (t - float(np.sum(X * X)))
+        mu -= (t - n_occ) / max(d, 1e-300)
+    raise RuntimeError("Newton on mu did not converge")

@@ -1,0 +1,64 @@
+"""Pins of the finite-temperature oracle: the definition against brute force and
+limits, the recursion against the definition within its error bound."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import eig, fermi, tb
+
+
+@pytest.fixture(scope="module")
+def system():
+    w = synth.small_workload((3, 3, 3), 4)
+    return w, tb.hamiltonian(w.positions(), None, synth.STATIC_MODEL)
+
+
+def test_fermi_definition_brute_force(system):
+    w, H = system
+    D, mu, f = fermi.fermi_density(H, w.n_occ, 0.5)
+    assert f.sum() == pytest.approx(w.n_occ, abs=1e-9)
+    assert np.trace(D) == pytest.approx(w.n_occ, abs=1e-9)
+    e, V = np.linalg.eigh(H)
+    for i in range(0, len(e), 17):                       # spot-check f(e_i) = 1/(1 + exp(beta (e_i - mu)))
+        assert f[i] == pytest.approx(1.0 / (1.0 + np.exp((e[i] - mu) / 0.5)), rel=1e-12)
+    np.testing.assert_allclose(D @ V, V * f, atol=1e-10)  # eigenvectors shared, eigenvalues f
+
+
+def test_fermi_zero_temperature_limit():
+    """A gapped system: as kT -> 0 the Fermi operator becomes the projector."""
+    w = synth.gapped_workload(2)
+    H = tb.hamiltonian0(w.positions(), synth.GAPPED_MODEL)
+    P, _, gap = eig.density_matrix(H, w.n_occ)
+    assert gap > 4.0
+    D, _, _ = fermi.fermi_density(H, w.n_occ, 0.05)
+    assert np.abs(D - P).max() < 1e-12
+
+
+def test_recursion_matches_definition_within_its_bound(system):
+    w, H = system
+    kT = 0.5
+    D, mu, f = fermi.fermi_density(H, w.n_occ, kT)
+    e = np.linalg.eigvalsh(H)
+    errs = []
+    for n in (8, 10, 12, 14):
+        X = fermi.recursive_fermi(H, mu, kT, n)
+        err = np.abs(X - D).max()
+        # exponent error (beta |e - mu| / 2^n)^2 / 12 times the slope f (1 - f) beta |e - mu|
+        x = np.abs(e - mu) / kT
+        bound = np.max(f * (1 - f) * x * (x / 2.0 ** n) ** 2 / 12.0) * len(e)
+        assert err <= bound + 1e-12
+        errs.append(err)
+    # the error falls as 2^(-2n): 16x per two steps, down to the rounding floor
+    for a, b in zip(errs, errs[1:]):
+        assert 12.0 < a / b < 20.0
+    assert np.abs(fermi.recursive_fermi(H, mu, kT, 18) - D).max() < 1e-10
+
+
+def test_canonical_recursion(system):
+    w, H = system
+    X, mu_x, its = fermi.recursive_fermi_canonical(H, w.n_occ, 0.5, 18)
+    D, mu, _ = fermi.fermi_density(H, w.n_occ, 0.5)
+    assert np.trace(X) == pytest.approx(w.n_occ, abs=1e-9)
+    assert mu_x == pytest.approx(mu, abs=1e-7)
+    assert np.abs(X - D).max() < 1e-8
+    assert its < 20
