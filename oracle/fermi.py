@@ -14,9 +14,14 @@ method without printing it, and leaves mu open):
   squares at every step and starts at (I/2 + y)/(I/2 - y) ~ exp(4y), so X_n
   approaches (exp(beta (H - mu I)) + 1)^(-1): its exponent carries a relative
   error of about (4y)^2 / 12, i.e. (beta |e - mu| / 2^n)^2 / 12;
-* mu for the recursion: Newton steps on Tr X_n = N_occ with
-  d Tr X_n / d mu ~ beta Tr[X_n (I - X_n)] (the derivative of the Fermi
-  function), from mu = the midpoint of the Gershgorin bounds.
+* mu for the recursion: Tr X_n grows monotonically with mu, so mu is solved
+  by Newton steps on Tr X_n = N_occ with d Tr X_n / d mu ~ beta Tr[X_n (I -
+  X_n)] (the derivative of the Fermi function), safeguarded by bisection: the
+  root stays bracketed, starting from [e_min - 40 kT, e_max + 40 kT] (the
+  Gershgorin bounds widened until every Fermi factor is below e^-40 at the
+  lower end and above 1 - e^-40 at the upper), and a Newton step that leaves
+  the bracket is replaced by its midpoint.  The first mu is the midpoint of the
+  Gershgorin bounds.
 """
 from __future__ import annotations
 
@@ -68,16 +73,22 @@ def recursive_fermi(H, mu, kT, n_steps):
     return X
 
 
-def recursive_fermi_canonical(H, n_occ, kT, n_steps, tol=1e-10, max_newton=50):
-    """(X_n, mu, Newton steps) with Tr X_n = n_occ."""
+def recursive_fermi_canonical(H, n_occ, kT, n_steps, tol=1e-10, max_newton=100):
+    """(X_n, mu, passes) with |Tr X_n - n_occ| < tol."""
     beta = 1.0 / kT
-    lo, hi = sp2.gershgorin(H)
-    mu = 0.5 * (lo + hi)
+    e_lo, e_hi = sp2.gershgorin(H)
+    lo, hi = e_lo - 40.0 * kT, e_hi + 40.0 * kT
+    mu = 0.5 * (e_lo + e_hi)
     for it in range(max_newton):
         X = recursive_fermi(H, mu, kT, n_steps)
         t = float(np.trace(X))
         if abs(t - n_occ) < tol:
             return X, mu, it + 1
+        if t < n_occ:
+            lo = mu
+        else:
+            hi = mu
         d = beta * (t - float(np.sum(X * X)))
-        mu -= (t - n_occ) / max(d, 1e-300)
+        step = mu - (t - n_occ) / d if d > 0.0 else np.nan
+        mu = step if lo < step < hi else 0.5 * (lo + hi)
     raise RuntimeError("Newton on mu did not converge")
