@@ -107,6 +107,8 @@ _SIGS = {
     "sp2_density_matrix_nonorth": (_I, [_P, _I, _P, _P, _I, ctypes.POINTER(Sp2Options), _P,
                                         ctypes.POINTER(Sp2Stats), ctypes.POINTER(_I)]),
     "sp2_mulliken_overlap": (_I, [_P, _I, _P, _P, ctypes.c_double, _P]),
+    "sp2_fermi_density_matrix": (_I, [_P, _I, _P, _D, _D, _I, _I, _D, ctypes.POINTER(_D), _P,
+                                      ctypes.POINTER(_I)]),
     "tb_overlap": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P]),
     "tb_hamiltonian_nonorth": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P]),
     "tb_forces_nonorth": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P, _P,
@@ -264,6 +266,28 @@ class Context:
                                               _ptr(D_out), ctypes.byref(stats), ctypes.byref(its))
         self._check(st, "sp2_density_matrix_nonorth")
         return D_out, stats.to_dict(), its.value
+
+    def sp2_fermi_density_matrix(self, H, n_occ: float, kT: float, n_steps: int, mu=None,
+                                 max_newton: int = 50, tol: float = 1e-10, D_out=None):
+        """(D, mu, passes): the Fermi operator at temperature kT by the recursive expansion.
+
+        max_newton == 0 keeps mu fixed (it must be given); otherwise mu is the
+        canonical chemical potential, Newton from mu (None: the middle of the
+        Gershgorin interval).
+        """
+        import torch
+        N = H.shape[0]
+        if H.shape != (N, N):
+            raise ValueError("H must be N x N")
+        if D_out is None:
+            D_out = torch.empty_like(H)
+        m = _D(float("nan") if mu is None else float(mu))
+        its = _I(0)
+        st = lib().sp2_fermi_density_matrix(self._h, N, _ptr(H), float(n_occ), float(kT), int(n_steps),
+                                            int(max_newton), float(tol), ctypes.byref(m), _ptr(D_out),
+                                            ctypes.byref(its))
+        self._check(st, "sp2_fermi_density_matrix")
+        return D_out, m.value, its.value
 
     def tb_overlap(self, model, xyz, S_out=None):
         """S of the non-orthogonal variant (model.overlap_s0, model.overlap_lam)."""

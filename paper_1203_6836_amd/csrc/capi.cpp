@@ -15,6 +15,7 @@
 #include <rocblas/rocblas.h>
 
 #include "../../include/sp2qmd.h"
+#include "fermi_internal.h"
 #include "nonorth_internal.h"
 #include "sp2_internal.h"
 #include "split_internal.h"
@@ -642,6 +643,122 @@ extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double
     if ((s = gemm_rm(c, N, W, Zm, D_out)) != SP2_OK) return s;
     HIPCHK(c, launch_symmetrize(D_out, N, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    return SP2_OK;
+}
+
+// ---------------------------------------------- finite electronic temperature
+// One pass of the recursive Fermi-operator expansion at chemical potential mu:
+// X_0 = I/2 - beta (H - mu I) / 2^(n+2), then n steps
+// X_{k+1} = X_k^2 (X_k^2 + (I - X_k)^2)^(-1), each made exactly symmetric.
+// buf holds five N x N matrices; returns the one holding X_n.
+static sp2_status fermi_pass(sp2_ctx* c, int N, const double* H, double mu, double beta, int n_steps, double* buf,
+                             double** Xn) {
+    const size_t n2 = (size_t)N * N;
+    double* X = buf;
+    double* X2 = buf + n2;
+    double* A = buf + 2 * n2;
+    double* Y = buf + 3 * n2;
+    double* R = buf + 4 * n2;
+    hipStream_t st = c->stream;
+    sp2_status s;
+    HIPCHK(c, launch_fermi_init(H, N, mu, beta / std::ldexp(1.0, n_steps + 2), X, st));
+    for (int k = 0; k < n_steps; ++k) {
+        if ((s = gemm_rm(c, N, X, X, X2)) != SP2_OK) return s;
+        HIPCHK(c, launch_fermi_a(X2, X, N, A, Y, st));        // A = X^2 + (I - X)^2, Y = Y_1
+        double* W = X;                                        // X is free until X_{k+1}
+        for (int j = 0; j < kFermiInvUpdates; ++j) {
+            if ((s = gemm_rm(c, N, A, Y, R)) != SP2_OK) return s;
+            HIPCHK(c, launch_two_minus(R, N, st));
+            if ((s = gemm_rm(c, N, Y, R, W)) != SP2_OK) return s;   // Y <- Y (2 I - A Y)
+            std::swap(Y, W);
+        }
+        if ((s = gemm_rm(c, N, X2, Y, W)) != SP2_OK) return s;      // X_{k+1} = X_k^2 A^(-1)
+        HIPCHK(c, launch_symmetrize(W, N, st));
+        X = W;
+    }
+    *Xn = X;
+    return SP2_OK;
+}
+
+extern "C" sp2_status sp2_fermi_density_matrix(sp2_ctx* c, int N, const double* H, double n_occ, double kT,
+                                                int n_steps, int max_newton, double tol, double* mu,
+                                                double* D_out, int* newton_iterations) {
+    if (!c) return SP2_EINVAL;
+    if (newton_iterations) *newton_iterations = 0;
+    if (N < 1 || N > 32768 || !H || !D_out || !mu) return fail(c, SP2_EINVAL, "bad Fermi-operator arguments");
+    if (!(kT > 0.0) || !std::isfinite(kT)) return fail(c, SP2_EINVAL, "need a finite kT > 0");
+    if (n_steps < 1 || n_steps > 60) return fail(c, SP2_EINVAL, "need 1 <= n_steps <= 60");
+    if (max_newton < 0 || max_newton > 1000) return fail(c, SP2_EINVAL, "need 0 <= max_newton <= 1000");
+    if (max_newton > 0 && (!(n_occ > 0.0) || !(n_occ < N) || !(tol > 0.0)))
+        return fail(c, SP2_EINVAL, "need 0 < n_occ < N and tol > 0");
+    if (max_newton == 0 && !std::isfinite(*mu)) return fail(c, SP2_EINVAL, "a fixed mu must be finite");
+    HIPCHK(c, hipSetDevice(c->device));
+    sp2_status s;
+    if ((s = ensure_blas(c)) != SP2_OK) return s;
+    const size_t n2 = (size_t)N * N;
+    size_t nb = c->nocap;
+    if ((s = grow(c, (void**)&c->nobuf, &nb, (5 * n2 + 2 * kFermiBlocks + 8) * sizeof(double))) != SP2_OK) return s;
+    c->nocap = nb;
+    double* part = c->nobuf + 5 * n2;
+    double* res = part + 2 * kFermiBlocks;
+    hipStream_t st = c->stream;
+    // validity of H and its Gershgorin interval
+    int ns = 0, nchk = 0;
+    HIPCHK(c, launch_check_h(H, N, c->chk, &nchk, st));
+    HIPCHK(c, launch_gershgorin(H, N, c->part, &ns, st));
+    HIPCHK(c, launch_bounds(c->part, ns, c->chk, nchk, c->st, st));
+    HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(State), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (c->st_host->done == 5) return fail(c, SP2_EINVAL, "H is not finite and symmetric");
+    const double e_lo = c->st_host->eps_min, e_hi = c->st_host->eps_max;
+    const double beta = 1.0 / kT;
+    // the root stays bracketed: below e_lo - 40 kT every Fermi factor is under
+    // e^-40 (Tr < n_occ), above e_hi + 40 kT over 1 - e^-40 (Tr > n_occ)
+    double lo = e_lo - 40.0 * kT, hi = e_hi + 40.0 * kT;
+    double m = max_newton == 0 ? *mu : (std::isfinite(*mu) && *mu > lo && *mu < hi) ? *mu : 0.5 * (e_lo + e_hi);
+    // X_0 has its spectrum in [0, 1] (and A in [1/2, 1]) when
+    // beta |e - mu| <= 2^(n+1) over the Gershgorin interval
+    const double reach = std::ldexp(1.0, n_steps + 1) / beta;
+    if (!(std::max(e_hi - m, m - e_lo) <= reach) || (max_newton > 0 && !(hi - lo <= reach)))
+        return fail(c, SP2_EINVAL, "beta |e - mu| can exceed 2^(n_steps + 1): more steps needed");
+    const int evals = max_newton == 0 ? 1 : max_newton;
+    for (int it = 0; it < evals; ++it) {
+        double* X = nullptr;
+        if ((s = fermi_pass(c, N, H, m, beta, n_steps, c->nobuf, &X)) != SP2_OK) return s;
+        if (newton_iterations) *newton_iterations = it + 1;
+        if (max_newton == 0) {
+            HIPCHK(c, hipMemcpyAsync(D_out, X, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            return SP2_OK;
+        }
+        HIPCHK(c, launch_trace_fro(X, N, part, st));
+        HIPCHK(c, launch_sum_pairs(part, kFermiBlocks, res, st));
+        HIPCHK(c, hipMemcpyAsync(c->scal_host, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        const double t = c->scal_host[0], fr = c->scal_host[1];
+        if (!std::isfinite(t) || !std::isfinite(fr)) return fail(c, SP2_EDEVICE, "non-finite Fermi-operator trace");
+        if (std::fabs(t - n_occ) < tol || it + 1 == evals) {
+            HIPCHK(c, hipMemcpyAsync(D_out, X, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            *mu = m;
+            if (std::fabs(t - n_occ) < tol) return SP2_OK;
+            return fail(c, SP2_ENOCONV, "Newton on mu did not reach Tr D = n_occ");
+        }
+        // Newton with dTr X / dmu ~ beta Tr[X (I - X)] (the Fermi function's
+        // derivative); a step out of the bracket bisects it instead
+        if (t < n_occ) lo = m;
+        else hi = m;
+        const double d = beta * (t - fr);
+        const double nm = d > 0.0 ? m - (t - n_occ) / d : NAN;
+        const double next = (nm > lo && nm < hi) ? nm : 0.5 * (lo + hi);
+        if (next == m) {   // X_0 cannot resolve a finer mu
+            HIPCHK(c, hipMemcpyAsync(D_out, X, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            *mu = m;
+            return fail(c, SP2_ENOCONV, "tol is below the resolution of Tr D in mu");
+        }
+        m = next;
+    }
     return SP2_OK;
 }
 

@@ -1,0 +1,131 @@
+"""Finite electronic temperature on the GPU: the Fermi operator by the
+recursive expansion (rocBLAS GEMMs, Newton-Schulz inverses, canonical mu by
+Newton) against the oracle's recursion at the same number of steps and against
+the definition by eigendecomposition."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fermi, sp2 as osp2, tb as otb
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_1203_6836_amd as p
+    c = p.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def lattice(dims, seed):
+    w = synth.small_workload(dims, seed)
+    return w, otb.hamiltonian(w.positions(), None, synth.STATIC_MODEL)
+
+
+@pytest.mark.parametrize("dims,seed,kT,n", [((3, 3, 3), 1, 0.5, 10), ((3, 3, 3), 2, 0.5, 14),
+                                            ((4, 4, 9), 3, 1.0, 12)])
+def test_fixed_mu_matches_oracle_recursion(ctx, dims, seed, kT, n):
+    w, H = lattice(dims, seed)
+    say(f"case fermi fixed mu N={w.n_orb} kT={kT} n={n}")
+    e = np.linalg.eigvalsh(H)
+    mu = 0.5 * (e[w.n_occ - 1] + e[w.n_occ])
+    ref = fermi.recursive_fermi(H, mu, kT, n)
+    D, mu_out, passes = ctx.sp2_fermi_density_matrix(to_dev(H), w.n_occ, kT, n, mu=mu, max_newton=0)
+    D = D.cpu().numpy()
+    err = float(np.abs(D - ref).max())
+    say(f"  max|D - oracle| {err:.2e}, passes {passes}")
+    assert passes == 1 and mu_out == mu
+    assert np.array_equal(D, D.T)
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("dims,seed,kT", [((3, 3, 3), 1, 0.5), ((4, 4, 8), 5, 0.25), ((4, 4, 9), 3, 2.0)])
+def test_canonical_matches_oracle_and_definition(ctx, dims, seed, kT):
+    w, H = lattice(dims, seed)
+    say(f"case fermi canonical N={w.n_orb} kT={kT}")
+    X, mu_ref, its_ref = fermi.recursive_fermi_canonical(H, w.n_occ, kT, 16, tol=1e-9)
+    Dd, mu_def, _ = fermi.fermi_density(H, w.n_occ, kT)
+    D, mu, passes = ctx.sp2_fermi_density_matrix(to_dev(H), w.n_occ, kT, 16, tol=1e-9)
+    D = D.cpu().numpy()
+    e_rec = float(np.abs(D - X).max())
+    e_def = float(np.abs(D - Dd).max())
+    say(f"  passes gpu={passes} oracle={its_ref}, mu {mu:.12f} (oracle {mu_ref:.12f}, definition {mu_def:.12f}), "
+        f"max|D - recursion| {e_rec:.2e}, max|D - definition| {e_def:.2e}, Tr D - n_occ {np.trace(D) - w.n_occ:+.1e}")
+    assert abs(passes - its_ref) <= 1
+    assert abs(mu - mu_ref) < 1e-9 and abs(mu - mu_def) < 1e-8
+    assert abs(np.trace(D) - w.n_occ) < 1e-9
+    assert e_rec < 1e-9 and e_def < 1e-8
+
+
+def test_low_temperature_limit_is_the_projector(ctx):
+    """kT = 0.02 eV on the gapped wire (gap ~5 eV): D equals the zero-temperature
+    projector (the oracle's SP2 result) to the Fermi tail's e^(-gap/2kT)."""
+    w = synth.gapped_workload(2)
+    H = otb.hamiltonian(w.positions(), None, synth.GAPPED_MODEL)
+    say(f"case fermi low T N={w.n_orb}")
+    P = osp2.sp2(H, w.n_occ).D
+    D, mu, passes = ctx.sp2_fermi_density_matrix(to_dev(H), w.n_occ, 0.02, 20, tol=1e-9)
+    D = D.cpu().numpy()
+    err = float(np.abs(D - P).max())
+    say(f"  mu {mu:.6f}, passes {passes}, max|D - projector| {err:.2e}")
+    assert err < 1e-9
+
+
+def test_fermi_rejects_bad_arguments(ctx):
+    import paper_1203_6836_amd as p
+    w, H = lattice((2, 2, 2), 1)
+    Hd = to_dev(H)
+    say("case fermi argument checks")
+    for kw in ({"kT": 0.0, "n_steps": 12}, {"kT": 0.5, "n_steps": 0}, {"kT": 0.5, "n_steps": 2},
+               {"kT": 0.5, "n_steps": 12, "max_newton": 0}):
+        with pytest.raises(p.Sp2Error) as ei:
+            ctx.sp2_fermi_density_matrix(Hd, w.n_occ, **kw)
+        assert ei.value.status == "EINVAL", kw
+    Hb = H.copy()
+    Hb[0, 1] += 1.0
+    with pytest.raises(p.Sp2Error) as ei:
+        ctx.sp2_fermi_density_matrix(to_dev(Hb), w.n_occ, 0.5, 12)
+    assert ei.value.status == "EINVAL"
+    e_lo = osp2.gershgorin(H)[0]
+    with pytest.raises(p.Sp2Error) as ei:   # one pass from a mu near the bottom of the spectrum
+        ctx.sp2_fermi_density_matrix(Hd, w.n_occ, 0.5, 12, mu=e_lo + 1.0, max_newton=1)
+    assert ei.value.status == "ENOCONV"
+
+
+def test_fermi_full_size_against_definition(ctx):
+    """N = 2048 (512 atoms): the canonical Fermi operator at kT = 0.5 eV with 16
+    steps against the definition (eigendecomposition on the host), and its
+    GEMM rate."""
+    import torch
+    w, H = lattice((8, 8, 8), 7)
+    say(f"case fermi N={w.n_orb}")
+    Hd = to_dev(H)
+    ctx.sp2_fermi_density_matrix(Hd, w.n_occ, 0.5, 16, tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    D, mu, passes = ctx.sp2_fermi_density_matrix(Hd, w.n_occ, 0.5, 16, tol=1e-8)
+    torch.cuda.synchronize()
+    s = time.perf_counter() - t0
+    tf = passes * 16 * 10 * 2.0 * w.n_orb ** 3 / s / 1e12
+    Dd, mu_def, _ = fermi.fermi_density(H, w.n_occ, 0.5)
+    err = float(np.abs(D.cpu().numpy() - Dd).max())
+    say(f"  {s * 1e3:.1f} ms, {passes} passes, {tf:.1f} TF/s in GEMMs, mu - mu_def {mu - mu_def:+.1e}, "
+        f"max|D - definition| {err:.2e}")
+    assert err < 1e-7 and abs(mu - mu_def) < 1e-6
