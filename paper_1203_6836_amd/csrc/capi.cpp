@@ -701,6 +701,12 @@ extern "C" sp2_status sp2_fermi_density_matrix(sp2_ctx* c, int N, const double* 
     c->nocap = nb;
     double* part = c->nobuf + 5 * n2;
     double* res = part + 2 * kFermiBlocks;
+    // the Gershgorin pass writes a (min, max) pair per 4 rows into c->part
+    size_t pbytes = c->partcap * sizeof(double);
+    if ((s = grow(c, (void**)&c->part, &pbytes, std::max<size_t>((size_t)(N + 3) / 4 * 2, 1024) * sizeof(double))) !=
+        SP2_OK)
+        return s;
+    c->partcap = pbytes / sizeof(double);
     hipStream_t st = c->stream;
     // validity of H and its Gershgorin interval
     int ns = 0, nchk = 0;
