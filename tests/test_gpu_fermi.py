@@ -97,16 +97,16 @@ def test_fermi_rejects_bad_arguments(ctx):
                {"kT": 0.5, "n_steps": 12, "max_newton": 0}):
         with pytest.raises(p.Sp2Error) as ei:
             ctx.sp2_fermi_density_matrix(Hd, w.n_occ, **kw)
-        assert ei.value.status == "EINVAL", kw
+        assert ei.value.status == p.SP2_EINVAL, kw
     Hb = H.copy()
     Hb[0, 1] += 1.0
     with pytest.raises(p.Sp2Error) as ei:
         ctx.sp2_fermi_density_matrix(to_dev(Hb), w.n_occ, 0.5, 12)
-    assert ei.value.status == "EINVAL"
+    assert ei.value.status == p.SP2_EINVAL
     e_lo = osp2.gershgorin(H)[0]
     with pytest.raises(p.Sp2Error) as ei:   # one pass from a mu near the bottom of the spectrum
         ctx.sp2_fermi_density_matrix(Hd, w.n_occ, 0.5, 12, mu=e_lo + 1.0, max_newton=1)
-    assert ei.value.status == "ENOCONV"
+    assert ei.value.status == p.SP2_ENOCONV
 
 
 def test_fermi_full_size_against_definition(ctx):
