@@ -329,6 +329,34 @@ def nonorthogonal(ctx):
     return out
 
 
+def finite_temperature(ctx, dims=(8, 8, 16), kT=0.5, n_steps=16):
+    """The Fermi operator at kT = 0.5 eV on a 1024-atom lattice (N = 4096) by
+    the recursive expansion with canonical mu: time per solve, Newton passes,
+    and the FP64 GEMM rate (10 products of N^3 multiply-adds per step)."""
+    import torch
+
+    import synth
+
+    w = synth.small_workload(dims, 7)
+    xyz = torch.from_numpy(w.positions()).cuda()
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, xyz)
+    N = w.n_orb
+    log(f"finite temperature: N={N}, kT={kT} eV, {n_steps} steps")
+    D = torch.empty_like(H)
+    ctx.sp2_fermi_density_matrix(H, w.n_occ, kT, n_steps, tol=1e-8, D_out=D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, mu, passes = ctx.sp2_fermi_density_matrix(H, w.n_occ, kT, n_steps, tol=1e-8, D_out=D)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    tf = passes * n_steps * 10 * 2.0 * N ** 3 / (ms * 1e-3) / 1e12
+    out = {"n": N, "kT_eV": kT, "n_steps": n_steps, "ms_per_solve": round(ms, 1), "newton_passes": passes,
+           "mu": mu, "gemm_tflops": round(tf, 1), "gemm_frac_of_fp64_peak": round(tf / PEAK["fp64"], 3),
+           "trace_minus_nocc": float(torch.trace(D)) - w.n_occ}
+    log(f"  {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,6 +373,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the counter-calibration kernels and one solve per precision "
                          "(for rocprofv3 --pmc passes); prints no JSON")
+    ap.add_argument("--only", choices=["finite_temperature", "nonorthogonal"],
+                    help="run only this leg and print its result as one JSON line (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -357,6 +387,12 @@ def main():
     import paper_1203_6836_amd as p
     import synth
 
+    if args.only:
+        ctx = p.Context(0)
+        print(json.dumps({args.only: {"finite_temperature": finite_temperature,
+                                      "nonorthogonal": nonorthogonal}[args.only](ctx)}), flush=True)
+        ctx.close()
+        return
     w = synth.MIXED
     N, nocc = w.n_orb, w.n_occ
     ctx = p.Context(0)
@@ -505,6 +541,7 @@ def main():
         torch.cuda.empty_cache()
         out["thresholded_scaling"] = thresholded_scaling(ctx)
         out["nonorthogonal"] = nonorthogonal(ctx)
+        out["finite_temperature"] = finite_temperature(ctx)
     if not args.no_cpu:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(H.cpu().numpy(), nocc)
