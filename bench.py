@@ -332,7 +332,7 @@ def nonorthogonal(ctx):
 def finite_temperature(ctx, dims=(8, 8, 16), kT=0.5, n_steps=16):
     """The Fermi operator at kT = 0.5 eV on a 1024-atom lattice (N = 4096) by
     the recursive expansion with canonical mu: time per solve, Newton passes,
-    and the FP64 GEMM rate (10 products of N^3 multiply-adds per step)."""
+    and the FP64 GEMM rate (N^3 multiply-adds per product made)."""
     import torch
 
     import synth
@@ -349,8 +349,10 @@ def finite_temperature(ctx, dims=(8, 8, 16), kT=0.5, n_steps=16):
     _, mu, passes = ctx.sp2_fermi_density_matrix(H, w.n_occ, kT, n_steps, tol=1e-8, D_out=D)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
-    tf = passes * n_steps * 10 * 2.0 * N ** 3 / (ms * 1e-3) / 1e12
+    prods = ctx.last_fermi_products
+    tf = prods * 2.0 * N ** 3 / (ms * 1e-3) / 1e12
     out = {"n": N, "kT_eV": kT, "n_steps": n_steps, "ms_per_solve": round(ms, 1), "newton_passes": passes,
+           "products": prods,
            "mu": mu, "gemm_tflops": round(tf, 1), "gemm_frac_of_fp64_peak": round(tf / PEAK["fp64"], 3),
            "trace_minus_nocc": float(torch.trace(D)) - w.n_occ}
     log(f"  {out}")

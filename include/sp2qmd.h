@@ -223,11 +223,15 @@ sp2_status sp2_mulliken_overlap(sp2_ctx *ctx, int n_atoms, const double *D, cons
  * symmetric; the inverse by Newton-Schulz in FP64, GEMMs in rocBLAS).  Its
  * exponent carries a relative error of about (beta |e - mu| / 2^n_steps)^2
  * / 12 per eigenvalue e; FP64 rounding sets a floor near 1e-11 for
- * n_steps >= 16.  H: N x N device, row-major, finite and symmetric (EINVAL
- * otherwise).  kT in the units of H (> 0).  n_steps in [1, 60] with
- * beta |e - mu| <= 2^(n_steps + 1) over H's Gershgorin interval, and over
- * the bracket below when mu is solved for (EINVAL otherwise).  max_newton == 0: *mu (in) is the fixed chemical potential and
- * D_out = X_n at it.  max_newton > 0: canonical mu with |Tr D - n_occ| < tol
+ * n_steps >= 16.
+ *
+ * H: N x N device, row-major, finite and symmetric (EINVAL otherwise).  kT in
+ * the units of H (> 0).  n_steps in [1, 60] with beta |e - mu| <=
+ * 2^(n_steps + 1) over H's Gershgorin interval, and over the bracket below
+ * when mu is solved for (EINVAL otherwise).
+ *
+ * max_newton == 0: *mu (in) is the fixed chemical potential and D_out = X_n
+ * at it.  max_newton > 0: canonical mu with |Tr D - n_occ| < tol
  * (0 < n_occ < N, fractional allowed) by Newton steps with
  * dTr/dmu ~ beta Tr[D (I - D)], safeguarded by bisection of the bracket
  * [e_min - 40 kT, e_max + 40 kT] (Gershgorin bounds; a step leaving it
@@ -235,12 +239,17 @@ sp2_status sp2_mulliken_overlap(sp2_ctx *ctx, int n_atoms, const double *D, cons
  * interval; *mu (out) is the result.  X_0 resolves mu to about
  * 2^(n_steps + 2) 2^-54 kT, so tol below dTr/dmu times that is not reached.
  * ENOCONV if max_newton passes end short of tol or mu stops changing (D_out,
- * *mu then hold the last pass).  D_out: N x N device, may not alias H.  newton_iterations
- * (may be NULL): passes made.  N <= 32768 (five N x N FP64 work matrices).
- * Blocks the host until D_out is written. */
+ * *mu then hold the last pass).
+ *
+ * D_out: N x N device, may not alias H.  newton_iterations (may be NULL):
+ * passes made.  products (may be NULL): N x N FP64 matrix products made over
+ * all passes (2 per step plus 2 per Newton-Schulz update; the updates per
+ * inverse follow from a bound on X's spectrum, fewer in the first steps,
+ * where X is near I/2).  N <= 32768 (five N x N FP64 work matrices).  Blocks
+ * the host until D_out is written. */
 sp2_status sp2_fermi_density_matrix(sp2_ctx *ctx, int N, const double *H, double n_occ, double kT,
                                     int n_steps, int max_newton, double tol, double *mu,
-                                    double *D_out, int *newton_iterations);
+                                    double *D_out, int *newton_iterations, long long *products);
 
 /* ---------------------------------------------------------------------
  * Tight-binding model, forces and XL-BOMD

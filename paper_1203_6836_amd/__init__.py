@@ -108,7 +108,7 @@ _SIGS = {
                                         ctypes.POINTER(Sp2Stats), ctypes.POINTER(_I)]),
     "sp2_mulliken_overlap": (_I, [_P, _I, _P, _P, ctypes.c_double, _P]),
     "sp2_fermi_density_matrix": (_I, [_P, _I, _P, _D, _D, _I, _I, _D, ctypes.POINTER(_D), _P,
-                                      ctypes.POINTER(_I)]),
+                                      ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_longlong)]),
     "tb_overlap": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P]),
     "tb_hamiltonian_nonorth": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P]),
     "tb_forces_nonorth": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P, _P,
@@ -273,7 +273,8 @@ class Context:
 
         max_newton == 0 keeps mu fixed (it must be given); otherwise mu is the
         canonical chemical potential, Newton from mu (None: the middle of the
-        Gershgorin interval).
+        Gershgorin interval).  The N x N products the call made are left in
+        ``self.last_fermi_products``.
         """
         import torch
         N = H.shape[0]
@@ -283,9 +284,11 @@ class Context:
             D_out = torch.empty_like(H)
         m = _D(float("nan") if mu is None else float(mu))
         its = _I(0)
+        prods = ctypes.c_longlong(0)
         st = lib().sp2_fermi_density_matrix(self._h, N, _ptr(H), float(n_occ), float(kT), int(n_steps),
                                             int(max_newton), float(tol), ctypes.byref(m), _ptr(D_out),
-                                            ctypes.byref(its))
+                                            ctypes.byref(its), ctypes.byref(prods))
+        self.last_fermi_products = prods.value
         self._check(st, "sp2_fermi_density_matrix")
         return D_out, m.value, its.value
 

@@ -650,9 +650,12 @@ extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double
 // One pass of the recursive Fermi-operator expansion at chemical potential mu:
 // X_0 = I/2 - beta (H - mu I) / 2^(n+2), then n steps
 // X_{k+1} = X_k^2 (X_k^2 + (I - X_k)^2)^(-1), each made exactly symmetric.
+// delta0 bounds |x - 1/2| over the spectrum of X_0 (from the Gershgorin
+// interval); under the step, a bound d becomes 2 d / (1 + 4 d^2), which sets
+// the Newton-Schulz start and update count of each inverse.
 // buf holds five N x N matrices; returns the one holding X_n.
-static sp2_status fermi_pass(sp2_ctx* c, int N, const double* H, double mu, double beta, int n_steps, double* buf,
-                             double** Xn) {
+static sp2_status fermi_pass(sp2_ctx* c, int N, const double* H, double mu, double beta, int n_steps, double delta0,
+                             double* buf, double** Xn, long long* products) {
     const size_t n2 = (size_t)N * N;
     double* X = buf;
     double* X2 = buf + n2;
@@ -662,11 +665,16 @@ static sp2_status fermi_pass(sp2_ctx* c, int N, const double* H, double mu, doub
     hipStream_t st = c->stream;
     sp2_status s;
     HIPCHK(c, launch_fermi_init(H, N, mu, beta / std::ldexp(1.0, n_steps + 2), X, st));
+    double delta = delta0;
     for (int k = 0; k < n_steps; ++k) {
+        const double db = std::min(0.5, delta * 1.01 + 1e-9);   // margin for rounding
+        const double rho = 2.0 * db * db / (1.0 + 2.0 * db * db);
+        int updates = 0;   // error rho^2 after Y_1, squared by each update
+        for (double err = rho * rho; err > kFermiInvErr && updates < kFermiInvUpdates; err *= err) ++updates;
         if ((s = gemm_rm(c, N, X, X, X2)) != SP2_OK) return s;
-        HIPCHK(c, launch_fermi_a(X2, X, N, A, Y, st));        // A = X^2 + (I - X)^2, Y = Y_1
+        HIPCHK(c, launch_fermi_a(X2, X, N, 2.0 / (1.0 + 2.0 * db * db), A, Y, st));   // A, Y_1
         double* W = X;                                        // X is free until X_{k+1}
-        for (int j = 0; j < kFermiInvUpdates; ++j) {
+        for (int j = 0; j < updates; ++j) {
             if ((s = gemm_rm(c, N, A, Y, R)) != SP2_OK) return s;
             HIPCHK(c, launch_two_minus(R, N, st));
             if ((s = gemm_rm(c, N, Y, R, W)) != SP2_OK) return s;   // Y <- Y (2 I - A Y)
@@ -675,6 +683,8 @@ static sp2_status fermi_pass(sp2_ctx* c, int N, const double* H, double mu, doub
         if ((s = gemm_rm(c, N, X2, Y, W)) != SP2_OK) return s;      // X_{k+1} = X_k^2 A^(-1)
         HIPCHK(c, launch_symmetrize(W, N, st));
         X = W;
+        *products += 2 + 2 * updates;
+        delta = std::min(0.5, 2.0 * delta / (1.0 + 4.0 * delta * delta));
     }
     *Xn = X;
     return SP2_OK;
@@ -682,9 +692,11 @@ static sp2_status fermi_pass(sp2_ctx* c, int N, const double* H, double mu, doub
 
 extern "C" sp2_status sp2_fermi_density_matrix(sp2_ctx* c, int N, const double* H, double n_occ, double kT,
                                                 int n_steps, int max_newton, double tol, double* mu,
-                                                double* D_out, int* newton_iterations) {
+                                                double* D_out, int* newton_iterations, long long* products) {
     if (!c) return SP2_EINVAL;
     if (newton_iterations) *newton_iterations = 0;
+    if (products) *products = 0;
+    long long nprod = 0;
     if (N < 1 || N > 32768 || !H || !D_out || !mu) return fail(c, SP2_EINVAL, "bad Fermi-operator arguments");
     if (!(kT > 0.0) || !std::isfinite(kT)) return fail(c, SP2_EINVAL, "need a finite kT > 0");
     if (n_steps < 1 || n_steps > 60) return fail(c, SP2_EINVAL, "need 1 <= n_steps <= 60");
@@ -730,8 +742,10 @@ extern "C" sp2_status sp2_fermi_density_matrix(sp2_ctx* c, int N, const double* 
     const int evals = max_newton == 0 ? 1 : max_newton;
     for (int it = 0; it < evals; ++it) {
         double* X = nullptr;
-        if ((s = fermi_pass(c, N, H, m, beta, n_steps, c->nobuf, &X)) != SP2_OK) return s;
+        const double delta0 = beta * std::max(e_hi - m, m - e_lo) / std::ldexp(1.0, n_steps + 2);
+        if ((s = fermi_pass(c, N, H, m, beta, n_steps, delta0, c->nobuf, &X, &nprod)) != SP2_OK) return s;
         if (newton_iterations) *newton_iterations = it + 1;
+        if (products) *products = nprod;
         if (max_newton == 0) {
             HIPCHK(c, hipMemcpyAsync(D_out, X, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipStreamSynchronize(st));

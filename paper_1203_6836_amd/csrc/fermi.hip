@@ -3,9 +3,9 @@
 // and n steps X_{k+1} = X_k^2 (X_k^2 + (I - X_k)^2)^(-1) give
 // (exp(beta (H - mu I)) + 1)^(-1) (the ratio (I - X)/X squares each step).
 // The host runs the GEMMs; these kernels form X_0, A = X^2 + (I - X)^2, the
-// Newton-Schulz steps of A^(-1) (A = I - 2 X (I - X) has its spectrum in
-// [1/2, 1] while X has its own in [0, 1]), and the trace and Frobenius sums of
-// the Newton step on mu.
+// Newton-Schulz steps of A^(-1) (A = I/2 + 2 (X - I/2)^2 has its spectrum in
+// [1/2, 1] while X has its own in [0, 1], and nearer 1/2 in the first steps),
+// and the trace and Frobenius sums of the Newton step on mu.
 #include "fermi_internal.h"
 
 namespace sp2 {
@@ -34,13 +34,13 @@ __global__ __launch_bounds__(256) void k_fermi_init(const double* __restrict__ H
 }
 
 __global__ __launch_bounds__(256) void k_fermi_a(const double* __restrict__ X2, const double* __restrict__ X, int N,
-                                                 double* __restrict__ A, double* __restrict__ Y) {
+                                                 double c, double* __restrict__ A, double* __restrict__ Y) {
     const size_t n2 = (size_t)N * N;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 256) {
         const double d = (e / N == e % N) ? 1.0 : 0.0;
         const double a = 2.0 * X2[e] - 2.0 * X[e] + d;
         A[e] = a;
-        Y[e] = kFermiY0 * (2.0 * d - kFermiY0 * a);
+        Y[e] = c * (2.0 * d - c * a);
     }
 }
 
@@ -91,8 +91,8 @@ hipError_t launch_fermi_init(const double* H, int N, double mu, double scale, do
     hipLaunchKernelGGL(k_fermi_init, dim3(grid_elem(N)), dim3(256), 0, s, H, N, mu, scale, X);
     return hipGetLastError();
 }
-hipError_t launch_fermi_a(const double* X2, const double* X, int N, double* A, double* Y, hipStream_t s) {
-    hipLaunchKernelGGL(k_fermi_a, dim3(grid_elem(N)), dim3(256), 0, s, X2, X, N, A, Y);
+hipError_t launch_fermi_a(const double* X2, const double* X, int N, double c, double* A, double* Y, hipStream_t s) {
+    hipLaunchKernelGGL(k_fermi_a, dim3(grid_elem(N)), dim3(256), 0, s, X2, X, N, c, A, Y);
     return hipGetLastError();
 }
 hipError_t launch_two_minus(double* R, int N, hipStream_t s) {

@@ -9,15 +9,16 @@ namespace sp2 {
 constexpr int kFermiBlocks = 1024;
 // X = I/2 - (H - mu I) * scale, scale = beta / 2^(n+2).
 hipError_t launch_fermi_init(const double* H, int N, double mu, double scale, double* X, hipStream_t s);
-// Newton-Schulz start of A^(-1): Y_0 = (4/3) I, the best multiple of I for a
-// spectrum in [1/2, 1] (|1 - 4 a / 3| <= 1/3); the first update
-// Y_1 = Y_0 (2 I - A Y_0) is formed here without a product.
-constexpr double kFermiY0 = 4.0 / 3.0;
-// Updates after Y_1 (two products each): the error I - A Y_j = (I - A Y_0)^(2^j)
-// is at most 3^(-32) ~ 5e-16 after j = 5.
-constexpr int kFermiInvUpdates = 4;
-// A = 2 X2 - 2 X + I (= X^2 + (I - X)^2), Y = Y_0 (2 I - Y_0 A).
-hipError_t launch_fermi_a(const double* X2, const double* X, int N, double* A, double* Y, hipStream_t s);
+// Newton-Schulz inverse of A = X^2 + (I - X)^2 = I/2 + 2 (X - I/2)^2: with
+// |x - 1/2| <= delta over the spectrum of X, A's spectrum lies in
+// [1/2, 1/2 + 2 delta^2]; the start Y_0 = c I, c = 2 / (1 + 2 delta^2), leaves
+// I - A Y_0 with norm rho = 2 delta^2 / (1 + 2 delta^2) <= 1/3, and after j
+// updates the error is rho^(2^j).  The first update Y_1 = Y_0 (2 I - A Y_0) is
+// formed without a product; the host adds updates until rho^(2^j) <= kFermiInvErr.
+constexpr double kFermiInvErr = 5.5e-16;   // 3^(-32): four updates after Y_1 at delta = 1/2
+constexpr int kFermiInvUpdates = 4;        // most updates after Y_1
+// A = 2 X2 - 2 X + I, Y = c (2 I - c A).
+hipError_t launch_fermi_a(const double* X2, const double* X, int N, double c, double* A, double* Y, hipStream_t s);
 // R <- 2 I - R in place.
 hipError_t launch_two_minus(double* R, int N, hipStream_t s);
 // part[2 b], part[2 b + 1] = block b's sums of X_ii and X_ij^2 (fixed order).

@@ -123,9 +123,11 @@ def test_fermi_full_size_against_definition(ctx):
     D, mu, passes = ctx.sp2_fermi_density_matrix(Hd, w.n_occ, 0.5, 16, tol=1e-8)
     torch.cuda.synchronize()
     s = time.perf_counter() - t0
-    tf = passes * 16 * 10 * 2.0 * w.n_orb ** 3 / s / 1e12
+    prods = ctx.last_fermi_products
+    assert passes * 2 * 16 <= prods <= passes * 10 * 16
+    tf = prods * 2.0 * w.n_orb ** 3 / s / 1e12
     Dd, mu_def, _ = fermi.fermi_density(H, w.n_occ, 0.5)
     err = float(np.abs(D.cpu().numpy() - Dd).max())
-    say(f"  {s * 1e3:.1f} ms, {passes} passes, {tf:.1f} TF/s in GEMMs, mu - mu_def {mu - mu_def:+.1e}, "
+    say(f"  {s * 1e3:.1f} ms, {passes} passes, {prods} products, {tf:.1f} TF/s in GEMMs, mu - mu_def {mu - mu_def:+.1e}, "
         f"max|D - definition| {err:.2e}")
     assert err < 1e-7 and abs(mu - mu_def) < 1e-6
