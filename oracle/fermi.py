@@ -14,6 +14,12 @@ method without printing it, and leaves mu open):
   squares at every step and starts at (I/2 + y)/(I/2 - y) ~ exp(4y), so X_n
   approaches (exp(beta (H - mu I)) + 1)^(-1): its exponent carries a relative
   error of about (4y)^2 / 12, i.e. (beta |e - mu| / 2^n)^2 / 12;
+* energy at T_e > 0: the electronic entropy of the occupations f_i (the
+  eigenvalues of D), S = -2 k_B sum_i [f_i ln f_i + (1 - f_i) ln(1 - f_i)]
+  (Eq. Entropy), and the free energy A = U(R; n) - T_e S with U as at T_e = 0
+  evaluated with the Fermi D.  D makes 2 Tr[D H[n]] - T_e S stationary at
+  fixed N, so -dA/dR at constant n is the T_e = 0 force expression with the
+  Fermi D (pinned by finite differences);
 * mu for the recursion: Tr X_n grows monotonically with mu, so mu is solved
   by Newton steps on Tr X_n = N_occ with d Tr X_n / d mu ~ beta Tr[X_n (I -
   X_n)] (the derivative of the Fermi function), safeguarded by bisection: the
@@ -27,7 +33,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import sp2
+from . import observables, sp2, tb
 
 KB_EV_PER_K = 8.617333262e-5
 
@@ -92,3 +98,20 @@ def recursive_fermi_canonical(H, n_occ, kT, n_steps, tol=1e-10, max_newton=100):
         step = mu - (t - n_occ) / d if d > 0.0 else np.nan
         mu = step if lo < step < hi else 0.5 * (lo + hi)
     raise RuntimeError("Newton on mu did not converge")
+
+
+def entropy(f):
+    """S / k_B of occupations f (Eq. Entropy; the factor 2 counts spin)."""
+    f = np.asarray(f, dtype=np.float64)
+    s = np.zeros_like(f)
+    inner = (f > 0.0) & (f < 1.0)
+    g = f[inner]
+    s[inner] = g * np.log(g) + (1.0 - g) * np.log1p(-g)
+    return -2.0 * float(s.sum())
+
+
+def free_energy(pos, n, m, n_occ, kT):
+    """(A, D, mu): A = U(R; n) - kT S / k_B with D the canonical Fermi operator of H[n]."""
+    H = tb.hamiltonian(pos, n, m)
+    D, mu, f = fermi_density(H, n_occ, kT)
+    return observables.potential_energy(pos, n, D, m) - kT * entropy(f), D, mu

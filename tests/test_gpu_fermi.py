@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import fermi, sp2 as osp2, tb as otb
+from oracle import fermi, observables, sp2 as osp2, tb as otb
 
 pytestmark = pytest.mark.gpu
 
@@ -131,3 +131,30 @@ def test_fermi_full_size_against_definition(ctx):
     say(f"  {s * 1e3:.1f} ms, {passes} passes, {prods} products, {tf:.1f} TF/s in GEMMs, mu - mu_def {mu - mu_def:+.1e}, "
         f"max|D - definition| {err:.2e}")
     assert err < 1e-7 and abs(mu - mu_def) < 1e-6
+
+
+def test_finite_temperature_forces_match_oracle(ctx):
+    """Forces and U at constant n with the Fermi D (kT = 0.5 eV): the GPU's
+    Fermi operator fed to the GPU's force kernel against the oracle's
+    definition and force expression (-dA/dR, A = U - T_e S, by the oracle's
+    finite-difference pin)."""
+    m = synth.MD_MODEL
+    dims = (3, 3, 3)
+    pos = synth.lattice_positions(dims, seed=21)
+    nat = len(pos)
+    n = np.random.default_rng(5).uniform(-0.2, 0.2, nat)
+    n_occ = 2 * nat
+    say(f"case fermi forces N={4 * nat} kT=0.5")
+    A, Dd, mu_d = fermi.free_energy(pos, n, m, n_occ, 0.5)
+    F_ref = observables.forces(pos, n, Dd, m)
+    U_ref = observables.potential_energy(pos, n, Dd, m)
+    xyz, nd = to_dev(pos), to_dev(n)
+    H = ctx.tb_hamiltonian(m, xyz, nd)
+    D, mu, _ = ctx.sp2_fermi_density_matrix(H, n_occ, 0.5, 16, tol=1e-9)
+    q = ctx.sp2_mulliken(D, nat)
+    F, U = ctx.tb_forces(m, xyz, D, q, nd)
+    dF = float(np.abs(F.cpu().numpy() - F_ref).max())
+    say(f"  mu {mu:.10f} (definition {mu_d:.10f}), max|dF| {dF:.2e} (max|F| {np.abs(F_ref).max():.1f}), "
+        f"dU {U - U_ref:+.2e}")
+    assert abs(mu - mu_d) < 1e-8
+    assert dF < 1e-8 and abs(U - U_ref) < 1e-8

@@ -62,3 +62,40 @@ def test_canonical_recursion(system):
     assert mu_x == pytest.approx(mu, abs=1e-7)
     assert np.abs(X - D).max() < 1e-8
     assert its < 20
+
+
+def test_entropy_limits():
+    assert fermi.entropy([0.0, 1.0, 1.0, 0.0]) == 0.0
+    assert fermi.entropy(np.full(6, 0.5)) == pytest.approx(2 * 6 * np.log(2.0), rel=1e-15)
+    # symmetric under f -> 1 - f, and positive
+    f = np.array([0.1, 0.3, 0.8, 0.999])
+    assert fermi.entropy(f) == pytest.approx(fermi.entropy(1.0 - f), rel=1e-14)
+    assert fermi.entropy(f) > 0.0
+
+
+def test_finite_temperature_forces_are_gradient_of_free_energy():
+    """At T_e > 0 the constant-n force expression with the Fermi D is -dA/dR,
+    A = U - T_e S, mu re-solved at every geometry (central differences)."""
+    from oracle import observables
+    m = synth.MD_MODEL.with_(pair_a=5.0)
+    pos = synth.lattice_positions((2, 2, 2), seed=21)
+    n_occ = 2 * len(pos)
+    n = np.array([0.3, -0.1, 0.05, -0.2, 0.1, -0.15, 0.0, 0.0])
+    kT = 0.5
+    _, D, _ = fermi.free_energy(pos, n, m, n_occ, kT)
+    F = observables.forces(pos, n, D, m)
+    h = 1e-4
+    for k in range(len(pos)):
+        for a in range(3):
+            p, q = pos.copy(), pos.copy()
+            p[k, a] += h
+            q[k, a] -= h
+            fd = -(fermi.free_energy(p, n, m, n_occ, kT)[0] - fermi.free_energy(q, n, m, n_occ, kT)[0]) / (2 * h)
+            assert F[k, a] == pytest.approx(fd, rel=1e-6, abs=1e-7)
+    # without the entropy term the same differences miss the force
+    def U(pp):
+        return observables.potential_energy(pp, n, fermi.free_energy(pp, n, m, n_occ, kT)[1], m)
+    p, q = pos.copy(), pos.copy()
+    p[0, 0] += h
+    q[0, 0] -= h
+    assert abs(-(U(p) - U(q)) / (2 * h) - F[0, 0]) > 1e-4
