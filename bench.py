@@ -351,10 +351,14 @@ def finite_temperature(ctx, dims=(8, 8, 16), kT=0.5, n_steps=16):
     ms = (time.perf_counter() - t0) * 1e3
     prods = ctx.last_fermi_products
     tf = prods * 2.0 * N ** 3 / (ms * 1e-3) / 1e12
+    t0 = time.perf_counter()
+    S, coefs = ctx.sp2_fermi_entropy(H, mu, kT)
+    ms_s = (time.perf_counter() - t0) * 1e3
     out = {"n": N, "kT_eV": kT, "n_steps": n_steps, "ms_per_solve": round(ms, 1), "newton_passes": passes,
            "products": prods,
            "mu": mu, "gemm_tflops": round(tf, 1), "gemm_frac_of_fp64_peak": round(tf / PEAK["fp64"], 3),
-           "trace_minus_nocc": float(torch.trace(D)) - w.n_occ}
+           "trace_minus_nocc": float(torch.trace(D)) - w.n_occ,
+           "entropy_kB": S, "entropy_coefficients": coefs, "entropy_ms": round(ms_s, 1)}
     log(f"  {out}")
     return out
 

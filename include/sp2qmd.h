@@ -251,6 +251,22 @@ sp2_status sp2_fermi_density_matrix(sp2_ctx *ctx, int N, const double *H, double
                                     int n_steps, int max_newton, double tol, double *mu,
                                     double *D_out, int *newton_iterations, long long *products);
 
+/* Electronic entropy (Eq. Entropy) in units of k_B:
+ * S = -2 sum_i [f_i ln f_i + (1 - f_i) ln(1 - f_i)], f_i = (exp((e_i - mu)
+ * / kT) + 1)^(-1) over the eigenvalues e_i of H (the occupations of the
+ * Fermi operator at mu; the factor 2 counts spin).  Computed without
+ * eigenvalues as Tr s((H - mu I) / kT) by a Chebyshev expansion over H's
+ * Gershgorin interval: coefficients on the host (8192 Chebyshev-Gauss nodes,
+ * kept while above 1e-15), moments Tr T_k from about half as many N x N
+ * FP64 products as coefficients (rocBLAS).  H: N x N device, finite and
+ * symmetric (EINVAL otherwise); mu finite; kT > 0 in the units of H; EINVAL
+ * when more than about 4000 coefficients would be needed (the count grows as
+ * the Gershgorin width over kT: about 1000 at kT = 0.5 and 2200 at 0.25 on
+ * the sp lattices, whose interval is about 30 eV wide).  S_out: host.  moments (may be NULL): the
+ * coefficients used.  N <= 32768.  Blocks the host until done. */
+sp2_status sp2_fermi_entropy(sp2_ctx *ctx, int N, const double *H, double mu, double kT, double *S_out,
+                             int *moments);
+
 /* ---------------------------------------------------------------------
  * Tight-binding model, forces and XL-BOMD
  * ------------------------------------------------------------------- */

@@ -107,6 +107,7 @@ _SIGS = {
     "sp2_density_matrix_nonorth": (_I, [_P, _I, _P, _P, _I, ctypes.POINTER(Sp2Options), _P,
                                         ctypes.POINTER(Sp2Stats), ctypes.POINTER(_I)]),
     "sp2_mulliken_overlap": (_I, [_P, _I, _P, _P, ctypes.c_double, _P]),
+    "sp2_fermi_entropy": (_I, [_P, _I, _P, _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_I)]),
     "sp2_fermi_density_matrix": (_I, [_P, _I, _P, _D, _D, _I, _I, _D, ctypes.POINTER(_D), _P,
                                       ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_longlong)]),
     "tb_overlap": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P]),
@@ -291,6 +292,17 @@ class Context:
         self.last_fermi_products = prods.value
         self._check(st, "sp2_fermi_density_matrix")
         return D_out, m.value, its.value
+
+    def sp2_fermi_entropy(self, H, mu: float, kT: float):
+        """(S / k_B, coefficients): -2 sum_i [f ln f + (1 - f) ln(1 - f)] of the Fermi occupations at mu."""
+        N = H.shape[0]
+        if H.shape != (N, N):
+            raise ValueError("H must be N x N")
+        S = _D(0.0)
+        m = _I(0)
+        self._check(lib().sp2_fermi_entropy(self._h, N, _ptr(H), float(mu), float(kT), ctypes.byref(S),
+                                            ctypes.byref(m)), "sp2_fermi_entropy")
+        return S.value, m.value
 
     def tb_overlap(self, model, xyz, S_out=None):
         """S of the non-orthogonal variant (model.overlap_s0, model.overlap_lam)."""

@@ -782,6 +782,99 @@ extern "C" sp2_status sp2_fermi_density_matrix(sp2_ctx* c, int N, const double* 
     return SP2_OK;
 }
 
+// Electronic entropy S / k_B = -2 sum_i [f_i ln f_i + (1 - f_i) ln(1 - f_i)]
+// (Eq. Entropy) of the Fermi occupations f_i = (exp(beta (e_i - mu)) + 1)^(-1)
+// of H's eigenvalues, as Tr s(beta (H - mu I)) expanded in Chebyshev
+// polynomials of Ht = (H - c I) / w over the Gershgorin interval [c - w, c + w].
+// s(x) = ln(1 + e^-|x|) + |x| / (1 + e^|x|) is analytic within pi / beta of the
+// real axis, so the coefficients fall geometrically.  The moments Tr T_k(Ht)
+// come from T_0 .. T_K alone: Tr T_2k = 2 <T_k, T_k> - N and
+// Tr T_(2k+1) = 2 <T_(k+1), T_k> - Tr T_1, one product per k.
+constexpr int kEntropyNodes = 8192;   // Chebyshev-Gauss nodes of the coefficients
+constexpr double kEntropyCoefTol = 1e-15;
+
+static double fermi_entropy_term(double x) {   // s(x) per state, spin not counted
+    const double a = std::fabs(x);
+    const double e = std::exp(-a);
+    return std::log1p(e) + a * e / (1.0 + e);
+}
+
+extern "C" sp2_status sp2_fermi_entropy(sp2_ctx* c, int N, const double* H, double mu, double kT, double* S_out,
+                                         int* moments) {
+    if (!c) return SP2_EINVAL;
+    if (moments) *moments = 0;
+    if (N < 1 || N > 32768 || !H || !S_out) return fail(c, SP2_EINVAL, "bad entropy arguments");
+    if (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu)) return fail(c, SP2_EINVAL, "need finite mu and kT > 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    sp2_status s;
+    if ((s = ensure_blas(c)) != SP2_OK) return s;
+    const size_t n2 = (size_t)N * N;
+    const int kmax = kEntropyNodes / 2;
+    size_t nb = c->nocap;
+    if ((s = grow(c, (void**)&c->nobuf, &nb, (3 * n2 + kmax + 8) * sizeof(double))) != SP2_OK) return s;
+    c->nocap = nb;
+    size_t pbytes = c->partcap * sizeof(double);
+    if ((s = grow(c, (void**)&c->part, &pbytes,
+                  std::max<size_t>({(size_t)(N + 3) / 4 * 2, (size_t)kDotBlocks, 1024}) * sizeof(double))) != SP2_OK)
+        return s;
+    c->partcap = pbytes / sizeof(double);
+    hipStream_t st = c->stream;
+    int ns = 0, nchk = 0;
+    HIPCHK(c, launch_check_h(H, N, c->chk, &nchk, st));
+    HIPCHK(c, launch_gershgorin(H, N, c->part, &ns, st));
+    HIPCHK(c, launch_bounds(c->part, ns, c->chk, nchk, c->st, st));
+    HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(State), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (c->st_host->done == 5) return fail(c, SP2_EINVAL, "H is not finite and symmetric");
+    const double beta = 1.0 / kT;
+    const double ctr = 0.5 * (c->st_host->eps_min + c->st_host->eps_max);
+    const double w = std::max(0.5 * (c->st_host->eps_max - c->st_host->eps_min) * (1.0 + 1e-12), 1e-300);
+    // coefficients a_k = (2 / M) sum_j s(beta (w t_j + ctr - mu)) cos(k theta_j), t_j = cos theta_j
+    std::vector<double> g(kEntropyNodes), a(kmax);
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < kEntropyNodes; ++j)
+        g[j] = fermi_entropy_term(beta * (w * std::cos(pi * (j + 0.5) / kEntropyNodes) + ctr - mu));
+    int m = 0;
+    for (int k = 0; k < kmax && k < m + 64; ++k) {   // stop after 64 coefficients below the tolerance
+        double acc = 0.0;
+        for (int j = 0; j < kEntropyNodes; ++j) acc += g[j] * std::cos(pi * k * (j + 0.5) / kEntropyNodes);
+        a[k] = 2.0 * acc / kEntropyNodes;
+        if (std::fabs(a[k]) > kEntropyCoefTol) m = k + 1;
+    }
+    if (m + 8 >= kmax)
+        return fail(c, SP2_EINVAL, "kT too small against the spectral width for the entropy's Chebyshev expansion");
+    m = std::max(m, 2);
+    const int K = (m + 1) / 2;   // T_0 .. T_K give the moments 0 .. 2K
+    double* Ht = c->nobuf;
+    double* Tp = Ht + n2;   // T_(k-1)
+    double* Tc = Tp + n2;   // T_k
+    double* mom = Tc + n2;  // <T_k, T_k>, <T_(k+1), T_k> pairs
+    HIPCHK(c, launch_cheb_init(H, N, ctr, 1.0 / w, Ht, Tp, st));   // Tp = T_0 = I
+    HIPCHK(c, hipMemcpyAsync(Tc, Ht, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));   // T_1
+    HIPCHK(c, launch_dot(Tp, Tc, n2, c->part, &ns, mom, st));   // Tr T_1
+    for (int k = 1; k <= K; ++k) {
+        // <T_k, T_k> (moment 2k); then T_(k+1) = 2 Ht T_k - T_(k-1) over T_(k-1)
+        HIPCHK(c, launch_dot(Tc, Tc, n2, c->part, &ns, mom + 2 * k, st));
+        if (k == K) break;
+        if ((s = gemm_rm(c, N, Ht, Tc, Tp, 2.0, -1.0)) != SP2_OK) return s;
+        std::swap(Tp, Tc);
+        HIPCHK(c, launch_dot(Tc, Tp, n2, c->part, &ns, mom + 2 * k + 1, st));   // <T_(k+1), T_k>
+    }
+    std::vector<double> h(2 * K + 1);
+    HIPCHK(c, hipMemcpyAsync(h.data(), mom, (2 * K + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    // moments: mu_0 = N, mu_1 = Tr T_1, mu_2k = 2 <T_k, T_k> - N, mu_(2k+1) = 2 <T_(k+1), T_k> - mu_1
+    double S = 0.5 * a[0] * N;
+    for (int k = 1; k < std::min(m, 2 * K + 1); ++k) {
+        const double mk = k == 1 ? h[0] : (k % 2 == 0 ? 2.0 * h[k] - N : 2.0 * h[k] - h[0]);
+        S += a[k] * mk;
+    }
+    if (!std::isfinite(S)) return fail(c, SP2_EDEVICE, "non-finite entropy");
+    *S_out = 2.0 * S;
+    if (moments) *moments = m;
+    return SP2_OK;
+}
+
 extern "C" sp2_status sp2_mulliken_overlap(sp2_ctx* c, int n_atoms, const double* D, const double* S, double z_val,
                                            double* q_out) {
     if (!c) return SP2_EINVAL;

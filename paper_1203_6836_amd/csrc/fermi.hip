@@ -82,6 +82,16 @@ __global__ __launch_bounds__(256) void k_sum_pairs(const double* __restrict__ pa
     }
 }
 
+__global__ __launch_bounds__(256) void k_cheb_init(const double* __restrict__ H, int N, double c, double inv_w,
+                                                   double* __restrict__ Ht, double* __restrict__ T0) {
+    const size_t n2 = (size_t)N * N;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 256) {
+        const bool d = e / N == e % N;
+        Ht[e] = (H[e] - (d ? c : 0.0)) * inv_w;
+        T0[e] = d ? 1.0 : 0.0;
+    }
+}
+
 static int grid_elem(int N) {
     const size_t g = ((size_t)N * N + 255) / 256;
     return (int)(g < 4096 ? g : 4096);
@@ -97,6 +107,10 @@ hipError_t launch_fermi_a(const double* X2, const double* X, int N, double c, do
 }
 hipError_t launch_two_minus(double* R, int N, hipStream_t s) {
     hipLaunchKernelGGL(k_two_minus, dim3(grid_elem(N)), dim3(256), 0, s, R, N);
+    return hipGetLastError();
+}
+hipError_t launch_cheb_init(const double* H, int N, double c, double inv_w, double* Ht, double* T0, hipStream_t s) {
+    hipLaunchKernelGGL(k_cheb_init, dim3(grid_elem(N)), dim3(256), 0, s, H, N, c, inv_w, Ht, T0);
     return hipGetLastError();
 }
 hipError_t launch_trace_fro(const double* X, int N, double* part, hipStream_t s) {

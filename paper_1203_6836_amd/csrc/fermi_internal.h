@@ -26,4 +26,7 @@ hipError_t launch_trace_fro(const double* X, int N, double* part, hipStream_t s)
 // out[0], out[1] = fixed-order sums of part[2 k], part[2 k + 1], k < n.
 hipError_t launch_sum_pairs(const double* part, int n, double* out, hipStream_t s);
 
+// Chebyshev moments of the entropy: Ht = (H - c I) * inv_w, T0 = I.
+hipError_t launch_cheb_init(const double* H, int N, double c, double inv_w, double* Ht, double* T0, hipStream_t s);
+
 }  // namespace sp2

@@ -158,3 +158,21 @@ def test_finite_temperature_forces_match_oracle(ctx):
         f"dU {U - U_ref:+.2e}")
     assert abs(mu - mu_d) < 1e-8
     assert dF < 1e-8 and abs(U - U_ref) < 1e-8
+
+
+@pytest.mark.parametrize("dims,seed,kT", [((3, 3, 3), 1, 0.5), ((4, 4, 8), 5, 0.25), ((4, 4, 9), 3, 2.0)])
+def test_entropy_matches_definition(ctx, dims, seed, kT):
+    """S / k_B by Chebyshev moments on the GPU against the oracle's entropy of
+    the eigenvalue occupations at the same mu."""
+    import paper_1203_6836_amd as p
+    w, H = lattice(dims, seed)
+    say(f"case fermi entropy N={w.n_orb} kT={kT}")
+    e = np.linalg.eigvalsh(H)
+    mu = fermi.canonical_mu(e, w.n_occ, 1.0 / kT)
+    S_ref = fermi.entropy(fermi.fermi_occupations(e, mu, 1.0 / kT))
+    S, m = ctx.sp2_fermi_entropy(to_dev(H), mu, kT)
+    say(f"  S {S:.12f} (oracle {S_ref:.12f}), rel {(S - S_ref) / S_ref:+.1e}, {m} coefficients")
+    assert abs(S - S_ref) < 1e-10 * S_ref
+    with pytest.raises(p.Sp2Error) as ei:
+        ctx.sp2_fermi_entropy(to_dev(H), mu, 0.01)
+    assert ei.value.status == p.SP2_EINVAL
