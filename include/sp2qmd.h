@@ -257,7 +257,7 @@ sp2_status sp2_fermi_density_matrix(sp2_ctx *ctx, int N, const double *H, double
  * Fermi operator at mu; the factor 2 counts spin).  Computed without
  * eigenvalues as Tr s((H - mu I) / kT) by a Chebyshev expansion over H's
  * Gershgorin interval: coefficients on the host (8192 Chebyshev-Gauss nodes,
- * kept while above 1e-15), moments Tr T_k from about half as many N x N
+ * kept while above 1e-13), moments Tr T_k from about half as many N x N
  * FP64 products as coefficients (rocBLAS).  H: N x N device, finite and
  * symmetric (EINVAL otherwise); mu finite; kT > 0 in the units of H; EINVAL
  * when more than about 4000 coefficients would be needed (the count grows as

@@ -791,7 +791,7 @@ extern "C" sp2_status sp2_fermi_density_matrix(sp2_ctx* c, int N, const double* 
 // come from T_0 .. T_K alone: Tr T_2k = 2 <T_k, T_k> - N and
 // Tr T_(2k+1) = 2 <T_(k+1), T_k> - Tr T_1, one product per k.
 constexpr int kEntropyNodes = 8192;   // Chebyshev-Gauss nodes of the coefficients
-constexpr double kEntropyCoefTol = 1e-15;
+constexpr double kEntropyCoefTol = 1e-13;
 
 static double fermi_entropy_term(double x) {   // s(x) per state, spin not counted
     const double a = std::fabs(x);
