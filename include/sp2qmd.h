@@ -373,6 +373,14 @@ typedef struct {
                            entry points each step; 0 (zero-initialised
                            options): orthogonal                              */
     double overlap_lam;
+    double kT;          /* > 0: finite electronic temperature (units of H):
+                           the density matrix is the Fermi operator of
+                           sp2_fermi_density_matrix (canonical mu, Newton from
+                           the previous step's mu, |Tr D - n_occ| < 1e-9),
+                           and the record's epot is the free energy
+                           U - kT S with S of sp2_fermi_entropy; 0: SP2.
+                           Orthogonal basis only (EINVAL with overlap_s0 > 0) */
+    int fermi_steps;    /* recursion steps of the Fermi operator (1..60)      */
 } xlbomd_options;
 
 typedef struct {

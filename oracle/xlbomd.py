@@ -30,7 +30,7 @@ import numpy as np
 
 import synth
 
-from . import eig, nonorth, observables, sp2, tb
+from . import eig, fermi, nonorth, observables, sp2, tb
 
 K5_KAPPA = 1.82
 K5_ALPHA = 0.018
@@ -46,6 +46,7 @@ class XLOptions:
     solver: str = "sp2"           # "sp2" or "jacobi"
     sp2_tol: float = 1e-10
     check_stability: bool = False  # refuse kappa outside the stability bound at t = 0
+    kT: float = 0.0               # > 0: finite electronic temperature (eV)
 
 
 def density(H, n_occ, solver="sp2", tol=1e-10):
@@ -81,8 +82,20 @@ def charges(pos, n, m, n_occ, solver="sp2"):
     return observables.mulliken(density(tb.hamiltonian(pos, n, m), n_occ, solver), m.z_val)
 
 
-def evaluate(pos, n, m, n_occ, solver="sp2", tol=1e-10, want_forces=True):
-    """One density-matrix construction at (R, n): returns dict of q, U, F, D."""
+def evaluate(pos, n, m, n_occ, solver="sp2", tol=1e-10, want_forces=True, kT=0.0):
+    """One density-matrix construction at (R, n): returns dict of q, U, F, D.
+    kT > 0 (orthogonal basis): D is the Fermi operator (definition) and U the
+    free energy U - T_e S (Eq. Entropy), whose constant-n gradient the forces
+    of D are."""
+    if kT > 0.0:
+        if _nonorth(m):
+            raise ValueError("finite electronic temperature is built for the orthogonal basis only")
+        H = tb.hamiltonian(pos, n, m)
+        D, mu, f = fermi.fermi_density(H, n_occ, kT)
+        q = observables.mulliken(D, m.z_val)
+        U = observables.potential_energy(pos, n, D, m) - kT * fermi.entropy(f)
+        F = observables.forces(pos, n, D, m) if want_forces else None
+        return {"q": q, "U": U, "F": F, "D": D, "H": H, "mu": mu}
     if _nonorth(m):
         S = nonorth.overlap(pos, m)
         H = nonorth.hamiltonian(pos, n, m, S)
@@ -174,7 +187,7 @@ def init_state(pos, vel, m, n_occ, opts: XLOptions, n0):
     n0 = np.array(n0, dtype=np.float64)
     if opts.check_stability:
         check_stability(pos, n0, m, n_occ, opts.kappa, opts.solver)
-    ev = evaluate(pos, n0, m, n_occ, opts.solver, opts.sp2_tol)
+    ev = evaluate(pos, n0, m, n_occ, opts.solver, opts.sp2_tol, kT=opts.kT)
     hist = [n0.copy() for _ in range(len(opts.c))]
     return XLState(pos.copy(), vel.copy(), hist, ev["q"], ev["F"], ev["U"])
 
@@ -190,7 +203,7 @@ def step(st: XLState, m, n_occ, opts: XLOptions) -> XLState:
     v_half = st.vel + 0.5 * dt * acc * st.F
     pos = st.pos + dt * v_half
     n_new = verlet_n(st.hist, st.q, opts.kappa, opts.alpha, opts.c)
-    ev = evaluate(pos, n_new, m, n_occ, opts.solver, opts.sp2_tol)
+    ev = evaluate(pos, n_new, m, n_occ, opts.solver, opts.sp2_tol, kT=opts.kT)
     vel = v_half + 0.5 * dt * acc * ev["F"]
     hist = [n_new] + st.hist[:-1]
     return XLState(pos, vel, hist, ev["q"], ev["F"], ev["U"], st.step + 1)

@@ -72,7 +72,8 @@ class XLOptions(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("K", ctypes.c_int),
                 ("c", ctypes.c_double * 9), ("sp2", Sp2Options),
                 ("scf_beta", ctypes.c_double), ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int),
-                ("diverge_q", ctypes.c_double), ("overlap_s0", ctypes.c_double), ("overlap_lam", ctypes.c_double)]
+                ("diverge_q", ctypes.c_double), ("overlap_s0", ctypes.c_double), ("overlap_lam", ctypes.c_double),
+                ("kT", ctypes.c_double), ("fermi_steps", ctypes.c_int)]
 
 
 class XLRecord(ctypes.Structure):
@@ -422,20 +423,23 @@ class Context:
 
     def xlbomd_create(self, model, xyz, vel, n0=None, dt_fs=0.25, kappa=0.91, alpha=0.018,
                       c=(-6.0, 14.0, -8.0, -3.0, 4.0, -1.0), sp2_opts=None,
-                      scf_beta=0.3, scf_tol=1e-10, scf_max_iter=None, diverge_q=1.0):
+                      scf_beta=0.3, scf_tol=1e-10, scf_max_iter=None, diverge_q=1.0, kT=0.0,
+                      fermi_steps=16):
         """scf_max_iter None: 0 (use n0 as given) if n0 is given, else 500 (SCF from zeros).
-        diverge_q: stop with SP2_EDIVERGE when max|q - n| exceeds it (0: never)."""
+        diverge_q: stop with SP2_EDIVERGE when max|q - n| exceeds it (0: never).
+        kT > 0: finite electronic temperature (Fermi operator with fermi_steps
+        recursion steps; epot is then the free energy U - kT S)."""
         if scf_max_iter is None:
             scf_max_iter = 0 if n0 is not None else 500
         return XLBOMD(self, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,
-                      scf_beta, scf_tol, scf_max_iter, diverge_q)
+                      scf_beta, scf_tol, scf_max_iter, diverge_q, kT, fermi_steps)
 
 
 class XLBOMD:
     """Handle of an xlbomd integrator; host numpy arrays in, host numpy arrays out."""
 
     def __init__(self, ctx, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,
-                 scf_beta=0.3, scf_tol=1e-10, scf_max_iter=500, diverge_q=1.0):
+                 scf_beta=0.3, scf_tol=1e-10, scf_max_iter=500, diverge_q=1.0, kT=0.0, fermi_steps=16):
         self.ctx = ctx
         self.nat = len(xyz)
         o = XLOptions()
@@ -447,6 +451,7 @@ class XLBOMD:
         o.diverge_q = diverge_q
         o.overlap_s0 = float(getattr(model, "overlap_s0", 0.0))
         o.overlap_lam = float(getattr(model, "overlap_lam", 0.5))
+        o.kT, o.fermi_steps = float(kT), int(fermi_steps)
         p = tb_params(model)
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)

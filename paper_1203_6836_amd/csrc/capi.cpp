@@ -1158,6 +1158,8 @@ struct xlbomd {
     int n_occ;            // doubly occupied states: z_val n_atoms / 2
     double *xyz, *vel, *F, *q, *hist, *H, *D, *dev, *dscal;
     double* S = nullptr;  // overlap (non-orthogonal basis only)
+    double mu = NAN;      // chemical potential of the last Fermi operator (kT > 0)
+    double ts = 0.0;      // kT S of the last Fermi operator
     int head;
     long step;
     double U;
@@ -1173,6 +1175,23 @@ static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true, fl
     sp2_status s = tb_hamiltonian(c, &m->p, nat, m->xyz, n_t, m->H);
     if (s != SP2_OK) return s;
     sp2_stats st;
+    if (m->o.kT > 0.0) {
+        // finite electronic temperature: the Fermi operator at the canonical mu
+        // (from the previous step's), its entropy, charges and forces
+        int passes = 0;
+        if ((s = sp2_fermi_density_matrix(c, N, m->H, (double)m->n_occ, m->o.kT, m->o.fermi_steps, 100, 1e-9, &m->mu,
+                                          m->D, &passes, nullptr)) != SP2_OK)
+            return s;
+        double S = 0.0;
+        if ((s = sp2_fermi_entropy(c, N, m->H, m->mu, m->o.kT, &S, nullptr)) != SP2_OK) return s;
+        m->ts = m->o.kT * S;
+        m->dm_count += 1;
+        if (iters) *iters = passes;
+        if (fill) *fill = 1.0f;
+        HIPCHK(c, launch_mulliken(m->D, nat, m->p.z_val, m->q, c->stream));
+        if (!with_forces) return SP2_OK;
+        return forces_impl(c, &m->p, nat, m->xyz, m->D, m->q, n_t, m->F, m->dscal);
+    }
     if (m->S) {
         // non-orthogonal basis: overlap at these positions, H[n] with it, the
         // density matrix through the Loewdin factor, charges and forces with S
@@ -1217,6 +1236,9 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
         return fail(c, SP2_EINVAL, "z_val * n_atoms must be an even electron count below 8 n_atoms");
     if (o->K < 1 || o->K > 8 || !(o->dt_fs > 0) || !(p->mass > 0) || !(o->diverge_q >= 0))
         return fail(c, SP2_EINVAL, "bad xlbomd options");
+    if (!(o->kT >= 0.0) || !std::isfinite(o->kT) ||
+        (o->kT > 0.0 && (o->fermi_steps < 1 || o->fermi_steps > 60 || o->overlap_s0 != 0.0)))
+        return fail(c, SP2_EINVAL, "kT > 0 needs 1 <= fermi_steps <= 60 and the orthogonal basis");
     if (!(o->overlap_s0 >= 0.0) || (o->overlap_s0 > 0.0 && !(o->overlap_lam > 0.0)))
         return fail(c, SP2_EINVAL, "bad overlap parameters");
     sp2_status s = check_options(c, o->sp2, 4 * n_atoms);
@@ -1320,7 +1342,7 @@ extern "C" sp2_status xlbomd_run(xlbomd* m, int n_steps, xlbomd_record* log) {
         HIPCHK(c, hipMemcpyAsync(c->scal_host, m->dscal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         m->step += 1;
-        const double U = c->scal_host[0];
+        const double U = c->scal_host[0] - m->ts;   // free energy at kT > 0
         const double ke = 0.5 * m->p.mass * kKeEv * c->scal_host[2];
         m->U = U;
         if (log) {

@@ -176,3 +176,46 @@ def test_entropy_matches_definition(ctx, dims, seed, kT):
     with pytest.raises(p.Sp2Error) as ei:
         ctx.sp2_fermi_entropy(to_dev(H), mu, 0.01)
     assert ei.value.status == p.SP2_EINVAL
+
+
+def test_finite_temperature_xlbomd_matches_oracle(ctx):
+    """XL-BOMD at kT = 0.5 eV (Fermi operator, its entropy in the free energy,
+    forces of the Fermi D every step) on the 3 x 3 x 3 cluster, whose gap
+    (0.16 eV) is well below kT: 20 steps from self-consistent finite-T charges
+    against the oracle integrator with the Fermi operator by definition."""
+    import paper_1203_6836_amd as p
+    from oracle import xlbomd as oxl
+    say("case fermi xlbomd 3x3x3 20 steps kT=0.5")
+    m = synth.MD_MODEL
+    pos = synth.lattice_positions((3, 3, 3), seed=21)
+    nat, nocc = len(pos), 2 * len(pos)
+    vel = synth.maxwell_velocities(nat, 300.0, m.mass, seed=5)
+    n0 = np.zeros(nat)
+    for _ in range(2000):   # finite-T SCF by linear mixing
+        q = oxl.evaluate(pos, n0, m, nocc, want_forces=False, kT=0.5)["q"]
+        if np.abs(q - n0).max() < 1e-11:
+            break
+        n0 = n0 + 0.1 * (q - n0)
+    assert np.abs(q - n0).max() < 1e-11
+    opts = oxl.XLOptions(kT=0.5)
+    ost, olog = oxl.run(oxl.init_state(pos, vel, m, nocc, opts, n0), m, nocc, opts, 20)
+    md = ctx.xlbomd_create(m, pos, vel, n0, dt_fs=opts.dt_fs, kappa=opts.kappa, alpha=opts.alpha,
+                           c=opts.c, sp2_opts=p.options("fp64"), kT=0.5, fermi_steps=16)
+    glog = md.xlbomd_run(20)
+    xyz, v, q, n = md.xlbomd_get()
+    md.close()
+    dx = float(np.abs(xyz - ost.pos).max())
+    eg = np.array([r["etot"] for r in glog])
+    eo = np.array([r["etot"] for r in olog])
+    passes = [r["sp2_iterations"] for r in glog]
+    say(f"  max|dx| {dx:.1e} A, max|dE_tot| {np.abs(eg - eo).max():.1e} eV, E_tot spread {np.ptp(eo) / nat:.1e} "
+        f"eV/atom, Newton passes per step {passes[:3]}..{passes[-3:]}")
+    np.testing.assert_allclose(xyz, ost.pos, atol=1e-9)
+    np.testing.assert_allclose(v, ost.vel, atol=1e-9)
+    # the step's canonical mu is solved to |Tr D - n_occ| < 1e-9, which bounds
+    # how closely the charges, and the auxiliary charges built from them, agree
+    np.testing.assert_allclose(n, ost.hist[0], atol=2e-8)
+    assert np.abs(eg - eo).max() < 1e-7
+    with pytest.raises(p.Sp2Error) as ei:
+        ctx.xlbomd_create(m.with_(overlap_s0=0.05), pos, vel, n0, kT=0.5)
+    assert ei.value.status == p.SP2_EINVAL
