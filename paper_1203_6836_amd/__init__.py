@@ -16,6 +16,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsp2qmd.so")
 
 SP2_OK, SP2_EINVAL, SP2_ENOMEM, SP2_EDEVICE, SP2_ENOCONV, SP2_EGAP = 0, -1, -2, -3, -4, -5
+# kappa of the K = 5 dissipative auxiliary-charge step (Eq. Verl_n) before its
+# rescaling: the paper's runs use half of it at zero electronic temperature and
+# three quarters at finite temperature, which damps the free energy's random walk.
+KAPPA_K5 = 1.82
+KAPPA_ZERO_T = 0.5 * KAPPA_K5
+KAPPA_FINITE_T = 0.75 * KAPPA_K5
 SP2_EBUDGET, SP2_ETIMEOUT, SP2_EDIVERGE = -6, -8, -9
 PREC_FP64, PREC_INT8X, PREC_BF16X2 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "int8x": PREC_INT8X, "bf16x2": PREC_BF16X2}
@@ -428,7 +434,8 @@ class Context:
         """scf_max_iter None: 0 (use n0 as given) if n0 is given, else 500 (SCF from zeros).
         diverge_q: stop with SP2_EDIVERGE when max|q - n| exceeds it (0: never).
         kT > 0: finite electronic temperature (Fermi operator with fermi_steps
-        recursion steps; epot is then the free energy U - kT S)."""
+        recursion steps; epot is then the free energy U - kT S); the paper's
+        finite-temperature runs use kappa=KAPPA_FINITE_T."""
         if scf_max_iter is None:
             scf_max_iter = 0 if n0 is not None else 500
         return XLBOMD(self, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,

@@ -197,7 +197,8 @@ def test_finite_temperature_xlbomd_matches_oracle(ctx):
             break
         n0 = n0 + 0.1 * (q - n0)
     assert np.abs(q - n0).max() < 1e-11
-    opts = oxl.XLOptions(kT=0.5)
+    opts = oxl.XLOptions(kT=0.5, kappa=p.KAPPA_FINITE_T)   # the kappa rescaling of finite-T runs
+    assert p.KAPPA_FINITE_T == 0.75 * oxl.K5_KAPPA
     ost, olog = oxl.run(oxl.init_state(pos, vel, m, nocc, opts, n0), m, nocc, opts, 20)
     md = ctx.xlbomd_create(m, pos, vel, n0, dt_fs=opts.dt_fs, kappa=opts.kappa, alpha=opts.alpha,
                            c=opts.c, sp2_opts=p.options("fp64"), kT=0.5, fermi_steps=16)
