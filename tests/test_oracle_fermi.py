@@ -99,3 +99,21 @@ def test_finite_temperature_forces_are_gradient_of_free_energy():
     p[0, 0] += h
     q[0, 0] -= h
     assert abs(-(U(p) - U(q)) / (2 * h) - F[0, 0]) > 1e-4
+
+
+def test_xlbomd_evaluate_at_finite_temperature_is_the_free_energy():
+    """The integrator's evaluation at kT > 0 returns the Fermi D, its charges,
+    U - T_e S and the forces of that D (the pinned free-energy gradient)."""
+    from oracle import observables, xlbomd
+    m = synth.MD_MODEL.with_(pair_a=5.0)
+    pos = synth.lattice_positions((2, 2, 2), seed=21)
+    n = np.linspace(-0.1, 0.1, len(pos))
+    ev = xlbomd.evaluate(pos, n, m, 2 * len(pos), kT=1.5)
+    A, D, mu = fermi.free_energy(pos, n, m, 2 * len(pos), 1.5)
+    assert ev["U"] == pytest.approx(A, rel=1e-14)
+    np.testing.assert_allclose(ev["D"], D, atol=1e-14)
+    np.testing.assert_allclose(ev["q"], observables.mulliken(D, m.z_val), atol=1e-14)
+    np.testing.assert_allclose(ev["F"], observables.forces(pos, n, D, m), atol=1e-12)
+    assert abs(np.trace(D) - 2 * len(pos)) < 1e-10
+    with pytest.raises(ValueError):
+        xlbomd.evaluate(pos, n, m.with_(overlap_s0=0.05), 2 * len(pos), kT=1.5)
