@@ -834,10 +834,30 @@ extern "C" sp2_status sp2_fermi_entropy(sp2_ctx* c, int N, const double* H, doub
     const double pi = 3.14159265358979323846;
     for (int j = 0; j < kEntropyNodes; ++j)
         g[j] = fermi_entropy_term(beta * (w * std::cos(pi * (j + 0.5) / kEntropyNodes) + ctr - mu));
+    // cos(k theta_j) by rotating (cos, sin)(k theta_j) by theta_j, recomputed
+    // exactly every 32 orders (rounding stays near 32 ulp)
+    std::vector<double> ck(kEntropyNodes), sk(kEntropyNodes), c1(kEntropyNodes), s1(kEntropyNodes);
+    for (int j = 0; j < kEntropyNodes; ++j) {
+        c1[j] = std::cos(pi * (j + 0.5) / kEntropyNodes);
+        s1[j] = std::sin(pi * (j + 0.5) / kEntropyNodes);
+    }
     int m = 0;
     for (int k = 0; k < kmax && k < m + 64; ++k) {   // stop after 64 coefficients below the tolerance
         double acc = 0.0;
-        for (int j = 0; j < kEntropyNodes; ++j) acc += g[j] * std::cos(pi * k * (j + 0.5) / kEntropyNodes);
+        if (k % 32 == 0) {
+            for (int j = 0; j < kEntropyNodes; ++j) {   // k theta_j reduced mod 2 pi in integers
+                const long long r = ((long long)k * (2 * j + 1)) % (4LL * kEntropyNodes);
+                ck[j] = std::cos(pi * (double)r / (2.0 * kEntropyNodes));
+                sk[j] = std::sin(pi * (double)r / (2.0 * kEntropyNodes));
+            }
+        } else {
+            for (int j = 0; j < kEntropyNodes; ++j) {
+                const double cn = ck[j] * c1[j] - sk[j] * s1[j];
+                sk[j] = sk[j] * c1[j] + ck[j] * s1[j];
+                ck[j] = cn;
+            }
+        }
+        for (int j = 0; j < kEntropyNodes; ++j) acc += g[j] * ck[j];
         a[k] = 2.0 * acc / kEntropyNodes;
         if (std::fabs(a[k]) > kEntropyCoefTol) m = k + 1;
     }
