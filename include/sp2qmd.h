@@ -153,6 +153,24 @@ sp2_status sp2_density_matrix(sp2_ctx *ctx, int N, const double *H, int n_occ,
                               const sp2_options *opt, double *D_out,
                               sp2_stats *stats);
 
+/* Allocation-free variant of sp2_density_matrix, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and errors as
+ * sp2_density_matrix, restricted to FP64 products (opt->precision 0) without
+ * a threshold (opt->tau 0) and 1 <= N <= 1024; other options as there.  It
+ * calls no hipMalloc/hipFree: its scratch (the two padded X buffers, partial
+ * sums and the FP64 product's K-split accumulators) lives in one static
+ * device array of 64 MiB that the library holds on every GPU it runs on until
+ * the process ends; its device address is looked up by sp2_ctx_create.
+ * N > 1024, another precision or tau != 0 give SP2_EINVAL.  Every call on a
+ * GPU shares that GPU's array, which keeps the last call's contents (each
+ * call writes all of it that it reads), so calls that overlap on one GPU
+ * (several contexts or streams, or host threads) race and must be serialised
+ * by the caller.  Results equal sp2_density_matrix's with the same options
+ * (same kernels, same K split). */
+sp2_status sp2_density_matrix_noalloc(sp2_ctx *ctx, int N, const double *H, int n_occ,
+                                      const sp2_options *opt, double *D_out, sp2_stats *stats);
+
 /* Autotuner of the product tile order: times the SP2 product kernel of the
  * given precision (and slices, for INT8X) at size N on the context's device
  * for each candidate super-tile size, and keeps the fastest for later solves

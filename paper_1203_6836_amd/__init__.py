@@ -107,6 +107,8 @@ _SIGS = {
     "sp2_last_error": (ctypes.c_char_p, [_P]),
     "sp2_density_matrix": (_I, [_P, _I, _P, _I, ctypes.POINTER(Sp2Options), _P,
                                 ctypes.POINTER(Sp2Stats)]),
+    "sp2_density_matrix_noalloc": (_I, [_P, _I, _P, _I, ctypes.POINTER(Sp2Options), _P,
+                                        ctypes.POINTER(Sp2Stats)]),
     "sp2_mulliken": (_I, [_P, _I, _P, _D, _P]),
     "sp2_autotune": (_I, [_P, _I, _I, _I, ctypes.POINTER(TuneResult)]),
     "sp2_int8_mfma_rate": (_I, [_P, ctypes.POINTER(_D)]),
@@ -247,6 +249,21 @@ class Context:
                                       ctypes.byref(opts) if opts is not None else None,
                                       _ptr(D_out), ctypes.byref(stats))
         self._check(st, "sp2_density_matrix")
+        return D_out, stats.to_dict()
+
+    def sp2_density_matrix_noalloc(self, H, n_occ: int, opts: Sp2Options | None = None, D_out=None):
+        """As sp2_density_matrix, with the library's static device scratch (FP64, tau 0, N <= 1024)."""
+        import torch
+        N = H.shape[0]
+        if H.shape != (N, N):
+            raise ValueError("H must be square")
+        if D_out is None:
+            D_out = torch.empty_like(H)
+        stats = Sp2Stats()
+        st = lib().sp2_density_matrix_noalloc(self._h, N, _ptr(H), int(n_occ),
+                                              ctypes.byref(opts) if opts is not None else None,
+                                              _ptr(D_out), ctypes.byref(stats))
+        self._check(st, "sp2_density_matrix_noalloc")
         return D_out, stats.to_dict()
 
     def sp2_density_matrix_status(self, H, n_occ: int, opts: Sp2Options | None = None):

@@ -16,6 +16,7 @@
 
 #include "../../include/sp2qmd.h"
 #include "fermi_internal.h"
+#include "noalloc_internal.h"
 #include "nonorth_internal.h"
 #include "sp2_internal.h"
 #include "split_internal.h"
@@ -74,6 +75,10 @@ struct sp2_ctx {
     size_t eatcap = 0;         // atoms
     // product tile order chosen by sp2_autotune, per (ld, precision, slices)
     std::map<std::tuple<int, int, int>, int> tuned;
+    // device address of the allocation-free solve's static scratch (NULL if
+    // the lookup at creation failed; sscratch_err then holds the HIP error)
+    void* sscratch = nullptr;
+    hipError_t sscratch_err = hipSuccess;
 };
 
 int sp2_ctx_device_of(const sp2_ctx* c) { return c->device; }
@@ -173,6 +178,9 @@ sp2_status sp2_ctx_create(sp2_ctx** out, int device, void* stream) {
         sp2_ctx_destroy(c);
         return SP2_EDEVICE;
     }
+    // set-up of the allocation-free solve: the static scratch's address on
+    // this device (the device is current)
+    c->sscratch_err = static_scratch_init(device, &c->sscratch);
     *out = c;
     return SP2_OK;
 }
@@ -237,30 +245,87 @@ static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
     return SP2_OK;
 }
 
-// Enqueue and run one SP2 solve of H (device, N x N) into D (device).
+// Device scratch of one SP2 solve: the two padded X buffers (2 ld^2 doubles),
+// the partial-sum slots, the chunk accumulators of the FP64 product's K split
+// (NULL: no split), and for thresholded solves the panel ranges and the
+// zero-tile flags with the work list.
+struct SolveScratch {
+    double* xbuf = nullptr;
+    double* part = nullptr;
+    double* f64tail = nullptr;
+    size_t f64tail_bytes = 0;
+    int* env = nullptr;
+    int* tz = nullptr;
+};
+
+static int padded_ld(int N) { return ((N + kTile - 1) / kTile) * kTile; }
+
+// Partial-sum slots any kernel of a solve of size N writes at most.
+static size_t solve_part_slots(int N) {
+    const int ld = padded_ld(N);
+    const int nt = ld / kTile;
+    return std::max<size_t>({(size_t)(N + 3) / 4 * 2, (size_t)ld / 4 * 3, (size_t)tri_tiles(nt) * 3, 1024,
+                             (size_t)kDotBlocks, split_part_slots(ld) * 3});
+}
+
+static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, const sp2_options& o, double* D,
+                               sp2_stats* stats, const SolveScratch& sc);
+
+// Enqueue and run one SP2 solve of H (device, N x N) into D (device), with
+// scratch owned by the context (grown on demand).
 static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const sp2_options& o, double* D,
                             sp2_stats* stats) {
-    const int ld = ((N + kTile - 1) / kTile) * kTile;
+    const int ld = padded_ld(N);
     const size_t ld2 = (size_t)ld * ld;
     const int nt = ld / kTile;
-    const size_t nslot_max = std::max<size_t>({(size_t)(N + 3) / 4 * 2, (size_t)ld / 4 * 3,
-                                               (size_t)tri_tiles(nt) * 3, 1024, (size_t)kDotBlocks,
-                                               split_part_slots(ld) * 3});
     sp2_status s;
     size_t xbytes = c->xcap * sizeof(double) * 2;
     if ((s = grow(c, (void**)&c->xbuf, &xbytes, 2 * ld2 * sizeof(double))) != SP2_OK) return s;
     c->xcap = xbytes / (2 * sizeof(double));
     size_t pbytes = c->partcap * sizeof(double);
-    if ((s = grow(c, (void**)&c->part, &pbytes, nslot_max * sizeof(double))) != SP2_OK) return s;
+    if ((s = grow(c, (void**)&c->part, &pbytes, solve_part_slots(N) * sizeof(double))) != SP2_OK) return s;
     c->partcap = pbytes / sizeof(double);
-    double* buf0 = c->xbuf;
-    double* buf1 = c->xbuf + ld2;
     const bool int8x = o.precision == SP2_PREC_INT8X;
     const bool bf16x = o.precision == SP2_PREC_BF16X2;
     if (int8x || bf16x) {
         if ((s = (sp2_status)split_reserve(c->split, ld, int8x ? o.slices : 0, bf16x)) != SP2_OK)
             return fail(c, SP2_ENOMEM, "device allocation for split operands failed");
     }
+    SolveScratch sc;
+    sc.xbuf = c->xbuf;
+    sc.part = c->part;
+    // the FP64 product runs in FP64 mode, in the FP64 head of INT8X and in the
+    // FP32 tail of BF16X2
+    if (!int8x || o.fp64_head > 0)
+        if ((s = f64_tail_buffer(c, ld, o.tail_split, &sc.f64tail, &sc.f64tail_bytes)) != SP2_OK) return s;
+    if (o.tau > 0.0) {
+        size_t eb = c->envcap;
+        if ((s = grow(c, (void**)&c->env, &eb, (size_t)nt * 2 * sizeof(int))) != SP2_OK) return s;
+        c->envcap = eb;
+        sc.env = c->env;
+    }
+    // zero-tile flags: int8 products from the first product on (the FP64
+    // product does not keep them)
+    if (o.tau > 0.0 && int8x && o.fp64_head == 0) {
+        size_t zb = c->tzcap;
+        // 2 T flags, then the product's work list (T entries) and its 2 counters
+        if ((s = grow(c, (void**)&c->tz, &zb, ((size_t)3 * tri_tiles(nt) + 2) * sizeof(int))) != SP2_OK) return s;
+        c->tzcap = zb;
+        sc.tz = c->tz;
+    }
+    return sp2_solve_in(c, N, H, n_occ, o, D, stats, sc);
+}
+
+static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, const sp2_options& o, double* D,
+                               sp2_stats* stats, const SolveScratch& sc) {
+    const int ld = padded_ld(N);
+    const size_t ld2 = (size_t)ld * ld;
+    const int nt = ld / kTile;
+    double* buf0 = sc.xbuf;
+    double* buf1 = sc.xbuf + ld2;
+    double* part = sc.part;
+    const bool int8x = o.precision == SP2_PREC_INT8X;
+    const bool bf16x = o.precision == SP2_PREC_BF16X2;
     // int8 products from the first one on, no threshold: the products write
     // their upper tiles only and the encode reads the upper triangle
     const bool upper = int8x && o.tau == 0.0 && o.fp64_head == 0;
@@ -288,42 +353,22 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     const double nb = (double)((N + 31) / 32);
     a.total_blocks = o.tau > 0.0 ? nb * nb : 0.0;
 
-    // the FP64 product runs in FP64 mode, in the FP64 head of INT8X and in the
-    // FP32 tail of BF16X2
-    double* f64tail = nullptr;
-    size_t f64tail_bytes = 0;
-    if (!int8x || o.fp64_head > 0)
-        if ((s = f64_tail_buffer(c, ld, o.tail_split, &f64tail, &f64tail_bytes)) != SP2_OK) return s;
-
-    int* env = nullptr;
-    if (o.tau > 0.0) {
-        size_t eb = c->envcap;
-        if ((s = grow(c, (void**)&c->env, &eb, (size_t)nt * 2 * sizeof(int))) != SP2_OK) return s;
-        c->envcap = eb;
-        env = c->env;
-    }
-    // zero-tile flags: int8 products from the first product on (the FP64
-    // product does not keep them)
-    int* tz = nullptr;
-    if (o.tau > 0.0 && int8x && o.fp64_head == 0) {
-        size_t zb = c->tzcap;
-        // 2 T flags, then the product's work list (T entries) and its 2 counters
-        if ((s = grow(c, (void**)&c->tz, &zb, ((size_t)3 * tri_tiles(nt) + 2) * sizeof(int))) != SP2_OK) return s;
-        c->tzcap = zb;
-        tz = c->tz;
-    }
+    double* f64tail = sc.f64tail;
+    const size_t f64tail_bytes = sc.f64tail_bytes;
+    int* env = sc.env;
+    int* tz = sc.tz;
     c->split.env = int8x ? env : nullptr;
     c->split.tz = tz;
     hipStream_t st = c->stream;
     HIPCHK(c, hipEventRecord(c->ev0, st));
     int ns = 0, nchk = 0;
     HIPCHK(c, launch_check_h(H, N, c->chk, &nchk, st));
-    HIPCHK(c, launch_gershgorin(H, N, c->part, &ns, st));
-    HIPCHK(c, launch_bounds(c->part, ns, c->chk, nchk, c->st, st));
-    HIPCHK(c, launch_init(H, N, ld, buf0, c->st, c->part, &ns, st, upper ? c->split.rmax : nullptr));
+    HIPCHK(c, launch_gershgorin(H, N, part, &ns, st));
+    HIPCHK(c, launch_bounds(part, ns, c->chk, nchk, c->st, st));
+    HIPCHK(c, launch_init(H, N, ld, buf0, c->st, part, &ns, st, upper ? c->split.rmax : nullptr));
     if (o.tau > 0.0)
-        HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, c->part, &ns, 1, st, env, tz));
-    HIPCHK(c, launch_ctrl_init(c->part, ns, c->st, a, st));
+        HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, part, &ns, 1, st, env, tz));
+    HIPCHK(c, launch_ctrl_init(part, ns, c->st, a, st));
 
     int launched = 0;
     bool finished = false;
@@ -335,16 +380,16 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
             if (pe) HIPCHK(c, hipEventRecord(pe[0], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
-            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, env, tile_group, f64tail,
+            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, part, &ns, st, env, tile_group, f64tail,
                                       f64tail_bytes));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
-            if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, env));
+            if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
             if (o.tau > 0.0)
-                HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, c->part, &ns, 0, st,
+                HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, part, &ns, 0, st,
                                                  env, tz, tz ? tz + (size_t)2 * tri_tiles(nt) : nullptr));
             if (pe) HIPCHK(c, hipEventRecord(pe[4], st));
-            HIPCHK(c, launch_ctrl_step(c->part, ns, c->st, a, st));
+            HIPCHK(c, launch_ctrl_step(part, ns, c->st, a, st));
         }
         launched += chunk;
         HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(State), hipMemcpyDeviceToHost, st));
@@ -423,6 +468,49 @@ extern "C" sp2_status sp2_density_matrix(sp2_ctx* c, int N, const double* H, int
     if (s != SP2_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
     return sp2_solve(c, N, H, n_occ, o, D_out, stats);
+}
+
+// Allocation-free variant of sp2_density_matrix: FP64 products, no threshold,
+// N <= kStaticMaxN, every scratch array carved from the static device array
+// (X buffers, partial slots, then the K-split chunk accumulators in the rest).
+// Calls no allocating routine: the context's control state, pinned read-back
+// record and events were made by sp2_ctx_create.
+extern "C" sp2_status sp2_density_matrix_noalloc(sp2_ctx* c, int N, const double* H, int n_occ,
+                                                 const sp2_options* opt, double* D_out, sp2_stats* stats) {
+    if (!c) return SP2_EINVAL;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (N < 1 || N > kStaticMaxN)
+        return fail(c, SP2_EINVAL, "sp2_density_matrix_noalloc: N must be in [1, " + std::to_string(kStaticMaxN) +
+                                       "] (the static scratch holds X buffers up to that size)");
+    if (!H || !D_out) return fail(c, SP2_EINVAL, "null matrix pointer");
+    if (n_occ <= 0 || n_occ >= N) return fail(c, SP2_EINVAL, "need 0 < n_occ < N");
+    sp2_options o;
+    if (opt) o = *opt;
+    else sp2_options_default(&o);
+    sp2_status s = check_options(c, o, N);
+    if (s != SP2_OK) return s;
+    if (o.precision != SP2_PREC_FP64)
+        return fail(c, SP2_EINVAL, "sp2_density_matrix_noalloc: only FP64 products (precision 0)");
+    if (o.tau != 0.0) return fail(c, SP2_EINVAL, "sp2_density_matrix_noalloc: no threshold (tau must be 0)");
+    if (!c->sscratch)
+        return fail(c, SP2_EDEVICE, std::string("static scratch address lookup failed: ") +
+                                        hipGetErrorString(c->sscratch_err));
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t ld = (size_t)padded_ld(N);
+    const auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t xbytes = up256(2 * ld * ld * sizeof(double));
+    const size_t pbytes = up256(solve_part_slots(N) * sizeof(double));
+    if (xbytes + pbytes > kStaticScratchBytes)
+        return fail(c, SP2_EINVAL, "sp2_density_matrix_noalloc: size exceeds the static scratch");
+    unsigned char* base = static_cast<unsigned char*>(c->sscratch);
+    SolveScratch sc;
+    sc.xbuf = reinterpret_cast<double*>(base);
+    sc.part = reinterpret_cast<double*>(base + xbytes);
+    if (o.tail_split != 0) {
+        sc.f64tail = reinterpret_cast<double*>(base + xbytes + pbytes);
+        sc.f64tail_bytes = kStaticScratchBytes - xbytes - pbytes;
+    }
+    return sp2_solve_in(c, N, H, n_occ, o, D_out, stats, sc);
 }
 
 extern "C" sp2_status sp2_int8_mfma_rate(sp2_ctx* c, double* ops_per_s) {
