@@ -220,3 +220,36 @@ def gapped_workload(n_layers: int, seed: int = 3) -> Workload:
 
 def small_workload(dims, seed) -> Workload:
     return Workload(f"lattice_{dims[0]}x{dims[1]}x{dims[2]}_s{seed}", tuple(dims), seed)
+
+
+# Seeded draws that select what a full-size comparison samples: Gaussian probe
+# vectors (D V estimates ||D - D_ref||_F, since E|A v|^2 = ||A||_F^2 for
+# v ~ N(0, I)), entries of H and 32 x 32 blocks of D.
+PROBE_SEED, PROBES = 12, 2
+H_SAMPLE_SEED, H_SAMPLES = 11, 4096
+BLOCK_SEED, BLOCKS = 13, 8
+
+
+def probe_vectors(n: int) -> np.ndarray:
+    """(n, PROBES) standard normal probe vectors."""
+    return np.random.default_rng(PROBE_SEED).standard_normal((n, PROBES))
+
+
+def h_sample_index(n: int):
+    """Row and column indices of sampled H entries: half uniform, half within
+    64 orbitals of the diagonal."""
+    rng = np.random.default_rng(H_SAMPLE_SEED)
+    i = rng.integers(0, n, H_SAMPLES)
+    j = np.where(np.arange(H_SAMPLES) % 2 == 0, rng.integers(0, n, H_SAMPLES),
+                 np.clip(i + rng.integers(-64, 65, H_SAMPLES), 0, n - 1))
+    return i, j
+
+
+def block_index(nb: int):
+    """Block-row and block-column indices of sampled 32 x 32 blocks of an
+    nb x nb block grid: half within two blocks of the diagonal, half uniform."""
+    rng = np.random.default_rng(BLOCK_SEED)
+    bi = rng.integers(0, nb, BLOCKS)
+    bj = np.where(np.arange(BLOCKS) < BLOCKS // 2, np.clip(bi + rng.integers(-2, 3, BLOCKS), 0, nb - 1),
+                  rng.integers(0, nb, BLOCKS))
+    return bi, bj

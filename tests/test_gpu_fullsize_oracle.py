@@ -1,0 +1,239 @@
+"""Full-size parity against the oracle: the 1024-atom XL-BOMD workload
+(Hamiltonian, charges, energy, forces, SCF start and the first ten steps) and
+the 16384-orbital block-thresholded solve, against oracle results stored by
+tests/golden/make_oracle_golden.py; forces past 64 atoms (orthogonal) and at
+128 atoms (non-orthogonal) against the oracle run here."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import eig, nonorth, observables, tb as otb
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def load(name):
+    with np.load(os.path.join(GOLDEN, name), allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_1203_6836_amd as p
+    c = p.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def c1_inputs():
+    w = synth.XLBOMD
+    m = synth.MD_MODEL
+    pos = w.positions()
+    vel = synth.maxwell_velocities(w.n_atoms, 300.0, m.mass, seed=synth.XLBOMD_VEL_SEED)
+    return w, m, pos, vel
+
+
+def test_evaluate_1024_atoms_against_oracle(ctx):
+    """H[n] (Eq. DFTB_2, S = I), charges, band energy, U and the forces at
+    constant n (Eqs. EL_Orth_a-c) at the self-consistent charges of the
+    1024-atom lattice, N = 4096: every pass of the per-atom pair loops."""
+    import paper_1203_6836_amd as p
+    g = load("c1_xlbomd_n4096.npz")
+    w, m, pos, _ = c1_inputs()
+    say("case evaluate 1024 atoms vs oracle")
+    xyz, n = to_dev(pos), to_dev(g["scf_q"])
+    H = ctx.tb_hamiltonian(m, xyz, n).cpu().numpy()
+    dH = float(np.max(np.abs(H[g["h_i"], g["h_j"]] - g["h_val"])))
+    q, eb, U, F, st = ctx.qmd_evaluate(m, xyz, n, w.n_occ, p.options("fp64"))
+    q, F = q.cpu().numpy(), F.cpu().numpy()
+    dq, dF = float(np.max(np.abs(q - g["q0"]))), float(np.max(np.abs(F - g["F0"])))
+    say(f"  max|dH| {dH:.1e}  max|dq| {dq:.1e}  dU {abs(U - float(g['U0'])):.1e}  "
+        f"d(2Tr DH) {abs(eb - float(g['e_band0'])):.1e}  max|dF| {dF:.1e} (max|F| {np.abs(g['F0']).max():.1f}); "
+        f"{st['iterations']} products")
+    assert dH <= 1e-12
+    assert dq <= 1e-9
+    assert abs(U - float(g["U0"])) <= 1e-8
+    assert abs(eb - float(g["e_band0"])) <= 1e-8
+    assert dF <= 1e-8
+
+
+def test_scf_start_1024_atoms_against_oracle(ctx):
+    """The SCF start on the GPU (linear mixing with beta = 1 from the +-4 e
+    checkerboard) reaches the oracle's self-consistent charges."""
+    import paper_1203_6836_amd as p
+    g = load("c1_xlbomd_n4096.npz")
+    w, m, pos, vel = c1_inputs()
+    say("case scf 1024 atoms vs oracle")
+    md = ctx.xlbomd_create(m, pos, vel, synth.checkerboard_charges(w.dims), sp2_opts=p.options("fp64"),
+                           scf_beta=1.0, scf_tol=1e-11, scf_max_iter=100)
+    it, res = md.xlbomd_info()
+    _, _, q, n = md.xlbomd_get()
+    md.close()
+    d = float(np.max(np.abs(n - g["scf_q"])))
+    say(f"  gpu {it} iterations (oracle {int(g['scf_iterations'])}), residual {res:.1e}, max|n - q_oracle| {d:.1e}")
+    assert d <= 1e-9
+    assert abs(it - int(g["scf_iterations"])) <= 1
+
+
+def test_xlbomd_1024_atoms_first_steps_against_oracle(ctx):
+    """The first ten XL-BOMD steps of the 1024-atom workload (velocity Verlet,
+    Eq. Verl_n with K = 5 dissipation, one FP64 SP2 solve per step) from the
+    oracle's self-consistent charges: positions, velocities, auxiliary charges
+    and the total energy of every step."""
+    import paper_1203_6836_amd as p
+    g = load("c1_xlbomd_n4096.npz")
+    w, m, pos, vel = c1_inputs()
+    say("case xlbomd 1024 atoms, 10 steps vs oracle")
+    md = ctx.xlbomd_create(m, pos, vel, g["scf_q"], sp2_opts=p.options("fp64"), scf_max_iter=0)
+    rec = md.xlbomd_run(len(g["etot"]))
+    xyz, v, q, n = md.xlbomd_get()
+    md.close()
+    et = np.array([r["etot"] for r in rec])
+    devs = {"pos": np.abs(xyz - g["pos"]).max(), "vel": np.abs(v - g["vel"]).max(),
+            "n": np.abs(n - g["hist"][0]).max(), "q": np.abs(q - g["q"]).max(), "etot": np.abs(et - g["etot"]).max()}
+    say("  " + "  ".join(f"max|d{k}| {float(x):.1e}" for k, x in devs.items()))
+    assert devs["pos"] <= 1e-9 and devs["vel"] <= 1e-9 and devs["n"] <= 1e-9 and devs["q"] <= 1e-9
+    assert devs["etot"] <= 1e-7
+    np.testing.assert_allclose([r["max_q_minus_n"] for r in rec], g["max_q_minus_n"], atol=1e-9)
+
+
+def sketch_error(D, g, n_atoms):
+    """(||D - D_ref||_F / sqrt(N) estimated from the stored probe vectors,
+    max charge deviation from the diagonal, max deviation over the sampled
+    32 x 32 blocks) against the oracle's stored solve."""
+    import torch
+    N = D.shape[0]
+    V = torch.from_numpy(synth.probe_vectors(N)).cuda()
+    E = (D @ V).cpu().numpy() - g["DV"]
+    est = float(np.linalg.norm(E) / np.sqrt(E.shape[1]) / np.sqrt(N))
+    dd = torch.diagonal(D).cpu().numpy() - g["diag"]
+    dq = float(np.max(np.abs(2.0 * dd.reshape(n_atoms, -1).sum(axis=1))))
+    blk = max(float(np.max(np.abs(D[32 * a:32 * a + 32, 32 * b:32 * b + 32].cpu().numpy() - ref)))
+              for a, b, ref in zip(g["block_i"], g["block_j"], g["blocks"]))
+    return est, dq, blk
+
+
+def test_blocksparse_n16384_fp64_against_oracle(ctx):
+    """The 16384-orbital elongated lattice with 32 x 32 blocks of Frobenius
+    norm below tau = 1e-5 dropped after X_0 and every update (Linear scaling
+    section, block form), FP64 products, against the oracle step by step:
+    products, branches, fill after every update, traces, and D (probe-vector
+    estimate of the Frobenius error, all charges, sampled blocks)."""
+    import torch
+    import paper_1203_6836_amd as p
+    g = load("c3_blocksparse_n16384.npz")
+    w = synth.SPARSE
+    say("case block-sparse N=16384 fp64 vs oracle")
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, to_dev(w.positions()))
+    D, st = ctx.sp2_density_matrix(H, w.n_occ, p.options("fp64", tau=float(g["tau"]), threshold=0))
+    n_upd = st["iterations"] - 1
+    fill_dev = float(np.max(np.abs(np.array(st["fill_hist"][:n_upd]) - g["fill"][1:1 + n_upd])))
+    est, dq, blk = sketch_error(D, g, w.n_atoms)
+    say(f"  products gpu={st['iterations']} oracle={int(g['iterations'])} status {st['status']} "
+        f"({g['status']}); max fill dev {fill_dev:.1e}; err/sqrtN ~{est:.1e}, max|dq| {dq:.1e}, "
+        f"block dev {blk:.1e}; fill {g['fill'][0]:.3f} -> {g['fill'][-1]:.3f}")
+    assert st["iterations"] == int(g["iterations"])
+    assert st["status"] == str(g["status"])
+    assert st["branches"] == [int(b) for b in g["branches"]]
+    assert fill_dev <= 1e-7
+    assert st["eps_min"] == pytest.approx(float(g["eps"][0]), abs=1e-10)
+    assert st["eps_max"] == pytest.approx(float(g["eps"][1]), abs=1e-10)
+    assert est <= 1e-9 and dq <= 1e-9 and blk <= 1e-9
+    del D, H
+    torch.cuda.empty_cache()
+
+
+def test_blocksparse_n16384_int8_against_oracle(ctx):
+    """The same thresholded solve with int8 digit-plane products against the
+    oracle's FP64 thresholded solve.  A block whose norm sits near tau can be
+    kept on one side and dropped on the other, so the bound is the int8
+    tolerance of the dense path (1e-6 per sqrt(N)) plus the threshold's
+    scale: err/sqrt(N) <= 5e-6 and charges within 5e-5 e."""
+    import torch
+    import paper_1203_6836_amd as p
+    g = load("c3_blocksparse_n16384.npz")
+    w = synth.SPARSE
+    say("case block-sparse N=16384 int8 vs oracle")
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, to_dev(w.positions()))
+    D, st = ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x", tau=float(g["tau"]), threshold=0))
+    n_upd = min(st["iterations"], int(g["iterations"])) - 1
+    fill_dev = float(np.max(np.abs(np.array(st["fill_hist"][:n_upd]) - g["fill"][1:1 + n_upd])))
+    est, dq, blk = sketch_error(D, g, w.n_atoms)
+    say(f"  products gpu={st['iterations']} oracle={int(g['iterations'])}; max fill dev {fill_dev:.1e}; "
+        f"err/sqrtN ~{est:.1e}, max|dq| {dq:.1e}, block dev {blk:.1e}")
+    assert abs(st["iterations"] - int(g["iterations"])) <= 1
+    assert fill_dev <= 1e-3
+    assert est <= 5e-6 and dq <= 5e-5
+    del D, H
+    torch.cuda.empty_cache()
+
+
+def test_forces_past_64_atoms_against_oracle(ctx):
+    """Forces and U at constant n on a 100-atom cluster: the per-atom pair
+    loops run a second pass over the other atoms (64 per pass)."""
+    MD = synth.MD_MODEL
+    pos = synth.lattice_positions((5, 5, 4), seed=9)
+    nat = len(pos)
+    say(f"case tb_forces {nat} atoms")
+    n = 0.2 * np.sin(np.arange(nat))
+    H = otb.hamiltonian(pos, n, MD)
+    D, _, _ = eig.density_matrix(H, 2 * nat)
+    q = observables.mulliken(D)
+    Hg = ctx.tb_hamiltonian(MD, to_dev(pos), to_dev(n)).cpu().numpy()
+    assert np.abs(Hg - H).max() <= 1e-12
+    F, U = ctx.tb_forces(MD, to_dev(pos), to_dev(D), to_dev(q), to_dev(n))
+    F_o = observables.forces(pos, n, D, MD)
+    dF = float(np.abs(F.cpu().numpy() - F_o).max())
+    say(f"  max|dF| {dF:.1e} (max|F| {np.abs(F_o).max():.1f}), dU {abs(U - observables.potential_energy(pos, n, D, MD)):.1e}")
+    assert dF <= 1e-9
+    assert U == pytest.approx(observables.potential_energy(pos, n, D, MD), abs=1e-8)
+
+
+def test_nonorth_forces_128_atoms_against_oracle(ctx):
+    """Non-orthogonal H[n], density matrix, overlap charges, U and forces at
+    constant n (with the overlap term) on a 128-atom lattice (N = 512)."""
+    import paper_1203_6836_amd as p
+    m = synth.MD_MODEL.with_(overlap_s0=0.05)
+    pos = synth.lattice_positions((4, 4, 8), seed=6)
+    nat = len(pos)
+    nocc = 2 * nat
+    n = np.random.default_rng(8).normal(0.0, 0.1, nat)
+    say(f"case nonorth forces {nat} atoms")
+    xyz, nd = to_dev(pos), to_dev(n)
+    S = ctx.tb_overlap(m, xyz)
+    H = ctx.tb_hamiltonian_nonorth(m, xyz, S, nd)
+    S_o = nonorth.overlap(pos, m)
+    H_o = nonorth.hamiltonian(pos, n, m, S_o)
+    assert np.abs(S.cpu().numpy() - S_o).max() <= 1e-13
+    assert np.abs(H.cpu().numpy() - H_o).max() <= 1e-12
+    D, st, _ = ctx.sp2_density_matrix_nonorth(H, S, nocc, p.options("fp64"))
+    q = ctx.sp2_mulliken_overlap(D, S, nat)
+    F, U = ctx.tb_forces_nonorth(m, xyz, D, H, q, nd)
+    rho_o, _, _, r = nonorth.density_matrix(H_o, S_o, nocc)
+    q_o = nonorth.mulliken(rho_o, S_o, m.z_val)
+    F_o = nonorth.forces(pos, n, rho_o, m, S_o)
+    U_o = nonorth.potential_energy(pos, n, rho_o, m, S_o)
+    dF = float(np.abs(F.cpu().numpy() - F_o).max())
+    dq = float(np.abs(q.cpu().numpy() - q_o).max())
+    say(f"  SP2 products gpu={st['iterations']} oracle={r.iterations}; max|dq| {dq:.1e}; max|dF| {dF:.1e} "
+        f"(max|F| {np.abs(F_o).max():.1f}), dU {abs(U - U_o):.1e}")
+    assert dq <= 1e-9
+    assert dF <= 1e-8
+    assert U == pytest.approx(U_o, abs=1e-8)
