@@ -8,9 +8,16 @@ of D, then Mulliken charges and the band energy.  H is built on the GPU
 
 Reported (one JSON line): useful SP2 TFLOP/s (2 N^3 per product, the
 GEMM-equivalent count) and solves/s of the reduced-precision path, the plain
-FP64 GPU path beside it, the error of D against the FP64 path, a roofline
-record of the dominant kernel measured with HIP events inside the timed
-region, and the CPU oracle timed on a bounded sample.
+FP64 GPU path beside it, the error of D against the FP64 path and against the
+oracle's stored FP64 solve, a roofline record of the dominant kernel measured
+with HIP events inside the timed region (2 N^3 per product over the kernel's
+mean launch time; what the matrix cores issue is a separate field), and the
+CPU oracle timed on a bounded sample (all host cores and one core).  Beside
+it: the 256-orbital FP64 solve, the 1024-atom XL-BOMD run (ms per step,
+total-energy statistics, the first steps against the oracle), the
+16384-orbital block-thresholded solve (fill per update, errors against dense
+FP64 and the oracle), the serving stream, the gapped-wire threshold scaling,
+the non-orthogonal solve and the finite-temperature Fermi operator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision int8x|fp64|bf16x2]
 """
@@ -79,23 +86,251 @@ def recorded_traffic(kernel: str):
         return None
 
 
-def cpu_baseline(H_np, n_occ, n_products=10):
-    """The oracle's SP2 loop (numpy/OpenBLAS) on a bounded sample: n_products products."""
+def cpu_baseline(H_np, n_occ, H0_np, n_occ0, n_products=6):
+    """The oracle as it stands, on the host: its SP2 loop (numpy/OpenBLAS FP64
+    products) on a bounded sample of the benchmarked solve, n_products products
+    on all host cores and one product on one core, and the whole small FP64
+    solve (N = 256) on all cores and on one core.  Returns (record, D of the
+    small solve)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
     from oracle import sp2 as osp2
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
     N = H_np.shape[0]
     t0 = time.perf_counter()
     osp2.sp2(H_np, n_occ, max_iter=n_products)
     dt = time.perf_counter() - t0
-    return {"value": round(2.0 * N ** 3 * n_products / dt / 1e12, 4), "unit": "TFLOP/s",
-            "cores": int(cores), "kind": "oracle",
-            "sample": f"{n_products} SP2 products (X^2 via numpy/OpenBLAS FP64) of the same N={N} "
-                      f"Hamiltonian, {dt:.1f} s, on {cpu_model()} ({os.cpu_count()} logical CPUs "
-                      f"visible); GEMM-equivalent 2N^3 flops per product"}
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        osp2.sp2(H_np, n_occ, max_iter=1)
+        dt1 = time.perf_counter() - t1
+    small = []
+    for lim in (None, 1):
+        with threadpool_limits(limits=lim):
+            t2 = time.perf_counter()
+            r0 = osp2.sp2(H0_np, n_occ0, tol=1e-10)
+            small.append((time.perf_counter() - t2) * 1e3)
+    N0 = H0_np.shape[0]
+    rec = {"value": round(2.0 * N ** 3 * n_products / dt / 1e12, 4), "unit": "TFLOP/s",
+           "cores": int(cores), "kind": "oracle",
+           "sample": f"{n_products} SP2 products (X^2 via numpy/OpenBLAS FP64) of the same N={N} "
+                     f"Hamiltonian, {dt:.1f} s, on {cpu_model()} ({os.cpu_count()} logical CPUs "
+                     f"visible); GEMM-equivalent 2N^3 flops per product",
+           "single_core": {"value": round(2.0 * N ** 3 / dt1 / 1e12, 4), "unit": "TFLOP/s", "cores": 1,
+                           "sample": f"1 SP2 product of the same N={N} Hamiltonian, {dt1:.1f} s"},
+           "fp64_n256_full_solve": {"ms_all_cores": round(small[0], 2), "ms_one_core": round(small[1], 2),
+                                    "products": r0.iterations, "n": N0, "status": r0.status}}
+    return rec, r0.D
+
+
+def golden(name):
+    """Stored oracle results of a full-size solve (written by
+    tests/golden/make_oracle_golden.py), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def against_golden(D, g, n_atoms):
+    """Error of a device D against the oracle's stored solve: ||D - D_ref||_F /
+    sqrt(N) estimated from the probe vectors, charges from the diagonal (all
+    atoms), and the largest deviation over the sampled 32 x 32 blocks."""
+    import numpy as np
+    import torch
+
+    import synth
+    N = D.shape[0]
+    V = torch.from_numpy(synth.probe_vectors(N)).to(D.device)
+    E = (D @ V).cpu().numpy() - g["DV"]
+    est = float(np.linalg.norm(E) / np.sqrt(E.shape[1]) / np.sqrt(N))
+    dd = torch.diagonal(D).cpu().numpy() - g["diag"]
+    dq = float(np.max(np.abs(2.0 * dd.reshape(n_atoms, -1).sum(axis=1))))
+    blk = 0.0
+    for a, b, ref in zip(g["block_i"], g["block_j"], g["blocks"]):
+        blk = max(blk, float(np.max(np.abs(D[32 * a:32 * a + 32, 32 * b:32 * b + 32].cpu().numpy() - ref))))
+    return {"err_per_sqrtN_est": est, "max_dq": dq, "max_block_dev": blk}
+
+
+def fp64_small(ctx, reps=20):
+    """The 64-atom (4 x 4 x 4) FP64 solve, N = 256, n_occ = 128, tolerance 1e-10:
+    milliseconds per solve (median of reps, launch-latency bound), products and
+    the residuals of D (idempotency, trace, commutator with H)."""
+    import numpy as np
+    import torch
+
+    import paper_1203_6836_amd as p
+    import synth
+
+    w = synth.SMALL
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, torch.from_numpy(w.positions()).cuda())
+    D = torch.empty_like(H)
+    opt = p.options("fp64")
+    ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    out = {"workload": "fp64_n256: 64-atom 4x4x4 lattice, N=256, n_occ=128, tol 1e-10",
+           "ms_per_solve": round(float(np.median(ts)), 3), "products": st["iterations"],
+           "idempotency": float(torch.linalg.norm(D @ D - D)), "trace_err": float(torch.trace(D)) - w.n_occ,
+           "commutator": float(torch.linalg.norm(H @ D - D @ H))}
+    log(f"  fp64_n256: {out}")
+    return out, H, D
+
+
+def energy_stats(et, dt_fs, n_atoms):
+    """Span, fluctuation about the linear fit and drift of a total-energy series (per atom)."""
+    import numpy as np
+    t = np.arange(len(et)) * dt_fs
+    a, b = np.polyfit(t, et, 1)
+    sig = float(np.std(et - (a * t + b)))
+    return {"etot_span_ev_per_atom": float(np.ptp(et)) / n_atoms, "sigma_ev_per_atom": sig / n_atoms,
+            "drift_ev_per_atom": float(abs(a) * t[-1]) / n_atoms}
+
+
+def xlbomd_c1(ctx, steps=200, quench_steps=400):
+    """The 1024-atom XL-BOMD workload (8 x 8 x 16 lattice, 300 K, dt = 0.25 fs,
+    K = 5, one SP2 solve per step, no SCF during the run): ms per MD step with
+    FP64 and int8 products from the self-consistent start, the total-energy
+    record of the literal jittered start (which relaxes and heats), the same
+    statistics after a quenched relaxation, and the first ten steps against
+    the oracle's stored trajectory."""
+    import numpy as np
+
+    import paper_1203_6836_amd as p
+    import synth
+
+    w = synth.XLBOMD
+    m = synth.MD_MODEL
+    pos = w.positions()
+    vel = synth.maxwell_velocities(w.n_atoms, 300.0, m.mass, seed=synth.XLBOMD_VEL_SEED)
+    guess = synth.checkerboard_charges(w.dims)
+    out = {"workload": "xlbomd_n4096: 1024-atom 8x8x16 lattice, N=4096, 300 K, dt 0.25 fs, K=5",
+           "steps": steps}
+    for prec in ("fp64", "int8x"):
+        log(f"xlbomd N=4096: {steps} steps, {prec}")
+        md = ctx.xlbomd_create(m, pos, vel, guess, sp2_opts=p.options(prec), scf_beta=1.0, scf_tol=1e-9,
+                               scf_max_iter=100)
+        it, _ = md.xlbomd_info()
+        t0 = time.perf_counter()
+        rec = md.xlbomd_run(steps)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        md.close()
+        et = np.array([r["etot"] for r in rec])
+        ek = np.array([r["ekin"] for r in rec])
+        row = {"ms_per_step": round(ms, 3), "scf_iterations": it,
+               "sp2_products_per_step": round(float(np.mean([r["sp2_iterations"] for r in rec])), 2),
+               "max_q_minus_n": max(r["max_q_minus_n"] for r in rec),
+               "ekin_first_ev": float(ek[0]), "ekin_max_ev": float(ek.max())}
+        row.update(energy_stats(et, 0.25, w.n_atoms))
+        out[prec] = row
+        log(f"  {row}")
+    # conservation from a relaxed start: quenched MD (velocities zeroed
+    # whenever F . v < 0), then NVE at 300 K
+    log(f"xlbomd N=4096: quench ({quench_steps} steps), then {steps} NVE steps")
+    md = ctx.xlbomd_create(m, pos, np.zeros_like(vel), guess, sp2_opts=p.options("fp64"), scf_beta=1.0,
+                           scf_tol=1e-9, scf_max_iter=100)
+    fmax, relaxed = quench(md, w.n_atoms, quench_steps)
+    md.close()
+    md = ctx.xlbomd_create(m, relaxed, vel, guess, sp2_opts=p.options("fp64"), scf_beta=1.0, scf_tol=1e-9,
+                           scf_max_iter=100)
+    rec = md.xlbomd_run(steps)
+    md.close()
+    q = {"quench_steps": quench_steps, "max_force_after_quench": fmax}
+    q.update(energy_stats(np.array([r["etot"] for r in rec]), 0.25, w.n_atoms))
+    out["quenched_start"] = q
+    log(f"  {q}")
+    g = golden("c1_xlbomd_n4096.npz")
+    if g is not None:
+        md = ctx.xlbomd_create(m, pos, vel, g["scf_q"], sp2_opts=p.options("fp64"), scf_max_iter=0)
+        rec = md.xlbomd_run(len(g["etot"]))
+        xyz, v, qq, n = md.xlbomd_get()
+        md.close()
+        out["vs_oracle_10_steps"] = {
+            "max_pos_dev_A": float(np.max(np.abs(xyz - g["pos"]))),
+            "max_vel_dev_A_per_fs": float(np.max(np.abs(v - g["vel"]))),
+            "max_n_dev": float(np.max(np.abs(n - g["hist"][0]))),
+            "max_etot_dev_ev": float(np.max(np.abs(np.array([r["etot"] for r in rec]) - g["etot"])))}
+        log(f"  vs oracle: {out['vs_oracle_10_steps']}")
+    return out
+
+
+def quench(md, nat, max_steps, ftol=1e-3):
+    """Relax by quenched MD: after each step the velocities are zeroed whenever
+    the power F . v is negative (checkpoint layout: header, then xyz,
+    vel, F).  Returns (largest force component, relaxed positions)."""
+    import numpy as np
+    import paper_1203_6836_amd as p
+    hdr, b3 = p.XL_CHECKPOINT_HEADER, 3 * nat * 8
+    fmax = float("inf")
+    for _ in range(max_steps):
+        md.xlbomd_run(1)
+        ck = bytearray(md.xlbomd_get_state())
+        v = np.frombuffer(bytes(ck[hdr + b3:hdr + 2 * b3]), dtype=np.float64)
+        F = np.frombuffer(bytes(ck[hdr + 2 * b3:hdr + 3 * b3]), dtype=np.float64)
+        fmax = float(np.abs(F).max())
+        if fmax < ftol:
+            break
+        if float(np.dot(F, v)) < 0.0:
+            ck[hdr + b3:hdr + 2 * b3] = bytes(b3)
+            md.xlbomd_set_state(bytes(ck))
+    xyz = np.frombuffer(bytes(ck[hdr:hdr + b3]), dtype=np.float64).reshape(nat, 3).copy()
+    return fmax, xyz
+
+
+def blocksparse_c3(ctx):
+    """The thresholded solve of the elongated 8 x 8 x 64 lattice (N = 16384):
+    32 x 32 blocks with Frobenius norm below 1e-5 dropped after every update,
+    int8 and FP64 products: ms per solve, kept-block fraction after every
+    update, error against the dense FP64 solve of the same H on the GPU and
+    against the oracle's stored thresholded solve."""
+    import torch
+
+    import paper_1203_6836_amd as p
+    import synth
+
+    w = synth.SPARSE
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, torch.from_numpy(w.positions()).cuda())
+    N = w.n_orb
+    log(f"block-sparse N={N}: dense FP64 reference")
+    Dd = torch.empty_like(H)
+    t0 = time.perf_counter()
+    _, sd = ctx.sp2_density_matrix(H, w.n_occ, p.options("fp64"), D_out=Dd)
+    torch.cuda.synchronize()
+    out = {"workload": "blocksparse_n16384: 4096-atom 8x8x64 lattice, N=16384, 32x32 blocks, tau=1e-5",
+           "dense_fp64": {"ms_per_solve": round((time.perf_counter() - t0) * 1e3, 1),
+                          "products": sd["iterations"]}}
+    g = golden("c3_blocksparse_n16384.npz")
+    D = torch.empty_like(H)
+    for prec in ("int8x", "fp64"):
+        opt = p.options(prec, tau=1e-5, threshold=0)
+        log(f"block-sparse N={N}: {prec}")
+        ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
+        torch.cuda.synchronize()
+        row = {"ms_per_solve": round((time.perf_counter() - t0) * 1e3, 1), "products": st["iterations"],
+               "fill_per_update": [round(f, 5) for f in st["fill_hist"][:st["iterations"] - 1]],
+               "err_vs_dense_fp64_per_sqrtN": float(torch.linalg.norm(D - Dd)) / N ** 0.5}
+        if g is not None:
+            row["vs_oracle"] = against_golden(D, g, w.n_atoms)
+            row["vs_oracle"]["same_products"] = int(g["iterations"]) == st["iterations"]
+            nf = min(len(g["fill"]), len(st["fill_hist"]))
+            row["vs_oracle"]["max_fill_dev"] = max(abs(float(a) - float(b))
+                                                   for a, b in zip(g["fill"][1:nf], st["fill_hist"][:nf - 1]))
+        out[prec] = row
+        log(f"  {prec}: {row['ms_per_solve']} ms, {row['products']} products, "
+            f"err vs dense {row['err_vs_dense_fp64_per_sqrtN']:.2e}")
+    del D, Dd, H
+    torch.cuda.empty_cache()
+    return out
 
 
 def serving(ctx, n_requests, rate):
@@ -379,7 +614,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the counter-calibration kernels and one solve per precision "
                          "(for rocprofv3 --pmc passes); prints no JSON")
-    ap.add_argument("--only", choices=["finite_temperature", "nonorthogonal"],
+    ap.add_argument("--only", choices=["finite_temperature", "nonorthogonal", "xlbomd_n4096",
+                                       "blocksparse_n16384", "fp64_n256"],
                     help="run only this leg and print its result as one JSON line (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -395,8 +631,10 @@ def main():
 
     if args.only:
         ctx = p.Context(0)
-        print(json.dumps({args.only: {"finite_temperature": finite_temperature,
-                                      "nonorthogonal": nonorthogonal}[args.only](ctx)}), flush=True)
+        legs = {"finite_temperature": finite_temperature, "nonorthogonal": nonorthogonal,
+                "xlbomd_n4096": xlbomd_c1, "blocksparse_n16384": blocksparse_c3,
+                "fp64_n256": lambda c: fp64_small(c)[0]}
+        print(json.dumps({args.only: legs[args.only](ctx)}), flush=True)
         ctx.close()
         return
     w = synth.MIXED
@@ -477,43 +715,50 @@ def main():
     iters = stats[-1]["iterations"]
     tflops = 2.0 * N ** 3 * iters / (ms * 1e-3) / 1e12
 
-    # error of D against the FP64 GPU path (itself pinned to the oracle in tests)
+    # error of D against the FP64 GPU path and against the oracle's stored
+    # FP64 solve of the same Hamiltonian (tests/golden/make_oracle_golden.py)
     err = float(torch.linalg.norm(D - D64)) / N ** 0.5
     dq = float((q - q64).abs().max())
     idem = float(torch.linalg.norm(D @ D - D))
+    g2 = golden("c2_mixed_n8192.npz")
+    vs_oracle = None
+    if g2 is not None:
+        vs_oracle = {prec: against_golden(D, g2, w.n_atoms), "fp64": against_golden(D64, g2, w.n_atoms),
+                     "oracle_products": int(g2["iterations"])}
 
-    # roofline of the dominant kernel: the product kernel of this precision
+    # roofline of the dominant kernel, the product kernel of this precision:
+    # algorithmic work 2 N^3 flops per SP2 product (the GEMM-equivalent count
+    # of the metric, one unit for every precision) over the kernel's mean
+    # launch time, against the peak of the instruction's own type
     k = 0 if prec == "fp64" else 1
     cnt = sum(s["prod_count"][k] for s in stats)
     kms = sum(s["prod_ms"][k] for s in stats) / max(cnt, 1)
+    useful = 2.0 * float(N) ** 3
     sym_flops = float(N) * N * (N + 1)          # distinct entries of a symmetric product
-    if prec == "int8x":
-        pairs = args.slices * (args.slices + 1) // 2
-        achieved = pairs * sym_flops / (kms * 1e-3) / 1e12
-        unit = "TOP/s"
-    elif prec == "bf16x2":
-        achieved = 3 * sym_flops / (kms * 1e-3) / 1e12
-        unit = "TFLOP/s"
-    else:
-        achieved = sym_flops / (kms * 1e-3) / 1e12
-        unit = "TFLOP/s"
+    achieved = useful / (kms * 1e-3) / 1e12
+    unit = "TOP/s" if prec == "int8x" else "TFLOP/s"
     kname = "k_gemm_f64" if prec == "fp64" else ("k_gemm_int8x" if prec == "int8x" else "k_gemm_bf16x2")
     traffic = recorded_traffic(kname) if kname in KERNEL_SOURCES else None
     if prec == "int8x" and args.slices != 5:
         traffic = None                      # counters are taken with 5 digit planes
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK[prec], "unit": unit,
             "frac": round(achieved / PEAK[prec], 4), "traffic": traffic,
+            "algorithmic_unit": "2 N^3 per SP2 product (GEMM-equivalent), every precision",
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "kernel": kname, "kernel_ms_avg": round(kms, 4), "launches": cnt}
-    # the same instruction's rate with no memory traffic, measured on this device
-    # (pseudo-random operands: the power-limited clock of real data)
+    # what the matrix cores actually issue: the upper tiles only (N^2 (N + 1)
+    # multiply-adds x 2), times the digit-plane products of the expansion
+    issue_mult = {"int8x": args.slices * (args.slices + 1) // 2, "bf16x2": 3, "fp64": 1}[prec]
+    issued = issue_mult * sym_flops / (kms * 1e-3) / 1e12
+    roof["mfma_issue"] = {"ops_per_launch": issue_mult * sym_flops, "rate": round(issued, 2), "unit": unit,
+                          "frac_of_peak": round(issued / PEAK[prec], 4)}
     if prec == "int8x":
         # the instruction's sustained rate on digit-range operands, measured here
         # (the power-limited clock makes it data dependent)
         log("int8 matrix-core rate probe")
         pm = ctx.sp2_int8_mfma_rate() / 1e12
-        roof["peak_measured"] = round(pm, 1)
-        roof["frac_of_measured"] = round(achieved / pm, 4)
+        roof["mfma_issue"]["peak_measured"] = round(pm, 1)
+        roof["mfma_issue"]["frac_of_measured"] = round(issued / pm, 4)
 
     out = {
         "metric": "SP2 TFLOP/s & solves/s (mixed vs FP64) at N=8192; p50/p99 served latency",
@@ -534,23 +779,33 @@ def main():
         "fp64_path": {"ms_per_solve": round(ms64, 2), "tflops": round(tflops64, 3),
                       "products": st64["iterations"],
                       "kernel": "k_gemm_f64", "kernel_ms_avg": round(kms64, 4),
-                      "kernel_tflops": round(sym_flops / (kms64 * 1e-3) / 1e12, 2),
-                      "kernel_frac_of_peak": round(sym_flops / (kms64 * 1e-3) / 1e12 / PEAK["fp64"], 4)},
+                      "kernel_tflops_2n3": round(useful / (kms64 * 1e-3) / 1e12, 2),
+                      "kernel_frac_2n3": round(useful / (kms64 * 1e-3) / 1e12 / PEAK["fp64"], 4),
+                      "mfma_issue_tflops": round(sym_flops / (kms64 * 1e-3) / 1e12, 2),
+                      "mfma_issue_frac_of_peak": round(sym_flops / (kms64 * 1e-3) / 1e12 / PEAK["fp64"], 4)},
         "speedup_vs_fp64": round(ms64 / ms, 3),
         "err_vs_fp64_per_sqrtN": err, "max_dq_vs_fp64": dq, "idempotency": idem,
+        "vs_oracle": vs_oracle,
         "roofline": roof,
     }
     if args.serve_requests > 0 and prec == "int8x":
         out["serving"] = serving(ctx, args.serve_requests, args.serve_rate)
+    log("fp64_n256 solve")
+    small, H0, D0 = fp64_small(ctx)
+    out["fp64_n256"] = small
     if not args.no_scaling:
         del D64
         torch.cuda.empty_cache()
+        out["xlbomd_n4096"] = xlbomd_c1(ctx)
+        out["blocksparse_n16384"] = blocksparse_c3(ctx)
         out["thresholded_scaling"] = thresholded_scaling(ctx)
         out["nonorthogonal"] = nonorthogonal(ctx)
         out["finite_temperature"] = finite_temperature(ctx)
     if not args.no_cpu:
         log("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(H.cpu().numpy(), nocc)
+        out["cpu_baseline"], D0_ref = cpu_baseline(H.cpu().numpy(), nocc, H0.cpu().numpy(), synth.SMALL.n_occ)
+        d0 = D0.cpu().numpy() - D0_ref
+        small["err_vs_oracle_per_sqrtN"] = float(np.linalg.norm(d0) / np.sqrt(d0.shape[0]))
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -394,11 +394,16 @@ typedef struct {
     double kT;          /* > 0: finite electronic temperature (units of H):
                            the density matrix is the Fermi operator of
                            sp2_fermi_density_matrix (canonical mu, Newton from
-                           the previous step's mu, |Tr D - n_occ| < 1e-9),
+                           the previous step's mu, |Tr D - n_occ| < fermi_tol),
                            and the record's epot is the free energy
                            U - kT S with S of sp2_fermi_entropy; 0: SP2.
                            Orthogonal basis only (EINVAL with overlap_s0 > 0) */
     int fermi_steps;    /* recursion steps of the Fermi operator (1..60)      */
+    double fermi_tol;   /* kT > 0: |Tr D - n_occ| bound of the mu solve per
+                           step; 0: 1e-9 max(1, N / 512) (X_0 quantises the
+                           trace at about 1e-10 per 512 orbitals)            */
+    int fermi_max_newton; /* kT > 0: mu passes per step before SP2_ENOCONV;
+                           0: 100                                            */
 } xlbomd_options;
 
 typedef struct {
@@ -434,16 +439,21 @@ sp2_status xlbomd_run(xlbomd *md, int n_steps, xlbomd_record *log);
 sp2_status xlbomd_get(xlbomd *md, double *xyz_host, double *vel_host,
                       double *q_host, double *n_host);
 /* Checkpoint: the complete integrator state (positions, velocities, forces,
- * charges q, the K + 1 auxiliary-charge history of Eq. Verl_n, step count)
- * as a versioned byte image in caller memory.  With buf NULL, *bytes is set
- * to the size needed; a smaller *bytes gives SP2_EINVAL (and the size).
- * Layout (version 1, native byte order): a 40-byte header {uint32 magic
+ * charges q, the K + 1 auxiliary-charge history of Eq. Verl_n, step count
+ * and, at kT > 0, the chemical potential that starts the next step's mu
+ * solve and the last kT S) as a versioned byte image in caller memory.  With
+ * buf NULL, *bytes is set to the size needed; a smaller *bytes gives
+ * SP2_EINVAL (and the size).
+ * Layout (version 2, native byte order): a 72-byte header {uint32 magic
  * 'XLBS', uint32 version, int32 n_atoms, int32 K, int64 step, int32 head,
- * int32 pad, double U}, then FP64 arrays xyz[3 n_atoms], vel[3 n_atoms],
- * F[3 n_atoms], q[n_atoms], n history[(K + 1) n_atoms] (slot `head` is n_t). */
+ * int32 fermi_steps (0 at kT = 0), double U, double mu (NaN at kT = 0),
+ * double kT S, double kT, double overlap_s0}, then FP64 arrays
+ * xyz[3 n_atoms], vel[3 n_atoms], F[3 n_atoms], q[n_atoms], n history
+ * [(K + 1) n_atoms] (slot `head` is n_t). */
 sp2_status xlbomd_get_state(const xlbomd *md, void *buf, size_t *bytes);
-/* Resume from a checkpoint of an integrator with the same n_atoms and K;
- * continuing is then bit-identical to continuing the original. */
+/* Resume from a checkpoint of an integrator with the same n_atoms, K, kT,
+ * fermi_steps and basis (overlap_s0), SP2_EINVAL otherwise; continuing is
+ * then bit-identical to continuing the original. */
 sp2_status xlbomd_set_state(xlbomd *md, const void *buf, size_t bytes);
 void xlbomd_destroy(xlbomd *md);
 

@@ -23,6 +23,8 @@ KAPPA_K5 = 1.82
 KAPPA_ZERO_T = 0.5 * KAPPA_K5
 KAPPA_FINITE_T = 0.75 * KAPPA_K5
 SP2_EBUDGET, SP2_ETIMEOUT, SP2_EDIVERGE = -6, -8, -9
+# bytes before the FP64 arrays (xyz, vel, F, q, n history) of an xlbomd checkpoint
+XL_CHECKPOINT_HEADER = 72
 PREC_FP64, PREC_INT8X, PREC_BF16X2 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "int8x": PREC_INT8X, "bf16x2": PREC_BF16X2}
 
@@ -79,7 +81,8 @@ class XLOptions(ctypes.Structure):
                 ("c", ctypes.c_double * 9), ("sp2", Sp2Options),
                 ("scf_beta", ctypes.c_double), ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int),
                 ("diverge_q", ctypes.c_double), ("overlap_s0", ctypes.c_double), ("overlap_lam", ctypes.c_double),
-                ("kT", ctypes.c_double), ("fermi_steps", ctypes.c_int)]
+                ("kT", ctypes.c_double), ("fermi_steps", ctypes.c_int),
+                ("fermi_tol", ctypes.c_double), ("fermi_max_newton", ctypes.c_int)]
 
 
 class XLRecord(ctypes.Structure):
@@ -447,23 +450,26 @@ class Context:
     def xlbomd_create(self, model, xyz, vel, n0=None, dt_fs=0.25, kappa=0.91, alpha=0.018,
                       c=(-6.0, 14.0, -8.0, -3.0, 4.0, -1.0), sp2_opts=None,
                       scf_beta=0.3, scf_tol=1e-10, scf_max_iter=None, diverge_q=1.0, kT=0.0,
-                      fermi_steps=16):
+                      fermi_steps=16, fermi_tol=0.0, fermi_max_newton=0):
         """scf_max_iter None: 0 (use n0 as given) if n0 is given, else 500 (SCF from zeros).
         diverge_q: stop with SP2_EDIVERGE when max|q - n| exceeds it (0: never).
         kT > 0: finite electronic temperature (Fermi operator with fermi_steps
         recursion steps; epot is then the free energy U - kT S); the paper's
-        finite-temperature runs use kappa=KAPPA_FINITE_T."""
+        finite-temperature runs use kappa=KAPPA_FINITE_T; fermi_tol and
+        fermi_max_newton bound the mu solve per step (0: the library's
+        defaults)."""
         if scf_max_iter is None:
             scf_max_iter = 0 if n0 is not None else 500
         return XLBOMD(self, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,
-                      scf_beta, scf_tol, scf_max_iter, diverge_q, kT, fermi_steps)
+                      scf_beta, scf_tol, scf_max_iter, diverge_q, kT, fermi_steps, fermi_tol, fermi_max_newton)
 
 
 class XLBOMD:
     """Handle of an xlbomd integrator; host numpy arrays in, host numpy arrays out."""
 
     def __init__(self, ctx, model, xyz, vel, n0, dt_fs, kappa, alpha, c, sp2_opts,
-                 scf_beta=0.3, scf_tol=1e-10, scf_max_iter=500, diverge_q=1.0, kT=0.0, fermi_steps=16):
+                 scf_beta=0.3, scf_tol=1e-10, scf_max_iter=500, diverge_q=1.0, kT=0.0, fermi_steps=16,
+                 fermi_tol=0.0, fermi_max_newton=0):
         self.ctx = ctx
         self.nat = len(xyz)
         o = XLOptions()
@@ -476,6 +482,7 @@ class XLBOMD:
         o.overlap_s0 = float(getattr(model, "overlap_s0", 0.0))
         o.overlap_lam = float(getattr(model, "overlap_lam", 0.5))
         o.kT, o.fermi_steps = float(kT), int(fermi_steps)
+        o.fermi_tol, o.fermi_max_newton = float(fermi_tol), int(fermi_max_newton)
         p = tb_params(model)
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)

@@ -1287,8 +1287,9 @@ static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true, fl
         // finite electronic temperature: the Fermi operator at the canonical mu
         // (from the previous step's), its entropy, charges and forces
         int passes = 0;
-        if ((s = sp2_fermi_density_matrix(c, N, m->H, (double)m->n_occ, m->o.kT, m->o.fermi_steps, 100, 1e-9, &m->mu,
-                                          m->D, &passes, nullptr)) != SP2_OK)
+        if ((s = sp2_fermi_density_matrix(c, N, m->H, (double)m->n_occ, m->o.kT, m->o.fermi_steps,
+                                          m->o.fermi_max_newton, m->o.fermi_tol, &m->mu, m->D, &passes, nullptr)) !=
+            SP2_OK)
             return s;
         double S = 0.0;
         if ((s = sp2_fermi_entropy(c, N, m->H, m->mu, m->o.kT, &S, nullptr)) != SP2_OK) return s;
@@ -1349,6 +1350,9 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
         return fail(c, SP2_EINVAL, "kT > 0 needs 1 <= fermi_steps <= 60 and the orthogonal basis");
     if (!(o->overlap_s0 >= 0.0) || (o->overlap_s0 > 0.0 && !(o->overlap_lam > 0.0)))
         return fail(c, SP2_EINVAL, "bad overlap parameters");
+    if (!(o->fermi_tol >= 0.0) || !std::isfinite(o->fermi_tol) || o->fermi_max_newton < 0 ||
+        o->fermi_max_newton > 1000)
+        return fail(c, SP2_EINVAL, "need fermi_tol >= 0 and 0 <= fermi_max_newton <= 1000");
     sp2_status s = check_options(c, o->sp2, 4 * n_atoms);
     if (s != SP2_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
@@ -1357,6 +1361,10 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
     m->c = c;
     m->p = *p;
     m->o = *o;
+    // finite-T defaults: Tr D to 1e-9 per 512 orbitals (X_0 quantises the
+    // trace at about 1e-10 per 512 orbitals for 16 recursion steps), 100 passes
+    if (m->o.fermi_tol == 0.0) m->o.fermi_tol = 1e-9 * std::max(1.0, (double)(4 * n_atoms) / 512.0);
+    if (m->o.fermi_max_newton == 0) m->o.fermi_max_newton = 100;
     m->nat = n_atoms;
     m->n_occ = (int)n_occ;
     const size_t N = 4 * (size_t)n_atoms;
@@ -1508,11 +1516,16 @@ struct XlCheckpoint {
     int32_t K;
     int64_t step;
     int32_t head;
-    int32_t pad_;
+    int32_t fermi_steps; // recursion steps of the Fermi operator (kT > 0)
     double U;
+    double mu;           // chemical potential of the last Fermi operator (NaN at kT = 0)
+    double ts;           // kT S of the last Fermi operator
+    double kT;           // electronic temperature of the integrator
+    double overlap_s0;   // > 0: non-orthogonal basis
 };
+static_assert(sizeof(XlCheckpoint) == 72, "checkpoint header layout");
 constexpr uint32_t kXlMagic = 0x53424c58u;
-constexpr uint32_t kXlVersion = 1;
+constexpr uint32_t kXlVersion = 2;
 size_t checkpoint_bytes(int nat, int K) {
     return sizeof(XlCheckpoint) + (size_t)(10 + K + 1) * nat * sizeof(double);
 }
@@ -1538,7 +1551,12 @@ extern "C" sp2_status xlbomd_get_state(const xlbomd* m, void* buf, size_t* bytes
     h.K = m->o.K;
     h.step = m->step;
     h.head = m->head;
+    h.fermi_steps = m->o.kT > 0.0 ? m->o.fermi_steps : 0;
     h.U = m->U;
+    h.mu = m->mu;
+    h.ts = m->ts;
+    h.kT = m->o.kT;
+    h.overlap_s0 = m->o.overlap_s0;
     char* out = static_cast<char*>(buf);
     std::memcpy(out, &h, sizeof(h));
     double* d = reinterpret_cast<double*>(out + sizeof(h));
@@ -1565,6 +1583,10 @@ extern "C" sp2_status xlbomd_set_state(xlbomd* m, const void* buf, size_t bytes)
         return fail(c, SP2_EINVAL, "checkpoint is for a different system size or history length");
     if (bytes != checkpoint_bytes(m->nat, m->o.K) || h.head < 0 || h.head > h.K || h.step < 0)
         return fail(c, SP2_EINVAL, "corrupt checkpoint");
+    // the same electronic model: temperature, Fermi recursion and basis
+    if (h.kT != m->o.kT || h.overlap_s0 != m->o.overlap_s0 ||
+        (m->o.kT > 0.0 && (h.fermi_steps != m->o.fermi_steps || !std::isfinite(h.mu))))
+        return fail(c, SP2_EINVAL, "checkpoint is for a different electronic temperature, Fermi recursion or basis");
     HIPCHK(c, hipSetDevice(c->device));
     const double* d = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(h));
     const size_t na = m->nat;
@@ -1578,6 +1600,8 @@ extern "C" sp2_status xlbomd_set_state(xlbomd* m, const void* buf, size_t bytes)
     m->step = h.step;
     m->head = h.head;
     m->U = h.U;
+    m->mu = h.mu;
+    m->ts = h.ts;
     return SP2_OK;
 }
 

@@ -220,3 +220,75 @@ def test_finite_temperature_xlbomd_matches_oracle(ctx):
     with pytest.raises(p.Sp2Error) as ei:
         ctx.xlbomd_create(m.with_(overlap_s0=0.05), pos, vel, n0, kT=0.5)
     assert ei.value.status == p.SP2_EINVAL
+
+
+def test_finite_temperature_checkpoint_resume_is_bit_identical(ctx):
+    """A checkpoint of a kT > 0 integrator carries the chemical potential
+    that starts the next step's mu solve: rewinding to it, or resuming it in a
+    second integrator, continues bit-identically; a checkpoint of a kT = 0
+    integrator is refused by a kT > 0 one and the other way round."""
+    import paper_1203_6836_amd as p
+    say("case fermi xlbomd checkpoint / resume 3x3x2 kT=0.5")
+    m = synth.MD_MODEL
+    pos = synth.lattice_positions((3, 3, 2), seed=4)
+    nat = len(pos)
+    vel = synth.maxwell_velocities(nat, 300.0, m.mass, seed=11)
+    # zero start charges without an SCF: q - n stays large, so the divergence
+    # check is off (the replay, not the physics, is under test)
+    kw = dict(sp2_opts=p.options("fp64"), kT=0.5, fermi_steps=16, kappa=p.KAPPA_FINITE_T, diverge_q=0.0)
+    md = ctx.xlbomd_create(m, pos, vel, np.zeros(nat), scf_max_iter=0, **kw)
+    md.xlbomd_run(4)
+    ck = md.xlbomd_get_state()
+    assert len(ck) >= p.XL_CHECKPOINT_HEADER
+    mu = np.frombuffer(ck[40:48], dtype=np.float64)[0]
+    assert np.isfinite(mu)
+    a = md.xlbomd_run(6)
+    xa = md.xlbomd_get()
+    md.xlbomd_set_state(ck)
+    b = md.xlbomd_run(6)
+    xb = md.xlbomd_get()
+    md2 = ctx.xlbomd_create(m, pos + 0.03, np.zeros_like(vel), np.zeros(nat), scf_max_iter=0, **kw)
+    md2.xlbomd_set_state(ck)
+    c = md2.xlbomd_run(6)
+    xc = md2.xlbomd_get()
+    assert a == b == c
+    for u, v, w in zip(xa, xb, xc):
+        assert np.array_equal(u, v) and np.array_equal(u, w)
+    md0 = ctx.xlbomd_create(m, pos, vel, np.zeros(nat), sp2_opts=p.options("fp64"), scf_max_iter=0,
+                            diverge_q=0.0)
+    ck0 = md0.xlbomd_get_state()
+    for target, state in ((md, ck0), (md0, ck)):
+        with pytest.raises(p.Sp2Error) as ei:
+            target.xlbomd_set_state(state)
+        assert ei.value.status == p.SP2_EINVAL
+    md3 = ctx.xlbomd_create(m, pos, vel, np.zeros(nat), scf_max_iter=0, **{**kw, "fermi_steps": 14})
+    with pytest.raises(p.Sp2Error) as ei:
+        md3.xlbomd_set_state(ck)
+    assert ei.value.status == p.SP2_EINVAL
+    for h in (md, md2, md0, md3):
+        h.close()
+
+
+def test_finite_temperature_xlbomd_2048_orbitals_newton_passes(ctx):
+    """XL-BOMD at kT = 0.5 eV on a 512-atom lattice (N = 2048) with the
+    default trace tolerance, which scales with N above the floor X_0 sets:
+    every step completes, and after the first the mu solve started from the
+    previous step's mu takes few passes."""
+    import paper_1203_6836_amd as p
+    say("case fermi xlbomd 8x8x8 kT=0.5, 6 steps")
+    m = synth.MD_MODEL
+    dims = (8, 8, 8)
+    pos = synth.lattice_positions(dims, seed=23)
+    nat = len(pos)
+    vel = synth.maxwell_velocities(nat, 300.0, m.mass, seed=24)
+    # the charge-ordered state's gap (about 18 eV) is far above kT: the SCF
+    # from the +-4 e checkerboard converges as at zero temperature
+    md = ctx.xlbomd_create(m, pos, vel, synth.checkerboard_charges(dims), sp2_opts=p.options("fp64"), kT=0.5,
+                           fermi_steps=16, kappa=p.KAPPA_FINITE_T, scf_beta=1.0, scf_tol=1e-7, scf_max_iter=100)
+    it, res = md.xlbomd_info()
+    rec = md.xlbomd_run(6)
+    md.close()
+    passes = [r["sp2_iterations"] for r in rec]
+    say(f"  SCF {it} iterations (res {res:.1e}); Newton passes per step {passes}, "
+        f"max|q-n| {max(r['max_q_minus_n'] for r in rec):.1e}")
+    assert max(passes[1:]) <= 8

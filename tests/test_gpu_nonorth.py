@@ -202,7 +202,8 @@ def test_nonorth_xlbomd_trajectory_matches_oracle(ctx):
 def quench(md, nat, max_steps=1500, ftol=1e-6):
     """Relax by quenched MD (velocities zeroed whenever F . v < 0; checkpoint
     layout: 40-byte header, then xyz, vel, F)."""
-    hdr, b3 = 40, 3 * nat * 8
+    import paper_1203_6836_amd as p
+    hdr, b3 = p.XL_CHECKPOINT_HEADER, 3 * nat * 8
     fmax = np.inf
     for _ in range(max_steps):
         md.xlbomd_run(1)

@@ -130,9 +130,10 @@ def test_xlbomd_1024_atoms_quenched_start_conserves(ctx):
 
 def quench(md, nat, max_steps=1500, ftol=1e-6):
     """Relax by quenched MD: after each step the velocities are zeroed whenever
-    the power F . v is negative (checkpoint layout: 40-byte header, then xyz,
+    the power F . v is negative (checkpoint layout: header, then xyz,
     vel, F).  Returns the largest force component reached."""
-    hdr, b3 = 40, 3 * nat * 8
+    import paper_1203_6836_amd as p
+    hdr, b3 = p.XL_CHECKPOINT_HEADER, 3 * nat * 8
     fmax = np.inf
     for _ in range(max_steps):
         md.xlbomd_run(1)
