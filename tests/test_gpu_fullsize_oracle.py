@@ -163,9 +163,10 @@ def test_blocksparse_n16384_fp64_against_oracle(ctx):
 def test_blocksparse_n16384_int8_against_oracle(ctx):
     """The same thresholded solve with int8 digit-plane products against the
     oracle's FP64 thresholded solve.  A block whose norm sits near tau can be
-    kept on one side and dropped on the other, so the bound is the int8
-    tolerance of the dense path (1e-6 per sqrt(N)) plus the threshold's
-    scale: err/sqrt(N) <= 5e-6 and charges within 5e-5 e."""
+    kept on one side and dropped on the other (the fill per update differs by
+    a few blocks), so the bound on D is twice the reduced-precision tolerance
+    of the dense path, 2e-6 per sqrt(N) (measured 6.3e-7; the probe-vector
+    estimate carries a spread of its own), and charges within 1e-6 e."""
     import torch
     import paper_1203_6836_amd as p
     g = load("c3_blocksparse_n16384.npz")
@@ -179,8 +180,8 @@ def test_blocksparse_n16384_int8_against_oracle(ctx):
     say(f"  products gpu={st['iterations']} oracle={int(g['iterations'])}; max fill dev {fill_dev:.1e}; "
         f"err/sqrtN ~{est:.1e}, max|dq| {dq:.1e}, block dev {blk:.1e}")
     assert abs(st["iterations"] - int(g["iterations"])) <= 1
-    assert fill_dev <= 1e-3
-    assert est <= 5e-6 and dq <= 5e-5
+    assert fill_dev <= 1e-4
+    assert est <= 2e-6 and dq <= 1e-6
     del D, H
     torch.cuda.empty_cache()
 
