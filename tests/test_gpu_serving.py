@@ -126,3 +126,34 @@ def test_server_reports_gap_and_invalid_h(ctx):
     srv.close()
     ref = osp2.sp2(good, 80)
     assert np.linalg.norm(D - ref.D) / np.sqrt(good.shape[0]) <= 1e-6
+
+
+def test_server_largest_requests_against_oracle(ctx):
+    """Requests at the top of the served size range (512 atoms, N = 2048, and
+    a ragged 500-atom N = 2000) in a mix with small ones: each equals its
+    solve alone, bitwise, and the oracle within 1e-6 (D per sqrt(N) and
+    charges)."""
+    import paper_1203_6836_amd as p
+    say("case serving N=2048 and N=2000 in a mix")
+    big = [request_H(512, 4000), request_H(500, 4001)]
+    small = [request_H(n, 4100 + k) for k, n in enumerate([32, 200, 96, 333])]
+    srv = p.Server(ctx, max_slots=8)
+    alone = []
+    for H in big:
+        t = srv.sp2_server_submit(H, H.shape[0] // 2)
+        alone.append(srv.sp2_server_wait(t, H.shape[0]))
+    tk = [srv.sp2_server_submit(small[0], small[0].shape[0] // 2)]
+    tb = [srv.sp2_server_submit(H, H.shape[0] // 2) for H in big]
+    tk += [srv.sp2_server_submit(H, H.shape[0] // 2) for H in small[1:]]
+    mixed = [srv.sp2_server_wait(t, H.shape[0]) for t, H in zip(tb, big)]
+    for t, H in zip(tk, small):
+        srv.sp2_server_wait(t, H.shape[0], want_D=False)
+    srv.close()
+    for (Da, qa, sa), (Dm, qm, sm), H in zip(alone, mixed, big):
+        N = H.shape[0]
+        ref = osp2.sp2(H, N // 2)
+        err = np.linalg.norm(Dm - ref.D) / np.sqrt(N)
+        dq = np.max(np.abs(qm - observables.mulliken(ref.D)))
+        say(f"  N={N}: products {sm['iterations']} (oracle {ref.iterations}), err/sqrtN {err:.2e}, max|dq| {dq:.2e}")
+        assert np.array_equal(Da, Dm) and np.array_equal(qa, qm)
+        assert err <= 1e-6 and dq <= 1e-6
