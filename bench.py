@@ -606,6 +606,8 @@ def main():
     ap.add_argument("--precision", default="int8x", choices=["int8x", "fp64", "bf16x2"])
     ap.add_argument("--slices", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--idem-tol", type=float, default=1e-10,
+                    help="stop tolerance on ||X^2 - X||_F for both paths of the main solve")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -647,6 +649,7 @@ def main():
 
     def solve(prec, Dout):
         opts = p.options(prec, slices=args.slices) if prec == "int8x" else p.options(prec)
+        opts.idem_tol = args.idem_tol
         Dout, st = ctx.sp2_density_matrix(H, nocc, opts, D_out=Dout)
         q = ctx.sp2_mulliken(Dout, w.n_atoms)
         e = ctx.sp2_band_energy(Dout, H)
@@ -784,6 +787,9 @@ def main():
                       "mfma_issue_tflops": round(sym_flops / (kms64 * 1e-3) / 1e12, 2),
                       "mfma_issue_frac_of_peak": round(sym_flops / (kms64 * 1e-3) / 1e12 / PEAK["fp64"], 4)},
         "speedup_vs_fp64": round(ms64 / ms, 3),
+        "idem_tol": args.idem_tol,
+        "idem_last": {prec: [float(f"{e:.3g}") for e in stats[-1]["idem_hist"][-6:]],
+                      "fp64": [float(f"{e:.3g}") for e in st64["idem_hist"][-6:]]},
         "err_vs_fp64_per_sqrtN": err, "max_dq_vs_fp64": dq, "idempotency": idem,
         "vs_oracle": vs_oracle,
         "roofline": roof,

@@ -47,9 +47,11 @@ typedef enum {
 typedef enum {
     SP2_PREC_FP64 = 0,   /* FP64 MFMA products                                   */
     SP2_PREC_INT8X = 1,  /* FP64 master X split into `slices` row-scaled int8
-                            digit planes; all digit products with level t+u <
-                            slices on int8 MFMA with exact int32 accumulation,
-                            levels combined in FP64                             */
+                            digit planes (8 bits per digit while
+                            (slices - 1) 2^14 N < 2^31, else 7); all digit
+                            products with level t+u < slices on int8 MFMA
+                            with exact int32 accumulation, levels combined
+                            in FP64                                             */
     SP2_PREC_BF16X2 = 2  /* BF16 hi+lo split with FP32 MFMA accumulation, FP32
                             master, then `fp32_tail` FP32 iterations            */
 } sp2_precision;
@@ -60,9 +62,12 @@ typedef struct {
     double idem_tol;     /* stop when ||X_n^2 - X_n||_F < idem_tol (1e-10)       */
     double stall_tol;    /* also stop when n >= 4, e_n >= r e_{n-2}, e_n <
                             stall_tol (idempotency error at its floor; 1e-2);
-                            r = 1, or when tau > 0 r = 1/2 and the bound is
-                            max(stall_tol, 0.1) (the floor set by the
-                            threshold keeps creeping down and grows with N) */
+                            r = 1 for FP64 and BF16X2 products without a
+                            threshold; r = 1/2 for INT8X products (their
+                            rounding floor) and whenever tau > 0, where the
+                            bound is also max(stall_tol, 0.1) (the floor set
+                            by the threshold keeps creeping down and grows
+                            with N) */
     int fp64_head;       /* INT8X: first products done in FP64 (default 0)      */
     int slices;          /* INT8X: digit planes, 2..6 (default 5)                */
     int fp32_tail;       /* BF16X2: FP32 iterations after the BF16 stage stalls

@@ -8,7 +8,12 @@ method without printing it, and leaves mu open):
 
 * definition: f(H) = V diag(f_i) V^T from the eigen-decomposition of H,
   f_i = 1 / (1 + exp(beta (e_i - mu))), with mu the canonical chemical
-  potential, sum_i f_i = N_occ (solved by bisection);
+  potential, sum_i f_i = N_occ (solved by bisection); the eigenpairs come
+  from the oracle's own Jacobi solver (solver="jacobi", the default) or, for
+  the few full-size comparisons where Jacobi is too slow (N > 600), from the
+  library eigensolver (solver="lapack", named at the call);
+* the inverse inside the recursion is a library primitive (numpy's inverse),
+  taken as one step of the printed formula;
 * the recursion: with y = beta (H - mu I) / 2^(n+2), X_0 = I/2 - y; then n
   times X_{k+1} = X_k^2 (X_k^2 + (I - X_k)^2)^(-1).  The ratio (I - X)/X
   squares at every step and starts at (I/2 + y)/(I/2 - y) ~ exp(4y), so X_n
@@ -33,7 +38,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import observables, sp2, tb
+from . import eig, observables, sp2, tb
 
 KB_EV_PER_K = 8.617333262e-5
 
@@ -57,10 +62,19 @@ def canonical_mu(e, n_occ, beta, tol=1e-14):
     return 0.5 * (lo + hi)
 
 
-def fermi_density(H, n_occ, kT):
+def eigenpairs(A, solver="jacobi"):
+    """Ascending eigenvalues and eigenvectors (columns) of symmetric A."""
+    if solver == "jacobi":
+        return eig.jacobi_eigh(A)
+    if solver == "lapack":
+        return np.linalg.eigh(A)
+    raise ValueError(solver)
+
+
+def fermi_density(H, n_occ, kT, solver="jacobi"):
     """(D, mu, occupations) of the definition (kT in eV)."""
     beta = 1.0 / kT
-    e, V = np.linalg.eigh(H)
+    e, V = eigenpairs(H, solver)
     mu = canonical_mu(e, n_occ, beta)
     f = fermi_occupations(e, mu, beta)
     return (V * f) @ V.T, mu, f
@@ -110,8 +124,8 @@ def entropy(f):
     return -2.0 * float(s.sum())
 
 
-def free_energy(pos, n, m, n_occ, kT):
+def free_energy(pos, n, m, n_occ, kT, solver="jacobi"):
     """(A, D, mu): A = U(R; n) - kT S / k_B with D the canonical Fermi operator of H[n]."""
     H = tb.hamiltonian(pos, n, m)
-    D, mu, f = fermi_density(H, n_occ, kT)
+    D, mu, f = fermi_density(H, n_occ, kT, solver)
     return observables.potential_energy(pos, n, D, m) - kT * entropy(f), D, mu

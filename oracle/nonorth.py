@@ -14,7 +14,10 @@ Readings (the paper leaves these open):
   with the hopping's tail, with the sign pattern opposite to the hopping's
   (overlap and hopping of a bonding pair have opposite signs);
 * Z: any congruence factor is allowed; the Loewdin factor S^(-1/2), the
-  symmetric one, is used (then rho does not depend on the choice);
+  symmetric one, is used (then rho does not depend on the choice), from the
+  eigenpairs of S by the oracle's Jacobi solver (solver="jacobi", the
+  default) or, for the comparisons at N > 600, the library eigensolver
+  (solver="lapack", named at the call);
 * charges: Mulliken, q_i = 2 sum_{alpha in i} (rho S)_{i alpha, i alpha} - z_i.
   The paper names them Mulliken charges and differentiates them as
   2 sum (rho S_R) (the charge-derivative equation), which is the derivative
@@ -43,7 +46,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import observables, sp2, tb
+from . import eig, observables, sp2, tb
 
 
 def overlap(pos, m):
@@ -62,16 +65,21 @@ def overlap(pos, m):
     return S
 
 
-def loewdin_factor(S):
+def loewdin_factor(S, solver="jacobi"):
     """Z = S^(-1/2) from the eigen-decomposition of S (Z^T S Z = I)."""
-    w, V = np.linalg.eigh(S)
+    if solver == "jacobi":
+        w, V = eig.jacobi_eigh(S)
+    elif solver == "lapack":
+        w, V = np.linalg.eigh(S)
+    else:
+        raise ValueError(solver)
     return (V / np.sqrt(w)) @ V.T
 
 
-def density_matrix(H, S, n_occ, **sp2_kw):
+def density_matrix(H, S, n_occ, solver="jacobi", **sp2_kw):
     """(rho, rho_perp, Z, SP2 result): SP2 of H_perp = Z^T H Z, then
-    rho = Z rho_perp Z^T."""
-    Z = loewdin_factor(S)
+    rho = Z rho_perp Z^T (solver: how the Loewdin factor is formed)."""
+    Z = loewdin_factor(S, solver)
     Hp = Z.T @ H @ Z
     Hp = 0.5 * (Hp + Hp.T)
     r = sp2.sp2(Hp, n_occ, **sp2_kw)

@@ -64,10 +64,14 @@ def _nonorth(m):
 
 
 def nonorth_density(H, S, n_occ, solver="sp2", tol=1e-10):
+    """rho of the generalized eigenproblem H c = e S c (Eq. DM_perp with the
+    Loewdin factor): solver "jacobi" takes the projector of Z H Z by Jacobi,
+    "sp2" by the oracle SP2; Z from Jacobi eigenpairs of S in both."""
     if solver == "jacobi":
-        import scipy.linalg
-        _, C = scipy.linalg.eigh(H, S)
-        return C[:, :n_occ] @ C[:, :n_occ].T
+        Z = nonorth.loewdin_factor(S)
+        Hp = Z @ H @ Z
+        Dp, _, _ = eig.density_matrix(0.5 * (Hp + Hp.T), n_occ)
+        return Z @ Dp @ Z
     rho, _, _, r = nonorth.density_matrix(H, S, n_occ, tol=tol)
     if r.status not in ("converged", "stalled"):
         raise RuntimeError(f"oracle SP2 ended with status {r.status}")

@@ -343,9 +343,11 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
     a.idem_tol = o.idem_tol;
     // with a threshold the floor of e_n grows with N; below 0.1 every
     // eigenvalue is within 0.113 of 0 or 1, where two products of opposite
-    // branches shrink its deviation by more than half
+    // branches shrink its deviation by more than half.  The int8 products'
+    // rounding floor is detected the same way (an error that fails to halve
+    // over two products has reached it)
     a.stall_tol = o.tau > 0.0 ? std::max(o.stall_tol, 0.1) : o.stall_tol;
-    a.stall_ratio = o.tau > 0.0 ? 0.5 : 1.0;
+    a.stall_ratio = (o.tau > 0.0 || int8x) ? 0.5 : 1.0;
     a.max_iter = o.max_iter;
     a.fp64_head = (int8x || bf16x) ? o.fp64_head : -1;
     a.fp32_tail = o.fp32_tail;

@@ -1,16 +1,28 @@
-// Reduced-precision SP2 product on int8 MFMA with exact integer accumulation.
+// Reduced-precision SP2 product on int8 MFMA with exact integer accumulation
+// (an error-free split of FP64 operands into integer slices whose products
+// are exact in integer arithmetic, the Ozaki scheme for matrix products).
 //
 // The FP64 master X_n is split row by row into fixed-point digit planes:
 // with s_i = 2^e_i >= max_j |X_ij| (a power of two, so the scaling is exact),
-// y = X_ij / s_i in (-1, 1) is written as y ~ sum_t d_t 2^-(6 + 7 t) with
-// integer digits |d_t| <= 64 taken by successive round-to-nearest of the
-// remainder (each remainder is exact in FP64).  Because X is symmetric,
-//     (X^2)_ij = sum_k X_ik X_jk ~ s_i s_j sum_{t,u} 2^-(12 + 7(t+u)) sum_k d_t[i,k] d_u[j,k],
+// y = X_ij / s_i in (-1, 1) is written as y ~ sum_t d_t 2^-(6 + W t), W bits
+// per digit (digit_bits):
+//   W = 8: the integer m = rint(y 2^(8S - 2)) (|m| <= 2^(8S - 2)) is written
+//     in base 256 with digits in [-128, 127] (the top one in [-64, 64]): the
+//     bytes of m + 0x80..80 (S bytes), each read back as a byte minus 128.
+//     One rounding, error <= 2^-(8S - 1); every level accumulator fits int32
+//     while (S - 1) 2^14 K < 2^31;
+//   W = 7: digits |d_t| <= 64 taken by successive round-to-nearest of the
+//     remainder (each remainder exact in FP64), for larger K.
+// Because X is symmetric,
+//     (X^2)_ij = sum_k X_ik X_jk ~ s_i s_j sum_{t,u} 2^-(12 + W(t+u)) sum_k d_t[i,k] d_u[j,k],
 // i.e. every digit product reads contiguous rows of the digit planes for both
 // operands.  Products with t + u < slices are kept; those of one level L = t+u
-// share an int32 accumulator, which is exact (|d| <= 64, at most 6 products
-// per level, K <= 65536: |acc| < 2^31).  Levels are combined in FP64 in the
-// epilogue, which then applies the SP2 update exactly like the FP64 product.
+// share an int32 accumulator, which is exact (W = 8: |acc| <= L 2^14 K < 2^31
+// by the choice of W; W = 7: |d| <= 64, at most 6 products per level,
+// K <= 65536).  Levels are combined in FP64 in the epilogue, which then
+// applies the SP2 update exactly like the FP64 product.  The plane count may
+// change from product to product (the host picks each launch's), so the
+// digit width is a function of (ld, S) that encode and product agree on.
 //
 // Work layout, storage and staging: see the comments at the kernels.
 #include <atomic>
@@ -42,12 +54,60 @@ __device__ __forceinline__ double wred_sum(double v) {
 __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 
 // --------------------------------------------------------------- encoding
+// Bits per digit of an S-plane split of operands with K = ld: 8 while every
+// level accumulator provably fits int32, else 7.
+__host__ __device__ __forceinline__ int digit_bits(int ld, int S) {
+    return (long long)(S - 1) * 16384LL * ld < 2147483648LL ? 8 : 7;
+}
+
+// W = 8: m + 0x80..80 (S bytes) for m = rint(y 2^(8S - 2)), |y| < 1; byte
+// S - 1 - t of it XOR 0x80 is digit t as an int8.
+__device__ __forceinline__ unsigned long long excess_digits(double y, int S) {
+    const long long m = (long long)rint(y * ldexp(1.0, 8 * S - 2));
+    return (unsigned long long)m + (0x8080808080808080ull >> (8 * (8 - S)));
+}
+__device__ __forceinline__ unsigned excess_digit(unsigned long long u, int S, int t) {
+    return (unsigned)((u >> (8 * (S - 1 - t))) & 0xFFull) ^ 0x80u;
+}
+
+// Digits of eight values y (|y| < 1) into eight packed bytes per plane.
+template <int S>
+__device__ __forceinline__ void pack_digits8(double (&y)[8], int W, unsigned long long (&packed)[S]) {
+    if (W == 8) {
+        unsigned long long u[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) u[q] = excess_digits(y[q], S);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            unsigned long long p = 0ull;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) p |= (unsigned long long)excess_digit(u[q], S, t) << (8 * q);
+            packed[t] = p;
+        }
+        return;
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        const double w = ldexp(1.0, 6 + 7 * t);      // digit weight 2^-(6+7t)
+        const double iw = ldexp(1.0, -(6 + 7 * t));
+        unsigned long long p = 0ull;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double d = rint(y[q] * w);        // |d| <= 64
+            y[q] -= d * iw;                          // exact remainder
+            p |= (unsigned long long)(uint8_t)(int8_t)d << (8 * q);
+        }
+        packed[t] = p;
+    }
+}
+
 // One wave per padded row: row scale and `slices` digit planes of columns
 // [c0, c1) (multiples of 32; the row is zero outside them).
 template <int S>
 __device__ __forceinline__ void encode_row(const double* __restrict__ X, int ld, int i, int lane, int8_t* __restrict__ digits,
                            double* __restrict__ scale, int c0, int c1) {
     const double* row = X + (size_t)i * ld;
+    const int W = digit_bits(ld, S);
     double m = 0.0;
     for (int j = c0 + 8 * lane; j < c1; j += 512) {
         const double4 a = *reinterpret_cast<const double4*>(row + j);
@@ -70,19 +130,10 @@ __device__ __forceinline__ void encode_row(const double* __restrict__ X, int ld,
         y[0] = a.x * inv; y[1] = a.y * inv; y[2] = a.z * inv; y[3] = a.w * inv;
         y[4] = b.x * inv; y[5] = b.y * inv; y[6] = b.z * inv; y[7] = b.w * inv;
         const size_t off = (rowblk + (j >> 5)) * 1024 + r32 * 32 + 16 * (((j >> 4) & 1) ^ dswz(r32)) + (j & 15);
+        unsigned long long packed[S];
+        pack_digits8<S>(y, W, packed);
 #pragma unroll
-        for (int t = 0; t < S; ++t) {
-            const double w = ldexp(1.0, 6 + 7 * t);      // digit weight 2^-(6+7t)
-            const double iw = ldexp(1.0, -(6 + 7 * t));
-            unsigned long long packed = 0ull;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const double d = rint(y[q] * w);        // |d| <= 64
-                y[q] -= d * iw;                          // exact remainder
-                packed |= (unsigned long long)(uint8_t)(int8_t)d << (8 * q);
-            }
-            *reinterpret_cast<unsigned long long*>(digits + t * plane + off) = packed;
-        }
+        for (int t = 0; t < S; ++t) *reinterpret_cast<unsigned long long*>(digits + t * plane + off) = packed[t];
     }
 }
 
@@ -150,19 +201,10 @@ __global__ __launch_bounds__(256) void k_encode_int8_reg(const double* __restric
             double y[8] = {va[c].x * inv, va[c].y * inv, va[c].z * inv, va[c].w * inv,
                            vb[c].x * inv, vb[c].y * inv, vb[c].z * inv, vb[c].w * inv};
             const size_t off = (rowblk + (j >> 5)) * 1024 + r32 * 32 + 16 * (((j >> 4) & 1) ^ dswz(r32)) + (j & 15);
+            unsigned long long packed[S];
+            pack_digits8<S>(y, digit_bits(ld, S), packed);
 #pragma unroll
-            for (int t = 0; t < S; ++t) {
-                const double wt = ldexp(1.0, 6 + 7 * t);
-                const double iw = ldexp(1.0, -(6 + 7 * t));
-                unsigned long long packed = 0ull;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const double d = rint(y[q] * wt);
-                    y[q] -= d * iw;
-                    packed |= (unsigned long long)(uint8_t)(int8_t)d << (8 * q);
-                }
-                *reinterpret_cast<unsigned long long*>(digits + t * plane + off) = packed;
-            }
+            for (int t = 0; t < S; ++t) *reinterpret_cast<unsigned long long*>(digits + t * plane + off) = packed[t];
         }
     }
 }
@@ -176,9 +218,21 @@ __global__ __launch_bounds__(256) void k_encode_int8_reg(const double* __restric
 // Same digits as encode_row (same scale, same per-element arithmetic).  The
 // diagonal blocks also write the row scales and clear rmax_next, which the
 // next product fills.
-__device__ __forceinline__ void pack_digits4(const double (&x)[4], double inv, int S, int8_t* __restrict__ out,
+__device__ __forceinline__ void pack_digits4(const double (&x)[4], double inv, int S, int W, int8_t* __restrict__ out,
                                              size_t plane) {
     double y[4] = {x[0] * inv, x[1] * inv, x[2] * inv, x[3] * inv};
+    if (W == 8) {
+        unsigned long long u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] = excess_digits(y[q], S);
+        for (int t = 0; t < S; ++t) {
+            uint32_t packed = 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) packed |= excess_digit(u[q], S, t) << (8 * q);
+            *reinterpret_cast<uint32_t*>(out + t * plane) = packed;
+        }
+        return;
+    }
     for (int t = 0; t < S; ++t) {
         const double wt = ldexp(1.0, 6 + 7 * t);
         const double iw = ldexp(1.0, -(6 + 7 * t));
@@ -227,7 +281,7 @@ __global__ __launch_bounds__(256) void k_encode_int8_upper(const double* __restr
     const double x[4] = {v.x, v.y, v.z, v.w};
     double sc;
     const double inv = scale_inv(rm[I * 32 + r], &sc);
-    pack_digits4(x, inv, S, digits + ((size_t)I * nb + J) * 1024 + r * 32 + 16 * ((c0 >> 4) ^ dswz(r)) + (c0 & 15),
+    pack_digits4(x, inv, S, digit_bits(ld, S), digits + ((size_t)I * nb + J) * 1024 + r * 32 + 16 * ((c0 >> 4) ^ dswz(r)) + (c0 & 15),
                  plane);
     if (I == J) {
         if ((tid & 7) == 0) {
@@ -245,7 +299,7 @@ __global__ __launch_bounds__(256) void k_encode_int8_upper(const double* __restr
     // row J*32 + r of X, columns I*32 + c0 .. + 3 = column r of the block, rows c0 ..
     const double xt[4] = {T[c0][r], T[c0 + 1][r], T[c0 + 2][r], T[c0 + 3][r]};
     const double invt = scale_inv(rm[J * 32 + r], nullptr);
-    pack_digits4(xt, invt, S, digits + ((size_t)J * nb + I) * 1024 + r * 32 + 16 * ((c0 >> 4) ^ dswz(r)) + (c0 & 15),
+    pack_digits4(xt, invt, S, digit_bits(ld, S), digits + ((size_t)J * nb + I) * 1024 + r * 32 + 16 * ((c0 >> 4) ^ dswz(r)) + (c0 & 15),
                  plane);
 }
 
@@ -477,11 +531,12 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     // end, the same order in both layouts (so both give identical partials).
     const int br = st->branch;
     const bool mirror = bi != bj;
+    const int W = digit_bits(ld, S);
     double trc[2] = {0.0, 0.0}, froc[2] = {0.0, 0.0}, idmc[2] = {0.0, 0.0};
     auto element = [&](int c, int r, int gi, int gj, double sj) -> double {
         double v = 0.0;
 #pragma unroll
-        for (int L = S - 1; L >= 0; --L) v += ldexp((double)acc[L][c][r], -(12 + 7 * L));
+        for (int L = S - 1; L >= 0; --L) v += ldexp((double)acc[L][c][r], -(12 + W * L));
         const double p = v * scale[gi] * sj;
         const double x = Xc[(size_t)gi * ld + gj];
         const double xn = br ? 2.0 * x - p : p;

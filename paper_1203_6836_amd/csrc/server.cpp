@@ -229,7 +229,7 @@ void sp2_server::build_group() {
         v.ctrl.n_occ = (double)r->n_occ;
         v.ctrl.idem_tol = opt.idem_tol;
         v.ctrl.stall_tol = 1e-2;
-        v.ctrl.stall_ratio = 1.0;
+        v.ctrl.stall_ratio = 0.5;   // int8 products: the floor rule of direct int8 solves
         v.ctrl.max_iter = opt.max_iter;
         v.ctrl.fp64_head = 0;
         v.ctrl.fp32_tail = 0;
@@ -297,7 +297,7 @@ sp2_status sp2_server::start_system(Request* r) {
     a.n_occ = (double)r->n_occ;
     a.idem_tol = opt.idem_tol;
     a.stall_tol = 1e-2;
-    a.stall_ratio = 1.0;
+    a.stall_ratio = 0.5;
     a.max_iter = opt.max_iter;
     a.fp64_head = 0;
     a.mixed = 1;

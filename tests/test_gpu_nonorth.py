@@ -63,7 +63,7 @@ def test_int8x_nonorth_matches_oracle(ctx):
     import paper_1203_6836_amd as p
     w, H, S = system((8, 8, 8), 2)
     say(f"case nonorth int8x N={w.n_orb}")
-    rho_ref, _, _, _ = nonorth.density_matrix(H, S, w.n_occ)
+    rho_ref, _, _, _ = nonorth.density_matrix(H, S, w.n_occ, solver="lapack")   # N = 2048: library eigensolver
     Sd = to_dev(S)
     D, st, its = ctx.sp2_density_matrix_nonorth(to_dev(H), Sd, w.n_occ, p.options("int8x"))
     q = ctx.sp2_mulliken_overlap(D, Sd, w.n_atoms).cpu().numpy()
@@ -271,8 +271,9 @@ def test_nonorth_thresholded_gapped_wire_vs_oracle(ctx):
     say(f"case nonorth tau=1e-5 element, gapped wire N={w.n_orb}")
     H = otb.hamiltonian0(pos, m)
     S = nonorth.overlap(pos, m)
-    ref, _, _, r = nonorth.density_matrix(H, S, w.n_occ, tau=1e-5, threshold="element")
-    dense, _, _, _ = nonorth.density_matrix(H, S, w.n_occ)
+    # N = 1024: the Loewdin factor from the library eigensolver
+    ref, _, _, r = nonorth.density_matrix(H, S, w.n_occ, solver="lapack", tau=1e-5, threshold="element")
+    dense, _, _, _ = nonorth.density_matrix(H, S, w.n_occ, solver="lapack")
     rn = np.sqrt(w.n_orb)
     err_thr = np.linalg.norm(ref - dense) / rn
     Hd, Sd = to_dev(H), to_dev(S)
