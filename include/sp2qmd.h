@@ -216,9 +216,11 @@ sp2_status sp2_band_energy(sp2_ctx *ctx, int N, const double *D, const double *H
  * subsection: H_perp = Z^T H Z with the congruence factor Z^T S Z = I of
  * Eq. Congr, the T_e = 0 density matrix of H_perp as in Eq. DM_perp, and the
  * de-orthogonalised rho = Z rho_perp Z^T).  Z is the Loewdin factor
- * S^(-1/2), built by a coupled Newton-Schulz iteration (its products are
- * plain rocBLAS FP64 GEMMs, as are the four products of the transforms);
- * H_perp and rho are symmetrised; rho_perp is an SP2 solve with *opt (any
+ * S^(-1/2), built by a coupled Newton-Schulz iteration whose products
+ * (polynomials in S) are formed as symmetric FP64 MFMA products of upper
+ * tiles; each transform is one full product and one symmetric one
+ * (W = H Z, H_perp = W^T Z), so H_perp and rho are exactly symmetric;
+ * rho_perp is an SP2 solve with *opt (any
  * precision and threshold), whose statistics go to *stats.  rho satisfies
  * Tr[rho S] = n_occ and rho S rho = rho.
  * H, S: N x N row-major FP64 device arrays (S symmetric positive definite;
@@ -242,8 +244,9 @@ sp2_status sp2_mulliken_overlap(sp2_ctx *ctx, int n_atoms, const double *D, cons
 /* Density matrix at finite electronic temperature (Eq. EL_4c with kT > 0):
  * D = (exp(beta (H - mu I)) + 1)^(-1), beta = 1/kT, by the recursive
  * Fermi-operator expansion: X_0 = I/2 - beta (H - mu I) / 2^(n_steps + 2),
- * then n_steps times X <- X^2 (X^2 + (I - X)^2)^(-1) (each X made exactly
- * symmetric; the inverse by Newton-Schulz in FP64, GEMMs in rocBLAS).  Its
+ * then n_steps times X <- X^2 (X^2 + (I - X)^2)^(-1) (every product is of
+ * polynomials in H, formed as a symmetric FP64 MFMA product of upper tiles,
+ * so each X is exactly symmetric; the inverse by Newton-Schulz).  Its
  * exponent carries a relative error of about (beta |e - mu| / 2^n_steps)^2
  * / 12 per eigenvalue e; FP64 rounding sets a floor near 1e-11 for
  * n_steps >= 16.
@@ -281,7 +284,7 @@ sp2_status sp2_fermi_density_matrix(sp2_ctx *ctx, int N, const double *H, double
  * eigenvalues as Tr s((H - mu I) / kT) by a Chebyshev expansion over H's
  * Gershgorin interval: coefficients on the host (8192 Chebyshev-Gauss nodes,
  * kept while above 1e-13), moments Tr T_k from about half as many N x N
- * FP64 products as coefficients (rocBLAS).  H: N x N device, finite and
+ * symmetric FP64 MFMA products as coefficients.  H: N x N device, finite and
  * symmetric (EINVAL otherwise); mu finite; kT > 0 in the units of H; EINVAL
  * when more than about 4000 coefficients would be needed (the count grows as
  * the Gershgorin width over kT: about 1000 at kT = 0.5 and 2200 at 0.25 on
@@ -346,7 +349,7 @@ sp2_status tb_hamiltonian_nonorth(sp2_ctx *ctx, const tb_params *p, int n_atoms,
  * (sp2_density_matrix_nonorth); H, D: (4 n_atoms)^2 device; q, n_aux:
  * n_atoms device; s0, lam_s: the overlap parameters of tb_overlap; F_out:
  * 3 n_atoms device; U_host: host or NULL.  Uses two N^2 scratch buffers of
- * the context (two rocBLAS GEMMs form D H D). */
+ * the context (two FP64 MFMA products form D H D = (H D)^T D). */
 sp2_status tb_forces_nonorth(sp2_ctx *ctx, const tb_params *p, double s0, double lam_s, int n_atoms,
                              const double *xyz, const double *D, const double *H, const double *q,
                              const double *n_aux, double *F_out, double *U_host);

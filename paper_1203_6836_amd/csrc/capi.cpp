@@ -12,10 +12,9 @@
 #include <string>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "../../include/sp2qmd.h"
 #include "fermi_internal.h"
+#include "gemm_internal.h"
 #include "noalloc_internal.h"
 #include "nonorth_internal.h"
 #include "sp2_internal.h"
@@ -59,9 +58,8 @@ struct sp2_ctx {
     size_t envcap = 0;
     int* tz = nullptr;         // per X buffer and upper tile: known all zero (thresholded int8)
     size_t tzcap = 0;
-    // non-orthogonal solves: rocBLAS handle (created on first use) and four
-    // N x N buffers (Z, Y / H_perp, T / D_perp, W) plus reduction slots
-    rocblas_handle blas = nullptr;
+    // non-orthogonal and finite-temperature solves: N x N work buffers (Z,
+    // Y / H_perp, T / D_perp, W) plus reduction slots
     double* nobuf = nullptr;
     size_t nocap = 0;
     double* f64tail = nullptr; // chunk accumulators of split last-wave FP64 tiles
@@ -192,7 +190,6 @@ void sp2_ctx_destroy(sp2_ctx* c) {
     else (void)hipDeviceSynchronize();
     void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->chk, c->V, c->eatom, c->qtmp, c->env, c->tz,
                    c->eH, c->eD, c->ezero, c->eF, c->f64tail, c->nobuf};
-    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     for (void* p : dev)
         if (p) (void)hipFree(p);
     split_free(c->split);
@@ -642,28 +639,24 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
 // Row-major C = alpha A B + beta C for N x N matrices: a row-major matrix read
 // as column-major is its transpose, so this is the column-major product
 // C^T = alpha B^T A^T + beta C^T.
-static sp2_status gemm_rm(sp2_ctx* c, int N, const double* A, const double* B, double* C, double alpha = 1.0,
-                          double beta = 0.0) {
-    const rocblas_status r = rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, N, N, N, &alpha,
-                                           B, N, A, N, &beta, C, N);
-    if (r != rocblas_status_success)
-        return fail(c, SP2_EDEVICE, std::string("rocblas_dgemm failed: ") + rocblas_status_to_string(r));
+// C = alpha A B + beta C_in + gamma I for a symmetric A (so that A B = A^T B,
+// the form the FP64 product kernel reads), N x N, leading dimension N; sym
+// when A B is symmetric (A and B symmetric and commuting, or a congruence
+// M^T B M): then only the upper tiles are formed and mirrored, and C is
+// exactly symmetric.  The K split of sparse last waves uses the context's
+// FP64 chunk buffer.
+static sp2_status prod(sp2_ctx* c, int N, const double* A, const double* B, double* C, bool sym,
+                       double alpha = 1.0, double gamma = 0.0, double beta = 0.0, const double* Cin = nullptr) {
+    double* chunk = nullptr;
+    size_t chunk_bytes = 0;
+    sp2_status s = f64_tail_buffer(c, 0, -1, &chunk, &chunk_bytes);
+    if (s != SP2_OK) return s;
+    GemmTN g{A, B, Cin, C, N, alpha, beta, gamma};
+    HIPCHK(c, launch_gemm_tn(g, sym, 8, chunk, chunk_bytes, c->stream));
     return SP2_OK;
 }
 
 constexpr int kNsMaxIter = 40;
-
-static sp2_status ensure_blas(sp2_ctx* c) {
-    if (!c->blas) {
-        if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
-            c->blas = nullptr;
-            return fail(c, SP2_EDEVICE, "rocblas_create_handle failed");
-        }
-    }
-    if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
-        return fail(c, SP2_EDEVICE, "rocblas_set_stream failed");
-    return SP2_OK;
-}
 
 extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double* H, const double* S, int n_occ,
                                                   const sp2_options* opt, double* D_out, sp2_stats* stats,
@@ -679,7 +672,6 @@ extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double
     sp2_status s = check_options(c, o, N);
     if (s != SP2_OK) return s;
     HIPCHK(c, hipSetDevice(c->device));
-    if ((s = ensure_blas(c)) != SP2_OK) return s;
     const size_t n2 = (size_t)N * N;
     size_t nb = c->nocap;
     if ((s = grow(c, (void**)&c->nobuf, &nb, (4 * n2 + kNsBlocks + 64) * sizeof(double))) != SP2_OK) return s;
@@ -701,7 +693,7 @@ extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double
     int it = 0;
     bool converged = false;
     for (; it < kNsMaxIter; ++it) {
-        if ((s = gemm_rm(c, N, Zm, Y, T)) != SP2_OK) return s;          // T = Z_k Y_k
+        if ((s = prod(c, N, Zm, Y, T, true)) != SP2_OK) return s;        // T = Z_k Y_k (polynomials in S)
         HIPCHK(c, launch_ns_step(T, N, part, st));                      // residual; T = (3 I - T) / 2
         HIPCHK(c, launch_sum_sqrt(part, kNsBlocks, res, st));
         HIPCHK(c, hipMemcpyAsync(c->scal_host, res, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -713,25 +705,24 @@ extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double
             break;
         }
         prev = r;
-        if ((s = gemm_rm(c, N, Y, T, W)) != SP2_OK) return s;           // Y_{k+1} = Y_k T_k
+        if ((s = prod(c, N, Y, T, W, true)) != SP2_OK) return s;         // Y_{k+1} = Y_k T_k
         std::swap(Y, W);
-        if ((s = gemm_rm(c, N, T, Zm, W)) != SP2_OK) return s;          // Z_{k+1} = T_k Z_k
+        if ((s = prod(c, N, T, Zm, W, true)) != SP2_OK) return s;        // Z_{k+1} = T_k Z_k
         std::swap(Zm, W);
     }
     if (factor_iterations) *factor_iterations = it + 1;
     if (!converged) return fail(c, SP2_ENOCONV, "inverse factor of S did not converge (S not positive definite?)");
     HIPCHK(c, launch_scale_inv_sqrt(Zm, N, mx, st));
-    // H_perp = Z^T H Z (Z symmetric), made exactly symmetric
+    // H_perp = Z^T H Z (Z symmetric): W = H Z, then H_perp = W^T Z, formed
+    // as a symmetric product (exactly symmetric)
     double* Hp = Y;
     double* Dp = T;
-    if ((s = gemm_rm(c, N, Zm, H, W)) != SP2_OK) return s;
-    if ((s = gemm_rm(c, N, W, Zm, Hp)) != SP2_OK) return s;
-    HIPCHK(c, launch_symmetrize(Hp, N, st));
-    // rho_perp = theta(mu0 I - H_perp) by SP2, then rho = Z rho_perp Z^T
+    if ((s = prod(c, N, H, Zm, W, false)) != SP2_OK) return s;
+    if ((s = prod(c, N, W, Zm, Hp, true)) != SP2_OK) return s;
+    // rho_perp = theta(mu0 I - H_perp) by SP2, then rho = Z rho_perp Z^T the same way
     if ((s = sp2_solve(c, N, Hp, n_occ, o, Dp, stats)) != SP2_OK) return s;
-    if ((s = gemm_rm(c, N, Zm, Dp, W)) != SP2_OK) return s;
-    if ((s = gemm_rm(c, N, W, Zm, D_out)) != SP2_OK) return s;
-    HIPCHK(c, launch_symmetrize(D_out, N, st));
+    if ((s = prod(c, N, Dp, Zm, W, false)) != SP2_OK) return s;
+    if ((s = prod(c, N, W, Zm, D_out, true)) != SP2_OK) return s;
     HIPCHK(c, hipStreamSynchronize(st));
     return SP2_OK;
 }
@@ -761,17 +752,16 @@ static sp2_status fermi_pass(sp2_ctx* c, int N, const double* H, double mu, doub
         const double rho = 2.0 * db * db / (1.0 + 2.0 * db * db);
         int updates = 0;   // error rho^2 after Y_1, squared by each update
         for (double err = rho * rho; err > kFermiInvErr && updates < kFermiInvUpdates; err *= err) ++updates;
-        if ((s = gemm_rm(c, N, X, X, X2)) != SP2_OK) return s;
+        // every factor is a polynomial in H: the products are symmetric
+        if ((s = prod(c, N, X, X, X2, true)) != SP2_OK) return s;
         HIPCHK(c, launch_fermi_a(X2, X, N, 2.0 / (1.0 + 2.0 * db * db), A, Y, st));   // A, Y_1
         double* W = X;                                        // X is free until X_{k+1}
         for (int j = 0; j < updates; ++j) {
-            if ((s = gemm_rm(c, N, A, Y, R)) != SP2_OK) return s;
-            HIPCHK(c, launch_two_minus(R, N, st));
-            if ((s = gemm_rm(c, N, Y, R, W)) != SP2_OK) return s;   // Y <- Y (2 I - A Y)
+            if ((s = prod(c, N, A, Y, R, true, -1.0, 2.0)) != SP2_OK) return s;   // R = 2 I - A Y
+            if ((s = prod(c, N, Y, R, W, true)) != SP2_OK) return s;               // Y <- Y (2 I - A Y)
             std::swap(Y, W);
         }
-        if ((s = gemm_rm(c, N, X2, Y, W)) != SP2_OK) return s;      // X_{k+1} = X_k^2 A^(-1)
-        HIPCHK(c, launch_symmetrize(W, N, st));
+        if ((s = prod(c, N, X2, Y, W, true)) != SP2_OK) return s;      // X_{k+1} = X_k^2 A^(-1)
         X = W;
         *products += 2 + 2 * updates;
         delta = std::min(0.5, 2.0 * delta / (1.0 + 4.0 * delta * delta));
@@ -796,7 +786,6 @@ extern "C" sp2_status sp2_fermi_density_matrix(sp2_ctx* c, int N, const double* 
     if (max_newton == 0 && !std::isfinite(*mu)) return fail(c, SP2_EINVAL, "a fixed mu must be finite");
     HIPCHK(c, hipSetDevice(c->device));
     sp2_status s;
-    if ((s = ensure_blas(c)) != SP2_OK) return s;
     const size_t n2 = (size_t)N * N;
     size_t nb = c->nocap;
     if ((s = grow(c, (void**)&c->nobuf, &nb, (5 * n2 + 2 * kFermiBlocks + 8) * sizeof(double))) != SP2_OK) return s;
@@ -897,7 +886,6 @@ extern "C" sp2_status sp2_fermi_entropy(sp2_ctx* c, int N, const double* H, doub
     if (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu)) return fail(c, SP2_EINVAL, "need finite mu and kT > 0");
     HIPCHK(c, hipSetDevice(c->device));
     sp2_status s;
-    if ((s = ensure_blas(c)) != SP2_OK) return s;
     const size_t n2 = (size_t)N * N;
     const int kmax = kEntropyNodes / 2;
     size_t nb = c->nocap;
@@ -966,7 +954,7 @@ extern "C" sp2_status sp2_fermi_entropy(sp2_ctx* c, int N, const double* H, doub
         // <T_k, T_k> (moment 2k); then T_(k+1) = 2 Ht T_k - T_(k-1) over T_(k-1)
         HIPCHK(c, launch_dot(Tc, Tc, n2, c->part, &ns, mom + 2 * k, st));
         if (k == K) break;
-        if ((s = gemm_rm(c, N, Ht, Tc, Tp, 2.0, -1.0)) != SP2_OK) return s;
+        if ((s = prod(c, N, Ht, Tc, Tp, true, 2.0, 0.0, -1.0, Tp)) != SP2_OK) return s;
         std::swap(Tp, Tc);
         HIPCHK(c, launch_dot(Tc, Tp, n2, c->part, &ns, mom + 2 * k + 1, st));   // <T_(k+1), T_k>
     }
@@ -1150,7 +1138,6 @@ static sp2_status tb_forces_nonorth_impl(sp2_ctx* c, const tb_params* p, double 
                                          const double* n, double* F, double* U_dev) {
     sp2_status s = ensure_atoms(c, n_atoms);
     if (s != SP2_OK) return s;
-    if ((s = ensure_blas(c)) != SP2_OK) return s;
     const int N = 4 * n_atoms;
     const size_t n2 = (size_t)N * N;
     size_t nb = c->nocap;
@@ -1160,9 +1147,9 @@ static sp2_status tb_forces_nonorth_impl(sp2_ctx* c, const tb_params* p, double 
     double* W2 = W1 + n2;
     // orthogonal terms (band with h, Coulomb with q, pair) and U; V = gamma n
     if ((s = forces_impl(c, p, n_atoms, xyz, D, q, n, F, U_dev)) != SP2_OK) return s;
-    // energy-weighted density matrix W = D H D, then M in place
-    if ((s = gemm_rm(c, N, D, H, W1)) != SP2_OK) return s;
-    if ((s = gemm_rm(c, N, W1, D, W2)) != SP2_OK) return s;
+    // energy-weighted density matrix D H D (= (H D)^T D), then M in place
+    if ((s = prod(c, N, H, D, W1, false)) != SP2_OK) return s;
+    if ((s = prod(c, N, W1, D, W2, true)) != SP2_OK) return s;
     HIPCHK(c, launch_force_matrix(W2, D, c->V, n_atoms, c->stream));
     HIPCHK(c, launch_forces_overlap(xyz, n_atoms, make_radial(s0, p->r0, lam_s, p->r_tail, p->r_cut), W2, F,
                                     c->stream));

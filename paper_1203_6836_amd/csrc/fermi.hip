@@ -2,7 +2,7 @@
 // Fermi-operator expansion): with y = beta (H - mu I) / 2^(n+2), X_0 = I/2 - y
 // and n steps X_{k+1} = X_k^2 (X_k^2 + (I - X_k)^2)^(-1) give
 // (exp(beta (H - mu I)) + 1)^(-1) (the ratio (I - X)/X squares each step).
-// The host runs the GEMMs; these kernels form X_0, A = X^2 + (I - X)^2, the
+// The products run in the FP64 product kernel; these kernels form X_0, A = X^2 + (I - X)^2, the
 // Newton-Schulz steps of A^(-1) (A = I/2 + 2 (X - I/2)^2 has its spectrum in
 // [1/2, 1] while X has its own in [0, 1], and nearer 1/2 in the first steps),
 // and the trace and Frobenius sums of the Newton step on mu.
@@ -42,12 +42,6 @@ __global__ __launch_bounds__(256) void k_fermi_a(const double* __restrict__ X2, 
         A[e] = a;
         Y[e] = c * (2.0 * d - c * a);
     }
-}
-
-__global__ __launch_bounds__(256) void k_two_minus(double* __restrict__ R, int N) {
-    const size_t n2 = (size_t)N * N;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 256)
-        R[e] = ((e / N == e % N) ? 2.0 : 0.0) - R[e];
 }
 
 __global__ __launch_bounds__(256) void k_trace_fro(const double* __restrict__ X, int N, double* __restrict__ part) {
@@ -103,10 +97,6 @@ hipError_t launch_fermi_init(const double* H, int N, double mu, double scale, do
 }
 hipError_t launch_fermi_a(const double* X2, const double* X, int N, double c, double* A, double* Y, hipStream_t s) {
     hipLaunchKernelGGL(k_fermi_a, dim3(grid_elem(N)), dim3(256), 0, s, X2, X, N, c, A, Y);
-    return hipGetLastError();
-}
-hipError_t launch_two_minus(double* R, int N, hipStream_t s) {
-    hipLaunchKernelGGL(k_two_minus, dim3(grid_elem(N)), dim3(256), 0, s, R, N);
     return hipGetLastError();
 }
 hipError_t launch_cheb_init(const double* H, int N, double c, double inv_w, double* Ht, double* T0, hipStream_t s) {

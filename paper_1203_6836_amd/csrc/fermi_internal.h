@@ -19,8 +19,6 @@ constexpr double kFermiInvErr = 5.5e-16;   // 3^(-32): four updates after Y_1 at
 constexpr int kFermiInvUpdates = 4;        // most updates after Y_1
 // A = 2 X2 - 2 X + I, Y = c (2 I - c A).
 hipError_t launch_fermi_a(const double* X2, const double* X, int N, double c, double* A, double* Y, hipStream_t s);
-// R <- 2 I - R in place.
-hipError_t launch_two_minus(double* R, int N, hipStream_t s);
 // part[2 b], part[2 b + 1] = block b's sums of X_ii and X_ij^2 (fixed order).
 hipError_t launch_trace_fro(const double* X, int N, double* part, hipStream_t s);
 // out[0], out[1] = fixed-order sums of part[2 k], part[2 k + 1], k < n.

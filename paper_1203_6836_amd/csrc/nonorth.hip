@@ -4,10 +4,10 @@
 //   Y_0 = S / c, Z_0 = I, T_k = (3 I - Z_k Y_k) / 2, Y_{k+1} = Y_k T_k,
 //   Z_{k+1} = T_k Z_k,
 // for which Z_k -> (S / c)^(-1/2) quadratically when the spectrum of S / c
-// lies in (0, 1] (c = the Gershgorin bound of S).  The products are plain
-// GEMMs (the host runs them); these kernels do the elementwise steps, the
-// residual ||Z_k Y_k - I||_F, the symmetrisation of Z^T H Z and Z rho Z^T,
-// and the Mulliken charges with the overlap.
+// lies in (0, 1] (c = the Gershgorin bound of S).  The products run in the
+// FP64 product kernel (symmetric ones for the polynomials in S and the two
+// congruences); these kernels do the elementwise steps, the residual
+// ||Z_k Y_k - I||_F and the Mulliken charges with the overlap.
 #include "nonorth_internal.h"
 
 #include <cmath>
@@ -80,38 +80,6 @@ __global__ __launch_bounds__(256) void k_scale_inv_sqrt(double* __restrict__ Z, 
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += (size_t)gridDim.x * 256) Z[e] *= f;
 }
 
-// Tile pair (bi, bj), bi <= bj, of 32 x 32: both read through LDS, averaged,
-// written back (a diagonal tile with its own transpose).
-__global__ __launch_bounds__(256) void k_symmetrize(double* __restrict__ A, int N) {
-    __shared__ double P[32][33], Q[32][33];
-    const int nb = (N + 31) / 32;
-    const long long T = (long long)nb * (nb + 1) / 2;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    for (long long t = blockIdx.x; t < T; t += gridDim.x) {
-        int bi = 0;
-        long long off = 0;
-        while (t >= off + (nb - bi)) { off += nb - bi; ++bi; }
-        const int bj = bi + (int)(t - off);
-        __syncthreads();
-        for (int r = ty; r < 32; r += 8) {
-            const int i = bi * 32 + r, j = bj * 32 + tx;
-            const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
-            P[r][tx] = (i < N && j < N) ? A[(size_t)i * N + j] : 0.0;
-            Q[r][tx] = (i2 < N && j2 < N) ? A[(size_t)i2 * N + j2] : 0.0;
-        }
-        __syncthreads();
-        for (int r = ty; r < 32; r += 8) {
-            const int i = bi * 32 + r, j = bj * 32 + tx;
-            const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
-            const double a = 0.5 * (P[r][tx] + Q[tx][r]);      // (A_ij + A_ji) / 2
-            const double b = 0.5 * (Q[r][tx] + P[tx][r]);      // (A_i2j2 + A_j2i2) / 2
-            if (i < N && j < N) A[(size_t)i * N + j] = a;
-            if (bi != bj && i2 < N && j2 < N) A[(size_t)i2 * N + j2] = b;
-        }
-    }
-}
-
-// One wave per atom: its four rows in order.
 __global__ __launch_bounds__(256) void k_mulliken_overlap(const double* __restrict__ D,
                                                           const double* __restrict__ S, int n_atoms, double z_val,
                                                           double* __restrict__ q) {
@@ -155,12 +123,6 @@ hipError_t launch_sum_sqrt(const double* part, int n, double* out, hipStream_t s
 }
 hipError_t launch_scale_inv_sqrt(double* Z, int N, const unsigned long long* mx, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(grid_for((size_t)N * N)), dim3(256), 0, s, Z, N, mx);
-    return hipGetLastError();
-}
-hipError_t launch_symmetrize(double* A, int N, hipStream_t s) {
-    const long long nb = (N + 31) / 32;
-    const long long T = nb * (nb + 1) / 2;
-    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)(T < 4096 ? T : 4096)), dim3(256), 0, s, A, N);
     return hipGetLastError();
 }
 hipError_t launch_mulliken_overlap(const double* D, const double* S, int n_atoms, double z_val, double* q,

@@ -1,6 +1,6 @@
-// Internal declarations of the non-orthogonal formulation: the Loewdin
-// factor by a coupled Newton-Schulz iteration, symmetrisation of the
-// transformed matrices, and Mulliken charges with the overlap.
+// Internal declarations of the non-orthogonal formulation: the elementwise
+// steps of the Loewdin factor's coupled Newton-Schulz iteration and Mulliken
+// charges with the overlap.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -22,8 +22,6 @@ hipError_t launch_ns_step(double* T, int N, double* part, hipStream_t s);
 hipError_t launch_sum_sqrt(const double* part, int n, double* out, hipStream_t s);
 // Z <- Z / sqrt(c) with c the bound in mx.
 hipError_t launch_scale_inv_sqrt(double* Z, int N, const unsigned long long* mx, hipStream_t s);
-// A <- (A + A^T) / 2 in place (32 x 32 tile pairs through LDS).
-hipError_t launch_symmetrize(double* A, int N, hipStream_t s);
 // q_i = 2 sum_{alpha in i} sum_beta D_{alpha beta} S_{alpha beta} - z_val (S
 // symmetric, so the inner sum is (D S)_{alpha alpha}); one wave per atom,
 // fixed order.
