@@ -54,7 +54,7 @@ struct sp2_ctx {
     double* eatom = nullptr;
     double* qtmp = nullptr;
     size_t natcap = 0;
-    int* env = nullptr;        // per-panel surviving column-block ranges (thresholded X)
+    int* env = nullptr;        // per-panel surviving column-block ranges and block masks (thresholded X)
     size_t envcap = 0;
     int* tz = nullptr;         // per X buffer and upper tile: known all zero (thresholded int8)
     size_t tzcap = 0;
@@ -297,7 +297,7 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
         if ((s = f64_tail_buffer(c, ld, o.tail_split, &sc.f64tail, &sc.f64tail_bytes)) != SP2_OK) return s;
     if (o.tau > 0.0) {
         size_t eb = c->envcap;
-        if ((s = grow(c, (void**)&c->env, &eb, (size_t)nt * 2 * sizeof(int))) != SP2_OK) return s;
+        if ((s = grow(c, (void**)&c->env, &eb, env_bytes(ld))) != SP2_OK) return s;
         c->envcap = eb;
         sc.env = c->env;
     }

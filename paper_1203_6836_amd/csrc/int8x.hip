@@ -400,19 +400,47 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     // fragment address inside a block: row lane % 32, k-half lane / 32
     const int fr = lane & 31;
     const int foff = fr * 32 + 16 * ((lane >> 5) ^ dswz(fr));
-    // K range: all of it, or the overlap of the two panels' surviving column
-    // blocks of a thresholded X (one 32-byte stage per 32-column block)
+    // K stages: all of them (or chunk [kc0, kc1)), or for a thresholded X
+    // those holding a 32-column block set in both panels' block masks (the
+    // other stages multiply a zero block on one side)
     int ks = 0, nk = ld / (QK * KS);
     if (kc1 >= 0) {
         ks = kc0;
         nk = kc1;
     }
+    const int nbk = ld / QK;
+    bool holes = false;
+    const unsigned long long* mk = THR ? env_mask(env, nt) : nullptr;
+    const unsigned long long* mi = THR ? mk + (size_t)bi * mask_words(ld) : nullptr;
+    const unsigned long long* mj = THR ? mk + (size_t)bj * mask_words(ld) : nullptr;
     if (THR) {
-        // rounded out to whole stages: the extra 32-column blocks are zero
-        const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
-        ks = lo / KS;
-        nk = lo > hi ? ks : hi / KS + 1;
+        // the stages between the first and the last common block; when some
+        // stage in between has none (the blocks are scattered, not banded),
+        // the loop below visits the working stages only
+        const unsigned long long mword = common_mask_word(mi, mj, nbk);
+        // per lane: stages of its word holding a common block (KS divides
+        // 64, so no stage straddles two words) and its last common block;
+        // then the wave's sum and maximum
+        int stages = 0, b1 = -1;
+        if (mword) {
+            unsigned long long m = mword;
+            if (KS == 2) m = (m | (m >> 1)) & 0x5555555555555555ull;
+            stages = __popcll(m);
+            b1 = (lane << 6) + 63 - __builtin_clzll(mword);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            stages += __shfl_xor(stages, o, 64);
+            b1 = max(b1, __shfl_xor(b1, o, 64));
+        }
+        if (b1 < 0) {
+            ks = nk = 0;
+        } else {
+            ks = next_block_in_wave(mword, 0, nbk) / KS;
+            nk = b1 / KS + 1;
+            holes = stages < nk - ks;
+        }
     }
+
     // Fragment reads are written in order of first use (B plane 0, the A
     // planes, B planes 1 ..), the products in level order, and the scheduler
     // is held to a pattern of one read per two products that keeps every
@@ -479,20 +507,56 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
         }
     };
     if (kmode == 2) nk = ks;          // accumulators come from the chunks
-    for (int q = 0; q < NST - 1; ++q)
-        if (ks + q < nk) issue(ks + q, q);
-    for (int kt = ks; kt < nk; ++kt) {
-        // this wave's blocks of stage kt have landed in LDS once only stage
-        // kt + 1's loads (three-deep ring) or none (two-deep) are
-        // outstanding; the bare barrier (no fence, which would wait for every
-        // outstanding load) then covers the other waves' blocks, and every
-        // wave has finished reading the buffer that stage kt + NST - 1
-        // overwrites
-        if (NST == 3 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                                 // vmcnt(0)
+    if (!holes) {
+        // every stage of [ks, nk) works: a plain loop
+        for (int q = 0; q < NST - 1; ++q)
+            if (ks + q < nk) issue(ks + q, q);
+        for (int kt = ks; kt < nk; ++kt) {
+            // this wave's blocks of stage kt have landed in LDS once only
+            // stage kt + 1's loads (three-deep ring) or none (two-deep) are
+            // outstanding; the bare barrier (no fence, which would wait for
+            // every outstanding load) then covers the other waves' blocks, and
+            // every wave has finished reading the buffer that stage
+            // kt + NST - 1 overwrites
+            if (NST == 3 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
+            else __builtin_amdgcn_s_waitcnt(0x0F70);                                 // vmcnt(0)
+            __builtin_amdgcn_s_barrier();
+            if (kt + NST - 1 < nk) issue(kt + NST - 1, (kt + NST - 1 - ks) % NST);
+            compute((kt - ks) % NST);
+        }
+    }
+    // with holes: the working stages in increasing order go round the ring:
+    // ic is the next stage to issue, n_iss / n_done count stages issued /
+    // multiplied (the common mask is reloaded here, so that it is not live
+    // across the plain loop)
+    const unsigned long long mword = (THR && holes) ? common_mask_word(mi, mj, nbk) : 0ull;
+    auto next_stage = [&](int s) -> int {      // first working stage >= s, or nk
+        const int b = next_block_in_wave(mword, s * KS, nbk);
+        return b >= nbk ? nk : b / KS;
+    };
+    int ic = holes ? next_stage(ks) : nk, n_iss = 0, n_done = 0;
+    while (n_iss < NST - 1 && ic < nk) {
+        issue(ic, n_iss % NST);
+        ++n_iss;
+        ic = next_stage(ic + 1);
+    }
+    while (n_done < n_iss) {
+        // this wave's blocks of the stage in ring slot n_done have landed in
+        // LDS once only the next stage's loads (three-deep ring) or none
+        // (two-deep) are outstanding; the bare barrier (no fence, which would
+        // wait for every outstanding load) then covers the other waves'
+        // blocks, and every wave has finished reading the slot that the next
+        // issue overwrites
+        if (NST == 3 && n_iss - n_done == 2) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                                         // vmcnt(0)
         __builtin_amdgcn_s_barrier();
-        if (kt + NST - 1 < nk) issue(kt + NST - 1, (kt + NST - 1 - ks) % NST);
-        compute((kt - ks) % NST);
+        if (ic < nk) {
+            issue(ic, n_iss % NST);
+            ++n_iss;
+            ic = next_stage(ic + 1);
+        }
+        compute(n_done % NST);
+        ++n_done;
     }
     __syncthreads();
     constexpr int CH = S * 2 * 16 * 512;   // int32 per chunk
@@ -747,8 +811,11 @@ __global__ __launch_bounds__(256) void k_tile_list(const State* __restrict__ st,
         int bi, bj;
         order_tile_rows(pos, nt, tile_group, bi, bj);
         const int t = tri_index(bi, bj, nt);
-        const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
-        const bool zero_next = lo > hi && tz[(size_t)st->cur * T + t] != 0;
+        // no 32-column block set in both panels' masks: the product tile is zero
+        const unsigned long long* mk = env_mask(env, nt);
+        const int W = mask_words(nt * QB), nbk = nt * QB / QK;
+        const bool k_empty = next_common_block(mk + (size_t)bi * W, mk + (size_t)bj * W, 0, nbk) >= nbk;
+        const bool zero_next = k_empty && tz[(size_t)st->cur * T + t] != 0;
         if (zero_next && tz[(size_t)(1 - st->cur) * T + t] != 0) {
             part[3 * t + 0] = 0.0;
             part[3 * t + 1] = 0.0;

@@ -434,20 +434,27 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // K range: all of it, or (thresholded X) the overlap of the two row panels'
-    // ranges of 32-column blocks that survived the threshold; outside it one
-    // of the two operands is zero.
+    // K stages: all of them (or the chunk [kc0, kc1)), or for a thresholded X
+    // the 16-wide stages of the 32-column blocks set in both row panels'
+    // block masks (elsewhere one of the two operands is zero, so skipping
+    // those stages leaves every sum bitwise unchanged)
     int ks = 0, ke = ld / GK;
     if (kc1 >= 0) {
         ks = kc0;
         ke = kc1;
     }
-    if (THR) {
-        const int lo = max(env[2 * bi], env[2 * bj]), hi = min(env[2 * bi + 1], env[2 * bj + 1]);
-        ks = lo * 2;                           // 16-wide stages, two per 32-column block
-        ke = lo > hi ? ks : (hi + 1) * 2;
-    }
     if (kmode == 2) ke = ks;                   // accumulators come from the chunks
+    const int nbk = ld / 32;
+    unsigned long long mword = 0ull;
+    if (THR) {
+        const unsigned long long* mk = env_mask(env, nt);
+        mword = common_mask_word(mk + (size_t)bi * mask_words(ld), mk + (size_t)bj * mask_words(ld), nbk);
+    }
+    auto next_stage = [&](int s) -> int {      // first working stage >= s, or ke
+        if (!THR || s >= ke) return s;
+        const int b = next_block_in_wave(mword, s >> 1, nbk);
+        return b >= nbk ? ke : max(s, 2 * b);
+    };
     auto compute = [&](int stg) {
 #pragma unroll
         for (int k4 = 0; k4 < GK / 4; ++k4) {
@@ -464,16 +471,20 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], acc[m][n], 0, 0, 0);
         }
     };
-    if (ks < ke) {
-        gload(ks * GK);
+    int kt = next_stage(ks);
+    if (kt < ke) {
+        gload(kt * GK);
         sstore(0);
         __syncthreads();
-        for (int kt = ks; kt < ke; ++kt) {
-            const int stg = (kt - ks) & 1;
-            if (kt + 1 < ke) gload((kt + 1) * GK);
+        int stg = 0;
+        while (kt < ke) {
+            const int kn = next_stage(kt + 1);
+            if (kn < ke) gload(kn * GK);
             compute(stg);
-            if (kt + 1 < ke) sstore(stg ^ 1);
+            if (kn < ke) sstore(stg ^ 1);
             __syncthreads();
+            stg ^= 1;
+            kt = kn;
         }
     }
 

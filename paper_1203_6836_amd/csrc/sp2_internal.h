@@ -145,6 +145,69 @@ __device__ __forceinline__ void tile_of_block(int w, int nt, int G, int& bi, int
     order_tile(xcd_deal(w, nt * (nt + 1) / 2), nt, G, bi, bj);
 }
 
+// Block mask of a thresholded X, kept after the panel ranges in the env
+// buffer (2 nt ints, then nt x mask_words(ld) 64-bit words): for 128-row
+// panel p, bit b of words [p W, (p + 1) W) is set when the 32-column block b
+// holds a nonzero in some row of the panel.  By symmetry of X it is also the
+// set of 32-row blocks with a nonzero in the panel's columns, so a product
+// tile (bi, bj) needs exactly the K blocks set in both panels' masks.
+__host__ __device__ __forceinline__ int mask_words(int ld) { return (ld / 32 + 63) / 64; }
+__host__ __device__ __forceinline__ unsigned long long* env_mask(int* env, int nt) {
+    return reinterpret_cast<unsigned long long*>(env + 2 * nt);
+}
+__host__ __device__ __forceinline__ const unsigned long long* env_mask(const int* env, int nt) {
+    return reinterpret_cast<const unsigned long long*>(env + 2 * nt);
+}
+// Env buffer bytes for nt panels of an ld-wide X.
+inline size_t env_bytes(int ld) {
+    const int nt = ld / kTile;
+    return (size_t)2 * nt * sizeof(int) + (size_t)nt * mask_words(ld) * sizeof(unsigned long long);
+}
+
+#ifdef __HIPCC__
+// Common block mask of one product tile held in registers: lane l of a wave
+// keeps word l of mi & mj (nb / 64 <= 64 words), so finding the next working
+// K block in the loop costs a ballot and a lane read, no memory access.
+__device__ __forceinline__ unsigned long long common_mask_word(const unsigned long long* __restrict__ mi,
+                                                               const unsigned long long* __restrict__ mj, int nb) {
+    const int lane = threadIdx.x & 63;
+    return lane < ((nb + 63) >> 6) ? (mi[lane] & mj[lane]) : 0ull;
+}
+// First block >= b (< nb) set in the wave's common mask word mword, or nb.
+// Uniform over the wave.
+__device__ __forceinline__ int next_block_in_wave(unsigned long long mword, int b, int nb) {
+    if (b >= nb) return nb;
+    const int lane = threadIdx.x & 63, wd = b >> 6;
+    unsigned long long m = lane < wd ? 0ull : mword;
+    if (lane == wd) m &= ~0ull << (b & 63);
+    const unsigned long long lanes = __ballot(m != 0ull);
+    if (lanes == 0ull) return nb;
+    const int l = __builtin_ctzll(lanes);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)m, l);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(m >> 32), l);
+    const int r = (l << 6) + __builtin_ctzll(((unsigned long long)hi << 32) | lo);
+    return r < nb ? r : nb;
+}
+
+// The first 32-column block b' >= b (b' < nb) set in both masks mi and mj
+// (W words each), or nb.  Uniform in a workgroup.
+__device__ __forceinline__ int next_common_block(const unsigned long long* __restrict__ mi,
+                                                 const unsigned long long* __restrict__ mj, int b, int nb) {
+    if (b >= nb) return nb;
+    const int W = (nb + 63) >> 6;
+    int wd = b >> 6;
+    unsigned long long m = (mi[wd] & mj[wd]) & (~0ull << (b & 63));
+    for (;;) {
+        if (m) {
+            const int r = (wd << 6) + __builtin_ctzll(m);
+            return r < nb ? r : nb;
+        }
+        if (++wd >= W) return nb;
+        m = mi[wd] & mj[wd];
+    }
+}
+#endif
+
 // Reading of a degenerate Fermi level: an idempotent X_n whose trace is not
 // n_occ, or >= kGapMinIter products without convergence and an idempotency
 // error still >= kGapIdem, or eps_max == eps_min, ends the solve with done = 4.

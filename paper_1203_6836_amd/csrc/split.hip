@@ -38,6 +38,7 @@ __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau
     const int nb = (N + 31) / 32;
     double tr = 0.0, fro = 0.0;
     int kept = 0;
+    int kbits = 0;   // column sub-blocks s of row sub-block w (this wave) kept
     // surviving 32-column blocks of panel bi (columns c0) and, by symmetry, of panel bj (rows r0)
     int lo_i = 0x7fffffff, hi_i = -1, lo_j = 0x7fffffff, hi_j = -1;
     // transposed copy of each wave's block, for coalesced writes of the
@@ -96,6 +97,7 @@ __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau
             __syncthreads();
         }
         if (keep) {
+            kbits |= 1 << s;
             fro += ss;
             if (r0 == c0) {
 #pragma unroll
@@ -113,11 +115,12 @@ __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau
     }
     tr = wsum64(tr);
     __shared__ double s_tr[4], s_fr[4];
-    __shared__ int s_k[4], s_env[4][4];
+    __shared__ int s_k[4], s_env[4][4], s_bits[4];
     if (lane == 0) {
         s_tr[w] = tr;
         s_fr[w] = fro;
         s_k[w] = kept;
+        s_bits[w] = kbits;
         s_env[w][0] = lo_i;
         s_env[w][1] = hi_i;
         s_env[w][2] = lo_j;
@@ -148,6 +151,18 @@ __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau
                 atomicMax(&env[2 * bi + 1], e[1]);
                 atomicMin(&env[2 * bj], e[2]);
                 atomicMax(&env[2 * bj + 1], e[3]);
+                // block masks: panel bi gains the kept column sub-blocks
+                // (blocks 4 bj .. 4 bj + 3), panel bj the kept row sub-blocks
+                const int nt = ld / 128, W = mask_words(ld);
+                unsigned long long* mk = env_mask(env, nt);
+                int ni = 0, nj = 0;
+                for (int q = 0; q < 4; ++q) {
+                    ni |= s_bits[q];
+                    nj |= (s_bits[q] != 0 ? 1 : 0) << q;
+                }
+                atomicOr(&mk[(size_t)bi * W + ((4 * bj) >> 6)], (unsigned long long)ni << ((4 * bj) & 63));
+                if (mirror)
+                    atomicOr(&mk[(size_t)bj * W + ((4 * bi) >> 6)], (unsigned long long)nj << ((4 * bi) & 63));
             }
         }
     }
@@ -199,14 +214,15 @@ __global__ __launch_bounds__(256) void k_block_threshold_list(double* __restrict
     }
 }
 
-// Empty ranges for every panel (before a threshold pass records new ones).
-__global__ void k_env_reset(int* __restrict__ env, int npanel, const State* __restrict__ st) {
+// Empty ranges and masks for every panel (before a threshold pass records new ones).
+__global__ void k_env_reset(int* __restrict__ env, int npanel, int nwords, const State* __restrict__ st) {
     if (st->done) return;
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p < npanel) {
         env[2 * p] = 0x7fffffff;
         env[2 * p + 1] = -1;
     }
+    if (p < npanel * nwords) env_mask(env, npanel)[p] = 0ull;
 }
 
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
@@ -215,7 +231,10 @@ hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, dou
     const int nt = ld / 128;
     const int T = nt * (nt + 1) / 2;
     *nslots = T;
-    if (env) hipLaunchKernelGGL(k_env_reset, dim3((nt + 255) / 256), dim3(256), 0, stream, env, nt, st);
+    if (env) {
+        const int W = mask_words(ld);
+        hipLaunchKernelGGL(k_env_reset, dim3((nt * W + 255) / 256), dim3(256), 0, stream, env, nt, W, st);
+    }
     if (list && tz && env && !init)
         hipLaunchKernelGGL(k_block_threshold_list, dim3(std::min(T, 2048)), dim3(256), 0, stream, buf0, buf1, ld, N,
                            tau, elem, st, part, env, tz, list, list + T);

@@ -253,3 +253,20 @@ def block_index(nb: int):
     bj = np.where(np.arange(BLOCKS) < BLOCKS // 2, np.clip(bi + rng.integers(-2, 3, BLOCKS), 0, nb - 1),
                   rng.integers(0, nb, BLOCKS))
     return bi, bj
+
+
+def permuted_groups(pos: np.ndarray, seed: int, group: int = 8) -> np.ndarray:
+    """The same atoms with consecutive groups of `group` atoms (32 orbitals,
+    one 32 x 32 block row, for group = 8) put in a seeded random order; the
+    order inside a group is kept.  The groups are spatially compact (8
+    neighbouring sites of a lattice row), so a Hamiltonian built from them is
+    as block-sparse as the banded one, but its nonzero blocks are scattered
+    over the whole matrix instead of lying in a band."""
+    n = len(pos)
+    ng = n // group
+    order = np.random.default_rng(seed).permutation(ng)
+    idx = (order[:, None] * group + np.arange(group)[None, :]).ravel()
+    return np.concatenate([pos[idx], pos[ng * group:]])
+
+
+PERMUTED_SEED = 31

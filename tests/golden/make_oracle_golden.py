@@ -19,6 +19,10 @@ results are stored once:
   measured on: branches, traces and idempotency error per product, the
   diagonal of D, D applied to two seeded Gaussian probe vectors, eight sampled
   32 x 32 blocks of D and its squared Frobenius norm.
+* ``c3p_blocksparse_permuted_n16384.npz`` — the same thresholded solve with
+  the lattice's 8-atom rows (one 32-orbital block each) in a seeded random
+  order (``synth.permuted_groups``): as block-sparse, but with the nonzero
+  blocks scattered instead of banded.
 * ``c3_blocksparse_n16384.npz`` — the thresholded SP2 solve of the
   elongated 8 x 8 x 64 lattice (seed 3, static model), 32 x 32 blocks with
   Frobenius norm below tau = 1e-5 dropped after X_0 and after every update
@@ -27,7 +31,7 @@ results are stored once:
   blocks kept after each update, the diagonal of D, D applied to two seeded
   Gaussian probe vectors, and eight sampled 32 x 32 blocks of D.
 
-Usage: python tests/golden/make_oracle_golden.py [c1] [c2] [c3]
+Usage: python tests/golden/make_oracle_golden.py [c1] [c2] [c3] [c3p]
 """
 from __future__ import annotations
 
@@ -48,6 +52,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 C1_FILE = os.path.join(HERE, "c1_xlbomd_n4096.npz")
 C2_FILE = os.path.join(HERE, "c2_mixed_n8192.npz")
 C3_FILE = os.path.join(HERE, "c3_blocksparse_n16384.npz")
+C3P_FILE = os.path.join(HERE, "c3p_blocksparse_permuted_n16384.npz")
 
 C1_STEPS = 10
 C3_TAU = 1e-5
@@ -124,7 +129,18 @@ def make_c3():
     log(f"c3: wrote {C3_FILE}")
 
 
+def make_c3p():
+    w = synth.SPARSE
+    H = otb.hamiltonian(synth.permuted_groups(w.positions(), synth.PERMUTED_SEED), None, synth.STATIC_MODEL)
+    t0 = time.time()
+    r = osp2.sp2(H, w.n_occ, tol=1e-10, tau=C3_TAU, threshold="block")
+    log(f"c3p: {r.iterations} products, status {r.status}, in {time.time() - t0:.0f} s")
+    del H
+    np.savez_compressed(C3P_FILE, **solve_summary(r, w.n_orb, tau=C3_TAU))
+    log(f"c3p: wrote {C3P_FILE}")
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c1", "c2", "c3"]
+    which = sys.argv[1:] or ["c1", "c2", "c3", "c3p"]
     for k in which:
-        {"c1": make_c1, "c2": make_c2, "c3": make_c3}[k]()
+        {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c3p": make_c3p}[k]()
