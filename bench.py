@@ -614,6 +614,7 @@ def main():
     ap.add_argument("--precision", default="int8x", choices=["int8x", "fp64", "bf16x2"])
     ap.add_argument("--slices", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-table", default=None, help="write the autotuner's table to this file")
     ap.add_argument("--idem-tol", type=float, default=1e-10,
                     help="stop tolerance on ||X^2 - X||_F for both paths of the main solve")
     ap.add_argument("--fp64-steps", type=int, default=1)
@@ -667,7 +668,10 @@ def main():
     tune = {"fp64": ctx.sp2_autotune(N, "fp64")}
     if args.precision != "fp64":
         tune[args.precision] = ctx.sp2_autotune(N, args.precision, args.slices)
-    log("autotune: " + ", ".join(f"{k} tile_group {v['tile_group']}" for k, v in tune.items()))
+    log("autotune: " + ", ".join(f"{k} tile_group {v['tile_group']} stage_cfg {v['stage_cfg']} split_cap "
+                                 f"{v['split_cap']}" for k, v in tune.items()))
+    if args.tune_table:
+        ctx.sp2_tune_save(args.tune_table)
 
     if args.traffic_probe:
         # calibration for the HBM byte counters: kernels of known traffic
@@ -782,9 +786,13 @@ def main():
         "config": {"workload": "mixed_n8192: 2048-atom 8x16x16 jittered sp tight-binding lattice, "
                                "N=8192, n_occ=4096", "precision": prec,
                    "slices": args.slices if prec == "int8x" else None,
-                   "tile_group": tune[prec]["tile_group"]},
-        "autotune_ms_per_product": {k: {str(g): round(ms, 4) for g, ms in v["ms_per_product"].items()}
-                                    for k, v in tune.items()},
+                   "tile_group": tune[prec]["tile_group"], "stage_cfg": tune[prec]["stage_cfg"],
+                   "split_cap": tune[prec]["split_cap"]},
+        "autotune": {k: {"chosen": {"tile_group": v["tile_group"], "stage_cfg": v["stage_cfg"],
+                                    "split_cap": v["split_cap"]},
+                         "ms_per_product": {"G%d/cfg%d/cap%d" % g: round(ms, 4)
+                                            for g, ms in v["ms_per_product"].items()}}
+                     for k, v in tune.items()},
         "solves_per_s": round(1e3 / ms, 4),
         "products": iters,
         "fp64_path": {"ms_per_solve": round(ms64, 2), "tflops": round(tflops64, 3),

@@ -78,10 +78,12 @@ typedef struct {
                             blocks outside each panel's nonzero range         */
     int tile_group;      /* order of the 128x128 product tiles: G x G super-tiles
                             dealt to the XCDs (G > 0), 0 = plain row-major, -1
-                            (default) = the value sp2_autotune chose for this
-                            size and precision, else 8.  INT8X results do not
-                            depend on it; FP64 products with a tail split (see
-                            below) may differ in the last bits               */
+                            (default) = the value sp2_autotune chose (or a
+                            loaded table holds) for this size and precision,
+                            else 8; the tuned K-stage configuration and split
+                            cap apply whatever tile_group is.  INT8X results
+                            do not depend on these; FP64 products with a tail
+                            split (see below) may differ in the last bits    */
     int tail_split;      /* N >= 4096: when the tiles of the last wave of
                             product workgroups would leave at least half of the
                             workgroup slots idle, split their K loops into
@@ -176,19 +178,39 @@ sp2_status sp2_density_matrix(sp2_ctx *ctx, int N, const double *H, int n_occ,
 sp2_status sp2_density_matrix_noalloc(sp2_ctx *ctx, int N, const double *H, int n_occ,
                                       const sp2_options *opt, double *D_out, sp2_stats *stats);
 
-/* Autotuner of the product tile order: times the SP2 product kernel of the
- * given precision (and slices, for INT8X) at size N on the context's device
- * for each candidate super-tile size, and keeps the fastest for later solves
- * of the same padded size and precision that leave tile_group at -1.
- * out (may be NULL): the choice and the measured ms per product of each
- * candidate.  Uses the context's scratch; results of solves are unaffected. */
+/* Autotuner of the SP2 product's launch configuration: times the product
+ * kernel of the given precision (and slices, for INT8X) at size N on the
+ * context's device for every candidate -- the tile order (G x G super-tiles,
+ * G in {0 (row-major), 4, 8, 16, 32}) and, for INT8X, the K-stage
+ * configuration of the LDS staging ring (stage_cfg 0: 64-byte K stages two
+ * deep (32-byte three deep at six planes), 1: 32-byte stages three deep, 2:
+ * 32-byte stages four deep, up to five planes), for FP64 the most chunks of a
+ * tile split along K (8 or 16) -- on a pseudo-random symmetric operand, and
+ * keeps the fastest for later solves of the same padded size and precision
+ * that leave tile_group at -1 (and for sizes within a factor of 2 that have
+ * no entry of their own).  out (may be NULL): the choice and the measured ms
+ * per product of each candidate.  Uses the context's scratch; INT8X results
+ * do not depend on the choice, FP64 results at the rounding level. */
 typedef struct {
     int tile_group;          /* chosen super-tile size (0 = row-major)            */
+    int stage_cfg;           /* INT8X: chosen K-stage configuration              */
+    int split_cap;           /* FP64: chosen most chunks of a split tile          */
     int n_candidates;
-    int candidates[8];
-    float ms_per_product[8];
+    int candidates[16][3];   /* (tile_group, stage_cfg, split_cap) per candidate  */
+    float ms_per_product[16];
 } sp2_tune_result;
 sp2_status sp2_autotune(sp2_ctx *ctx, int N, int precision, int slices, sp2_tune_result *out);
+
+/* Persisted autotuner table.  sp2_tune_save writes every configuration the
+ * context holds (tuned or loaded) to the text file at path, one line per
+ * (device architecture, compute units, padded N, precision, slices);
+ * sp2_tune_load adds a file's entries for this context's device type (other
+ * architectures and out-of-range entries are skipped).  sp2_ctx_create loads
+ * the table named by the environment variable SP2QMD_TUNE_TABLE when it is
+ * set and readable.  SP2_EINVAL: NULL arguments, an unreadable or unwritable
+ * file, a malformed line. */
+sp2_status sp2_tune_save(const sp2_ctx *ctx, const char *path);
+sp2_status sp2_tune_load(sp2_ctx *ctx, const char *path);
 
 /* Measurement aid, not a step of the path: the rate of the int8 product
  * kernel's instruction (v_mfma_i32_32x32x32_i8; 2 ops per multiply-add) this

@@ -39,8 +39,9 @@ class Sp2Options(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("tile_group", ctypes.c_int), ("n_candidates", ctypes.c_int),
-                ("candidates", ctypes.c_int * 8), ("ms_per_product", ctypes.c_float * 8)]
+    _fields_ = [("tile_group", ctypes.c_int), ("stage_cfg", ctypes.c_int), ("split_cap", ctypes.c_int),
+                ("n_candidates", ctypes.c_int), ("candidates", (ctypes.c_int * 3) * 16),
+                ("ms_per_product", ctypes.c_float * 16)]
 
 
 class Sp2Stats(ctypes.Structure):
@@ -114,6 +115,8 @@ _SIGS = {
                                         ctypes.POINTER(Sp2Stats)]),
     "sp2_mulliken": (_I, [_P, _I, _P, _D, _P]),
     "sp2_autotune": (_I, [_P, _I, _I, _I, ctypes.POINTER(TuneResult)]),
+    "sp2_tune_save": (_I, [_P, ctypes.c_char_p]),
+    "sp2_tune_load": (_I, [_P, ctypes.c_char_p]),
     "sp2_int8_mfma_rate": (_I, [_P, ctypes.POINTER(_D)]),
     "sp2_band_energy": (_I, [_P, _I, _P, _P, ctypes.POINTER(_D)]),
     "sp2_density_matrix_nonorth": (_I, [_P, _I, _P, _P, _I, ctypes.POINTER(Sp2Options), _P,
@@ -384,13 +387,20 @@ class Context:
         return v.value
 
     def sp2_autotune(self, N: int, precision="int8x", slices: int = 5):
-        """Time the product kernel per tile order at size N; the choice is kept
-        for later solves of that size and precision (tile_group = -1)."""
+        """Time the product kernel per launch configuration (tile order; K-stage
+        configuration for int8x; split cap for fp64) at size N; the choice is
+        kept for later solves of that size and precision (tile_group = -1)."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         r = TuneResult()
         self._check(lib().sp2_autotune(self._h, int(N), prec, int(slices), ctypes.byref(r)), "sp2_autotune")
-        return {"tile_group": r.tile_group,
-                "ms_per_product": {r.candidates[k]: r.ms_per_product[k] for k in range(r.n_candidates)}}
+        return {"tile_group": r.tile_group, "stage_cfg": r.stage_cfg, "split_cap": r.split_cap,
+                "ms_per_product": {tuple(r.candidates[k]): r.ms_per_product[k] for k in range(r.n_candidates)}}
+
+    def sp2_tune_save(self, path: str):
+        self._check(lib().sp2_tune_save(self._h, str(path).encode()), "sp2_tune_save")
+
+    def sp2_tune_load(self, path: str):
+        self._check(lib().sp2_tune_load(self._h, str(path).encode()), "sp2_tune_load")
 
     def sp2_mulliken(self, D, n_atoms: int, z_val: float = 4.0, q_out=None):
         import torch

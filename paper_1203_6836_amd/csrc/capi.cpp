@@ -8,6 +8,9 @@
 #include <map>
 #include <tuple>
 #include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -30,6 +33,14 @@ constexpr double kAccAFs2 = 9.648533212e-3;  // 1 eV/(A amu) in A/fs^2
 constexpr double kKeEv = 103.6426965;        // 1 amu A^2/fs^2 in eV
 
 }  // namespace
+
+// One autotuned launch configuration of the product kernel of a precision.
+struct TuneChoice {
+    int tile_group = 8;   // super-tile size of the tile order
+    int stage_cfg = 0;    // INT8X: K-stage configuration of dense products
+    int split_cap = 16;   // FP64: most chunks of a split tile
+    float ms = 0.f;       // measured ms per product
+};
 
 struct sp2_ctx {
     int device = 0;
@@ -71,8 +82,11 @@ struct sp2_ctx {
     double* ezero = nullptr;
     double* eF = nullptr;
     size_t eatcap = 0;         // atoms
-    // product tile order chosen by sp2_autotune, per (ld, precision, slices)
-    std::map<std::tuple<int, int, int>, int> tuned;
+    // launch configuration chosen by sp2_autotune (or loaded from a table),
+    // per (padded N, precision, slices)
+    std::map<std::tuple<int, int, int>, TuneChoice> tuned;
+    std::string arch;          // device architecture name (gfx...), the tables' key
+    int cus = 0;
     // device address of the allocation-free solve's static scratch (NULL if
     // the lookup at creation failed; sscratch_err then holds the HIP error)
     void* sscratch = nullptr;
@@ -179,6 +193,14 @@ sp2_status sp2_ctx_create(sp2_ctx** out, int device, void* stream) {
     // set-up of the allocation-free solve: the static scratch's address on
     // this device (the device is current)
     c->sscratch_err = static_scratch_init(device, &c->sscratch);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->arch = prop.gcnArchName;
+        c->arch = c->arch.substr(0, c->arch.find(':'));
+        c->cus = prop.multiProcessorCount;
+    }
+    // an autotuner table named by the environment (missing file: no table)
+    if (const char* path = std::getenv("SP2QMD_TUNE_TABLE")) (void)sp2_tune_load(c, path);
     *out = c;
     return SP2_OK;
 }
@@ -257,6 +279,25 @@ struct SolveScratch {
 
 static int padded_ld(int N) { return ((N + kTile - 1) / kTile) * kTile; }
 
+// The autotuned configuration for (padded N, precision, slices): the entry
+// of that size, else the one of the nearest tuned size within a factor of 2
+// (the N bucket), else the defaults.
+static TuneChoice tuned_choice(const sp2_ctx* c, int ld, int precision, int slices) {
+    auto it = c->tuned.find(std::make_tuple(ld, precision, slices));
+    if (it != c->tuned.end()) return it->second;
+    TuneChoice best;
+    double dist = 1e300;
+    for (const auto& kv : c->tuned) {
+        if (std::get<1>(kv.first) != precision || std::get<2>(kv.first) != slices) continue;
+        const double d = std::fabs(std::log((double)std::get<0>(kv.first) / ld));
+        if (d <= std::log(2.0) && d < dist) {
+            dist = d;
+            best = kv.second;
+        }
+    }
+    return best;
+}
+
 // Partial-sum slots any kernel of a solve of size N writes at most.
 static size_t solve_part_slots(int N) {
     const int ld = padded_ld(N);
@@ -327,12 +368,10 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
     // their upper tiles only and the encode reads the upper triangle
     const bool upper = int8x && o.tau == 0.0 && o.fp64_head == 0;
     c->split.upper = upper;
-    int tile_group = o.tile_group;
-    if (tile_group < 0) {
-        auto it = c->tuned.find(std::make_tuple(ld, o.precision, int8x ? o.slices : 0));
-        tile_group = it != c->tuned.end() ? it->second : 8;
-    }
+    const TuneChoice tc = tuned_choice(c, ld, o.precision, int8x ? o.slices : 0);
+    const int tile_group = o.tile_group >= 0 ? o.tile_group : tc.tile_group;
     c->split.tile_group = tile_group;
+    c->split.stage_cfg = tc.stage_cfg;
     c->split.tail_split = o.tail_split;
 
     CtrlArgs a;
@@ -380,7 +419,7 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
             HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, part, &ns, st, env, tile_group, f64tail,
-                                      f64tail_bytes));
+                                      f64tail_bytes, tuned_choice(c, ld, SP2_PREC_FP64, 0).split_cap));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
@@ -587,54 +626,119 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         sp2_status s = f64_tail_buffer(c, ld, -1, &f64tail, &f64tail_bytes);
         if (s != SP2_OK) return s;
     }
-    std::vector<int> cand;
-    for (int g : {0, 4, 8, 16, 32})
-        if (g == 0 || g < nt) cand.push_back(g);
-    // about 50 ms of products per candidate, at least 3
+    // candidates: tile order G x (INT8X) K-stage configuration or (FP64) the
+    // most chunks of a split tile
+    std::vector<TuneChoice> cand;
+    for (int g : {0, 4, 8, 16, 32}) {
+        if (!(g == 0 || g < nt)) continue;
+        TuneChoice t;
+        t.tile_group = g;
+        if (int8x) {
+            for (int cfg = 0; cfg < 3; ++cfg) {
+                if (cfg == 2 && slices > 5) continue;
+                t.stage_cfg = cfg;
+                cand.push_back(t);
+            }
+        } else if (precision == SP2_PREC_FP64) {
+            for (int cap : {8, 16}) {
+                t.split_cap = cap;
+                cand.push_back(t);
+            }
+        } else {
+            cand.push_back(t);
+        }
+    }
+    // about 40 ms of products per candidate, at least 3
     const double est_ms = (precision == SP2_PREC_FP64 ? 1.0 / 40e9 : 1.0 / 1.2e12) * (double)ld * ld * ld;
-    const int reps = std::max(3, std::min(50, (int)(50.0 / std::max(est_ms, 1e-3))));
-    auto launch = [&](int g) -> sp2_status {
+    const int reps = std::max(3, std::min(40, (int)(40.0 / std::max(est_ms, 1e-3))));
+    auto launch = [&](const TuneChoice& t) -> sp2_status {
         int ns = 0;
-        c->split.tile_group = g;
+        c->split.tile_group = t.tile_group;
+        c->split.stage_cfg = t.stage_cfg;
         if (precision == SP2_PREC_FP64) {
-            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, g, f64tail, f64tail_bytes));
+            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, t.tile_group, f64tail,
+                                      f64tail_bytes, t.split_cap));
         } else {
             HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, nullptr));
         }
         return SP2_OK;
     };
-    int best = 8;
-    float best_ms = 1e30f;
+    TuneChoice best;
+    best.ms = 1e30f;
     sp2_tune_result r{};
     for (size_t k = 0; k < cand.size(); ++k) {
-        const int g = cand[k];
-        if ((s = launch(g)) != SP2_OK) return s;   // warm-up
+        if ((s = launch(cand[k])) != SP2_OK) return s;   // warm-up
         HIPCHK(c, hipEventRecord(c->ev0, st));
         for (int q = 0; q < reps; ++q)
-            if ((s = launch(g)) != SP2_OK) return s;
+            if ((s = launch(cand[k])) != SP2_OK) return s;
         HIPCHK(c, hipEventRecord(c->ev1, st));
         HIPCHK(c, hipEventSynchronize(c->ev1));
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
         ms /= reps;
-        if (k < 8) {
-            r.candidates[k] = g;
+        if (k < 16) {
+            r.candidates[k][0] = cand[k].tile_group;
+            r.candidates[k][1] = cand[k].stage_cfg;
+            r.candidates[k][2] = cand[k].split_cap;
             r.ms_per_product[k] = ms;
             r.n_candidates = (int)k + 1;
         }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = g;
+        if (ms < best.ms) {
+            best = cand[k];
+            best.ms = ms;
         }
     }
-    c->split.tile_group = best;
+    c->split.tile_group = best.tile_group;
+    c->split.stage_cfg = best.stage_cfg;
     c->tuned[std::make_tuple(ld, precision, int8x ? slices : 0)] = best;
-    r.tile_group = best;
+    r.tile_group = best.tile_group;
+    r.stage_cfg = best.stage_cfg;
+    r.split_cap = best.split_cap;
     if (out) *out = r;
     return SP2_OK;
 }
 
+// Table format: a header line, then one line per tuned configuration:
+//   <arch> <compute units> <padded N> <precision> <slices> <tile_group> <stage_cfg> <split_cap> <ms>
+extern "C" sp2_status sp2_tune_save(const sp2_ctx* c, const char* path) {
+    if (!c || !path) return SP2_EINVAL;
+    std::ofstream f(path);
+    if (!f) return SP2_EINVAL;
+    f << "# sp2qmd autotuner table: arch cus ld precision slices tile_group stage_cfg split_cap ms_per_product\n";
+    for (const auto& kv : c->tuned)
+        f << c->arch << ' ' << c->cus << ' ' << std::get<0>(kv.first) << ' ' << std::get<1>(kv.first) << ' '
+          << std::get<2>(kv.first) << ' ' << kv.second.tile_group << ' ' << kv.second.stage_cfg << ' '
+          << kv.second.split_cap << ' ' << kv.second.ms << '\n';
+    return f ? SP2_OK : SP2_EINVAL;
+}
+
+extern "C" sp2_status sp2_tune_load(sp2_ctx* c, const char* path) {
+    if (!c || !path) return SP2_EINVAL;
+    std::ifstream f(path);
+    if (!f) return fail(c, SP2_EINVAL, std::string("cannot read autotuner table ") + path);
+    std::string line;
+    int loaded = 0;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream in(line);
+        std::string arch;
+        int cus, ld, prec, slices;
+        TuneChoice t;
+        if (!(in >> arch >> cus >> ld >> prec >> slices >> t.tile_group >> t.stage_cfg >> t.split_cap >> t.ms))
+            return fail(c, SP2_EINVAL, "malformed autotuner table line: " + line);
+        // entries of another device type, or out of range, are skipped
+        if (arch != c->arch || cus != c->cus) continue;
+        if (ld < kTile || ld % kTile || prec < SP2_PREC_FP64 || prec > SP2_PREC_BF16X2 || t.tile_group < 0 ||
+            t.tile_group > 64 || t.stage_cfg < 0 || t.stage_cfg > 2 || (t.stage_cfg == 2 && slices > 5) ||
+            t.split_cap < 2 || t.split_cap > 16)
+            continue;
+        c->tuned[std::make_tuple(ld, prec, slices)] = t;
+        ++loaded;
+    }
+    (void)loaded;
+    return SP2_OK;
+}
 // ------------------------------------------------ non-orthogonal formulation
 // Row-major C = alpha A B + beta C for N x N matrices: a row-major matrix read
 // as column-major is its transpose, so this is the column-major product

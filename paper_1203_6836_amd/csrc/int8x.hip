@@ -327,14 +327,19 @@ __global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __
 constexpr int QB = 128;          // tile
 constexpr int QK = 32;           // k bytes per block
 
-// K stage: KS blocks of 32 k-bytes; ring depth NST.  Up to five planes fit a
-// 64-byte stage twice in LDS (2 x 80 KiB at five), which halves the
-// barriers per product against 32-byte stages; six planes keep 32-byte
-// stages three deep (3 x 48 KiB).
-template <int S> struct I8Stage {
-    static constexpr int KS = S <= 5 ? 2 : 1;
-    static constexpr int NST = S <= 5 ? 2 : 3;
+// K stage: KS blocks of 32 k-bytes; ring depth NST.  Configuration C = 0
+// (the default): up to five planes fit a 64-byte stage twice in LDS
+// (2 x 80 KiB at five), which halves the barriers per product against
+// 32-byte stages; six planes keep 32-byte stages three deep (3 x 48 KiB).
+// C = 1: 32-byte stages three deep; C = 2: 32-byte stages four deep (up to
+// five planes).  The autotuner picks C per size for dense products.
+template <int S, int C = 0> struct I8Stage {
+    static constexpr int KS = (C == 0 && S <= 5) ? 2 : 1;
+    static constexpr int NST = C == 0 ? (S <= 5 ? 2 : 3) : (C == 1 ? 3 : 4);
+    static_assert(NST * 2 * S * 4 * KS <= 160, "stage ring exceeds the LDS");
 };
+// Configurations valid for S planes.
+__host__ __device__ constexpr bool i8_cfg_ok(int S, int C) { return C == 0 || C == 1 || (C == 2 && S <= 5); }
 
 // The staging ring; after the K loop the same LDS holds half of the finished
 // tile, transposed, so the mirrored (lower-triangle) copy is written as
@@ -342,10 +347,10 @@ template <int S> struct I8Stage {
 // spreads the column-wise LDS stores over the banks.
 constexpr int TR_LD = 129;
 
-template <int S>
+template <int S, int C = 0>
 struct I8Smem {
     union {
-        int8_t buf[I8Stage<S>::NST][2 * S * 4 * I8Stage<S>::KS][1024];   // [stage][((op S + slice) 4 + row block) KS + k block][block]
+        int8_t buf[I8Stage<S, C>::NST][2 * S * 4 * I8Stage<S, C>::KS][1024];   // [stage][((op S + slice) 4 + row block) KS + k block][block]
         double tr[64][TR_LD];                  // [tile column (one half)][tile row]
         struct {
             unsigned long long rm[128], cm[128];   // tile row / column maxima (upper-only mode)
@@ -366,11 +371,11 @@ struct I8Smem {
 // only (no mirrored copy below the diagonal) and fold its row and column
 // maxima of |X_{n+1}| into rmax_next (bit patterns of non-negative doubles
 // order like the values, so atomicMax on them is exact and order-free).
-template <int S, bool THR, bool UPPER>
+template <int S, bool THR, bool UPPER, int C = 0>
 __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1, int ld,
                            const State* __restrict__ st, const int8_t* __restrict__ digits,
                            const double* __restrict__ scale, double* __restrict__ part, int bi, int bj,
-                           I8Smem<S>& sm, const int* __restrict__ env,
+                           I8Smem<S, C>& sm, const int* __restrict__ env,
                            unsigned long long* __restrict__ rmax_next, int kmode = 0, int kc0 = 0,
                            int kc1 = -1, int* __restrict__ chunk_acc = nullptr, int nchunks = 0) {
     const int nt = ld / QB;
@@ -384,7 +389,7 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
 
-    constexpr int KS = I8Stage<S>::KS, NST = I8Stage<S>::NST;
+    constexpr int KS = I8Stage<S, C>::KS, NST = I8Stage<S, C>::NST;
     constexpr int NBLK = 2 * S * 4 * KS;        // 1 KiB blocks per stage
     constexpr int PER = NBLK * 64 / 512;        // 16-byte chunks per thread
     static_assert((NBLK * 64) % 512 == 0, "stage must split evenly over 512 threads");
@@ -518,8 +523,9 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
             // every outstanding load) then covers the other waves' blocks, and
             // every wave has finished reading the buffer that stage
             // kt + NST - 1 overwrites
-            if (NST == 3 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
-            else __builtin_amdgcn_s_waitcnt(0x0F70);                                 // vmcnt(0)
+            if (NST == 4 && kt + 2 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * PER));   // vmcnt(2 PER)
+            else if (NST >= 3 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
+            else __builtin_amdgcn_s_waitcnt(0x0F70);                                      // vmcnt(0)
             __builtin_amdgcn_s_barrier();
             if (kt + NST - 1 < nk) issue(kt + NST - 1, (kt + NST - 1 - ks) % NST);
             compute((kt - ks) % NST);
@@ -547,8 +553,9 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
         // wait for every outstanding load) then covers the other waves'
         // blocks, and every wave has finished reading the slot that the next
         // issue overwrites
-        if (NST == 3 && n_iss - n_done == 2) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                                         // vmcnt(0)
+        if (NST == 4 && n_iss - n_done == 3) __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * PER));   // vmcnt(2 PER)
+        else if (NST >= 3 && n_iss - n_done >= 2) __builtin_amdgcn_s_waitcnt(0x0F70 | PER);   // vmcnt(PER)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                                              // vmcnt(0)
         __builtin_amdgcn_s_barrier();
         if (ic < nk) {
             issue(ic, n_iss % NST);
@@ -719,7 +726,7 @@ __device__ __forceinline__ void diag_tile(int pos, int nt, int& bi, int& bj) {
     bj = bi + d;
 }
 
-template <int S, bool THR, bool UPPER>
+template <int S, bool THR, bool UPPER, int C = 0>
 __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
                                                     int ld, const State* __restrict__ st,
                                                     const int8_t* __restrict__ digits,
@@ -729,7 +736,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
                                                     int t_full, int nsplit, int* __restrict__ chunk_acc) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
-    I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
+    I8Smem<S, C>& sm = *reinterpret_cast<I8Smem<S, C>*>(smem_raw);
     const int nt = ld / QB, w = blockIdx.x;
     int pos, kmode = 0, kc0 = 0, kc1 = -1;
     int* cacc = nullptr;
@@ -738,7 +745,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
     } else if (w < t_full) {
         pos = xcd_deal(w, t_full);
     } else {
-        const int j = w - t_full, p = j / nsplit, ch = j - p * nsplit, nk = ld / (QK * I8Stage<S>::KS);
+        const int j = w - t_full, p = j / nsplit, ch = j - p * nsplit, nk = ld / (QK * I8Stage<S, C>::KS);
         pos = t_full + p;
         kmode = 1;
         kc0 = ch * nk / nsplit;
@@ -748,7 +755,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
     int bi, bj;
     if (THR) diag_tile(pos, nt, bi, bj);
     else order_tile(pos, nt, tile_group, bi, bj);
-    int8x_tile<S, THR, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
+    int8x_tile<S, THR, UPPER, C>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
                               UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, kmode, kc0, kc1, cacc, 0);
 }
 
@@ -887,7 +894,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_list(double* __restrict__ bu
 
 // Epilogue of the split tiles: workgroup p sums the nsplit chunks of the tile
 // at visiting position t_full + p and applies the update.
-template <int S, bool UPPER>
+template <int S, bool UPPER, int C = 0>
 __global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ buf0, double* __restrict__ buf1,
                                                          int ld, const State* __restrict__ st,
                                                          const int8_t* __restrict__ digits,
@@ -897,10 +904,10 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ bu
                                                          int t_full, int nsplit, int* __restrict__ chunk_acc) {
     if (st->done || st->phase != 1) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
-    I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
+    I8Smem<S, C>& sm = *reinterpret_cast<I8Smem<S, C>*>(smem_raw);
     int bi, bj;
     order_tile(t_full + blockIdx.x, ld / QB, tile_group, bi, bj);
-    int8x_tile<S, false, UPPER>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, nullptr,
+    int8x_tile<S, false, UPPER, C>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, nullptr,
                                 UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, 2, 0, -1,
                                 chunk_acc + (size_t)blockIdx.x * nsplit * (S * 2 * 16 * 512), nsplit);
 }
@@ -939,18 +946,18 @@ int device_cus() {
     return n;
 }
 
-template <int S, bool THR, bool UPPER>
+template <int S, bool THR, bool UPPER, int C = 0>
 static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                                      hipStream_t stream, const int* env) {
     const int nt = ld / QB;
     const int T = nt * (nt + 1) / 2;
-    const size_t lds = sizeof(I8Smem<S>);
+    const size_t lds = sizeof(I8Smem<S, C>);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, THR, UPPER>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, THR, UPPER, C>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e == hipSuccess && !THR)
-            e = hipFuncSetAttribute((const void*)k_gemm_int8x_tail<S, UPPER>,
+            e = hipFuncSetAttribute((const void*)k_gemm_int8x_tail<S, UPPER, C>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -970,10 +977,10 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
         }
     }
     const int grid = t_full + (T - t_full) * nsplit;
-    hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits,
-                       s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
+    hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER, C>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st,
+                       s.digits, s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
     if (t_full < T)
-        hipLaunchKernelGGL((k_gemm_int8x_tail<S, UPPER>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
+        hipLaunchKernelGGL((k_gemm_int8x_tail<S, UPPER, C>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
                            st, s.digits, s.scale, part, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
     return hipGetLastError();
 }
@@ -1007,6 +1014,15 @@ static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld,
                             hipStream_t stream, const int* env) {
     if (env && s.tz) return launch_list_kernel<S>(s, buf0, buf1, ld, st, part, stream, env);
     if (env) return launch_tile_kernel<S, true, false>(s, buf0, buf1, ld, st, part, stream, env);
+    // dense products: the stage configuration chosen by the autotuner
+    if constexpr (i8_cfg_ok(S, 2)) {
+        if (s.stage_cfg == 2)
+            return s.upper ? launch_tile_kernel<S, false, true, 2>(s, buf0, buf1, ld, st, part, stream, nullptr)
+                           : launch_tile_kernel<S, false, false, 2>(s, buf0, buf1, ld, st, part, stream, nullptr);
+    }
+    if (s.stage_cfg == 1)
+        return s.upper ? launch_tile_kernel<S, false, true, 1>(s, buf0, buf1, ld, st, part, stream, nullptr)
+                       : launch_tile_kernel<S, false, false, 1>(s, buf0, buf1, ld, st, part, stream, nullptr);
     if (s.upper) return launch_tile_kernel<S, false, true>(s, buf0, buf1, ld, st, part, stream, nullptr);
     return launch_tile_kernel<S, false, false>(s, buf0, buf1, ld, st, part, stream, nullptr);
 }

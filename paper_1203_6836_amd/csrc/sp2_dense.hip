@@ -756,7 +756,7 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s) {
 }
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
                            int* nslots, hipStream_t s, const int* env, int tile_group, double* tail_buf,
-                           size_t tail_bytes) {
+                           size_t tail_bytes, int split_cap) {
     const int nt = ld / GB;
     const int T = tri_tiles(nt);
     *nslots = T;
@@ -767,7 +767,7 @@ hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double
     // workgroup walks its K stages one after another): all of its tiles are
     // split.  The chunk count balances the stages a chunk walks (~2.8 us
     // each) against the chunks the tail kernel reads back one after another
-    // (~2 us each): about sqrt(1.4 nk), at most 16 and no more than fit.
+    // (~2 us each): about sqrt(1.4 nk), at most split_cap and no more than fit.
     int t_full = T, nsplit = 1;
     if (!env && tail_buf) {
         const int slots = 2 * device_cus();
@@ -775,10 +775,10 @@ hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double
         int r = 0;
         if (nk >= 256) {
             r = T % slots;
-            if (r > 0 && 2 * r <= slots) nsplit = std::min(16, slots / r);
+            if (r > 0 && 2 * r <= slots) nsplit = std::min(split_cap, slots / r);
         } else if (2 * T <= slots) {
             r = T;
-            nsplit = std::min({16, slots / T, nk, (int)std::lround(std::sqrt(1.4 * nk))});
+            nsplit = std::min({split_cap, slots / T, nk, (int)std::lround(std::sqrt(1.4 * nk))});
         }
         if (nsplit >= 2 && (size_t)r * nsplit * kF64Chunk * sizeof(double) <= tail_bytes) t_full = T - r;
         else nsplit = 1;

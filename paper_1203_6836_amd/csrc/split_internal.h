@@ -22,6 +22,7 @@ struct SplitScratch {
     unsigned long long* rmax = nullptr;  // 2 x ld row maxima of |X| (bit patterns), one row per X buffer
     bool upper = false;         // int8 products write upper tiles only (set per solve)
     int tile_group = 8;         // super-tile size of the product tile order (set per solve)
+    int stage_cfg = 0;          // int8 K-stage configuration of dense products (0, 1, 2; set per solve)
     int tail_split = -1;        // split the tiles of a partly filled last wave along K (0: never)
     int* tail_acc = nullptr;    // int32 accumulators of the K chunks of split tiles
     size_t tail_bytes = 0;

@@ -150,7 +150,9 @@ def test_bf16x2_configured_recipe_reported(ctx, dims, seed):
 
 
 def test_autotune_and_tile_order_invariance(ctx):
-    """The autotuner times each tile order; every order gives bitwise the same D."""
+    """The autotuner times every candidate launch configuration (tile order;
+    int8: K-stage configuration; FP64: split cap) and keeps the fastest;
+    every tile order gives bitwise the same D."""
     import torch
     import paper_1203_6836_amd as p
     say("case autotune + tile-order invariance N=2048")
@@ -159,13 +161,58 @@ def test_autotune_and_tile_order_invariance(ctx):
     nocc = 2 * len(pos)
     for prec in ("int8x", "fp64"):
         r = ctx.sp2_autotune(H.shape[0], prec)
-        say(f"  {prec}: chose {r['tile_group']} from {r['ms_per_product']}")
-        assert r["tile_group"] in r["ms_per_product"]
+        key = (r["tile_group"], r["stage_cfg"], r["split_cap"])
+        say(f"  {prec}: chose {key} from {len(r['ms_per_product'])} candidates")
+        assert key in r["ms_per_product"]
+        # tile orders G in {0, 4, 8, 16, 32} with G < 16 tiles per side: {0, 4, 8}
+        assert len(r["ms_per_product"]) == (9 if prec == "int8x" else 6)
         assert all(ms > 0 for ms in r["ms_per_product"].values())
-        assert r["ms_per_product"][r["tile_group"]] == min(r["ms_per_product"].values())
+        assert r["ms_per_product"][key] == min(r["ms_per_product"].values())
         Ds = [ctx.sp2_density_matrix(H, nocc, p.options(prec, tile_group=g))[0] for g in (-1, 0, 4, 8)]
         for D in Ds[1:]:
             assert torch.equal(D, Ds[0])
+
+
+def test_tune_table_round_trip_and_stage_configs(ctx, tmp_path):
+    """A saved autotuner table loads into a new context (explicitly and from
+    SP2QMD_TUNE_TABLE at creation) and saves back identically; every int8
+    K-stage configuration it can select gives bitwise the same D."""
+    import os
+    import torch
+    import paper_1203_6836_amd as p
+    say("case autotuner table round trip and int8 stage configurations N=2048")
+    pos = synth.lattice_positions((8, 8, 8), seed=2)
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, torch.from_numpy(pos).cuda())
+    nocc = 2 * len(pos)
+    ctx.sp2_autotune(H.shape[0], "int8x")
+    path = tmp_path / "tune.txt"
+    ctx.sp2_tune_save(str(path))
+    lines = [l for l in path.read_text().splitlines() if l and not l.startswith("#")]
+    assert lines
+    arch, cus = lines[0].split()[:2]
+    c2 = p.Context(0)
+    c2.sp2_tune_load(str(path))
+    c2.sp2_tune_save(str(tmp_path / "tune2.txt"))
+    assert (tmp_path / "tune2.txt").read_text() == path.read_text()
+    c2.close()
+    os.environ["SP2QMD_TUNE_TABLE"] = str(path)
+    try:
+        c3 = p.Context(0)
+    finally:
+        del os.environ["SP2QMD_TUNE_TABLE"]
+    c3.sp2_tune_save(str(tmp_path / "tune3.txt"))
+    assert (tmp_path / "tune3.txt").read_text() == path.read_text()
+    c3.close()
+    ref, _ = ctx.sp2_density_matrix(H, nocc, p.options("int8x", tile_group=8))
+    for cfg in (0, 1, 2):
+        tp = tmp_path / f"cfg{cfg}.txt"
+        tp.write_text(f"{arch} {cus} 2048 1 5 8 {cfg} 16 1.0\n")
+        cc = p.Context(0)
+        cc.sp2_tune_load(str(tp))
+        D, st = cc.sp2_density_matrix(H, nocc, p.options("int8x"))
+        say(f"  stage_cfg {cfg}: {st['iterations']} products")
+        assert torch.equal(D, ref)
+        cc.close()
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 16), (8, 8, 16)])
