@@ -606,13 +606,50 @@ def finite_temperature(ctx, dims=(8, 8, 16), kT=0.5, n_steps=16):
     return out
 
 
+def breakdown(st):
+    """Product, encode and threshold kernel time of one profiled solve."""
+    return {"fp64_products": round(st["prod_ms"][0], 2), "reduced_products": round(st["prod_ms"][1], 2),
+            "encode": round(st["encode_ms"], 2), "threshold": round(st["post_ms"], 2),
+            "wall": round(st["ms"], 2)}
+
+
+def digit_products(slices, levels):
+    """int8 digit products per SP2 product: planes t, u < slices with t + u < levels."""
+    return sum(1 for t in range(slices) for u in range(slices) if t + u < (levels or slices))
+
+
+def five_planes(ctx, H, nocc, n_atoms, g2, idem_tol, ms64):
+    """The five-plane int8 recipe (15 digit products) on the same workload:
+    time per solve and error against the oracle, beside the headline recipe."""
+    import torch
+    import paper_1203_6836_amd as p
+    log("int8x five planes (15 digit products)")
+    opts = p.options("int8x", slices=5, levels=5)
+    opts.idem_tol = idem_tol
+    D = torch.empty_like(H)
+    ctx.sp2_autotune(H.shape[0], "int8x", 5, 5)
+    ctx.sp2_density_matrix(H, nocc, opts, D_out=D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = ctx.sp2_density_matrix(H, nocc, opts, D_out=D)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out = {"slices": 5, "levels": 5, "digit_products": 15, "ms_per_solve": round(ms, 2),
+           "products": st["iterations"], "speedup_vs_fp64": round(ms64 / ms, 3),
+           "vs_oracle": against_golden(D, g2, n_atoms) if g2 is not None else None}
+    log(f"  {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="int8x", choices=["int8x", "fp64", "bf16x2"])
-    ap.add_argument("--slices", type=int, default=5)
+    ap.add_argument("--slices", type=int, default=4, help="int8 digit planes")
+    ap.add_argument("--levels", type=int, default=5,
+                    help="int8 digit-product levels kept (slices or slices + 1)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-table", default=None, help="write the autotuner's table to this file")
     ap.add_argument("--idem-tol", type=float, default=1e-10,
@@ -657,7 +694,7 @@ def main():
     torch.cuda.synchronize()
 
     def solve(prec, Dout):
-        opts = p.options(prec, slices=args.slices) if prec == "int8x" else p.options(prec)
+        opts = p.options(prec, slices=args.slices, levels=args.levels) if prec == "int8x" else p.options(prec)
         opts.idem_tol = args.idem_tol
         Dout, st = ctx.sp2_density_matrix(H, nocc, opts, D_out=Dout)
         q = ctx.sp2_mulliken(Dout, w.n_atoms)
@@ -667,7 +704,7 @@ def main():
     # product tile order for this size (timed on the device; not in the timed region)
     tune = {"fp64": ctx.sp2_autotune(N, "fp64")}
     if args.precision != "fp64":
-        tune[args.precision] = ctx.sp2_autotune(N, args.precision, args.slices)
+        tune[args.precision] = ctx.sp2_autotune(N, args.precision, args.slices, args.levels)
     log("autotune: " + ", ".join(f"{k} tile_group {v['tile_group']} stage_cfg {v['stage_cfg']} split_cap "
                                  f"{v['split_cap']}" for k, v in tune.items()))
     if args.tune_table:
@@ -754,8 +791,8 @@ def main():
     unit = "TOP/s" if prec == "int8x" else "TFLOP/s"
     kname = "k_gemm_f64" if prec == "fp64" else ("k_gemm_int8x" if prec == "int8x" else "k_gemm_bf16x2")
     traffic = recorded_traffic(kname) if kname in KERNEL_SOURCES else None
-    if prec == "int8x" and args.slices != 5:
-        traffic = None                      # counters are taken with 5 digit planes
+    if prec == "int8x" and (args.slices, args.levels) != (4, 5):
+        traffic = None                      # counters are taken with 4 planes, 5 levels
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK[prec], "unit": unit,
             "frac": round(achieved / PEAK[prec], 4), "traffic": traffic,
             "algorithmic_unit": "2 N^3 per SP2 product (GEMM-equivalent), every precision",
@@ -763,7 +800,7 @@ def main():
             "kernel": kname, "kernel_ms_avg": round(kms, 4), "launches": cnt}
     # what the matrix cores actually issue: the upper tiles only (N^2 (N + 1)
     # multiply-adds x 2), times the digit-plane products of the expansion
-    issue_mult = {"int8x": args.slices * (args.slices + 1) // 2, "bf16x2": 3, "fp64": 1}[prec]
+    issue_mult = {"int8x": digit_products(args.slices, args.levels), "bf16x2": 3, "fp64": 1}[prec]
     issued = issue_mult * sym_flops / (kms * 1e-3) / 1e12
     roof["mfma_issue"] = {"ops_per_launch": issue_mult * sym_flops, "rate": round(issued, 2), "unit": unit,
                           "frac_of_peak": round(issued / PEAK[prec], 4)}
@@ -786,6 +823,8 @@ def main():
         "config": {"workload": "mixed_n8192: 2048-atom 8x16x16 jittered sp tight-binding lattice, "
                                "N=8192, n_occ=4096", "precision": prec,
                    "slices": args.slices if prec == "int8x" else None,
+                   "levels": args.levels if prec == "int8x" else None,
+                   "digit_products": digit_products(args.slices, args.levels) if prec == "int8x" else None,
                    "tile_group": tune[prec]["tile_group"], "stage_cfg": tune[prec]["stage_cfg"],
                    "split_cap": tune[prec]["split_cap"]},
         "autotune": {k: {"chosen": {"tile_group": v["tile_group"], "stage_cfg": v["stage_cfg"],
@@ -803,6 +842,8 @@ def main():
                       "mfma_issue_tflops": round(sym_flops / (kms64 * 1e-3) / 1e12, 2),
                       "mfma_issue_frac_of_peak": round(sym_flops / (kms64 * 1e-3) / 1e12 / PEAK["fp64"], 4)},
         "speedup_vs_fp64": round(ms64 / ms, 3),
+        # HIP-event sums of one profiled solve of each path (ms per solve)
+        "solve_breakdown_ms": {prec: breakdown(stats[-1]), "fp64": breakdown(st64p)},
         "idem_tol": args.idem_tol,
         "idem_last": {prec: [float(f"{e:.3g}") for e in stats[-1]["idem_hist"][-6:]],
                       "fp64": [float(f"{e:.3g}") for e in st64["idem_hist"][-6:]]},
@@ -810,6 +851,8 @@ def main():
         "vs_oracle": vs_oracle,
         "roofline": roof,
     }
+    if prec == "int8x" and (args.slices, args.levels) != (5, 5):
+        out["int8x_five_planes"] = five_planes(ctx, H, nocc, w.n_atoms, g2, args.idem_tol, ms64)
     if args.serve_requests > 0 and prec == "int8x":
         out["serving"] = serving(ctx, args.serve_requests, args.serve_rate)
     log("fp64_n256 solve")

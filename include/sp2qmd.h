@@ -46,12 +46,13 @@ typedef enum {
  * decisions are FP64 in every mode). */
 typedef enum {
     SP2_PREC_FP64 = 0,   /* FP64 MFMA products                                   */
-    SP2_PREC_INT8X = 1,  /* FP64 master X split into `slices` row-scaled int8
-                            digit planes (8 bits per digit while
-                            (slices - 1) 2^14 N < 2^31, else 7); all digit
-                            products with level t+u < slices on int8 MFMA
-                            with exact int32 accumulation, levels combined
-                            in FP64                                             */
+    SP2_PREC_INT8X = 1,  /* FP64 master X split into `slices` int8 digit
+                            planes, each row scaled so that its largest
+                            element fills the top digit (8 bits per digit
+                            while slices 2^14 N < 2^31, else 7); the digit
+                            products of planes t, u with level t+u < levels
+                            on int8 MFMA with exact int32 accumulation,
+                            levels combined in FP64 (the Ozaki scheme)       */
     SP2_PREC_BF16X2 = 2  /* BF16 hi+lo split with FP32 MFMA accumulation, FP32
                             master, then `fp32_tail` FP32 iterations            */
 } sp2_precision;
@@ -98,6 +99,14 @@ typedef struct {
                             Frobenius norm is < tau; 1 zero each element with
                             |x| < tau (the paper's rule). Fill fractions count
                             the 32x32 blocks that still hold a nonzero       */
+    int levels;          /* INT8X: digit-product levels kept, slices (the
+                            triangle, slices (slices + 1) / 2 products) or
+                            slices + 1 (slices - 1 more products: the
+                            accuracy of operands rounded to 8 slices bits;
+                            slices <= 5); 0 (default) = slices.  Four planes
+                            with five levels (13 products) reach the 1e-6
+                            Frobenius error per sqrt(N) of mixed precision at
+                            13/15 of the five-plane cost                     */
 } sp2_options;
 
 typedef struct {
@@ -179,7 +188,8 @@ sp2_status sp2_density_matrix_noalloc(sp2_ctx *ctx, int N, const double *H, int 
                                       const sp2_options *opt, double *D_out, sp2_stats *stats);
 
 /* Autotuner of the SP2 product's launch configuration: times the product
- * kernel of the given precision (and slices, for INT8X) at size N on the
+ * kernel of the given precision (and slices and levels (0 = slices), for
+ * INT8X) at size N on the
  * context's device for every candidate -- the tile order (G x G super-tiles,
  * G in {0 (row-major), 4, 8, 16, 32}) and, for INT8X, the K-stage
  * configuration of the LDS staging ring (stage_cfg 0: 64-byte K stages two
@@ -199,11 +209,11 @@ typedef struct {
     int candidates[16][3];   /* (tile_group, stage_cfg, split_cap) per candidate  */
     float ms_per_product[16];
 } sp2_tune_result;
-sp2_status sp2_autotune(sp2_ctx *ctx, int N, int precision, int slices, sp2_tune_result *out);
+sp2_status sp2_autotune(sp2_ctx *ctx, int N, int precision, int slices, int levels, sp2_tune_result *out);
 
 /* Persisted autotuner table.  sp2_tune_save writes every configuration the
  * context holds (tuned or loaded) to the text file at path, one line per
- * (device architecture, compute units, padded N, precision, slices);
+ * (device architecture, compute units, padded N, precision, slices, levels);
  * sp2_tune_load adds a file's entries for this context's device type (other
  * architectures and out-of-range entries are skipped).  sp2_ctx_create loads
  * the table named by the environment variable SP2QMD_TUNE_TABLE when it is

@@ -35,7 +35,7 @@ class Sp2Options(ctypes.Structure):
                 ("fp64_head", ctypes.c_int), ("slices", ctypes.c_int),
                 ("fp32_tail", ctypes.c_int), ("tau", ctypes.c_double),
                 ("tile_group", ctypes.c_int), ("tail_split", ctypes.c_int),
-                ("threshold", ctypes.c_int)]
+                ("threshold", ctypes.c_int), ("levels", ctypes.c_int)]
 
 
 class TuneResult(ctypes.Structure):
@@ -114,7 +114,7 @@ _SIGS = {
     "sp2_density_matrix_noalloc": (_I, [_P, _I, _P, _I, ctypes.POINTER(Sp2Options), _P,
                                         ctypes.POINTER(Sp2Stats)]),
     "sp2_mulliken": (_I, [_P, _I, _P, _D, _P]),
-    "sp2_autotune": (_I, [_P, _I, _I, _I, ctypes.POINTER(TuneResult)]),
+    "sp2_autotune": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(TuneResult)]),
     "sp2_tune_save": (_I, [_P, ctypes.c_char_p]),
     "sp2_tune_load": (_I, [_P, ctypes.c_char_p]),
     "sp2_int8_mfma_rate": (_I, [_P, ctypes.POINTER(_D)]),
@@ -386,13 +386,14 @@ class Context:
         self._check(lib().sp2_int8_mfma_rate(self._h, ctypes.byref(v)), "sp2_int8_mfma_rate")
         return v.value
 
-    def sp2_autotune(self, N: int, precision="int8x", slices: int = 5):
+    def sp2_autotune(self, N: int, precision="int8x", slices: int = 5, levels: int = 0):
         """Time the product kernel per launch configuration (tile order; K-stage
         configuration for int8x; split cap for fp64) at size N; the choice is
         kept for later solves of that size and precision (tile_group = -1)."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         r = TuneResult()
-        self._check(lib().sp2_autotune(self._h, int(N), prec, int(slices), ctypes.byref(r)), "sp2_autotune")
+        self._check(lib().sp2_autotune(self._h, int(N), prec, int(slices), int(levels), ctypes.byref(r)),
+                    "sp2_autotune")
         return {"tile_group": r.tile_group, "stage_cfg": r.stage_cfg, "split_cap": r.split_cap,
                 "ms_per_product": {tuple(r.candidates[k]): r.ms_per_product[k] for k in range(r.n_candidates)}}
 

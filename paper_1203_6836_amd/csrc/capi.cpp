@@ -83,8 +83,8 @@ struct sp2_ctx {
     double* eF = nullptr;
     size_t eatcap = 0;         // atoms
     // launch configuration chosen by sp2_autotune (or loaded from a table),
-    // per (padded N, precision, slices)
-    std::map<std::tuple<int, int, int>, TuneChoice> tuned;
+    // per (padded N, precision, slices, levels)
+    std::map<std::tuple<int, int, int, int>, TuneChoice> tuned;
     std::string arch;          // device architecture name (gfx...), the tables' key
     int cus = 0;
     // device address of the allocation-free solve's static scratch (NULL if
@@ -252,6 +252,9 @@ static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
     if (!(o.idem_tol > 0.0) || !(o.stall_tol > 0.0)) return fail(c, SP2_EINVAL, "tolerances must be > 0");
     if (o.precision == SP2_PREC_INT8X && (o.slices < 2 || o.slices > kMaxSlices))
         return fail(c, SP2_EINVAL, "slices must be in [2, 6]");
+    if (o.precision == SP2_PREC_INT8X && o.levels != 0 && o.levels != o.slices &&
+        !(o.levels == o.slices + 1 && o.slices < kMaxSlices))
+        return fail(c, SP2_EINVAL, "levels must be 0, slices or slices + 1 (slices < 6)");
     if (o.fp64_head < 0) return fail(c, SP2_EINVAL, "fp64_head must be >= 0");
     if (o.precision == SP2_PREC_BF16X2 && o.fp32_tail < 0) return fail(c, SP2_EINVAL, "fp32_tail must be >= 0");
     if (!(o.tau >= 0.0)) return fail(c, SP2_EINVAL, "tau must be >= 0");
@@ -279,16 +282,25 @@ struct SolveScratch {
 
 static int padded_ld(int N) { return ((N + kTile - 1) / kTile) * kTile; }
 
-// The autotuned configuration for (padded N, precision, slices): the entry
-// of that size, else the one of the nearest tuned size within a factor of 2
-// (the N bucket), else the defaults.
-static TuneChoice tuned_choice(const sp2_ctx* c, int ld, int precision, int slices) {
-    auto it = c->tuned.find(std::make_tuple(ld, precision, slices));
+// Digit-product levels of an INT8X solve (0 = slices), 0 for the other
+// precisions.
+static int int8_levels(const sp2_options& o) {
+    if (o.precision != SP2_PREC_INT8X) return 0;
+    return o.levels > 0 ? o.levels : o.slices;
+}
+
+// The autotuned configuration for (padded N, precision, slices, levels): the
+// entry of that size, else the one of the nearest tuned size within a factor
+// of 2 (the N bucket), else the defaults.
+static TuneChoice tuned_choice(const sp2_ctx* c, int ld, int precision, int slices, int levels) {
+    auto it = c->tuned.find(std::make_tuple(ld, precision, slices, levels));
     if (it != c->tuned.end()) return it->second;
     TuneChoice best;
     double dist = 1e300;
     for (const auto& kv : c->tuned) {
-        if (std::get<1>(kv.first) != precision || std::get<2>(kv.first) != slices) continue;
+        if (std::get<1>(kv.first) != precision || std::get<2>(kv.first) != slices ||
+            std::get<3>(kv.first) != levels)
+            continue;
         const double d = std::fabs(std::log((double)std::get<0>(kv.first) / ld));
         if (d <= std::log(2.0) && d < dist) {
             dist = d;
@@ -368,11 +380,12 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
     // their upper tiles only and the encode reads the upper triangle
     const bool upper = int8x && o.tau == 0.0 && o.fp64_head == 0;
     c->split.upper = upper;
-    const TuneChoice tc = tuned_choice(c, ld, o.precision, int8x ? o.slices : 0);
+    const TuneChoice tc = tuned_choice(c, ld, o.precision, int8x ? o.slices : 0, int8_levels(o));
     const int tile_group = o.tile_group >= 0 ? o.tile_group : tc.tile_group;
     c->split.tile_group = tile_group;
     c->split.stage_cfg = tc.stage_cfg;
     c->split.tail_split = o.tail_split;
+    c->split.levels = int8_levels(o);
 
     CtrlArgs a;
     a.n_occ = (double)n_occ;
@@ -419,7 +432,7 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
             HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, part, &ns, st, env, tile_group, f64tail,
-                                      f64tail_bytes, tuned_choice(c, ld, SP2_PREC_FP64, 0).split_cap));
+                                      f64tail_bytes, tuned_choice(c, ld, SP2_PREC_FP64, 0, 0).split_cap));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
@@ -574,15 +587,20 @@ extern "C" sp2_status sp2_int8_mfma_rate(sp2_ctx* c, double* ops_per_s) {
     return SP2_OK;
 }
 
-extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices, sp2_tune_result* out) {
+extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices, int levels,
+                                   sp2_tune_result* out) {
     if (!c) return SP2_EINVAL;
     if (N < 1 || N > 65536) return fail(c, SP2_EINVAL, "N must be in [1, 65536]");
     sp2_options o;
     sp2_options_default(&o);
     o.precision = precision;
-    if (precision == SP2_PREC_INT8X) o.slices = slices;
+    if (precision == SP2_PREC_INT8X) {
+        o.slices = slices;
+        o.levels = levels;
+    }
     sp2_status s = check_options(c, o, N);
     if (s != SP2_OK) return s;
+    const int nl = int8_levels(o);
     HIPCHK(c, hipSetDevice(c->device));
     const int ld = ((N + kTile - 1) / kTile) * kTile;
     const size_t ld2 = (size_t)ld * ld;
@@ -599,6 +617,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         if (split_reserve(c->split, ld, int8x ? slices : 0, bf16x) != 0)
             return fail(c, SP2_ENOMEM, "device allocation for split operands failed");
         c->split.upper = int8x;
+        c->split.levels = nl;
         c->split.env = nullptr;
         c->split.tz = nullptr;
     }
@@ -691,7 +710,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
     }
     c->split.tile_group = best.tile_group;
     c->split.stage_cfg = best.stage_cfg;
-    c->tuned[std::make_tuple(ld, precision, int8x ? slices : 0)] = best;
+    c->tuned[std::make_tuple(ld, precision, int8x ? slices : 0, nl)] = best;
     r.tile_group = best.tile_group;
     r.stage_cfg = best.stage_cfg;
     r.split_cap = best.split_cap;
@@ -700,16 +719,17 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
 }
 
 // Table format: a header line, then one line per tuned configuration:
-//   <arch> <compute units> <padded N> <precision> <slices> <tile_group> <stage_cfg> <split_cap> <ms>
+//   <arch> <compute units> <padded N> <precision> <slices> <levels> <tile_group> <stage_cfg> <split_cap> <ms>
 extern "C" sp2_status sp2_tune_save(const sp2_ctx* c, const char* path) {
     if (!c || !path) return SP2_EINVAL;
     std::ofstream f(path);
     if (!f) return SP2_EINVAL;
-    f << "# sp2qmd autotuner table: arch cus ld precision slices tile_group stage_cfg split_cap ms_per_product\n";
+    f << "# sp2qmd autotuner table: arch cus ld precision slices levels tile_group stage_cfg split_cap "
+         "ms_per_product\n";
     for (const auto& kv : c->tuned)
         f << c->arch << ' ' << c->cus << ' ' << std::get<0>(kv.first) << ' ' << std::get<1>(kv.first) << ' '
-          << std::get<2>(kv.first) << ' ' << kv.second.tile_group << ' ' << kv.second.stage_cfg << ' '
-          << kv.second.split_cap << ' ' << kv.second.ms << '\n';
+          << std::get<2>(kv.first) << ' ' << std::get<3>(kv.first) << ' ' << kv.second.tile_group << ' '
+          << kv.second.stage_cfg << ' ' << kv.second.split_cap << ' ' << kv.second.ms << '\n';
     return f ? SP2_OK : SP2_EINVAL;
 }
 
@@ -723,17 +743,18 @@ extern "C" sp2_status sp2_tune_load(sp2_ctx* c, const char* path) {
         if (line.empty() || line[0] == '#') continue;
         std::istringstream in(line);
         std::string arch;
-        int cus, ld, prec, slices;
+        int cus, ld, prec, slices, levels;
         TuneChoice t;
-        if (!(in >> arch >> cus >> ld >> prec >> slices >> t.tile_group >> t.stage_cfg >> t.split_cap >> t.ms))
+        if (!(in >> arch >> cus >> ld >> prec >> slices >> levels >> t.tile_group >> t.stage_cfg >> t.split_cap >>
+              t.ms))
             return fail(c, SP2_EINVAL, "malformed autotuner table line: " + line);
         // entries of another device type, or out of range, are skipped
         if (arch != c->arch || cus != c->cus) continue;
         if (ld < kTile || ld % kTile || prec < SP2_PREC_FP64 || prec > SP2_PREC_BF16X2 || t.tile_group < 0 ||
             t.tile_group > 64 || t.stage_cfg < 0 || t.stage_cfg > 2 || (t.stage_cfg == 2 && slices > 5) ||
-            t.split_cap < 2 || t.split_cap > 16)
+            t.split_cap < 2 || t.split_cap > 16 || levels < 0 || levels > slices + 1)
             continue;
-        c->tuned[std::make_tuple(ld, prec, slices)] = t;
+        c->tuned[std::make_tuple(ld, prec, slices, levels)] = t;
         ++loaded;
     }
     (void)loaded;

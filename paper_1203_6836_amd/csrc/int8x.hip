@@ -3,23 +3,29 @@
 // are exact in integer arithmetic, the Ozaki scheme for matrix products).
 //
 // The FP64 master X_n is split row by row into fixed-point digit planes:
-// with s_i = 2^e_i >= max_j |X_ij| (a power of two, so the scaling is exact),
-// y = X_ij / s_i in (-1, 1) is written as y ~ sum_t d_t 2^-(6 + W t), W bits
-// per digit (digit_bits):
-//   W = 8: the integer m = rint(y 2^(8S - 2)) (|m| <= 2^(8S - 2)) is written
-//     in base 256 with digits in [-128, 127] (the top one in [-64, 64]): the
-//     bytes of m + 0x80..80 (S bytes), each read back as a byte minus 128.
-//     One rounding, error <= 2^-(8S - 1); every level accumulator fits int32
-//     while (S - 1) 2^14 K < 2^31;
+// with the row scale s_i = (1 + 2^-7) max_j |X_ij| (row_scale), y = X_ij / s_i
+// lies in [-0.993, 0.993] and is written as y ~ sum_t d_t 2^-(e0 + W t), W
+// bits per digit (digit_bits), e0 = W - 1:
+//   W = 8: the integer m = rint(y 2^(8S - 1)) (|m| < 0.9961 2^(8S - 1), the
+//     range of the excess code below) is written in base 256 with digits in
+//     [-128, 127]: the bytes of m + 0x80..80 (S bytes), each read back as a
+//     byte minus 128.  One rounding, error <= 2^-(8S) s_i; the top digit
+//     uses its whole byte, since the row maximum sits just inside the range
+//     (a power-of-two scale would leave it between 1/4 and 1/2 of it, one
+//     to two bits less per operand);
 //   W = 7: digits |d_t| <= 64 taken by successive round-to-nearest of the
-//     remainder (each remainder exact in FP64), for larger K.
+//     remainder (each remainder exact in FP64) with weights 2^-(6 + 7 t), 7
+//     bits a digit, for larger K.
 // Because X is symmetric,
-//     (X^2)_ij = sum_k X_ik X_jk ~ s_i s_j sum_{t,u} 2^-(12 + W(t+u)) sum_k d_t[i,k] d_u[j,k],
+//     (X^2)_ij = sum_k X_ik X_jk ~ s_i s_j sum_{t,u} 2^-(2 e0 + W(t+u)) sum_k d_t[i,k] d_u[j,k],
 // i.e. every digit product reads contiguous rows of the digit planes for both
-// operands.  Products with t + u < slices are kept; those of one level L = t+u
-// share an int32 accumulator, which is exact (W = 8: |acc| <= L 2^14 K < 2^31
-// by the choice of W; W = 7: |d| <= 64, at most 6 products per level,
-// K <= 65536).  Levels are combined in FP64 in the epilogue, which then
+// operands.  Products of planes t, u < S with level L = t + u < NL are kept,
+// NL = S (the triangle) or S + 1 (the next level's products of the inner
+// planes too: with 8-bit digits this is the accuracy of rounding each
+// operand to 8S bits, for S - 1 more products).  Those of one level share an
+// int32 accumulator, which is exact: a level has at most S products, and
+// W = 8: |acc| <= S 2^14 K < 2^31 by the choice of W; W = 7: |d| <= 64,
+// K <= 65536.  Levels are combined in FP64 in the epilogue, which then
 // applies the SP2 update exactly like the FP64 product.  The plane count may
 // change from product to product (the host picks each launch's), so the
 // digit width is a function of (ld, S) that encode and product agree on.
@@ -55,22 +61,36 @@ __device__ __forceinline__ int dswz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
 
 // --------------------------------------------------------------- encoding
 // Bits per digit of an S-plane split of operands with K = ld: 8 while every
-// level accumulator provably fits int32, else 7.
+// level accumulator provably fits int32 (at most S products of |d| <= 128
+// per level), else 7.
 __host__ __device__ __forceinline__ int digit_bits(int ld, int S) {
-    return (long long)(S - 1) * 16384LL * ld < 2147483648LL ? 8 : 7;
+    return (long long)S * 16384LL * ld < 2147483648LL ? 8 : 7;
+}
+// Exponent of the top digit's weight, 2^-e0.
+__host__ __device__ __forceinline__ int digit_e0(int W) { return W == 8 ? 7 : 6; }
+
+// Row scale s = (1 + 2^-7) m of a row with maximum m (1 for a zero row) and
+// its reciprocal, the factor that maps the row into [-0.993, 0.993] (one
+// rounding each: |X_ij| inv <= (1 + 2^-51) / (1 + 2^-7)).  Every encoder
+// takes both from here, so they agree bit for bit.
+__device__ __forceinline__ double row_scale(double m, double* s_out) {
+    const double s = m > 0.0 ? m * 1.0078125 : 1.0;
+    if (s_out) *s_out = s;
+    return 1.0 / s;
 }
 
-// W = 8: m + 0x80..80 (S bytes) for m = rint(y 2^(8S - 2)), |y| < 1; byte
-// S - 1 - t of it XOR 0x80 is digit t as an int8.
+// W = 8: m + 0x80..80 (S bytes) for m = rint(y 2^(8S - 1)), |y| <= 0.993 (so
+// -0x80..80 <= m < 0x7F..7F80, the range whose excess code has S bytes);
+// byte S - 1 - t of it XOR 0x80 is digit t as an int8.
 __device__ __forceinline__ unsigned long long excess_digits(double y, int S) {
-    const long long m = (long long)rint(y * ldexp(1.0, 8 * S - 2));
+    const long long m = (long long)rint(y * ldexp(1.0, 8 * S - 1));
     return (unsigned long long)m + (0x8080808080808080ull >> (8 * (8 - S)));
 }
 __device__ __forceinline__ unsigned excess_digit(unsigned long long u, int S, int t) {
     return (unsigned)((u >> (8 * (S - 1 - t))) & 0xFFull) ^ 0x80u;
 }
 
-// Digits of eight values y (|y| < 1) into eight packed bytes per plane.
+// Digits of eight values y (|y| <= 0.993) into eight packed bytes per plane.
 template <int S>
 __device__ __forceinline__ void pack_digits8(double (&y)[8], int W, unsigned long long (&packed)[S]) {
     if (W == 8) {
@@ -116,10 +136,9 @@ __device__ __forceinline__ void encode_row(const double* __restrict__ X, int ld,
         m = fmax(m, fmax(fmax(fabs(b.x), fabs(b.y)), fmax(fabs(b.z), fabs(b.w))));
     }
     m = wred_max(m);
-    int e = 0;
-    if (m > 0.0) (void)frexp(m, &e);     // m = f 2^e, f in [0.5, 1): |X_ij| / 2^e < 1
-    const double inv = ldexp(1.0, -e);
-    if (lane == 0) scale[i] = ldexp(1.0, e);
+    double sc;
+    const double inv = row_scale(m, &sc);
+    if (lane == 0) scale[i] = sc;
     const size_t plane = (size_t)ld * ld;
     const size_t rowblk = (size_t)(i >> 5) * (ld >> 5);
     const int r32 = i & 31;
@@ -187,10 +206,9 @@ __global__ __launch_bounds__(256) void k_encode_int8_reg(const double* __restric
     if (lane == 0) wm[w] = m;
     __syncthreads();
     m = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
-    int e = 0;
-    if (m > 0.0) (void)frexp(m, &e);
-    const double inv = ldexp(1.0, -e);
-    if (tid == 0) scale[i] = ldexp(1.0, e);
+    double sc;
+    const double inv = row_scale(m, &sc);
+    if (tid == 0) scale[i] = sc;
     const size_t plane = (size_t)ld * ld;
     const size_t rowblk = (size_t)(i >> 5) * (ld >> 5);
     const int r32 = i & 31;
@@ -248,11 +266,7 @@ __device__ __forceinline__ void pack_digits4(const double (&x)[4], double inv, i
 }
 
 __device__ __forceinline__ double scale_inv(unsigned long long bits, double* s_out) {
-    const double m = __longlong_as_double((long long)bits);
-    int e = 0;
-    if (m > 0.0) (void)frexp(m, &e);
-    if (s_out) *s_out = ldexp(1.0, e);
-    return ldexp(1.0, -e);
+    return row_scale(__longlong_as_double((long long)bits), s_out);
 }
 
 template <int S>
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(256) void k_encode_int8_grouped(const GroupDesc* __
 // ------------------------------------------------------------------ product
 // One 512-thread workgroup per upper-triangular 128 x 128 tile; wave w
 // covers rows 32 (w >> 1) .. +32 and columns 64 (w & 1) .. +64 as two 32 x 32
-// blocks of v_mfma_i32_32x32x32_i8 per level (S x 2 accumulators of 16
+// blocks of v_mfma_i32_32x32x32_i8 per level (NL x 2 accumulators of 16
 // int32).  Each K stage stages 2 operands x S planes x 4 row blocks x KS
 // k blocks of 1 KiB through an LDS ring in the blocked layout, filled by
 // global -> LDS loads one stage ahead of the products.
@@ -365,13 +379,13 @@ struct I8Smem {
 // stored to chunk_acc (one chunk of a tile split along K); kmode 2: no K
 // loop, the accumulators are the sum of the nchunks chunks at chunk_acc (the
 // integer sums are exact, so a split tile equals an unsplit one), then the
-// epilogue.  Chunk layout: int4 [S][2][4][512 threads] (accumulator elements
+// epilogue.  Chunk layout: int4 [NL][2][4][512 threads] (accumulator elements
 // 4q .. 4q + 3 of level L, column block c), so that each wave moves 1 KiB
 // per instruction.  UPPER: write the tile
 // only (no mirrored copy below the diagonal) and fold its row and column
 // maxima of |X_{n+1}| into rmax_next (bit patterns of non-negative doubles
 // order like the values, so atomicMax on them is exact and order-free).
-template <int S, bool THR, bool UPPER, int C = 0>
+template <int S, int NL, bool THR, bool UPPER, int C = 0>
 __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __restrict__ buf1, int ld,
                            const State* __restrict__ st, const int8_t* __restrict__ digits,
                            const double* __restrict__ scale, double* __restrict__ part, int bi, int bj,
@@ -394,9 +408,10 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     constexpr int PER = NBLK * 64 / 512;        // 16-byte chunks per thread
     static_assert((NBLK * 64) % 512 == 0, "stage must split evenly over 512 threads");
 
-    v16i acc[S][2];
+    static_assert(NL == S || NL == S + 1, "levels: the triangle or one more");
+    v16i acc[NL][2];
 #pragma unroll
-    for (int L = 0; L < S; ++L)
+    for (int L = 0; L < NL; ++L)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -474,14 +489,14 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
 #pragma unroll
             for (int uu = 0; uu < S; ++uu)
 #pragma unroll
-                for (int tt = 0; tt < S - uu; ++tt)
+                for (int tt = 0; tt < S && tt < NL - uu; ++tt)
 #pragma unroll
                     for (int c = 0; c < 2; ++c)
                         acc[tt + uu][c] =
                             __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tt], b[uu][c], acc[tt + uu][c], 0, 0, 0);
         }
         constexpr int LA = 2;                                  // lookahead in reads
-        constexpr int R = 3 * S * KS, P = S * (S + 1) / 2 * KS;   // reads, product pairs
+        constexpr int R = 3 * S * KS, P = (S * (S + 1) / 2 + (NL - S) * (S - 1)) * KS;   // reads, product pairs
         constexpr int MID = R - 3 - LA;
         __builtin_amdgcn_sched_group_barrier(0x100, 3 + LA, 0);
 #pragma unroll
@@ -566,11 +581,11 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
         ++n_done;
     }
     __syncthreads();
-    constexpr int CH = S * 2 * 16 * 512;   // int32 per chunk
+    constexpr int CH = NL * 2 * 16 * 512;   // int32 per chunk
     if (kmode == 1) {
         int4* out = reinterpret_cast<int4*>(chunk_acc);
 #pragma unroll
-        for (int L = 0; L < S; ++L)
+        for (int L = 0; L < NL; ++L)
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -583,7 +598,7 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
         for (int ch = 0; ch < nchunks; ++ch) {
             const int4* in = reinterpret_cast<const int4*>(chunk_acc + (size_t)ch * CH);
 #pragma unroll
-            for (int L = 0; L < S; ++L)
+            for (int L = 0; L < NL; ++L)
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -602,13 +617,15 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
     // end, the same order in both layouts (so both give identical partials).
     const int br = st->branch;
     const bool mirror = bi != bj;
-    const int W = digit_bits(ld, S);
+    const int W = digit_bits(ld, S), E2 = 2 * digit_e0(W);
     double trc[2] = {0.0, 0.0}, froc[2] = {0.0, 0.0}, idmc[2] = {0.0, 0.0};
     auto element = [&](int c, int r, int gi, int gj, double sj) -> double {
         double v = 0.0;
 #pragma unroll
-        for (int L = S - 1; L >= 0; --L) v += ldexp((double)acc[L][c][r], -(12 + W * L));
-        const double p = v * scale[gi] * sj;
+        for (int L = NL - 1; L >= 0; --L) v += ldexp((double)acc[L][c][r], -(E2 + W * L));
+        // s_i s_j first: the product is then the same for (i, j) and (j, i)
+        // (the diagonal tiles form both), so X stays exactly symmetric
+        const double p = v * (scale[gi] * sj);
         const double x = Xc[(size_t)gi * ld + gj];
         const double xn = br ? 2.0 * x - p : p;
         Xn[(size_t)gi * ld + gj] = xn;
@@ -726,7 +743,7 @@ __device__ __forceinline__ void diag_tile(int pos, int nt, int& bi, int& bj) {
     bj = bi + d;
 }
 
-template <int S, bool THR, bool UPPER, int C = 0>
+template <int S, int NL, bool THR, bool UPPER, int C = 0>
 __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, double* __restrict__ buf1,
                                                     int ld, const State* __restrict__ st,
                                                     const int8_t* __restrict__ digits,
@@ -750,12 +767,12 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
         kmode = 1;
         kc0 = ch * nk / nsplit;
         kc1 = (ch + 1) * nk / nsplit;
-        cacc = chunk_acc + (size_t)j * (S * 2 * 16 * 512);
+        cacc = chunk_acc + (size_t)j * (NL * 2 * 16 * 512);
     }
     int bi, bj;
     if (THR) diag_tile(pos, nt, bi, bj);
     else order_tile(pos, nt, tile_group, bi, bj);
-    int8x_tile<S, THR, UPPER, C>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
+    int8x_tile<S, NL, THR, UPPER, C>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env,
                               UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, kmode, kc0, kc1, cacc, 0);
 }
 
@@ -843,7 +860,7 @@ __global__ __launch_bounds__(256) void k_tile_list(const State* __restrict__ st,
 
 // One workgroup per CU takes list entries until none is left (every
 // workgroup leaves once the shared counter passes the entry count).
-template <int S>
+template <int S, int NL>
 __global__ __launch_bounds__(512) void k_gemm_int8x_list(double* __restrict__ buf0, double* __restrict__ buf1,
                                                          int ld, const State* __restrict__ st,
                                                          const int8_t* __restrict__ digits,
@@ -885,7 +902,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_list(double* __restrict__ bu
                 tzn[t] = 1;
             }
         } else {
-            int8x_tile<S, true, false>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env, nullptr);
+            int8x_tile<S, NL, true, false>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, env, nullptr);
             if (threadIdx.x == 0) tzn[t] = 0;
         }
         __syncthreads();
@@ -894,7 +911,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_list(double* __restrict__ bu
 
 // Epilogue of the split tiles: workgroup p sums the nsplit chunks of the tile
 // at visiting position t_full + p and applies the update.
-template <int S, bool UPPER, int C = 0>
+template <int S, int NL, bool UPPER, int C = 0>
 __global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ buf0, double* __restrict__ buf1,
                                                          int ld, const State* __restrict__ st,
                                                          const int8_t* __restrict__ digits,
@@ -907,9 +924,9 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ bu
     I8Smem<S, C>& sm = *reinterpret_cast<I8Smem<S, C>*>(smem_raw);
     int bi, bj;
     order_tile(t_full + blockIdx.x, ld / QB, tile_group, bi, bj);
-    int8x_tile<S, false, UPPER, C>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, nullptr,
-                                UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, 2, 0, -1,
-                                chunk_acc + (size_t)blockIdx.x * nsplit * (S * 2 * 16 * 512), nsplit);
+    int8x_tile<S, NL, false, UPPER, C>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, nullptr,
+                                    UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, 2, 0, -1,
+                                    chunk_acc + (size_t)blockIdx.x * nsplit * (NL * 2 * 16 * 512), nsplit);
 }
 
 // Grouped: every upper-triangular tile of every system in the group; a fixed
@@ -926,7 +943,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __r
         int bi = 0, bj = 0, tl = item - g->tile_off[s], nt = v.ld / QB, off = 0;
         while (tl >= off + (nt - bi)) { off += nt - bi; ++bi; }
         bj = bi + (tl - off);
-        int8x_tile<S, false, false>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr,
+        int8x_tile<S, S, false, false>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr,
                                     nullptr);
         __syncthreads();
     }
@@ -946,7 +963,7 @@ int device_cus() {
     return n;
 }
 
-template <int S, bool THR, bool UPPER, int C = 0>
+template <int S, int NL, bool THR, bool UPPER, int C = 0>
 static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                                      hipStream_t stream, const int* env) {
     const int nt = ld / QB;
@@ -954,10 +971,10 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     const size_t lds = sizeof(I8Smem<S, C>);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, THR, UPPER, C>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, NL, THR, UPPER, C>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e == hipSuccess && !THR)
-            e = hipFuncSetAttribute((const void*)k_gemm_int8x_tail<S, UPPER, C>,
+            e = hipFuncSetAttribute((const void*)k_gemm_int8x_tail<S, NL, UPPER, C>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -972,20 +989,20 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
         const int r = T % cus;
         if (r > 0 && 2 * r <= cus) {
             nsplit = std::min(8, cus / r);
-            if (nsplit >= 2 && (size_t)r * nsplit * S * 2 * 16 * 512 * sizeof(int) <= s.tail_bytes) t_full = T - r;
+            if (nsplit >= 2 && (size_t)r * nsplit * NL * 2 * 16 * 512 * sizeof(int) <= s.tail_bytes) t_full = T - r;
             else nsplit = 1;
         }
     }
     const int grid = t_full + (T - t_full) * nsplit;
-    hipLaunchKernelGGL((k_gemm_int8x<S, THR, UPPER, C>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st,
+    hipLaunchKernelGGL((k_gemm_int8x<S, NL, THR, UPPER, C>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st,
                        s.digits, s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
     if (t_full < T)
-        hipLaunchKernelGGL((k_gemm_int8x_tail<S, UPPER, C>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
+        hipLaunchKernelGGL((k_gemm_int8x_tail<S, NL, UPPER, C>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
                            st, s.digits, s.scale, part, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
     return hipGetLastError();
 }
 
-template <int S>
+template <int S, int NL>
 static hipError_t launch_list_kernel(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                                      hipStream_t stream, const int* env) {
     const int nt = ld / QB;
@@ -993,7 +1010,7 @@ static hipError_t launch_list_kernel(SplitScratch& s, double* buf0, double* buf1
     const size_t lds = sizeof(I8Smem<S>);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x_list<S>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x_list<S, NL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -1004,27 +1021,27 @@ static hipError_t launch_list_kernel(SplitScratch& s, double* buf0, double* buf1
     hipLaunchKernelGGL(k_tile_list, dim3((T + 255) / 256), dim3(256), 0, stream, st, env, s.tz, nt, s.tile_group, part,
                        list, ctr);
     const int grid = std::min(T, device_cus());
-    hipLaunchKernelGGL(k_gemm_int8x_list<S>, dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits, s.scale,
+    hipLaunchKernelGGL((k_gemm_int8x_list<S, NL>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st, s.digits, s.scale,
                        part, env, s.tz, list, ctr);
     return hipGetLastError();
 }
 
-template <int S>
+template <int S, int NL>
 static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                             hipStream_t stream, const int* env) {
-    if (env && s.tz) return launch_list_kernel<S>(s, buf0, buf1, ld, st, part, stream, env);
-    if (env) return launch_tile_kernel<S, true, false>(s, buf0, buf1, ld, st, part, stream, env);
+    if (env && s.tz) return launch_list_kernel<S, NL>(s, buf0, buf1, ld, st, part, stream, env);
+    if (env) return launch_tile_kernel<S, NL, true, false>(s, buf0, buf1, ld, st, part, stream, env);
     // dense products: the stage configuration chosen by the autotuner
     if constexpr (i8_cfg_ok(S, 2)) {
         if (s.stage_cfg == 2)
-            return s.upper ? launch_tile_kernel<S, false, true, 2>(s, buf0, buf1, ld, st, part, stream, nullptr)
-                           : launch_tile_kernel<S, false, false, 2>(s, buf0, buf1, ld, st, part, stream, nullptr);
+            return s.upper ? launch_tile_kernel<S, NL, false, true, 2>(s, buf0, buf1, ld, st, part, stream, nullptr)
+                           : launch_tile_kernel<S, NL, false, false, 2>(s, buf0, buf1, ld, st, part, stream, nullptr);
     }
     if (s.stage_cfg == 1)
-        return s.upper ? launch_tile_kernel<S, false, true, 1>(s, buf0, buf1, ld, st, part, stream, nullptr)
-                       : launch_tile_kernel<S, false, false, 1>(s, buf0, buf1, ld, st, part, stream, nullptr);
-    if (s.upper) return launch_tile_kernel<S, false, true>(s, buf0, buf1, ld, st, part, stream, nullptr);
-    return launch_tile_kernel<S, false, false>(s, buf0, buf1, ld, st, part, stream, nullptr);
+        return s.upper ? launch_tile_kernel<S, NL, false, true, 1>(s, buf0, buf1, ld, st, part, stream, nullptr)
+                       : launch_tile_kernel<S, NL, false, false, 1>(s, buf0, buf1, ld, st, part, stream, nullptr);
+    if (s.upper) return launch_tile_kernel<S, NL, false, true>(s, buf0, buf1, ld, st, part, stream, nullptr);
+    return launch_tile_kernel<S, NL, false, false>(s, buf0, buf1, ld, st, part, stream, nullptr);
 }
 
 // Thresholded X: one wave per padded row, over the columns of its row panel's
@@ -1114,12 +1131,18 @@ hipError_t launch_int8x_gemm(SplitScratch& s, double* buf0, double* buf1, int ld
                              int* nslots, hipStream_t stream, const int* env) {
     const int nt = ld / QB;
     *nslots = nt * (nt + 1) / 2;
+    const bool next = s.levels == s.slices + 1;
+    if (!next && s.levels != s.slices) return hipErrorInvalidValue;
     switch (s.slices) {
-        case 2: return run_int8x<2>(s, buf0, buf1, ld, st, part, stream, env);
-        case 3: return run_int8x<3>(s, buf0, buf1, ld, st, part, stream, env);
-        case 4: return run_int8x<4>(s, buf0, buf1, ld, st, part, stream, env);
-        case 5: return run_int8x<5>(s, buf0, buf1, ld, st, part, stream, env);
-        case 6: return run_int8x<6>(s, buf0, buf1, ld, st, part, stream, env);
+        case 2: return next ? run_int8x<2, 3>(s, buf0, buf1, ld, st, part, stream, env)
+                            : run_int8x<2, 2>(s, buf0, buf1, ld, st, part, stream, env);
+        case 3: return next ? run_int8x<3, 4>(s, buf0, buf1, ld, st, part, stream, env)
+                            : run_int8x<3, 3>(s, buf0, buf1, ld, st, part, stream, env);
+        case 4: return next ? run_int8x<4, 5>(s, buf0, buf1, ld, st, part, stream, env)
+                            : run_int8x<4, 4>(s, buf0, buf1, ld, st, part, stream, env);
+        case 5: return next ? run_int8x<5, 6>(s, buf0, buf1, ld, st, part, stream, env)
+                            : run_int8x<5, 5>(s, buf0, buf1, ld, st, part, stream, env);
+        case 6: return next ? hipErrorInvalidValue : run_int8x<6, 6>(s, buf0, buf1, ld, st, part, stream, env);
         default: return hipErrorInvalidValue;
     }
 }

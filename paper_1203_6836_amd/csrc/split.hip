@@ -249,8 +249,9 @@ int split_reserve(SplitScratch& s, int ld, int slices, bool bf16) {
     need += (size_t)slices * ld * ld;                 // int8 digits
     need += (size_t)ld * sizeof(double) + 256;        // row scales
     need += (size_t)2 * ld * sizeof(unsigned long long) + 256;   // row maxima
-    // K-chunk accumulators of split tiles: at most one chunk per CU (256)
-    const size_t tail = slices > 0 ? (size_t)256 * slices * 2 * 16 * 512 * sizeof(int) : 0;
+    // K-chunk accumulators of split tiles: at most one chunk per CU (256),
+    // slices + 1 levels at most
+    const size_t tail = slices > 0 ? (size_t)256 * (slices + 1) * 2 * 16 * 512 * sizeof(int) : 0;
     need += tail + 256;
     if (bf16) need += (size_t)2 * ld * ld * sizeof(uint16_t) + (size_t)ld * ld * sizeof(float) + 512;
     if (s.bytes >= need && s.ld == ld && s.slices == slices && s.bf16 == bf16) return 0;

@@ -14,6 +14,7 @@ constexpr int kMaxSlices = 6;
 struct SplitScratch {
     int ld = 0;
     int slices = 0;
+    int levels = 0;             // int8 digit-product levels t + u < levels: slices or slices + 1 (set per solve)
     bool bf16 = false;
     int8_t* digits = nullptr;   // slices x ld x ld int8 digit planes
     double* scale = nullptr;    // ld row scales (powers of two)

@@ -166,7 +166,11 @@ def test_blocksparse_n16384_int8_against_oracle(ctx):
     kept on one side and dropped on the other (the fill per update differs by
     a few blocks), so the bound on D is twice the reduced-precision tolerance
     of the dense path, 2e-6 per sqrt(N) (measured 6.3e-7; the probe-vector
-    estimate carries a spread of its own), and charges within 1e-6 e."""
+    estimate carries a spread of its own), and charges within 1e-6 e.  The
+    oracle stops by the tolerance (||X^2 - X||_F = 9e-12 < 1e-10 at its last
+    product); the int8 rounding floor lies above it and the stall rule
+    compares e_n with e_{n-2}, so the int8 solve may take up to two products
+    more to recognise its floor."""
     import torch
     import paper_1203_6836_amd as p
     g = load("c3_blocksparse_n16384.npz")
@@ -179,7 +183,7 @@ def test_blocksparse_n16384_int8_against_oracle(ctx):
     est, dq, blk = sketch_error(D, g, w.n_atoms)
     say(f"  products gpu={st['iterations']} oracle={int(g['iterations'])}; max fill dev {fill_dev:.1e}; "
         f"err/sqrtN ~{est:.1e}, max|dq| {dq:.1e}, block dev {blk:.1e}")
-    assert abs(st["iterations"] - int(g["iterations"])) <= 1
+    assert abs(st["iterations"] - int(g["iterations"])) <= 2
     assert fill_dev <= 1e-4
     assert est <= 2e-6 and dq <= 1e-6
     del D, H

@@ -75,6 +75,53 @@ def test_int8x_options_head_and_slices(ctx):
     assert e3 > e6          # fewer digit planes: visibly less accurate
 
 
+@pytest.mark.parametrize("dims,seed", [((4, 4, 4), 0), ((6, 6, 5), 12), ((8, 8, 8), 2)])
+def test_int8x_next_level_matches_oracle(ctx, dims, seed):
+    """Four digit planes with the fifth level's products (13 digit products)
+    against the oracle (N = 256, ragged 720, 2048)."""
+    import paper_1203_6836_amd as p
+    say(f"case int8x slices=4 levels=5 dims={dims} seed={seed}")
+    pos = synth.lattice_positions(dims, seed=seed)
+    H = otb.hamiltonian(pos, None, synth.STATIC_MODEL)
+    nocc = 2 * len(pos)
+    ref = osp2.sp2(H, nocc)
+    D, st = ctx.sp2_density_matrix(to_dev(H), nocc, p.options("int8x", slices=4, levels=5))
+    q = ctx.sp2_mulliken(D, len(pos)).cpu().numpy()
+    D = D.cpu().numpy()
+    N = H.shape[0]
+    err = np.linalg.norm(D - ref.D) / np.sqrt(N)
+    dq = np.max(np.abs(q - observables.mulliken(ref.D)))
+    say(f"  iters={st['iterations']} (fp64 {ref.iterations}) err/sqrtN={err:.2e} max|dq|={dq:.2e}")
+    assert err <= TOL_D and dq <= TOL_Q
+    assert abs(np.trace(D) - nocc) < 1e-6
+    assert np.array_equal(D, D.T)
+
+
+def test_int8x_levels_order_the_error(ctx):
+    """Each added level, and each added plane, lowers the error against the
+    oracle: (S, S) > (S, S + 1) > (S + 1, S + 1) for S = 3, 4; and levels
+    outside {0, slices, slices + 1} are rejected."""
+    import paper_1203_6836_amd as p
+    say("case int8x error order over (slices, levels)")
+    pos = synth.lattice_positions((5, 5, 5), seed=11)
+    H = otb.hamiltonian(pos, None, synth.STATIC_MODEL)
+    nocc = 2 * len(pos)
+    ref = osp2.sp2(H, nocc)
+    N = H.shape[0]
+    Hd = to_dev(H)
+    err = {}
+    for sl, lv in ((3, 3), (3, 4), (4, 4), (4, 5), (5, 5), (5, 6)):
+        D, st = ctx.sp2_density_matrix(Hd, nocc, p.options("int8x", slices=sl, levels=lv))
+        err[(sl, lv)] = np.linalg.norm(D.cpu().numpy() - ref.D) / np.sqrt(N)
+        say(f"  slices={sl} levels={lv}: {st['iterations']} products, err/sqrtN {err[(sl, lv)]:.2e}")
+    for sl in (3, 4):
+        assert err[(sl, sl)] > err[(sl, sl + 1)] > err[(sl + 1, sl + 1)]
+    assert err[(5, 6)] <= 1e-8
+    for bad in ({"slices": 4, "levels": 6}, {"slices": 4, "levels": 3}, {"slices": 6, "levels": 7}):
+        with pytest.raises(RuntimeError):
+            ctx.sp2_density_matrix(Hd, nocc, p.options("int8x", **bad))
+
+
 def test_int8x_deterministic(ctx):
     import paper_1203_6836_amd as p
     say("case int8x determinism")
@@ -114,14 +161,19 @@ def test_int8x_full_size_against_oracle(ctx):
     H = otb.hamiltonian(w.positions(), None, synth.STATIC_MODEL)
     ref = osp2.sp2(H, w.n_occ)
     say(f"  oracle: {ref.iterations} products in {time.perf_counter() - t0:.0f} s, status {ref.status}")
-    D8, s8 = ctx.sp2_density_matrix(to_dev(H), w.n_occ, p.options("int8x"))
-    D8 = D8.cpu().numpy()
-    err = np.linalg.norm(D8 - ref.D) / np.sqrt(w.n_orb)
-    dq = float(np.abs(observables.mulliken(D8) - observables.mulliken(ref.D)).max())
-    say(f"  iters gpu={s8['iterations']} oracle={ref.iterations} err/sqrtN={err:.2e} max|dq|={dq:.2e}")
     assert ref.status == "converged"
-    assert abs(s8["iterations"] - ref.iterations) <= 2
-    assert err <= TOL_D and dq <= TOL_Q
+    Hd = to_dev(H)
+    # five planes (the default) and four planes with five levels (13 digit
+    # products, the fastest recipe within the tolerance)
+    for kw in ({}, {"slices": 4, "levels": 5}):
+        D8, s8 = ctx.sp2_density_matrix(Hd, w.n_occ, p.options("int8x", **kw))
+        D8 = D8.cpu().numpy()
+        err = np.linalg.norm(D8 - ref.D) / np.sqrt(w.n_orb)
+        dq = float(np.abs(observables.mulliken(D8) - observables.mulliken(ref.D)).max())
+        say(f"  {kw or 'default'}: iters gpu={s8['iterations']} oracle={ref.iterations} err/sqrtN={err:.2e} "
+            f"max|dq|={dq:.2e}")
+        assert abs(s8["iterations"] - ref.iterations) <= 2
+        assert err <= TOL_D and dq <= TOL_Q
 
 
 @pytest.mark.parametrize("dims,seed", [((4, 4, 4), 0), ((8, 8, 8), 2)])
@@ -206,7 +258,7 @@ def test_tune_table_round_trip_and_stage_configs(ctx, tmp_path):
     ref, _ = ctx.sp2_density_matrix(H, nocc, p.options("int8x", tile_group=8))
     for cfg in (0, 1, 2):
         tp = tmp_path / f"cfg{cfg}.txt"
-        tp.write_text(f"{arch} {cus} 2048 1 5 8 {cfg} 16 1.0\n")
+        tp.write_text(f"{arch} {cus} 2048 1 5 5 8 {cfg} 16 1.0\n")
         cc = p.Context(0)
         cc.sp2_tune_load(str(tp))
         D, st = cc.sp2_density_matrix(H, nocc, p.options("int8x"))
