@@ -7,7 +7,8 @@
  * ---------------------------------------
  * - Matrices are dense, N x N, row-major, FP64, leading dimension N.
  * - Every array argument is a DEVICE pointer (hipMalloc'd or a torch CUDA
- *   tensor) on the context's device, unless the name ends in _host.  The
+ *   tensor) on the context's device, unless the name ends in _host or the
+ *   call takes an sp2_memkind that says where its matrices live.  The
  *   caller owns all arrays; the library never frees or retains them.  Inputs
  *   are only read; outputs are written only when SP2_OK is returned (stats
  *   structs are always filled).
@@ -17,7 +18,8 @@
  * - Orbitals are atom-major: orbital index = 4 * atom + {s, px, py, pz}.
  * - No exception crosses this ABI.  On error a status < 0 is returned and a
  *   message is kept in the context (sp2_last_error).
- * - A context is used by one host thread at a time.
+ * - A context serves one call at a time: a call made from another host
+ *   thread while one is in progress returns SP2_EBUSY and does nothing.
  */
 #ifndef SP2QMD_H
 #define SP2QMD_H
@@ -38,6 +40,9 @@ typedef enum {
     SP2_EGAP = -5,      /* no resolvable gap at the Fermi level: the set of
                            n_occ occupied states is not unique               */
     SP2_EBUDGET = -6,   /* serving: request larger than the memory budget    */
+    SP2_EBUSY = -7,     /* the context is inside a call from another thread
+                           (a context serves one call at a time; the error
+                           string is left as it is)                          */
     SP2_ETIMEOUT = -8,  /* serving: wait timed out                           */
     SP2_EDIVERGE = -9   /* XL-BOMD: auxiliary charges ran away from q        */
 } sp2_status;
@@ -168,6 +173,22 @@ const char *sp2_last_error(const sp2_ctx *ctx);
 sp2_status sp2_density_matrix(sp2_ctx *ctx, int N, const double *H, int n_occ,
                               const sp2_options *opt, double *D_out,
                               sp2_stats *stats);
+
+/* Where the matrices of sp2_density_matrix_mem and tb_hamiltonian_mem live. */
+typedef enum {
+    SP2_MEM_HOST = 0,    /* host memory (pageable or pinned)                     */
+    SP2_MEM_DEVICE = 1   /* device memory of the context's device                */
+} sp2_memkind;
+
+/* sp2_density_matrix with H and D_out in memory of the given kind.  Host
+ * arrays are copied through a device staging buffer owned by the context
+ * (2 N^2 doubles, grown on demand): H in before the solve, D out after a
+ * successful one; the call then synchronises the context's stream, so D_out
+ * is ready when it returns.  Same errors as sp2_density_matrix (D_out is not
+ * written on error); stats->ms times the solve without the copies.  Device
+ * memory: exactly sp2_density_matrix. */
+sp2_status sp2_density_matrix_mem(sp2_ctx *ctx, int N, const double *H, sp2_memkind kind, int n_occ,
+                                  const sp2_options *opt, double *D_out, sp2_stats *stats);
 
 /* Allocation-free variant of sp2_density_matrix, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
@@ -351,6 +372,11 @@ typedef struct {
  * or NULL (then H = h); H_out: (4 n_atoms)^2 device. */
 sp2_status tb_hamiltonian(sp2_ctx *ctx, const tb_params *p, int n_atoms,
                           const double *xyz, const double *n_aux, double *H_out);
+/* tb_hamiltonian with xyz, n_aux (may be NULL) and H_out in memory of the
+ * given kind; host arrays are staged through the context's device buffer and
+ * the call synchronises the context's stream before returning. */
+sp2_status tb_hamiltonian_mem(sp2_ctx *ctx, const tb_params *p, int n_atoms, const double *xyz,
+                              const double *n_aux, double *H_out, sp2_memkind kind);
 
 /* Overlap matrix of the non-orthogonal variant of the model (the paper's S of
  * the Non-orthogonal formulation subsection; its parameters are not given, so

@@ -22,7 +22,8 @@ SP2_OK, SP2_EINVAL, SP2_ENOMEM, SP2_EDEVICE, SP2_ENOCONV, SP2_EGAP = 0, -1, -2, 
 KAPPA_K5 = 1.82
 KAPPA_ZERO_T = 0.5 * KAPPA_K5
 KAPPA_FINITE_T = 0.75 * KAPPA_K5
-SP2_EBUDGET, SP2_ETIMEOUT, SP2_EDIVERGE = -6, -8, -9
+SP2_EBUDGET, SP2_EBUSY, SP2_ETIMEOUT, SP2_EDIVERGE = -6, -7, -8, -9
+SP2_MEM_HOST, SP2_MEM_DEVICE = 0, 1
 # bytes before the FP64 arrays (xyz, vel, F, q, n history) of an xlbomd checkpoint
 XL_CHECKPOINT_HEADER = 72
 PREC_FP64, PREC_INT8X, PREC_BF16X2 = 0, 1, 2
@@ -113,6 +114,9 @@ _SIGS = {
                                 ctypes.POINTER(Sp2Stats)]),
     "sp2_density_matrix_noalloc": (_I, [_P, _I, _P, _I, ctypes.POINTER(Sp2Options), _P,
                                         ctypes.POINTER(Sp2Stats)]),
+    "sp2_density_matrix_mem": (_I, [_P, _I, _P, _I, _I, ctypes.POINTER(Sp2Options), _P,
+                                    ctypes.POINTER(Sp2Stats)]),
+    "tb_hamiltonian_mem": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _I]),
     "sp2_mulliken": (_I, [_P, _I, _P, _D, _P]),
     "sp2_autotune": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(TuneResult)]),
     "sp2_tune_save": (_I, [_P, ctypes.c_char_p]),
@@ -173,6 +177,16 @@ class Sp2Error(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
         self.status = status
+
+
+def _host_ptr(a):
+    """Pointer to a C-contiguous float64 numpy array (host memory)."""
+    if a is None:
+        return None
+    import numpy as np
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+        raise TypeError("expected a C-contiguous float64 numpy array")
+    return ctypes.c_void_p(a.ctypes.data)
 
 
 def _ptr(t):
@@ -270,6 +284,24 @@ class Context:
                                               ctypes.byref(opts) if opts is not None else None,
                                               _ptr(D_out), ctypes.byref(stats))
         self._check(st, "sp2_density_matrix_noalloc")
+        return D_out, stats.to_dict()
+
+    def sp2_density_matrix_mem(self, H, n_occ: int, opts: Sp2Options | None = None, D_out=None):
+        """H and D in host memory (numpy float64 arrays: SP2_MEM_HOST) or on
+        the device (CUDA tensors: SP2_MEM_DEVICE)."""
+        import numpy as np
+        N = H.shape[0]
+        if tuple(H.shape) != (N, N):
+            raise ValueError("H must be square")
+        host = isinstance(H, np.ndarray)
+        if D_out is None:
+            D_out = np.empty_like(H) if host else H.new_empty(H.shape)
+        conv = _host_ptr if host else _ptr
+        stats = Sp2Stats()
+        st = lib().sp2_density_matrix_mem(self._h, N, conv(H), SP2_MEM_HOST if host else SP2_MEM_DEVICE,
+                                          int(n_occ), ctypes.byref(opts) if opts is not None else None,
+                                          conv(D_out), ctypes.byref(stats))
+        self._check(st, "sp2_density_matrix_mem")
         return D_out, stats.to_dict()
 
     def sp2_density_matrix_status(self, H, n_occ: int, opts: Sp2Options | None = None):
@@ -425,6 +457,20 @@ class Context:
         p = tb_params(model)
         self._check(lib().tb_hamiltonian(self._h, ctypes.byref(p), nat, _ptr(xyz), _ptr(n_aux),
                                          _ptr(H_out)), "tb_hamiltonian")
+        return H_out
+
+    def tb_hamiltonian_mem(self, model, xyz, n_aux=None, H_out=None):
+        """xyz, n_aux and H in host memory (numpy) or on the device (CUDA tensors)."""
+        import numpy as np
+        nat = xyz.shape[0]
+        host = isinstance(xyz, np.ndarray)
+        if H_out is None:
+            H_out = (np.empty((4 * nat, 4 * nat)) if host else
+                     xyz.new_empty((4 * nat, 4 * nat)))
+        conv = _host_ptr if host else _ptr
+        p = tb_params(model)
+        self._check(lib().tb_hamiltonian_mem(self._h, ctypes.byref(p), nat, conv(xyz), conv(n_aux), conv(H_out),
+                                             SP2_MEM_HOST if host else SP2_MEM_DEVICE), "tb_hamiltonian_mem")
         return H_out
 
     def tb_forces(self, model, xyz, D, q, n_aux, F_out=None):

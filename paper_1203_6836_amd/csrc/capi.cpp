@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <tuple>
@@ -46,6 +47,13 @@ struct sp2_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    // token of the host thread inside a call on this context (0: none); a
+    // call from another thread meanwhile returns SP2_EBUSY
+    std::atomic<unsigned long long> owner{0};
+    // device staging of host-memory matrices (sp2_density_matrix_mem,
+    // tb_hamiltonian_mem): H, D
+    double* stage = nullptr;
+    size_t stagecap = 0;
     // SP2 scratch
     double* xbuf = nullptr;   // 2 * ld * ld
     size_t xcap = 0;          // elements per buffer
@@ -107,6 +115,35 @@ static sp2_status fail(sp2_ctx* c, sp2_status s, const std::string& msg) {
             return fail((c), SP2_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
     } while (0)
 
+// One call at a time per context: the first call of a thread takes the
+// context, nested calls of the same thread pass, a call of another thread
+// meanwhile returns SP2_EBUSY (without touching the error string, which the
+// owner may be writing).
+static unsigned long long thread_token() {
+    static std::atomic<unsigned long long> next{1};
+    thread_local unsigned long long t = next.fetch_add(1);
+    return t;
+}
+struct CtxGuard {
+    sp2_ctx* c;
+    bool owner = false, ok = true;
+    explicit CtxGuard(sp2_ctx* ctx) : c(ctx) {
+        if (!c) return;
+        unsigned long long expected = 0;
+        const unsigned long long me = thread_token();
+        if (c->owner.compare_exchange_strong(expected, me)) owner = true;
+        else ok = expected == me;
+    }
+    ~CtxGuard() {
+        if (owner) c->owner.store(0);
+    }
+    CtxGuard(const CtxGuard&) = delete;
+    CtxGuard& operator=(const CtxGuard&) = delete;
+};
+#define CTX_ENTER(ctx)                   \
+    CtxGuard _ctx_guard(ctx);            \
+    if (!_ctx_guard.ok) return SP2_EBUSY
+
 static sp2_status grow(sp2_ctx* c, void** p, size_t* cap, size_t need_bytes) {
     if (*cap >= need_bytes && *p) return SP2_OK;
     if (*p) (void)hipFree(*p);
@@ -163,6 +200,7 @@ const char* sp2_strerror(int s) {
         case SP2_ENOCONV: return "SP2 did not converge within max_iter";
         case SP2_EGAP: return "no resolvable gap at the Fermi level (theta(mu0 I - H) undefined)";
         case SP2_EBUDGET: return "request exceeds the memory budget";
+        case SP2_EBUSY: return "context busy with a call from another thread";
         case SP2_ETIMEOUT: return "timed out";
         case SP2_EDIVERGE: return "XL-BOMD auxiliary charges diverged from q";
         default: return "unknown status";
@@ -211,7 +249,7 @@ void sp2_ctx_destroy(sp2_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->chk, c->V, c->eatom, c->qtmp, c->env, c->tz,
-                   c->eH, c->eD, c->ezero, c->eF, c->f64tail, c->nobuf};
+                   c->eH, c->eD, c->ezero, c->eF, c->f64tail, c->nobuf, c->stage};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     split_free(c->split);
@@ -224,12 +262,14 @@ void sp2_ctx_destroy(sp2_ctx* c) {
 }
 
 sp2_status sp2_ctx_set_stream(sp2_ctx* c, void* stream) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     c->stream = (hipStream_t)stream;
     return SP2_OK;
 }
 
 sp2_status sp2_ctx_set_profiling(sp2_ctx* c, int on) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (on && c->pev.empty()) {
         if (hipSetDevice(c->device) != hipSuccess) return SP2_EDEVICE;
@@ -507,6 +547,7 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
 
 extern "C" sp2_status sp2_density_matrix(sp2_ctx* c, int N, const double* H, int n_occ, const sp2_options* opt,
                                          double* D_out, sp2_stats* stats) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (N < 1 || N > 65536) return fail(c, SP2_EINVAL, "N must be in [1, 65536]");
@@ -521,6 +562,41 @@ extern "C" sp2_status sp2_density_matrix(sp2_ctx* c, int N, const double* H, int
     return sp2_solve(c, N, H, n_occ, o, D_out, stats);
 }
 
+// Device staging buffer of at least `elems` doubles (grown on demand).
+static sp2_status stage_buffer(sp2_ctx* c, size_t elems, double** out) {
+    size_t cap = c->stagecap;
+    sp2_status s = grow(c, (void**)&c->stage, &cap, elems * sizeof(double));
+    if (s != SP2_OK) return s;
+    c->stagecap = cap;
+    *out = c->stage;
+    return SP2_OK;
+}
+
+// sp2_density_matrix with H and D_out in host or device memory: host arrays
+// are staged through the context's device buffer (H in, D out after a
+// successful solve, then the stream is synchronised).
+extern "C" sp2_status sp2_density_matrix_mem(sp2_ctx* c, int N, const double* H, sp2_memkind kind, int n_occ,
+                                             const sp2_options* opt, double* D_out, sp2_stats* stats) {
+    CTX_ENTER(c);
+    if (!c) return SP2_EINVAL;
+    if (kind == SP2_MEM_DEVICE) return sp2_density_matrix(c, N, H, n_occ, opt, D_out, stats);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (kind != SP2_MEM_HOST) return fail(c, SP2_EINVAL, "unknown memory kind");
+    if (N < 1 || N > 65536) return fail(c, SP2_EINVAL, "N must be in [1, 65536]");
+    if (!H || !D_out) return fail(c, SP2_EINVAL, "null matrix pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n2 = (size_t)N * N;
+    double* Hd = nullptr;
+    sp2_status s = stage_buffer(c, 2 * n2, &Hd);
+    if (s != SP2_OK) return s;
+    double* Dd = Hd + n2;
+    HIPCHK(c, hipMemcpyAsync(Hd, H, n2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if ((s = sp2_density_matrix(c, N, Hd, n_occ, opt, Dd, stats)) != SP2_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(D_out, Dd, n2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SP2_OK;
+}
+
 // Allocation-free variant of sp2_density_matrix: FP64 products, no threshold,
 // N <= kStaticMaxN, every scratch array carved from the static device array
 // (X buffers, partial slots, then the K-split chunk accumulators in the rest).
@@ -528,6 +604,7 @@ extern "C" sp2_status sp2_density_matrix(sp2_ctx* c, int N, const double* H, int
 // record and events were made by sp2_ctx_create.
 extern "C" sp2_status sp2_density_matrix_noalloc(sp2_ctx* c, int N, const double* H, int n_occ,
                                                  const sp2_options* opt, double* D_out, sp2_stats* stats) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (N < 1 || N > kStaticMaxN)
@@ -565,6 +642,7 @@ extern "C" sp2_status sp2_density_matrix_noalloc(sp2_ctx* c, int N, const double
 }
 
 extern "C" sp2_status sp2_int8_mfma_rate(sp2_ctx* c, double* ops_per_s) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (!ops_per_s) return fail(c, SP2_EINVAL, "sp2_int8_mfma_rate: NULL output");
     HIPCHK(c, hipSetDevice(c->device));
@@ -589,6 +667,7 @@ extern "C" sp2_status sp2_int8_mfma_rate(sp2_ctx* c, double* ops_per_s) {
 
 extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices, int levels,
                                    sp2_tune_result* out) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (N < 1 || N > 65536) return fail(c, SP2_EINVAL, "N must be in [1, 65536]");
     sp2_options o;
@@ -734,6 +813,7 @@ extern "C" sp2_status sp2_tune_save(const sp2_ctx* c, const char* path) {
 }
 
 extern "C" sp2_status sp2_tune_load(sp2_ctx* c, const char* path) {
+    CTX_ENTER(c);
     if (!c || !path) return SP2_EINVAL;
     std::ifstream f(path);
     if (!f) return fail(c, SP2_EINVAL, std::string("cannot read autotuner table ") + path);
@@ -786,6 +866,7 @@ constexpr int kNsMaxIter = 40;
 extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double* H, const double* S, int n_occ,
                                                   const sp2_options* opt, double* D_out, sp2_stats* stats,
                                                   int* factor_iterations) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (factor_iterations) *factor_iterations = 0;
@@ -898,6 +979,7 @@ static sp2_status fermi_pass(sp2_ctx* c, int N, const double* H, double mu, doub
 extern "C" sp2_status sp2_fermi_density_matrix(sp2_ctx* c, int N, const double* H, double n_occ, double kT,
                                                 int n_steps, int max_newton, double tol, double* mu,
                                                 double* D_out, int* newton_iterations, long long* products) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (newton_iterations) *newton_iterations = 0;
     if (products) *products = 0;
@@ -1005,6 +1087,7 @@ static double fermi_entropy_term(double x) {   // s(x) per state, spin not count
 
 extern "C" sp2_status sp2_fermi_entropy(sp2_ctx* c, int N, const double* H, double mu, double kT, double* S_out,
                                          int* moments) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (moments) *moments = 0;
     if (N < 1 || N > 32768 || !H || !S_out) return fail(c, SP2_EINVAL, "bad entropy arguments");
@@ -1100,6 +1183,7 @@ extern "C" sp2_status sp2_fermi_entropy(sp2_ctx* c, int N, const double* H, doub
 
 extern "C" sp2_status sp2_mulliken_overlap(sp2_ctx* c, int n_atoms, const double* D, const double* S, double z_val,
                                            double* q_out) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (n_atoms < 1 || n_atoms > 16384 || !D || !S || !q_out)
         return fail(c, SP2_EINVAL, "bad mulliken arguments");
@@ -1109,6 +1193,7 @@ extern "C" sp2_status sp2_mulliken_overlap(sp2_ctx* c, int n_atoms, const double
 }
 
 extern "C" sp2_status sp2_mulliken(sp2_ctx* c, int n_atoms, const double* D, double z_val, double* q_out) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (n_atoms < 1 || n_atoms > 16384 || !D || !q_out) return fail(c, SP2_EINVAL, "bad mulliken arguments");
     HIPCHK(c, hipSetDevice(c->device));
@@ -1117,6 +1202,7 @@ extern "C" sp2_status sp2_mulliken(sp2_ctx* c, int n_atoms, const double* D, dou
 }
 
 extern "C" sp2_status sp2_band_energy(sp2_ctx* c, int N, const double* D, const double* H, double* e_host) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (N < 1 || N > 65536 || !D || !H || !e_host) return fail(c, SP2_EINVAL, "bad band-energy arguments");
     HIPCHK(c, hipSetDevice(c->device));
@@ -1201,6 +1287,7 @@ static sp2_status ensure_atoms(sp2_ctx* c, int nat) {
 
 extern "C" sp2_status tb_hamiltonian(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz,
                                      const double* n_aux, double* H_out) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (!params_ok(p)) return fail(c, SP2_EINVAL, "bad tb_params");
     if (n_atoms < 1 || n_atoms > 16384 || !xyz || !H_out) return fail(c, SP2_EINVAL, "bad tb_hamiltonian arguments");
@@ -1217,8 +1304,35 @@ extern "C" sp2_status tb_hamiltonian(sp2_ctx* c, const tb_params* p, int n_atoms
     return SP2_OK;
 }
 
+// tb_hamiltonian with xyz, n_aux and H_out in host or device memory (host
+// arrays staged through the context's device buffer; the stream is
+// synchronised before returning).
+extern "C" sp2_status tb_hamiltonian_mem(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz,
+                                         const double* n_aux, double* H_out, sp2_memkind kind) {
+    CTX_ENTER(c);
+    if (!c) return SP2_EINVAL;
+    if (kind == SP2_MEM_DEVICE) return tb_hamiltonian(c, p, n_atoms, xyz, n_aux, H_out);
+    if (kind != SP2_MEM_HOST) return fail(c, SP2_EINVAL, "unknown memory kind");
+    if (n_atoms < 1 || n_atoms > 16384 || !xyz || !H_out) return fail(c, SP2_EINVAL, "bad tb_hamiltonian arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n2 = (size_t)16 * n_atoms * n_atoms;   // N = 4 n_atoms
+    double* Hd = nullptr;
+    sp2_status s = stage_buffer(c, n2 + 4 * (size_t)n_atoms, &Hd);
+    if (s != SP2_OK) return s;
+    double* xd = Hd + n2;
+    double* nd = n_aux ? xd + 3 * (size_t)n_atoms : nullptr;
+    HIPCHK(c, hipMemcpyAsync(xd, xyz, 3 * (size_t)n_atoms * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (n_aux)
+        HIPCHK(c, hipMemcpyAsync(nd, n_aux, (size_t)n_atoms * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if ((s = tb_hamiltonian(c, p, n_atoms, xd, nd, Hd)) != SP2_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(H_out, Hd, n2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SP2_OK;
+}
+
 extern "C" sp2_status tb_overlap(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
                                  const double* xyz, double* S_out) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (!params_ok(p) || !(s0 >= 0.0) || !(lam_s > 0.0)) return fail(c, SP2_EINVAL, "bad overlap parameters");
     if (n_atoms < 1 || n_atoms > 16384 || !xyz || !S_out) return fail(c, SP2_EINVAL, "bad tb_overlap arguments");
@@ -1231,6 +1345,7 @@ extern "C" sp2_status tb_overlap(sp2_ctx* c, const tb_params* p, double s0, doub
 // of atom i (h alone when n_aux is NULL).
 extern "C" sp2_status tb_hamiltonian_nonorth(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz,
                                              const double* n_aux, const double* S, double* H_out) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (!params_ok(p)) return fail(c, SP2_EINVAL, "bad tb_params");
     if (n_atoms < 1 || n_atoms > 16384 || !xyz || !S || !H_out)
@@ -1284,6 +1399,7 @@ static sp2_status tb_forces_nonorth_impl(sp2_ctx* c, const tb_params* p, double 
 extern "C" sp2_status tb_forces_nonorth(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
                                         const double* xyz, const double* D, const double* H, const double* q,
                                         const double* n_aux, double* F_out, double* U_host) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (!params_ok(p) || !(s0 >= 0.0) || !(lam_s > 0.0)) return fail(c, SP2_EINVAL, "bad overlap parameters");
     if (n_atoms < 1 || n_atoms > 16384 || !xyz || !D || !H || !q || !n_aux || !F_out)
@@ -1303,6 +1419,7 @@ extern "C" sp2_status tb_forces_nonorth(sp2_ctx* c, const tb_params* p, double s
 
 extern "C" sp2_status tb_forces(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz, const double* D,
                                 const double* q, const double* n_aux, double* F_out, double* U_host) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (!params_ok(p)) return fail(c, SP2_EINVAL, "bad tb_params");
     if (n_atoms < 1 || n_atoms > 16384 || !xyz || !D || !q || !n_aux)
@@ -1322,6 +1439,7 @@ extern "C" sp2_status tb_forces(sp2_ctx* c, const tb_params* p, int n_atoms, con
 extern "C" sp2_status qmd_evaluate(sp2_ctx* c, const tb_params* p, int n_atoms, const double* xyz,
                                    const double* n_aux, int n_occ, const sp2_options* opt, double* q_out,
                                    double* e_band_host, double* e_pot_host, double* F_out, sp2_stats* stats) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (!params_ok(p)) return fail(c, SP2_EINVAL, "bad tb_params");
@@ -1443,6 +1561,7 @@ static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true, fl
 extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd_options* o, int n_atoms,
                                     const double* xyz_host, const double* vel_host, const double* n0_host,
                                     xlbomd** out) {
+    CTX_ENTER(c);
     if (!c) return SP2_EINVAL;
     if (!out || !params_ok(p) || !o || !xyz_host || !vel_host)
         return fail(c, SP2_EINVAL, "bad xlbomd_create arguments");
@@ -1547,6 +1666,7 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
 }
 
 extern "C" sp2_status xlbomd_run(xlbomd* m, int n_steps, xlbomd_record* log) {
+    CTX_ENTER(m ? m->c : nullptr);
     if (!m) return SP2_EINVAL;
     sp2_ctx* c = m->c;
     if (n_steps < 0) return fail(c, SP2_EINVAL, "n_steps < 0");
@@ -1607,6 +1727,7 @@ extern "C" sp2_status xlbomd_info(const xlbomd* m, int* scf_iterations, double* 
 }
 
 extern "C" sp2_status xlbomd_get(xlbomd* m, double* xyz_host, double* vel_host, double* q_host, double* n_host) {
+    CTX_ENTER(m ? m->c : nullptr);
     if (!m) return SP2_EINVAL;
     sp2_ctx* c = m->c;
     HIPCHK(c, hipSetDevice(c->device));
@@ -1687,6 +1808,7 @@ extern "C" sp2_status xlbomd_get_state(const xlbomd* m, void* buf, size_t* bytes
 }
 
 extern "C" sp2_status xlbomd_set_state(xlbomd* m, const void* buf, size_t bytes) {
+    CTX_ENTER(m ? m->c : nullptr);
     if (!m || !buf) return SP2_EINVAL;
     sp2_ctx* c = m->c;
     XlCheckpoint h;
