@@ -663,7 +663,7 @@ def main():
                     help="only run the counter-calibration kernels and one solve per precision "
                          "(for rocprofv3 --pmc passes); prints no JSON")
     ap.add_argument("--only", choices=["finite_temperature", "nonorthogonal", "xlbomd_n4096",
-                                       "blocksparse_n16384", "fp64_n256"],
+                                       "blocksparse_n16384", "thresholded_scaling", "fp64_n256"],
                     help="run only this leg and print its result as one JSON line (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -681,6 +681,7 @@ def main():
         ctx = p.Context(0)
         legs = {"finite_temperature": finite_temperature, "nonorthogonal": nonorthogonal,
                 "xlbomd_n4096": xlbomd_c1, "blocksparse_n16384": blocksparse_c3,
+                "thresholded_scaling": thresholded_scaling,
                 "fp64_n256": lambda c: fp64_small(c)[0]}
         print(json.dumps({args.only: legs[args.only](ctx)}), flush=True)
         ctx.close()
