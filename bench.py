@@ -613,6 +613,29 @@ def breakdown(st):
             "wall": round(st["ms"], 2)}
 
 
+def host_memory(ctx, H, nocc, opts):
+    """The same solve with H and D in pinned host memory (sp2_density_matrix_mem):
+    the PCIe-inclusive time per solve beside the solve alone."""
+    import numpy as np
+    import torch
+    log("host-memory solve (H in, D out over PCIe)")
+    N = H.shape[0]
+    Hh = torch.empty((N, N), dtype=torch.float64, pin_memory=True)
+    Hh.copy_(H)
+    Dh = torch.empty((N, N), dtype=torch.float64, pin_memory=True)
+    H_np, D_np = Hh.numpy(), Dh.numpy()
+    ctx.sp2_density_matrix_mem(H_np, nocc, opts, D_out=D_np)     # warm-up (stages the buffers)
+    t0 = time.perf_counter()
+    _, st = ctx.sp2_density_matrix_mem(H_np, nocc, opts, D_out=D_np)
+    ms = (time.perf_counter() - t0) * 1e3
+    ok = bool(np.isfinite(D_np).all())
+    out = {"ms_per_solve": round(ms, 2), "solve_ms": round(st["ms"], 2), "copies_ms": round(ms - st["ms"], 2),
+           "bytes_over_pcie": 2 * 8 * N * N, "useful_tflops": round(2.0 * N ** 3 * st["iterations"] / (ms * 1e-3) / 1e12, 2),
+           "products": st["iterations"], "finite": ok}
+    log(f"  {out}")
+    return out
+
+
 def digit_products(slices, levels):
     """int8 digit products per SP2 product: planes t, u < slices with t + u < levels."""
     return sum(1 for t in range(slices) for u in range(slices) if t + u < (levels or slices))
@@ -854,6 +877,9 @@ def main():
     }
     if prec == "int8x" and (args.slices, args.levels) != (5, 5):
         out["int8x_five_planes"] = five_planes(ctx, H, nocc, w.n_atoms, g2, args.idem_tol, ms64)
+    hopts = p.options(prec, slices=args.slices, levels=args.levels) if prec == "int8x" else p.options(prec)
+    hopts.idem_tol = args.idem_tol
+    out["host_memory"] = host_memory(ctx, H, nocc, hopts)
     if args.serve_requests > 0 and prec == "int8x":
         out["serving"] = serving(ctx, args.serve_requests, args.serve_rate)
     log("fp64_n256 solve")
