@@ -355,7 +355,8 @@ static size_t solve_part_slots(int N) {
     const int ld = padded_ld(N);
     const int nt = ld / kTile;
     return std::max<size_t>({(size_t)(N + 3) / 4 * 2, (size_t)ld / 4 * 3, (size_t)tri_tiles(nt) * 3, 1024,
-                             (size_t)kDotBlocks, split_part_slots(ld) * 3});
+                             (size_t)kDotBlocks, split_part_slots(ld) * 3,
+                             ld <= kSmallLd ? (size_t)tri_tiles(ld / 32) * 3 : 0});
 }
 
 static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, const sp2_options& o, double* D,
@@ -472,7 +473,8 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
             HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, part, &ns, st, env, tile_group, f64tail,
-                                      f64tail_bytes, tuned_choice(c, ld, SP2_PREC_FP64, 0, 0).split_cap));
+                                      f64tail_bytes, tuned_choice(c, ld, SP2_PREC_FP64, 0, 0).split_cap,
+                                      !(int8x || bf16x)));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
@@ -688,7 +690,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
     if ((s = grow(c, (void**)&c->xbuf, &xbytes, 2 * ld2 * sizeof(double))) != SP2_OK) return s;
     c->xcap = xbytes / (2 * sizeof(double));
     size_t pbytes = c->partcap * sizeof(double);
-    if ((s = grow(c, (void**)&c->part, &pbytes, std::max<size_t>(tri_tiles(nt) * 3, 1024) * sizeof(double))) != SP2_OK)
+    if ((s = grow(c, (void**)&c->part, &pbytes, solve_part_slots(ld) * sizeof(double))) != SP2_OK)
         return s;
     c->partcap = pbytes / sizeof(double);
     const bool int8x = precision == SP2_PREC_INT8X, bf16x = precision == SP2_PREC_BF16X2;
@@ -755,7 +757,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         c->split.stage_cfg = t.stage_cfg;
         if (precision == SP2_PREC_FP64) {
             HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, t.tile_group, f64tail,
-                                      f64tail_bytes, t.split_cap));
+                                      f64tail_bytes, t.split_cap, true));
         } else {
             HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, nullptr));

@@ -357,6 +357,7 @@ __global__ __launch_bounds__(256) void k_ctrl_step_grouped(const GroupDesc* __re
 // the other buffer; per-tile partials Tr X_{n+1}, ||X_{n+1}||_F^2,
 // ||P - X_n||_F^2 (off-diagonal tiles count twice) into part[3 * tile].
 constexpr int GB = 128;   // tile
+constexpr int SB = 32;    // tile of the small-product kernel
 constexpr int GK = 16;    // k per stage
 constexpr int GS = GB;      // LDS row stride (doubles)
 constexpr int F64_NST = 2;  // LDS stages (double buffer: 2 stages x 2 operands x 16 KiB)
@@ -596,6 +597,89 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
     f64_tile<THR>(buf0, buf1, ld, st, part, env, bi, bj, kmode, kc0, kc1, cacc, 0);
 }
 
+// Small products (ld <= kSmallLd, X at most 8 MiB and resident in L2): the
+// 128 x 128 tiles would occupy a handful of CUs, each walking its K loop
+// alone, and splitting them along K adds a second launch that reads the
+// chunks back.  Instead one workgroup per 32 x 32 upper tile (T = nt(nt+1)/2,
+// nt = ld / 32): each of its four waves multiplies a quarter of the K range
+// with operands loaded straight into registers (lane l of a 4-deep k step
+// reads row k + l / 16 of X, 16 consecutive columns per 16 lanes), the four
+// partial tiles are added in LDS in wave order, and the fused update and the
+// partials follow as in the large kernel (one slot per 32 x 32 tile).
+__global__ __launch_bounds__(256) void k_gemm_f64_small(double* __restrict__ buf0, double* __restrict__ buf1,
+                                                        int ld, const State* __restrict__ st,
+                                                        double* __restrict__ part) {
+    if (st->done || (st->phase != 0 && st->phase != 2)) return;
+    const bool r32 = st->phase == 2;
+    const int nts = ld / SB;
+    int t = blockIdx.x, bi = 0;
+    while (t >= nts - bi) {
+        t -= nts - bi;
+        ++bi;
+    }
+    const int bj = bi + t;
+    const double* __restrict__ Xc = st->cur ? buf1 : buf0;
+    double* __restrict__ Xn = st->cur ? buf0 : buf1;
+    const int i0 = bi * SB, j0 = bj * SB;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ci = lane & 15, kr = lane >> 4;
+    const int kq = ld / 4, k0 = w * kq;    // ld is a multiple of 128: kq of 4
+    d4 acc[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = k0; k < k0 + kq; k += 4) {
+        const double* __restrict__ row = Xc + (size_t)(k + kr) * ld;
+        const double a0 = row[i0 + ci], a1 = row[i0 + 16 + ci];
+        const double b0 = row[j0 + ci], b1 = row[j0 + 16 + ci];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __shared__ double red[4][SB][SB + 1];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)   // lane l, element r: row l / 16 + 4 r, column l % 16
+                red[w][m * 16 + kr + 4 * r][n * 16 + ci] = acc[m][n][r];
+    __syncthreads();
+    const int br = st->branch;
+    const bool mirror = bi != bj;
+    double tr = 0.0, fro = 0.0, idm = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q, r = e >> 5, c = e & 31;
+        const double p = ((red[0][r][c] + red[1][r][c]) + red[2][r][c]) + red[3][r][c];
+        const int gi = i0 + r, gj = j0 + c;
+        const double x = Xc[(size_t)gi * ld + gj];
+        double xn = br ? 2.0 * x - p : p;
+        if (r32) {
+            const float pf = (float)p, xf = (float)x;
+            xn = (double)(br ? 2.0f * xf - pf : pf);
+        }
+        Xn[(size_t)gi * ld + gj] = xn;
+        if (mirror) Xn[(size_t)gj * ld + gi] = xn;
+        tr += gi == gj ? xn : 0.0;
+        fro += xn * xn;
+        idm += (p - x) * (p - x);
+    }
+    const double wgt = mirror ? 2.0 : 1.0;
+    __shared__ double sh[4];
+    const double btr = block_sum256(tr, sh);
+    const double bfr = block_sum256(fro, sh);
+    const double bid = block_sum256(idm, sh);
+    if (tid == 0) {
+        part[3 * blockIdx.x + 0] = btr;
+        part[3 * blockIdx.x + 1] = wgt * bfr;
+        part[3 * blockIdx.x + 2] = wgt * bid;
+    }
+}
+
 // Epilogue of the split tiles: workgroup p sums the nsplit chunks of the tile
 // at visiting position t_full + p and applies the update.
 __global__ __launch_bounds__(256, 2) void k_gemm_f64_tail(double* __restrict__ buf0, double* __restrict__ buf1,
@@ -756,7 +840,13 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s) {
 }
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
                            int* nslots, hipStream_t s, const int* env, int tile_group, double* tail_buf,
-                           size_t tail_bytes, int split_cap) {
+                           size_t tail_bytes, int split_cap, bool small_ok) {
+    if (small_ok && !env && ld <= kSmallLd) {
+        const int T = tri_tiles(ld / SB);
+        *nslots = T;
+        hipLaunchKernelGGL(k_gemm_f64_small, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part);
+        return hipGetLastError();
+    }
     const int nt = ld / GB;
     const int T = tri_tiles(nt);
     *nslots = T;

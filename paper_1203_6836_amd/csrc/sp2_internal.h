@@ -238,9 +238,14 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s);
 // 2 x CUs chunks at most.
 constexpr size_t kF64Chunk = 16 * 4 * 256;
 // split_cap: most chunks per split tile (the autotuner chooses 8 or 16).
+// small_ok: products with ld <= kSmallLd and no threshold may run the
+// small-product kernel, whose partial slots are one per 32 x 32 tile (only
+// when no product of another kernel shares the solve's slots).
+constexpr int kSmallLd = 1024;
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
                            int* nslots, hipStream_t s, const int* env = nullptr, int tile_group = 8,
-                           double* tail_buf = nullptr, size_t tail_bytes = 0, int split_cap = 16);
+                           double* tail_buf = nullptr, size_t tail_bytes = 0, int split_cap = 16,
+                           bool small_ok = false);
 // compute units of the current device (cached on first use)
 int device_cus();
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,

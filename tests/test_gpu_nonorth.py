@@ -263,7 +263,8 @@ def test_nonorth_thresholded_gapped_wire_vs_oracle(ctx):
     """The SP2 of H_perp with the elementwise threshold (tau = 1e-5, int8 and
     FP64 products) on the gapped 4 x 4 x 16 wire with an overlap, against the
     oracle's thresholded non-orthogonal solve: FP64 step by step, int8 within
-    a quarter of what the threshold itself moves rho."""
+    the mixed-precision tolerance 1e-6 per sqrt(N) (measured 8.6e-11; the
+    threshold itself moves rho by 1.9e-4)."""
     import paper_1203_6836_amd as p
     m = synth.GAPPED_MODEL.with_(overlap_s0=0.05)
     w = synth.gapped_workload(16)
@@ -285,4 +286,4 @@ def test_nonorth_thresholded_gapped_wire_vs_oracle(ctx):
         f"int8 {e8:.1e}, threshold's own {err_thr:.1e}, fill min {s8['fill_min']:.3f}")
     assert s64["iterations"] == r.iterations
     assert e64 <= 1e-9
-    assert e8 <= 0.25 * err_thr
+    assert e8 <= 1e-6

@@ -9,6 +9,13 @@ import synth
 from oracle import sp2 as osp2, tb as otb
 
 pytestmark = pytest.mark.gpu
+# ||D - D_ref||_F / sqrt(N) of reduced-precision products against the oracle's
+# solve with the same threshold: the mixed-precision tolerance.  An element
+# (or block) within the products' rounding of tau can land on the other side
+# of it, moving D by about tau there; with the int8 expansion's 1e-10
+# relative accuracy this happens to a handful of elements at most (measured
+# 1e-10 at N = 2048, 2.5e-7 at N = 8192, 3.5e-7 on the scattered N = 4096 wire).
+TOL_D = 1e-6
 
 
 def say(msg):
@@ -127,9 +134,8 @@ def test_fp64_threshold_gapped_wire_matches_oracle(ctx, rule, layers):
 def test_int8x_elementwise_gapped_wire_vs_oracle(ctx, layers):
     """int8 products with the elementwise rule on the gapped wire (N = 2048; a
     ragged N = 2112 whose last tiles are mostly padding; a one-tile N = 64):
-    the products differ from FP64 by ~1e-7 relative, which moves a few
-    elements across tau; the result stays within the error the threshold
-    itself makes."""
+    within the mixed-precision tolerance of the oracle's thresholded solve
+    (the threshold itself moves D 200 times further)."""
     import paper_1203_6836_amd as p
     w = synth.gapped_workload(layers)
     say(f"case int8x tau=1e-5 element rule, gapped wire N={w.n_orb}")
@@ -144,7 +150,7 @@ def test_int8x_elementwise_gapped_wire_vs_oracle(ctx, layers):
     say(f"  iters gpu={st['iterations']} oracle={ref.iterations}; err vs oracle {err:.2e}, "
         f"oracle thresholded vs dense {err_thr:.2e}, trace {np.trace(D) - w.n_occ:+.1e}")
     assert abs(st["iterations"] - ref.iterations) <= 1
-    assert err <= 0.25 * err_thr
+    assert err <= TOL_D
     assert abs(np.trace(D) - w.n_occ) < 1e-4
 
 
@@ -153,7 +159,7 @@ def test_int8x_threshold_after_fp64_head_vs_oracle(ctx):
     the int8 products then run on the full grid of tiles, diagonal by
     diagonal, without zero-tile flags, from the band-limited encode.  Both
     rules against the oracle on the gapped 4 x 4 x 32 wire (N = 2048), to the
-    same bar as the list-driven path."""
+    mixed-precision tolerance like the list-driven path."""
     import paper_1203_6836_amd as p
     w = synth.gapped_workload(32)
     H = otb.hamiltonian0(w.positions(), synth.GAPPED_MODEL)
@@ -171,7 +177,7 @@ def test_int8x_threshold_after_fp64_head_vs_oracle(ctx):
             f"err vs oracle {err:.2e}, threshold's own {err_thr:.2e}")
         assert st["fp64_products"] == 3
         assert abs(st["iterations"] - ref.iterations) <= 1
-        assert err <= 0.25 * err_thr
+        assert err <= TOL_D
         assert abs(np.trace(D) - w.n_occ) < 1e-4
 
 
@@ -179,9 +185,8 @@ def test_gapped_wire_full_size_against_oracle(ctx):
     """The smallest size of the benchmark's thresholded-scaling leg (gapped
     wire, N = 8192, elementwise tau = 1e-5) against the oracle's thresholded
     SP2: FP64 products step by step (iterations, fill after every update, D),
-    and the benchmark's int8 products within 1e-5 per sqrt N (a twentieth of
-    what the threshold itself moves D, 2.2e-4: the int8 products differ from
-    FP64 by ~1e-7 relative and move a few elements across tau)."""
+    and the benchmark's int8 products within the mixed-precision tolerance
+    (the threshold itself moves D by 2.2e-4)."""
     import time
     import paper_1203_6836_amd as p
     say("case gapped wire N=8192 elementwise tau=1e-5 vs oracle (full size)")
@@ -206,7 +211,7 @@ def test_gapped_wire_full_size_against_oracle(ctx):
     err8 = np.linalg.norm(D8 - ref.D) / rn
     say(f"  int8: iters {s8['iterations']} err/sqrtN {err8:.2e}, trace {np.trace(D8) - w.n_occ:+.1e}")
     assert abs(s8["iterations"] - ref.iterations) <= 1
-    assert err8 <= 1e-5
+    assert err8 <= TOL_D
 
 
 def test_gapped_wire_thresholded_scaling(ctx):
@@ -257,7 +262,7 @@ def test_block_mask_on_a_scattered_wire_against_oracle(ctx):
     over the whole range, so only the 32 x 32 block masks (not a column
     range) keep the products sparse.  FP64 products against the oracle step
     by step (products, fill after every update, D); int8 products within the
-    bound of the banded wire.  The masks are kept per 128-row panel (the
+    mixed-precision tolerance.  The masks are kept per 128-row panel (the
     product tile): a panel of four scattered groups has about three quarters
     of its 32-column blocks set, so the scattered solve still costs a few
     times the banded one, but less than the dense one (measured 7.3 ms
@@ -293,7 +298,7 @@ def test_block_mask_on_a_scattered_wire_against_oracle(ctx):
     say(f"  int8: products {s8['iterations']}, err {e8:.1e} (threshold's own {err_thr:.1e}); "
         f"{s8['ms']:.1f} ms scattered vs {sb['ms']:.1f} ms banded vs {sd['ms']:.1f} ms dense")
     assert abs(s8["iterations"] - ref.iterations) <= 1
-    assert e8 <= 0.25 * err_thr
+    assert e8 <= TOL_D
     assert s8["ms"] < 0.85 * sd["ms"]
 
 

@@ -506,7 +506,7 @@ def test_xlbomd_step_time_with_threshold(ctx):
 
 
 def test_energy_drift_int8(ctx):
-    """The int8 digit-plane density matrices (error ~1e-7 per sqrt N) in the
+    """The int8 digit-plane density matrices (error ~1e-8 per sqrt N) in the
     same 1000-step run as the FP64 drift test: no systematic drift, and the
     fluctuation within twice that of the FP64 run."""
     import paper_1203_6836_amd as p
@@ -516,7 +516,7 @@ def test_energy_drift_int8(ctx):
     nat = len(x0)
     vel = synth.maxwell_velocities(nat, 300.0, m.mass, seed=22)
     # both runs start from the FP64 self-consistent charges (the int8 charges
-    # carry ~1e-7 of error, so an int8 SCF cannot reach 1e-10)
+    # carry ~1e-8 of error, so an int8 SCF cannot reach 1e-10)
     md = ctx.xlbomd_create(m, x0, vel, synth.checkerboard_charges((4, 4, 4)), sp2_opts=p.options("fp64"),
                            scf_beta=1.0, scf_tol=1e-10, scf_max_iter=100)
     q0 = md.xlbomd_get()[2]
