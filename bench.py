@@ -730,7 +730,7 @@ def main():
     if args.precision != "fp64":
         tune[args.precision] = ctx.sp2_autotune(N, args.precision, args.slices, args.levels)
     log("autotune: " + ", ".join(f"{k} tile_group {v['tile_group']} stage_cfg {v['stage_cfg']} split_cap "
-                                 f"{v['split_cap']}" for k, v in tune.items()))
+                                 f"{v['split_cap']} tile {v['tile']}" for k, v in tune.items()))
     if args.tune_table:
         ctx.sp2_tune_save(args.tune_table)
 
@@ -850,10 +850,10 @@ def main():
                    "levels": args.levels if prec == "int8x" else None,
                    "digit_products": digit_products(args.slices, args.levels) if prec == "int8x" else None,
                    "tile_group": tune[prec]["tile_group"], "stage_cfg": tune[prec]["stage_cfg"],
-                   "split_cap": tune[prec]["split_cap"]},
+                   "split_cap": tune[prec]["split_cap"], "tile": tune[prec]["tile"]},
         "autotune": {k: {"chosen": {"tile_group": v["tile_group"], "stage_cfg": v["stage_cfg"],
-                                    "split_cap": v["split_cap"]},
-                         "ms_per_product": {"G%d/cfg%d/cap%d" % g: round(ms, 4)
+                                    "split_cap": v["split_cap"], "tile": v["tile"]},
+                         "ms_per_product": {"G%d/cfg%d/cap%d/tile%d" % g: round(ms, 4)
                                             for g, ms in v["ms_per_product"].items()}}
                      for k, v in tune.items()},
         "solves_per_s": round(1e3 / ms, 4),

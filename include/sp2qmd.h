@@ -86,8 +86,9 @@ typedef struct {
                             dealt to the XCDs (G > 0), 0 = plain row-major, -1
                             (default) = the value sp2_autotune chose (or a
                             loaded table holds) for this size and precision,
-                            else 8; the tuned K-stage configuration and split
-                            cap apply whatever tile_group is.  INT8X results
+                            else 8; the tuned K-stage configuration, split
+                            cap and FP64 output tile apply whatever
+                            tile_group is (32 x 32 tiles have no order).  INT8X results
                             do not depend on these; FP64 products with a tail
                             split (see below) may differ in the last bits    */
     int tail_split;      /* N >= 4096: when the tiles of the last wave of
@@ -216,7 +217,10 @@ sp2_status sp2_density_matrix_noalloc(sp2_ctx *ctx, int N, const double *H, int 
  * configuration of the LDS staging ring (stage_cfg 0: 64-byte K stages two
  * deep (32-byte three deep at six planes), 1: 32-byte stages three deep, 2:
  * 32-byte stages four deep, up to five planes), for FP64 the most chunks of a
- * tile split along K (8 or 16) -- on a pseudo-random symmetric operand, and
+ * tile split along K (8 or 16) and, up to a padded N of 2048, the output tile
+ * shape (128 x 128 tiles of 4 waves, or 32 x 32 tiles whose 4 waves split K,
+ * no tile order; without an entry pure FP64 solves take the 32 x 32 tile up
+ * to a padded N of 1024) -- on a pseudo-random symmetric operand, and
  * keeps the fastest for later solves of the same padded size and precision
  * that leave tile_group at -1 (and for sizes within a factor of 2 that have
  * no entry of their own).  out (may be NULL): the choice and the measured ms
@@ -226,8 +230,9 @@ typedef struct {
     int tile_group;          /* chosen super-tile size (0 = row-major)            */
     int stage_cfg;           /* INT8X: chosen K-stage configuration              */
     int split_cap;           /* FP64: chosen most chunks of a split tile          */
+    int tile;                /* chosen output tile side: 128, or 32 (FP64 only)   */
     int n_candidates;
-    int candidates[16][3];   /* (tile_group, stage_cfg, split_cap) per candidate  */
+    int candidates[16][4];   /* (tile_group, stage_cfg, split_cap, tile) each     */
     float ms_per_product[16];
 } sp2_tune_result;
 sp2_status sp2_autotune(sp2_ctx *ctx, int N, int precision, int slices, int levels, sp2_tune_result *out);

@@ -41,7 +41,7 @@ class Sp2Options(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("tile_group", ctypes.c_int), ("stage_cfg", ctypes.c_int), ("split_cap", ctypes.c_int),
-                ("n_candidates", ctypes.c_int), ("candidates", (ctypes.c_int * 3) * 16),
+                ("tile", ctypes.c_int), ("n_candidates", ctypes.c_int), ("candidates", (ctypes.c_int * 4) * 16),
                 ("ms_per_product", ctypes.c_float * 16)]
 
 
@@ -420,13 +420,15 @@ class Context:
 
     def sp2_autotune(self, N: int, precision="int8x", slices: int = 5, levels: int = 0):
         """Time the product kernel per launch configuration (tile order; K-stage
-        configuration for int8x; split cap for fp64) at size N; the choice is
-        kept for later solves of that size and precision (tile_group = -1)."""
+        configuration for int8x; split cap and, up to N = 2048, output tile for
+        fp64) at size N; the choice is kept for later solves of that size and
+        precision (tile_group = -1).  Candidates are keyed (tile_group,
+        stage_cfg, split_cap, tile)."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         r = TuneResult()
         self._check(lib().sp2_autotune(self._h, int(N), prec, int(slices), int(levels), ctypes.byref(r)),
                     "sp2_autotune")
-        return {"tile_group": r.tile_group, "stage_cfg": r.stage_cfg, "split_cap": r.split_cap,
+        return {"tile_group": r.tile_group, "stage_cfg": r.stage_cfg, "split_cap": r.split_cap, "tile": r.tile,
                 "ms_per_product": {tuple(r.candidates[k]): r.ms_per_product[k] for k in range(r.n_candidates)}}
 
     def sp2_tune_save(self, path: str):

@@ -40,6 +40,7 @@ struct TuneChoice {
     int tile_group = 8;   // super-tile size of the tile order
     int stage_cfg = 0;    // INT8X: K-stage configuration of dense products
     int split_cap = 16;   // FP64: most chunks of a split tile
+    int tile = 0;         // FP64: output tile side, 128 or 32 (0 = 32 up to kSmallLd, else 128)
     float ms = 0.f;       // measured ms per product
 };
 
@@ -331,7 +332,8 @@ static int int8_levels(const sp2_options& o) {
 
 // The autotuned configuration for (padded N, precision, slices, levels): the
 // entry of that size, else the one of the nearest tuned size within a factor
-// of 2 (the N bucket), else the defaults.
+// of 2 (the N bucket; a 32 x 32 tile entry only up to kSmallMaxLd), else the
+// defaults.
 static TuneChoice tuned_choice(const sp2_ctx* c, int ld, int precision, int slices, int levels) {
     auto it = c->tuned.find(std::make_tuple(ld, precision, slices, levels));
     if (it != c->tuned.end()) return it->second;
@@ -339,7 +341,7 @@ static TuneChoice tuned_choice(const sp2_ctx* c, int ld, int precision, int slic
     double dist = 1e300;
     for (const auto& kv : c->tuned) {
         if (std::get<1>(kv.first) != precision || std::get<2>(kv.first) != slices ||
-            std::get<3>(kv.first) != levels)
+            std::get<3>(kv.first) != levels || (kv.second.tile == 32 && ld > kSmallMaxLd))
             continue;
         const double d = std::fabs(std::log((double)std::get<0>(kv.first) / ld));
         if (d <= std::log(2.0) && d < dist) {
@@ -356,7 +358,7 @@ static size_t solve_part_slots(int N) {
     const int nt = ld / kTile;
     return std::max<size_t>({(size_t)(N + 3) / 4 * 2, (size_t)ld / 4 * 3, (size_t)tri_tiles(nt) * 3, 1024,
                              (size_t)kDotBlocks, split_part_slots(ld) * 3,
-                             ld <= kSmallLd ? (size_t)tri_tiles(ld / 32) * 3 : 0});
+                             ld <= kSmallMaxLd ? (size_t)tri_tiles(ld / 32) * 3 : 0});
 }
 
 static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, const sp2_options& o, double* D,
@@ -427,6 +429,12 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
     c->split.stage_cfg = tc.stage_cfg;
     c->split.tail_split = o.tail_split;
     c->split.levels = int8_levels(o);
+    // FP64 products: the tuned split cap and output tile (the 32 x 32 tile
+    // kernel in pure FP64 solves only: it writes one partial slot per 32 x 32
+    // tile, and does not keep the row maxima of the int8 encode)
+    const TuneChoice f64c = tuned_choice(c, ld, SP2_PREC_FP64, 0, 0);
+    const bool f64_small =
+        !(int8x || bf16x) && ((f64c.tile == 32 && ld <= kSmallMaxLd) || (f64c.tile == 0 && ld <= kSmallLd));
 
     CtrlArgs a;
     a.n_occ = (double)n_occ;
@@ -473,8 +481,7 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
             HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, part, &ns, st, env, tile_group, f64tail,
-                                      f64tail_bytes, tuned_choice(c, ld, SP2_PREC_FP64, 0, 0).split_cap,
-                                      !(int8x || bf16x)));
+                                      f64tail_bytes, f64c.split_cap, f64_small));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, part, &ns, st, env));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
@@ -733,6 +740,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         if (!(g == 0 || g < nt)) continue;
         TuneChoice t;
         t.tile_group = g;
+        t.tile = 128;
         if (int8x) {
             for (int cfg = 0; cfg < 3; ++cfg) {
                 if (cfg == 2 && slices > 5) continue;
@@ -748,6 +756,13 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
             cand.push_back(t);
         }
     }
+    // FP64 up to kSmallMaxLd: the 32 x 32 output tile (no tile order, no split)
+    if (precision == SP2_PREC_FP64 && ld <= kSmallMaxLd) {
+        TuneChoice t;
+        t.tile_group = 0;
+        t.tile = 32;
+        cand.push_back(t);
+    }
     // about 40 ms of products per candidate, at least 3
     const double est_ms = (precision == SP2_PREC_FP64 ? 1.0 / 40e9 : 1.0 / 1.2e12) * (double)ld * ld * ld;
     const int reps = std::max(3, std::min(40, (int)(40.0 / std::max(est_ms, 1e-3))));
@@ -757,7 +772,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         c->split.stage_cfg = t.stage_cfg;
         if (precision == SP2_PREC_FP64) {
             HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, t.tile_group, f64tail,
-                                      f64tail_bytes, t.split_cap, true));
+                                      f64tail_bytes, t.split_cap, t.tile == 32));
         } else {
             HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, nullptr));
@@ -781,6 +796,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
             r.candidates[k][0] = cand[k].tile_group;
             r.candidates[k][1] = cand[k].stage_cfg;
             r.candidates[k][2] = cand[k].split_cap;
+            r.candidates[k][3] = cand[k].tile;
             r.ms_per_product[k] = ms;
             r.n_candidates = (int)k + 1;
         }
@@ -795,22 +811,26 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
     r.tile_group = best.tile_group;
     r.stage_cfg = best.stage_cfg;
     r.split_cap = best.split_cap;
+    r.tile = best.tile;
     if (out) *out = r;
     return SP2_OK;
 }
 
 // Table format: a header line, then one line per tuned configuration:
-//   <arch> <compute units> <padded N> <precision> <slices> <levels> <tile_group> <stage_cfg> <split_cap> <ms>
+//   <arch> <compute units> <padded N> <precision> <slices> <levels> <tile_group> <stage_cfg> <split_cap> <tile>
+//   <ms>
+// (tile: the FP64 output tile side, 128 or 32; 128 for the other precisions)
 extern "C" sp2_status sp2_tune_save(const sp2_ctx* c, const char* path) {
     if (!c || !path) return SP2_EINVAL;
     std::ofstream f(path);
     if (!f) return SP2_EINVAL;
-    f << "# sp2qmd autotuner table: arch cus ld precision slices levels tile_group stage_cfg split_cap "
+    f << "# sp2qmd autotuner table: arch cus ld precision slices levels tile_group stage_cfg split_cap tile "
          "ms_per_product\n";
     for (const auto& kv : c->tuned)
         f << c->arch << ' ' << c->cus << ' ' << std::get<0>(kv.first) << ' ' << std::get<1>(kv.first) << ' '
           << std::get<2>(kv.first) << ' ' << std::get<3>(kv.first) << ' ' << kv.second.tile_group << ' '
-          << kv.second.stage_cfg << ' ' << kv.second.split_cap << ' ' << kv.second.ms << '\n';
+          << kv.second.stage_cfg << ' ' << kv.second.split_cap << ' ' << kv.second.tile << ' ' << kv.second.ms
+          << '\n';
     return f ? SP2_OK : SP2_EINVAL;
 }
 
@@ -828,13 +848,14 @@ extern "C" sp2_status sp2_tune_load(sp2_ctx* c, const char* path) {
         int cus, ld, prec, slices, levels;
         TuneChoice t;
         if (!(in >> arch >> cus >> ld >> prec >> slices >> levels >> t.tile_group >> t.stage_cfg >> t.split_cap >>
-              t.ms))
+              t.tile >> t.ms))
             return fail(c, SP2_EINVAL, "malformed autotuner table line: " + line);
         // entries of another device type, or out of range, are skipped
         if (arch != c->arch || cus != c->cus) continue;
         if (ld < kTile || ld % kTile || prec < SP2_PREC_FP64 || prec > SP2_PREC_BF16X2 || t.tile_group < 0 ||
             t.tile_group > 64 || t.stage_cfg < 0 || t.stage_cfg > 2 || (t.stage_cfg == 2 && slices > 5) ||
-            t.split_cap < 2 || t.split_cap > 16 || levels < 0 || levels > slices + 1)
+            t.split_cap < 2 || t.split_cap > 16 || levels < 0 || levels > slices + 1 ||
+            !(t.tile == 128 || (t.tile == 32 && prec == SP2_PREC_FP64 && ld <= kSmallMaxLd)))
             continue;
         c->tuned[std::make_tuple(ld, prec, slices, levels)] = t;
         ++loaded;

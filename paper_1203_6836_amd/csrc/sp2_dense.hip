@@ -597,10 +597,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
     f64_tile<THR>(buf0, buf1, ld, st, part, env, bi, bj, kmode, kc0, kc1, cacc, 0);
 }
 
-// Small products (ld <= kSmallLd, X at most 8 MiB and resident in L2): the
-// 128 x 128 tiles would occupy a handful of CUs, each walking its K loop
-// alone, and splitting them along K adds a second launch that reads the
-// chunks back.  Instead one workgroup per 32 x 32 upper tile (T = nt(nt+1)/2,
+// Small products (ld <= kSmallMaxLd; at ld <= 1024 X is at most 8 MiB and
+// stays in L2): the 128 x 128 tiles would occupy a handful of CUs, each
+// walking its K loop alone, and splitting them along K adds a second launch
+// that reads the chunks back.  Instead one workgroup per 32 x 32 upper tile (T = nt(nt+1)/2,
 // nt = ld / 32): each of its four waves multiplies a quarter of the K range
 // with operands loaded straight into registers (lane l of a 4-deep k step
 // reads row k + l / 16 of X, 16 consecutive columns per 16 lanes), the four
@@ -841,7 +841,7 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s) {
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
                            int* nslots, hipStream_t s, const int* env, int tile_group, double* tail_buf,
                            size_t tail_bytes, int split_cap, bool small_ok) {
-    if (small_ok && !env && ld <= kSmallLd) {
+    if (small_ok && !env && ld <= kSmallMaxLd) {
         const int T = tri_tiles(ld / SB);
         *nslots = T;
         hipLaunchKernelGGL(k_gemm_f64_small, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part);

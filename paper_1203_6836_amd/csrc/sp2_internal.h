@@ -238,10 +238,13 @@ hipError_t launch_ctrl_step_grouped(const GroupDesc* g, hipStream_t s);
 // 2 x CUs chunks at most.
 constexpr size_t kF64Chunk = 16 * 4 * 256;
 // split_cap: most chunks per split tile (the autotuner chooses 8 or 16).
-// small_ok: products with ld <= kSmallLd and no threshold may run the
-// small-product kernel, whose partial slots are one per 32 x 32 tile (only
-// when no product of another kernel shares the solve's slots).
+// small_ok: a product with ld <= kSmallMaxLd and no threshold runs the
+// small-product kernel (32 x 32 tiles), whose partial slots are one per
+// 32 x 32 tile (only when no product of another kernel shares the solve's
+// slots).  Untuned solves use it up to kSmallLd; the autotuner times it
+// against the 128 x 128 kernel up to kSmallMaxLd.
 constexpr int kSmallLd = 1024;
+constexpr int kSmallMaxLd = 2048;
 hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double* part,
                            int* nslots, hipStream_t s, const int* env = nullptr, int tile_group = 8,
                            double* tail_buf = nullptr, size_t tail_bytes = 0, int split_cap = 16,

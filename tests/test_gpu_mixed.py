@@ -203,8 +203,8 @@ def test_bf16x2_configured_recipe_reported(ctx, dims, seed):
 
 def test_autotune_and_tile_order_invariance(ctx):
     """The autotuner times every candidate launch configuration (tile order;
-    int8: K-stage configuration; FP64: split cap) and keeps the fastest;
-    every tile order gives bitwise the same D."""
+    int8: K-stage configuration; FP64: split cap and output tile) and keeps
+    the fastest; every tile order gives bitwise the same D."""
     import torch
     import paper_1203_6836_amd as p
     say("case autotune + tile-order invariance N=2048")
@@ -213,11 +213,13 @@ def test_autotune_and_tile_order_invariance(ctx):
     nocc = 2 * len(pos)
     for prec in ("int8x", "fp64"):
         r = ctx.sp2_autotune(H.shape[0], prec)
-        key = (r["tile_group"], r["stage_cfg"], r["split_cap"])
+        key = (r["tile_group"], r["stage_cfg"], r["split_cap"], r["tile"])
         say(f"  {prec}: chose {key} from {len(r['ms_per_product'])} candidates")
         assert key in r["ms_per_product"]
-        # tile orders G in {0, 4, 8, 16, 32} with G < 16 tiles per side: {0, 4, 8}
-        assert len(r["ms_per_product"]) == (9 if prec == "int8x" else 6)
+        # tile orders G in {0, 4, 8, 16, 32} with G < 16 tiles per side: {0, 4, 8};
+        # FP64 also the 32 x 32 output tile
+        assert len(r["ms_per_product"]) == (9 if prec == "int8x" else 7)
+        assert {k[3] for k in r["ms_per_product"]} == ({128} if prec == "int8x" else {32, 128})
         assert all(ms > 0 for ms in r["ms_per_product"].values())
         assert r["ms_per_product"][key] == min(r["ms_per_product"].values())
         Ds = [ctx.sp2_density_matrix(H, nocc, p.options(prec, tile_group=g))[0] for g in (-1, 0, 4, 8)]
@@ -258,13 +260,56 @@ def test_tune_table_round_trip_and_stage_configs(ctx, tmp_path):
     ref, _ = ctx.sp2_density_matrix(H, nocc, p.options("int8x", tile_group=8))
     for cfg in (0, 1, 2):
         tp = tmp_path / f"cfg{cfg}.txt"
-        tp.write_text(f"{arch} {cus} 2048 1 5 5 8 {cfg} 16 1.0\n")
+        tp.write_text(f"{arch} {cus} 2048 1 5 5 8 {cfg} 16 128 1.0\n")
         cc = p.Context(0)
         cc.sp2_tune_load(str(tp))
         D, st = cc.sp2_density_matrix(H, nocc, p.options("int8x"))
         say(f"  stage_cfg {cfg}: {st['iterations']} products")
         assert torch.equal(D, ref)
         cc.close()
+
+
+def test_fp64_output_tile_from_table(ctx, tmp_path):
+    """FP64 solves at N = 2048 and a ragged N = 720 (padded 768) with either
+    output tile a table entry selects (128 x 128, or 32 x 32 with K split over
+    the waves) match the oracle's D to the FP64 bar; a 32 x 32 entry beyond
+    the small kernel's largest padded size (2048) is skipped on load."""
+    import paper_1203_6836_amd as p
+    ctx.sp2_autotune(256, "fp64")
+    ctx.sp2_tune_save(str(tmp_path / "probe.txt"))
+    arch, cus = [l for l in (tmp_path / "probe.txt").read_text().splitlines() if not l.startswith("#")][0].split()[:2]
+    for dims in ((8, 8, 8), (6, 6, 5)):
+        pos = synth.lattice_positions(dims, seed=4)
+        H = otb.hamiltonian(pos, None, synth.STATIC_MODEL)
+        N, nocc = H.shape[0], 2 * len(pos)
+        ld = (N + 127) // 128 * 128
+        say(f"case FP64 output tile from the table N={N}")
+        ref = osp2.sp2(H, nocc)
+        out = {}
+        for tile in (128, 32):
+            tp = tmp_path / f"t{tile}_{N}.txt"
+            line = f"{arch} {cus} {ld} 0 0 0 8 0 16 {tile} 1"
+            tp.write_text(line + "\n")
+            cc = p.Context(0)
+            cc.sp2_tune_load(str(tp))
+            cc.sp2_tune_save(str(tmp_path / "back.txt"))
+            assert [l for l in (tmp_path / "back.txt").read_text().splitlines() if not l.startswith("#")] == [line]
+            D, st = cc.sp2_density_matrix(to_dev(H), nocc, p.options("fp64"))
+            D = D.cpu().numpy()
+            err = np.linalg.norm(D - ref.D) / np.sqrt(N)
+            say(f"  tile {tile}: {st['iterations']} products (oracle {ref.iterations}), err/sqrtN {err:.2e}")
+            assert st["iterations"] == ref.iterations
+            assert err <= 1e-10
+            out[tile] = D
+            cc.close()
+        assert np.abs(out[128] - out[32]).max() < 1e-10
+    tp = tmp_path / "big.txt"
+    tp.write_text(f"{arch} {cus} 4096 0 0 0 8 0 16 32 1\n")
+    cc = p.Context(0)
+    cc.sp2_tune_load(str(tp))
+    cc.sp2_tune_save(str(tmp_path / "big_back.txt"))
+    assert [l for l in (tmp_path / "big_back.txt").read_text().splitlines() if not l.startswith("#")] == []
+    cc.close()
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 16), (8, 8, 16)])
