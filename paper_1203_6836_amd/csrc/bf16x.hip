@@ -198,13 +198,12 @@ hipError_t launch_bf16x2_gemm(SplitScratch& s, double* buf0, double* buf1, int l
     const int nt = ld / BB;
     const int T = nt * (nt + 1) / 2;
     *nslots = T;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_bf16x2, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)sizeof(BfSmem));
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<unsigned long long> attr_done{0};
+    hipError_t e = once_per_device(attr_done, [] {
+        return hipFuncSetAttribute((const void*)k_gemm_bf16x2, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)sizeof(BfSmem));
+    });
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gemm_bf16x2, dim3(T), dim3(512), sizeof(BfSmem), stream, buf0, buf1, ld, st, s.bf, part,
                        s.tile_group);
     return hipGetLastError();

@@ -969,16 +969,16 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     const int nt = ld / QB;
     const int T = nt * (nt + 1) / 2;
     const size_t lds = sizeof(I8Smem<S, C>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x<S, NL, THR, UPPER, C>,
+    static std::atomic<unsigned long long> attr_done{0};
+    hipError_t e = once_per_device(attr_done, [&] {
+        hipError_t r = hipFuncSetAttribute((const void*)k_gemm_int8x<S, NL, THR, UPPER, C>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e == hipSuccess && !THR)
-            e = hipFuncSetAttribute((const void*)k_gemm_int8x_tail<S, NL, UPPER, C>,
+        if (r == hipSuccess && !THR)
+            r = hipFuncSetAttribute((const void*)k_gemm_int8x_tail<S, NL, UPPER, C>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+        return r;
+    });
+    if (e != hipSuccess) return e;
     // Tiles of a last wave that would leave at least half of the CUs idle
     // are split along K into nsplit <= 8 chunks (wave quantisation of the
     // tail), when a tile's K loop covers at least 4096 columns: shorter tiles
@@ -1008,13 +1008,12 @@ static hipError_t launch_list_kernel(SplitScratch& s, double* buf0, double* buf1
     const int nt = ld / QB;
     const int T = nt * (nt + 1) / 2;
     const size_t lds = sizeof(I8Smem<S>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x_list<S, NL>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<unsigned long long> attr_done{0};
+    hipError_t e = once_per_device(attr_done, [&] {
+        return hipFuncSetAttribute((const void*)k_gemm_int8x_list<S, NL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds);
+    });
+    if (e != hipSuccess) return e;
     int* list = s.tz + (size_t)2 * T;
     int* ctr = list + T;
     hipLaunchKernelGGL(k_list_reset, dim3(1), dim3(64), 0, stream, ctr, st);
@@ -1092,13 +1091,12 @@ static hipError_t run_encode(SplitScratch& s, const double* buf0, const double* 
 template <int S>
 static hipError_t run_grouped(const GroupDesc* g, int gemm_blocks, hipStream_t stream) {
     const size_t lds = sizeof(I8Smem<S>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_int8x_grouped<S>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<unsigned long long> attr_done{0};
+    hipError_t e = once_per_device(attr_done, [&] {
+        return hipFuncSetAttribute((const void*)k_gemm_int8x_grouped<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds);
+    });
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_encode_int8_grouped<S>, dim3(1024), dim3(256), 0, stream, g);
     hipLaunchKernelGGL(k_gemm_int8x_grouped<S>, dim3(gemm_blocks), dim3(512), lds, stream, g);
     return hipGetLastError();

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 struct sp2_ctx;
 int sp2_ctx_device_of(const sp2_ctx* c);   // defined with the context
 
@@ -249,6 +251,21 @@ hipError_t launch_gemm_f64(double* buf0, double* buf1, int ld, State* st, double
                            int* nslots, hipStream_t s, const int* env = nullptr, int tile_group = 8,
                            double* tail_buf = nullptr, size_t tail_bytes = 0, int split_cap = 16,
                            bool small_ok = false);
+// Kernel attributes (the dynamic LDS limit) are set per device: `done` holds
+// one bit per device id below 64 on which `set()` has succeeded (higher ids
+// call it every time).
+template <typename F>
+hipError_t once_per_device(std::atomic<unsigned long long>& done, F set) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return set();
+    const unsigned long long bit = 1ull << dev;
+    if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
+    e = set();
+    if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
 // compute units of the current device (cached on first use)
 int device_cus();
 hipError_t launch_finalize(const double* buf0, const double* buf1, int ld, int N, double* D,
