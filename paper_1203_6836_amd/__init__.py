@@ -36,7 +36,7 @@ class Sp2Options(ctypes.Structure):
                 ("fp64_head", ctypes.c_int), ("slices", ctypes.c_int),
                 ("fp32_tail", ctypes.c_int), ("tau", ctypes.c_double),
                 ("tile_group", ctypes.c_int), ("tail_split", ctypes.c_int),
-                ("threshold", ctypes.c_int), ("levels", ctypes.c_int)]
+                ("threshold", ctypes.c_int), ("levels", ctypes.c_int), ("dense_fill", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):

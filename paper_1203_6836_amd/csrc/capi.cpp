@@ -190,6 +190,7 @@ void sp2_options_default(sp2_options* o) {
     o->threshold = 0;
     o->tile_group = -1;
     o->tail_split = -1;
+    o->dense_fill = 0.95;
 }
 
 const char* sp2_strerror(int s) {
@@ -302,6 +303,7 @@ static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
     if (o.tile_group < -1 || o.tile_group > 64) return fail(c, SP2_EINVAL, "tile_group must be in [-1, 64]");
     if (o.tail_split < -1 || o.tail_split > 1) return fail(c, SP2_EINVAL, "tail_split must be -1, 0 or 1");
     if (o.threshold < 0 || o.threshold > 1) return fail(c, SP2_EINVAL, "threshold must be 0 (block) or 1 (element)");
+    if (!(o.dense_fill >= 0.0)) return fail(c, SP2_EINVAL, "dense_fill must be >= 0");
     if (o.tau > 0.0 && o.precision == SP2_PREC_BF16X2)
         return fail(c, SP2_EINVAL, "block thresholding runs with FP64 or INT8X products");
     (void)N;
@@ -459,6 +461,12 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
     int* tz = sc.tz;
     c->split.env = int8x ? env : nullptr;
     c->split.tz = tz;
+    // thresholded int8 products from the first one on (work-list path): the
+    // dense tile kernel takes over while X_n's kept fraction is at least
+    // dense_fill
+    const bool dense_switch = int8x && tz && env && o.dense_fill <= 1.0;
+    c->split.dense_switch = dense_switch;
+    a.dense_fill = dense_switch ? o.dense_fill : 2.0;
     hipStream_t st = c->stream;
     HIPCHK(c, hipEventRecord(c->ev0, st));
     int ns = 0, nchk = 0;
@@ -487,7 +495,8 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
             if (o.tau > 0.0)
                 HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, part, &ns, 0, st,
-                                                 env, tz, tz ? tz + (size_t)2 * tri_tiles(nt) : nullptr));
+                                                 env, tz, tz ? tz + (size_t)2 * tri_tiles(nt) : nullptr,
+                                                 dense_switch));
             if (pe) HIPCHK(c, hipEventRecord(pe[4], st));
             HIPCHK(c, launch_ctrl_step(part, ns, c->st, a, st));
         }
@@ -708,6 +717,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         c->split.levels = nl;
         c->split.env = nullptr;
         c->split.tz = nullptr;
+        c->split.dense_switch = false;
     }
     double* buf0 = c->xbuf;
     double* buf1 = c->xbuf + ld2;

@@ -750,8 +750,9 @@ __global__ __launch_bounds__(512) void k_gemm_int8x(double* __restrict__ buf0, d
                                                     const double* __restrict__ scale,
                                                     double* __restrict__ part, const int* __restrict__ env,
                                                     unsigned long long* __restrict__ rmax, int tile_group,
-                                                    int t_full, int nsplit, int* __restrict__ chunk_acc) {
-    if (st->done || st->phase != 1) return;
+                                                    int t_full, int nsplit, int* __restrict__ chunk_acc,
+                                                    int when_full) {
+    if (st->done || st->phase != 1 || (when_full && !st->full_fill)) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S, C>& sm = *reinterpret_cast<I8Smem<S, C>*>(smem_raw);
     const int nt = ld / QB, w = blockIdx.x;
@@ -818,7 +819,7 @@ __device__ __forceinline__ void order_tile_rows(int t, int nt, int G, int& bi, i
 // list order, so whatever the order the work is balanced, and concurrent
 // workgroups work on nearby tiles that share row panels.
 __global__ void k_list_reset(int* __restrict__ list_ctr, const State* __restrict__ st) {
-    if (st->done || st->phase != 1) return;
+    if (st->done || st->phase != 1 || st->full_fill) return;
     if (threadIdx.x < 2) list_ctr[threadIdx.x] = 0;
 }
 
@@ -826,7 +827,7 @@ __global__ __launch_bounds__(256) void k_tile_list(const State* __restrict__ st,
                                                    const int* __restrict__ tz, int nt, int tile_group,
                                                    double* __restrict__ part, int* __restrict__ list,
                                                    int* __restrict__ list_ctr) {
-    if (st->done || st->phase != 1) return;
+    if (st->done || st->phase != 1 || st->full_fill) return;
     const int T = nt * (nt + 1) / 2;
     const int pos = blockIdx.x * 256 + threadIdx.x;
     bool listed = false;
@@ -868,7 +869,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_list(double* __restrict__ bu
                                                          double* __restrict__ part, const int* __restrict__ env,
                                                          int* __restrict__ tz, const int* __restrict__ list,
                                                          int* __restrict__ list_ctr) {
-    if (st->done || st->phase != 1) return;
+    if (st->done || st->phase != 1 || st->full_fill) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
     // the entry index is passed through the first word of the staging ring,
@@ -918,8 +919,9 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ bu
                                                          const double* __restrict__ scale,
                                                          double* __restrict__ part,
                                                          unsigned long long* __restrict__ rmax, int tile_group,
-                                                         int t_full, int nsplit, int* __restrict__ chunk_acc) {
-    if (st->done || st->phase != 1) return;
+                                                         int t_full, int nsplit, int* __restrict__ chunk_acc,
+                                                         int when_full) {
+    if (st->done || st->phase != 1 || (when_full && !st->full_fill)) return;
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S, C>& sm = *reinterpret_cast<I8Smem<S, C>*>(smem_raw);
     int bi, bj;
@@ -965,7 +967,7 @@ int device_cus() {
 
 template <int S, int NL, bool THR, bool UPPER, int C = 0>
 static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
-                                     hipStream_t stream, const int* env) {
+                                     hipStream_t stream, const int* env, int when_full = 0) {
     const int nt = ld / QB;
     const int T = nt * (nt + 1) / 2;
     const size_t lds = sizeof(I8Smem<S, C>);
@@ -995,10 +997,10 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     }
     const int grid = t_full + (T - t_full) * nsplit;
     hipLaunchKernelGGL((k_gemm_int8x<S, NL, THR, UPPER, C>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st,
-                       s.digits, s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
+                       s.digits, s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc, when_full);
     if (t_full < T)
         hipLaunchKernelGGL((k_gemm_int8x_tail<S, NL, UPPER, C>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
-                           st, s.digits, s.scale, part, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc);
+                           st, s.digits, s.scale, part, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc, when_full);
     return hipGetLastError();
 }
 
@@ -1028,7 +1030,16 @@ static hipError_t launch_list_kernel(SplitScratch& s, double* buf0, double* buf1
 template <int S, int NL>
 static hipError_t run_int8x(SplitScratch& s, double* buf0, double* buf1, int ld, State* st, double* part,
                             hipStream_t stream, const int* env) {
-    if (env && s.tz) return launch_list_kernel<S, NL>(s, buf0, buf1, ld, st, part, stream, env);
+    if (env && s.tz) {
+        // thresholded: the work-list product, and with the dense switch the
+        // dense tile kernel over every upper tile (rows encoded whole); of
+        // the two, the first runs while State::full_fill is clear, the second
+        // while it is set.  The same tiles get the same integer sums either way.
+        hipError_t e = launch_list_kernel<S, NL>(s, buf0, buf1, ld, st, part, stream, env);
+        if (e == hipSuccess && s.dense_switch)
+            e = launch_tile_kernel<S, NL, false, false>(s, buf0, buf1, ld, st, part, stream, nullptr, 1);
+        return e;
+    }
     if (env) return launch_tile_kernel<S, NL, true, false>(s, buf0, buf1, ld, st, part, stream, env);
     // dense products: the stage configuration chosen by the autotuner
     if constexpr (i8_cfg_ok(S, 2)) {
@@ -1057,6 +1068,10 @@ __global__ __launch_bounds__(256) void k_encode_int8_env(const double* __restric
     if (st->done || st->phase != 1) return;
     constexpr int KS = I8Stage<S>::KS;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (st->full_fill) {   // the dense tile kernel reads every K block
+        encode_row<S>(st->cur ? buf1 : buf0, ld, i, lane, digits, scale, 0, ld);
+        return;
+    }
     const int p = i / QB;
     const int lo = env[2 * p], hi = env[2 * p + 1];
     if (lo > hi) {

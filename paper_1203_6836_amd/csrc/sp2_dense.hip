@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void k_bounds(const double* __restrict__ part,
         st->fp64_products = 0;
         st->head_switch = -1;
         st->tail_left = 0;
+        st->full_fill = 0;
         st->kept = 0ull;
         if (!(d <= kSymTol * m)) st->done = 5;                          // also catches NaN / inf
         else if (!(st->eps_max > st->eps_min)) st->done = 4;            // H = c I: no gap anywhere
@@ -242,6 +243,7 @@ __device__ __forceinline__ double take_fill(State* st, const CtrlArgs& a) {
     if (a.total_blocks <= 0.0) return -1.0;
     const double f = (double)st->kept / a.total_blocks;
     st->kept = 0ull;
+    st->full_fill = f >= a.dense_fill ? 1 : 0;
     st->fill_min = fmin(st->fill_min, f);
     st->fill_max = fmax(st->fill_max, f);
     return f;

@@ -33,7 +33,9 @@ struct State {
     int fp64_products;
     int head_switch;
     int tail_left;              // FP32 tail products still to do (BF16X2)
-    int pad_;
+    int full_fill;              // 1 while the kept fraction of X_n is at least
+                                // CtrlArgs::dense_fill (thresholded int8 products
+                                // then run the dense tile kernel)
 };
 
 struct CtrlArgs {
@@ -46,6 +48,7 @@ struct CtrlArgs {
     int fp32_tail;   // BF16X2: FP32 products after the BF16 stage stalls
     int mixed;       // 0: FP64 only, 1: INT8X, 2: BF16X2
     double total_blocks;  // block threshold: number of 32 x 32 blocks of N x N (0: off)
+    double dense_fill;    // kept fraction from which State::full_fill is set (> 1: never)
 };
 
 // ---- grouped (multi-system) launches used by the serving loop ----

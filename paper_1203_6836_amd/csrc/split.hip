@@ -171,14 +171,17 @@ __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau
 __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ buf0, double* __restrict__ buf1,
                                                          int ld, int N, double tau, int elem,
                                                          State* __restrict__ st, double* __restrict__ part,
-                                                         int init, int* __restrict__ env, int* __restrict__ tz) {
-    if (st->done) return;
+                                                         int init, int* __restrict__ env, int* __restrict__ tz,
+                                                         int when_full) {
+    if (st->done || (when_full && !st->full_fill)) return;
     const int xb = init ? 0 : (st->cur ? 0 : 1);
     const int nt = ld / 128;
     const int t = blockIdx.x;
     const int T = nt * (nt + 1) / 2;
     // a tile the product wrote as all zero: nothing to threshold or record
-    if (tz && !init && tz[(size_t)xb * T + t]) {
+    // (after the dense tile kernel, which writes every tile and no flags,
+    // every tile is thresholded and its flag rewritten)
+    if (tz && !init && !when_full && tz[(size_t)xb * T + t]) {
         if (threadIdx.x == 0) {
             part[3 * t + 0] = 0.0;
             part[3 * t + 1] = 0.0;
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(256) void k_block_threshold_list(double* __restrict
                                                               int* __restrict__ env, int* __restrict__ tz,
                                                               const int* __restrict__ list,
                                                               const int* __restrict__ list_ctr) {
-    if (st->done) return;
+    if (st->done || st->full_fill) return;
     const int xb = st->cur ? 0 : 1;
     double* X = xb == 0 ? buf0 : buf1;
     const int nt = ld / 128, T = nt * (nt + 1) / 2;
@@ -227,7 +230,7 @@ __global__ void k_env_reset(int* __restrict__ env, int npanel, int nwords, const
 
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
                                   double* part, int* nslots, int init, hipStream_t stream, int* env, int* tz,
-                                  const int* list) {
+                                  const int* list, bool dense_switch) {
     const int nt = ld / 128;
     const int T = nt * (nt + 1) / 2;
     *nslots = T;
@@ -235,12 +238,16 @@ hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, dou
         const int W = mask_words(ld);
         hipLaunchKernelGGL(k_env_reset, dim3((nt * W + 255) / 256), dim3(256), 0, stream, env, nt, W, st);
     }
-    if (list && tz && env && !init)
+    if (list && tz && env && !init) {
         hipLaunchKernelGGL(k_block_threshold_list, dim3(std::min(T, 2048)), dim3(256), 0, stream, buf0, buf1, ld, N,
                            tau, elem, st, part, env, tz, list, list + T);
-    else
+        if (dense_switch)
+            hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, elem, st,
+                               part, 0, env, tz, 1);
+    } else {
         hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, elem, st, part,
-                           init, env, tz);
+                           init, env, tz, 0);
+    }
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ struct SplitScratch {
     int levels = 0;             // int8 digit-product levels t + u < levels: slices or slices + 1 (set per solve)
     bool bf16 = false;
     int8_t* digits = nullptr;   // slices x ld x ld int8 digit planes
-    double* scale = nullptr;    // ld row scales (powers of two)
+    double* scale = nullptr;    // ld row scales (1 + 2^-7) max_j |X_ij| (1 for a zero row)
     uint16_t* bf = nullptr;     // 2 x ld x ld BF16 hi/lo planes
     float* x32 = nullptr;       // ld x ld FP32 master (BF16X2)
     unsigned long long* rmax = nullptr;  // 2 x ld row maxima of |X| (bit patterns), one row per X buffer
@@ -35,6 +35,10 @@ struct SplitScratch {
     // room for the product's work list (T entries) and 2 counters
     const int* env = nullptr;
     int* tz = nullptr;
+    // thresholded int8 products: besides the work-list product, launch the
+    // dense tile kernel, which runs (and the work-list kernels return at
+    // once) while State::full_fill is set
+    bool dense_switch = false;
 };
 
 int split_reserve(SplitScratch& s, int ld, int slices, bool bf16);
@@ -59,10 +63,13 @@ hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld
 // whether it is all zero after thresholding; the X_0 pass reads no flags,
 // sets those of buffer 0 and clears those of buffer 1.  With list non-null
 // as well (the int8 product's work list: T entries, then its entry count),
-// updates visit only the tiles the product computed.
+// updates visit only the tiles the product computed; with dense_switch as
+// well, a pass over every tile is launched beside it, and of the two the
+// list pass runs while State::full_fill is clear, the full pass while it is
+// set (the product then ran the dense tile kernel and built no list).
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
                                   double* part, int* nslots, int init, hipStream_t stream, int* env = nullptr,
-                                  int* tz = nullptr, const int* list = nullptr);
+                                  int* tz = nullptr, const int* list = nullptr, bool dense_switch = false);
 
 // int8 digit-plane product (int8x.hip)
 hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,

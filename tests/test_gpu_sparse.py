@@ -95,6 +95,48 @@ def test_int8x_threshold_full_size(ctx):
     assert abs(float(torch.trace(Ds)) - w.n_occ) < 1e-3
 
 
+@pytest.mark.parametrize("case,rule", [("8x8x8", 0), ("6x6x5", 0), ("6x6x5", 1), ("sparse", 0)])
+def test_dense_switch_is_exact(ctx, case, rule):
+    """Thresholded int8 solves give bitwise the same D, products, branches and
+    fill per update whether their products switch to the dense tile kernel
+    from the first product on (dense_fill 0: rows of X_n encoded whole), at
+    the default kept fraction 0.95, or never (dense_fill 2): N = 2048, a
+    ragged 720 (padded 768: the padding's digits) under both threshold
+    rules, and the 16384-orbital workload, whose products run dense from
+    the update where every block is kept."""
+    import torch
+    import paper_1203_6836_amd as p
+    if case == "sparse":
+        w = synth.SPARSE
+        pos, nocc = w.positions(), w.n_occ
+    else:
+        pos = synth.lattice_positions(tuple(int(x) for x in case.split("x")), seed=5)
+        nocc = 2 * len(pos)
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, to_dev(pos))
+    say(f"case dense switch {case} N={H.shape[0]} rule={rule}")
+    res = {}
+    for f in (2.0, 0.95, 0.0):
+        o = p.options("int8x", tau=1e-5, threshold=rule, dense_fill=f)
+        D, st = ctx.sp2_density_matrix(H, nocc, o)
+        res[f] = (D, st)
+        fills = st["fill_hist"][:st["iterations"] - 1]
+        say(f"  dense_fill {f}: {st['iterations']} products, {st['ms']:.1f} ms, fill max {max(fills):.3f}")
+    D2, s2 = res[2.0]
+    for f in (0.95, 0.0):
+        D, st = res[f]
+        assert st["iterations"] == s2["iterations"]
+        assert st["branches"] == s2["branches"]
+        assert st["fill_hist"] == s2["fill_hist"]
+        assert torch.equal(D, D2)
+
+
+def test_dense_fill_is_validated(ctx):
+    import paper_1203_6836_amd as p
+    H = to_dev(np.diag(np.arange(8.0)))
+    with pytest.raises(p.Sp2Error):
+        ctx.sp2_density_matrix(H, 4, p.options("int8x", tau=1e-5, dense_fill=-0.5))
+
+
 def test_threshold_rule_is_validated(ctx):
     import paper_1203_6836_amd as p
     H = to_dev(np.diag(np.arange(8.0)))
