@@ -160,9 +160,11 @@ def test_blocksparse_n16384_fp64_against_oracle(ctx):
     torch.cuda.empty_cache()
 
 
-def test_blocksparse_n16384_int8_against_oracle(ctx):
-    """The same thresholded solve with int8 digit-plane products against the
-    oracle's FP64 thresholded solve.  A block whose norm sits near tau can be
+@pytest.mark.parametrize("slices,levels", [(5, 0), (4, 5)])
+def test_blocksparse_n16384_int8_against_oracle(ctx, slices, levels):
+    """The same thresholded solve with int8 digit-plane products (five planes,
+    and four planes with five levels as benchmarked) against the oracle's FP64
+    thresholded solve.  A block whose norm sits near tau can be
     kept on one side and dropped on the other; the bound on D is the
     mixed-precision tolerance, 1e-6 per sqrt(N) by the probe-vector estimate
     (measured 1.1e-8, fill per update identical), and charges within 1e-6 e.  The
@@ -174,9 +176,10 @@ def test_blocksparse_n16384_int8_against_oracle(ctx):
     import paper_1203_6836_amd as p
     g = load("c3_blocksparse_n16384.npz")
     w = synth.SPARSE
-    say("case block-sparse N=16384 int8 vs oracle")
+    say(f"case block-sparse N=16384 int8 ({slices} planes, levels {levels}) vs oracle")
     H = ctx.tb_hamiltonian(synth.STATIC_MODEL, to_dev(w.positions()))
-    D, st = ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x", tau=float(g["tau"]), threshold=0))
+    D, st = ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x", tau=float(g["tau"]), threshold=0,
+                                                         slices=slices, levels=levels))
     n_upd = min(st["iterations"], int(g["iterations"])) - 1
     fill_dev = float(np.max(np.abs(np.array(st["fill_hist"][:n_upd]) - g["fill"][1:1 + n_upd])))
     est, dq, blk = sketch_error(D, g, w.n_atoms)
