@@ -33,6 +33,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# digit recipe of every int8 solve of the benchmark (--slices, --levels)
+INT8_RECIPE = {"slices": 4, "levels": 5}
 PEAK = {"fp64": 78.6, "int8x": 5000.0, "bf16x2": 2500.0}   # TFLOP/s (TOP/s for int8), dense
 PEAK_HBM_GBS = 8000.0
 
@@ -215,8 +217,9 @@ def xlbomd_c1(ctx, steps=200, quench_steps=400):
            "steps": steps}
     for prec in ("fp64", "int8x"):
         log(f"xlbomd N=4096: {steps} steps, {prec}")
-        md = ctx.xlbomd_create(m, pos, vel, guess, sp2_opts=p.options(prec), scf_beta=1.0, scf_tol=1e-9,
-                               scf_max_iter=100)
+        recipe = INT8_RECIPE if prec == "int8x" else {}
+        md = ctx.xlbomd_create(m, pos, vel, guess, sp2_opts=p.options(prec, **recipe), scf_beta=1.0,
+                               scf_tol=1e-9, scf_max_iter=100)
         it, _ = md.xlbomd_info()
         t0 = time.perf_counter()
         rec = md.xlbomd_run(steps)
@@ -229,6 +232,7 @@ def xlbomd_c1(ctx, steps=200, quench_steps=400):
                "max_q_minus_n": max(r["max_q_minus_n"] for r in rec),
                "ekin_first_ev": float(ek[0]), "ekin_max_ev": float(ek.max())}
         row.update(energy_stats(et, 0.25, w.n_atoms))
+        row.update(recipe)
         out[prec] = row
         log(f"  {row}")
     # conservation from a relaxed start: quenched MD (velocities zeroed
@@ -284,7 +288,7 @@ def quench(md, nat, max_steps, ftol=1e-3):
     return fmax, xyz
 
 
-def blocksparse_c3(ctx, slices=4, levels=5):
+def blocksparse_c3(ctx):
     """The thresholded solve of the elongated 8 x 8 x 64 lattice (N = 16384):
     32 x 32 blocks with Frobenius norm below 1e-5 dropped after every update,
     int8 (the benchmark's digit recipe) and FP64 products: ms per solve,
@@ -310,7 +314,7 @@ def blocksparse_c3(ctx, slices=4, levels=5):
     g = golden("c3_blocksparse_n16384.npz")
     D = torch.empty_like(H)
     for prec in ("int8x", "fp64"):
-        recipe = {"slices": slices, "levels": levels} if prec == "int8x" else {}
+        recipe = INT8_RECIPE if prec == "int8x" else {}
         opt = p.options(prec, tau=1e-5, threshold=0, **recipe)
         log(f"block-sparse N={N}: {prec}")
         ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
@@ -464,7 +468,7 @@ def thresholded_scaling(ctx, layers=(128, 256, 512, 1024), dense_max=16384):
         log(f"thresholded scaling: gapped wire N={w.n_orb}")
         H = ctx.tb_hamiltonian(synth.GAPPED_MODEL, torch.from_numpy(w.positions()).cuda())
         D = torch.empty_like(H)
-        opt = p.options("int8x", tau=1e-5, threshold=1)
+        opt = p.options("int8x", tau=1e-5, threshold=1, **INT8_RECIPE)
         ctx.sp2_density_matrix(H, w.n_occ, opt, D_out=D)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -481,10 +485,10 @@ def thresholded_scaling(ctx, layers=(128, 256, 512, 1024), dense_max=16384):
                                "threshold": round(sp["post_ms"], 2)}}
         if w.n_orb <= dense_max:
             Dd = torch.empty_like(H)
-            ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x"), D_out=Dd)
+            ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x", **INT8_RECIPE), D_out=Dd)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, sd = ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x"), D_out=Dd)
+            _, sd = ctx.sp2_density_matrix(H, w.n_occ, p.options("int8x", **INT8_RECIPE), D_out=Dd)
             torch.cuda.synchronize()
             row["dense_ms_per_solve"] = round((time.perf_counter() - t0) * 1e3, 2)
             row["dense_products"] = sd["iterations"]
@@ -495,7 +499,7 @@ def thresholded_scaling(ctx, layers=(128, 256, 512, 1024), dense_max=16384):
         del D, H
         torch.cuda.empty_cache()
     return {"workload": "gapped sp wire 4x4xL, 2.0 A, p level +4 eV, 2 electrons per atom",
-            "precision": "int8x", "tau": 1e-5, "threshold": "element", "rows": rows,
+            "precision": "int8x", **INT8_RECIPE, "tau": 1e-5, "threshold": "element", "rows": rows,
             "xlbomd": thresholded_md(ctx)}
 
 
@@ -516,7 +520,8 @@ def thresholded_md(ctx, layers=(128, 256), steps=20):
         xyz = w.positions()
         vel = synth.maxwell_velocities(w.n_atoms, 300.0, m.mass, seed=31)
         row = {"n_atoms": w.n_atoms, "n": w.n_orb, "steps": steps}
-        for name, opt in (("tau0", p.options("int8x")), ("tau1e-5", p.options("int8x", tau=1e-5, threshold=1))):
+        for name, opt in (("tau0", p.options("int8x", **INT8_RECIPE)),
+                          ("tau1e-5", p.options("int8x", tau=1e-5, threshold=1, **INT8_RECIPE))):
             log(f"thresholded MD: {w.n_atoms} atoms, {name}")
             md = ctx.xlbomd_create(m, xyz, vel, np.zeros(w.n_atoms), sp2_opts=opt, scf_max_iter=0)
             md.xlbomd_run(2)                          # warm (allocation, first solves)
@@ -551,7 +556,7 @@ def nonorthogonal(ctx):
     H = ctx.tb_hamiltonian(m, xyz)
     S = ctx.tb_overlap(m, xyz)
     D = torch.empty_like(H)
-    opt = p.options("int8x")
+    opt = p.options("int8x", **INT8_RECIPE)
     ctx.sp2_density_matrix_nonorth(H, S, w.n_occ, opt, D_out=D)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -563,7 +568,7 @@ def nonorthogonal(ctx):
     V = torch.from_numpy(synth.probe_vectors(w.n_orb)).cuda()
     DV = D @ V
     E = D @ (S @ DV) - DV
-    out = {"n": w.n_orb, "ms_per_solve": round(ms, 1), "sp2_ms": round(st["ms"], 1),
+    out = {"n": w.n_orb, **INT8_RECIPE, "ms_per_solve": round(ms, 1), "sp2_ms": round(st["ms"], 1),
            "sp2_products": st["iterations"], "factor_steps": its,
            "trace_DS_minus_nocc": float((D * S).sum()) - w.n_occ,
            "idempotency_DSD_probe_rel": float(torch.linalg.norm(E) / torch.linalg.norm(DV))}
@@ -703,6 +708,7 @@ def main():
     import paper_1203_6836_amd as p
     import synth
 
+    INT8_RECIPE.update(slices=args.slices, levels=args.levels)
     if args.only:
         ctx = p.Context(0)
         legs = {"finite_temperature": finite_temperature, "nonorthogonal": nonorthogonal,
@@ -892,7 +898,7 @@ def main():
         del D64
         torch.cuda.empty_cache()
         out["xlbomd_n4096"] = xlbomd_c1(ctx)
-        out["blocksparse_n16384"] = blocksparse_c3(ctx, args.slices, args.levels)
+        out["blocksparse_n16384"] = blocksparse_c3(ctx)
         out["thresholded_scaling"] = thresholded_scaling(ctx)
         out["nonorthogonal"] = nonorthogonal(ctx)
         out["finite_temperature"] = finite_temperature(ctx)

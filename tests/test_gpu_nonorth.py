@@ -59,13 +59,16 @@ def test_fp64_nonorth_matches_oracle(ctx, dims, seed):
     assert abs(np.trace(D @ S) - w.n_occ) < 1e-8
 
 
-def test_int8x_nonorth_matches_oracle(ctx):
+@pytest.mark.parametrize("recipe", [{}, {"slices": 4, "levels": 5}])
+def test_int8x_nonorth_matches_oracle(ctx, recipe):
+    """Five planes (the library default) and four planes with five levels
+    (the benchmark's recipe)."""
     import paper_1203_6836_amd as p
     w, H, S = system((8, 8, 8), 2)
-    say(f"case nonorth int8x N={w.n_orb}")
+    say(f"case nonorth int8x N={w.n_orb} {recipe}")
     rho_ref, _, _, _ = nonorth.density_matrix(H, S, w.n_occ, solver="lapack")   # N = 2048: library eigensolver
     Sd = to_dev(S)
-    D, st, its = ctx.sp2_density_matrix_nonorth(to_dev(H), Sd, w.n_occ, p.options("int8x"))
+    D, st, its = ctx.sp2_density_matrix_nonorth(to_dev(H), Sd, w.n_occ, p.options("int8x", **recipe))
     q = ctx.sp2_mulliken_overlap(D, Sd, w.n_atoms).cpu().numpy()
     D = D.cpu().numpy()
     err = np.linalg.norm(D - rho_ref) / np.sqrt(w.n_orb)

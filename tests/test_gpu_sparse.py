@@ -227,8 +227,9 @@ def test_gapped_wire_full_size_against_oracle(ctx):
     """The smallest size of the benchmark's thresholded-scaling leg (gapped
     wire, N = 8192, elementwise tau = 1e-5) against the oracle's thresholded
     SP2: FP64 products step by step (iterations, fill after every update, D),
-    and the benchmark's int8 products within the mixed-precision tolerance
-    (the threshold itself moves D by 2.2e-4)."""
+    and int8 products (five planes; four planes with five levels as
+    benchmarked) within the mixed-precision tolerance (the threshold itself
+    moves D by 2.2e-4)."""
     import time
     import paper_1203_6836_amd as p
     say("case gapped wire N=8192 elementwise tau=1e-5 vs oracle (full size)")
@@ -248,12 +249,13 @@ def test_gapped_wire_full_size_against_oracle(ctx):
     assert st["iterations"] == ref.iterations and st["status"] == ref.status
     assert err <= 1e-9
     np.testing.assert_allclose(st["fill_hist"][:n_upd], ref.fill[1:1 + n_upd], atol=1e-7)
-    D8, s8 = ctx.sp2_density_matrix(Hd, w.n_occ, p.options("int8x", tau=1e-5, threshold=1))
-    D8 = D8.cpu().numpy()
-    err8 = np.linalg.norm(D8 - ref.D) / rn
-    say(f"  int8: iters {s8['iterations']} err/sqrtN {err8:.2e}, trace {np.trace(D8) - w.n_occ:+.1e}")
-    assert abs(s8["iterations"] - ref.iterations) <= 1
-    assert err8 <= TOL_D
+    for recipe in ({}, {"slices": 4, "levels": 5}):
+        D8, s8 = ctx.sp2_density_matrix(Hd, w.n_occ, p.options("int8x", tau=1e-5, threshold=1, **recipe))
+        D8 = D8.cpu().numpy()
+        err8 = np.linalg.norm(D8 - ref.D) / rn
+        say(f"  int8 {recipe}: iters {s8['iterations']} err/sqrtN {err8:.2e}, trace {np.trace(D8) - w.n_occ:+.1e}")
+        assert abs(s8["iterations"] - ref.iterations) <= 1
+        assert err8 <= TOL_D
 
 
 def test_gapped_wire_thresholded_scaling(ctx):

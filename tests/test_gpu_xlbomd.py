@@ -45,7 +45,12 @@ def test_scf_start_matches_oracle(ctx):
     assert abs(it_g - it_o) <= 2
 
 
-@pytest.mark.parametrize("prec", ["fp64", "int8x"])
+# digit recipes of the int8 products: the library default (five planes) and
+# the benchmark's four planes with five levels (13 digit products)
+RECIPES = {"fp64": ("fp64", {}), "int8x": ("int8x", {}), "int8x13": ("int8x", {"slices": 4, "levels": 5})}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "int8x", "int8x13"])
 def test_xlbomd_1024_atoms_200_steps(ctx, prec):
     """8 x 8 x 16 jittered lattice, 300 K, dt = 0.25 fs, K = 5, 200 steps.
 
@@ -64,8 +69,8 @@ def test_xlbomd_1024_atoms_200_steps(ctx, prec):
     vel = synth.maxwell_velocities(w.n_atoms, 300.0, m.mass, seed=synth.XLBOMD_VEL_SEED)
     t0 = time.perf_counter()
     guess = synth.checkerboard_charges(w.dims)
-    md = ctx.xlbomd_create(m, pos, vel, guess, sp2_opts=p.options(prec), scf_beta=1.0, scf_tol=1e-9,
-                           scf_max_iter=100)
+    md = ctx.xlbomd_create(m, pos, vel, guess, sp2_opts=p.options(RECIPES[prec][0], **RECIPES[prec][1]),
+                           scf_beta=1.0, scf_tol=1e-9, scf_max_iter=100)
     t_scf = time.perf_counter() - t0
     it, res = md.xlbomd_info()
     log, stopped = [], None
@@ -506,9 +511,10 @@ def test_xlbomd_step_time_with_threshold(ctx):
 
 
 def test_energy_drift_int8(ctx):
-    """The int8 digit-plane density matrices (error ~1e-8 per sqrt N) in the
-    same 1000-step run as the FP64 drift test: no systematic drift, and the
-    fluctuation within twice that of the FP64 run."""
+    """The int8 digit-plane density matrices (error ~1e-8 per sqrt N with five
+    planes, ~2e-7 with four planes and five levels) in the same 1000-step run
+    as the FP64 drift test: no systematic drift, and the fluctuation within
+    twice that of the FP64 run."""
     import paper_1203_6836_amd as p
     say("case xlbomd 64 atoms, int8x, 1000 steps")
     m = synth.MD_MODEL
@@ -522,8 +528,9 @@ def test_energy_drift_int8(ctx):
     q0 = md.xlbomd_get()[2]
     md.close()
     sig = {}
-    for prec in ("fp64", "int8x"):
-        md = ctx.xlbomd_create(m, x0, vel, q0, sp2_opts=p.options(prec), scf_max_iter=0)
+    for prec in ("fp64", "int8x", "int8x13"):
+        md = ctx.xlbomd_create(m, x0, vel, q0, sp2_opts=p.options(RECIPES[prec][0], **RECIPES[prec][1]),
+                               scf_max_iter=0)
         log = []
         while len(log) < 1000:
             log += md.xlbomd_run(200)
@@ -538,3 +545,4 @@ def test_energy_drift_int8(ctx):
         assert drift <= 2.0 * sigma
         sig[prec] = sigma
     assert sig["int8x"] <= 2.0 * sig["fp64"]
+    assert sig["int8x13"] <= 2.0 * sig["fp64"]
