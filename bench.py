@@ -360,7 +360,7 @@ def serving(ctx, n_requests, rate):
     torch.cuda.synchronize()
 
     log("serving: continuous batching (int8 digit planes)")
-    srv = p.Server(ctx)
+    srv = p.Server(ctx, **INT8_RECIPE)
     lag = [0.0] * len(reqs)
     tickets = [None] * len(reqs)
 
@@ -396,7 +396,7 @@ def serving(ctx, n_requests, rate):
     # does not limit the server), timed until drained
     window, clients = 16, 4
     log(f"serving: saturated ({clients} clients x {window} requests in flight)")
-    srv = p.Server(ctx)
+    srv = p.Server(ctx, **INT8_RECIPE)
 
     def client(c):
         mine = list(range(c, len(reqs), clients))

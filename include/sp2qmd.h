@@ -552,6 +552,8 @@ typedef struct {
                                   more amortize the host round trip of a tick,
                                   a finished system waits out the rest of its
                                   tick (its launches return at once)            */
+    int levels;                /* digit-product levels, as sp2_options.levels: 0
+                                  (default) = slices, or slices + 1 (slices <= 5) */
 } sp2_server_options;
 
 typedef struct sp2_server sp2_server;

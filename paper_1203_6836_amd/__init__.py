@@ -96,7 +96,7 @@ class XLRecord(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int),
                 ("slices", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("idem_tol", ctypes.c_double), ("iters_per_tick", ctypes.c_int)]
+                ("idem_tol", ctypes.c_double), ("iters_per_tick", ctypes.c_int), ("levels", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p

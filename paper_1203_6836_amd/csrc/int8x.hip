@@ -933,7 +933,7 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ bu
 
 // Grouped: every upper-triangular tile of every system in the group; a fixed
 // grid loops over them (so the launch can be captured once and replayed).
-template <int S>
+template <int S, int NL>
 __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __restrict__ g) {
     extern __shared__ __align__(16) int8_t smem_raw[];
     I8Smem<S>& sm = *reinterpret_cast<I8Smem<S>*>(smem_raw);
@@ -945,8 +945,8 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_grouped(const GroupDesc* __r
         int bi = 0, bj = 0, tl = item - g->tile_off[s], nt = v.ld / QB, off = 0;
         while (tl >= off + (nt - bi)) { off += nt - bi; ++bi; }
         bj = bi + (tl - off);
-        int8x_tile<S, S, false, false>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr,
-                                    nullptr);
+        int8x_tile<S, NL, false, false>(v.buf0, v.buf1, v.ld, v.st, v.digits, v.scale, v.part, bi, bj, sm, nullptr,
+                                     nullptr);
         __syncthreads();
     }
 }
@@ -1103,27 +1103,29 @@ static hipError_t run_encode(SplitScratch& s, const double* buf0, const double* 
     return hipGetLastError();
 }
 
-template <int S>
+template <int S, int NL>
 static hipError_t run_grouped(const GroupDesc* g, int gemm_blocks, hipStream_t stream) {
     const size_t lds = sizeof(I8Smem<S>);
     static std::atomic<unsigned long long> attr_done{0};
     hipError_t e = once_per_device(attr_done, [&] {
-        return hipFuncSetAttribute((const void*)k_gemm_int8x_grouped<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds);
+        return hipFuncSetAttribute((const void*)k_gemm_int8x_grouped<S, NL>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_encode_int8_grouped<S>, dim3(1024), dim3(256), 0, stream, g);
-    hipLaunchKernelGGL(k_gemm_int8x_grouped<S>, dim3(gemm_blocks), dim3(512), lds, stream, g);
+    hipLaunchKernelGGL((k_gemm_int8x_grouped<S, NL>), dim3(gemm_blocks), dim3(512), lds, stream, g);
     return hipGetLastError();
 }
 
-hipError_t launch_int8x_grouped(int slices, const GroupDesc* g, int gemm_blocks, hipStream_t stream) {
+hipError_t launch_int8x_grouped(int slices, int levels, const GroupDesc* g, int gemm_blocks, hipStream_t stream) {
+    const bool next = levels == slices + 1;
+    if (!next && levels != slices) return hipErrorInvalidValue;
     switch (slices) {
-        case 2: return run_grouped<2>(g, gemm_blocks, stream);
-        case 3: return run_grouped<3>(g, gemm_blocks, stream);
-        case 4: return run_grouped<4>(g, gemm_blocks, stream);
-        case 5: return run_grouped<5>(g, gemm_blocks, stream);
-        case 6: return run_grouped<6>(g, gemm_blocks, stream);
+        case 2: return next ? run_grouped<2, 3>(g, gemm_blocks, stream) : run_grouped<2, 2>(g, gemm_blocks, stream);
+        case 3: return next ? run_grouped<3, 4>(g, gemm_blocks, stream) : run_grouped<3, 3>(g, gemm_blocks, stream);
+        case 4: return next ? run_grouped<4, 5>(g, gemm_blocks, stream) : run_grouped<4, 4>(g, gemm_blocks, stream);
+        case 5: return next ? run_grouped<5, 6>(g, gemm_blocks, stream) : run_grouped<5, 5>(g, gemm_blocks, stream);
+        case 6: return next ? hipErrorInvalidValue : run_grouped<6, 6>(g, gemm_blocks, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -520,6 +520,8 @@ sp2_status sp2_server_create(sp2_ctx* ctx, const sp2_server_options* opt, sp2_se
     sp2_server_options o;
     if (opt) o = *opt;
     else sp2_server_options_default(&o);
+    if (o.levels == 0) o.levels = o.slices;
+    if (!(o.levels == o.slices || (o.levels == o.slices + 1 && o.slices <= 5))) return SP2_EINVAL;
     if (o.max_slots < 1 || o.max_slots > kMaxGroup || o.slices < 2 || o.slices > kMaxSlices ||
         o.hbm_budget_bytes < ((uint64_t)1 << 20) || o.max_iter < 1 || o.max_iter > kMaxIter ||
         !(o.idem_tol > 0) || o.iters_per_tick < 1 || o.iters_per_tick > 16)
@@ -548,14 +550,14 @@ sp2_status sp2_server_create(sp2_ctx* ctx, const sp2_server_options* opt, sp2_se
     // capture one tick: iters_per_tick x (grouped encode, product, control)
     ok = hipMemcpy(s->g_dev, s->g_host, sizeof(GroupDesc), hipMemcpyHostToDevice) == hipSuccess;
     // make the lazily set kernel attributes happen outside the capture
-    ok = ok && launch_int8x_grouped(o.slices, s->g_dev, 256, s->stream) == hipSuccess;
+    ok = ok && launch_int8x_grouped(o.slices, o.levels, s->g_dev, 256, s->stream) == hipSuccess;
     ok = ok && launch_ctrl_step_grouped(s->g_dev, s->stream) == hipSuccess;
     ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
     hipGraph_t g = nullptr;
     ok = ok && hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
         for (int k = 0; k < o.iters_per_tick && ok; ++k) {
-            ok = launch_int8x_grouped(o.slices, s->g_dev, 256, s->stream) == hipSuccess;
+            ok = launch_int8x_grouped(o.slices, o.levels, s->g_dev, 256, s->stream) == hipSuccess;
             ok = ok && launch_ctrl_step_grouped(s->g_dev, s->stream) == hipSuccess;
         }
         ok = (hipStreamEndCapture(s->stream, &g) == hipSuccess) && ok;

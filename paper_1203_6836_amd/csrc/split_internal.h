@@ -85,6 +85,6 @@ hipError_t launch_bf16x2_gemm(SplitScratch& s, double* buf0, double* buf1, int l
 
 // Grouped encode + product over every system of g (fixed grids: 1024 encode
 // workgroups, gemm_blocks product workgroups), for the serving loop.
-hipError_t launch_int8x_grouped(int slices, const GroupDesc* g, int gemm_blocks, hipStream_t stream);
+hipError_t launch_int8x_grouped(int slices, int levels, const GroupDesc* g, int gemm_blocks, hipStream_t stream);
 
 }  // namespace sp2

@@ -32,13 +32,18 @@ def request_H(n_atoms, seed):
     return otb.hamiltonian(pos, None, synth.STATIC_MODEL)
 
 
-def test_server_alone_equals_mix_and_direct(ctx):
+@pytest.mark.parametrize("recipe", [{}, {"slices": 4, "levels": 5}])
+def test_server_alone_equals_mix_and_direct(ctx, recipe):
+    """A request served alone and in a mix gives bitwise the same D and q, the
+    same as the direct int8 solve with the same digit recipe (five planes;
+    four planes with five levels), and every result is within the
+    mixed-precision tolerance of the oracle."""
     import torch
     import paper_1203_6836_amd as p
-    say("case serving alone vs mix")
+    say(f"case serving alone vs mix {recipe}")
     probe = request_H(40, 1000)           # N = 160 (ragged: ld = 256)
     others = [request_H(n, 2000 + k) for k, n in enumerate([32, 150, 77, 300, 64, 129])]
-    srv = p.Server(ctx, max_slots=8)
+    srv = p.Server(ctx, max_slots=8, **recipe)
     t = srv.sp2_server_submit(probe, 80)
     D_alone, q_alone, st_alone = srv.sp2_server_wait(t, probe.shape[0])
     # in a mix: submit others first, the probe in the middle, more after
@@ -52,7 +57,7 @@ def test_server_alone_equals_mix_and_direct(ctx):
     say(f"  iters {st_alone['iterations']} / {st_mix['iterations']}; report {rep}")
     assert np.array_equal(D_alone, D_mix) and np.array_equal(q_alone, q_mix)
     # the same as the direct (non-served) int8 solve
-    D_direct, _ = ctx.sp2_density_matrix(torch.from_numpy(probe).cuda(), 80, p.options("int8x"))
+    D_direct, _ = ctx.sp2_density_matrix(torch.from_numpy(probe).cuda(), 80, p.options("int8x", **recipe))
     assert np.array_equal(D_alone, D_direct.cpu().numpy())
     # every result in the mix within the tolerance of the oracle
     for (D, q, st), H in zip(outs, others):
@@ -61,6 +66,14 @@ def test_server_alone_equals_mix_and_direct(ctx):
         dq = np.max(np.abs(q - observables.mulliken(ref.D)))
         assert err <= 1e-6 and dq <= 1e-6, (H.shape[0], err, dq)
     assert rep["p50_ms"] > 0 and rep["p99_ms"] >= rep["p50_ms"]
+
+
+def test_server_levels_are_validated(ctx):
+    import paper_1203_6836_amd as p
+    with pytest.raises(p.Sp2Error):
+        p.Server(ctx, slices=6, levels=7)
+    with pytest.raises(p.Sp2Error):
+        p.Server(ctx, slices=4, levels=3)
 
 
 def test_server_admission_by_footprint(ctx):
