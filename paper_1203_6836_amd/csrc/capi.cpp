@@ -473,9 +473,11 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
     HIPCHK(c, launch_check_h(H, N, c->chk, &nchk, st));
     HIPCHK(c, launch_gershgorin(H, N, part, &ns, st));
     HIPCHK(c, launch_bounds(part, ns, c->chk, nchk, c->st, st));
-    HIPCHK(c, launch_init(H, N, ld, buf0, c->st, part, &ns, st, upper ? c->split.rmax : nullptr));
-    if (o.tau > 0.0)
-        HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, part, &ns, 1, st, env, tz));
+    if (o.tau > 0.0)   // X_0 formed and thresholded in one pass over H
+        HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, part, &ns, 1, st, env, tz,
+                                         nullptr, false, H));
+    else
+        HIPCHK(c, launch_init(H, N, ld, buf0, c->st, part, &ns, st, upper ? c->split.rmax : nullptr));
     HIPCHK(c, launch_ctrl_init(part, ns, c->st, a, st));
 
     int launched = 0;

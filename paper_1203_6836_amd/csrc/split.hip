@@ -29,11 +29,19 @@ __device__ __forceinline__ void tri_coords_t(int t, int nt, int& bi, int& bj) {
 // symmetric, so both copies take the same decision), and a block counts as
 // kept while any element of it survives.  The tile's trace and ||X||_F^2
 // partials are rewritten for the thresholded X; the idempotency partial of
-// the product is kept (zeroed for X_0).
+// the product is kept (zeroed for X_0).  FROM_H (the first pass of a
+// thresholded solve, H N x N): the tile's X_0 = (eps_max I - H) /
+// (eps_max - eps_min) is formed here from H instead of read from X (zero
+// outside N x N) and every block is written, the mirror of an off-diagonal
+// tile from its upper copy: one pass over H instead of forming X_0 and
+// thresholding it in two.
+template <bool FROM_H>
 __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau, int elem, State* __restrict__ st,
                                double* __restrict__ part, int init, int* __restrict__ env, int* __restrict__ tz,
-                               int xb, int T, int t, int bi, int bj) {
+                               int xb, int T, int t, int bi, int bj, const double* __restrict__ H) {
     const bool mirror = bi != bj;
+    const double emax = FROM_H ? st->eps_max : 0.0;
+    const double inv = FROM_H ? 1.0 / (st->eps_max - st->eps_min) : 0.0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nb = (N + 31) / 32;
     double tr = 0.0, fro = 0.0;
@@ -44,16 +52,38 @@ __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau
     // transposed copy of each wave's block, for coalesced writes of the
     // mirrored block (row stride 33 spreads the column-wise stores over banks)
     __shared__ double tb[4][32][33];
+    // FROM_H: the wave's four blocks of H are loaded first, all in flight at
+    // once (the pass streams the whole matrix); otherwise one block at a time
+    double vv[FROM_H ? 4 : 1][16];
+    if constexpr (FROM_H) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int b = w * 4 + s, br = b >> 2, bc = b & 3;
+            const int r0 = bi * 128 + br * 32, c0 = bj * 128 + bc * 32;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int e = lane + 64 * m, r = e >> 5, c = e & 31;
+                const int i = r0 + r, j = c0 + c;
+                vv[s][m] = (i < N && j < N) ? ((i == j ? emax : 0.0) - H[(size_t)i * N + j]) * inv : 0.0;
+            }
+        }
+    }
+#pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int b = w * 4 + s, br = b >> 2, bc = b & 3;
         const int r0 = bi * 128 + br * 32, c0 = bj * 128 + bc * 32;
-        double v[16];
+        double* v = vv[FROM_H ? s : 0];
+        if constexpr (!FROM_H) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int e = lane + 64 * m, r = e >> 5, c = e & 31;
+                v[m] = X[(size_t)(r0 + r) * ld + c0 + c];
+            }
+        }
         double ss = 0.0;
         bool nz = false, changed = false;
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
-            const int e = lane + 64 * m, r = e >> 5, c = e & 31;
-            v[m] = X[(size_t)(r0 + r) * ld + c0 + c];
             if (elem && v[m] != 0.0 && fabs(v[m]) < tau) {
                 v[m] = 0.0;
                 changed = true;
@@ -72,7 +102,7 @@ __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau
         }
         // write back only blocks that changed: the block row by row, and its
         // mirror (X is exactly symmetric, so the mirror is the transpose)
-        const bool wchanged = __any(changed);
+        const bool wchanged = FROM_H || __any(changed);
         if (wchanged) {
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
@@ -190,7 +220,22 @@ __global__ __launch_bounds__(256) void k_block_threshold(double* __restrict__ bu
     }
     int bi, bj;
     tri_coords_t(t, nt, bi, bj);
-    threshold_tile(xb == 0 ? buf0 : buf1, ld, N, tau, elem, st, part, init, env, tz, xb, T, t, bi, bj);
+    threshold_tile<false>(xb == 0 ? buf0 : buf1, ld, N, tau, elem, st, part, init, env, tz, xb, T, t, bi, bj,
+                          nullptr);
+}
+
+// The X_0 pass of a thresholded solve, X_0 formed from H (N x N) on the fly.
+__global__ __launch_bounds__(256) void k_block_threshold_x0(const double* __restrict__ H, double* __restrict__ X,
+                                                            int ld, int N, double tau, int elem,
+                                                            State* __restrict__ st, double* __restrict__ part,
+                                                            int* __restrict__ env, int* __restrict__ tz) {
+    if (st->done) return;
+    const int nt = ld / 128;
+    const int t = blockIdx.x;
+    const int T = nt * (nt + 1) / 2;
+    int bi, bj;
+    tri_coords_t(t, nt, bi, bj);
+    threshold_tile<true>(X, ld, N, tau, elem, st, part, 1, env, tz, 0, T, t, bi, bj, H);
 }
 
 // Thresholded int8 products driven by a work list (entries (zero_store << 30)
@@ -212,7 +257,7 @@ __global__ __launch_bounds__(256) void k_block_threshold_list(double* __restrict
         const int it = list[k];
         if (it >> 30) continue;
         const int bi = (it >> 15) & 0x7fff, bj = it & 0x7fff;
-        threshold_tile(X, ld, N, tau, elem, st, part, 0, env, tz, xb, T, tri_index(bi, bj, nt), bi, bj);
+        threshold_tile<false>(X, ld, N, tau, elem, st, part, 0, env, tz, xb, T, tri_index(bi, bj, nt), bi, bj, nullptr);
         __syncthreads();   // the tile's shared sums are reused by the next entry
     }
 }
@@ -230,7 +275,7 @@ __global__ void k_env_reset(int* __restrict__ env, int npanel, int nwords, const
 
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
                                   double* part, int* nslots, int init, hipStream_t stream, int* env, int* tz,
-                                  const int* list, bool dense_switch) {
+                                  const int* list, bool dense_switch, const double* H) {
     const int nt = ld / 128;
     const int T = nt * (nt + 1) / 2;
     *nslots = T;
@@ -245,8 +290,12 @@ hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, dou
             hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, elem, st,
                                part, 0, env, tz, 1);
     } else {
-        hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, elem, st, part,
-                           init, env, tz, 0);
+        if (init && H)
+            hipLaunchKernelGGL(k_block_threshold_x0, dim3(T), dim3(256), 0, stream, H, buf0, ld, N, tau, elem, st,
+                               part, env, tz);
+        else
+            hipLaunchKernelGGL(k_block_threshold, dim3(T), dim3(256), 0, stream, buf0, buf1, ld, N, tau, elem, st,
+                               part, init, env, tz, 0);
     }
     return hipGetLastError();
 }

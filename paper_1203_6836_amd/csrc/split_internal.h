@@ -66,10 +66,13 @@ hipError_t launch_split_gemm(SplitScratch& s, double* buf0, double* buf1, int ld
 // updates visit only the tiles the product computed; with dense_switch as
 // well, a pass over every tile is launched beside it, and of the two the
 // list pass runs while State::full_fill is clear, the full pass while it is
-// set (the product then ran the dense tile kernel and built no list).
+// set (the product then ran the dense tile kernel and built no list).  With
+// init and H (N x N) non-null, the X_0 pass forms X_0 from H itself (no
+// launch_init before it).
 hipError_t launch_block_threshold(double* buf0, double* buf1, int ld, int N, double tau, int elem, State* st,
                                   double* part, int* nslots, int init, hipStream_t stream, int* env = nullptr,
-                                  int* tz = nullptr, const int* list = nullptr, bool dense_switch = false);
+                                  int* tz = nullptr, const int* list = nullptr, bool dense_switch = false,
+                                  const double* H = nullptr);
 
 // int8 digit-plane product (int8x.hip)
 hipError_t launch_int8x_encode(SplitScratch& s, const double* buf0, const double* buf1, int ld, State* st,
