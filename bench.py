@@ -683,6 +683,9 @@ def main():
                     help="int8 digit-product levels kept (slices or slices + 1)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-table", default=None, help="write the autotuner's table to this file")
+    ap.add_argument("--probe-table", default=None,
+                    help="with --traffic-probe: load this autotuner table (written by --tune-table) instead of "
+                         "tuning, so that counter passes on one box all run the same launch configuration")
     ap.add_argument("--idem-tol", type=float, default=1e-10,
                     help="stop tolerance on ||X^2 - X||_F for both paths of the main solve")
     ap.add_argument("--fp64-steps", type=int, default=1)
@@ -735,13 +738,19 @@ def main():
         return st, q, e
 
     # product tile order for this size (timed on the device; not in the timed region)
-    tune = {"fp64": ctx.sp2_autotune(N, "fp64")}
-    if args.precision != "fp64":
-        tune[args.precision] = ctx.sp2_autotune(N, args.precision, args.slices, args.levels)
-    log("autotune: " + ", ".join(f"{k} tile_group {v['tile_group']} stage_cfg {v['stage_cfg']} split_cap "
-                                 f"{v['split_cap']} tile {v['tile']}" for k, v in tune.items()))
-    if args.tune_table:
-        ctx.sp2_tune_save(args.tune_table)
+    if args.traffic_probe and args.probe_table:
+        ctx.sp2_tune_load(args.probe_table)
+        with open(args.probe_table) as f:
+            log("traffic probe: launch configuration from " + args.probe_table + ": " +
+                "; ".join(l.strip() for l in f if l.strip() and not l.startswith("#")))
+    else:
+        tune = {"fp64": ctx.sp2_autotune(N, "fp64")}
+        if args.precision != "fp64":
+            tune[args.precision] = ctx.sp2_autotune(N, args.precision, args.slices, args.levels)
+        log("autotune: " + ", ".join(f"{k} tile_group {v['tile_group']} stage_cfg {v['stage_cfg']} split_cap "
+                                     f"{v['split_cap']} tile {v['tile']}" for k, v in tune.items()))
+        if args.tune_table:
+            ctx.sp2_tune_save(args.tune_table)
 
     if args.traffic_probe:
         # calibration for the HBM byte counters: kernels of known traffic
