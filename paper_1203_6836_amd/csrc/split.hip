@@ -100,8 +100,9 @@ __device__ void threshold_tile(double* __restrict__ X, int ld, int N, double tau
                 v[m] = 0.0;
             }
         }
-        // write back only blocks that changed: the block row by row, and its
-        // mirror (X is exactly symmetric, so the mirror is the transpose)
+        // write back only blocks that changed (every block when X_0 is formed
+        // here): the block row by row, and its mirror (X is exactly
+        // symmetric, so the mirror is the transpose)
         const bool wchanged = FROM_H || __any(changed);
         if (wchanged) {
 #pragma unroll
