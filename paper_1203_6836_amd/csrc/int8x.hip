@@ -367,6 +367,7 @@ struct I8Smem {
         int8_t buf[I8Stage<S, C>::NST][2 * S * 4 * I8Stage<S, C>::KS][1024];   // [stage][((op S + slice) 4 + row block) KS + k block][block]
         double tr[64][TR_LD];                  // [tile column (one half)][tile row]
         struct {
+            double xs[128][128];                   // the X_n tile (upper-only mode), staged for the update
             unsigned long long rm[128], cm[128];   // tile row / column maxima (upper-only mode)
             double red[3][8];                      // per-wave partials, after the last use of tr / rm / cm
         } mx;
@@ -612,6 +613,20 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
         }
     }
 
+    if constexpr (UPPER) {
+        // the X_n tile to LDS in one burst (16 rows of 1 KiB per wave, all in
+        // flight at once) instead of dependent global loads inside the
+        // update; the ring is free once every wave is past its last stage
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int row = w + 8 * m;
+            __builtin_amdgcn_global_load_lds((const void*)(Xc + (size_t)(i0 + row) * ld + j0 + 2 * lane),
+                                             (__attribute__((address_space(3))) void*)&sm.mx.xs[row][0], 16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        __syncthreads();
+    }
     // epilogue: combine levels in FP64, apply the SP2 update, partials.
     // Partial sums are kept per column block c in row order and added at the
     // end, the same order in both layouts (so both give identical partials).
@@ -626,7 +641,7 @@ __device__ __forceinline__ void int8x_tile(double* __restrict__ buf0, double* __
         // s_i s_j first: the product is then the same for (i, j) and (j, i)
         // (the diagonal tiles form both), so X stays exactly symmetric
         const double p = v * (scale[gi] * sj);
-        const double x = Xc[(size_t)gi * ld + gj];
+        const double x = UPPER ? sm.mx.xs[gi - i0][gj - j0] : Xc[(size_t)gi * ld + gj];
         const double xn = br ? 2.0 * x - p : p;
         Xn[(size_t)gi * ld + gj] = xn;
         if (gi == gj) trc[c] += xn;
@@ -910,8 +925,8 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_list(double* __restrict__ bu
     }
 }
 
-// Epilogue of the split tiles: workgroup p sums the nsplit chunks of the tile
-// at visiting position t_full + p and applies the update.
+// Epilogue of the split tiles: workgroup p takes the summed chunks of the
+// tile at visiting position t_full + p and applies the update.
 template <int S, int NL, bool UPPER, int C = 0>
 __global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ buf0, double* __restrict__ buf1,
                                                          int ld, const State* __restrict__ st,
@@ -926,9 +941,38 @@ __global__ __launch_bounds__(512) void k_gemm_int8x_tail(double* __restrict__ bu
     I8Smem<S, C>& sm = *reinterpret_cast<I8Smem<S, C>*>(smem_raw);
     int bi, bj;
     order_tile(t_full + blockIdx.x, ld / QB, tile_group, bi, bj);
+    // k_chunk_sum has added the tile's chunks into its first one
     int8x_tile<S, NL, false, UPPER, C>(buf0, buf1, ld, st, digits, scale, part, bi, bj, sm, nullptr,
                                     UPPER ? rmax + (size_t)(1 - st->cur) * ld : nullptr, 2, 0, -1,
-                                    chunk_acc + (size_t)blockIdx.x * nsplit * (NL * 2 * 16 * 512), nsplit);
+                                    chunk_acc + (size_t)blockIdx.x * nsplit * (NL * 2 * 16 * 512), 1);
+}
+
+// The int32 accumulators of the nsplit K chunks of each split tile, added
+// into the tile's first chunk (exact: every partial sum over a range of K is
+// bounded like the whole sum).  kChunkSumParts workgroups per tile, each over
+// an equal share of the tile's NL x 2 x 16 x 512 accumulators, so the sums
+// are read by many CUs at once instead of by the tile's one tail workgroup.
+constexpr int kChunkSumParts = 8;
+template <int NL>
+__global__ __launch_bounds__(256) void k_chunk_sum(int* __restrict__ chunk_acc, int nsplit,
+                                                   const State* __restrict__ st, int when_full) {
+    if (st->done || st->phase != 1 || (when_full && !st->full_fill)) return;
+    constexpr int CH4 = NL * 2 * 16 * 512 / 4;          // int4 per chunk
+    constexpr int PER = CH4 / kChunkSumParts;
+    static_assert(CH4 % kChunkSumParts == 0, "chunk must split evenly");
+    const int tile = blockIdx.x / kChunkSumParts, share = blockIdx.x % kChunkSumParts;
+    int4* __restrict__ base = reinterpret_cast<int4*>(chunk_acc) + (size_t)tile * nsplit * CH4;
+    for (int e = share * PER + threadIdx.x; e < (share + 1) * PER; e += 256) {
+        int4 s = base[e];
+        for (int ch = 1; ch < nsplit; ++ch) {
+            const int4 v = base[(size_t)ch * CH4 + e];
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+        base[e] = s;
+    }
 }
 
 // Grouped: every upper-triangular tile of every system in the group; a fixed
@@ -998,9 +1042,12 @@ static hipError_t launch_tile_kernel(SplitScratch& s, double* buf0, double* buf1
     const int grid = t_full + (T - t_full) * nsplit;
     hipLaunchKernelGGL((k_gemm_int8x<S, NL, THR, UPPER, C>), dim3(grid), dim3(512), lds, stream, buf0, buf1, ld, st,
                        s.digits, s.scale, part, env, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc, when_full);
-    if (t_full < T)
+    if (t_full < T) {
+        hipLaunchKernelGGL(k_chunk_sum<NL>, dim3((T - t_full) * kChunkSumParts), dim3(256), 0, stream, s.tail_acc,
+                           nsplit, st, when_full);
         hipLaunchKernelGGL((k_gemm_int8x_tail<S, NL, UPPER, C>), dim3(T - t_full), dim3(512), lds, stream, buf0, buf1, ld,
                            st, s.digits, s.scale, part, s.rmax, s.tile_group, t_full, nsplit, s.tail_acc, when_full);
+    }
     return hipGetLastError();
 }
 
