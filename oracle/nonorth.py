@@ -41,12 +41,23 @@ the way the orthogonal oracle writes them (observables module):
   of the charge-derivative term of the paper's non-orthogonal force equation
   (at T_e = 0 and idempotent rho, W = rho H rho).  Pinned by central finite
   differences of U with rho recomputed at each displaced geometry.
+
+Finite electronic temperature in this basis (the non-orthogonal free energy
+with the entropy term of the Non-orthogonal formulation subsection): rho =
+Z f(H_perp) Z^T with f the Fermi function at the canonical mu (Tr[rho S] =
+n_occ), the free energy U - T_e S of the entropy of the occupations (Eq.
+Entropy), and the forces of the free energy: the generalized
+Hellmann-Feynman theorem for Fermi occupations gives the same expression
+with the energy-weighted W = Z f(H_perp) H_perp Z^T in place of rho H rho
+(they differ when rho is not idempotent).  Pinned by central finite
+differences of the free energy with rho and mu recomputed at each displaced
+geometry.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import eig, observables, sp2, tb
+from . import eig, fermi, observables, sp2, tb
 
 
 def overlap(pos, m):
@@ -123,14 +134,16 @@ def overlap_block_grad(dv, m):
     return -tb.sk_block_grad(dv, ms)
 
 
-def forces(pos, n, rho, m, S=None):
-    """F_k = -dU/dR_k at constant n; shape (n_atoms, 3)."""
+def forces(pos, n, rho, m, S=None, W=None):
+    """F_k = -dU/dR_k at constant n; shape (n_atoms, 3).  W: the
+    energy-weighted density matrix (default rho H rho, the T_e = 0 form)."""
     S = overlap(pos, m) if S is None else S
     q = mulliken(rho, S, m.z_val)
     F = observables.forces(pos, n, rho, m, q=q)
     H = hamiltonian(pos, n, m, S)
     v = potential(pos, n, m)
-    M = 2.0 * (rho @ H @ rho) - (v[:, None] + v[None, :]) * rho
+    W = rho @ H @ rho if W is None else W
+    M = 2.0 * W - (v[:, None] + v[None, :]) * rho
     ii, jj, d, r = tb.neighbour_pairs(pos, m.r_cut)
     for a, b, dv in zip(ii, jj, d):
         G = overlap_block_grad(dv, m)
@@ -138,3 +151,29 @@ def forces(pos, n, rho, m, S=None):
         F[b] += g
         F[a] -= g
     return F
+
+
+def fermi_density_matrix(H, S, n_occ, kT, solver="jacobi"):
+    """(rho, W, mu, f): the Fermi operator of the generalized eigenproblem
+    H c = e S c at the canonical mu (kT in eV): rho = Z f(H_perp) Z^T, and
+    the energy-weighted W = Z f(H_perp) H_perp Z^T, from the eigenpairs of
+    H_perp = Z^T H Z (Z the Loewdin factor; solver as in loewdin_factor)."""
+    Z = loewdin_factor(S, solver)
+    Hp = Z.T @ H @ Z
+    e, V = fermi.eigenpairs(0.5 * (Hp + Hp.T), solver)
+    beta = 1.0 / kT
+    mu = fermi.canonical_mu(e, n_occ, beta)
+    f = fermi.fermi_occupations(e, mu, beta)
+    C = Z @ V
+    rho = (C * f) @ C.T
+    W = (C * (f * e)) @ C.T
+    return rho, W, mu, f
+
+
+def free_energy(pos, n, m, n_occ, kT, solver="jacobi"):
+    """(A, rho, W, mu): A = U(R; n) - kT S / k_B with rho the Fermi operator
+    of H[n] in this basis."""
+    S = overlap(pos, m)
+    H = hamiltonian(pos, n, m, S)
+    rho, W, mu, f = fermi_density_matrix(H, S, n_occ, kT, solver)
+    return potential_energy(pos, n, rho, m, S) - kT * fermi.entropy(f), rho, W, mu

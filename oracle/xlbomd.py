@@ -88,12 +88,18 @@ def charges(pos, n, m, n_occ, solver="sp2"):
 
 def evaluate(pos, n, m, n_occ, solver="sp2", tol=1e-10, want_forces=True, kT=0.0):
     """One density-matrix construction at (R, n): returns dict of q, U, F, D.
-    kT > 0 (orthogonal basis): D is the Fermi operator (definition) and U the
-    free energy U - T_e S (Eq. Entropy), whose constant-n gradient the forces
-    of D are."""
+    kT > 0: D is the Fermi operator (definition; in a non-orthogonal basis
+    that of the generalized eigenproblem) and U the free energy U - T_e S
+    (Eq. Entropy), whose constant-n gradient the forces of D are."""
     if kT > 0.0:
         if _nonorth(m):
-            raise ValueError("finite electronic temperature is built for the orthogonal basis only")
+            S = nonorth.overlap(pos, m)
+            H = nonorth.hamiltonian(pos, n, m, S)
+            D, W, mu, f = nonorth.fermi_density_matrix(H, S, n_occ, kT)
+            q = nonorth.mulliken(D, S, m.z_val)
+            U = nonorth.potential_energy(pos, n, D, m, S) - kT * fermi.entropy(f)
+            F = nonorth.forces(pos, n, D, m, S, W) if want_forces else None
+            return {"q": q, "U": U, "F": F, "D": D, "H": H, "S": S, "W": W, "mu": mu}
         H = tb.hamiltonian(pos, n, m)
         D, mu, f = fermi.fermi_density(H, n_occ, kT)
         q = observables.mulliken(D, m.z_val)

@@ -109,3 +109,67 @@ def test_nonorth_energy_and_forces_reduce_to_orthogonal():
     assert np.array_equal(nonorth.hamiltonian(pos, n, m0), tb.hamiltonian(pos, n, m0))
     assert nonorth.potential_energy(pos, n, rho, m0) == observables.potential_energy(pos, n, rho, m0)
     np.testing.assert_allclose(nonorth.forces(pos, n, rho, m0), observables.forces(pos, n, rho, m0), atol=1e-12)
+
+
+def test_nonorth_finite_temperature_forces_are_free_energy_gradient():
+    """Finite electronic temperature in the non-orthogonal basis: central
+    finite differences of the free energy U - kT S (rho and the canonical mu
+    recomputed at each displaced geometry) give the forces with the
+    energy-weighted W = Z f(H_perp) H_perp Z^T; the T_e = 0 form rho H rho
+    in its place does not."""
+    m, pos, n, nocc = _md_system()
+    kT = 0.3
+    A, rho, W, mu = nonorth.free_energy(pos, n, m, nocc, kT)
+    S = nonorth.overlap(pos, m)
+    F = nonorth.forces(pos, n, rho, m, S, W)
+    F_idempotent_form = nonorth.forces(pos, n, rho, m, S)
+    h = 1e-5
+    fd = np.zeros_like(F)
+    for k in range(len(pos)):
+        for a in range(3):
+            pp = pos.copy()
+            pp[k, a] += h
+            pm = pos.copy()
+            pm[k, a] -= h
+            fd[k, a] = -(nonorth.free_energy(pp, n, m, nocc, kT)[0] - nonorth.free_energy(pm, n, m, nocc, kT)[0]) / (2 * h)
+    assert np.abs(F - fd).max() < 1e-5
+    assert np.abs(F_idempotent_form - fd).max() > 1e-3
+
+
+def test_nonorth_fermi_operator_invariants():
+    """Tr[rho S] = n_occ at the canonical mu; rho = f of the generalized
+    eigenproblem (scipy's generalized eigensolver, not the Loewdin route);
+    with S = I it is the orthogonal Fermi operator and W = rho H; as kT -> 0
+    it tends to the generalized projector."""
+    from oracle import fermi
+    m, pos, n, nocc = _md_system()
+    S = nonorth.overlap(pos, m)
+    H = nonorth.hamiltonian(pos, n, m, S)
+    kT = 0.3
+    rho, W, mu, f = nonorth.fermi_density_matrix(H, S, nocc, kT)
+    assert np.trace(rho @ S) == pytest.approx(nocc, abs=1e-9)
+    E, C = scipy.linalg.eigh(H, S)
+    fg = 1.0 / (1.0 + np.exp((E - mu) / kT))
+    np.testing.assert_allclose(rho, (C * fg) @ C.T, atol=1e-10)
+    np.testing.assert_allclose(W, (C * (fg * E)) @ C.T, atol=1e-9)
+    H0 = tb.hamiltonian(pos, n, m.with_(overlap_s0=0.0))
+    rho0, W0, mu0, _ = nonorth.fermi_density_matrix(H0, np.eye(len(H0)), nocc, kT)
+    D, mu_o, _ = fermi.fermi_density(H0, nocc, kT)
+    np.testing.assert_allclose(rho0, D, atol=1e-10)
+    assert mu0 == pytest.approx(mu_o, abs=1e-9)
+    np.testing.assert_allclose(W0, rho0 @ H0, atol=1e-9)
+    rho_cold, _, _, _ = nonorth.fermi_density_matrix(H, S, nocc, 1e-3)
+    np.testing.assert_allclose(rho_cold, _rho(pos, n, m, nocc), atol=1e-6)
+
+
+def test_xlbomd_evaluation_at_finite_temperature_in_the_nonorthogonal_basis():
+    """The integrator's evaluation at kT > 0 with an overlap is the
+    non-orthogonal free energy, its Fermi operator's charges and forces."""
+    from oracle import xlbomd
+    m, pos, n, nocc = _md_system()
+    ev = xlbomd.evaluate(pos, n, m, nocc, kT=0.3)
+    A, rho, W, mu = nonorth.free_energy(pos, n, m, nocc, 0.3)
+    assert ev["U"] == pytest.approx(A, abs=1e-12)
+    np.testing.assert_allclose(ev["D"], rho, atol=1e-14)
+    np.testing.assert_allclose(ev["q"], nonorth.mulliken(rho, nonorth.overlap(pos, m), m.z_val), atol=1e-12)
+    np.testing.assert_allclose(ev["F"], nonorth.forces(pos, n, rho, m, None, W), atol=1e-12)
