@@ -115,5 +115,9 @@ def test_xlbomd_evaluate_at_finite_temperature_is_the_free_energy():
     np.testing.assert_allclose(ev["q"], observables.mulliken(D, m.z_val), atol=1e-14)
     np.testing.assert_allclose(ev["F"], observables.forces(pos, n, D, m), atol=1e-12)
     assert abs(np.trace(D) - 2 * len(pos)) < 1e-10
-    with pytest.raises(ValueError):
-        xlbomd.evaluate(pos, n, m.with_(overlap_s0=0.05), 2 * len(pos), kT=1.5)
+    # with an overlap the evaluation is the non-orthogonal free energy (pinned
+    # in test_oracle_nonorth.py); its Fermi operator keeps Tr[D S] = n_occ
+    from oracle import nonorth
+    mo = m.with_(overlap_s0=0.05)
+    evo = xlbomd.evaluate(pos, n, mo, 2 * len(pos), kT=1.5)
+    assert abs(np.trace(evo["D"] @ nonorth.overlap(pos, mo)) - 2 * len(pos)) < 1e-9
