@@ -361,6 +361,25 @@ sp2_status sp2_fermi_density_matrix(sp2_ctx *ctx, int N, const double *H, double
 sp2_status sp2_fermi_entropy(sp2_ctx *ctx, int N, const double *H, double mu, double kT, double *S_out,
                              int *moments);
 
+/* Finite electronic temperature in a non-orthogonal basis (Non-orthogonal
+ * formulation subsection, with the Fermi function of Eq. EL_4c and the
+ * entropy of Eq. Entropy): H_perp = Z^T H Z with the Loewdin factor Z =
+ * S^(-1/2) (Eq. Congr), D_perp = the Fermi operator of H_perp by
+ * sp2_fermi_density_matrix (n_steps, max_newton, tol and mu as there; the
+ * canonical mu makes Tr[D S] = n_occ), D = Z D_perp Z^T (Eq. DM_perp).
+ * W_out (may be NULL): the energy-weighted density matrix Z D_perp H_perp
+ * Z^T, which takes the place of D H D in the forces of the free energy
+ * (tb_forces_nonorth uses D H D, the form for an idempotent D).
+ * entropy_out (may be NULL, host): S / k_B of the occupations
+ * (sp2_fermi_entropy of H_perp at the final mu).  H, S, D_out, W_out: device,
+ * N x N row-major, caller-owned; N <= 32768.  Errors as the calls it makes
+ * (SP2_ENOCONV when the factor of S or mu does not converge).  Blocks the
+ * host until done. */
+sp2_status sp2_fermi_density_matrix_nonorth(sp2_ctx *ctx, int N, const double *H, const double *S, double n_occ,
+                                            double kT, int n_steps, int max_newton, double tol, double *mu,
+                                            double *D_out, double *W_out, double *entropy_out,
+                                            int *newton_iterations);
+
 /* ---------------------------------------------------------------------
  * Tight-binding model, forces and XL-BOMD
  * ------------------------------------------------------------------- */
@@ -478,7 +497,9 @@ typedef struct {
                            the previous step's mu, |Tr D - n_occ| < fermi_tol),
                            and the record's epot is the free energy
                            U - kT S with S of sp2_fermi_entropy; 0: SP2.
-                           Orthogonal basis only (EINVAL with overlap_s0 > 0) */
+                           With overlap_s0 > 0: the density matrix, W and
+                           entropy of sp2_fermi_density_matrix_nonorth, the
+                           forces of the free energy with that W           */
     int fermi_steps;    /* recursion steps of the Fermi operator (1..60)      */
     double fermi_tol;   /* kT > 0: |Tr D - n_occ| bound of the mu solve per
                            step; 0: 1e-9 max(1, N / 512) (X_0 quantises the

@@ -129,6 +129,8 @@ _SIGS = {
     "sp2_fermi_entropy": (_I, [_P, _I, _P, _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_I)]),
     "sp2_fermi_density_matrix": (_I, [_P, _I, _P, _D, _D, _I, _I, _D, ctypes.POINTER(_D), _P,
                                       ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_longlong)]),
+    "sp2_fermi_density_matrix_nonorth": (_I, [_P, _I, _P, _P, _D, _D, _I, _I, _D, ctypes.POINTER(_D), _P, _P,
+                                              ctypes.POINTER(_D), ctypes.POINTER(_I)]),
     "tb_overlap": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P]),
     "tb_hamiltonian_nonorth": (_I, [_P, ctypes.POINTER(TBParams), _I, _P, _P, _P, _P]),
     "tb_forces_nonorth": (_I, [_P, ctypes.POINTER(TBParams), ctypes.c_double, ctypes.c_double, _I, _P, _P, _P,
@@ -354,6 +356,29 @@ class Context:
         self.last_fermi_products = prods.value
         self._check(st, "sp2_fermi_density_matrix")
         return D_out, m.value, its.value
+
+    def sp2_fermi_density_matrix_nonorth(self, H, S, n_occ: float, kT: float, n_steps: int, mu=None,
+                                         max_newton: int = 50, tol: float = 1e-10, D_out=None, W_out=None):
+        """(D, W, mu, S_entropy / k_B, passes): the Fermi operator in the
+        non-orthogonal basis of overlap S, its energy-weighted density matrix
+        and the entropy of its occupations (mu as in sp2_fermi_density_matrix)."""
+        import torch
+        N = H.shape[0]
+        if H.shape != (N, N) or S.shape != (N, N):
+            raise ValueError("H and S must be N x N")
+        if D_out is None:
+            D_out = torch.empty_like(H)
+        if W_out is None:
+            W_out = torch.empty_like(H)
+        m = _D(float("nan") if mu is None else float(mu))
+        ent = _D(0.0)
+        its = _I(0)
+        self._check(lib().sp2_fermi_density_matrix_nonorth(self._h, N, _ptr(H), _ptr(S), float(n_occ), float(kT),
+                                                           int(n_steps), int(max_newton), float(tol),
+                                                           ctypes.byref(m), _ptr(D_out), _ptr(W_out),
+                                                           ctypes.byref(ent), ctypes.byref(its)),
+                    "sp2_fermi_density_matrix_nonorth")
+        return D_out, W_out, m.value, ent.value, its.value
 
     def sp2_fermi_entropy(self, H, mu: float, kT: float):
         """(S / k_B, coefficients): -2 sum_i [f ln f + (1 - f) ln(1 - f)] of the Fermi occupations at mu."""

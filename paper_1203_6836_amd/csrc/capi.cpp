@@ -82,6 +82,10 @@ struct sp2_ctx {
     // Y / H_perp, T / D_perp, W) plus reduction slots
     double* nobuf = nullptr;
     size_t nocap = 0;
+    // non-orthogonal finite-temperature solves: Z, H_perp, D_perp kept
+    // across the Fermi-operator and entropy calls (which use nobuf)
+    double* ftbuf = nullptr;
+    size_t ftcap = 0;
     double* f64tail = nullptr; // chunk accumulators of split last-wave FP64 tiles
     size_t f64tailcap = 0;
     // qmd_evaluate scratch: H[n], D, zero charges, forces
@@ -251,7 +255,7 @@ void sp2_ctx_destroy(sp2_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     void* dev[] = {c->xbuf, c->part, c->st, c->scal, c->chk, c->V, c->eatom, c->qtmp, c->env, c->tz,
-                   c->eH, c->eD, c->ezero, c->eF, c->f64tail, c->nobuf, c->stage};
+                   c->eH, c->eD, c->ezero, c->eF, c->f64tail, c->nobuf, c->ftbuf, c->stage};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     split_free(c->split);
@@ -898,21 +902,13 @@ static sp2_status prod(sp2_ctx* c, int N, const double* A, const double* B, doub
 
 constexpr int kNsMaxIter = 40;
 
-extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double* H, const double* S, int n_occ,
-                                                  const sp2_options* opt, double* D_out, sp2_stats* stats,
-                                                  int* factor_iterations) {
-    CTX_ENTER(c);
-    if (!c) return SP2_EINVAL;
-    if (stats) std::memset(stats, 0, sizeof(*stats));
-    if (factor_iterations) *factor_iterations = 0;
-    if (N < 1 || N > 65536 || !H || !S || !D_out) return fail(c, SP2_EINVAL, "bad non-orthogonal solve arguments");
-    if (n_occ <= 0 || n_occ >= N) return fail(c, SP2_EINVAL, "need 0 < n_occ < N");
-    sp2_options o;
-    if (opt) o = *opt;
-    else sp2_options_default(&o);
-    sp2_status s = check_options(c, o, N);
-    if (s != SP2_OK) return s;
-    HIPCHK(c, hipSetDevice(c->device));
+// Loewdin factor Z = S^(-1/2) (Eq. Congr) of an N x N overlap by the coupled
+// Newton-Schulz iteration, in the context's nobuf: *Z is the factor, *F1 ..
+// *F3 the other three N x N work buffers (free for the caller until nobuf
+// is next grown); *iters the iterations.
+static sp2_status loewdin_factor(sp2_ctx* c, int N, const double* S, double** Zout, double** F1, double** F2,
+                                 double** F3, int* iters) {
+    sp2_status s;
     const size_t n2 = (size_t)N * N;
     size_t nb = c->nocap;
     if ((s = grow(c, (void**)&c->nobuf, &nb, (4 * n2 + kNsBlocks + 64) * sizeof(double))) != SP2_OK) return s;
@@ -925,7 +921,6 @@ extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double
     double* res = part + kNsBlocks;
     unsigned long long* mx = reinterpret_cast<unsigned long long*>(res + 8);
     hipStream_t st = c->stream;
-    // Loewdin factor Z = S^(-1/2) (Eq. Congr) by the coupled Newton-Schulz iteration
     HIPCHK(c, launch_zero_word(mx, st));
     HIPCHK(c, launch_row_abs_max(S, N, mx, st));
     HIPCHK(c, launch_ns_init(S, N, mx, Y, Zm, st));
@@ -951,9 +946,37 @@ extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double
         if ((s = prod(c, N, T, Zm, W, true)) != SP2_OK) return s;        // Z_{k+1} = T_k Z_k
         std::swap(Zm, W);
     }
-    if (factor_iterations) *factor_iterations = it + 1;
+    *iters = it + 1;
     if (!converged) return fail(c, SP2_ENOCONV, "inverse factor of S did not converge (S not positive definite?)");
     HIPCHK(c, launch_scale_inv_sqrt(Zm, N, mx, st));
+    *Zout = Zm;
+    *F1 = Y;
+    *F2 = T;
+    *F3 = W;
+    return SP2_OK;
+}
+
+extern "C" sp2_status sp2_density_matrix_nonorth(sp2_ctx* c, int N, const double* H, const double* S, int n_occ,
+                                                  const sp2_options* opt, double* D_out, sp2_stats* stats,
+                                                  int* factor_iterations) {
+    CTX_ENTER(c);
+    if (!c) return SP2_EINVAL;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (factor_iterations) *factor_iterations = 0;
+    if (N < 1 || N > 65536 || !H || !S || !D_out) return fail(c, SP2_EINVAL, "bad non-orthogonal solve arguments");
+    if (n_occ <= 0 || n_occ >= N) return fail(c, SP2_EINVAL, "need 0 < n_occ < N");
+    sp2_options o;
+    if (opt) o = *opt;
+    else sp2_options_default(&o);
+    sp2_status s = check_options(c, o, N);
+    if (s != SP2_OK) return s;
+    HIPCHK(c, hipSetDevice(c->device));
+    double *Zm, *Y, *T, *W;
+    int it = 0;
+    s = loewdin_factor(c, N, S, &Zm, &Y, &T, &W, &it);
+    if (factor_iterations) *factor_iterations = it;
+    if (s != SP2_OK) return s;
+    hipStream_t st = c->stream;
     // H_perp = Z^T H Z (Z symmetric): W = H Z, then H_perp = W^T Z, formed
     // as a symmetric product (exactly symmetric)
     double* Hp = Y;
@@ -1216,6 +1239,56 @@ extern "C" sp2_status sp2_fermi_entropy(sp2_ctx* c, int N, const double* H, doub
     return SP2_OK;
 }
 
+// Finite electronic temperature in the non-orthogonal basis: the Fermi
+// operator of H_perp = Z^T H Z (Z the Loewdin factor) at the canonical mu,
+// rho = Z f(H_perp) Z^T, the energy-weighted W = Z f(H_perp) H_perp Z^T of
+// the free-energy forces, and the entropy of the occupations.
+extern "C" sp2_status sp2_fermi_density_matrix_nonorth(sp2_ctx* c, int N, const double* H, const double* S,
+                                                        double n_occ, double kT, int n_steps, int max_newton,
+                                                        double tol, double* mu, double* D_out, double* W_out,
+                                                        double* entropy_out, int* newton_iterations) {
+    CTX_ENTER(c);
+    if (!c) return SP2_EINVAL;
+    if (newton_iterations) *newton_iterations = 0;
+    if (N < 1 || N > 32768 || !H || !S || !D_out || !mu)
+        return fail(c, SP2_EINVAL, "bad non-orthogonal Fermi-operator arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n2 = (size_t)N * N;
+    sp2_status s;
+    size_t fb = c->ftcap;
+    if ((s = grow(c, (void**)&c->ftbuf, &fb, 3 * n2 * sizeof(double))) != SP2_OK) return s;
+    c->ftcap = fb;
+    double* Zf = c->ftbuf;
+    double* Hp = Zf + n2;
+    double* Dp = Hp + n2;
+    double *Zm, *F1, *F2, *F3;
+    int it = 0;
+    if ((s = loewdin_factor(c, N, S, &Zm, &F1, &F2, &F3, &it)) != SP2_OK) return s;
+    hipStream_t st = c->stream;
+    // Z and H_perp = Z^T H Z kept outside nobuf, which the Fermi operator and
+    // the entropy reuse
+    HIPCHK(c, hipMemcpyAsync(Zf, Zm, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if ((s = prod(c, N, H, Zf, F1, false)) != SP2_OK) return s;
+    if ((s = prod(c, N, F1, Zf, Hp, true)) != SP2_OK) return s;
+    if ((s = sp2_fermi_density_matrix(c, N, Hp, n_occ, kT, n_steps, max_newton, tol, mu, Dp, newton_iterations,
+                                      nullptr)) != SP2_OK)
+        return s;
+    if (entropy_out && (s = sp2_fermi_entropy(c, N, Hp, *mu, kT, entropy_out, nullptr)) != SP2_OK) return s;
+    double* tmp = c->nobuf;   // at least 3 N x N after the calls above
+    // rho = Z D_perp Z^T
+    if ((s = prod(c, N, Dp, Zf, tmp, false)) != SP2_OK) return s;
+    if ((s = prod(c, N, tmp, Zf, D_out, true)) != SP2_OK) return s;
+    if (W_out) {
+        // W = Z (D_perp H_perp) Z^T; D_perp and H_perp commute, so their
+        // product is symmetric
+        if ((s = prod(c, N, Dp, Hp, tmp, true)) != SP2_OK) return s;
+        if ((s = prod(c, N, tmp, Zf, Dp, false)) != SP2_OK) return s;
+        if ((s = prod(c, N, Dp, Zf, W_out, true)) != SP2_OK) return s;
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    return SP2_OK;
+}
+
 extern "C" sp2_status sp2_mulliken_overlap(sp2_ctx* c, int n_atoms, const double* D, const double* S, double z_val,
                                            double* q_out) {
     CTX_ENTER(c);
@@ -1406,11 +1479,12 @@ static sp2_status forces_impl(sp2_ctx* c, const tb_params* p, int nat, const dou
 }
 
 // Non-orthogonal forces at constant n: the orthogonal terms with the overlap
-// charges q, plus sum_ab M_ab dS_ab/dR_k with M = 2 D H D - (V_a + V_b) D_ab;
-// U to the device slot U_dev.
+// charges q, plus sum_ab M_ab dS_ab/dR_k with M = 2 W - (V_a + V_b) D_ab, W
+// the energy-weighted density matrix (Wen; NULL: D H D, its form for an
+// idempotent D); U to the device slot U_dev.
 static sp2_status tb_forces_nonorth_impl(sp2_ctx* c, const tb_params* p, double s0, double lam_s, int n_atoms,
                                          const double* xyz, const double* D, const double* H, const double* q,
-                                         const double* n, double* F, double* U_dev) {
+                                         const double* n, double* F, double* U_dev, const double* Wen = nullptr) {
     sp2_status s = ensure_atoms(c, n_atoms);
     if (s != SP2_OK) return s;
     const int N = 4 * n_atoms;
@@ -1422,9 +1496,14 @@ static sp2_status tb_forces_nonorth_impl(sp2_ctx* c, const tb_params* p, double 
     double* W2 = W1 + n2;
     // orthogonal terms (band with h, Coulomb with q, pair) and U; V = gamma n
     if ((s = forces_impl(c, p, n_atoms, xyz, D, q, n, F, U_dev)) != SP2_OK) return s;
-    // energy-weighted density matrix D H D (= (H D)^T D), then M in place
-    if ((s = prod(c, N, H, D, W1, false)) != SP2_OK) return s;
-    if ((s = prod(c, N, W1, D, W2, true)) != SP2_OK) return s;
+    // energy-weighted density matrix D H D (= (H D)^T D), or the one given,
+    // then M in place
+    if (Wen) {
+        HIPCHK(c, hipMemcpyAsync(W2, Wen, n2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        if ((s = prod(c, N, H, D, W1, false)) != SP2_OK) return s;
+        if ((s = prod(c, N, W1, D, W2, true)) != SP2_OK) return s;
+    }
     HIPCHK(c, launch_force_matrix(W2, D, c->V, n_atoms, c->stream));
     HIPCHK(c, launch_forces_overlap(xyz, n_atoms, make_radial(s0, p->r0, lam_s, p->r_tail, p->r_cut), W2, F,
                                     c->stream));
@@ -1533,6 +1612,7 @@ struct xlbomd {
     int n_occ;            // doubly occupied states: z_val n_atoms / 2
     double *xyz, *vel, *F, *q, *hist, *H, *D, *dev, *dscal;
     double* S = nullptr;  // overlap (non-orthogonal basis only)
+    double* Wen = nullptr;  // energy-weighted density matrix (non-orthogonal basis at kT > 0)
     double mu = NAN;      // chemical potential of the last Fermi operator (kT > 0)
     double ts = 0.0;      // kT S of the last Fermi operator
     int head;
@@ -1550,6 +1630,27 @@ static sp2_status md_evaluate(xlbomd* m, int* iters, bool with_forces = true, fl
     sp2_status s = tb_hamiltonian(c, &m->p, nat, m->xyz, n_t, m->H);
     if (s != SP2_OK) return s;
     sp2_stats st;
+    if (m->o.kT > 0.0 && m->S) {
+        // finite electronic temperature in the non-orthogonal basis: overlap,
+        // H[n] with it, the Fermi operator of H_perp (canonical mu), its
+        // entropy, charges with S and the free-energy forces with W
+        if ((s = tb_overlap(c, &m->p, m->o.overlap_s0, m->o.overlap_lam, nat, m->xyz, m->S)) != SP2_OK) return s;
+        if ((s = tb_hamiltonian_nonorth(c, &m->p, nat, m->xyz, n_t, m->S, m->H)) != SP2_OK) return s;
+        int passes = 0;
+        double Se = 0.0;
+        if ((s = sp2_fermi_density_matrix_nonorth(c, N, m->H, m->S, (double)m->n_occ, m->o.kT, m->o.fermi_steps,
+                                                  m->o.fermi_max_newton, m->o.fermi_tol, &m->mu, m->D, m->Wen,
+                                                  &Se, &passes)) != SP2_OK)
+            return s;
+        m->ts = m->o.kT * Se;
+        m->dm_count += 1;
+        if (iters) *iters = passes;
+        if (fill) *fill = 1.0f;
+        HIPCHK(c, launch_mulliken_overlap(m->D, m->S, nat, m->p.z_val, m->q, c->stream));
+        if (!with_forces) return SP2_OK;
+        return tb_forces_nonorth_impl(c, &m->p, m->o.overlap_s0, m->o.overlap_lam, nat, m->xyz, m->D, m->H, m->q,
+                                      n_t, m->F, m->dscal, m->Wen);
+    }
     if (m->o.kT > 0.0) {
         // finite electronic temperature: the Fermi operator at the canonical mu
         // (from the previous step's), its entropy, charges and forces
@@ -1614,8 +1715,8 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
     if (o->K < 1 || o->K > 8 || !(o->dt_fs > 0) || !(p->mass > 0) || !(o->diverge_q >= 0))
         return fail(c, SP2_EINVAL, "bad xlbomd options");
     if (!(o->kT >= 0.0) || !std::isfinite(o->kT) ||
-        (o->kT > 0.0 && (o->fermi_steps < 1 || o->fermi_steps > 60 || o->overlap_s0 != 0.0)))
-        return fail(c, SP2_EINVAL, "kT > 0 needs 1 <= fermi_steps <= 60 and the orthogonal basis");
+        (o->kT > 0.0 && (o->fermi_steps < 1 || o->fermi_steps > 60)))
+        return fail(c, SP2_EINVAL, "kT > 0 needs 1 <= fermi_steps <= 60");
     if (!(o->overlap_s0 >= 0.0) || (o->overlap_s0 > 0.0 && !(o->overlap_lam > 0.0)))
         return fail(c, SP2_EINVAL, "bad overlap parameters");
     if (!(o->fermi_tol >= 0.0) || !std::isfinite(o->fermi_tol) || o->fermi_max_newton < 0 ||
@@ -1645,6 +1746,8 @@ extern "C" sp2_status xlbomd_create(sp2_ctx* c, const tb_params* p, const xlbomd
     ok = ok && hipMalloc((void**)&m->D, N * N * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void**)&m->dscal, 8 * sizeof(double)) == hipSuccess;
     if (o->overlap_s0 > 0.0) ok = ok && hipMalloc((void**)&m->S, N * N * sizeof(double)) == hipSuccess;
+    if (o->overlap_s0 > 0.0 && o->kT > 0.0)
+        ok = ok && hipMalloc((void**)&m->Wen, N * N * sizeof(double)) == hipSuccess;
     if (!ok) {
         xlbomd_destroy(m);
         return fail(c, SP2_ENOMEM, "xlbomd allocation failed");
@@ -1880,7 +1983,7 @@ extern "C" void xlbomd_destroy(xlbomd* m) {
     if (!m) return;
     (void)hipSetDevice(m->c->device);
     (void)hipStreamSynchronize(m->c->stream);
-    double* bufs[] = {m->xyz, m->vel, m->F, m->q, m->dev, m->hist, m->H, m->D, m->dscal, m->S};
+    double* bufs[] = {m->xyz, m->vel, m->F, m->q, m->dev, m->hist, m->H, m->D, m->dscal, m->S, m->Wen};
     for (double* b : bufs)
         if (b) (void)hipFree(b);
     delete m;

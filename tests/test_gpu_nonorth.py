@@ -1,6 +1,6 @@
-"""Non-orthogonal formulation on the GPU (Loewdin factor by Newton-Schulz over
-rocBLAS GEMMs, SP2 of Z^T H Z, rho = Z rho_perp Z^T, Mulliken charges with S)
-against the oracle."""
+"""Non-orthogonal formulation on the GPU (Loewdin factor by Newton-Schulz on
+the project's FP64 product kernel, SP2 or the Fermi operator of Z^T H Z,
+rho = Z rho_perp Z^T, Mulliken charges with S) against the oracle."""
 import sys
 import time
 
@@ -200,6 +200,64 @@ def test_nonorth_xlbomd_trajectory_matches_oracle(ctx):
     np.testing.assert_allclose(v, ost.vel, atol=1e-9)
     np.testing.assert_allclose(n, ost.hist[0], atol=1e-9)
     assert de < 1e-7
+
+
+@pytest.mark.parametrize("dims,seed,kT", [((3, 3, 3), 2, 0.5), ((4, 4, 4), 7, 0.25)])
+def test_nonorth_fermi_operator_matches_oracle(ctx, dims, seed, kT):
+    """Finite electronic temperature in the non-orthogonal basis: D = Z f(H_perp)
+    Z^T at the canonical mu, the energy-weighted W = Z f(H_perp) H_perp Z^T and
+    the entropy, against the oracle's definition (generalized eigenpairs);
+    the recursion's error bound as for the orthogonal Fermi operator."""
+    from oracle import fermi
+    w, H, S = system(dims, seed)
+    say(f"case nonorth fermi N={w.n_orb} kT={kT}")
+    rho, W, mu_o, f = nonorth.fermi_density_matrix(H, S, w.n_occ, kT)
+    D, Wg, mu, ent, passes = ctx.sp2_fermi_density_matrix_nonorth(to_dev(H), to_dev(S), w.n_occ, kT, 16, tol=1e-9)
+    D, Wg = D.cpu().numpy(), Wg.cpu().numpy()
+    eD, eW = float(np.abs(D - rho).max()), float(np.abs(Wg - W).max())
+    ent_o = fermi.entropy(f)
+    say(f"  passes {passes}, mu {mu:.10f} (oracle {mu_o:.10f}), max|D - rho| {eD:.1e}, max|W - W_o| {eW:.1e}, "
+        f"S/kB {ent:.8f} (oracle {ent_o:.8f}), Tr[D S] - n_occ {np.trace(D @ S) - w.n_occ:+.1e}")
+    assert abs(mu - mu_o) < 1e-8
+    assert eD < 1e-8 and eW < 1e-7
+    assert abs(np.trace(D @ S) - w.n_occ) < 1e-8
+    assert abs(ent - ent_o) < 1e-8 * max(1.0, abs(ent_o))
+
+
+def test_nonorth_finite_temperature_xlbomd_matches_oracle(ctx):
+    """XL-BOMD at kT = 0.5 eV in the non-orthogonal basis (overlap, H[n], the
+    Fermi operator of H_perp, its entropy in the free energy, the free-energy
+    forces with the energy-weighted W): 20 steps of the 2 x 2 x 2 cluster from
+    self-consistent finite-T charges against the oracle integrator."""
+    import paper_1203_6836_amd as p
+    from oracle import xlbomd as oxl
+    say("case nonorth fermi xlbomd 2x2x2 20 steps kT=0.5")
+    m = synth.MD_MODEL.with_(overlap_s0=0.05)
+    pos = synth.lattice_positions((2, 2, 2), seed=21)
+    nat, nocc = len(pos), 2 * len(pos)
+    vel = synth.maxwell_velocities(nat, 300.0, m.mass, seed=5)
+    n0 = np.zeros(nat)
+    for _ in range(2000):   # finite-T SCF by linear mixing
+        q = oxl.evaluate(pos, n0, m, nocc, want_forces=False, kT=0.5)["q"]
+        if np.abs(q - n0).max() < 1e-11:
+            break
+        n0 = n0 + 0.1 * (q - n0)
+    assert np.abs(q - n0).max() < 1e-11
+    opts = oxl.XLOptions(kT=0.5, kappa=p.KAPPA_FINITE_T)
+    ost, olog = oxl.run(oxl.init_state(pos, vel, m, nocc, opts, n0), m, nocc, opts, 20)
+    md = ctx.xlbomd_create(m, pos, vel, n0, dt_fs=opts.dt_fs, kappa=opts.kappa, alpha=opts.alpha,
+                           c=opts.c, sp2_opts=p.options("fp64"), kT=0.5, fermi_steps=16)
+    glog = md.xlbomd_run(20)
+    xyz, v, q, n = md.xlbomd_get()
+    md.close()
+    eg = np.array([r["etot"] for r in glog])
+    eo = np.array([r["etot"] for r in olog])
+    say(f"  max|dx| {np.abs(xyz - ost.pos).max():.1e} A, max|dE_tot| {np.abs(eg - eo).max():.1e} eV, "
+        f"E_tot spread {np.ptp(eo) / nat:.1e} eV/atom")
+    np.testing.assert_allclose(xyz, ost.pos, atol=1e-9)
+    np.testing.assert_allclose(v, ost.vel, atol=1e-9)
+    np.testing.assert_allclose(n, ost.hist[0], atol=2e-8)
+    assert np.abs(eg - eo).max() < 1e-7
 
 
 def quench(md, nat, max_steps=1500, ftol=1e-6):
