@@ -58,8 +58,13 @@ typedef enum {
                             products of planes t, u with level t+u < levels
                             on int8 MFMA with exact int32 accumulation,
                             levels combined in FP64 (the Ozaki scheme)       */
-    SP2_PREC_BF16X2 = 2  /* BF16 hi+lo split with FP32 MFMA accumulation, FP32
-                            master, then `fp32_tail` FP32 iterations            */
+    SP2_PREC_BF16X2 = 2, /* BF16 hi+lo split with FP32 MFMA accumulation, FP32
+                            master, then `fp32_tail` FP32 products (as in
+                            SP2_PREC_FP32) once the BF16 stage stalls            */
+    SP2_PREC_FP32 = 3    /* FP32 operands (X_0 rounded to FP32) on FP32 MFMA with
+                            FP32 accumulation, update in FP32; stops at the
+                            FP32 rounding floor by the stall rule with r = 1/2.
+                            No threshold (tau = 0)                           */
 } sp2_precision;
 
 typedef struct {
@@ -69,8 +74,8 @@ typedef struct {
     double stall_tol;    /* also stop when n >= 4, e_n >= r e_{n-2}, e_n <
                             stall_tol (idempotency error at its floor; 1e-2);
                             r = 1 for FP64 and BF16X2 products without a
-                            threshold; r = 1/2 for INT8X products (their
-                            rounding floor) and whenever tau > 0, where the
+                            threshold; r = 1/2 for INT8X and FP32 products
+                            (their rounding floor) and whenever tau > 0, where the
                             bound is also max(stall_tol, 0.1) (the floor set
                             by the threshold keeps creeping down and grows
                             with N) */

@@ -26,8 +26,8 @@ SP2_EBUDGET, SP2_EBUSY, SP2_ETIMEOUT, SP2_EDIVERGE = -6, -7, -8, -9
 SP2_MEM_HOST, SP2_MEM_DEVICE = 0, 1
 # bytes before the FP64 arrays (xyz, vel, F, q, n history) of an xlbomd checkpoint
 XL_CHECKPOINT_HEADER = 72
-PREC_FP64, PREC_INT8X, PREC_BF16X2 = 0, 1, 2
-PRECISIONS = {"fp64": PREC_FP64, "int8x": PREC_INT8X, "bf16x2": PREC_BF16X2}
+PREC_FP64, PREC_INT8X, PREC_BF16X2, PREC_FP32 = 0, 1, 2, 3
+PRECISIONS = {"fp64": PREC_FP64, "int8x": PREC_INT8X, "bf16x2": PREC_BF16X2, "fp32": PREC_FP32}
 
 
 class Sp2Options(ctypes.Structure):

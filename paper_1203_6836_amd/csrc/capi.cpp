@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/sp2qmd.h"
+#include "f32_internal.h"
 #include "fermi_internal.h"
 #include "gemm_internal.h"
 #include "noalloc_internal.h"
@@ -291,7 +292,7 @@ sp2_status sp2_ctx_set_profiling(sp2_ctx* c, int on) {
 
 // ----------------------------------------------------------------- SP2 solve
 static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
-    if (o.precision < SP2_PREC_FP64 || o.precision > SP2_PREC_BF16X2)
+    if (o.precision < SP2_PREC_FP64 || o.precision > SP2_PREC_FP32)
         return fail(c, SP2_EINVAL, "unknown precision");
     if (o.max_iter < 1 || o.max_iter > kMaxIter)
         return fail(c, SP2_EINVAL, "max_iter must be in [1, 128]");
@@ -308,10 +309,17 @@ static sp2_status check_options(sp2_ctx* c, const sp2_options& o, int N) {
     if (o.tail_split < -1 || o.tail_split > 1) return fail(c, SP2_EINVAL, "tail_split must be -1, 0 or 1");
     if (o.threshold < 0 || o.threshold > 1) return fail(c, SP2_EINVAL, "threshold must be 0 (block) or 1 (element)");
     if (!(o.dense_fill >= 0.0)) return fail(c, SP2_EINVAL, "dense_fill must be >= 0");
-    if (o.tau > 0.0 && o.precision == SP2_PREC_BF16X2)
+    if (o.tau > 0.0 && (o.precision == SP2_PREC_BF16X2 || o.precision == SP2_PREC_FP32))
         return fail(c, SP2_EINVAL, "block thresholding runs with FP64 or INT8X products");
     (void)N;
     return SP2_OK;
+}
+
+// Whether a solve with these options forms any product on the FP64 kernel:
+// the FP64 mode, and the FP64 head of INT8X and BF16X2.
+static bool fp64_products(const sp2_options& o) {
+    return o.precision == SP2_PREC_FP64 ||
+           ((o.precision == SP2_PREC_INT8X || o.precision == SP2_PREC_BF16X2) && o.fp64_head > 0);
 }
 
 // Device scratch of one SP2 solve: the two padded X buffers (2 ld^2 doubles),
@@ -393,9 +401,9 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     SolveScratch sc;
     sc.xbuf = c->xbuf;
     sc.part = c->part;
-    // the FP64 product runs in FP64 mode, in the FP64 head of INT8X and in the
-    // FP32 tail of BF16X2
-    if (!int8x || o.fp64_head > 0)
+    // the FP64 product runs in FP64 mode and in the FP64 head of INT8X and
+    // BF16X2
+    if (fp64_products(o))
         if ((s = f64_tail_buffer(c, ld, o.tail_split, &sc.f64tail, &sc.f64tail_bytes)) != SP2_OK) return s;
     if (o.tau > 0.0) {
         size_t eb = c->envcap;
@@ -425,6 +433,8 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
     double* part = sc.part;
     const bool int8x = o.precision == SP2_PREC_INT8X;
     const bool bf16x = o.precision == SP2_PREC_BF16X2;
+    const bool fp32 = o.precision == SP2_PREC_FP32;
+    const bool f64p = fp64_products(o);
     // int8 products from the first one on, no threshold: the products write
     // their upper tiles only and the encode reads the upper triangle
     const bool upper = int8x && o.tau == 0.0 && o.fp64_head == 0;
@@ -451,11 +461,11 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
     // rounding floor is detected the same way (an error that fails to halve
     // over two products has reached it)
     a.stall_tol = o.tau > 0.0 ? std::max(o.stall_tol, 0.1) : o.stall_tol;
-    a.stall_ratio = (o.tau > 0.0 || int8x) ? 0.5 : 1.0;
+    a.stall_ratio = (o.tau > 0.0 || int8x || fp32) ? 0.5 : 1.0;
     a.max_iter = o.max_iter;
     a.fp64_head = (int8x || bf16x) ? o.fp64_head : -1;
     a.fp32_tail = o.fp32_tail;
-    a.mixed = int8x ? 1 : (bf16x ? 2 : 0);
+    a.mixed = int8x ? 1 : (bf16x ? 2 : (fp32 ? 3 : 0));
     const double nb = (double)((N + 31) / 32);
     a.total_blocks = o.tau > 0.0 ? nb * nb : 0.0;
 
@@ -494,10 +504,12 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
             if (pe) HIPCHK(c, hipEventRecord(pe[0], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
-            HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, part, &ns, st, env, tile_group, f64tail,
-                                      f64tail_bytes, f64c.split_cap, f64_small));
+            if (f64p)
+                HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, part, &ns, st, env, tile_group, f64tail,
+                                          f64tail_bytes, f64c.split_cap, f64_small));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, part, &ns, st, env));
+            if (bf16x || fp32) HIPCHK(c, launch_gemm_f32(buf0, buf1, ld, c->st, part, &ns, tile_group, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
             if (o.tau > 0.0)
                 HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, part, &ns, 0, st,
@@ -741,7 +753,7 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         HIPCHK(c, hipMemcpy(c->split.rmax, half.data(), half.size() * sizeof(bits), hipMemcpyHostToDevice));
     }
     std::memset(c->st_host, 0, sizeof(State));
-    c->st_host->phase = precision == SP2_PREC_FP64 ? 0 : 1;
+    c->st_host->phase = precision == SP2_PREC_FP64 ? 0 : (precision == SP2_PREC_FP32 ? 2 : 1);
     HIPCHK(c, hipMemcpyAsync(c->st, c->st_host, sizeof(State), hipMemcpyHostToDevice, st));
     double* f64tail = nullptr;
     size_t f64tail_bytes = 0;
@@ -780,7 +792,9 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         cand.push_back(t);
     }
     // about 40 ms of products per candidate, at least 3
-    const double est_ms = (precision == SP2_PREC_FP64 ? 1.0 / 40e9 : 1.0 / 1.2e12) * (double)ld * ld * ld;
+    const double est_ms = (precision == SP2_PREC_FP64 ? 1.0 / 40e9
+                           : precision == SP2_PREC_FP32 ? 1.0 / 80e9
+                                                        : 1.0 / 1.2e12) * (double)ld * ld * ld;
     const int reps = std::max(3, std::min(40, (int)(40.0 / std::max(est_ms, 1e-3))));
     auto launch = [&](const TuneChoice& t) -> sp2_status {
         int ns = 0;
@@ -789,6 +803,8 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         if (precision == SP2_PREC_FP64) {
             HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, t.tile_group, f64tail,
                                       f64tail_bytes, t.split_cap, t.tile == 32));
+        } else if (precision == SP2_PREC_FP32) {
+            HIPCHK(c, launch_gemm_f32(buf0, buf1, ld, c->st, c->part, &ns, t.tile_group, st));
         } else {
             HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, nullptr));
@@ -868,7 +884,7 @@ extern "C" sp2_status sp2_tune_load(sp2_ctx* c, const char* path) {
             return fail(c, SP2_EINVAL, "malformed autotuner table line: " + line);
         // entries of another device type, or out of range, are skipped
         if (arch != c->arch || cus != c->cus) continue;
-        if (ld < kTile || ld % kTile || prec < SP2_PREC_FP64 || prec > SP2_PREC_BF16X2 || t.tile_group < 0 ||
+        if (ld < kTile || ld % kTile || prec < SP2_PREC_FP64 || prec > SP2_PREC_FP32 || t.tile_group < 0 ||
             t.tile_group > 64 || t.stage_cfg < 0 || t.stage_cfg > 2 || (t.stage_cfg == 2 && slices > 5) ||
             t.split_cap < 2 || t.split_cap > 16 || levels < 0 || levels > slices + 1 ||
             !(t.tile == 128 || (t.tile == 32 && prec == SP2_PREC_FP64 && ld <= kSmallMaxLd)))

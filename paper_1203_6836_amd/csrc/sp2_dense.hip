@@ -260,7 +260,9 @@ __global__ __launch_bounds__(256) void k_ctrl_init(const double* __restrict__ pa
         const int b = choose_branch(r[0], r[1], a.n_occ);
         st->branch = b;
         set_bit(st, 0, b);
-        st->phase = (a.mixed != 0 && a.fp64_head == 0) ? 1 : 0;
+        // phase 0: FP64 products; 1: the reduced-precision (int8 or BF16)
+        // products; 2: FP32 products (mixed 3 throughout)
+        st->phase = a.mixed == 3 ? 2 : ((a.mixed != 0 && a.fp64_head == 0) ? 1 : 0);
         if (st->phase == 1) st->head_switch = 0;
     }
 }
@@ -283,7 +285,7 @@ __device__ __forceinline__ void ctrl_step_body(const double* __restrict__ part, 
     const double f = take_fill(st, a);
     if (f >= 0.0) st->fill[n] = (float)f;
     st->iter = n + 1;
-    if (st->phase != 1) st->fp64_products += 1;   // FP64-kernel products (head or FP32 tail)
+    if (st->phase == 0) st->fp64_products += 1;   // FP64 products (the whole solve, or the head)
     const bool stall = n >= 4 && e >= a.stall_ratio * st->idem[n - 2] && e < a.stall_tol;
     // BF16X2 runs its own schedule: a stall of the BF16 stage starts a fixed
     // FP32 tail instead of stopping
@@ -391,9 +393,6 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
                                          const State* __restrict__ st, double* __restrict__ part,
                                          const int* __restrict__ env, int bi, int bj, int kmode, int kc0,
                                          int kc1, double* __restrict__ chunk, int nchunks) {
-    // phase 0: FP64 products; phase 2: the FP32 tail of the BF16 hi+lo mode
-    // (FP32-valued operands, update rounded to FP32)
-    const bool r32 = st->phase == 2;
     const int nt = ld / GB;
     const int t = tri_index(bi, bj, nt);
     const double* __restrict__ Xc = st->cur ? buf1 : buf0;
@@ -513,11 +512,10 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
     const int br = st->branch;
     const bool mirror = bi != bj;
     double tr = 0.0, fro = 0.0, idm = 0.0;
-    // one straight-line body per (FP32 rounding, mirrored) pair: both flags
-    // are uniform, and branching on them per element keeps many values live
-    // across blocks
-    auto epilogue = [&](auto r32c, auto mirc) {
-        constexpr bool R32 = decltype(r32c)::value, MIR = decltype(mirc)::value;
+    // one straight-line body per mirrored flag: it is uniform, and branching
+    // on it per element keeps many values live across blocks
+    auto epilogue = [&](auto mirc) {
+        constexpr bool MIR = decltype(mirc)::value;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
 #pragma unroll
@@ -529,11 +527,7 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
                     const int gi = i0 + wi * 64 + m * 16 + (lane >> 4) + 4 * r;
                     const double p = acc[m][n][r];
                     const double x = Xc[(size_t)gi * ld + gj];
-                    double xn = br ? 2.0 * x - p : p;
-                    if constexpr (R32) {
-                        const float pf = (float)p, xf = (float)x;
-                        xn = (double)(br ? 2.0f * xf - pf : pf);
-                    }
+                    const double xn = br ? 2.0 * x - p : p;
                     Xn[(size_t)gi * ld + gj] = xn;
                     if constexpr (MIR) Xn[(size_t)gj * ld + gi] = xn;
                     tr += gi == gj ? xn : 0.0;
@@ -543,15 +537,8 @@ __device__ __forceinline__ void f64_tile(double* __restrict__ buf0, double* __re
             }
         }
     };
-    using T_ = std::true_type;
-    using F_ = std::false_type;
-    if (r32) {
-        if (mirror) epilogue(T_{}, T_{});
-        else epilogue(T_{}, F_{});
-    } else {
-        if (mirror) epilogue(F_{}, T_{});
-        else epilogue(F_{}, F_{});
-    }
+    if (mirror) epilogue(std::true_type{});
+    else epilogue(std::false_type{});
     const double wgt = mirror ? 2.0 : 1.0;
     __shared__ double sh[4];
     const double btr = block_sum256(tr, sh);
@@ -580,7 +567,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
                                                      double* __restrict__ part,
                                                      const int* __restrict__ env, int tile_group, int t_full,
                                                      int nsplit, double* __restrict__ chunk) {
-    if (st->done || (st->phase != 0 && st->phase != 2)) return;
+    if (st->done || st->phase != 0) return;
     const int nt = ld / GB, w = blockIdx.x;
     int pos, kmode = 0, kc0 = 0, kc1 = -1;
     double* cacc = nullptr;
@@ -611,8 +598,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(double* __restrict__ buf0,
 __global__ __launch_bounds__(256) void k_gemm_f64_small(double* __restrict__ buf0, double* __restrict__ buf1,
                                                         int ld, const State* __restrict__ st,
                                                         double* __restrict__ part) {
-    if (st->done || (st->phase != 0 && st->phase != 2)) return;
-    const bool r32 = st->phase == 2;
+    if (st->done || st->phase != 0) return;
     const int nts = ld / SB;
     int t = blockIdx.x, bi = 0;
     while (t >= nts - bi) {
@@ -659,11 +645,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64_small(double* __restrict__ buf
         const double p = ((red[0][r][c] + red[1][r][c]) + red[2][r][c]) + red[3][r][c];
         const int gi = i0 + r, gj = j0 + c;
         const double x = Xc[(size_t)gi * ld + gj];
-        double xn = br ? 2.0 * x - p : p;
-        if (r32) {
-            const float pf = (float)p, xf = (float)x;
-            xn = (double)(br ? 2.0f * xf - pf : pf);
-        }
+        const double xn = br ? 2.0 * x - p : p;
         Xn[(size_t)gi * ld + gj] = xn;
         if (mirror) Xn[(size_t)gj * ld + gi] = xn;
         tr += gi == gj ? xn : 0.0;
@@ -688,7 +670,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64_tail(double* __restrict__ b
                                                           int ld, const State* __restrict__ st,
                                                           double* __restrict__ part, int tile_group, int t_full,
                                                           int nsplit, double* __restrict__ chunk) {
-    if (st->done || (st->phase != 0 && st->phase != 2)) return;
+    if (st->done || st->phase != 0) return;
     const int nt = ld / GB, p = blockIdx.x;
     int bi, bj;
     order_tile(t_full + p, nt, tile_group, bi, bj);

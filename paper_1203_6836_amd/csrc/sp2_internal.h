@@ -46,7 +46,7 @@ struct CtrlArgs {
     int max_iter;
     int fp64_head;   // products in FP64 before switching phase (-1: never switch)
     int fp32_tail;   // BF16X2: FP32 products after the BF16 stage stalls
-    int mixed;       // 0: FP64 only, 1: INT8X, 2: BF16X2
+    int mixed;       // 0: FP64 only, 1: INT8X, 2: BF16X2, 3: FP32
     double total_blocks;  // block threshold: number of 32 x 32 blocks of N x N (0: off)
     double dense_fill;    // kept fraction from which State::full_fill is set (> 1: never)
 };

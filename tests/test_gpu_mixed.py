@@ -197,6 +197,7 @@ def test_bf16x2_configured_recipe_reported(ctx, dims, seed):
     say(f"  iters={st['iterations']} tail from {st['head_switch']} err/sqrtN={err:.2e} max|dq|={dq:.2e} idem={idem:.2e}")
     assert st["status"] == "stalled" and st["head_switch"] > 0
     assert st["iterations"] - st["head_switch"] == 3        # three FP32 products
+    assert st["fp64_products"] == 0                         # on the FP32 kernel, not the FP64 one
     assert abs(np.trace(D) - nocc) < 1e-3
     assert err < 1e-2
 
