@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 # digit recipe of every int8 solve of the benchmark (--slices, --levels)
 INT8_RECIPE = {"slices": 4, "levels": 5}
-PEAK = {"fp64": 78.6, "int8x": 5000.0, "bf16x2": 2500.0}   # TFLOP/s (TOP/s for int8), dense
+PEAK = {"fp64": 78.6, "int8x": 5000.0, "bf16x2": 2500.0, "fp32": 157.3}   # TFLOP/s (TOP/s for int8), dense
 PEAK_HBM_GBS = 8000.0
 
 
@@ -672,12 +672,57 @@ def five_planes(ctx, H, nocc, n_atoms, g2, idem_tol, ms64):
     return out
 
 
+def fp32_path(ctx, H, nocc, n_atoms, g2, idem_tol, ms64):
+    """The FP32 products (FP32 MFMA, FP32 accumulation and update) on the same
+    workload: time per solve, the product kernel's rate against the FP32
+    matrix peak, and the error against the oracle's FP64 solve."""
+    import torch
+    import paper_1203_6836_amd as p
+    log("fp32 path")
+    N = H.shape[0]
+    opts = p.options("fp32")
+    opts.idem_tol = idem_tol
+    D = torch.empty_like(H)
+    ctx.sp2_autotune(N, "fp32")
+    ctx.sp2_density_matrix(H, nocc, opts, D_out=D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = ctx.sp2_density_matrix(H, nocc, opts, D_out=D)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    ctx.sp2_ctx_set_profiling(True)
+    _, stp = ctx.sp2_density_matrix(H, nocc, opts, D_out=D)
+    ctx.sp2_ctx_set_profiling(False)
+    kms = stp["prod_ms"][1] / max(stp["prod_count"][1], 1)
+    useful = 2.0 * float(N) ** 3
+    sym_flops = float(N) * N * (N + 1)
+    out = {"ms_per_solve": round(ms, 2), "products": st["iterations"], "status": st["status"],
+           "speedup_vs_fp64": round(ms64 / ms, 3) if ms64 else None, "kernel": "k_gemm_f32",
+           "kernel_ms_avg": round(kms, 4),
+           "kernel_tflops_2n3": round(useful / (kms * 1e-3) / 1e12, 2),
+           "mfma_issue_tflops": round(sym_flops / (kms * 1e-3) / 1e12, 2),
+           "mfma_issue_frac_of_peak": round(sym_flops / (kms * 1e-3) / 1e12 / PEAK["fp32"], 4),
+           "vs_oracle": against_golden(D, g2, n_atoms) if g2 is not None else None}
+    log(f"  {out}")
+    return out
+
+
+def fp32_n8192(ctx):
+    """The FP32 leg alone on the mixed_n8192 workload (for profiling)."""
+    import torch
+
+    import synth
+    w = synth.MIXED
+    H = ctx.tb_hamiltonian(synth.STATIC_MODEL, torch.from_numpy(w.positions()).cuda())
+    return fp32_path(ctx, H, w.n_occ, w.n_atoms, golden("c2_mixed_n8192.npz"), 1e-10, None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="int8x", choices=["int8x", "fp64", "bf16x2"])
+    ap.add_argument("--precision", default="int8x", choices=["int8x", "fp64", "bf16x2", "fp32"])
     ap.add_argument("--slices", type=int, default=4, help="int8 digit planes")
     ap.add_argument("--levels", type=int, default=5,
                     help="int8 digit-product levels kept (slices or slices + 1)")
@@ -697,7 +742,7 @@ def main():
                     help="only run the counter-calibration kernels and one solve per precision "
                          "(for rocprofv3 --pmc passes); prints no JSON")
     ap.add_argument("--only", choices=["finite_temperature", "nonorthogonal", "xlbomd_n4096",
-                                       "blocksparse_n16384", "thresholded_scaling", "fp64_n256"],
+                                       "blocksparse_n16384", "thresholded_scaling", "fp64_n256", "fp32_n8192"],
                     help="run only this leg and print its result as one JSON line (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -717,7 +762,7 @@ def main():
         legs = {"finite_temperature": finite_temperature, "nonorthogonal": nonorthogonal,
                 "xlbomd_n4096": xlbomd_c1, "blocksparse_n16384": blocksparse_c3,
                 "thresholded_scaling": thresholded_scaling,
-                "fp64_n256": lambda c: fp64_small(c)[0]}
+                "fp64_n256": lambda c: fp64_small(c)[0], "fp32_n8192": fp32_n8192}
         print(json.dumps({args.only: legs[args.only](ctx)}), flush=True)
         ctx.close()
         return
@@ -831,7 +876,7 @@ def main():
     sym_flops = float(N) * N * (N + 1)          # distinct entries of a symmetric product
     achieved = useful / (kms * 1e-3) / 1e12
     unit = "TOP/s" if prec == "int8x" else "TFLOP/s"
-    kname = "k_gemm_f64" if prec == "fp64" else ("k_gemm_int8x" if prec == "int8x" else "k_gemm_bf16x2")
+    kname = {"fp64": "k_gemm_f64", "int8x": "k_gemm_int8x", "bf16x2": "k_gemm_bf16x2", "fp32": "k_gemm_f32"}[prec]
     traffic = recorded_traffic(kname) if kname in KERNEL_SOURCES else None
     if prec == "int8x" and (args.slices, args.levels) != (4, 5):
         traffic = None                      # counters are taken with 4 planes, 5 levels
@@ -842,7 +887,7 @@ def main():
             "kernel": kname, "kernel_ms_avg": round(kms, 4), "launches": cnt}
     # what the matrix cores actually issue: the upper tiles only (N^2 (N + 1)
     # multiply-adds x 2), times the digit-plane products of the expansion
-    issue_mult = {"int8x": digit_products(args.slices, args.levels), "bf16x2": 3, "fp64": 1}[prec]
+    issue_mult = {"int8x": digit_products(args.slices, args.levels), "bf16x2": 3, "fp64": 1, "fp32": 1}[prec]
     issued = issue_mult * sym_flops / (kms * 1e-3) / 1e12
     roof["mfma_issue"] = {"ops_per_launch": issue_mult * sym_flops, "rate": round(issued, 2), "unit": unit,
                           "frac_of_peak": round(issued / PEAK[prec], 4)}
@@ -860,7 +905,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"int8x": "i8 (int32 accumulation, f64 combine)", "fp64": "f64",
-                  "bf16x2": "bf16 (f32 accumulation)"}[prec],
+                  "bf16x2": "bf16 (f32 accumulation)", "fp32": "f32"}[prec],
         "data": "synthetic",
         "config": {"workload": "mixed_n8192: 2048-atom 8x16x16 jittered sp tight-binding lattice, "
                                "N=8192, n_occ=4096", "precision": prec,
@@ -895,6 +940,8 @@ def main():
     }
     if prec == "int8x" and (args.slices, args.levels) != (5, 5):
         out["int8x_five_planes"] = five_planes(ctx, H, nocc, w.n_atoms, g2, args.idem_tol, ms64)
+    if prec != "fp32":
+        out["fp32_path"] = fp32_path(ctx, H, nocc, w.n_atoms, g2, args.idem_tol, ms64)
     hopts = p.options(prec, slices=args.slices, levels=args.levels) if prec == "int8x" else p.options(prec)
     hopts.idem_tol = args.idem_tol
     out["host_memory"] = host_memory(ctx, H, nocc, hopts)
