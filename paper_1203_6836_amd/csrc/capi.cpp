@@ -393,9 +393,10 @@ static sp2_status sp2_solve(sp2_ctx* c, int N, const double* H, int n_occ, const
     if ((s = grow(c, (void**)&c->part, &pbytes, solve_part_slots(N) * sizeof(double))) != SP2_OK) return s;
     c->partcap = pbytes / sizeof(double);
     const bool int8x = o.precision == SP2_PREC_INT8X;
-    const bool bf16x = o.precision == SP2_PREC_BF16X2;
-    if (int8x || bf16x) {
-        if ((s = (sp2_status)split_reserve(c->split, ld, int8x ? o.slices : 0, bf16x)) != SP2_OK)
+    // BF16X2 and FP32: the BF16 planes and the FP32 copy of X_n
+    const bool f32ops = o.precision == SP2_PREC_BF16X2 || o.precision == SP2_PREC_FP32;
+    if (int8x || f32ops) {
+        if ((s = (sp2_status)split_reserve(c->split, ld, int8x ? o.slices : 0, f32ops)) != SP2_OK)
             return fail(c, SP2_ENOMEM, "device allocation for split operands failed");
     }
     SolveScratch sc;
@@ -503,13 +504,15 @@ static sp2_status sp2_solve_in(sp2_ctx* c, int N, const double* H, int n_occ, co
             hipEvent_t* pe = c->profile ? &c->pev[5 * g] : nullptr;
             if (pe) HIPCHK(c, hipEventRecord(pe[0], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
+            if (bf16x || fp32) HIPCHK(c, launch_encode_f32(buf0, buf1, ld, c->st, c->split.x32, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[1], st));
             if (f64p)
                 HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, part, &ns, st, env, tile_group, f64tail,
                                           f64tail_bytes, f64c.split_cap, f64_small));
             if (pe) HIPCHK(c, hipEventRecord(pe[2], st));
             if (int8x || bf16x) HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, part, &ns, st, env));
-            if (bf16x || fp32) HIPCHK(c, launch_gemm_f32(buf0, buf1, ld, c->st, part, &ns, tile_group, st));
+            if (bf16x || fp32)
+                HIPCHK(c, launch_gemm_f32(buf0, buf1, ld, c->st, c->split.x32, part, &ns, tile_group, st));
             if (pe) HIPCHK(c, hipEventRecord(pe[3], st));
             if (o.tau > 0.0)
                 HIPCHK(c, launch_block_threshold(buf0, buf1, ld, N, o.tau, o.threshold, c->st, part, &ns, 0, st,
@@ -728,8 +731,9 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         return s;
     c->partcap = pbytes / sizeof(double);
     const bool int8x = precision == SP2_PREC_INT8X, bf16x = precision == SP2_PREC_BF16X2;
-    if (int8x || bf16x) {
-        if (split_reserve(c->split, ld, int8x ? slices : 0, bf16x) != 0)
+    const bool fp32 = precision == SP2_PREC_FP32;
+    if (int8x || bf16x || fp32) {
+        if (split_reserve(c->split, ld, int8x ? slices : 0, bf16x || fp32) != 0)
             return fail(c, SP2_ENOMEM, "device allocation for split operands failed");
         c->split.upper = int8x;
         c->split.levels = nl;
@@ -803,8 +807,9 @@ extern "C" sp2_status sp2_autotune(sp2_ctx* c, int N, int precision, int slices,
         if (precision == SP2_PREC_FP64) {
             HIPCHK(c, launch_gemm_f64(buf0, buf1, ld, c->st, c->part, &ns, st, nullptr, t.tile_group, f64tail,
                                       f64tail_bytes, t.split_cap, t.tile == 32));
-        } else if (precision == SP2_PREC_FP32) {
-            HIPCHK(c, launch_gemm_f32(buf0, buf1, ld, c->st, c->part, &ns, t.tile_group, st));
+        } else if (fp32) {
+            HIPCHK(c, launch_encode_f32(buf0, buf1, ld, c->st, c->split.x32, st));
+            HIPCHK(c, launch_gemm_f32(buf0, buf1, ld, c->st, c->split.x32, c->part, &ns, t.tile_group, st));
         } else {
             HIPCHK(c, launch_split_encode(c->split, buf0, buf1, ld, c->st, st));
             HIPCHK(c, launch_split_gemm(c->split, buf0, buf1, ld, c->st, c->part, &ns, st, nullptr));

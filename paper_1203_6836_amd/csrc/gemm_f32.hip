@@ -2,13 +2,17 @@
 // accumulation over the whole K, and the SP2 update in FP32 (the FP32
 // precision mode, and the FP32 tail of the BF16 hi + lo mode).
 //
-// The master X holds FP32 values in FP64 storage (X_0 is rounded when it is
-// first staged).  One workgroup per upper 128 x 128 output tile, four waves
-// of 64 x 64, each a 2 x 2 grid of v_mfma_f32_32x32x2f32 blocks; K is staged
-// 16 rows at a time through LDS, double buffered, the operand rows rounded
-// to FP32 on their way in.  The update X_{n+1} = P or 2 X_n - P is formed in
-// FP32 and stored as FP64, mirrored below the diagonal; the traces, the
-// squared norm and the idempotency error are FP64 sums of the FP32 values.
+// The master X holds FP32 values in FP64 storage (X_0 is rounded by the
+// first encode).  Before each product k_encode_f32 writes X_n as an FP32
+// copy, so that the product streams 4-byte operands: at the FP32 matrix rate
+// the 8-byte master would need twice the L2 bandwidth the FP64 product uses.
+// One workgroup per upper 128 x 128 output tile, four waves of 64 x 64, each
+// a 2 x 2 grid of v_mfma_f32_32x32x2f32 blocks; K is staged 32 rows at a time
+// through LDS, double buffered.  The update X_{n+1} = P or 2 X_n - P is
+// formed in FP32 and stored in the FP64 master, mirrored below the diagonal;
+// the traces, the squared norm and the idempotency error are FP64 sums of
+// the FP32 values.
+#include <algorithm>
 #include <type_traits>
 
 #include "f32_internal.h"
@@ -16,48 +20,64 @@
 namespace sp2 {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int FB = 128;   // output tile
-constexpr int FK = 16;    // K rows per stage
-// LDS row stride (floats): a fragment read takes 32 consecutive floats of
-// rows k and k + 1 (one per half-wave); a stride of 32 mod 64 banks puts the
-// two halves in disjoint banks
-constexpr int FS = 160;
+constexpr int FK = 32;    // K rows per stage
+
+// FP32 copy of X_n (phase 2 only): four elements per thread.
+__global__ __launch_bounds__(256) void k_encode_f32(const double* __restrict__ buf0,
+                                                    const double* __restrict__ buf1, size_t n4,
+                                                    const State* __restrict__ st, float* __restrict__ x32) {
+    if (st->done || st->phase != 2) return;
+    const double* __restrict__ X = st->cur ? buf1 : buf0;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += (size_t)gridDim.x * 256) {
+        const double2 a = reinterpret_cast<const double2*>(X)[2 * q];
+        const double2 b = reinterpret_cast<const double2*>(X)[2 * q + 1];
+        reinterpret_cast<float4*>(x32)[q] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+    }
+}
 
 __global__ __launch_bounds__(256, 2) void k_gemm_f32(double* __restrict__ buf0, double* __restrict__ buf1,
                                                      int ld, const State* __restrict__ st,
-                                                     double* __restrict__ part, int tile_group) {
+                                                     const float* __restrict__ x32, double* __restrict__ part,
+                                                     int tile_group) {
     if (st->done || st->phase != 2) return;
-    __shared__ float As[2][FK][FS];
-    __shared__ float Bs[2][FK][FS];
+    // row k of a stage holds column c at (c + 32 (k & 1)) % 128: the two
+    // half-waves of a fragment read (rows k and k + 1, 32 consecutive
+    // columns each) then fall in disjoint LDS banks
+    __shared__ float As[2][FK][FB];
+    __shared__ float Bs[2][FK][FB];
     const int nt = ld / FB;
     int bi, bj;
     tile_of_block(blockIdx.x, nt, tile_group, bi, bj);
     const int t = tri_index(bi, bj, nt);
     const int i0 = bi * FB, j0 = bj * FB;
-    const double* __restrict__ Xc = st->cur ? buf1 : buf0;
     double* __restrict__ Xn = st->cur ? buf0 : buf1;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wi = w >> 1, wj = w & 1;
 
     // X is symmetric, so P_ij = sum_k X_ki X_kj: both operands are row
-    // segments of X (rows k, columns i0 .. i0 + 127 and j0 .. j0 + 127).
-    // Thread tid stages rows lrow + 4 s, columns lcol and lcol + 1.
-    const int lrow = tid >> 6, lcol = 2 * lane;
-    double2 ra[4], rb[4];
+    // segments of the FP32 copy (rows k, columns i0 .. i0 + 127 and
+    // j0 .. j0 + 127).  Thread tid stages rows lrow + 8 s, columns lcol ..
+    // lcol + 3.
+    const int lrow = tid >> 5, lcol = 4 * (tid & 31);
+    v4f ra[4], rb[4];
     auto gload = [&](int k0) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const size_t off = (size_t)(k0 + lrow + 4 * s) * ld;
-            ra[s] = *reinterpret_cast<const double2*>(Xc + off + i0 + lcol);
-            rb[s] = *reinterpret_cast<const double2*>(Xc + off + j0 + lcol);
+            const size_t off = (size_t)(k0 + lrow + 8 * s) * ld;
+            ra[s] = *reinterpret_cast<const v4f*>(x32 + off + i0 + lcol);
+            rb[s] = *reinterpret_cast<const v4f*>(x32 + off + j0 + lcol);
         }
     };
     auto sstore = [&](int stg) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            *reinterpret_cast<float2*>(&As[stg][lrow + 4 * s][lcol]) = make_float2((float)ra[s].x, (float)ra[s].y);
-            *reinterpret_cast<float2*>(&Bs[stg][lrow + 4 * s][lcol]) = make_float2((float)rb[s].x, (float)rb[s].y);
+            const int r = lrow + 8 * s;
+            const int c = (lcol + 32 * (r & 1)) & (FB - 1);
+            *reinterpret_cast<v4f*>(&As[stg][r][c]) = ra[s];
+            *reinterpret_cast<v4f*>(&Bs[stg][r][c]) = rb[s];
         }
     };
 
@@ -83,9 +103,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(double* __restrict__ buf0, 
             const int kr = k2 + (lane >> 5);
             float a[2], b[2];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) a[m] = As[stg][kr][wi * 64 + m * 32 + (lane & 31)];
+            for (int m = 0; m < 2; ++m) a[m] = As[stg][kr][(wi * 64 + m * 32 + (lane & 31) + 32 * (kr & 1)) & (FB - 1)];
 #pragma unroll
-            for (int n = 0; n < 2; ++n) b[n] = Bs[stg][kr][wj * 64 + n * 32 + (lane & 31)];
+            for (int n = 0; n < 2; ++n) b[n] = Bs[stg][kr][(wj * 64 + n * 32 + (lane & 31) + 32 * (kr & 1)) & (FB - 1)];
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -113,7 +133,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(double* __restrict__ buf0, 
                     // result: lane l, element r is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
                     const int gi = i0 + wi * 64 + m * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                     const float p = acc[m][n][r];
-                    const float x = (float)Xc[(size_t)gi * ld + gj];
+                    const float x = x32[(size_t)gi * ld + gj];
                     const float xn = br ? 2.0f * x - p : p;
                     Xn[(size_t)gi * ld + gj] = (double)xn;
                     if constexpr (MIR) Xn[(size_t)gj * ld + gi] = (double)xn;
@@ -148,12 +168,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(double* __restrict__ buf0, 
     }
 }
 
-hipError_t launch_gemm_f32(double* buf0, double* buf1, int ld, State* st, double* part, int* nslots,
-                           int tile_group, hipStream_t s) {
+hipError_t launch_encode_f32(const double* buf0, const double* buf1, int ld, State* st, float* x32,
+                             hipStream_t s) {
+    const size_t n4 = (size_t)ld * ld / 4;
+    const int grid = (int)std::min<size_t>((n4 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_encode_f32, dim3(grid), dim3(256), 0, s, buf0, buf1, n4, st, x32);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32(double* buf0, double* buf1, int ld, State* st, const float* x32, double* part,
+                           int* nslots, int tile_group, hipStream_t s) {
     const int nt = ld / FB;
     const int T = tri_tiles(nt);
     *nslots = T;
-    hipLaunchKernelGGL(k_gemm_f32, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, part, tile_group);
+    hipLaunchKernelGGL(k_gemm_f32, dim3(T), dim3(256), 0, s, buf0, buf1, ld, st, x32, part, tile_group);
     return hipGetLastError();
 }
 
