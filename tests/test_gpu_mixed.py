@@ -149,10 +149,12 @@ def test_int8x_full_size_against_fp64_path(ctx):
     assert err <= TOL_D and dq <= TOL_Q
 
 
-def test_int8x_full_size_against_oracle(ctx):
-    """N = 8192 as benchmarked (int8, 5 planes, default launch): against the
-    oracle's FP64 SP2 of the same Hamiltonian, built by the oracle (about a
-    minute of host BLAS)."""
+def test_reduced_precision_full_size_against_oracle(ctx):
+    """N = 8192 as benchmarked (int8, 5 planes, default launch, and 4 planes
+    with 5 levels): against the oracle's FP64 SP2 of the same Hamiltonian,
+    built by the oracle (about a minute of host BLAS); the FP32 products on
+    the same H at FP32 distance from it (the oracle's FP32 recipe lands at
+    4.6e-6 to 1.3e-5 per sqrt(N) at N = 600 to 2048)."""
     import time
     import paper_1203_6836_amd as p
     say("case int8x N=8192 vs oracle (full size)")
@@ -174,6 +176,13 @@ def test_int8x_full_size_against_oracle(ctx):
             f"max|dq|={dq:.2e}")
         assert abs(s8["iterations"] - ref.iterations) <= 2
         assert err <= TOL_D and dq <= TOL_Q
+    D32, s32 = ctx.sp2_density_matrix(Hd, w.n_occ, p.options("fp32"))
+    D32 = D32.cpu().numpy()
+    err = np.linalg.norm(D32 - ref.D) / np.sqrt(w.n_orb)
+    dq = float(np.abs(observables.mulliken(D32) - observables.mulliken(ref.D)).max())
+    say(f"  fp32: iters gpu={s32['iterations']} ({s32['status']}) err/sqrtN={err:.2e} max|dq|={dq:.2e}")
+    assert s32["status"] == "stalled" and abs(s32["iterations"] - ref.iterations) <= 4
+    assert err <= 3e-5 and dq <= 1e-4
 
 
 @pytest.mark.parametrize("dims,seed", [((4, 4, 4), 0), ((8, 8, 8), 2)])

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import eig, observables, sp2 as osp2, tb as otb
+from oracle import eig, observables, sp2 as osp2, sp2_fp32 as osp2_32, tb as otb
 
 pytestmark = pytest.mark.gpu
 
@@ -201,10 +201,11 @@ def degenerate_cases():
 
 def test_gap_reported_like_the_oracle(ctx):
     import paper_1203_6836_amd as p
-    say("case degenerate Fermi level -> SP2_EGAP (fp64, int8x)")
+    say("case degenerate Fermi level -> SP2_EGAP (fp64, int8x, fp32)")
     for H, nocc in degenerate_cases():
         assert osp2.sp2(H, nocc).status == "gap"
-        for prec in ("fp64", "int8x"):
+        assert osp2_32.sp2_fp32(H, nocc).status == "gap"
+        for prec in ("fp64", "int8x", "fp32"):
             st, stats = ctx.sp2_density_matrix_status(to_dev(H), nocc, p.options(prec))
             assert st == p.SP2_EGAP and stats["status"] == "gap", (H.shape, prec, st, stats["status"])
     # a short budget on the same degenerate pair is ENOCONV, as in the oracle
