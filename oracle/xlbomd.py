@@ -11,8 +11,9 @@ Test infrastructure only.
   text does not reprint; kappa is rescaled by 1/2 (General remarks).  Reading:
   kappa = 1.82 / 2, alpha = 0.018, c = (-6, 14, -8, -3, 4, -1); they are
   inputs, and what the tests pin is sum c_k = 0 and sum k c_k = 0 (the
-  dissipation vanishes on histories linear in t) and time reversibility for
-  alpha = 0.
+  dissipation vanishes on histories linear in t), time reversibility for
+  alpha = 0, and that at a fixed q the set damps every mode of n - q while
+  reversed or negated coefficients make the recurrence grow.
 * Nuclei: velocity Verlet with the forces of ``observables.forces`` at the
   new (R, n) — one density-matrix construction per step.
 * Constant of motion: E_tot = kinetic + U(R; n) (Eq. EtotOrth, S = 0).
