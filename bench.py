@@ -58,6 +58,7 @@ def cpu_model() -> str:
 KERNEL_SOURCES = {
     "k_gemm_int8x": ["int8x.hip", "split_internal.h", "sp2_internal.h"],
     "k_gemm_f64": ["sp2_dense.hip", "sp2_internal.h"],
+    "k_gemm_f32": ["gemm_f32.hip", "f32_internal.h", "sp2_internal.h"],
 }
 
 
@@ -792,6 +793,9 @@ def main():
         tune = {"fp64": ctx.sp2_autotune(N, "fp64")}
         if args.precision != "fp64":
             tune[args.precision] = ctx.sp2_autotune(N, args.precision, args.slices, args.levels)
+        if args.tune_table and "fp32" not in tune:
+            # the counter passes replay the FP32 solve with the same table
+            ctx.sp2_autotune(N, "fp32")
         log("autotune: " + ", ".join(f"{k} tile_group {v['tile_group']} stage_cfg {v['stage_cfg']} split_cap "
                                      f"{v['split_cap']} tile {v['tile']}" for k, v in tune.items()))
         if args.tune_table:
@@ -810,7 +814,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-        for prec in ("int8x", "fp64"):
+        for prec in ("int8x", "fp64", "fp32"):
             log(f"traffic probe: one {prec} solve at N={N}")
             solve(prec, D)
             torch.cuda.synchronize()
