@@ -708,6 +708,30 @@ def fp32_path(ctx, H, nocc, n_atoms, g2, idem_tol, ms64):
     return out
 
 
+def bf16x2_path(ctx, H, nocc, n_atoms, g2, ms64):
+    """The configured BF16 hi + lo recipe (FP32 accumulation, then three FP32
+    products on the FP32 kernel) on the same workload: time per solve and its
+    error against the oracle's FP64 solve (it is not expected to reach 1e-6)."""
+    import torch
+    import paper_1203_6836_amd as p
+    log("bf16x2 path")
+    N = H.shape[0]
+    opts = p.options("bf16x2")
+    D = torch.empty_like(H)
+    ctx.sp2_autotune(N, "bf16x2")
+    ctx.sp2_density_matrix(H, nocc, opts, D_out=D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = ctx.sp2_density_matrix(H, nocc, opts, D_out=D)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out = {"ms_per_solve": round(ms, 2), "products": st["iterations"], "fp32_tail_from": st["head_switch"],
+           "status": st["status"], "speedup_vs_fp64": round(ms64 / ms, 3) if ms64 else None,
+           "vs_oracle": against_golden(D, g2, n_atoms) if g2 is not None else None}
+    log(f"  {out}")
+    return out
+
+
 def fp32_n8192(ctx):
     """The FP32 leg alone on the mixed_n8192 workload (for profiling)."""
     import torch
@@ -946,6 +970,8 @@ def main():
         out["int8x_five_planes"] = five_planes(ctx, H, nocc, w.n_atoms, g2, args.idem_tol, ms64)
     if prec != "fp32":
         out["fp32_path"] = fp32_path(ctx, H, nocc, w.n_atoms, g2, args.idem_tol, ms64)
+    if prec != "bf16x2":
+        out["bf16x2_path"] = bf16x2_path(ctx, H, nocc, w.n_atoms, g2, ms64)
     hopts = p.options(prec, slices=args.slices, levels=args.levels) if prec == "int8x" else p.options(prec)
     hopts.idem_tol = args.idem_tol
     out["host_memory"] = host_memory(ctx, H, nocc, hopts)
